@@ -1,0 +1,235 @@
+/*
+ * gsw.h -- graph-property-switched breadth-first search on MI355X (gfx950).
+ *
+ * C ABI of libgsw.so.  Plain pointers and sizes only; no C++ types cross it
+ * and no C++ exception escapes it.  Every call returns a gsw_status; on a
+ * non-OK status gsw_last_error() holds a message for the calling thread and
+ * the contents of output buffers are unspecified.  GSW_EHIP reports a failed
+ * HIP runtime call; HIP errors can be sticky, so a process that sees it
+ * should not keep using the device.
+ *
+ * The method (Verstraaten, Varbanescu, de Laat, "Using Graph Properties to
+ * Speed-up GPU-based Graph Traversal: A Model-driven Approach", 2017):
+ * level-synchronous BFS whose frontier expansion at each level is done by one
+ * of several interchangeable kernels (Section III-A), the kernel being chosen
+ * per level by a binary decision tree over graph and frontier properties
+ * (Section IV-A), with the paper's rule for undecided leaves.
+ *
+ * Graph convention: CSR with int64 row offsets and int32 column ids,
+ * 1 <= n < 2^31 vertices.  Row v lists the neighbours of v.  Self-loops and
+ * repeated entries are tolerated and do not change any result.  Bottom-up
+ * (pull) expansion needs every arc (u,v) to have its reverse (v,u).
+ *
+ * Ownership: the caller owns every buffer it passes and the library never
+ * frees them.  Objects returned through gsw_*_create are owned by the caller
+ * and released with the matching gsw_*_destroy.
+ *
+ * Threading: calls on one gsw_graph are serialised internally (one BFS at a
+ * time per graph).  Different graphs may be used from different threads.
+ */
+#ifndef GSW_H
+#define GSW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GSW_ABI_VERSION 1
+
+typedef enum {
+  GSW_OK = 0,
+  GSW_EINVAL = -1,   /* malformed argument or graph */
+  GSW_ENOMEM = -2,   /* device or host allocation failed */
+  GSW_EHIP = -3,     /* a HIP runtime call failed */
+  GSW_ERANGE = -4,   /* a result does not fit its type (int8 levels > 127) */
+  GSW_EBUSY = -5,    /* no free slot */
+  GSW_ENOTREE = -6,  /* tree policy without a tree */
+  GSW_ENOTSYM = -7   /* bottom-up expansion asked for on a non-symmetric graph */
+} gsw_status;
+
+/*
+ * Frontier-expansion kernels (Section III-A).  Each one performs a whole BFS
+ * level: given the vertices at depth d it finds every unvisited vertex
+ * adjacent to them, gives it depth d+1 and a parent at depth d, and emits the
+ * next frontier both as a queue and as a bitmap, so any kernel may follow any
+ * other at the next level.
+ */
+enum {
+  GSW_K_PUSH_VERTEX = 0,  /* top-down, one lane per frontier vertex ("vertex push") */
+  GSW_K_PUSH_WAVE4 = 1,   /* top-down, W lanes cooperate on each frontier vertex, */
+  GSW_K_PUSH_WAVE8 = 2,   /*   W vertices per group ("vertex push warp", virtual */
+  GSW_K_PUSH_WAVE16 = 3,  /*   warps of W lanes inside a 64-lane wavefront)       */
+  GSW_K_PUSH_WAVE32 = 4,
+  GSW_K_PUSH_WAVE64 = 5,
+  GSW_K_PUSH_EDGE = 6,    /* top-down, one lane per frontier edge (edge-centric) */
+  GSW_K_PULL_BITMAP = 7,  /* bottom-up, one lane per unvisited vertex, early exit
+                             on the first neighbour in the frontier bitmap ("vertex pull") */
+  GSW_K_VERTEX_SCAN = 8,  /* vertex push over all n vertices, testing depth == d */
+  GSW_K_EDGE_SCAN = 9,    /* edge list: one lane per arc over all arcs, testing the
+                             depth of the arc's origin (needs the origin array) */
+  GSW_N_KERNELS = 10
+};
+
+/* Kernel used when the tree cannot decide at the first level (Section IV-A:
+ * the edge-centric implementation, as the least likely to be very slow). */
+#define GSW_DEFAULT_KERNEL GSW_K_PUSH_EDGE
+
+/* Graph creation flags. */
+#define GSW_ASSUME_SYMMETRIC 0x1u /* skip the symmetry check; caller vouches for it */
+#define GSW_WITH_ORIGIN 0x2u      /* build the per-arc origin array now, not on first use */
+#define GSW_TRUSTED 0x4u          /* skip validation of offsets and columns */
+
+/*
+ * Per-level feature vector fed to the tree (Section IV-A feature list; the
+ * paper's best model uses graph size, fraction discovered, the out-degree
+ * distribution and the frontier's vertex count, Section IV-B):
+ *   0 n vertices            4 degree median          8 frontier vertices n_f(d)
+ *   1 arcs (CSR entries)    5 degree third quartile  9 n_f(d) / n
+ *   2 degree minimum        6 degree maximum        10 discovered (depths 0..d)
+ *   3 degree first quartile 7 degree std (ddof 0)   11 discovered / n
+ * Quartiles interpolate linearly between order statistics.
+ */
+#define GSW_N_FEATURES 12
+
+typedef struct gsw_graph gsw_graph;
+typedef struct gsw_tree gsw_tree;
+
+/* One row per BFS level and source. */
+typedef struct {
+  int32_t source_idx;   /* index into the sources array */
+  int32_t level;        /* d: this row expanded the depth-d vertices */
+  int32_t kernel;       /* GSW_K_* that ran */
+  int32_t flags;        /* bit0: tree leaf undecided, fallback rule applied */
+  int64_t n_frontier;   /* n_f(d): vertices at depth d */
+  int64_t discovered;   /* vertices at depths 0..d */
+  int64_t n_next;       /* vertices found at depth d+1 (0 on the last row) */
+  float ms;             /* kernel time of this level (HIP events), or -1 */
+  int32_t reserved;
+} gsw_level_trace;
+
+enum { GSW_POLICY_TREE = 0, GSW_POLICY_FIXED = 1, GSW_POLICY_SCHEDULE = 2 };
+
+typedef struct {
+  int32_t policy;            /* GSW_POLICY_* */
+  int32_t fixed_kernel;      /* GSW_POLICY_FIXED: kernel for every level */
+  const int32_t *schedule;   /* GSW_POLICY_SCHEDULE: kernel per level (host array); */
+  int32_t schedule_len;      /*   levels beyond the end repeat the last entry */
+  const gsw_tree *tree;      /* GSW_POLICY_TREE */
+  int32_t time_levels;       /* 1: fill gsw_level_trace.ms with HIP event times */
+  int32_t canonical_parents; /* 1: parent[v] = smallest neighbour one level up */
+  int32_t device_ptrs;       /* 1: levels/parents are device pointers; 0: host */
+  int32_t reserved0;
+  void *stream;              /* hipStream_t for the work; NULL = library stream */
+} gsw_bfs_opts;
+
+/* Fills opts with: tree policy, no tree, host pointers, library stream. */
+void gsw_bfs_opts_default(gsw_bfs_opts *opts);
+
+/* ---------------------------------------------------------------- graphs */
+
+/* Host-only check of a CSR graph: 1 <= n < 2^31, nnz >= 0, offs[0] == 0,
+ * offs non-decreasing, offs[n] == nnz, every column in [0, n).  When
+ * is_symmetric is non-NULL it receives 1 if every arc has its reverse, else 0
+ * (cost O(nnz log deg)).  Needs no GPU. */
+gsw_status gsw_graph_validate(int64_t n, int64_t nnz, const int64_t *offs, const int32_t *cols,
+                              int32_t *is_symmetric);
+
+/* Copies a host CSR into device memory owned by the graph.  flags: GSW_*
+ * creation flags.  Degree statistics are computed here (host, untimed). */
+gsw_status gsw_graph_create_host(int64_t n, int64_t nnz, const int64_t *offs, const int32_t *cols,
+                                 uint32_t flags, gsw_graph **out);
+
+/* Borrows a device CSR (e.g. torch tensors); the caller keeps d_offs/d_cols
+ * alive and unchanged until gsw_graph_destroy.  Validation and statistics
+ * copy the arrays to the host once (skipped checks with GSW_TRUSTED). */
+gsw_status gsw_graph_create_device(int64_t n, int64_t nnz, const int64_t *d_offs,
+                                   const int32_t *d_cols, uint32_t flags, void *stream,
+                                   gsw_graph **out);
+
+void gsw_graph_destroy(gsw_graph *g);
+
+/* n, nnz, deg_stats = {min, q1, median, q3, max, std}, device bytes held by
+ * the graph (CSR, origin array, BFS workspace).  Any output may be NULL. */
+gsw_status gsw_graph_info(const gsw_graph *g, int64_t *n, int64_t *nnz, double deg_stats[6],
+                          size_t *dev_bytes);
+
+/* Degree statistics of a host CSR, as used in the feature vector:
+ * {min, q1, median, q3, max, std}.  Host only; needs no GPU. */
+gsw_status gsw_degree_stats(int64_t n, const int64_t *offs, double out[6]);
+
+/* The tree's feature vector (see GSW_N_FEATURES) for a level whose frontier
+ * has n_frontier vertices after `discovered` vertices have depths 0..d. */
+gsw_status gsw_level_features(const gsw_graph *g, int64_t n_frontier, int64_t discovered,
+                              double out[GSW_N_FEATURES]);
+
+/* ----------------------------------------------------------------- trees */
+
+/* Builds a tree from flat node arrays (a fitted CART tree): node 0 is the
+ * root; left[i] == -1 marks a leaf; an inner node sends x to left[i] when
+ * (double)(float)x[feature[i]] <= threshold[i], else to right[i] (features
+ * are compared in float32, as scikit-learn does).  value[i*n_classes + c] is
+ * the weight of class c in node i's bucket; class_kernel[c] is the GSW_K_*
+ * of class c.  A leaf whose largest weight is shared by two or more classes
+ * is undecided (Section IV-A, "unknown prediction"). */
+gsw_status gsw_tree_create(int32_t n_nodes, int32_t n_classes, const int32_t *feature,
+                           const double *threshold, const int32_t *left, const int32_t *right,
+                           const double *value, const int32_t *class_kernel, gsw_tree **out);
+void gsw_tree_destroy(gsw_tree *t);
+
+/* Host-side prediction for one feature vector.  An undecided leaf repeats
+ * prev_kernel when level > 0 and gives GSW_DEFAULT_KERNEL at level 0
+ * (Section IV-A); *unknown is set to 1 in that case.  Needs no GPU. */
+gsw_status gsw_tree_predict(const gsw_tree *t, const double x[GSW_N_FEATURES], int32_t prev_kernel,
+                            int32_t level, int32_t *kernel, int32_t *unknown);
+
+/* ------------------------------------------------------------------- BFS */
+
+/*
+ * Level-synchronous BFS from each of n_sources sources (Section III-A: all
+ * depths start at infinity, the root at 0; every level gives depth d+1 to the
+ * unvisited neighbours of depth-d vertices; the search ends when a level
+ * finds nothing).
+ *   sources  host array of n_sources vertex ids in [0, n).
+ *   levels   [n_sources][n] int32: hop distance from the source, -1 if
+ *            unreachable.  Device memory when opts->device_ptrs, else host.
+ *   parents  [n_sources][n] int32 or NULL: a neighbour one level up
+ *            (parent[source] = source, -1 if unreachable).  Not unique
+ *            unless opts->canonical_parents.
+ *   trace    host array of trace_cap rows or NULL; *trace_len (may be NULL)
+ *            receives the number of rows produced, which can exceed
+ *            trace_cap (extra rows are dropped).
+ * The host drives the level loop: after each level it reads the new frontier
+ * size, computes the features and asks the policy for the next kernel.
+ */
+gsw_status gsw_bfs(const gsw_graph *g, const int32_t *sources, int32_t n_sources, int32_t *levels,
+                   int32_t *parents, gsw_level_trace *trace, int32_t trace_cap,
+                   int32_t *trace_len, const gsw_bfs_opts *opts);
+
+/*
+ * Per-level timing of every listed kernel from the same BFS state (the
+ * training data of Section IV-A).  At each level the state is saved, each
+ * kernel in kernels[0..n_kernels) runs `reps` times from the saved state and
+ * times[level*n_kernels + k] receives the median kernel time in ms; then the
+ * BFS advances one level with advance_kernel.  frontier[level] receives
+ * n_f(level).  Stops at max_levels rows (GSW_ERANGE if the BFS is longer).
+ * Kernels that cannot run on this graph (pull on a non-symmetric graph) get
+ * a time of -1.
+ */
+gsw_status gsw_bfs_profile(const gsw_graph *g, int32_t source, const int32_t *kernels,
+                           int32_t n_kernels, int32_t reps, int32_t advance_kernel, float *times,
+                           int64_t *frontier, int32_t max_levels, int32_t *n_levels, void *stream);
+
+/* ------------------------------------------------------------------ misc */
+
+const char *gsw_last_error(void);
+const char *gsw_kernel_name(int32_t kernel_id); /* "?" for an unknown id */
+int32_t gsw_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSW_H */

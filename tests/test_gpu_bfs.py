@@ -1,0 +1,263 @@
+"""GPU parity: every expansion kernel, random per-level schedules and the tree
+policy against the CPU oracle.  Levels must match bit-exactly; parents are
+not unique and must pass the Graph500-style invariants (or, in canonical
+mode, equal the smallest neighbour one level up)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import checks
+from oracle import features as ofeat
+from oracle import tree as otree
+from paper_1708_01159_amd import graphgen as gg
+from paper_1708_01159_amd import gsw
+
+pytestmark = pytest.mark.gpu
+
+ALL_KERNELS = list(range(gsw.N_KERNELS))
+
+
+def _path(n):
+    return gg.from_edges(n, list(range(n - 1)), list(range(1, n)), name="path%d" % n)
+
+
+def _star(n):
+    return gg.from_edges(n, [0] * (n - 1), list(range(1, n)), name="star%d" % n)
+
+
+def _disjoint():
+    a = gg.rmat(8, 8, seed=31)
+    # second copy shifted, plus 40 isolated vertices at the end
+    rows = np.repeat(np.arange(a.n), a.degrees())
+    src = np.concatenate([rows, rows + a.n])
+    dst = np.concatenate([a.cols, a.cols + a.n])
+    return gg.from_edges(2 * a.n + 40, src, dst, name="disjoint")
+
+
+def _dirty():
+    a = gg.rmat(9, 8, seed=32)
+    rows = np.repeat(np.arange(a.n), a.degrees())
+    keep = rows < a.cols
+    src = np.concatenate([rows[keep], rows[keep][:200], np.arange(0, a.n, 5)])
+    dst = np.concatenate([a.cols[keep], a.cols[keep][:200], np.arange(0, a.n, 5)])
+    return gg.from_edges(a.n, src, dst, symmetrize=True, drop_loops=False, dedup=False, name="dirty")
+
+
+CASES = {
+    "rmat10": lambda: gg.rmat(10, 16, seed=1),
+    "rmat14": lambda: gg.rmat(14, 16, seed=11),
+    "er_ragged": lambda: gg.erdos_renyi(100037, 300000, seed=12),
+    "grid": lambda: gg.grid(37, 53, 0.05, seed=13),
+    "chunglu": lambda: gg.chung_lu(20000, 2.1, 12.0, seed=14),
+    "path": lambda: _path(300),
+    "star": lambda: _star(5000),
+    "disjoint": _disjoint,
+    "dirty": _dirty,
+    "single": lambda: gg.from_edges(1, [], [], name="single"),
+}
+
+_cache = {}
+
+
+def case(name):
+    if name not in _cache:
+        g = CASES[name]()
+        if name == "rmat10":
+            srcs = gg.pick_sources(g, 1, 101)
+        elif name == "single":
+            srcs = np.array([0], dtype=np.int32)
+        elif name == "disjoint":
+            srcs = np.array([0, g.n // 2 - 20 + 3, g.n - 1], dtype=np.int32)  # incl. isolated
+        elif name == "star":
+            srcs = np.array([0, 17], dtype=np.int32)
+        else:
+            srcs = gg.pick_sources(g, 2, 7)
+        G = gsw.Graph.from_csr(g.offs, g.cols)
+        refs = [oracle.bfs(g.offs, g.cols, int(s)) for s in srcs]
+        comp = checks.components(g.n, g.offs, g.cols)
+        _cache[name] = (g, G, srcs, refs, comp)
+    return _cache[name]
+
+
+def _check_result(g, srcs, refs, comp, lv, pa, trace):
+    for i, s in enumerate(srcs):
+        ref_lv, _, hist, _ = refs[i]
+        assert np.array_equal(lv[i], ref_lv), "levels differ for source %d" % s
+        checks.check_bfs(g.offs, g.cols, int(s), lv[i], pa[i], comp)
+        rows = [t for t in trace if t.source_idx == i]
+        assert [t.level for t in rows] == list(range(len(hist)))
+        assert [t.n_frontier for t in rows] == hist.tolist()
+        assert [t.n_next for t in rows] == hist[1:].tolist() + [0]
+        assert [t.discovered for t in rows] == np.cumsum(hist).tolist()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("kernel", ALL_KERNELS, ids=gsw.KERNEL_NAMES)
+def test_fixed_kernel_parity(name, kernel):
+    g, G, srcs, refs, comp = case(name)
+    lv, pa, trace = gsw.bfs(G, srcs, policy="fixed", kernel=kernel)
+    assert all(t.kernel == kernel for t in trace)
+    _check_result(g, srcs, refs, comp, lv, pa, trace)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_random_schedules(name):
+    g, G, srcs, refs, comp = case(name)
+    rng = np.random.default_rng(1234)
+    depth = max(len(r[2]) for r in refs)
+    for trial in range(6):
+        sched = rng.integers(0, gsw.N_KERNELS, size=depth).astype(np.int32)
+        lv, pa, trace = gsw.bfs(G, srcs, policy="schedule", schedule=sched)
+        for t in trace:
+            assert t.kernel == sched[min(t.level, depth - 1)]
+        _check_result(g, srcs, refs, comp, lv, pa, trace)
+
+
+def _handmade_tree():
+    # split on the frontier fraction, then on the discovered fraction
+    return dict(
+        left=[1, 3, 5, -1, -1, -1, -1], right=[2, 4, 6, -1, -1, -1, -1],
+        feature=[9, 11, 11, -2, -2, -2, -2], threshold=[0.01, 0.5, 0.9, -2, -2, -2, -2],
+        value=[[1, 1, 1, 1], [3, 1, 0, 0], [0, 0, 2, 1], [0, 4, 0, 0], [5, 0, 0, 0],
+               [0, 0, 6, 0], [0, 0, 1, 1]],
+        class_kernel=[gsw.PUSH_WAVE32, gsw.PUSH_VERTEX, gsw.PULL_BITMAP, gsw.PUSH_EDGE])
+
+
+@pytest.mark.parametrize("name", ["rmat10", "rmat14", "er_ragged", "grid", "chunglu", "star"])
+def test_tree_policy_matches_oracle_walk(name):
+    g, G, srcs, refs, comp = case(name)
+    T = _handmade_tree()
+    tree = gsw.Tree(T)
+    lv, pa, trace = gsw.bfs(G, srcs, policy="tree", tree=tree)
+    _check_result(g, srcs, refs, comp, lv, pa, trace)
+    gf = ofeat.graph_features(g.offs)
+    for i in range(len(srcs)):
+        hist = refs[i][2]
+        prev = gsw.DEFAULT_KERNEL
+        for t in [t for t in trace if t.source_idx == i]:
+            x = ofeat.level_features(g.offs, hist, t.level, gf)
+            k, unknown = otree.predict(T, x, prev, t.level, gsw.DEFAULT_KERNEL)
+            assert t.kernel == k and bool(t.flags & 1) == unknown
+            prev = k
+
+
+def test_level_features_match_oracle():
+    g, G, srcs, refs, comp = case("rmat14")
+    hist = refs[0][2]
+    gf = ofeat.graph_features(g.offs)
+    for d in range(len(hist)):
+        want = ofeat.level_features(g.offs, hist, d, gf)
+        got = G.level_features(int(hist[d]), int(hist[: d + 1].sum()))
+        np.testing.assert_allclose(got, want, rtol=1e-12)
+        assert np.array_equal(got[[0, 1, 2, 3, 4, 5, 6, 8, 10]], want[[0, 1, 2, 3, 4, 5, 6, 8, 10]])
+
+
+def _canonical(g, lv):
+    par = np.full(g.n, -1, dtype=np.int64)
+    rows = np.repeat(np.arange(g.n), g.degrees())
+    ok = (lv[rows] > 0) & (lv[g.cols] == lv[rows] - 1)
+    cand = np.full(g.n, np.iinfo(np.int64).max)
+    np.minimum.at(cand, rows[ok], g.cols[ok].astype(np.int64))
+    has = lv > 0
+    par[has] = cand[has]
+    par[lv == 0] = np.flatnonzero(lv == 0)
+    return par
+
+
+@pytest.mark.parametrize("name", ["rmat14", "grid", "dirty", "disjoint"])
+def test_canonical_parents_exact(name):
+    g, G, srcs, refs, comp = case(name)
+    for kernel in (gsw.PUSH_VERTEX, gsw.PULL_BITMAP, gsw.PUSH_EDGE):
+        lv, pa, _ = gsw.bfs(G, srcs, policy="fixed", kernel=kernel, canonical_parents=True)
+        for i in range(len(srcs)):
+            assert np.array_equal(pa[i], _canonical(g, refs[i][0]))
+
+
+def test_device_pointers_and_torch_stream():
+    import torch
+
+    g, G, srcs, refs, comp = case("rmat14")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        lv, pa, trace = gsw.bfs(G, srcs, policy="fixed", kernel=gsw.PULL_BITMAP, device=True)
+    stream.synchronize()
+    assert lv.is_cuda and lv.shape == (len(srcs), g.n)
+    _check_result(g, srcs, refs, comp, lv.cpu().numpy(), pa.cpu().numpy(), trace)
+    # borrowed device CSR
+    offs_t = torch.from_numpy(g.offs).cuda()
+    cols_t = torch.from_numpy(g.cols).cuda()
+    G2 = gsw.Graph.from_csr(offs_t, cols_t)
+    lv2, pa2, trace2 = gsw.bfs(G2, srcs, policy="fixed", kernel=gsw.PUSH_EDGE)
+    _check_result(g, srcs, refs, comp, lv2, pa2, trace2)
+    G2.close()
+
+
+def test_time_levels_and_no_parents():
+    g, G, srcs, refs, comp = case("rmat14")
+    lv, pa, trace = gsw.bfs(G, srcs, policy="fixed", kernel=gsw.PUSH_WAVE16, parents=False,
+                            time_levels=True)
+    assert pa is None
+    assert all(t.ms >= 0 for t in trace)
+    for i in range(len(srcs)):
+        assert np.array_equal(lv[i], refs[i][0])
+
+
+def test_directed_graph_push_only():
+    a = gg.rmat(10, 8, seed=40)
+    rows = np.repeat(np.arange(a.n), a.degrees())
+    keep = rows < a.cols  # orient every edge from low id to high id
+    d = gg.from_edges(a.n, rows[keep], a.cols[keep], symmetrize=False)
+    G = gsw.Graph.from_csr(d.offs, d.cols)
+    s = int(np.flatnonzero(d.degrees() > 0)[0])
+    ref = oracle.levels(d.offs, d.cols, s)
+    for k in (gsw.PUSH_VERTEX, gsw.PUSH_WAVE8, gsw.PUSH_EDGE, gsw.VERTEX_SCAN, gsw.EDGE_SCAN):
+        lv, _, _ = gsw.bfs(G, [s], policy="fixed", kernel=k)
+        assert np.array_equal(lv[0], ref)
+    with pytest.raises(gsw.GswError) as ei:
+        gsw.bfs(G, [s], policy="fixed", kernel=gsw.PULL_BITMAP)
+    assert ei.value.status == gsw.ENOTSYM
+    # the tree may name pull: on a directed graph the driver substitutes the
+    # default kernel and flags the row
+    lv, _, trace = gsw.bfs(G, [s], policy="tree", tree=gsw.Tree.constant(gsw.PULL_BITMAP))
+    assert np.array_equal(lv[0], ref)
+    assert all(t.kernel == gsw.DEFAULT_KERNEL and t.flags & 2 for t in trace)
+
+
+def test_error_paths():
+    g, G, srcs, refs, comp = case("rmat10")
+    with pytest.raises(gsw.GswError) as ei:
+        gsw.bfs(G, [g.n], policy="fixed", kernel=0)
+    assert ei.value.status == gsw.EINVAL
+    with pytest.raises(gsw.GswError) as ei:
+        gsw.bfs(G, [0], policy="fixed", kernel=gsw.N_KERNELS)
+    assert ei.value.status == gsw.EINVAL
+    o = gsw.BfsOpts()
+    gsw.lib().gsw_bfs_opts_default(o)
+    lv = np.empty(g.n, dtype=np.int32)
+    src = np.array([0], dtype=np.int32)
+    st = gsw.lib().gsw_bfs(G.handle, src.ctypes.data, 1, lv.ctypes.data, None, None, 0, None, o)
+    assert st == gsw.ENOTREE
+    # a result is still right after the errors
+    lv, pa, trace = gsw.bfs(G, srcs, policy="fixed", kernel=gsw.PUSH_EDGE)
+    _check_result(g, srcs, refs, comp, lv, pa, trace)
+
+
+def test_profile_api():
+    g, G, srcs, refs, comp = case("rmat14")
+    s = int(srcs[0])
+    times, frontier, ks = gsw.bfs_profile(G, s, reps=3)
+    hist = refs[0][2]
+    assert times.shape == (len(hist), gsw.N_KERNELS)
+    assert np.array_equal(frontier, hist)
+    assert np.all(times > 0)
+    # the profiled state is left consistent: a normal BFS afterwards is exact
+    lv, pa, trace = gsw.bfs(G, srcs, policy="fixed", kernel=gsw.PUSH_VERTEX)
+    _check_result(g, srcs, refs, comp, lv, pa, trace)
+
+
+def test_graph_info():
+    g, G, srcs, refs, comp = case("rmat14")
+    info = G.info()
+    assert info["n"] == g.n and info["nnz"] == g.nnz
+    np.testing.assert_allclose(info["deg_stats"], ofeat.graph_features(g.offs)[2:8], rtol=1e-12)
+    assert info["dev_bytes"] >= 8 * (g.n + 1) + 4 * g.nnz
