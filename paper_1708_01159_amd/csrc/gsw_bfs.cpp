@@ -16,7 +16,8 @@ namespace {
 struct Policy {
   const gsw_bfs_opts* o;
   bool symmetric;
-  // Kernel for level d; *flags gets bit0 when the tree leaf was undecided.
+  // Kernel for level d; *flags gets bit0 when the tree leaf was undecided,
+  // bit1 when a pull choice was replaced on a non-symmetric graph.
   int choose(const gsw_graph* g, int32_t d, int64_t nf, int64_t disc, int prev, int32_t* flags) const {
     *flags = 0;
     int k = GSW_DEFAULT_KERNEL;
@@ -37,7 +38,7 @@ struct Policy {
         break;
       }
     }
-    if (kernel_is_pull(k) && !symmetric) {  // tree picked pull on a directed graph
+    if (kernel_is_pull(k) && !symmetric) {
       k = GSW_DEFAULT_KERNEL;
       *flags |= 2;
     }
@@ -45,6 +46,9 @@ struct Policy {
   }
 };
 
+// Buffers of level d: queue q[d&1] with counter slot d&3 in, q[(d+1)&1] and
+// slot (d+1)&3 out, slot (d+2)&3 zeroed for the level after next; frontier
+// bitmap bm[d&1] in (pull), bm[(d+1)&1] out (pull).
 LevelLaunch level_args(const gsw_graph* g, int32_t* lv, int32_t* pa, int32_t d, uint32_t nf) {
   const Workspace& w = g->ws;
   LevelLaunch l;
@@ -54,13 +58,13 @@ LevelLaunch level_args(const gsw_graph* g, int32_t* lv, int32_t* pa, int32_t d, 
   l.level = lv;
   l.parent = pa;
   l.vis = w.vis;
-  l.fr = w.bm[d % 3];
-  l.nx = w.bm[(d + 1) % 3];
-  l.clr = w.bm[(d + 2) % 3];
+  l.fr = w.bm[d & 1];
+  l.nx = w.bm[(d + 1) & 1];
   l.qin = w.q[d & 1];
+  l.cin = w.ctr + (size_t)(d & 3) * kCtrSlot;
   l.qout = w.q[(d + 1) & 1];
-  l.ctr = w.ctr + (d & 3);
-  l.ctr_clr = w.ctr + ((d + 2) & 3);
+  l.cout = w.ctr + (size_t)((d + 1) & 3) * kCtrSlot;
+  l.cclr = w.ctr + (size_t)((d + 2) & 3) * kCtrSlot;
   l.n = g->n;
   l.nw = w.nw;
   l.nnz = g->nnz;
@@ -69,12 +73,55 @@ LevelLaunch level_args(const gsw_graph* g, int32_t* lv, int32_t* pa, int32_t d, 
   return l;
 }
 
-gsw_status read_next(const gsw_graph* g, int32_t d, hipStream_t s, int64_t* nn) {
+// Size of the depth-(d+1) queue (sum over its segments); bins[] receives the
+// per-segment counts when non-null.
+gsw_status read_next(const gsw_graph* g, int32_t d, hipStream_t s, int64_t* nn, uint32_t* bins) {
   const Workspace& w = g->ws;
-  GSW_HIP(hipMemcpyAsync(w.h_ctr, w.ctr + (d & 3), sizeof(LevelCtr), hipMemcpyDeviceToHost, s));
+  GSW_HIP(hipMemcpyAsync(w.h_ctr, w.ctr + (size_t)((d + 1) & 3) * kCtrSlot,
+                         kCtrSlot * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   GSW_HIP(hipStreamSynchronize(s));
-  *nn = (int64_t)w.h_ctr->n_next;
+  int64_t t = 0;
+  for (int b = 0; b < kQueueBins; ++b) {
+    t += w.h_ctr[b * kCtrStride];
+    if (bins) bins[b] = w.h_ctr[b * kCtrStride];
+  }
+  *nn = t;
   return GSW_OK;
+}
+
+// Waits until the device has stored level d's next-frontier size in host
+// memory (k_finalize).  Polls the stream for errors now and then so a failed
+// launch cannot leave the host spinning.
+gsw_status wait_next(const gsw_graph* g, int32_t d, hipStream_t s, int64_t* nn) {
+  volatile uint32_t* f = g->ws.h_flag + (size_t)(d % kFlagSlots) * 64;
+  for (uint64_t it = 0;; ++it) {
+    const uint32_t v = *f;
+    if (v != kNotReady) {
+      *nn = (int64_t)v;
+      return GSW_OK;
+    }
+    if ((it & 4095u) == 4095u) {
+      const hipError_t e = hipStreamQuery(s);
+      if (e == hipSuccess) {
+        const uint32_t v2 = *f;
+        if (v2 != kNotReady) {
+          *nn = (int64_t)v2;
+          return GSW_OK;
+        }
+        return fail(GSW_EHIP, "level %d finished without reporting its frontier size", d);
+      }
+      if (e != hipErrorNotReady) return fail(GSW_EHIP, "level %d: %s", d, hipGetErrorString(e));
+    }
+    __builtin_ia32_pause();
+  }
+}
+
+// One level: the frontier bitmap is rebuilt first when pull follows a
+// top-down level (its input bitmap is otherwise stale).
+gsw_status run_level(const gsw_graph* g, int k, const LevelLaunch& l, bool fr_valid, hipStream_t s) {
+  if (kernel_is_pull(k) && !fr_valid)
+    GSW_TRY(launch_frontier_bitmap(g, l.level, l.d, const_cast<unsigned long long*>(l.fr), s));
+  return launch_level(g, k, l, s);
 }
 
 gsw_status check_kernel(const gsw_graph* g, int k) {
@@ -92,18 +139,26 @@ gsw_status run_one(gsw_graph* g, const Policy& pol, int32_t src_idx, int32_t src
   GSW_TRY(launch_init(g, lv, pa, src, s));
   int64_t nf = 1, disc = 1;
   int prev = GSW_DEFAULT_KERNEL;
+  bool fr_valid = true;  // init wrote the depth-0 bitmap
   for (int32_t d = 0;; ++d) {
     int32_t flags = 0;
     const int k = pol.choose(g, d, nf, disc, prev, &flags);
     if (k == GSW_K_EDGE_SCAN) GSW_TRY(ensure_origin(g));
     const LevelLaunch l = level_args(g, lv, pa, d, (uint32_t)nf);
+    const size_t slot = (size_t)(d % kFlagSlots) * 64;
+    w.h_flag[slot] = kNotReady;
     if (o->time_levels) GSW_HIP(hipEventRecord(w.ev[0], s));
-    GSW_TRY(launch_level(g, k, l, s));
+    GSW_TRY(run_level(g, k, l, fr_valid, s));
     if (o->time_levels) GSW_HIP(hipEventRecord(w.ev[1], s));
+    GSW_TRY(launch_finalize(l.cout, w.d_flag + slot, s));
+    fr_valid = kernel_is_pull(k);
     int64_t nn = 0;
-    GSW_TRY(read_next(g, d, s, &nn));
+    GSW_TRY(wait_next(g, d, s, &nn));
     float ms = -1.0f;
-    if (o->time_levels) GSW_HIP(hipEventElapsedTime(&ms, w.ev[0], w.ev[1]));
+    if (o->time_levels) {
+      GSW_HIP(hipEventSynchronize(w.ev[1]));
+      GSW_HIP(hipEventElapsedTime(&ms, w.ev[0], w.ev[1]));
+    }
     if (trace && *rows < trace_cap) {
       gsw_level_trace& t = trace[*rows];
       t.source_idx = src_idx;
@@ -123,6 +178,7 @@ gsw_status run_one(gsw_graph* g, const Policy& pol, int32_t src_idx, int32_t src
     prev = k;
   }
   if (o->canonical_parents && pa) GSW_TRY(launch_canonical_parents(g, lv, pa, s));
+  GSW_HIP(hipStreamSynchronize(s));
   return GSW_OK;
 }
 
@@ -224,39 +280,50 @@ gsw_status gsw_bfs_profile(const gsw_graph* cg, int32_t source, const int32_t* k
   const hipStream_t s = pick_stream(g, stream);
   const int64_t n = g->n;
   const size_t vb = (size_t)n * sizeof(int32_t), bb = (size_t)w.nw * sizeof(unsigned long long);
+  const size_t cb = 4 * kCtrSlot * sizeof(uint32_t);
   DevBuf s_lv, s_pa, s_vis, s_bm, s_q, s_ctr;
   GSW_TRY(dalloc(s_lv, vb));
   GSW_TRY(dalloc(s_pa, vb));
   GSW_TRY(dalloc(s_vis, bb));
-  GSW_TRY(dalloc(s_bm, 3 * bb));
-  GSW_TRY(dalloc(s_q, vb));
-  GSW_TRY(dalloc(s_ctr, 4 * sizeof(LevelCtr)));
+  GSW_TRY(dalloc(s_bm, 2 * bb));
+  GSW_TRY(dalloc(s_q, (size_t)kQueueBins * vb));
+  GSW_TRY(dalloc(s_ctr, cb));
   int32_t* lv = w.lvl_tmp;
   int32_t* pa = w.par_tmp;
   GSW_TRY(launch_init(g, lv, pa, source, s));
   int64_t nf = 1;
+  uint32_t bins[kQueueBins] = {1};  // segment sizes of the current queue
+  bool fr_valid = true;
   std::vector<float> samples((size_t)reps);
   for (int32_t d = 0;; ++d) {
     if (d >= max_levels) return fail(GSW_ERANGE, "BFS longer than max_levels=%d", max_levels);
     int32_t* qin = w.q[d & 1];
+    // copies queue segments of the current frontier only
+    auto copy_queue = [&](int32_t* dst, const int32_t* src) -> gsw_status {
+      for (int b = 0; b < kQueueBins; ++b)
+        if (bins[b])
+          GSW_HIP(hipMemcpyAsync(dst + (size_t)b * n, src + (size_t)b * n, bins[b] * sizeof(int32_t),
+                                 hipMemcpyDeviceToDevice, s));
+      return GSW_OK;
+    };
     auto save = [&]() -> gsw_status {
       GSW_HIP(hipMemcpyAsync(s_lv.p, lv, vb, hipMemcpyDeviceToDevice, s));
       GSW_HIP(hipMemcpyAsync(s_pa.p, pa, vb, hipMemcpyDeviceToDevice, s));
       GSW_HIP(hipMemcpyAsync(s_vis.p, w.vis, bb, hipMemcpyDeviceToDevice, s));
-      for (int b = 0; b < 3; ++b)
+      for (int b = 0; b < 2; ++b)
         GSW_HIP(hipMemcpyAsync((char*)s_bm.p + b * bb, w.bm[b], bb, hipMemcpyDeviceToDevice, s));
-      GSW_HIP(hipMemcpyAsync(s_q.p, qin, (size_t)nf * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-      GSW_HIP(hipMemcpyAsync(s_ctr.p, w.ctr, 4 * sizeof(LevelCtr), hipMemcpyDeviceToDevice, s));
+      GSW_TRY(copy_queue((int32_t*)s_q.p, qin));
+      GSW_HIP(hipMemcpyAsync(s_ctr.p, w.ctr, cb, hipMemcpyDeviceToDevice, s));
       return GSW_OK;
     };
     auto restore = [&]() -> gsw_status {
       GSW_HIP(hipMemcpyAsync(lv, s_lv.p, vb, hipMemcpyDeviceToDevice, s));
       GSW_HIP(hipMemcpyAsync(pa, s_pa.p, vb, hipMemcpyDeviceToDevice, s));
       GSW_HIP(hipMemcpyAsync(w.vis, s_vis.p, bb, hipMemcpyDeviceToDevice, s));
-      for (int b = 0; b < 3; ++b)
+      for (int b = 0; b < 2; ++b)
         GSW_HIP(hipMemcpyAsync(w.bm[b], (char*)s_bm.p + b * bb, bb, hipMemcpyDeviceToDevice, s));
-      GSW_HIP(hipMemcpyAsync(qin, s_q.p, (size_t)nf * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-      GSW_HIP(hipMemcpyAsync(w.ctr, s_ctr.p, 4 * sizeof(LevelCtr), hipMemcpyDeviceToDevice, s));
+      GSW_TRY(copy_queue(qin, (const int32_t*)s_q.p));
+      GSW_HIP(hipMemcpyAsync(w.ctr, s_ctr.p, cb, hipMemcpyDeviceToDevice, s));
       return GSW_OK;
     };
     GSW_TRY(save());
@@ -270,7 +337,7 @@ gsw_status gsw_bfs_profile(const gsw_graph* cg, int32_t source, const int32_t* k
       for (int32_t r = 0; r < reps; ++r) {
         GSW_TRY(restore());
         GSW_HIP(hipEventRecord(w.ev[0], s));
-        GSW_TRY(launch_level(g, k, l, s));
+        GSW_TRY(run_level(g, k, l, fr_valid, s));
         GSW_HIP(hipEventRecord(w.ev[1], s));
         GSW_HIP(hipEventSynchronize(w.ev[1]));
         GSW_HIP(hipEventElapsedTime(&samples[(size_t)r], w.ev[0], w.ev[1]));
@@ -279,9 +346,10 @@ gsw_status gsw_bfs_profile(const gsw_graph* cg, int32_t source, const int32_t* k
       times[(size_t)d * n_kernels + ki] = samples[(size_t)reps / 2];
     }
     GSW_TRY(restore());
-    GSW_TRY(launch_level(g, advance_kernel, l, s));
+    GSW_TRY(run_level(g, advance_kernel, l, fr_valid, s));
+    fr_valid = kernel_is_pull(advance_kernel);
     int64_t nn = 0;
-    GSW_TRY(read_next(g, d, s, &nn));
+    GSW_TRY(read_next(g, d, s, &nn, bins));
     if (frontier) frontier[d] = nf;
     if (n_levels) *n_levels = d + 1;
     if (nn == 0) break;

@@ -149,10 +149,9 @@ gsw_status ensure_workspace(gsw_graph* g) {
       {(void**)&w.vis, bmb},
       {(void**)&w.bm[0], bmb},
       {(void**)&w.bm[1], bmb},
-      {(void**)&w.bm[2], bmb},
-      {(void**)&w.q[0], (size_t)n * sizeof(int32_t)},
-      {(void**)&w.q[1], (size_t)n * sizeof(int32_t)},
-      {(void**)&w.ctr, 4 * sizeof(LevelCtr)},
+      {(void**)&w.q[0], (size_t)kQueueBins * n * sizeof(int32_t)},
+      {(void**)&w.q[1], (size_t)kQueueBins * n * sizeof(int32_t)},
+      {(void**)&w.ctr, 4 * kCtrSlot * sizeof(uint32_t)},
       {(void**)&w.scan, (size_t)n * sizeof(int64_t)},
       {(void**)&w.ebeg, (size_t)n * sizeof(int64_t)},
       {(void**)&w.bsum, (size_t)nb * sizeof(int64_t)},
@@ -169,7 +168,22 @@ gsw_status ensure_workspace(gsw_graph* g) {
     }
     w.bytes += it.bytes;
   }
-  GSW_HIP(hipHostMalloc((void**)&w.h_ctr, sizeof(LevelCtr), hipHostMallocDefault));
+  GSW_HIP(hipHostMalloc((void**)&w.h_ctr, kCtrSlot * sizeof(uint32_t), hipHostMallocDefault));
+  GSW_HIP(hipHostMalloc((void**)&w.h_flag, kFlagSlots * 64 * sizeof(uint32_t),
+                        hipHostMallocMapped | hipHostMallocCoherent));
+  GSW_HIP(hipHostGetDevicePointer((void**)&w.d_flag, w.h_flag, 0));
+  if (g->symmetric && !g->iso) {
+    const size_t ib = (size_t)w.nw * sizeof(unsigned long long);
+    hipError_t e = hipMalloc((void**)&g->iso, ib);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      g->iso = nullptr;
+      return fail(GSW_ENOMEM, "hipMalloc(%zu) for the isolated-vertex bitmap failed", ib);
+    }
+    w.bytes += ib;
+    GSW_TRY(launch_isolated(g, g->iso, g->stream));
+    GSW_HIP(hipStreamSynchronize(g->stream));
+  }
   GSW_HIP(hipEventCreate(&w.ev[0]));
   GSW_HIP(hipEventCreate(&w.ev[1]));
   return GSW_OK;
@@ -199,11 +213,13 @@ namespace {
 void free_graph(gsw_graph* g) {
   if (!g) return;
   Workspace& w = g->ws;
-  void* dev[] = {w.vis, w.bm[0], w.bm[1], w.bm[2], w.q[0], w.q[1], w.ctr, w.scan, w.ebeg,
+  void* dev[] = {w.vis, w.bm[0], w.bm[1], w.q[0], w.q[1], w.ctr, w.scan, w.ebeg,
                  w.bsum, w.etot, w.lvl_tmp, w.par_tmp, g->origin};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   if (w.h_ctr) (void)hipHostFree(w.h_ctr);
+  if (w.h_flag) (void)hipHostFree(w.h_flag);
+  if (g->iso) (void)hipFree(g->iso);
   for (hipEvent_t ev : w.ev)
     if (ev) (void)hipEventDestroy(ev);
   if (g->owns_csr) {

@@ -30,12 +30,15 @@ void clear_error();
     if (s_ != GSW_OK) return s_;      \
   } while (0)
 
-// Per-level counters written by the expansion kernels (16 bytes).
-struct LevelCtr {
-  uint32_t n_next;   // vertices discovered at depth d+1
-  uint32_t pad;
-  unsigned long long e_next;
-};
+// Frontier queues are split into kQueueBins segments, one per residue of the
+// producing workgroup id, each with room for every vertex; a workgroup stages
+// its discoveries in LDS and appends them with one atomic on its segment's
+// counter.  Same-address atomics serialise (about 11 ns each on MI355X), so
+// spreading the appends over several counters keeps a level's append cost
+// small.  Counters sit kCtrStride words apart (separate 128-byte lines).
+constexpr int kQueueBins = 8;
+constexpr int kCtrStride = 32;
+constexpr int kCtrSlot = kQueueBins * kCtrStride;  // words per level in the counter ring
 
 // Device state of one BFS in flight.  Bitmaps are 64-bit words, bit (v & 63)
 // of word v >> 6; the last word's bits beyond n are set in `vis` so they are
@@ -43,16 +46,18 @@ struct LevelCtr {
 struct Workspace {
   int64_t n = 0, nw = 0;
   unsigned long long* vis = nullptr;     // visited
-  unsigned long long* bm[3] = {};        // rotating frontier bitmaps
-  int32_t* q[2] = {};                    // frontier queues
-  LevelCtr* ctr = nullptr;               // ring of 4 counters
+  unsigned long long* bm[2] = {};        // frontier bitmaps (depth d and d+1)
+  int32_t* q[2] = {};                    // frontier queues, kQueueBins segments of n
+  uint32_t* ctr = nullptr;               // ring of 4 levels x kCtrSlot words
   int64_t* scan = nullptr;               // push_edge: per-entry exclusive degree scan
   int64_t* ebeg = nullptr;               // push_edge: row start per queue entry
   int64_t* bsum = nullptr;               // push_edge: per-block sums
   unsigned long long* etot = nullptr;    // push_edge: total frontier edges
   int32_t* lvl_tmp = nullptr;            // levels when the caller passes host memory
   int32_t* par_tmp = nullptr;            // parents when the caller passes host memory
-  LevelCtr* h_ctr = nullptr;             // pinned host copy of one counter
+  uint32_t* h_ctr = nullptr;             // pinned host copy of one counter slot
+  uint32_t* h_flag = nullptr;            // mapped host memory: frontier size per level slot
+  uint32_t* d_flag = nullptr;            // the same memory as seen by the device
   hipEvent_t ev[2] = {};
   size_t bytes = 0;
 };
@@ -65,6 +70,7 @@ struct gsw_graph {
   const int64_t* offs = nullptr;  // device
   const int32_t* cols = nullptr;  // device
   int32_t* origin = nullptr;      // device, built on demand (edge_scan)
+  unsigned long long* iso = nullptr;  // device bitmap of degree-0 vertices (symmetric graphs)
   bool owns_csr = false;
   int symmetric = 0;              // 1 when checked or vouched for
   double deg_stats[6] = {};       // min, q1, median, q3, max, std
@@ -88,15 +94,15 @@ struct LevelLaunch {
   const int32_t* cols;
   const int32_t* origin;
   int32_t* level;
-  int32_t* parent;  // may be null
+  int32_t* parent;          // may be null
   unsigned long long* vis;
-  const unsigned long long* fr;
-  unsigned long long* nx;
-  unsigned long long* clr;
-  const int32_t* qin;
-  int32_t* qout;
-  LevelCtr* ctr;
-  LevelCtr* ctr_clr;
+  const unsigned long long* fr;  // frontier bitmap of depth d (pull only)
+  unsigned long long* nx;        // depth d+1 bitmap, written whole by pull
+  const int32_t* qin;       // queue of depth d (kQueueBins segments)
+  const uint32_t* cin;      // its segment counts (a counter slot)
+  int32_t* qout;            // queue of depth d+1
+  uint32_t* cout;           // its segment counters (zero on entry)
+  uint32_t* cclr;           // counter slot to zero for the level after next
   int64_t n, nw, nnz;
   uint32_t n_in;
   int32_t d;
@@ -105,6 +111,10 @@ struct LevelLaunch {
 gsw_status launch_init(const gsw_graph* g, int32_t* level, int32_t* parent, int32_t source,
                        hipStream_t s);
 gsw_status launch_level(const gsw_graph* g, int kernel, const LevelLaunch& a, hipStream_t s);
+gsw_status launch_frontier_bitmap(const gsw_graph* g, const int32_t* level, int32_t d,
+                                  unsigned long long* bm, hipStream_t s);
+gsw_status launch_isolated(const gsw_graph* g, unsigned long long* iso, hipStream_t s);
+gsw_status launch_finalize(const uint32_t* cslot, uint32_t* d_flag, hipStream_t s);
 gsw_status launch_canonical_parents(const gsw_graph* g, const int32_t* level, int32_t* parent,
                                     hipStream_t s);
 gsw_status launch_build_origin(const gsw_graph* g, int32_t* origin, hipStream_t s);
@@ -114,5 +124,9 @@ gsw_status ensure_origin(gsw_graph* g);
 hipStream_t pick_stream(gsw_graph* g, void* user_stream);
 
 bool kernel_is_pull(int k);
+
+// Marker of a level-size slot in host memory that the device has not written.
+constexpr uint32_t kNotReady = 0xffffffffu;
+constexpr int kFlagSlots = 4;
 
 }  // namespace gsw

@@ -2,24 +2,26 @@
 //
 // Every kernel performs one whole BFS level d (Section III-A): it finds the
 // unvisited vertices adjacent to depth-d vertices, gives each depth d+1 and a
-// parent at depth d, and emits the depth-(d+1) frontier twice -- as a queue
-// (for the top-down kernels) and as a bitmap (for the bottom-up kernel) -- so
-// that any kernel can run the next level.  Only the queue's order and the
-// parent choice depend on the kernel; levels do not.
+// parent at depth d, and appends it to the depth-(d+1) queue.  The bottom-up
+// kernel also writes the depth-(d+1) frontier bitmap in full; after a top-down
+// level that bitmap is rebuilt from the level array only if the next level is
+// bottom-up.  Any kernel can therefore run the next level; only the queue's
+// order and the parent choice depend on the kernel, never the levels.
 //
 // Ownership of a new vertex v is decided by atomicOr on its 64-bit visited
 // word: exactly one lane sees the bit clear and becomes the writer of v's
-// level, parent, next-bitmap bit and queue slot.  A plain load of the word
-// first filters out vertices already visited (a stale read only costs an
-// atomic, because bits are only ever set).
+// level, parent and queue slot.  A plain load of the word first filters out
+// vertices already visited (a stale read only costs an atomic, because bits
+// are only ever set).
 //
-// The next queue is appended wave-aggregated: one atomicAdd per wavefront
-// per round of discoveries, lanes placed by their rank among the winners.
-// (The paper tried one global atomic per thread and warp/block reductions,
-// Section III-A "Variants"; on this hardware the per-wave form is used.)
-//
-// Each launch also zeroes the bitmap and counter that the level after next
-// will use, so a level costs one launch.
+// Appends are staged per workgroup in LDS (one LDS atomic per wavefront and
+// round) and flushed with one global atomic per workgroup into the queue
+// segment of its bin; a workgroup whose stage fills up appends further rounds
+// directly, one atomic per wavefront.  (The paper compared a global atomic
+// per thread with warp- and block-level reductions, Section III-A
+// "Variants"; here the aggregation is per workgroup because same-address
+// atomics serialise.)  Producer grids are persistent (at most kMaxGrid
+// workgroups, grid-stride loops) so that few workgroups flush.
 #include <hip/hip_runtime.h>
 
 #include "gsw_internal.h"
@@ -28,11 +30,14 @@ namespace gsw {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kClearPerThread = 8;
-constexpr int kScanItems = 4;                     // push_edge: entries per thread in the scan
-constexpr int kScanTile = kBlock * kScanItems;    // entries per scan block
-constexpr int kEdgeTile = 1024;                   // push_edge: edges per tile
-constexpr int kEdgeWin = kEdgeTile;               // push_edge: queue entries staged per tile
+constexpr int kWaves = kBlock / 64;
+constexpr int kMaxGrid = 1024;                   // persistent producer grids
+constexpr int kStage = 2048;                     // LDS-staged queue entries per workgroup
+constexpr int kScanItems = 4;                    // push_edge: entries per thread in the scan
+constexpr int kScanTile = kBlock * kScanItems;   // entries per scan block
+constexpr int kEdgeTile = 1024;                  // push_edge: edges per tile
+constexpr int kEdgeWin = kEdgeTile;              // push_edge: queue entries staged per tile
+constexpr int kPullEager = 8;                    // pull: neighbours probed per lane up front
 
 typedef unsigned long long u64;
 
@@ -45,11 +50,11 @@ struct Args {
   u64* vis;
   const u64* __restrict__ fr;
   u64* nx;
-  u64* clr;
   const int32_t* __restrict__ qin;
+  const uint32_t* cin;
   int32_t* __restrict__ qout;
-  LevelCtr* ctr;
-  LevelCtr* ctr_clr;
+  uint32_t* cout;
+  uint32_t* cclr;
   int64_t n, nw, nnz;
   uint32_t n_in;
   int32_t d;
@@ -59,17 +64,93 @@ __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
 __device__ __forceinline__ u64 lanes_below(int lane) { return (1ull << lane) - 1ull; }
 
-// Zero this launch's share of the bitmap (and counter) the level after next uses.
+__device__ __forceinline__ int my_bin() { return (int)(blockIdx.x % kQueueBins); }
+
+// Zero the counter slot that the level after next appends to.
 __device__ __forceinline__ void clear_ahead(const Args& a) {
-  if (a.clr) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.nw; i += stride)
-      a.clr[i] = 0ull;
+  if (blockIdx.x == 0 && threadIdx.x < kQueueBins) a.cclr[threadIdx.x * kCtrStride] = 0u;
+}
+
+// ----------------------------------------------------------- queue input
+// The input queue is the concatenation of its kQueueBins segments.
+struct QueueIn {
+  uint32_t pre[kQueueBins + 1];
+};
+
+__device__ __forceinline__ void queue_in_load(const Args& a, QueueIn& q) {
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (int b = 0; b < kQueueBins; ++b) {
+      q.pre[b] = acc;
+      acc += a.cin[b * kCtrStride];
+    }
+    q.pre[kQueueBins] = acc;
   }
-  if (a.ctr_clr && blockIdx.x == 0 && threadIdx.x == 0) {
-    a.ctr_clr->n_next = 0u;
-    a.ctr_clr->e_next = 0ull;
+  __syncthreads();
+}
+
+__device__ __forceinline__ int32_t queue_at(const Args& a, const QueueIn& q, uint32_t i) {
+  int b = 0;
+#pragma unroll
+  for (int k = 1; k < kQueueBins; ++k) b += i >= q.pre[k] ? 1 : 0;
+  return a.qin[(int64_t)b * a.n + (i - q.pre[b])];
+}
+
+// ---------------------------------------------------------- queue output
+struct Stage {
+  int32_t buf[kStage];
+  uint32_t n;      // entries reserved (may exceed kStage once it overflowed)
+  uint32_t valid;  // reservations at or past this position went to global memory
+  uint32_t base;
+};
+
+__device__ __forceinline__ void stage_init(Stage& s) {
+  if (threadIdx.x == 0) {
+    s.n = 0u;
+    s.valid = kStage;
   }
+  __syncthreads();
+}
+
+// Appends the winning lanes' vertices.  Called by every active lane of the
+// wave with the same control flow; no workgroup barrier inside.
+__device__ __forceinline__ void stage_push(Stage& s, const Args& a, bool win, int32_t v) {
+  const u64 m = __ballot(win);
+  if (m == 0ull) return;
+  const int lane = lane_id();
+  const int leader = __ffsll((long long)m) - 1;
+  const uint32_t k = (uint32_t)__popcll(m);
+  uint32_t pos = 0;
+  if (lane == leader) {
+    pos = atomicAdd(&s.n, k);
+    if (pos + k > (uint32_t)kStage) {
+      atomicMin(&s.valid, pos);
+      pos = (uint32_t)kStage + atomicAdd(a.cout + my_bin() * kCtrStride, k);
+    }
+  }
+  pos = (uint32_t)__shfl((int)pos, leader);
+  const uint32_t r = (uint32_t)__popcll(m & lanes_below(lane));
+  if (win) {
+    if (pos < (uint32_t)kStage)
+      s.buf[pos + r] = v;
+    else
+      a.qout[(int64_t)my_bin() * a.n + (pos - (uint32_t)kStage) + r] = v;
+  }
+}
+
+// Copies the staged entries to the workgroup's queue segment.  Every thread
+// of the workgroup must call it.
+__device__ __forceinline__ void stage_flush(Stage& s, const Args& a) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t cnt = s.n < s.valid ? s.n : s.valid;
+    s.valid = cnt;
+    s.base = cnt ? atomicAdd(a.cout + my_bin() * kCtrStride, cnt) : 0u;
+  }
+  __syncthreads();
+  const uint32_t cnt = s.valid;
+  int32_t* dst = a.qout + (int64_t)my_bin() * a.n + s.base;
+  for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) dst[i] = s.buf[i];
 }
 
 // True for the one lane (device-wide) that first sets v's visited bit.
@@ -80,37 +161,24 @@ __device__ __forceinline__ bool claim(u64* vis, int32_t v) {
   return (atomicOr(w, bit) & bit) == 0ull;
 }
 
-// Appends the winning lanes' vertices to the next queue: one atomic per wave.
-// Called by every active lane of the wave with the same control flow.
-__device__ __forceinline__ void wave_append(bool win, int32_t v, int32_t* qout, uint32_t* count) {
-  const u64 m = __ballot(win);
-  if (m == 0ull) return;
-  const int lane = lane_id();
-  const int leader = __ffsll((long long)m) - 1;
-  uint32_t base = 0;
-  if (lane == leader) base = atomicAdd(count, (uint32_t)__popcll(m));
-  base = (uint32_t)__shfl((int)base, leader);
-  if (win) qout[base + (uint32_t)__popcll(m & lanes_below(lane))] = v;
-}
-
-// Level/parent/next-bit writes of a newly owned vertex.
 __device__ __forceinline__ void settle(const Args& a, int32_t v, int32_t u) {
   a.level[v] = a.d + 1;
   if (a.parent) a.parent[v] = u;
-  atomicOr(a.nx + (v >> 6), 1ull << (v & 63));
 }
 
-__device__ __forceinline__ void visit(const Args& a, int32_t v, int32_t u) {
+__device__ __forceinline__ void visit(Stage& s, const Args& a, int32_t v, int32_t u) {
   const bool win = claim(a.vis, v);
   if (win) settle(a, v, u);
-  wave_append(win, v, a.qout, &a.ctr->n_next);
+  stage_push(s, a, win, v);
 }
 
 // ---------------------------------------------------------------- init
+// Degree-0 vertices of a symmetric graph can never be reached (except as
+// the source): they start out marked visited so pull never scans them.
 __global__ void __launch_bounds__(kBlock) k_init(int32_t* __restrict__ level,
-                                                 int32_t* __restrict__ parent, u64* vis, u64* b0,
-                                                 u64* b1, u64* b2, int32_t* q0, LevelCtr* ctr,
-                                                 int64_t n, int64_t nw, int32_t s) {
+                                                 int32_t* __restrict__ parent, u64* vis, u64* fr,
+                                                 const u64* __restrict__ iso, int32_t* q0,
+                                                 uint32_t* ctr, int64_t n, int64_t nw, int32_t s) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t i = gid; i < n; i += stride) {
@@ -124,64 +192,79 @@ __global__ void __launch_bounds__(kBlock) k_init(int32_t* __restrict__ level,
     u64 pad = 0ull;
     if (w == nw - 1 && tail) pad = ~0ull << tail;  // bits beyond n count as visited
     const u64 here = w == sw ? sbit : 0ull;
-    vis[w] = here | pad;
-    b0[w] = here;
-    b1[w] = 0ull;
-    b2[w] = 0ull;
+    vis[w] = here | pad | (iso ? iso[w] : 0ull);
+    fr[w] = here;
   }
-  if (gid == 0) q0[0] = s;
-  if (gid < 4) {
-    ctr[gid].n_next = 0u;
-    ctr[gid].pad = 0u;
-    ctr[gid].e_next = 0ull;
-  }
+  if (gid == 0) q0[0] = s;  // segment 0 of the depth-0 queue
+  if (gid < 4 * kCtrSlot) ctr[gid] = gid == 0 ? 1u : 0u;
 }
 
 // ------------------------------------------------- push_vertex (lane / vertex)
 __global__ void __launch_bounds__(kBlock) k_push_vertex(Args a) {
+  __shared__ Stage st;
+  __shared__ QueueIn qi;
   clear_ahead(a);
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  int32_t u = 0;
-  int64_t beg = 0, end = 0;
-  if (i < a.n_in) {
-    u = a.qin[i];
-    beg = a.offs[u];
-    end = a.offs[u + 1];
+  stage_init(st);
+  queue_in_load(a, qi);
+  const uint32_t stride = gridDim.x * kBlock;
+  for (uint32_t base = blockIdx.x * kBlock; base < a.n_in; base += stride) {
+    const uint32_t i = base + threadIdx.x;
+    int32_t u = 0;
+    int64_t beg = 0, end = 0;
+    if (i < a.n_in) {
+      u = queue_at(a, qi, i);
+      beg = a.offs[u];
+      end = a.offs[u + 1];
+    }
+    for (int64_t e = beg; e < end; ++e) visit(st, a, a.cols[e], u);
   }
-  for (int64_t e = beg; e < end; ++e) visit(a, a.cols[e], u);
+  stage_flush(st, a);
 }
 
 // ------------------------------------- push_wave<W> (W lanes / vertex, W vertices / group)
+// The paper's virtual warps (Section III-A, vertex push warp): a group of W
+// lanes takes W frontier vertices and walks their rows one after another,
+// the W lanes striding over each row together.
 template <int W>
 __global__ void __launch_bounds__(kBlock) k_push_wave(Args a) {
+  __shared__ Stage st;
+  __shared__ QueueIn qi;
   clear_ahead(a);
+  stage_init(st);
+  queue_in_load(a, qi);
   const int lane = lane_id();
   const int sub = lane & (W - 1);
   const int first = lane & ~(W - 1);
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;  // this lane's own entry
-  int32_t u = 0;
-  int64_t beg = 0, end = 0;
-  if (i < a.n_in) {
-    u = a.qin[i];
-    beg = a.offs[u];
-    end = a.offs[u + 1];
+  const uint32_t stride = gridDim.x * kBlock;
+  for (uint32_t base = blockIdx.x * kBlock; base < a.n_in; base += stride) {
+    const uint32_t i = base + threadIdx.x;  // this lane's own entry
+    int32_t u = 0;
+    int64_t beg = 0, end = 0;
+    if (i < a.n_in) {
+      u = queue_at(a, qi, i);
+      beg = a.offs[u];
+      end = a.offs[u + 1];
+    }
+    for (int j = 0; j < W; ++j) {
+      const int src = first + j;
+      const int32_t uj = __shfl(u, src);
+      const int64_t bj = __shfl(beg, src);
+      const int64_t ej = __shfl(end, src);
+      for (int64_t e = bj + sub; e < ej; e += W) visit(st, a, a.cols[e], uj);
+    }
   }
-  for (int j = 0; j < W; ++j) {
-    const int src = first + j;
-    const int32_t uj = __shfl(u, src);
-    const int64_t bj = __shfl(beg, src);
-    const int64_t ej = __shfl(end, src);
-    for (int64_t e = bj + sub; e < ej; e += W) visit(a, a.cols[e], uj);
-  }
+  stage_flush(st, a);
 }
 
 // ------------------------------------------------ push_edge (lane / frontier edge)
-// Phase 1: per-entry degree, block-local exclusive scan.
+// Phase 1: per-entry degree and row start, block-local exclusive scan.
 __global__ void __launch_bounds__(kBlock) k_edge_scan_local(Args a, int64_t* __restrict__ scan,
                                                             int64_t* __restrict__ ebeg,
                                                             int64_t* __restrict__ bsum) {
+  __shared__ int64_t wsum[kWaves];
+  __shared__ QueueIn qi;
   clear_ahead(a);
-  __shared__ int64_t wsum[kBlock / 64];
+  queue_in_load(a, qi);
   const int lane = lane_id();
   const int wid = threadIdx.x >> 6;
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
@@ -192,14 +275,13 @@ __global__ void __launch_bounds__(kBlock) k_edge_scan_local(Args a, int64_t* __r
     const int64_t i = base + k;
     deg[k] = 0;
     if (i < a.n_in) {
-      const int32_t u = a.qin[i];
+      const int32_t u = queue_at(a, qi, (uint32_t)i);
       const int64_t b = a.offs[u];
       ebeg[i] = b;
       deg[k] = a.offs[u + 1] - b;
     }
     tot += deg[k];
   }
-  // inclusive scan of per-thread totals within the wave
   int64_t inc = tot;
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
@@ -208,9 +290,8 @@ __global__ void __launch_bounds__(kBlock) k_edge_scan_local(Args a, int64_t* __r
   }
   if (lane == 63) wsum[wid] = inc;
   __syncthreads();
-  int64_t wpre = 0;
-  for (int k = 0; k < wid; ++k) wpre += wsum[k];
-  int64_t run = wpre + inc - tot;  // exclusive prefix of this thread within the block
+  int64_t run = inc - tot;
+  for (int k = 0; k < wid; ++k) run += wsum[k];
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t i = base + k;
@@ -275,6 +356,10 @@ __global__ void __launch_bounds__(kBlock) k_edge_expand(Args a, const int64_t* _
   __shared__ int64_t s_beg[kEdgeWin];
   __shared__ int32_t s_u[kEdgeWin];
   __shared__ int64_t s_range[2];
+  __shared__ Stage st;
+  __shared__ QueueIn qi;
+  stage_init(st);
+  queue_in_load(a, qi);
   const int64_t total = (int64_t)*etot;
   const int64_t ntiles = (total + kEdgeTile - 1) / kEdgeTile;
   const int64_t last = (int64_t)a.n_in - 1;
@@ -287,10 +372,10 @@ __global__ void __launch_bounds__(kBlock) k_edge_expand(Args a, const int64_t* _
     const int64_t span = i1 - i0 + 1;
     const bool staged = span <= kEdgeWin;
     if (staged) {
-      for (int64_t k = threadIdx.x; k < span; k += blockDim.x) {
+      for (int64_t k = threadIdx.x; k < span; k += kBlock) {
         s_start[k] = gscan(scan, bsum, i0 + k);
         s_beg[k] = ebeg[i0 + k];
-        s_u[k] = a.qin[i0 + k];
+        s_u[k] = queue_at(a, qi, (uint32_t)(i0 + k));
       }
     }
     __syncthreads();
@@ -299,95 +384,140 @@ __global__ void __launch_bounds__(kBlock) k_edge_expand(Args a, const int64_t* _
       const bool live = t <= t1;
       int32_t v = 0, u = 0;
       if (live) {
-        int64_t j, st, eb;
+        int64_t st0, eb;
         if (staged) {
           int64_t lo = 0, hi = span - 1;
           while (lo < hi) {
             const int64_t mid = lo + (hi - lo + 1) / 2;
             if (s_start[mid] <= t) lo = mid; else hi = mid - 1;
           }
-          st = s_start[lo];
+          st0 = s_start[lo];
           eb = s_beg[lo];
           u = s_u[lo];
-          j = lo;
         } else {
-          j = find_entry(scan, bsum, i0, i1, t);
-          st = gscan(scan, bsum, j);
+          const int64_t j = find_entry(scan, bsum, i0, i1, t);
+          st0 = gscan(scan, bsum, j);
           eb = ebeg[j];
-          u = a.qin[j];
+          u = queue_at(a, qi, (uint32_t)j);
         }
-        (void)j;
-        v = a.cols[eb + (t - st)];
+        v = a.cols[eb + (t - st0)];
       }
       bool win = false;
       if (live) {
         win = claim(a.vis, v);
         if (win) settle(a, v, u);
       }
-      wave_append(win, v, a.qout, &a.ctr->n_next);
+      stage_push(st, a, win, v);
     }
     __syncthreads();
   }
+  stage_flush(st, a);
 }
 
 // ------------------------------------------- pull_bitmap (wave / 64-vertex word)
+// Each lane owns one vertex of the word.  An unvisited vertex looks for a
+// neighbour in the frontier bitmap, in row order, and stops at the first one
+// (Section III-A, vertex pull).  Phase 1: every lane probes the first
+// kPullEager neighbours of its row with independent loads (many misses in
+// flight instead of one dependent chain).  Phase 2: rows that are longer and
+// still unresolved are scanned by the whole wavefront, 64 neighbours per step,
+// one row at a time -- a high-degree row no longer stalls its wave for
+// deg(v) dependent steps.  Every word of the depth-(d+1) bitmap is written.
 __global__ void __launch_bounds__(kBlock) k_pull(Args a) {
+  __shared__ Stage st;
   clear_ahead(a);
+  stage_init(st);
   const int lane = lane_id();
-  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  if (w >= a.nw) return;  // whole wave
-  const u64 seen = a.vis[w];
-  const u64 todo = ~seen;
-  if (todo == 0ull) return;  // whole wave
-  const int32_t v = (int32_t)(w * 64 + lane);
-  bool found = false;
-  int32_t par = -1;
-  if ((todo >> lane) & 1ull) {
-    const int64_t end = a.offs[v + 1];
-    for (int64_t e = a.offs[v]; e < end; ++e) {
-      const int32_t u = a.cols[e];
-      if ((a.fr[u >> 6] >> (u & 63)) & 1ull) {
-        found = true;
-        par = u;
-        break;
-      }
+  const int64_t nwaves = (int64_t)gridDim.x * kWaves;
+  for (int64_t w = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6; w < a.nw; w += nwaves) {
+    const u64 seen = a.vis[w];
+    const u64 todo = ~seen;
+    if (todo == 0ull) {  // whole wave
+      if (lane == 0) a.nx[w] = 0ull;
+      continue;
     }
+    const int32_t v = (int32_t)(w * 64 + lane);
+    const bool mine = (todo >> lane) & 1ull;
+    int64_t beg = 0, end = 0;
+    if (mine) {
+      beg = a.offs[v];
+      end = a.offs[v + 1];
+    }
+    int32_t u[kPullEager];
+    u64 fw[kPullEager];
+#pragma unroll
+    for (int k = 0; k < kPullEager; ++k) u[k] = beg + k < end ? a.cols[beg + k] : -1;
+#pragma unroll
+    for (int k = 0; k < kPullEager; ++k) fw[k] = u[k] >= 0 ? a.fr[u[k] >> 6] : 0ull;
+    int32_t par = -1;
+#pragma unroll
+    for (int k = kPullEager - 1; k >= 0; --k)
+      if (u[k] >= 0 && ((fw[k] >> (u[k] & 63)) & 1ull)) par = u[k];
+    u64 rest = __ballot(mine && par < 0 && end - beg > kPullEager);
+    while (rest != 0ull) {
+      const int owner = __ffsll((long long)rest) - 1;
+      rest &= rest - 1ull;
+      const int64_t lo = __shfl(beg, owner) + kPullEager;
+      const int64_t hi = __shfl(end, owner);
+      int32_t hit = -1;
+      for (int64_t c = lo; c < hi; c += 64) {
+        const int64_t e = c + lane;
+        int32_t x = -1;
+        bool h = false;
+        if (e < hi) {
+          x = a.cols[e];
+          h = (a.fr[x >> 6] >> (x & 63)) & 1ull;
+        }
+        const u64 hm = __ballot(h);
+        if (hm != 0ull) {
+          hit = __shfl(x, __ffsll((long long)hm) - 1);
+          break;
+        }
+      }
+      if (lane == owner) par = hit;
+    }
+    const bool found = par >= 0;
+    const u64 fm = __ballot(found);
+    if (found) {
+      a.level[v] = a.d + 1;
+      if (a.parent) a.parent[v] = par;
+    }
+    if (lane == 0) {
+      a.nx[w] = fm;
+      if (fm) a.vis[w] = seen | fm;  // this wave is the word's only writer in a pull level
+    }
+    stage_push(st, a, found, v);
   }
-  const u64 fm = __ballot(found);
-  if (fm == 0ull) return;
-  if (found) {
-    a.level[v] = a.d + 1;
-    if (a.parent) a.parent[v] = par;
-  }
-  uint32_t base = 0;
-  if (lane == 0) {
-    a.vis[w] = seen | fm;  // this wave is the word's only writer in a pull level
-    a.nx[w] = fm;
-    base = atomicAdd(&a.ctr->n_next, (uint32_t)__popcll(fm));
-  }
-  base = (uint32_t)__shfl((int)base, 0);
-  if (found) a.qout[base + (uint32_t)__popcll(fm & lanes_below(lane))] = v;
+  stage_flush(st, a);
 }
 
 // ------------------------------------------ vertex_scan (lane / vertex, all n)
 __global__ void __launch_bounds__(kBlock) k_vertex_scan(Args a) {
+  __shared__ Stage st;
   clear_ahead(a);
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t beg = 0, end = 0;
-  if (v < a.n && a.level[v] == a.d) {
-    beg = a.offs[v];
-    end = a.offs[v + 1];
+  stage_init(st);
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t base = (int64_t)blockIdx.x * kBlock; base < a.n; base += stride) {
+    const int64_t v = base + threadIdx.x;
+    int64_t beg = 0, end = 0;
+    if (v < a.n && a.level[v] == a.d) {
+      beg = a.offs[v];
+      end = a.offs[v + 1];
+    }
+    for (int64_t e = beg; e < end; ++e) visit(st, a, a.cols[e], (int32_t)v);
   }
-  for (int64_t e = beg; e < end; ++e) visit(a, a.cols[e], (int32_t)v);
+  stage_flush(st, a);
 }
 
 // -------------------------------------------- edge_scan (lane / arc, all arcs)
 __global__ void __launch_bounds__(kBlock) k_edge_scan(Args a) {
+  __shared__ Stage st;
   clear_ahead(a);
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  stage_init(st);
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
   // uniform trip count so every lane of a wave reaches the ballots together
   const int64_t rounds = (a.nnz + stride - 1) / stride;
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   for (int64_t r = 0; r < rounds; ++r, e += stride) {
     bool win = false;
     int32_t v = 0;
@@ -399,11 +529,47 @@ __global__ void __launch_bounds__(kBlock) k_edge_scan(Args a) {
         if (win) settle(a, v, u);
       }
     }
-    wave_append(win, v, a.qout, &a.ctr->n_next);
+    stage_push(st, a, win, v);
   }
+  stage_flush(st, a);
 }
 
 // ------------------------------------------------------------ helpers
+__global__ void __launch_bounds__(kBlock) k_isolated(const int64_t* __restrict__ offs,
+                                                     u64* __restrict__ iso, int64_t n, int64_t nw) {
+  const int lane = lane_id();
+  const int64_t nwaves = (int64_t)gridDim.x * kWaves;
+  for (int64_t w = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6; w < nw; w += nwaves) {
+    const int64_t v = w * 64 + lane;
+    const u64 m = __ballot(v < n && offs[v + 1] == offs[v]);
+    if (lane == 0) iso[w] = m;
+  }
+}
+
+// Sum of a counter slot's segments, stored to host memory for the level loop.
+__global__ void __launch_bounds__(64) k_finalize(const uint32_t* __restrict__ cslot,
+                                                 uint32_t* host_flag) {
+  const int lane = lane_id();
+  uint32_t x = lane < kQueueBins ? cslot[lane * kCtrStride] : 0u;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += (uint32_t)__shfl_xor((int)x, off);
+  if (lane == 0) __hip_atomic_store(host_flag, x, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Frontier bitmap of depth d from the level array (before a pull level that
+// follows a top-down level).
+__global__ void __launch_bounds__(kBlock) k_frontier_bitmap(const int32_t* __restrict__ level,
+                                                            int32_t d, u64* __restrict__ bm,
+                                                            int64_t n, int64_t nw) {
+  const int lane = lane_id();
+  const int64_t nwaves = (int64_t)gridDim.x * kWaves;
+  for (int64_t w = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6; w < nw; w += nwaves) {
+    const int64_t v = w * 64 + lane;
+    const u64 m = __ballot(v < n && level[v] == d);
+    if (lane == 0) bm[w] = m;
+  }
+}
+
 __global__ void __launch_bounds__(kBlock) k_canonical_parents(const int64_t* __restrict__ offs,
                                                               const int32_t* __restrict__ cols,
                                                               const int32_t* __restrict__ level,
@@ -440,11 +606,11 @@ Args to_args(const LevelLaunch& l) {
   a.vis = l.vis;
   a.fr = l.fr;
   a.nx = l.nx;
-  a.clr = l.clr;
   a.qin = l.qin;
+  a.cin = l.cin;
   a.qout = l.qout;
-  a.ctr = l.ctr;
-  a.ctr_clr = l.ctr_clr;
+  a.cout = l.cout;
+  a.cclr = l.cclr;
   a.n = l.n;
   a.nw = l.nw;
   a.nnz = l.nnz;
@@ -455,19 +621,15 @@ Args to_args(const LevelLaunch& l) {
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Blocks needed so that clear_ahead touches each word at most kClearPerThread times.
-inline int64_t clear_blocks(int64_t nw) { return cdiv(nw, (int64_t)kBlock * kClearPerThread); }
-
-inline unsigned grid_of(int64_t work_blocks, int64_t nw) {
-  int64_t g = work_blocks > clear_blocks(nw) ? work_blocks : clear_blocks(nw);
-  if (g < 1) g = 1;
-  return (unsigned)g;
+inline unsigned persistent_grid(int64_t work_blocks) {
+  if (work_blocks < 1) return 1u;
+  return (unsigned)(work_blocks < kMaxGrid ? work_blocks : kMaxGrid);
 }
 
 template <int W>
 void push_wave_launch(const Args& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_push_wave<W>, dim3(grid_of(cdiv(a.n_in, kBlock), a.nw)), dim3(kBlock), 0, s,
-                     a);
+  hipLaunchKernelGGL(k_push_wave<W>, dim3(persistent_grid(cdiv(a.n_in, kBlock))), dim3(kBlock), 0,
+                     s, a);
 }
 
 }  // namespace
@@ -477,10 +639,11 @@ bool kernel_is_pull(int k) { return k == GSW_K_PULL_BITMAP; }
 gsw_status launch_init(const gsw_graph* g, int32_t* level, int32_t* parent, int32_t source,
                        hipStream_t s) {
   const Workspace& w = g->ws;
-  const int64_t blocks = cdiv(g->n, kBlock * 4);
-  const unsigned grid = (unsigned)(blocks < 1 ? 1 : (blocks > 65536 ? 65536 : blocks));
-  hipLaunchKernelGGL(k_init, dim3(grid), dim3(kBlock), 0, s, level, parent, w.vis, w.bm[0], w.bm[1],
-                     w.bm[2], w.q[0], w.ctr, g->n, w.nw, source);
+  int64_t blocks = cdiv(g->n, kBlock * 4);
+  if (blocks < cdiv(4 * kCtrSlot, kBlock)) blocks = cdiv(4 * kCtrSlot, kBlock);
+  const unsigned grid = (unsigned)(blocks > 65536 ? 65536 : blocks);
+  hipLaunchKernelGGL(k_init, dim3(grid), dim3(kBlock), 0, s, level, parent, w.vis, w.bm[0], g->iso,
+                     w.q[0], w.ctr, g->n, w.nw, source);
   GSW_HIP(hipGetLastError());
   return GSW_OK;
 }
@@ -489,8 +652,8 @@ gsw_status launch_level(const gsw_graph* g, int kernel, const LevelLaunch& l, hi
   const Args a = to_args(l);
   switch (kernel) {
     case GSW_K_PUSH_VERTEX:
-      hipLaunchKernelGGL(k_push_vertex, dim3(grid_of(cdiv(a.n_in, kBlock), a.nw)), dim3(kBlock), 0,
-                         s, a);
+      hipLaunchKernelGGL(k_push_vertex, dim3(persistent_grid(cdiv(a.n_in, kBlock))), dim3(kBlock),
+                         0, s, a);
       break;
     case GSW_K_PUSH_WAVE4: push_wave_launch<4>(a, s); break;
     case GSW_K_PUSH_WAVE8: push_wave_launch<8>(a, s); break;
@@ -500,31 +663,50 @@ gsw_status launch_level(const gsw_graph* g, int kernel, const LevelLaunch& l, hi
     case GSW_K_PUSH_EDGE: {
       const Workspace& w = g->ws;
       const int64_t nb = cdiv(a.n_in, kScanTile);
-      hipLaunchKernelGGL(k_edge_scan_local, dim3(grid_of(nb, a.nw)), dim3(kBlock), 0, s, a, w.scan,
+      hipLaunchKernelGGL(k_edge_scan_local, dim3((unsigned)nb), dim3(kBlock), 0, s, a, w.scan,
                          w.ebeg, w.bsum);
       hipLaunchKernelGGL(k_edge_scan_blocks, dim3(1), dim3(1024), 0, s, w.bsum, nb, w.etot);
-      // enough tiles in flight to fill the chip; tiles are grid-strided
-      hipLaunchKernelGGL(k_edge_expand, dim3(2048), dim3(kBlock), 0, s, a, w.scan, w.ebeg, w.bsum,
-                         w.etot);
+      hipLaunchKernelGGL(k_edge_expand, dim3(kMaxGrid), dim3(kBlock), 0, s, a, w.scan, w.ebeg,
+                         w.bsum, w.etot);
       break;
     }
     case GSW_K_PULL_BITMAP:
-      hipLaunchKernelGGL(k_pull, dim3(grid_of(cdiv(a.nw * 64, kBlock), a.nw)), dim3(kBlock), 0, s,
-                         a);
+      hipLaunchKernelGGL(k_pull, dim3(persistent_grid(cdiv(a.nw, kWaves))), dim3(kBlock), 0, s, a);
       break;
     case GSW_K_VERTEX_SCAN:
-      hipLaunchKernelGGL(k_vertex_scan, dim3(grid_of(cdiv(a.n, kBlock), a.nw)), dim3(kBlock), 0, s,
-                         a);
+      hipLaunchKernelGGL(k_vertex_scan, dim3(persistent_grid(cdiv(a.n, kBlock))), dim3(kBlock), 0,
+                         s, a);
       break;
-    case GSW_K_EDGE_SCAN: {
-      int64_t blocks = cdiv(a.nnz, kBlock * 8);
-      if (blocks > 8192) blocks = 8192;
-      hipLaunchKernelGGL(k_edge_scan, dim3(grid_of(blocks, a.nw)), dim3(kBlock), 0, s, a);
+    case GSW_K_EDGE_SCAN:
+      hipLaunchKernelGGL(k_edge_scan, dim3(persistent_grid(cdiv(a.nnz, kBlock))), dim3(kBlock), 0,
+                         s, a);
       break;
-    }
     default:
       return fail(GSW_EINVAL, "unknown kernel id %d", kernel);
   }
+  GSW_HIP(hipGetLastError());
+  return GSW_OK;
+}
+
+gsw_status launch_frontier_bitmap(const gsw_graph* g, const int32_t* level, int32_t d,
+                                  unsigned long long* bm, hipStream_t s) {
+  const int64_t nw = g->ws.nw;
+  hipLaunchKernelGGL(k_frontier_bitmap, dim3(persistent_grid(cdiv(nw, kWaves))), dim3(kBlock), 0, s,
+                     level, d, bm, g->n, nw);
+  GSW_HIP(hipGetLastError());
+  return GSW_OK;
+}
+
+gsw_status launch_isolated(const gsw_graph* g, unsigned long long* iso, hipStream_t s) {
+  const int64_t nw = (g->n + 63) / 64;
+  hipLaunchKernelGGL(k_isolated, dim3(persistent_grid(cdiv(nw, kWaves))), dim3(kBlock), 0, s,
+                     g->offs, iso, g->n, nw);
+  GSW_HIP(hipGetLastError());
+  return GSW_OK;
+}
+
+gsw_status launch_finalize(const uint32_t* cslot, uint32_t* d_flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, cslot, d_flag);
   GSW_HIP(hipGetLastError());
   return GSW_OK;
 }
@@ -543,7 +725,5 @@ gsw_status launch_build_origin(const gsw_graph* g, int32_t* origin, hipStream_t 
   GSW_HIP(hipGetLastError());
   return GSW_OK;
 }
-
-int64_t edge_scan_blocks_needed(int64_t n) { return cdiv(n, kScanTile); }
 
 }  // namespace gsw
