@@ -2,18 +2,24 @@
 """Benchmark: GTEPS of tree-switched BFS on R-MAT scale 22 vs every fixed
 kernel and the best-per-level schedule, on one MI355X.
 
-One step = a tree-switched BFS (level loop, per-level kernel choice, all
-expansion kernels it picks) from each of the 64 seeded sources of the
+One step = a tree-switched BFS (level loop, per-level kernel choice, every
+expansion kernel it picks) from each of the 64 seeded sources of the
 workload.  GTEPS of a source = undirected edges of its component / time of
-its gsw_bfs call (graph upload and result copy-back excluded); the reported
-value is the harmonic mean over sources of the per-source median over steps.
+its gsw_bfs call (graph upload and result copy-back excluded, as in the
+paper's measurements); the reported value is the harmonic mean over sources
+of each source's median over the timed steps.
 
-Prints ONE JSON line.  Extra fields:
+Prints ONE JSON line.  Besides the contract fields:
   fixed            harmonic-mean GTEPS of each kernel used at every level
   best_per_level   GTEPS of replaying, per source, the fastest kernel of each
-                   level (measured from the same saved state)
-  roofline         dominant kernel of the timed region: algorithmic bytes per
-                   launch / mean launch time (HIP events on the launch stream)
+                   level (times measured from the same saved BFS state)
+  tree_agreement   share of levels where the tree picked that fastest kernel
+  roofline         the dominant kernel of the switched path: algorithmic bytes
+                   per launch / mean launch time, from HIP events the library
+                   records on the launch stream around each level, in one
+                   instrumented pass over the same sources right after the
+                   timed steps (the events add host time to every level, so
+                   the timed steps run without them)
   cpu_baseline     the CPU oracle on a bounded sample of the same sources
 """
 from __future__ import annotations
@@ -31,6 +37,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GTEPS (RMAT-22) switched vs best fixed kernel; batched p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+WORKLOAD_TEXT = {
+    "rmat22": "R-MAT scale 22 (4,194,304 vertices), edgefactor 16, A/B/C/D .57/.19/.19/.05, "
+              "seed 2, symmetrised, loops and repeats removed, int32 CSR with int64 offsets; "
+              "64 seeded sources of degree > 0",
+}
 
 
 def log(*a):
@@ -60,16 +71,23 @@ def cpu_baseline(g, srcs, m_c, budget_s):
     t_start = time.perf_counter()
     for i, s in enumerate(srcs):
         t0 = time.perf_counter()
-        lv = oracle.levels(g.offs, g.cols, int(s))
+        oracle.levels(g.offs, g.cols, int(s))
         times.append(time.perf_counter() - t0)
         edges.append(m_c[i])
         if time.perf_counter() - t_start > budget_s:
             break
     gteps = [e / t / 1e9 for e, t in zip(edges, times)]
-    return {"value": hmean(gteps), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+    return {"value": round(hmean(gteps), 4), "unit": "GTEPS", "cores": 1, "kind": "oracle",
             "sample": "%d of %d sources of the same workload, single-threaded FIFO BFS, %.1f s"
                       % (len(times), len(srcs), sum(times)),
             "cpu": cpu_model()}
+
+
+def timed(runner, src, sync):
+    sync()
+    t0 = time.perf_counter()
+    runner.run(int(src))
+    return time.perf_counter() - t0
 
 
 def main():
@@ -104,6 +122,7 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     torch.cuda.set_device(0)
+    sync = torch.cuda.synchronize
 
     t = time.perf_counter()
     g = gg.workload(args.workload)
@@ -120,13 +139,10 @@ def main():
     out_lv = torch.empty((1, n), dtype=torch.int32, device="cuda")
     out_pa = torch.empty((1, n), dtype=torch.int32, device="cuda")
     deg = g.degrees()
-
-    def run(src, **kw):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, _, tr = gsw.bfs(G, [int(src)], device=True, out=(out_lv, out_pa), **kw)
-        dt = time.perf_counter() - t0
-        return dt, tr
+    sw = gsw.Runner(G, out_lv, out_pa, policy="tree", tree=tree)
+    # the same path with HIP events around every level's kernels (about 6 us
+    # of host time per level, so it is kept out of the timed steps)
+    sw_ev = gsw.Runner(G, out_lv, out_pa, policy="tree", tree=tree, time_levels=True)
 
     # warm-up (also: component sizes from the GPU's own levels, and the level
     # arrays of the first few sources for the byte model)
@@ -134,7 +150,7 @@ def main():
     keep_lv = {}
     for w in range(max(args.warmup, 1)):
         for i, s in enumerate(srcs):
-            run(s, policy="tree", tree=tree, time_levels=True)
+            sw.run(int(s))
             if w == 0:
                 lv = out_lv[0].cpu().numpy()
                 m_c[i] = int(deg[lv >= 0].sum() // 2)
@@ -145,20 +161,24 @@ def main():
     # timed region: K steps of the tree-switched path over every source
     per_src = np.zeros((args.steps, len(srcs)))
     traces = []
-    torch.cuda.synchronize()
+    sync()
     t_all = time.perf_counter()
     for k in range(args.steps):
         for i, s in enumerate(srcs):
-            dt, tr = run(s, policy="tree", tree=tree, time_levels=True)
-            per_src[k, i] = dt
-            traces.append((i, tr))
-    torch.cuda.synchronize()
+            per_src[k, i] = timed(sw, s, sync)
+    sync()
     wall = time.perf_counter() - t_all
     med = np.median(per_src, axis=0)
     gteps_src = m_c / med / 1e9
     value = hmean(gteps_src)
     ms_per_step = wall / args.steps * 1e3
-    log("switched: %.2f GTEPS (harmonic), %.1f ms/step" % (value, ms_per_step))
+    log("switched: %.2f GTEPS (harmonic), %.2f ms/step, %.3f ms median source"
+        % (value, ms_per_step, np.median(med) * 1e3))
+    # instrumented pass over the same sources: per-level kernel times
+    per_src_ev = np.zeros(len(srcs))
+    for i, s in enumerate(srcs):
+        per_src_ev[i] = timed(sw_ev, s, sync)
+        traces.append((i, sw_ev.rows()))
 
     # dominant kernel of the timed region and its roofline
     ktime = np.zeros(gsw.N_KERNELS)
@@ -186,25 +206,37 @@ def main():
                 "bytes_per_launch": int(b_sum / max(launches, 1)),
                 "mean_launch_ms": round(t_sum / max(launches, 1) * 1e3, 4),
                 "launches_sampled": launches,
+                "mean_launch_ms_all": round(float(ktime[dom] / max(kcount[dom], 1)), 4),
+                "launches_all": int(kcount[dom]),
                 "share_of_kernel_time": round(float(ktime[dom] / ktime.sum()), 3)}
+    kernel_ms = float(ktime.sum() / len(srcs))
+    roofline["instrumented_pass_median_source_ms"] = round(float(np.median(per_src_ev)) * 1e3, 4)
 
     extra = {}
     if not args.no_compare:
         fixed = {}
         for kern in range(gsw.N_KERNELS):
-            run(srcs[0], policy="fixed", kernel=kern)  # warm
-            ts = np.array([run(s, policy="fixed", kernel=kern)[0] for s in srcs])
+            fx = gsw.Runner(G, out_lv, out_pa, policy="fixed", kernel=kern)
+            fx.run(int(srcs[0]))  # warm
+            ts = np.array([timed(fx, s, sync) for s in srcs])
             fixed[gsw.KERNEL_NAMES[kern]] = round(hmean(m_c / ts / 1e9), 3)
             log("fixed %-12s %.2f GTEPS" % (gsw.KERNEL_NAMES[kern], fixed[gsw.KERNEL_NAMES[kern]]))
         best_fixed = max(fixed, key=fixed.get)
         # best-per-level schedule: fastest kernel per level from the same saved state
-        t_bpl, t_sw = [], []
+        t_bpl, agree, levels_total, regret = [], 0, 0, 0.0
+        sched_runner = gsw.Runner(G, out_lv, out_pa, policy="schedule", schedule=[0])
+        last_trace = dict(traces)  # the last timed step's choices per source
         for i, s in enumerate(srcs):
-            times, _, _ = gsw.bfs_profile(G, int(s), reps=args.profile_reps)
+            times, _, _ = gsw.bfs_profile(G, int(s), reps=args.profile_reps, advance_kernel=-1)
             sched = np.argmin(times, axis=1).astype(np.int32)
-            run(s, policy="schedule", schedule=sched)
-            t_bpl.append(np.median([run(s, policy="schedule", schedule=sched)[0]
-                                    for _ in range(max(args.steps, 1))]))
+            sched_runner.set_schedule(sched)
+            sched_runner.run(int(s))
+            t_bpl.append(np.median([timed(sched_runner, s, sync) for _ in range(max(args.steps, 1))]))
+            picks = [r.kernel for r in last_trace[i]]
+            for d, kk in enumerate(picks[:len(sched)]):
+                agree += int(kk == sched[d])
+                regret += float(times[d, kk] - times[d, sched[d]])
+                levels_total += 1
         t_bpl = np.array(t_bpl)
         gteps_bpl = hmean(m_c / t_bpl / 1e9)
         extra = {
@@ -212,9 +244,12 @@ def main():
             "best_fixed": {"kernel": best_fixed, "gteps": fixed[best_fixed]},
             "switched_over_best_fixed": round(value / fixed[best_fixed], 3),
             "best_per_level": {"gteps": round(gteps_bpl, 3)},
-            "switched_time_over_best_per_level": round(float(med.sum() / t_bpl.sum()), 3),
+            "switched_time_over_best_per_level": round(float(med.sum() / t_bpl.sum()), 4),
+            "tree_agreement": {"levels": levels_total, "fastest_picked": round(agree / max(levels_total, 1), 3),
+                               "mean_regret_ms_per_source": round(regret / len(srcs), 4)},
         }
-        log("best fixed %s %.2f; best-per-level %.2f GTEPS" % (best_fixed, fixed[best_fixed], gteps_bpl))
+        log("best fixed %s %.2f; best-per-level %.2f GTEPS; tree picked the fastest at %d/%d levels"
+            % (best_fixed, fixed[best_fixed], gteps_bpl, agree, levels_total))
 
     cpu = cpu_baseline(g, srcs, m_c, args.cpu_budget)
     log("cpu oracle %.3f GTEPS" % cpu["value"])
@@ -224,15 +259,15 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": "%s: R-MAT scale 22, edgefactor 16, A/B/C/D .57/.19/.19/.05, "
-                               "seed 2, symmetric int32 CSR (int64 offsets)" % args.workload
-                   if args.workload == "rmat22" else args.workload,
+        "config": {"workload": WORKLOAD_TEXT.get(args.workload, args.workload),
                    "n": g.n, "nnz": g.nnz, "sources": len(srcs), "source_seed": int(seed),
                    "tree": tree_name, "policy": "tree-switched per level"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernel_time_share": {gsw.KERNEL_NAMES[k]: round(float(ktime[k] / ktime.sum()), 3)
                               for k in range(gsw.N_KERNELS) if kcount[k]},
+        "kernel_ms_per_source": round(kernel_ms, 4),
+        "median_source_ms": round(float(np.median(med) * 1e3), 4),
         "gteps_median_source": round(float(np.median(gteps_src)), 3),
     }
     line.update(extra)

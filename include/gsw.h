@@ -118,7 +118,9 @@ typedef struct {
   const int32_t *schedule;   /* GSW_POLICY_SCHEDULE: kernel per level (host array); */
   int32_t schedule_len;      /*   levels beyond the end repeat the last entry */
   const gsw_tree *tree;      /* GSW_POLICY_TREE */
-  int32_t time_levels;       /* 1: fill gsw_level_trace.ms with HIP event times */
+  int32_t time_levels;       /* 1: fill gsw_level_trace.ms with HIP event times (events
+                                recorded on the work stream around each level's kernels,
+                                read once the BFS has finished; first 8192 levels) */
   int32_t canonical_parents; /* 1: parent[v] = smallest neighbour one level up */
   int32_t device_ptrs;       /* 1: levels/parents are device pointers; 0: host */
   int32_t reserved0;
@@ -213,7 +215,8 @@ gsw_status gsw_bfs(const gsw_graph *g, const int32_t *sources, int32_t n_sources
  * training data of Section IV-A).  At each level the state is saved, each
  * kernel in kernels[0..n_kernels) runs `reps` times from the saved state and
  * times[level*n_kernels + k] receives the median kernel time in ms; then the
- * BFS advances one level with advance_kernel.  frontier[level] receives
+ * BFS advances one level with advance_kernel (or, when advance_kernel < 0,
+ * with the fastest kernel just measured).  frontier[level] receives
  * n_f(level).  Stops at max_levels rows (GSW_ERANGE if the BFS is longer).
  * Kernels that cannot run on this graph (pull on a non-symmetric graph) get
  * a time of -1.

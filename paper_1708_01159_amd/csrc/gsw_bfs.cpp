@@ -140,6 +140,8 @@ gsw_status run_one(gsw_graph* g, const Policy& pol, int32_t src_idx, int32_t src
   int64_t nf = 1, disc = 1;
   int prev = GSW_DEFAULT_KERNEL;
   bool fr_valid = true;  // init wrote the depth-0 bitmap
+  const int32_t row0 = *rows;
+  int32_t timed = 0;  // levels bracketed by events (read after the last level)
   for (int32_t d = 0;; ++d) {
     int32_t flags = 0;
     const int k = pol.choose(g, d, nf, disc, prev, &flags);
@@ -147,18 +149,24 @@ gsw_status run_one(gsw_graph* g, const Policy& pol, int32_t src_idx, int32_t src
     const LevelLaunch l = level_args(g, lv, pa, d, (uint32_t)nf);
     const size_t slot = (size_t)(d % kFlagSlots) * 64;
     w.h_flag[slot] = kNotReady;
-    if (o->time_levels) GSW_HIP(hipEventRecord(w.ev[0], s));
+    const bool timing = o->time_levels && d < kMaxTimedLevels && *rows < trace_cap;
+    if (timing) {
+      while (w.lev.size() < 2 * (size_t)(d + 1)) {
+        hipEvent_t e;
+        GSW_HIP(hipEventCreate(&e));
+        w.lev.push_back(e);
+      }
+      GSW_HIP(hipEventRecord(w.lev[2 * (size_t)d], s));
+    }
     GSW_TRY(run_level(g, k, l, fr_valid, s));
-    if (o->time_levels) GSW_HIP(hipEventRecord(w.ev[1], s));
+    if (timing) {
+      GSW_HIP(hipEventRecord(w.lev[2 * (size_t)d + 1], s));
+      timed = d + 1;
+    }
     GSW_TRY(launch_finalize(l.cout, w.d_flag + slot, s));
     fr_valid = kernel_is_pull(k);
     int64_t nn = 0;
     GSW_TRY(wait_next(g, d, s, &nn));
-    float ms = -1.0f;
-    if (o->time_levels) {
-      GSW_HIP(hipEventSynchronize(w.ev[1]));
-      GSW_HIP(hipEventElapsedTime(&ms, w.ev[0], w.ev[1]));
-    }
     if (trace && *rows < trace_cap) {
       gsw_level_trace& t = trace[*rows];
       t.source_idx = src_idx;
@@ -168,7 +176,7 @@ gsw_status run_one(gsw_graph* g, const Policy& pol, int32_t src_idx, int32_t src
       t.n_frontier = nf;
       t.discovered = disc;
       t.n_next = nn;
-      t.ms = ms;
+      t.ms = -1.0f;
       t.reserved = 0;
     }
     ++*rows;
@@ -179,6 +187,8 @@ gsw_status run_one(gsw_graph* g, const Policy& pol, int32_t src_idx, int32_t src
   }
   if (o->canonical_parents && pa) GSW_TRY(launch_canonical_parents(g, lv, pa, s));
   GSW_HIP(hipStreamSynchronize(s));
+  for (int32_t d = 0; d < timed && trace && row0 + d < trace_cap; ++d)
+    GSW_HIP(hipEventElapsedTime(&trace[row0 + d].ms, w.lev[2 * (size_t)d], w.lev[2 * (size_t)d + 1]));
   return GSW_OK;
 }
 
@@ -269,7 +279,7 @@ gsw_status gsw_bfs_profile(const gsw_graph* cg, int32_t source, const int32_t* k
   if (source < 0 || source >= g->n) return fail(GSW_EINVAL, "source %d out of range", source);
   for (int32_t i = 0; i < n_kernels; ++i)
     if (kernels[i] < 0 || kernels[i] >= GSW_N_KERNELS) return fail(GSW_EINVAL, "bad kernel id %d", kernels[i]);
-  GSW_TRY(check_kernel(g, advance_kernel));
+  if (advance_kernel >= 0) GSW_TRY(check_kernel(g, advance_kernel));
   std::lock_guard<std::mutex> lock(g->mu);
   GSW_HIP(hipSetDevice(g->device));
   GSW_TRY(ensure_workspace(g));
@@ -345,9 +355,21 @@ gsw_status gsw_bfs_profile(const gsw_graph* cg, int32_t source, const int32_t* k
       std::sort(samples.begin(), samples.end());
       times[(size_t)d * n_kernels + ki] = samples[(size_t)reps / 2];
     }
+    // advance with the given kernel, or with this level's fastest one
+    int adv = advance_kernel;
+    if (adv < 0) {
+      float best = 0.0f;
+      for (int32_t ki = 0; ki < n_kernels; ++ki) {
+        const float t = times[(size_t)d * n_kernels + ki];
+        if (t >= 0.0f && (adv < 0 || t < best)) {
+          best = t;
+          adv = kernels[ki];
+        }
+      }
+    }
     GSW_TRY(restore());
-    GSW_TRY(run_level(g, advance_kernel, l, fr_valid, s));
-    fr_valid = kernel_is_pull(advance_kernel);
+    GSW_TRY(run_level(g, adv, l, fr_valid, s));
+    fr_valid = kernel_is_pull(adv);
     int64_t nn = 0;
     GSW_TRY(read_next(g, d, s, &nn, bins));
     if (frontier) frontier[d] = nf;

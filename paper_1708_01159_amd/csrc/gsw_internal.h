@@ -59,6 +59,7 @@ struct Workspace {
   uint32_t* h_flag = nullptr;            // mapped host memory: frontier size per level slot
   uint32_t* d_flag = nullptr;            // the same memory as seen by the device
   hipEvent_t ev[2] = {};
+  std::vector<hipEvent_t> lev;           // per-level timing events (2 per level), grown on use
   size_t bytes = 0;
 };
 
@@ -128,5 +129,7 @@ bool kernel_is_pull(int k);
 // Marker of a level-size slot in host memory that the device has not written.
 constexpr uint32_t kNotReady = 0xffffffffu;
 constexpr int kFlagSlots = 4;
+// Levels of one BFS whose kernel time time_levels records (later levels get -1).
+constexpr int kMaxTimedLevels = 8192;
 
 }  // namespace gsw

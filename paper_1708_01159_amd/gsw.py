@@ -339,6 +339,46 @@ def bfs(graph: Graph, sources, policy: str = "tree", kernel: int = PUSH_VERTEX, 
     return lv, pa, rows
 
 
+class Runner:
+    """Repeated single-source BFS on one graph with arguments marshalled once.
+
+    ``run(source)`` calls gsw_bfs directly (levels/parents in the given
+    device tensors, trace rows in a reusable buffer) and returns the number
+    of trace rows; ``rows()`` decodes them on demand.
+    """
+
+    def __init__(self, graph: Graph, levels, parents=None, policy: str = "tree", kernel=PUSH_VERTEX,
+                 schedule=None, tree: Tree = None, time_levels: bool = False, stream=None,
+                 trace_cap: int = 4096):
+        import torch
+
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.graph, self.levels, self.parents, self.tree = graph, levels, parents, tree
+        self.opts, self._keep = _opts(policy, kernel, schedule, tree, time_levels, False, True, stream)
+        self.trace = (LevelTrace * trace_cap)()
+        self.cap = trace_cap
+        self.tlen = ctypes.c_int32(0)
+        self.src = np.zeros(1, dtype=np.int32)
+        self._args = None
+
+    def set_schedule(self, schedule):
+        self._keep = np.ascontiguousarray(schedule, dtype=np.int32)
+        self.opts.schedule = self._keep.ctypes.data
+        self.opts.schedule_len = self._keep.shape[0]
+
+    def run(self, source: int) -> int:
+        self.src[0] = source
+        _check(lib().gsw_bfs(self.graph.handle, self.src.ctypes.data, 1, _ptr(self.levels),
+                             _ptr(self.parents) if self.parents is not None else None, self.trace,
+                             self.cap, ctypes.byref(self.tlen), ctypes.byref(self.opts)))
+        return self.tlen.value
+
+    def rows(self):
+        return [TraceRow(t.source_idx, t.level, t.kernel, t.flags, t.n_frontier, t.discovered,
+                         t.n_next, t.ms) for t in self.trace[:min(self.tlen.value, self.cap)]]
+
+
 def bfs_profile(graph: Graph, source: int, kernels=None, reps: int = 5,
                 advance_kernel: int = PUSH_EDGE, max_levels: int = 100000, stream=None):
     """Per-level median time (ms) of each kernel from the same saved state.
