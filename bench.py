@@ -15,11 +15,14 @@ Prints ONE JSON line.  Besides the contract fields:
                    level (times measured from the same saved BFS state)
   tree_agreement   share of levels where the tree picked that fastest kernel
   roofline         the dominant kernel of the switched path: algorithmic bytes
-                   per launch / mean launch time, from HIP events the library
-                   records on the launch stream around each level, in one
-                   instrumented pass over the same sources right after the
-                   timed steps (the events add host time to every level, so
-                   the timed steps run without them)
+                   per launch / mean launch time, the time taken from the
+                   library's per-level device timers (every workgroup of the
+                   level's kernel stamps the GPU's constant-rate wall clock at
+                   entry and exit; the level lasts from the first entry to the
+                   last exit) in one instrumented pass over the same sources
+                   right after the timed steps; traffic = HBM bytes per launch
+                   from the committed rocprofv3 counter summary, while the
+                   kernel source it was taken on is unchanged
   cpu_baseline     the CPU oracle on a bounded sample of the same sources
 """
 from __future__ import annotations
@@ -83,6 +86,26 @@ def cpu_baseline(g, srcs, m_c, budget_s):
             "cpu": cpu_model()}
 
 
+def counter_traffic(kernel_name):
+    """HBM bytes per launch of ``kernel_name`` from the committed rocprofv3
+    counter summary, or None when that summary is missing, is for another
+    kernel, or was taken on a different kernel source."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "%s_rmat22.md" % kernel_name)
+    src = os.path.join(ROOT, "paper_1708_01159_amd", "csrc", "gsw_kernels.hip")
+    try:
+        text = open(path).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and
+                  line.split(": ", 1)[0] in ("traffic_bytes_per_launch", "kernel", "kernel_source_sha256"))
+    if fields.get("kernel") != kernel_name or fields.get("kernel_source_sha256") != sha:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def timed(runner, src, sync):
     sync()
     t0 = time.perf_counter()
@@ -103,6 +126,8 @@ def main():
     ap.add_argument("--profile-reps", type=int, default=3)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--roofline-sources", type=int, default=4)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 1 GiB device copy (scale for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -202,7 +227,7 @@ def main():
     achieved = b_sum / t_sum / 1e9 if t_sum > 0 else 0.0
     roofline = {"bound": "hbm", "kernel": gsw.KERNEL_NAMES[dom], "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None,
+                "traffic": counter_traffic(gsw.KERNEL_NAMES[dom]),
                 "bytes_per_launch": int(b_sum / max(launches, 1)),
                 "mean_launch_ms": round(t_sum / max(launches, 1) * 1e3, 4),
                 "launches_sampled": launches,
@@ -250,6 +275,20 @@ def main():
         }
         log("best fixed %s %.2f; best-per-level %.2f GTEPS; tree picked the fastest at %d/%d levels"
             % (best_fixed, fixed[best_fixed], gteps_bpl, agree, levels_total))
+
+    if args.copy_calib:
+        a = torch.empty(1 << 28, dtype=torch.int32, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        b.copy_(a)
+        ev0.record()
+        b.copy_(a)
+        ev1.record()
+        sync()
+        ms = ev0.elapsed_time(ev1)
+        extra["copy_calibration"] = {"bytes_read": a.numel() * 4, "bytes_written": a.numel() * 4,
+                                     "ms": round(ms, 4), "gbs": round(2 * a.numel() * 4 / ms / 1e6, 1)}
+        del a, b
 
     cpu = cpu_baseline(g, srcs, m_c, args.cpu_budget)
     log("cpu oracle %.3f GTEPS" % cpu["value"])

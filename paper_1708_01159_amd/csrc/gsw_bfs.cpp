@@ -65,6 +65,7 @@ LevelLaunch level_args(const gsw_graph* g, int32_t* lv, int32_t* pa, int32_t d, 
   l.qout = w.q[(d + 1) & 1];
   l.cout = w.ctr + (size_t)((d + 1) & 3) * kCtrSlot;
   l.cclr = w.ctr + (size_t)((d + 2) & 3) * kCtrSlot;
+  l.tst = nullptr;
   l.n = g->n;
   l.nw = w.nw;
   l.nnz = g->nnz;
@@ -150,20 +151,18 @@ gsw_status run_one(gsw_graph* g, const Policy& pol, int32_t src_idx, int32_t src
     const size_t slot = (size_t)(d % kFlagSlots) * 64;
     w.h_flag[slot] = kNotReady;
     const bool timing = o->time_levels && d < kMaxTimedLevels && *rows < trace_cap;
+    // the bitmap rebuild before a pull that follows a top-down level stays
+    // outside the timed bracket: trace ms is the expansion kernel(s) only
+    if (kernel_is_pull(k) && !fr_valid)
+      GSW_TRY(launch_frontier_bitmap(g, l.level, l.d, const_cast<unsigned long long*>(l.fr), s));
+    LevelLaunch lt = l;
     if (timing) {
-      while (w.lev.size() < 2 * (size_t)(d + 1)) {
-        hipEvent_t e;
-        GSW_HIP(hipEventCreate(&e));
-        w.lev.push_back(e);
-      }
-      GSW_HIP(hipEventRecord(w.lev[2 * (size_t)d], s));
-    }
-    GSW_TRY(run_level(g, k, l, fr_valid, s));
-    if (timing) {
-      GSW_HIP(hipEventRecord(w.lev[2 * (size_t)d + 1], s));
+      lt.tst = w.tst;
       timed = d + 1;
     }
-    GSW_TRY(launch_finalize(l.cout, w.d_flag + slot, s));
+    GSW_TRY(launch_level(g, k, lt, s));
+    GSW_TRY(launch_finalize(l.cout, w.d_flag + slot, timing ? w.tst : nullptr,
+                            timing ? w.lvl_ticks + d : nullptr, s));
     fr_valid = kernel_is_pull(k);
     int64_t nn = 0;
     GSW_TRY(wait_next(g, d, s, &nn));
@@ -187,8 +186,13 @@ gsw_status run_one(gsw_graph* g, const Policy& pol, int32_t src_idx, int32_t src
   }
   if (o->canonical_parents && pa) GSW_TRY(launch_canonical_parents(g, lv, pa, s));
   GSW_HIP(hipStreamSynchronize(s));
-  for (int32_t d = 0; d < timed && trace && row0 + d < trace_cap; ++d)
-    GSW_HIP(hipEventElapsedTime(&trace[row0 + d].ms, w.lev[2 * (size_t)d], w.lev[2 * (size_t)d + 1]));
+  if (timed > 0 && trace) {
+    GSW_HIP(hipMemcpyAsync(w.h_ticks, w.lvl_ticks, (size_t)timed * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, s));
+    GSW_HIP(hipStreamSynchronize(s));
+    for (int32_t d = 0; d < timed && row0 + d < trace_cap; ++d)
+      trace[row0 + d].ms = (float)((double)w.h_ticks[d] * w.tick_ms);
+  }
   return GSW_OK;
 }
 

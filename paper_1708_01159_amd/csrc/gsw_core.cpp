@@ -186,6 +186,28 @@ gsw_status ensure_workspace(gsw_graph* g) {
   }
   GSW_HIP(hipEventCreate(&w.ev[0]));
   GSW_HIP(hipEventCreate(&w.ev[1]));
+  {
+    // level timing: per-workgroup stamp slots (start = max, end = 0 when unused)
+    std::vector<unsigned long long> init(2 * (size_t)kStampBlocks);
+    for (size_t i = 0; i < init.size(); i += 2) {
+      init[i] = ~0ull;
+      init[i + 1] = 0ull;
+    }
+    const size_t tb = init.size() * sizeof(unsigned long long);
+    const size_t lb = (size_t)kMaxTimedLevels * sizeof(unsigned long long);
+    hipError_t e1 = hipMalloc((void**)&w.tst, tb);
+    hipError_t e2 = e1 == hipSuccess ? hipMalloc((void**)&w.lvl_ticks, lb) : e1;
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(GSW_ENOMEM, "hipMalloc for the level timers failed");
+    }
+    w.bytes += tb + lb;
+    GSW_HIP(hipMemcpy(w.tst, init.data(), tb, hipMemcpyHostToDevice));
+    GSW_HIP(hipHostMalloc((void**)&w.h_ticks, lb, hipHostMallocDefault));
+    int khz = 0;
+    GSW_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, g->device));
+    w.tick_ms = khz > 0 ? 1.0 / (double)khz : 0.0;
+  }
   return GSW_OK;
 }
 
@@ -222,8 +244,9 @@ void free_graph(gsw_graph* g) {
   if (g->iso) (void)hipFree(g->iso);
   for (hipEvent_t ev : w.ev)
     if (ev) (void)hipEventDestroy(ev);
-  for (hipEvent_t ev : w.lev)
-    if (ev) (void)hipEventDestroy(ev);
+  if (w.tst) (void)hipFree(w.tst);
+  if (w.lvl_ticks) (void)hipFree(w.lvl_ticks);
+  if (w.h_ticks) (void)hipHostFree(w.h_ticks);
   if (g->owns_csr) {
     if (g->offs) (void)hipFree((void*)g->offs);
     if (g->cols) (void)hipFree((void*)g->cols);

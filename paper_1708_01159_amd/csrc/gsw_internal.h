@@ -59,7 +59,10 @@ struct Workspace {
   uint32_t* h_flag = nullptr;            // mapped host memory: frontier size per level slot
   uint32_t* d_flag = nullptr;            // the same memory as seen by the device
   hipEvent_t ev[2] = {};
-  std::vector<hipEvent_t> lev;           // per-level timing events (2 per level), grown on use
+  unsigned long long* tst = nullptr;     // per-workgroup start/end wall-clock stamps of a level
+  unsigned long long* lvl_ticks = nullptr;  // per-level kernel duration in wall-clock ticks
+  unsigned long long* h_ticks = nullptr;    // pinned host copy of lvl_ticks
+  double tick_ms = 0.0;                     // milliseconds per wall-clock tick
   size_t bytes = 0;
 };
 
@@ -104,6 +107,7 @@ struct LevelLaunch {
   int32_t* qout;            // queue of depth d+1
   uint32_t* cout;           // its segment counters (zero on entry)
   uint32_t* cclr;           // counter slot to zero for the level after next
+  unsigned long long* tst;  // wall-clock stamps per workgroup (null: not timed)
   int64_t n, nw, nnz;
   uint32_t n_in;
   int32_t d;
@@ -115,7 +119,8 @@ gsw_status launch_level(const gsw_graph* g, int kernel, const LevelLaunch& a, hi
 gsw_status launch_frontier_bitmap(const gsw_graph* g, const int32_t* level, int32_t d,
                                   unsigned long long* bm, hipStream_t s);
 gsw_status launch_isolated(const gsw_graph* g, unsigned long long* iso, hipStream_t s);
-gsw_status launch_finalize(const uint32_t* cslot, uint32_t* d_flag, hipStream_t s);
+gsw_status launch_finalize(const uint32_t* cslot, uint32_t* d_flag, unsigned long long* tst,
+                           unsigned long long* ticks, hipStream_t s);
 gsw_status launch_canonical_parents(const gsw_graph* g, const int32_t* level, int32_t* parent,
                                     hipStream_t s);
 gsw_status launch_build_origin(const gsw_graph* g, int32_t* origin, hipStream_t s);
@@ -131,5 +136,8 @@ constexpr uint32_t kNotReady = 0xffffffffu;
 constexpr int kFlagSlots = 4;
 // Levels of one BFS whose kernel time time_levels records (later levels get -1).
 constexpr int kMaxTimedLevels = 8192;
+// Workgroups whose start/end stamps time a level (larger grids stamp from
+// their first kStampBlocks workgroups).
+constexpr int kStampBlocks = 4096;
 
 }  // namespace gsw

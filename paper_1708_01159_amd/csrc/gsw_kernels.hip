@@ -31,7 +31,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
-constexpr int kMaxGrid = 1024;                   // persistent producer grids
+constexpr int kMaxGrid = 2048;                   // persistent producer grids (8 per CU)
 constexpr int kStage = 2048;                     // LDS-staged queue entries per workgroup
 constexpr int kScanItems = 4;                    // push_edge: entries per thread in the scan
 constexpr int kScanTile = kBlock * kScanItems;   // entries per scan block
@@ -55,6 +55,7 @@ struct Args {
   int32_t* __restrict__ qout;
   uint32_t* cout;
   uint32_t* cclr;
+  u64* tst;
   int64_t n, nw, nnz;
   uint32_t n_in;
   int32_t d;
@@ -65,6 +66,22 @@ __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 __device__ __forceinline__ u64 lanes_below(int lane) { return (1ull << lane) - 1ull; }
 
 __device__ __forceinline__ int my_bin() { return (int)(blockIdx.x % kQueueBins); }
+
+// Level timing (only when a.tst is set): the first kStampBlocks workgroups
+// stamp the constant-rate wall clock at entry and exit; k_finalize reduces
+// the stamps to the level's duration.
+__device__ __forceinline__ void stamp_begin(const Args& a) {
+  if (a.tst && threadIdx.x == 0 && blockIdx.x < kStampBlocks)
+    a.tst[2 * blockIdx.x] = (u64)wall_clock64();
+}
+
+__device__ __forceinline__ void stamp_end(const Args& a) {
+  if (a.tst) {
+    __syncthreads();
+    if (threadIdx.x == 0 && blockIdx.x < kStampBlocks)
+      a.tst[2 * blockIdx.x + 1] = (u64)wall_clock64();
+  }
+}
 
 // Zero the counter slot that the level after next appends to.
 __device__ __forceinline__ void clear_ahead(const Args& a) {
@@ -201,6 +218,7 @@ __global__ void __launch_bounds__(kBlock) k_init(int32_t* __restrict__ level,
 
 // ------------------------------------------------- push_vertex (lane / vertex)
 __global__ void __launch_bounds__(kBlock) k_push_vertex(Args a) {
+  stamp_begin(a);
   __shared__ Stage st;
   __shared__ QueueIn qi;
   clear_ahead(a);
@@ -219,6 +237,7 @@ __global__ void __launch_bounds__(kBlock) k_push_vertex(Args a) {
     for (int64_t e = beg; e < end; ++e) visit(st, a, a.cols[e], u);
   }
   stage_flush(st, a);
+  stamp_end(a);
 }
 
 // ------------------------------------- push_wave<W> (W lanes / vertex, W vertices / group)
@@ -227,6 +246,7 @@ __global__ void __launch_bounds__(kBlock) k_push_vertex(Args a) {
 // the W lanes striding over each row together.
 template <int W>
 __global__ void __launch_bounds__(kBlock) k_push_wave(Args a) {
+  stamp_begin(a);
   __shared__ Stage st;
   __shared__ QueueIn qi;
   clear_ahead(a);
@@ -254,6 +274,7 @@ __global__ void __launch_bounds__(kBlock) k_push_wave(Args a) {
     }
   }
   stage_flush(st, a);
+  stamp_end(a);
 }
 
 // ------------------------------------------------ push_edge (lane / frontier edge)
@@ -261,6 +282,7 @@ __global__ void __launch_bounds__(kBlock) k_push_wave(Args a) {
 __global__ void __launch_bounds__(kBlock) k_edge_scan_local(Args a, int64_t* __restrict__ scan,
                                                             int64_t* __restrict__ ebeg,
                                                             int64_t* __restrict__ bsum) {
+  stamp_begin(a);
   __shared__ int64_t wsum[kWaves];
   __shared__ QueueIn qi;
   clear_ahead(a);
@@ -412,6 +434,7 @@ __global__ void __launch_bounds__(kBlock) k_edge_expand(Args a, const int64_t* _
     __syncthreads();
   }
   stage_flush(st, a);
+  stamp_end(a);
 }
 
 // ------------------------------------------- pull_bitmap (wave / 64-vertex word)
@@ -424,13 +447,18 @@ __global__ void __launch_bounds__(kBlock) k_edge_expand(Args a, const int64_t* _
 // one row at a time -- a high-degree row no longer stalls its wave for
 // deg(v) dependent steps.  Every word of the depth-(d+1) bitmap is written.
 __global__ void __launch_bounds__(kBlock) k_pull(Args a) {
+  stamp_begin(a);
   __shared__ Stage st;
   clear_ahead(a);
   stage_init(st);
   const int lane = lane_id();
   const int64_t nwaves = (int64_t)gridDim.x * kWaves;
-  for (int64_t w = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6; w < a.nw; w += nwaves) {
-    const u64 seen = a.vis[w];
+  int64_t w = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  u64 next_seen = w < a.nw ? a.vis[w] : ~0ull;
+  for (; w < a.nw; w += nwaves) {
+    const u64 seen = next_seen;
+    // the next word's visited mask is fetched while this word is worked on
+    if (w + nwaves < a.nw) next_seen = a.vis[w + nwaves];
     const u64 todo = ~seen;
     if (todo == 0ull) {  // whole wave
       if (lane == 0) a.nx[w] = 0ull;
@@ -489,10 +517,12 @@ __global__ void __launch_bounds__(kBlock) k_pull(Args a) {
     stage_push(st, a, found, v);
   }
   stage_flush(st, a);
+  stamp_end(a);
 }
 
 // ------------------------------------------ vertex_scan (lane / vertex, all n)
 __global__ void __launch_bounds__(kBlock) k_vertex_scan(Args a) {
+  stamp_begin(a);
   __shared__ Stage st;
   clear_ahead(a);
   stage_init(st);
@@ -507,10 +537,12 @@ __global__ void __launch_bounds__(kBlock) k_vertex_scan(Args a) {
     for (int64_t e = beg; e < end; ++e) visit(st, a, a.cols[e], (int32_t)v);
   }
   stage_flush(st, a);
+  stamp_end(a);
 }
 
 // -------------------------------------------- edge_scan (lane / arc, all arcs)
 __global__ void __launch_bounds__(kBlock) k_edge_scan(Args a) {
+  stamp_begin(a);
   __shared__ Stage st;
   clear_ahead(a);
   stage_init(st);
@@ -532,6 +564,7 @@ __global__ void __launch_bounds__(kBlock) k_edge_scan(Args a) {
     stage_push(st, a, win, v);
   }
   stage_flush(st, a);
+  stamp_end(a);
 }
 
 // ------------------------------------------------------------ helpers
@@ -546,13 +579,33 @@ __global__ void __launch_bounds__(kBlock) k_isolated(const int64_t* __restrict__
   }
 }
 
-// Sum of a counter slot's segments, stored to host memory for the level loop.
+// Sum of a counter slot's segments, stored to host memory for the level loop;
+// with timing on, also the level's duration (latest end stamp minus earliest
+// start stamp), after which the stamp slots are reset.
 __global__ void __launch_bounds__(64) k_finalize(const uint32_t* __restrict__ cslot,
-                                                 uint32_t* host_flag) {
+                                                 uint32_t* host_flag, u64* tst, u64* ticks) {
   const int lane = lane_id();
   uint32_t x = lane < kQueueBins ? cslot[lane * kCtrStride] : 0u;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) x += (uint32_t)__shfl_xor((int)x, off);
+  if (tst) {
+    u64 lo = ~0ull, hi = 0ull;
+    for (int b = lane; b < kStampBlocks; b += 64) {
+      const u64 s0 = tst[2 * b], s1 = tst[2 * b + 1];
+      lo = s0 < lo ? s0 : lo;
+      hi = s1 > hi ? s1 : hi;
+      tst[2 * b] = ~0ull;
+      tst[2 * b + 1] = 0ull;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const u64 l2 = __shfl_xor(lo, off);
+      const u64 h2 = __shfl_xor(hi, off);
+      lo = l2 < lo ? l2 : lo;
+      hi = h2 > hi ? h2 : hi;
+    }
+    if (lane == 0) *ticks = hi > lo ? hi - lo : 0ull;
+  }
   if (lane == 0) __hip_atomic_store(host_flag, x, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
@@ -611,6 +664,7 @@ Args to_args(const LevelLaunch& l) {
   a.qout = l.qout;
   a.cout = l.cout;
   a.cclr = l.cclr;
+  a.tst = l.tst;
   a.n = l.n;
   a.nw = l.nw;
   a.nnz = l.nnz;
@@ -648,6 +702,8 @@ gsw_status launch_init(const gsw_graph* g, int32_t* level, int32_t* parent, int3
   return GSW_OK;
 }
 
+// With l.tst set, the level's kernels stamp their workgroups' start and end
+// (push_edge: its first phase starts, its last phase ends the interval).
 gsw_status launch_level(const gsw_graph* g, int kernel, const LevelLaunch& l, hipStream_t s) {
   const Args a = to_args(l);
   switch (kernel) {
@@ -705,8 +761,9 @@ gsw_status launch_isolated(const gsw_graph* g, unsigned long long* iso, hipStrea
   return GSW_OK;
 }
 
-gsw_status launch_finalize(const uint32_t* cslot, uint32_t* d_flag, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, cslot, d_flag);
+gsw_status launch_finalize(const uint32_t* cslot, uint32_t* d_flag, unsigned long long* tst,
+                           unsigned long long* ticks, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, cslot, d_flag, tst, ticks);
   GSW_HIP(hipGetLastError());
   return GSW_OK;
 }
