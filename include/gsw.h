@@ -229,6 +229,40 @@ gsw_status gsw_bfs_profile(const gsw_graph *g, int32_t source, const int32_t *ke
                            int32_t n_kernels, int32_t reps, int32_t advance_kernel, float *times,
                            int64_t *frontier, int32_t max_levels, int32_t *n_levels, void *stream);
 
+/* ----------------------------------------------------------- batched BFS */
+
+#define GSW_MSBFS_MAX_SOURCES 1024
+#define GSW_MSBFS_LEVEL_CAP 127 /* int8 levels */
+
+typedef struct {
+  float push_to_pull;  /* switch to bottom-up when the frontier's edges exceed this
+                          fraction of all arcs ... */
+  float pull_to_push;  /* ... and back to top-down below this fraction */
+  int32_t device_ptrs; /* 1: levels is device memory; 0: host */
+  int32_t reserved0;
+  void *stream;        /* hipStream_t; NULL = library stream */
+} gsw_msbfs_opts;
+
+/* Fills opts: push_to_pull 0.05, pull_to_push 0.01, host pointers. */
+void gsw_msbfs_opts_default(gsw_msbfs_opts *opts);
+
+/*
+ * Multi-source BFS of up to GSW_MSBFS_MAX_SOURCES sources in one traversal
+ * (not in the paper; a batching of its level-synchronous BFS).  Every vertex
+ * carries one bit per source; each level either pushes the frontier bits
+ * along the arcs or pulls them into unvisited vertices (bottom-up needs a
+ * symmetric graph; otherwise every level is top-down), so one pass over the
+ * edges serves the whole batch.
+ *   levels    [n_sources][n] int8: hop distance from sources[i], -1 if
+ *             unreachable.  Sources may repeat.
+ *   n_levels  receives the number of levels run (may be NULL).
+ * Returns GSW_ERANGE when some source reaches a depth above
+ * GSW_MSBFS_LEVEL_CAP (int8 cannot hold it); levels are then unspecified --
+ * run those sources through gsw_bfs instead.
+ */
+gsw_status gsw_msbfs(const gsw_graph *g, const int32_t *sources, int32_t n_sources, int8_t *levels,
+                     int32_t *n_levels, const gsw_msbfs_opts *opts);
+
 /* ------------------------------------------------------------------ misc */
 
 const char *gsw_last_error(void);

@@ -251,6 +251,7 @@ void free_graph(gsw_graph* g) {
     if (g->offs) (void)hipFree((void*)g->offs);
     if (g->cols) (void)hipFree((void*)g->cols);
   }
+  ms_release(g);
   if (g->stream) (void)hipStreamDestroy(g->stream);
   delete g;
 }

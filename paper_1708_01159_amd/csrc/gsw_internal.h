@@ -66,6 +66,8 @@ struct Workspace {
   size_t bytes = 0;
 };
 
+struct MsWorkspace;  // batched BFS state (gsw_msbfs.hip)
+
 }  // namespace gsw
 
 struct gsw_graph {
@@ -80,6 +82,7 @@ struct gsw_graph {
   double deg_stats[6] = {};       // min, q1, median, q3, max, std
   size_t csr_bytes = 0, origin_bytes = 0;
   gsw::Workspace ws;
+  gsw::MsWorkspace* ms = nullptr; // batched BFS workspace, sized for the largest batch seen
   hipStream_t stream = nullptr;   // library stream for this graph
   std::mutex mu;
 };
@@ -130,6 +133,7 @@ gsw_status ensure_origin(gsw_graph* g);
 hipStream_t pick_stream(gsw_graph* g, void* user_stream);
 
 bool kernel_is_pull(int k);
+void ms_release(gsw_graph* g);
 
 // Marker of a level-size slot in host memory that the device has not written.
 constexpr uint32_t kNotReady = 0xffffffffu;

@@ -58,6 +58,15 @@ class BfsOpts(ctypes.Structure):
                 ("reserved0", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
+class MsbfsOpts(ctypes.Structure):
+    _fields_ = [("push_to_pull", ctypes.c_float), ("pull_to_push", ctypes.c_float),
+                ("device_ptrs", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
+
+
+MSBFS_MAX_SOURCES = 1024
+MSBFS_LEVEL_CAP = 127
+
 _lib = None
 
 
@@ -96,6 +105,8 @@ def lib():
         "gsw_tree_predict": (i32, [vp, vp, i32, i32, P(i32), P(i32)]),
         "gsw_bfs": (i32, [vp, vp, i32, vp, vp, vp, i32, P(i32), P(BfsOpts)]),
         "gsw_bfs_profile": (i32, [vp, i32, vp, i32, i32, i32, vp, vp, i32, P(i32), vp]),
+        "gsw_msbfs_opts_default": (None, [P(MsbfsOpts)]),
+        "gsw_msbfs": (i32, [vp, vp, i32, vp, P(i32), P(MsbfsOpts)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -377,6 +388,33 @@ class Runner:
     def rows(self):
         return [TraceRow(t.source_idx, t.level, t.kernel, t.flags, t.n_frontier, t.discovered,
                          t.n_next, t.ms) for t in self.trace[:min(self.tlen.value, self.cap)]]
+
+
+def msbfs(graph: Graph, sources, push_to_pull: float = None, pull_to_push: float = None,
+          device: bool = False, stream=None, out=None):
+    """Batched BFS of up to 1024 sources.  Returns ``(levels int8 [S][n], n_levels)``;
+    levels are a torch CUDA tensor when ``device`` (or ``out`` is given)."""
+    src = np.ascontiguousarray(np.atleast_1d(np.asarray(sources)), dtype=np.int32)
+    S, n = src.shape[0], graph.n
+    o = MsbfsOpts()
+    lib().gsw_msbfs_opts_default(ctypes.byref(o))
+    if push_to_pull is not None:
+        o.push_to_pull = push_to_pull
+    if pull_to_push is not None:
+        o.pull_to_push = pull_to_push
+    if device or out is not None:
+        import torch
+
+        lv = out if out is not None else torch.empty((S, n), dtype=torch.int8, device="cuda")
+        o.device_ptrs = 1
+        o.stream = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    else:
+        lv = np.empty((S, n), dtype=np.int8)
+        o.stream = stream
+    nl = ctypes.c_int32(0)
+    _check(lib().gsw_msbfs(graph.handle, src.ctypes.data, S, _ptr(lv), ctypes.byref(nl),
+                           ctypes.byref(o)))
+    return lv, nl.value
 
 
 def bfs_profile(graph: Graph, source: int, kernels=None, reps: int = 5,

@@ -1,0 +1,110 @@
+"""GPU parity of the batched multi-source BFS: every source's int8 levels
+equal the CPU oracle's levels bit-exactly; a depth beyond the int8 cap is a
+range error, never a truncation."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1708_01159_amd import graphgen as gg
+from paper_1708_01159_amd import gsw
+
+pytestmark = pytest.mark.gpu
+
+_cache = {}
+
+
+def graph(name):
+    if name not in _cache:
+        g = {"rmat12": lambda: gg.rmat(12, 16, seed=51),
+             "er_ragged": lambda: gg.erdos_renyi(20011, 50000, seed=52),
+             "grid": lambda: gg.grid(40, 37, 0.05, seed=53),
+             "chunglu": lambda: gg.chung_lu(8000, 2.1, 10.0, seed=54)}[name]()
+        _cache[name] = (g, gsw.Graph.from_csr(g.offs, g.cols))
+    return _cache[name]
+
+
+def expected(g, srcs):
+    lv, ok = oracle.msbfs_levels(g.offs, g.cols, srcs)
+    assert ok
+    return lv
+
+
+@pytest.mark.parametrize("name", ["rmat12", "er_ragged", "grid", "chunglu"])
+@pytest.mark.parametrize("nsrc", [1, 5, 64, 65, 200])
+def test_msbfs_matches_oracle(name, nsrc):
+    g, G = graph(name)
+    srcs = gg.pick_sources(g, nsrc, 1000 + nsrc)
+    lv, nl = gsw.msbfs(G, srcs)
+    assert lv.shape == (len(srcs), g.n) and lv.dtype == np.int8
+    exp = expected(g, srcs)
+    for i in range(len(srcs)):
+        assert np.array_equal(lv[i], exp[i]), "source index %d (%d)" % (i, srcs[i])
+
+
+@pytest.mark.parametrize("p2p", [(0.0, 0.0), (1e9, 1e9), (0.01, 0.005)])
+def test_msbfs_directions(p2p):
+    # all-pull, all-push and a switching run give the same levels
+    g, G = graph("rmat12")
+    srcs = gg.pick_sources(g, 130, 77)
+    lv, _ = gsw.msbfs(G, srcs, push_to_pull=p2p[0], pull_to_push=p2p[1])
+    exp = expected(g, srcs)
+    assert np.array_equal(lv, exp)
+
+
+def test_msbfs_1024_sources_device():
+    import torch
+
+    g, G = graph("rmat12")
+    srcs = gg.pick_sources(g, 1024, 5)
+    lv, nl = gsw.msbfs(G, srcs, device=True)
+    torch.cuda.synchronize()
+    exp = expected(g, srcs)
+    assert np.array_equal(lv.cpu().numpy(), exp)
+
+
+def test_msbfs_repeated_and_isolated_sources():
+    a = gg.rmat(9, 8, seed=60)
+    g = gg.from_edges(a.n + 3, np.repeat(np.arange(a.n), a.degrees()), a.cols)  # 3 isolated
+    G = gsw.Graph.from_csr(g.offs, g.cols)
+    s0 = int(np.flatnonzero(g.degrees() > 0)[0])
+    srcs = np.array([s0, s0, g.n - 1, s0, g.n - 2], dtype=np.int32)
+    lv, _ = gsw.msbfs(G, srcs)
+    exp = expected(g, srcs)
+    assert np.array_equal(lv, exp)
+    assert lv[2, g.n - 1] == 0 and (lv[2] >= 0).sum() == 1
+
+
+def test_msbfs_directed_graph_push_only():
+    a = gg.rmat(10, 8, seed=61)
+    rows = np.repeat(np.arange(a.n), a.degrees())
+    keep = rows < a.cols
+    d = gg.from_edges(a.n, rows[keep], a.cols[keep], symmetrize=False)
+    G = gsw.Graph.from_csr(d.offs, d.cols)
+    srcs = np.flatnonzero(d.degrees() > 0)[:70].astype(np.int32)
+    lv, _ = gsw.msbfs(G, srcs, push_to_pull=0.0)  # pull would be chosen; the graph forbids it
+    for i, s in enumerate(srcs):
+        ref = oracle.levels(d.offs, d.cols, int(s))
+        assert np.array_equal(lv[i].astype(np.int32), ref)
+
+
+def test_msbfs_level_cap_is_a_range_error():
+    n = 200
+    p = gg.from_edges(n, list(range(n - 1)), list(range(1, n)))
+    G = gsw.Graph.from_csr(p.offs, p.cols)
+    with pytest.raises(gsw.GswError) as ei:
+        gsw.msbfs(G, [0])
+    assert ei.value.status == gsw.ERANGE
+    # a source in the middle stays within the cap (eccentricity 100)
+    lv, nl = gsw.msbfs(G, [100, 0 + 90])
+    assert np.array_equal(lv[0].astype(np.int32), np.abs(np.arange(n) - 100))
+    # single-source BFS on the same graph and source still works afterwards
+    l2, _, _ = gsw.bfs(G, [0], policy="fixed", kernel=gsw.PUSH_VERTEX)
+    assert np.array_equal(l2[0], np.arange(n))
+
+
+def test_msbfs_bad_arguments():
+    g, G = graph("rmat12")
+    with pytest.raises(gsw.GswError):
+        gsw.msbfs(G, np.arange(1025))
+    with pytest.raises(gsw.GswError):
+        gsw.msbfs(G, [g.n])
