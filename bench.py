@@ -113,6 +113,148 @@ def timed(runner, src, sync):
     return time.perf_counter() - t0
 
 
+def bench_batched(log, batches=(64, 256, 1024)):
+    """Batched multi-source BFS on R-MAT scale 20 vs the same sources one at a
+    time on the tree-switched single-source path."""
+    import torch
+
+    from paper_1708_01159_amd import autotune, gsw, serve, trees
+    from paper_1708_01159_amd import graphgen as gg
+
+    sync = torch.cuda.synchronize
+    g = gg.workload("rmat20")
+    k, seed = gg.WORKLOAD_SOURCES["rmat20"]
+    srcs = gg.pick_sources(g, max(batches), seed)
+    G = gsw.Graph.from_csr(g.offs, g.cols, flags=gsw.ASSUME_SYMMETRIC | gsw.TRUSTED)
+    ce = serve.component_edges(g.offs, g.cols)
+    tree = trees.load_default()
+    lv1 = torch.empty((1, g.n), dtype=torch.int32, device="cuda")
+    single = gsw.Runner(G, lv1, None, policy="tree", tree=tree)
+    single.run(int(srcs[0]))
+    t_single = np.array([timed(single, s, sync) for s in srcs])
+    p2p, p2s, table = autotune.tune(G, srcs[:256], log=None)
+    log("batched: autotuned push_to_pull=%g pull_to_push=%g" % (p2p, p2s))
+    out = {}
+    for B in batches:
+        src = srcs[:B]
+        lvB = torch.empty((B, g.n), dtype=torch.int8, device="cuda")
+        gsw.msbfs(G, src, p2p, p2s, out=lvB)
+        ts = []
+        for _ in range(3):
+            sync()
+            t0 = time.perf_counter()
+            _, nl = gsw.msbfs(G, src, p2p, p2s, out=lvB)
+            ts.append(time.perf_counter() - t0)
+        t = float(np.median(ts))
+        edges = int(ce[src].sum())
+        one = float(t_single[:B].sum())
+        out[str(B)] = {"ms": round(t * 1e3, 3), "gteps": round(edges / t / 1e9, 2),
+                       "one_at_a_time_ms": round(one * 1e3, 3),
+                       "one_at_a_time_gteps": round(edges / one / 1e9, 2),
+                       "speedup": round(one / t, 2), "levels": nl}
+        log("batched B=%d: %.2f ms (%.1f GTEPS) vs one at a time %.2f ms (%.1f GTEPS)"
+            % (B, t * 1e3, edges / t / 1e9, one * 1e3, edges / one / 1e9))
+    G.close()
+    return {"workload": "R-MAT scale 20 (1,048,576 vertices), edgefactor 16, seed 6; sources seed 106",
+            "push_to_pull": p2p, "pull_to_push": p2s, "level_type": "int8", "batches": out}
+
+
+def bench_sweep(tree, args, log):
+    """Structure sweep: switched vs every fixed kernel vs best-per-level."""
+    import torch
+
+    from paper_1708_01159_amd import gsw
+    from paper_1708_01159_amd import graphgen as gg
+
+    sync = torch.cuda.synchronize
+    res = {}
+    for name, prof_src in (("grid2048_del5", 2), ("chunglu23", 8), ("er22", 8)):
+        t = time.perf_counter()
+        g = gg.workload(name)
+        k, seed = gg.WORKLOAD_SOURCES[name]
+        srcs = gg.pick_sources(g, k, seed)
+        G = gsw.Graph.from_csr(g.offs, g.cols, flags=gsw.ASSUME_SYMMETRIC | gsw.TRUSTED)
+        lv = torch.empty((1, g.n), dtype=torch.int32, device="cuda")
+        deg = g.degrees()
+        sw = gsw.Runner(G, lv, None, policy="tree", tree=tree, trace_cap=1 << 16)
+        m_c = np.zeros(len(srcs), dtype=np.int64)
+        for i, s in enumerate(srcs):
+            sw.run(int(s))
+            m_c[i] = int(deg[lv[0].cpu().numpy() >= 0].sum() // 2)
+        t_sw = np.array([min(timed(sw, s, sync), timed(sw, s, sync)) for s in srcs])
+        fixed = {}
+        for kern in range(gsw.N_KERNELS):
+            fx = gsw.Runner(G, lv, None, policy="fixed", kernel=kern, trace_cap=1 << 16)
+            ts = np.array([timed(fx, s, sync) for s in srcs])
+            fixed[gsw.KERNEL_NAMES[kern]] = round(hmean(m_c / ts / 1e9), 3)
+        bf = max(fixed, key=fixed.get)
+        sched = gsw.Runner(G, lv, None, policy="schedule", schedule=[0], trace_cap=1 << 16)
+        r_sw, r_bpl = [], []
+        for i, s in enumerate(srcs[:prof_src]):
+            times, _, _ = gsw.bfs_profile(G, int(s), reps=2, advance_kernel=-1)
+            sched.set_schedule(np.argmin(times, axis=1).astype(np.int32))
+            sched.run(int(s))
+            r_bpl.append(min(timed(sched, s, sync), timed(sched, s, sync)))
+            r_sw.append(t_sw[i])
+        gt = hmean(m_c / t_sw / 1e9)
+        res[name] = {"n": g.n, "nnz": g.nnz, "sources": len(srcs), "switched_gteps": round(gt, 3),
+                     "fixed": fixed, "best_fixed": bf, "switched_over_best_fixed": round(gt / fixed[bf], 3),
+                     "switched_time_over_best_per_level": round(float(np.sum(r_sw) / np.sum(r_bpl)), 4),
+                     "best_per_level_sources": prof_src}
+        log("sweep %s: switched %.2f GTEPS, best fixed %s %.2f, vs best-per-level %.3f (%.0f s)"
+            % (name, gt, bf, fixed[bf], res[name]["switched_time_over_best_per_level"],
+               time.perf_counter() - t))
+        G.close()
+    return res
+
+
+def bench_serving(args, tree, log, preloaded):
+    """Continuous-batching serving vs one query at a time, p50/p99 latency."""
+    from paper_1708_01159_amd import gsw, serve
+    from paper_1708_01159_amd import graphgen as gg
+
+    if args.serving_full:
+        specs = [("rmat16", lambda: gg.rmat(16, 16, seed=7)), ("rmat18", lambda: gg.rmat(18, 16, seed=8)),
+                 ("rmat20", lambda: gg.rmat(20, 16, seed=9)), ("rmat22", lambda: gg.rmat(22, 16, seed=10)),
+                 ("rmat24", lambda: gg.rmat(24, 16, seed=11)), ("grid4096", lambda: gg.grid(4096, 4096, 0.0, seed=12)),
+                 ("chunglu23", lambda: gg.chung_lu(1 << 23, 2.1, 20.0, seed=13)),
+                 ("er24", lambda: gg.erdos_renyi(1 << 24, 4 << 24, seed=14))]
+        rates, duration, slots = (100, 500, 1000, 2000, 5000), 5.0, 64
+        budget = 48 << 30
+    else:
+        specs = [("rmat22", None), ("rmat20", lambda: gg.rmat(20, 16, seed=9)),
+                 ("er20", lambda: gg.erdos_renyi(1 << 20, 4 << 20, seed=14))]
+        rates, duration, slots = (500, 2000), 2.0, 64
+        budget = 16 << 30
+    residents, cands = {}, {}
+    for name, make in specs:
+        if make is None:
+            g, G = preloaded[name]
+        else:
+            g = make()
+            G = gsw.Graph.from_csr(g.offs, g.cols, flags=gsw.ASSUME_SYMMETRIC | gsw.TRUSTED)
+        residents[name] = serve.Resident(name, G, serve.component_edges(g.offs, g.cols))
+        cands[name] = np.flatnonzero(g.degrees() > 0)
+    names = [s[0] for s in specs]
+    runs = []
+    for rate in rates:
+        trace = serve.poisson_trace(rate, duration, names, cands, seed=107 + rate)
+        srv = serve.Server(residents, slots=slots, hbm_budget=budget, levels_per_step=4)
+        qb = srv.run(trace, timeout_s=120)
+        sb = serve.summarize(qb, residents, "continuous batching")
+        row = {"rate_qps": rate, "batched": sb}
+        if not args.serving_full or rate <= 500:
+            qo = serve.serve_one_at_a_time(residents, trace, tree, timeout_s=120)
+            row["one_at_a_time"] = serve.summarize(qo, residents, "one at a time")
+        runs.append(row)
+        log("serving %d QPS: batched p50 %.2f ms p99 %.2f ms %.1f GTEPS; one-at-a-time %s"
+            % (rate, sb["p50_ms"], sb["p99_ms"], sb["gteps"],
+               "p50 %.2f p99 %.2f %.1f GTEPS" % (row["one_at_a_time"]["p50_ms"], row["one_at_a_time"]["p99_ms"],
+                                                   row["one_at_a_time"]["gteps"]) if "one_at_a_time" in row else "-"))
+    return {"graphs": names, "zipf": 1.1, "duration_s": duration, "slots": slots,
+            "hbm_budget_bytes": budget, "runs": runs}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +268,13 @@ def main():
     ap.add_argument("--profile-reps", type=int, default=3)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--roofline-sources", type=int, default=4)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-source section")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
+    ap.add_argument("--serving-full", action="store_true",
+                    help="serving over the 8-graph set (RMAT 16-24, 4096^2 grid, Chung-Lu 2^23, "
+                         "ER 2^24) at 100-5000 QPS instead of the short default")
+    ap.add_argument("--sweep", action="store_true",
+                    help="also the structure sweep: grid 2048^2 (5%% deleted), Chung-Lu 2^23, ER 2^22")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -289,6 +438,13 @@ def main():
         extra["copy_calibration"] = {"bytes_read": a.numel() * 4, "bytes_written": a.numel() * 4,
                                      "ms": round(ms, 4), "gbs": round(2 * a.numel() * 4 / ms / 1e6, 1)}
         del a, b
+
+    if not args.no_batched and not args.no_compare:
+        extra["batched"] = bench_batched(log)
+    if args.sweep:
+        extra["sweep"] = bench_sweep(tree, args, log)
+    if not args.no_serving and not args.no_compare:
+        extra["serving"] = bench_serving(args, tree, log, {"rmat22": (g, G)})
 
     cpu = cpu_baseline(g, srcs, m_c, args.cpu_budget)
     log("cpu oracle %.3f GTEPS" % cpu["value"])

@@ -263,6 +263,46 @@ void gsw_msbfs_opts_default(gsw_msbfs_opts *opts);
 gsw_status gsw_msbfs(const gsw_graph *g, const int32_t *sources, int32_t n_sources, int8_t *levels,
                      int32_t *n_levels, const gsw_msbfs_opts *opts);
 
+/* -------------------------------------------------------- serving sessions */
+
+/*
+ * A session runs many single-source BFS queries on one graph as one
+ * continuously batched multi-source traversal: each query owns one of up to
+ * GSW_MSBFS_MAX_SOURCES slots (one bit per vertex mask).  A query admitted
+ * while others are in flight joins at the next level boundary with its own
+ * start level, so queries of different ages share every pass over the edges;
+ * a slot finishes when its frontier is empty and is reused after its result
+ * has been fetched.  Results are int32 hop distances (-1 unreachable), equal
+ * to a single-source BFS from the same source.  Device memory: 4 masks of
+ * n * ceil(slots/64) words plus slots * n int32 levels.  A session is used
+ * by one thread at a time (calls are serialised); sessions of different
+ * graphs or of the same graph may run concurrently on their own streams.
+ */
+typedef struct gsw_session gsw_session;
+
+gsw_status gsw_session_create(const gsw_graph *g, int32_t max_slots, gsw_session **out);
+void gsw_session_destroy(gsw_session *ss);
+
+/* Takes a free slot for a query from `source`; GSW_EBUSY when none is free. */
+gsw_status gsw_session_admit(gsw_session *ss, int32_t source, int32_t *slot);
+
+/* Seeds admitted queries, then runs levels until a slot finishes or
+ * max_levels levels have run.  finished[0..*n_finished) receives the
+ * finished slots (finished_cap should be at least the slot count);
+ * *levels_run the number of levels run. */
+gsw_status gsw_session_step(gsw_session *ss, int32_t max_levels, int32_t *finished,
+                            int32_t finished_cap, int32_t *n_finished, int32_t *levels_run);
+
+/* Copies a finished slot's n levels (device or host memory) and frees it. */
+gsw_status gsw_session_fetch(gsw_session *ss, int32_t slot, int32_t *levels, int32_t device_ptr);
+
+/* Slot count, slots in use, levels run so far, device bytes held. */
+gsw_status gsw_session_info(const gsw_session *ss, int32_t *slots, int32_t *busy,
+                            int64_t *iteration, size_t *dev_bytes);
+
+/* Direction thresholds as in gsw_msbfs_opts (defaults 0.05 / 0.01). */
+gsw_status gsw_session_set_thresholds(gsw_session *ss, float push_to_pull, float pull_to_push);
+
 /* ------------------------------------------------------------------ misc */
 
 const char *gsw_last_error(void);

@@ -107,6 +107,13 @@ def lib():
         "gsw_bfs_profile": (i32, [vp, i32, vp, i32, i32, i32, vp, vp, i32, P(i32), vp]),
         "gsw_msbfs_opts_default": (None, [P(MsbfsOpts)]),
         "gsw_msbfs": (i32, [vp, vp, i32, vp, P(i32), P(MsbfsOpts)]),
+        "gsw_session_create": (i32, [vp, i32, P(vp)]),
+        "gsw_session_destroy": (None, [vp]),
+        "gsw_session_admit": (i32, [vp, i32, P(i32)]),
+        "gsw_session_step": (i32, [vp, i32, vp, i32, P(i32), P(i32)]),
+        "gsw_session_fetch": (i32, [vp, i32, vp, i32]),
+        "gsw_session_info": (i32, [vp, P(i32), P(i32), P(i64), P(ctypes.c_size_t)]),
+        "gsw_session_set_thresholds": (i32, [vp, ctypes.c_float, ctypes.c_float]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -415,6 +422,63 @@ def msbfs(graph: Graph, sources, push_to_pull: float = None, pull_to_push: float
     _check(lib().gsw_msbfs(graph.handle, src.ctypes.data, S, _ptr(lv), ctypes.byref(nl),
                            ctypes.byref(o)))
     return lv, nl.value
+
+
+class Session:
+    """Continuously batched single-source queries on one graph (gsw_session_*)."""
+
+    def __init__(self, graph: Graph, slots: int = 64):
+        out = ctypes.c_void_p()
+        _check(lib().gsw_session_create(graph.handle, slots, ctypes.byref(out)))
+        self._h = out
+        self.graph = graph
+        self.slots = slots
+        self._fin = np.zeros(slots, dtype=np.int32)
+
+    def admit(self, source: int):
+        """Slot index, or None when every slot is busy."""
+        k = ctypes.c_int32(-1)
+        st = lib().gsw_session_admit(self._h, int(source), ctypes.byref(k))
+        if st == EBUSY:
+            return None
+        _check(st)
+        return k.value
+
+    def step(self, max_levels: int = 8):
+        """Runs levels until a slot finishes; returns (finished slots, levels run)."""
+        nf, lr = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(lib().gsw_session_step(self._h, max_levels, self._fin.ctypes.data, self.slots,
+                                      ctypes.byref(nf), ctypes.byref(lr)))
+        return self._fin[:nf.value].tolist(), lr.value
+
+    def fetch(self, slot: int, out=None):
+        """The slot's int32 levels (into ``out``, a torch CUDA tensor or numpy
+        array, when given) and frees the slot."""
+        if out is None:
+            out = np.empty(self.graph.n, dtype=np.int32)
+        dev = 1 if hasattr(out, "data_ptr") else 0
+        _check(lib().gsw_session_fetch(self._h, int(slot), _ptr(out), dev))
+        return out
+
+    def info(self):
+        s, b, it, nb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64(), ctypes.c_size_t()
+        _check(lib().gsw_session_info(self._h, ctypes.byref(s), ctypes.byref(b), ctypes.byref(it),
+                                      ctypes.byref(nb)))
+        return dict(slots=s.value, busy=b.value, iteration=it.value, dev_bytes=nb.value)
+
+    def set_thresholds(self, push_to_pull: float, pull_to_push: float):
+        _check(lib().gsw_session_set_thresholds(self._h, push_to_pull, pull_to_push))
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().gsw_session_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def bfs_profile(graph: Graph, source: int, kernels=None, reps: int = 5,

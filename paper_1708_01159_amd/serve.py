@@ -1,0 +1,240 @@
+"""Serving: single-source BFS queries over several resident graphs, with
+continuous batching, admission by device memory, and latency percentiles.
+
+Each graph that has queries gets a gsw session (a continuously batched
+multi-source traversal with a fixed number of slots).  A query is admitted
+into a free slot of its graph's session as soon as one is free -- also while
+the session's other queries are mid-traversal; it joins at the next level
+boundary.  Sessions are created only while their device memory fits the
+budget; an idle session (no slot in use) is destroyed to make room for
+another graph's.  Each session is stepped by its own worker thread on its own
+HIP stream, so the work of different graphs overlaps on the device.
+
+Latency of a query = completion time - arrival time.  Throughput = sum over
+queries of the undirected edges of the source's component / makespan.
+
+The one-at-a-time reference serves the same arrival trace in FIFO order with
+one tree-switched gsw_bfs per query.
+"""
+from __future__ import annotations
+
+import collections
+import threading
+import time
+from concurrent.futures import FIRST_COMPLETED, ThreadPoolExecutor
+from concurrent.futures import wait as futures_wait
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import gsw
+
+
+@dataclass
+class Query:
+    qid: int
+    graph: str
+    source: int
+    t_arrival: float
+    t_admit: float = -1.0
+    t_done: float = -1.0
+    levels: object = None
+
+
+@dataclass
+class Resident:
+    """A graph in device memory with what serving needs to know about it."""
+
+    name: str
+    graph: gsw.Graph
+    comp_edges: np.ndarray = None  # undirected edges of the component of each vertex
+    session_bytes: int = 0
+
+
+def component_edges(offs, cols) -> np.ndarray:
+    """Per vertex: undirected edges in its connected component (host; used to
+    account throughput, not to answer queries)."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+
+    n = offs.shape[0] - 1
+    a = sp.csr_matrix((np.ones(cols.shape[0], dtype=np.int8), cols, offs), shape=(n, n))
+    _, lab = connected_components(a, directed=False)
+    deg = np.diff(offs)
+    per = np.bincount(lab, weights=deg).astype(np.int64) // 2
+    return per[lab]
+
+
+def session_bytes(n: int, slots: int) -> int:
+    w = (slots + 63) // 64
+    return 4 * n * w * 8 + slots * n * 4
+
+
+def poisson_trace(rate_qps: float, duration_s: float, graphs, candidates, zipf_s: float = 1.1,
+                  seed: int = 107):
+    """Arrival times (Poisson), graph choice Zipf(zipf_s) over ``graphs`` in the
+    given order, source uniform over ``candidates[graph]``."""
+    rng = np.random.default_rng(seed)
+    k = len(graphs)
+    p = 1.0 / np.arange(1, k + 1) ** zipf_s
+    p /= p.sum()
+    t, out = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate_qps)
+        if t >= duration_s:
+            break
+        gi = int(rng.choice(k, p=p))
+        cand = candidates[graphs[gi]]
+        out.append((t, graphs[gi], int(cand[rng.integers(0, cand.shape[0])])))
+    return out
+
+
+class Server:
+    def __init__(self, residents: dict, slots: int = 64, hbm_budget: int = None,
+                 levels_per_step: int = 4, keep_levels: bool = False, session_factory=None):
+        self.res = residents
+        self.new_session = session_factory or gsw.Session
+        self.slots = slots
+        self.budget = hbm_budget
+        self.levels_per_step = levels_per_step
+        self.keep = keep_levels
+        self.sessions = {}          # graph -> gsw.Session
+        self.workers = {}           # graph -> single-thread executor
+        self.used = 0
+        self.evictions = 0
+
+    def _ensure_session(self, name):
+        if name in self.sessions:
+            return self.sessions[name]
+        need = session_bytes(self.res[name].graph.n, self.slots)
+        if self.budget is not None:
+            # make room by closing idle sessions of other graphs
+            while self.used + need > self.budget:
+                idle = [g for g, s in self.sessions.items() if s.info()["busy"] == 0]
+                if not idle:
+                    return None
+                self._close(idle[0])
+                self.evictions += 1
+        s = self.new_session(self.res[name].graph, self.slots)
+        self.sessions[name] = s
+        self.workers[name] = ThreadPoolExecutor(max_workers=1)
+        self.used += need
+        return s
+
+    def _close(self, name):
+        s = self.sessions.pop(name)
+        self.workers.pop(name).shutdown(wait=True)
+        self.used -= session_bytes(self.res[name].graph.n, self.slots)
+        s.close()
+
+    def _step(self, name, sess, slot_query):
+        """Worker: one step of a session and the fetch of its finished slots."""
+        fin, _ = sess.step(self.levels_per_step)
+        done = []
+        for k in fin:
+            out = np.empty(self.res[name].graph.n, dtype=np.int32) if self.keep else None
+            if out is None:
+                out = self._scratch(name)
+            sess.fetch(k, out)
+            done.append((k, out.copy() if self.keep else None))
+        return done
+
+    _scratch_bufs = {}
+
+    def _scratch(self, name):
+        buf = self._scratch_bufs.get((id(self), name))
+        if buf is None:
+            import torch
+
+            buf = torch.empty(self.res[name].graph.n, dtype=torch.int32, device="cuda")
+            self._scratch_bufs[(id(self), name)] = buf
+        return buf
+
+    def run(self, trace, timeout_s: float = 600.0):
+        """Serves ``trace`` = [(t_arrival, graph, source)] in real time; returns
+        the list of completed Query objects."""
+        queries = [Query(i, g, s, t) for i, (t, g, s) in enumerate(sorted(trace))]
+        pending = collections.defaultdict(collections.deque)
+        inflight = {}               # graph -> future
+        slot_q = collections.defaultdict(dict)  # graph -> slot -> Query
+        nxt = 0
+        done = 0
+        t0 = time.perf_counter()
+        while done < len(queries):
+            now = time.perf_counter() - t0
+            if now > timeout_s:
+                raise TimeoutError("serving run exceeded %.0f s" % timeout_s)
+            while nxt < len(queries) and queries[nxt].t_arrival <= now:
+                pending[queries[nxt].graph].append(queries[nxt])
+                nxt += 1
+            # admission: free slots of each graph's session (created under the budget)
+            for name, dq in pending.items():
+                if not dq or name in inflight:
+                    continue
+                sess = self._ensure_session(name)
+                if sess is None:
+                    continue
+                while dq:
+                    k = sess.admit(dq[0].source)
+                    if k is None:
+                        break
+                    q = dq.popleft()
+                    q.t_admit = time.perf_counter() - t0
+                    slot_q[name][k] = q
+            # steps: every session with busy slots and no step in flight
+            for name, sess in list(self.sessions.items()):
+                if name not in inflight and slot_q[name]:
+                    inflight[name] = self.workers[name].submit(self._step, name, sess, slot_q[name])
+            # completions
+            progressed = False
+            for name, fut in list(inflight.items()):
+                if fut.done():
+                    del inflight[name]
+                    progressed = True
+                    t_done = time.perf_counter() - t0
+                    for k, lv in fut.result():
+                        q = slot_q[name].pop(k)
+                        q.t_done = t_done
+                        q.levels = lv
+                        done += 1
+            if not progressed:
+                until_next = queries[nxt].t_arrival - now if nxt < len(queries) else 0.01
+                if inflight:
+                    futures_wait(list(inflight.values()), timeout=max(0.0, min(until_next, 0.01)),
+                                 return_when=FIRST_COMPLETED)
+                elif nxt < len(queries):
+                    time.sleep(max(0.0, min(until_next, 0.001)))
+        for name in list(self.sessions):
+            self._close(name)
+        return queries
+
+
+def serve_one_at_a_time(residents: dict, trace, tree, timeout_s: float = 600.0):
+    """FIFO, one tree-switched gsw_bfs per query, in real time."""
+    import torch
+
+    queries = [Query(i, g, s, t) for i, (t, g, s) in enumerate(sorted(trace))]
+    runners = {}
+    for name, r in residents.items():
+        lv = torch.empty((1, r.graph.n), dtype=torch.int32, device="cuda")
+        runners[name] = gsw.Runner(r.graph, lv, None, policy="tree", tree=tree)
+    t0 = time.perf_counter()
+    for q in queries:
+        now = time.perf_counter() - t0
+        if now > timeout_s:
+            raise TimeoutError("one-at-a-time run exceeded %.0f s" % timeout_s)
+        if q.t_arrival > now:
+            time.sleep(q.t_arrival - now)
+        q.t_admit = time.perf_counter() - t0
+        runners[q.graph].run(q.source)
+        q.t_done = time.perf_counter() - t0
+    return queries
+
+
+def summarize(queries, residents, label):
+    lat = np.array([q.t_done - q.t_arrival for q in queries]) * 1e3
+    span = max(q.t_done for q in queries) - min(q.t_arrival for q in queries)
+    edges = sum(int(residents[q.graph].comp_edges[q.source]) for q in queries)
+    return {"mode": label, "queries": len(queries), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3), "mean_ms": round(float(lat.mean()), 3),
+            "gteps": round(edges / span / 1e9, 3), "makespan_s": round(span, 3)}

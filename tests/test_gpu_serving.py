@@ -1,0 +1,134 @@
+"""GPU: continuously batched serving sessions.  Every query's levels equal
+the CPU oracle's and the same query run alone through gsw_bfs, whether it
+ran alone or among many others admitted at different times."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1708_01159_amd import graphgen as gg
+from paper_1708_01159_amd import gsw, serve
+
+pytestmark = pytest.mark.gpu
+
+_cache = {}
+
+
+def resident(name):
+    if name not in _cache:
+        g = {"rmat12": lambda: gg.rmat(12, 16, seed=71),
+             "grid": lambda: gg.grid(60, 45, 0.05, seed=72),
+             "er": lambda: gg.erdos_renyi(30011, 60000, seed=73)}[name]()
+        G = gsw.Graph.from_csr(g.offs, g.cols)
+        _cache[name] = (g, G)
+    return _cache[name]
+
+
+def alone(G, s):
+    return gsw.bfs(G, [int(s)], policy="fixed", kernel=gsw.PUSH_EDGE, parents=False)[0][0]
+
+
+def test_session_results_and_slot_reuse():
+    g, G = resident("rmat12")
+    sess = gsw.Session(G, slots=4)
+    srcs = gg.pick_sources(g, 10, 3)
+    got = {}
+    it = iter(srcs)
+    slot_src = {}
+    for _ in range(200):
+        for s in it:
+            k = sess.admit(int(s))
+            if k is None:
+                it = iter([s] + list(it))
+                break
+            slot_src[k] = int(s)
+        fin, _ = sess.step(2)
+        for k in fin:
+            got[slot_src.pop(k)] = sess.fetch(k)
+        if len(got) == len(srcs):
+            break
+    assert len(got) == len(srcs)
+    for s, lv in got.items():
+        assert np.array_equal(lv, oracle.levels(g.offs, g.cols, s))
+    sess.close()
+
+
+def test_session_busy_and_mid_flight_admission():
+    g, G = resident("grid")
+    sess = gsw.Session(G, slots=2)
+    a, b, c = gg.pick_sources(g, 3, 9).tolist()
+    ka = sess.admit(a)
+    sess.step(3)  # a is mid-traversal (the grid is deep)
+    kb = sess.admit(b)
+    assert sess.admit(c) is None  # both slots busy
+    res = {}
+    while len(res) < 2:
+        fin, _ = sess.step(5)
+        for k in fin:
+            res[k] = sess.fetch(k)
+    assert np.array_equal(res[ka], oracle.levels(g.offs, g.cols, a))
+    assert np.array_equal(res[kb], oracle.levels(g.offs, g.cols, b))
+    kc = sess.admit(c)
+    assert kc is not None
+    while True:
+        fin, _ = sess.step(50)
+        if fin:
+            break
+    assert np.array_equal(sess.fetch(kc), oracle.levels(g.offs, g.cols, c))
+
+
+def test_session_isolated_source_and_thresholds():
+    a = gg.rmat(9, 8, seed=74)
+    g = gg.from_edges(a.n + 2, np.repeat(np.arange(a.n), a.degrees()), a.cols)
+    G = gsw.Graph.from_csr(g.offs, g.cols)
+    for p2p in ((0.0, 0.0), (1e9, 1e9)):
+        sess = gsw.Session(G, slots=70)
+        sess.set_thresholds(*p2p)
+        srcs = [g.n - 1] + gg.pick_sources(g, 65, 11).tolist()
+        slots = [sess.admit(s) for s in srcs]
+        res = {}
+        while len(res) < len(srcs):
+            fin, _ = sess.step(4)
+            for k in fin:
+                res[k] = sess.fetch(k)
+        for s, k in zip(srcs, slots):
+            assert np.array_equal(res[k], oracle.levels(g.offs, g.cols, s)), s
+
+
+def test_server_mix_equals_alone():
+    names = ["rmat12", "grid", "er"]
+    residents = {}
+    cands = {}
+    for nm in names:
+        g, G = resident(nm)
+        residents[nm] = serve.Resident(nm, G, serve.component_edges(g.offs, g.cols))
+        cands[nm] = np.flatnonzero(g.degrees() > 0)
+    # 96 queries arriving within 30 ms: they overlap on the device
+    trace = serve.poisson_trace(3200.0, 0.03, names, cands, seed=5)
+    assert len(trace) >= 64 and len({t[1] for t in trace}) == 3
+    srv = serve.Server(residents, slots=64, levels_per_step=3, keep_levels=True)
+    qs = srv.run(trace)
+    assert all(q.t_done >= q.t_arrival for q in qs)
+    for q in qs:
+        g, G = resident(q.graph)
+        ref = oracle.levels(g.offs, g.cols, q.source)
+        assert np.array_equal(q.levels, ref), (q.graph, q.source)
+        assert np.array_equal(q.levels, alone(G, q.source)), (q.graph, q.source)
+    stats = serve.summarize(qs, residents, "batched")
+    assert stats["queries"] == len(trace) and stats["p99_ms"] >= stats["p50_ms"] > 0
+
+
+def test_server_tiny_budget_queues_instead_of_failing():
+    names = ["rmat12", "grid"]
+    residents = {nm: serve.Resident(nm, resident(nm)[1],
+                                    serve.component_edges(resident(nm)[0].offs, resident(nm)[0].cols))
+                 for nm in names}
+    cands = {nm: np.flatnonzero(resident(nm)[0].degrees() > 0) for nm in names}
+    trace = serve.poisson_trace(2000.0, 0.02, names, cands, seed=6)
+    # room for one session at a time: the other graph's queries wait for eviction
+    budget = max(serve.session_bytes(resident(nm)[1].n, 8) for nm in names) + 1
+    srv = serve.Server(residents, slots=8, hbm_budget=budget, keep_levels=True)
+    qs = srv.run(trace)
+    for q in qs:
+        g, _ = resident(q.graph)
+        assert np.array_equal(q.levels, oracle.levels(g.offs, g.cols, q.source))
+    assert srv.evictions >= 1

@@ -1,0 +1,121 @@
+"""Serving scheduler on the CPU: a stub session (answers from the oracle, one
+simulated level per step) exercises admission, slot reuse, the memory budget
+and eviction without a GPU."""
+import numpy as np
+
+import oracle
+from paper_1708_01159_amd import graphgen as gg
+from paper_1708_01159_amd import serve
+
+
+class StubGraph:
+    def __init__(self, csr):
+        self.csr = csr
+        self.n = csr.n
+
+
+class StubSession:
+    created = 0
+
+    def __init__(self, graph, slots):
+        StubSession.created += 1
+        self.g = graph
+        self.slots = slots
+        self.state = {}  # slot -> [source, start, depth]
+        self.pending = {}
+        self.it = 0
+        self.finished = {}
+
+    def admit(self, source):
+        used = set(self.state) | set(self.pending) | set(self.finished)
+        free = [k for k in range(self.slots) if k not in used]
+        if not free:
+            return None
+        self.pending[free[0]] = source
+        return free[0]
+
+    def step(self, max_levels):
+        for k, s in self.pending.items():
+            lv = oracle.levels(self.g.csr.offs, self.g.csr.cols, s)
+            self.state[k] = [s, self.it, int(lv.max()) + 1, lv]
+        self.pending = {}
+        fin = []
+        for run in range(max_levels):
+            if not self.state:
+                break
+            self.it += 1
+            for k in list(self.state):
+                s, start, depth, lv = self.state[k]
+                if self.it - start >= depth:
+                    fin.append(k)
+                    self.finished[k] = lv
+                    del self.state[k]
+            if fin:
+                return fin, run + 1
+        return fin, max_levels
+
+    def fetch(self, slot, out=None):
+        lv = self.finished.pop(slot)
+        if out is not None:
+            out[:] = lv
+            return out
+        return lv.copy()
+
+    def info(self):
+        return dict(slots=self.slots, busy=len(self.state) + len(self.pending) + len(self.finished),
+                    iteration=self.it, dev_bytes=0)
+
+    def close(self):
+        pass
+
+
+def make(names):
+    res, cands = {}, {}
+    graphs = {"a": gg.rmat(9, 8, seed=1), "b": gg.grid(12, 9, 0.0, seed=1), "c": gg.erdos_renyi(700, 900, seed=2)}
+    for nm in names:
+        g = graphs[nm]
+        res[nm] = serve.Resident(nm, StubGraph(g), serve.component_edges(g.offs, g.cols))
+        cands[nm] = np.flatnonzero(g.degrees() > 0)
+    return res, cands
+
+
+def test_scheduler_answers_every_query_correctly():
+    res, cands = make(["a", "b", "c"])
+    trace = serve.poisson_trace(5000.0, 0.02, ["a", "b", "c"], cands, seed=3)
+    srv = serve.Server(res, slots=4, levels_per_step=2, keep_levels=True, session_factory=StubSession)
+    qs = srv.run(trace, timeout_s=60)
+    assert len(qs) == len(trace)
+    for q in qs:
+        g = res[q.graph].graph.csr
+        assert np.array_equal(q.levels, oracle.levels(g.offs, g.cols, q.source))
+        assert q.t_admit >= q.t_arrival and q.t_done >= q.t_admit
+    st = serve.summarize(qs, res, "stub")
+    assert st["queries"] == len(trace) and st["p99_ms"] >= st["p50_ms"]
+
+
+def test_budget_forces_eviction_and_queueing():
+    res, cands = make(["a", "b"])
+    trace = serve.poisson_trace(3000.0, 0.02, ["a", "b"], cands, seed=4)
+    budget = max(serve.session_bytes(r.graph.n, 2) for r in res.values())  # one session fits
+    StubSession.created = 0
+    srv = serve.Server(res, slots=2, hbm_budget=budget, keep_levels=True, session_factory=StubSession)
+    qs = srv.run(trace, timeout_s=60)
+    assert all(q.t_done >= 0 for q in qs)
+    assert srv.evictions >= 1 and StubSession.created >= 2
+    assert srv.used <= budget
+
+
+def test_poisson_trace_shape():
+    res, cands = make(["a", "b", "c"])
+    tr = serve.poisson_trace(1000.0, 2.0, ["a", "b", "c"], cands, seed=9)
+    ts = np.array([t for t, _, _ in tr])
+    assert np.all(np.diff(ts) >= 0) and 1700 < len(tr) < 2300  # ~ rate x duration
+    share = np.mean([g == "a" for _, g, _ in tr])
+    assert share > np.mean([g == "c" for _, g, _ in tr])  # Zipf: first graph most frequent
+    for _, g, s in tr:
+        assert s in set(cands[g].tolist())
+
+
+def test_session_bytes():
+    assert serve.session_bytes(1000, 64) == 4 * 1000 * 8 + 64 * 1000 * 4
+    assert serve.session_bytes(1000, 65) == 4 * 1000 * 2 * 8 + 65 * 1000 * 4
