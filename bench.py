@@ -239,7 +239,7 @@ def bench_serving(args, tree, log, preloaded):
     runs = []
     for rate in rates:
         trace = serve.poisson_trace(rate, duration, names, cands, seed=107 + rate)
-        srv = serve.Server(residents, slots=slots, hbm_budget=budget, levels_per_step=4)
+        srv = serve.Server(residents, slots=slots, hbm_budget=budget)
         qb = srv.run(trace, timeout_s=120)
         sb = serve.summarize(qb, residents, "continuous batching")
         row = {"rate_qps": rate, "batched": sb}

@@ -235,8 +235,8 @@ gsw_status gsw_bfs_profile(const gsw_graph *g, int32_t source, const int32_t *ke
 #define GSW_MSBFS_LEVEL_CAP 127 /* int8 levels */
 
 typedef struct {
-  float push_to_pull;  /* switch to bottom-up when the frontier's edges exceed this
-                          fraction of all arcs ... */
+  float push_to_pull;  /* per source: switch it to bottom-up when its frontier's edges
+                          exceed this fraction of all arcs ... */
   float pull_to_push;  /* ... and back to top-down below this fraction */
   int32_t device_ptrs; /* 1: levels is device memory; 0: host */
   int32_t reserved0;
@@ -249,8 +249,9 @@ void gsw_msbfs_opts_default(gsw_msbfs_opts *opts);
 /*
  * Multi-source BFS of up to GSW_MSBFS_MAX_SOURCES sources in one traversal
  * (not in the paper; a batching of its level-synchronous BFS).  Every vertex
- * carries one bit per source; each level either pushes the frontier bits
- * along the arcs or pulls them into unvisited vertices (bottom-up needs a
+ * carries one bit per source; in each level every source either pushes its
+ * frontier bits along the arcs or has them pulled into its unvisited
+ * vertices, chosen per source by the thresholds above (bottom-up needs a
  * symmetric graph; otherwise every level is top-down), so one pass over the
  * edges serves the whole batch.
  *   levels    [n_sources][n] int8: hop distance from sources[i], -1 if
@@ -272,11 +273,15 @@ gsw_status gsw_msbfs(const gsw_graph *g, const int32_t *sources, int32_t n_sourc
  * while others are in flight joins at the next level boundary with its own
  * start level, so queries of different ages share every pass over the edges;
  * a slot finishes when its frontier is empty and is reused after its result
- * has been fetched.  Results are int32 hop distances (-1 unreachable), equal
- * to a single-source BFS from the same source.  Device memory: 4 masks of
- * n * ceil(slots/64) words plus slots * n int32 levels.  A session is used
- * by one thread at a time (calls are serialised); sessions of different
- * graphs or of the same graph may run concurrently on their own streams.
+ * has been fetched.  Each slot picks its own direction every level (the rule
+ * of gsw_msbfs_opts), so a young query pushes while older ones pull in the
+ * same pass.  Results are int32 hop distances (-1 unreachable), equal to a
+ * single-source BFS from the same source.  Device memory: 4 masks of
+ * n * ceil(slots/64) words plus slots * n int32 levels.  admit, info and
+ * set_thresholds may be called from any thread while another thread is in
+ * step or fetch (step and fetch are serialised with each other); sessions of
+ * different graphs or of the same graph run concurrently on their own
+ * streams.
  */
 typedef struct gsw_session gsw_session;
 
@@ -286,10 +291,11 @@ void gsw_session_destroy(gsw_session *ss);
 /* Takes a free slot for a query from `source`; GSW_EBUSY when none is free. */
 gsw_status gsw_session_admit(gsw_session *ss, int32_t source, int32_t *slot);
 
-/* Seeds admitted queries, then runs levels until a slot finishes or
- * max_levels levels have run.  finished[0..*n_finished) receives the
+/* Runs levels until a slot finishes, max_levels levels have run, or no slot
+ * is admitted or running.  Queries admitted before or during the call join
+ * at the next level boundary.  finished[0..*n_finished) receives the
  * finished slots (finished_cap should be at least the slot count);
- * *levels_run the number of levels run. */
+ * *levels_run the number of levels run (0: nothing to run). */
 gsw_status gsw_session_step(gsw_session *ss, int32_t max_levels, int32_t *finished,
                             int32_t finished_cap, int32_t *n_finished, int32_t *levels_run);
 

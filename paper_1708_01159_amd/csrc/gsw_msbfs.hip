@@ -1,21 +1,29 @@
 // Batched multi-source BFS: up to 1024 sources traverse one graph together.
 //
 // Every vertex carries W = ceil(B/64) 64-bit masks, one bit per source:
-// visited, frontier (depth d) and next frontier (depth d+1).  A level is
-// either top-down (each frontier vertex ORs its frontier mask, minus what a
-// neighbour has already seen, into the neighbour's next mask) or bottom-up
-// (each vertex with unvisited sources ORs its neighbours' frontier masks and
-// stops once every unvisited source is covered).  One pass over the edges
-// thus advances every source whose frontier touches them: the edge stream is
-// shared by the whole batch.  The per-source result is the same hop distance
-// as a single-source BFS (Section III-A); levels are stored as int8 (-1 =
-// unreachable) and a depth above 127 is reported as a range error.
+// visited, frontier (depth d) and next frontier (depth d+1).  Each source
+// picks its own direction every level with the rule the single-source search
+// uses (its frontier's edges against a fraction of all arcs), so one level
+// runs both halves for disjoint sets of sources:
+//   top-down   each frontier vertex ORs its frontier mask (restricted to the
+//              top-down sources), minus what a neighbour has already seen,
+//              into the neighbour's accumulator;
+//   bottom-up  each vertex with unvisited bottom-up sources ORs its
+//              neighbours' frontier masks and stops once all of them are
+//              covered.
+// One pass over the edges advances every source whose frontier touches
+// them.  The per-source result is the same hop distance as a single-source
+// BFS (Section III-A); levels are stored as int8 (-1 = unreachable) and a
+// depth above 127 is reported as a range error.
 //
 // Layout: masks are vertex-major ([n][W] words, one 128-byte line per vertex
-// at B = 1024), worked on by groups of W lanes (lane j owns word j) so a
-// vertex's masks are read and written coalesced.  Levels are kept
-// vertex-major ([n][B] bytes, each lane writing its own 64-byte run) and
-// transposed to [B][n] at the end.
+// at B = 1024), worked on by groups of G = W (rounded up to a power of two)
+// lanes, lane j of a group owning word j, so a vertex's masks are read and
+// written coalesced.  A row longer than kMsLong is walked by the whole wave,
+// each group taking every (64/G)-th edge, so one high-degree vertex does not
+// hold its wave for its whole row.  Levels are kept vertex-major ([n][B]
+// bytes, each lane updating its own 64-byte run word by word) and transposed
+// to [B][n] at the end.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,6 +41,17 @@ constexpr int kMsBlock = 256;
 constexpr int kMsMaxGrid = 2048;
 constexpr int kMsStats = 8;        // stat counters, spread like the queue bins
 constexpr int kMsStatStride = 32;  // u64 words between counters
+constexpr int kMsLong = 32;        // rows longer than this are walked by the whole wave
+constexpr int kMaxWords = GSW_MSBFS_MAX_SOURCES / 64;  // mask words per vertex at most
+constexpr int kMaxSlots = GSW_MSBFS_MAX_SOURCES;
+
+// Mapped host words written by the finalize kernel: [0] vertices with new
+// bits (stored last, ~0 while the level runs), [1] their degree sum,
+// [kHostActive + j] OR of the new frontier's word j, [kHostEf + k] source k's
+// new frontier edges.
+constexpr int kHostActive = 2;
+constexpr int kHostEf = 32;
+constexpr int kHostWords = kHostEf + kMaxSlots;
 
 struct MsArgs {
   const int64_t* __restrict__ offs;
@@ -40,21 +59,22 @@ struct MsArgs {
   u64* vis;
   const u64* __restrict__ fr;  // depth-d masks
   u64* frn;                    // depth-(d+1) masks (written for every vertex)
-  u64* nx;                     // top-down scratch: ORed masks, zero between levels
+  u64* nx;                     // top-down accumulator, zero between levels
   int8_t* lev;                 // [n][B] levels, vertex-major
-  u64* stats;                  // [kMsStats][2]: vertices with new bits, their degree sum
-  int64_t n;
-  int32_t W, B;                // words per vertex, sources
-  int32_t d;
+  u64* stats;                  // [kMsStats] rows: vertices with new bits, their degree sum
+  u64* slot_ef;                // [kMsStats][kMaxSlots]: per source, degree sum of its new frontier
+  u64* active;                 // [kMsStats][kMaxWords]: OR of the new frontier masks
   // serving sessions: int32 levels per slot ([slots][n]), level = d + 1 -
-  // start[slot] where d is the session's iteration; OR of the new frontier
-  // masks per word (which slots are still running), spread over kMsStats rows
+  // start[slot] where d is the session's iteration (null for the batch)
   int32_t* dist;
   const int32_t* start;
-  u64* active;
+  int64_t n;
+  int32_t W, B;  // words per vertex, level bytes per vertex
+  int32_t d;
+  int32_t any_push;       // the top-down pass ran this level (nx holds its bits)
+  u64 pmask[kMaxWords];   // sources expanded top-down this level
+  u64 qmask[kMaxWords];   // sources expanded bottom-up this level
 };
-
-constexpr int kMaxWords = GSW_MSBFS_MAX_SOURCES / 64;  // mask words per vertex at most
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
@@ -65,7 +85,26 @@ __device__ __forceinline__ u64 valid_bits(int j, int W, int B) {
   return (1ull << (B & 63)) - 1ull;
 }
 
-// Levels d+1 for the sources in `m` at vertex v, word j.
+// Word j of a per-source mask held in the kernel arguments (uniform loads,
+// then a per-lane select).
+__device__ __forceinline__ u64 mask_word(const u64 (&m)[kMaxWords], int j) {
+  u64 r = 0ull;
+#pragma unroll
+  for (int w = 0; w < kMaxWords; ++w)
+    if (w == j) r = m[w];
+  return r;
+}
+
+// 8 bits -> 8 bytes holding 0x01 where the bit is set.
+__device__ __forceinline__ u64 bits_to_bytes(u64 c) {
+  c = (c | (c << 28)) & 0x0000000F0000000Full;
+  c = (c | (c << 14)) & 0x0003000300030003ull;
+  c = (c | (c << 7)) & 0x0101010101010101ull;
+  return c;
+}
+
+// Levels d+1 for the sources in `m` (word j) at vertex v.  Only v's group
+// writes v's levels, so the batch's 8-byte read-modify-writes need no atomics.
 __device__ __forceinline__ void write_levels(const MsArgs& a, int64_t v, int j, u64 m) {
   if (a.dist) {
     while (m) {
@@ -76,12 +115,14 @@ __device__ __forceinline__ void write_levels(const MsArgs& a, int64_t v, int j, 
     }
     return;
   }
-  int8_t* row = a.lev + v * (int64_t)a.B + (int64_t)j * 64;
-  const int8_t val = (int8_t)(a.d + 1 > 127 ? 127 : a.d + 1);
-  while (m) {
-    const int b = __ffsll((long long)m) - 1;
-    m &= m - 1ull;
-    row[b] = val;
+  u64* row = reinterpret_cast<u64*>(a.lev + v * (int64_t)a.B + (int64_t)j * 64);
+  const u64 val = (u64)(uint8_t)(a.d + 1 > 127 ? 127 : a.d + 1) * 0x0101010101010101ull;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const u64 c = (m >> (8 * k)) & 0xffull;
+    if (!c) continue;
+    const u64 bm = bits_to_bytes(c) * 0xffull;
+    row[k] = (row[k] & ~bm) | (val & bm);
   }
 }
 
@@ -94,7 +135,6 @@ __device__ __forceinline__ void add_stats(const MsArgs& a, u64 nv, u64 ne) {
     s_e = 0ull;
   }
   __syncthreads();
-  // wave reduction, then one LDS atomic per wave
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     nv += __shfl_xor(nv, off);
@@ -112,10 +152,9 @@ __device__ __forceinline__ void add_stats(const MsArgs& a, u64 nv, u64 ne) {
   }
 }
 
-// Sessions: OR of this lane's new-frontier words into the active masks
-// (LDS per block, then one atomic per word into the block's spread row).
+// OR of this lane's new-frontier words into the active masks (LDS per
+// block, then one atomic per word into the block's spread row).
 __device__ __forceinline__ void add_active(const MsArgs& a, int j, u64 act) {
-  if (!a.active) return;
   __shared__ u64 s_act[kMaxWords];
   if (threadIdx.x < kMaxWords) s_act[threadIdx.x] = 0ull;
   __syncthreads();
@@ -125,36 +164,27 @@ __device__ __forceinline__ void add_active(const MsArgs& a, int j, u64 act) {
     atomicOr(a.active + (size_t)(blockIdx.x % kMsStats) * kMaxWords + threadIdx.x, s_act[threadIdx.x]);
 }
 
-// Group geometry: groups of G = W (rounded to a power of two, at most 64)
-// lanes, one vertex per group.
-struct Group {
-  int G, sub, first;  // lanes per group, lane within group, first lane of group in the wave
-  int64_t gid, ngroups;
+// Wave geometry: groups of G lanes (a power of two <= 16), one vertex per
+// group; a wave covers 64/G consecutive vertices per step.
+struct Wave {
+  int G, j, gi, gpw;
+  u64 gmask;  // this lane's group within the wave
+  int64_t first, stride;
 };
 
-__device__ __forceinline__ Group group_of(int G) {
-  Group g;
-  g.G = G;
+__device__ __forceinline__ Wave wave_of(int G) {
+  Wave w;
   const int lane = lane_id();
-  g.sub = lane & (G - 1);
-  g.first = lane & ~(G - 1);
-  const int64_t tid = (int64_t)blockIdx.x * kMsBlock + threadIdx.x;
-  g.gid = tid / G;
-  g.ngroups = (int64_t)gridDim.x * kMsBlock / G;
-  return g;
-}
-
-// OR of a per-lane flag over the lanes of this lane's group.
-__device__ __forceinline__ bool group_any(bool x, const Group& g) {
-  const u64 m = __ballot(x);
-  const u64 gm = g.G == 64 ? ~0ull : (((1ull << g.G) - 1ull) << g.first);
-  return (m & gm) != 0ull;
-}
-
-__device__ __forceinline__ bool group_all(bool x, const Group& g) {
-  const u64 m = __ballot(x);
-  const u64 gm = g.G == 64 ? ~0ull : (((1ull << g.G) - 1ull) << g.first);
-  return (m & gm) == gm;
+  w.G = G;
+  w.j = lane & (G - 1);
+  w.gi = lane / G;
+  w.gpw = 64 / G;
+  w.gmask = G == 64 ? ~0ull : (((1ull << G) - 1ull) << (w.gi * G));
+  const int64_t wave = ((int64_t)blockIdx.x * kMsBlock + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * kMsBlock) >> 6;
+  w.first = wave * w.gpw;
+  w.stride = nwaves * w.gpw;
+  return w;
 }
 
 // ------------------------------------------------------------------ init
@@ -189,113 +219,177 @@ __global__ void k_ms_sources(u64* vis, u64* fr, int8_t* lev, int W, int B,
 }
 
 // --------------------------------------------------------------- top-down
-// Group per frontier vertex u (grid-stride); for each neighbour v, lane j
-// ORs fr[u][j] & ~vis[v][j] into nx[v][j].
+// For each vertex u in the frontier of a top-down source: lane j ORs
+// fr[u][j] & pmask[j] & ~vis[v][j] into nx[v][j] for every neighbour v.
 __global__ void __launch_bounds__(kMsBlock) k_ms_push(MsArgs a, int G) {
-  const Group g = group_of(G);
-  const int j = g.sub;
-  const bool lane_live = j < a.W;
-  for (int64_t u = g.gid; u < a.n; u += g.ngroups) {
-    const u64 f = lane_live ? a.fr[u * a.W + j] : 0ull;
-    if (!group_any(f != 0ull, g)) continue;  // u is in no source's frontier
-    const int64_t end = a.offs[u + 1];
-    for (int64_t e = a.offs[u]; e < end; ++e) {
-      const int64_t v = a.cols[e];
-      if (f) {
+  const Wave w = wave_of(G);
+  const int j = w.j;
+  const u64 pm = j < a.W ? mask_word(a.pmask, j) : 0ull;
+  for (int64_t base = w.first; base < a.n; base += w.stride) {
+    const int64_t u = base + w.gi;
+    const u64 f = (u < a.n && pm) ? (a.fr[u * a.W + j] & pm) : 0ull;
+    const bool act = (__ballot(f != 0ull) & w.gmask) != 0ull;
+    int64_t beg = 0, end = 0;
+    if (act) {
+      beg = a.offs[u];
+      end = a.offs[u + 1];
+    }
+    const bool lng = end - beg > kMsLong;
+    if (f && !lng) {
+      for (int64_t e = beg; e < end; ++e) {
+        const int64_t v = a.cols[e];
         const u64 m = f & ~a.vis[v * a.W + j];
         if (m) atomicOr(a.nx + v * a.W + j, m);
       }
     }
-  }
-}
-
-// After a top-down level: new = nx & ~vis, then vis |= new, frn = new,
-// nx = 0, levels for the new bits, and the level's statistics.
-__global__ void __launch_bounds__(kMsBlock) k_ms_update(MsArgs a, int G) {
-  const Group g = group_of(G);
-  const int j = g.sub;
-  const bool lane_live = j < a.W;
-  u64 nv = 0, ne = 0, act = 0;
-  for (int64_t v = g.gid; v < a.n; v += g.ngroups) {
-    u64 nw = 0ull;
-    if (lane_live) {
-      const int64_t i = v * a.W + j;
-      const u64 x = a.nx[i];
-      const u64 s = a.vis[i];
-      nw = x & ~s;
-      if (x) a.nx[i] = 0ull;
-      if (nw) {
-        a.vis[i] = s | nw;
-        write_levels(a, v, j, nw);
+    // long rows: the whole wave, group gi taking edges gi, gi + 64/G, ...
+    u64 lm = __ballot(lng && j == 0);
+    while (lm) {
+      const int src = __ffsll((long long)lm) - 1;
+      lm &= lm - 1ull;
+      const int64_t b = __shfl((long long)beg, src);
+      const int64_t en = __shfl((long long)end, src);
+      const u64 fw = __shfl(f, src + j);
+      if (fw) {
+        for (int64_t e = b + w.gi; e < en; e += w.gpw) {
+          const int64_t v = a.cols[e];
+          const u64 m = fw & ~a.vis[v * a.W + j];
+          if (m) atomicOr(a.nx + v * a.W + j, m);
+        }
       }
-      a.frn[i] = nw;
-      act |= nw;
-    }
-    if (group_any(nw != 0ull, g) && g.sub == 0) {
-      nv += 1;
-      ne += (u64)(a.offs[v + 1] - a.offs[v]);
     }
   }
-  add_stats(a, nv, ne);
-  add_active(a, j, act);
 }
 
-// -------------------------------------------------------------- bottom-up
-// Group per vertex v with unvisited sources: OR the neighbours' frontier
-// masks restricted to what v still needs, stop when every needed source is
-// covered; v's own masks are updated in place (v's group is their only
-// writer), frn is written for every vertex.
-__global__ void __launch_bounds__(kMsBlock) k_ms_pull(MsArgs a, int G) {
-  const Group g = group_of(G);
-  const int j = g.sub;
+// ------------------------------------------------------ bottom-up + update
+// Every vertex v: the bottom-up sources it still needs (~vis & qmask) are
+// looked up in its neighbours' frontier masks, stopping once all are
+// covered; what the top-down pass left in nx (minus vis) joins them.  v's
+// group is the only writer of v's masks and levels.  Also accumulates the
+// level's statistics: vertices with new bits and their degrees, per source
+// the degree sum of its new frontier (sessions and the batch both steer
+// each source's direction by it), and the OR of the new frontier masks.
+__global__ void __launch_bounds__(kMsBlock) k_ms_level(MsArgs a, int G) {
+  __shared__ u64 s_ef[kMaxSlots];
+  const Wave w = wave_of(G);
+  const int j = w.j;
   const bool lane_live = j < a.W;
+  const u64 qm = lane_live ? mask_word(a.qmask, j) : 0ull;
+  const int nslots = a.W * 64;
+  for (int k = threadIdx.x; k < nslots; k += kMsBlock) s_ef[k] = 0ull;
+  __syncthreads();
   u64 nv = 0, ne = 0, act = 0;
-  for (int64_t v = g.gid; v < a.n; v += g.ngroups) {
+  for (int64_t base = w.first; base < a.n; base += w.stride) {
+    const int64_t v = base + w.gi;
+    const bool in = v < a.n && lane_live;
     const int64_t i = v * a.W + j;
-    const u64 s = lane_live ? a.vis[i] : ~0ull;
-    const u64 need = ~s;
+    const u64 s = in ? a.vis[i] : ~0ull;
+    const u64 x = (in && a.any_push) ? a.nx[i] : 0ull;
+    const u64 need = ~s & qm;
+    const bool want = (__ballot(need != 0ull) & w.gmask) != 0ull;
+    int64_t beg = 0, end = 0;
+    if (want) {
+      beg = a.offs[v];
+      end = a.offs[v + 1];
+    }
+    const bool lng = end - beg > kMsLong;
     u64 acc = 0ull;
-    if (group_any(need != 0ull, g)) {
-      const int64_t end = a.offs[v + 1];
-      for (int64_t e = a.offs[v]; e < end; ++e) {
+    if (want && !lng) {
+      for (int64_t e = beg; e < end; ++e) {
         const int64_t u = a.cols[e];
-        if (lane_live && need) acc |= a.fr[u * a.W + j] & need;
-        if (group_all(acc == need, g)) break;
+        if (need) acc |= a.fr[u * a.W + j] & need;
+        if ((__ballot(acc == need) & w.gmask) == w.gmask) break;
       }
     }
-    if (lane_live) {
-      if (acc) {
-        a.vis[i] = s | acc;
-        write_levels(a, v, j, acc);
+    u64 lm = __ballot(lng && j == 0);
+    while (lm) {
+      const int src = __ffsll((long long)lm) - 1;
+      lm &= lm - 1ull;
+      const int64_t b = __shfl((long long)beg, src);
+      const int64_t en = __shfl((long long)end, src);
+      const u64 nw = __shfl(need, src + j);
+      u64 c = 0ull;
+      for (int64_t e0 = b; e0 < en; e0 += w.gpw) {  // same trip count on every lane
+        const int64_t e = e0 + w.gi;
+        if (e < en && nw) c |= a.fr[(int64_t)a.cols[e] * a.W + j] & nw;
+        for (int off = G; off < 64; off <<= 1) c |= __shfl_xor(c, off);
+        if (__all(c == nw)) break;
       }
-      a.frn[i] = acc;
-      act |= acc;
+      if (w.gi * G == src) acc = c;
     }
-    if (group_any(acc != 0ull, g) && g.sub == 0) {
+    const u64 nb = (x & ~s) | acc;  // acc is within ~s
+    const bool grp_new = (__ballot(nb != 0ull) & w.gmask) != 0ull;
+    if (grp_new && !want) {
+      beg = a.offs[v];
+      end = a.offs[v + 1];
+    }
+    const u64 deg = (u64)(end - beg);
+    if (in) {
+      if (x) a.nx[i] = 0ull;
+      if (nb) {
+        a.vis[i] = s | nb;
+        write_levels(a, v, j, nb);
+        u64 m = nb;
+        while (m) {
+          const int bt = __ffsll((long long)m) - 1;
+          m &= m - 1ull;
+          atomicAdd(&s_ef[j * 64 + bt], deg);
+        }
+      }
+      a.frn[i] = nb;
+      act |= nb;
+    }
+    if (grp_new && j == 0) {
       nv += 1;
-      ne += (u64)(a.offs[v + 1] - a.offs[v]);
+      ne += deg;
     }
   }
   add_stats(a, nv, ne);
   add_active(a, j, act);
+  __syncthreads();
+  u64* row = a.slot_ef + (size_t)(blockIdx.x % kMsStats) * kMaxSlots;
+  for (int k = threadIdx.x; k < nslots; k += kMsBlock)
+    if (s_ef[k]) atomicAdd(row + k, s_ef[k]);
 }
 
-// Sum of the spread statistics counters to mapped host memory, then zero.
-__global__ void k_ms_finalize(u64* stats, u64* host) {
-  const int lane = lane_id();
+// Sums the spread counters into mapped host memory (layout at kHostEf), then
+// zeroes them.  Word 0 is stored last, after every other word is visible.
+__global__ void __launch_bounds__(256) k_ms_finalize(u64* stats, u64* active, u64* slot_ef, int W,
+                                                     int nslots, u64* host) {
+  const int t = threadIdx.x;
+  for (int k = t; k < nslots; k += 256) {
+    u64 x = 0ull;
+    for (int r = 0; r < kMsStats; ++r) {
+      x += slot_ef[r * kMaxSlots + k];
+      slot_ef[r * kMaxSlots + k] = 0ull;
+    }
+    __hip_atomic_store(host + kHostEf + k, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+  if (t < W) {
+    u64 x = 0ull;
+    for (int r = 0; r < kMsStats; ++r) {
+      x |= active[r * kMaxWords + t];
+      active[r * kMaxWords + t] = 0ull;
+    }
+    __hip_atomic_store(host + kHostActive + t, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
   u64 v = 0, e = 0;
-  if (lane < kMsStats) {
-    v = stats[lane * kMsStatStride];
-    e = stats[lane * kMsStatStride + 1];
-    stats[lane * kMsStatStride] = 0ull;
-    stats[lane * kMsStatStride + 1] = 0ull;
-  }
+  if (t < 64) {  // wave 0
+    if (t < kMsStats) {
+      v = stats[t * kMsStatStride];
+      e = stats[t * kMsStatStride + 1];
+      stats[t * kMsStatStride] = 0ull;
+      stats[t * kMsStatStride + 1] = 0ull;
+    }
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    v += __shfl_xor(v, off);
-    e += __shfl_xor(e, off);
+    for (int off = 32; off > 0; off >>= 1) {
+      v += __shfl_xor(v, off);
+      e += __shfl_xor(e, off);
+    }
   }
-  if (lane == 0) {
+  __threadfence_system();
+  __syncthreads();
+  if (t == 0) {
     __hip_atomic_store(host + 1, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     __hip_atomic_store(host, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   }
@@ -354,38 +448,6 @@ __global__ void __launch_bounds__(kMsBlock) k_ss_fill(int32_t* p, int64_t count,
   for (int64_t i = (int64_t)blockIdx.x * kMsBlock + threadIdx.x; i < count; i += stride) p[i] = val;
 }
 
-// Level statistics and the OR of the active rows to mapped host memory
-// ([0] vertices with new bits, [1] their degree sum, [2 + j] active word j),
-// then zero.  [0] is stored last.
-__global__ void k_ss_finalize(u64* stats, u64* active, int W, u64* host) {
-  const int lane = lane_id();
-  u64 v = 0, e = 0;
-  if (lane < kMsStats) {
-    v = stats[lane * kMsStatStride];
-    e = stats[lane * kMsStatStride + 1];
-    stats[lane * kMsStatStride] = 0ull;
-    stats[lane * kMsStatStride + 1] = 0ull;
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    v += __shfl_xor(v, off);
-    e += __shfl_xor(e, off);
-  }
-  if (lane < W) {
-    u64 x = 0ull;
-    for (int b = 0; b < kMsStats; ++b) {
-      x |= active[b * kMaxWords + lane];
-      active[b * kMaxWords + lane] = 0ull;
-    }
-    __hip_atomic_store(host + 2 + lane, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  }
-  __syncthreads();
-  if (lane == 0) {
-    __hip_atomic_store(host + 1, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(host, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-  }
-}
-
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 inline int group_lanes(int W) {
@@ -394,9 +456,116 @@ inline int group_lanes(int W) {
   return G;  // W <= 16 -> G <= 16
 }
 
-inline unsigned ms_grid(int64_t groups, int G) {
-  const int64_t blocks = cdiv(groups * G, kMsBlock);
+// Enough waves for n vertices at 64/G per wave step, at most kMsMaxGrid blocks.
+inline unsigned ms_grid(int64_t n, int G) {
+  const int64_t blocks = cdiv(n * G, kMsBlock);
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks, kMsMaxGrid));
+}
+
+// Spread statistics counters and the mapped host words of one traversal.
+struct LevelStats {
+  u64 *stats = nullptr, *active = nullptr, *slot_ef = nullptr;
+  u64 *h = nullptr, *d_h = nullptr;  // mapped host memory (kHostWords)
+  size_t bytes = 0;
+};
+
+gsw_status stats_alloc(LevelStats* st) {
+  const size_t sb = (size_t)kMsStats * kMsStatStride * sizeof(u64);
+  const size_t ab = (size_t)kMsStats * kMaxWords * sizeof(u64);
+  const size_t eb = (size_t)kMsStats * kMaxSlots * sizeof(u64);
+  void** ps[] = {(void**)&st->stats, (void**)&st->active, (void**)&st->slot_ef};
+  const size_t bs[] = {sb, ab, eb};
+  for (int k = 0; k < 3; ++k) {
+    if (hipMalloc(ps[k], bs[k]) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(GSW_ENOMEM, "hipMalloc(%zu) for level statistics failed", bs[k]);
+    }
+    st->bytes += bs[k];
+    GSW_HIP(hipMemset(*ps[k], 0, bs[k]));
+  }
+  GSW_HIP(hipHostMalloc((void**)&st->h, kHostWords * sizeof(u64), hipHostMallocMapped | hipHostMallocCoherent));
+  GSW_HIP(hipHostGetDevicePointer((void**)&st->d_h, st->h, 0));
+  return GSW_OK;
+}
+
+void stats_free(LevelStats* st) {
+  void* p[] = {st->stats, st->active, st->slot_ef};
+  for (void* x : p)
+    if (x) (void)hipFree(x);
+  if (st->h) (void)hipHostFree(st->h);
+  *st = LevelStats();
+}
+
+// Spins until the level's finalize kernel has published word 0, polling the
+// stream for errors now and then.
+gsw_status stats_wait(const LevelStats& st, hipStream_t s, const char* who) {
+  volatile u64* f = st.h;
+  for (uint64_t it = 0;; ++it) {
+    if (f[0] != ~0ull) return GSW_OK;
+    if ((it & 4095u) == 4095u) {
+      const hipError_t e = hipStreamQuery(s);
+      if (e == hipSuccess) {
+        if (f[0] != ~0ull) continue;
+        return fail(GSW_EHIP, "%s: level finished without reporting its statistics", who);
+      }
+      if (e != hipErrorNotReady) return fail(GSW_EHIP, "%s: %s", who, hipGetErrorString(e));
+    }
+    __builtin_ia32_pause();
+  }
+}
+
+// Per-source direction, the single-source rule applied to each source:
+// bottom-up once its frontier's edges exceed push_to_pull of all arcs, back
+// to top-down below pull_to_push.  Sources not running are in neither mask.
+struct Direction {
+  std::vector<uint8_t> pull;
+  std::vector<u64> ef;
+  void reset(int slots) {
+    pull.assign((size_t)slots, 0);
+    ef.assign((size_t)slots, 0ull);
+  }
+  void start(int k) {
+    pull[(size_t)k] = 0;
+    ef[(size_t)k] = 0ull;
+  }
+  // running: W words; fills pm/qm (kMaxWords words each)
+  void choose(const u64* running, int W, bool pull_ok, double a_arcs, double b_arcs, u64* pm,
+              u64* qm) {
+    for (int j = 0; j < kMaxWords; ++j) pm[j] = qm[j] = 0ull;
+    for (int j = 0; j < W; ++j) {
+      u64 r = running[j];
+      while (r) {
+        const int b = __builtin_ctzll(r);
+        r &= r - 1ull;
+        const size_t k = (size_t)j * 64 + b;
+        if (pull_ok) {
+          if (!pull[k] && (double)ef[k] > a_arcs) pull[k] = 1;
+          else if (pull[k] && (double)ef[k] < b_arcs) pull[k] = 0;
+        } else {
+          pull[k] = 0;
+        }
+        (pull[k] ? qm : pm)[j] |= 1ull << b;
+      }
+    }
+  }
+};
+
+// Launches one level: the top-down pass when some source pushes, then the
+// bottom-up + update pass and the finalize kernel.  a.pmask / a.qmask are
+// set by the caller.
+gsw_status launch_ms_level(MsArgs& a, const LevelStats& st, int G, int nslots, hipStream_t s) {
+  a.stats = st.stats;
+  a.active = st.active;
+  a.slot_ef = st.slot_ef;
+  a.any_push = 0;
+  for (int j = 0; j < kMaxWords; ++j) a.any_push |= a.pmask[j] != 0ull;
+  const unsigned grid = ms_grid(a.n, G);
+  if (a.any_push) hipLaunchKernelGGL(k_ms_push, dim3(grid), dim3(kMsBlock), 0, s, a, G);
+  hipLaunchKernelGGL(k_ms_level, dim3(grid), dim3(kMsBlock), 0, s, a, G);
+  hipLaunchKernelGGL(k_ms_finalize, dim3(1), dim3(256), 0, s, st.stats, st.active, st.slot_ef, a.W, nslots,
+                     st.d_h);
+  GSW_HIP(hipGetLastError());
+  return GSW_OK;
 }
 
 }  // namespace
@@ -404,27 +573,26 @@ inline unsigned ms_grid(int64_t groups, int G) {
 struct MsWorkspace {
   int64_t n = 0;
   int W = 0, B = 0;
-  u64 *vis = nullptr, *fr = nullptr, *frn = nullptr, *nx = nullptr, *stats = nullptr;
+  u64 *vis = nullptr, *fr = nullptr, *frn = nullptr, *nx = nullptr;
   int8_t* lev = nullptr;
   int32_t* src = nullptr;
-  u64* h_stats = nullptr;  // mapped host memory
-  u64* d_hstats = nullptr;
+  LevelStats st;
   size_t bytes = 0;
 };
 
 namespace {
 void ms_free(MsWorkspace* m) {
   if (!m) return;
-  void* p[] = {m->vis, m->fr, m->frn, m->nx, m->stats, m->lev, m->src};
+  void* p[] = {m->vis, m->fr, m->frn, m->nx, m->lev, m->src};
   for (void* x : p)
     if (x) (void)hipFree(x);
-  if (m->h_stats) (void)hipHostFree(m->h_stats);
+  stats_free(&m->st);
   delete m;
 }
 
-gsw_status ms_ensure(gsw_graph* g, int W, int B) {
+gsw_status ms_ensure(gsw_graph* g, int W) {
   MsWorkspace*& m = g->ms;
-  if (m && m->W >= W && m->B >= B) return GSW_OK;
+  if (m && m->W >= W) return GSW_OK;
   ms_free(m);
   m = new (std::nothrow) MsWorkspace();
   if (!m) return fail(GSW_ENOMEM, "host allocation failed");
@@ -439,45 +607,25 @@ gsw_status ms_ensure(gsw_graph* g, int W, int B) {
                {(void**)&m->fr, mb},
                {(void**)&m->frn, mb},
                {(void**)&m->nx, mb},
-               {(void**)&m->stats, (size_t)kMsStats * kMsStatStride * sizeof(u64)},
                {(void**)&m->lev, (size_t)g->n * m->B},
                {(void**)&m->src, (size_t)m->B * sizeof(int32_t)}};
+  gsw_status st = GSW_OK;
   for (auto& it : items) {
-    hipError_t e = hipMalloc(it.p, it.bytes);
-    if (e != hipSuccess) {
+    if (hipMalloc(it.p, it.bytes) != hipSuccess) {
       (void)hipGetLastError();
-      ms_free(m);
-      m = nullptr;
-      return fail(GSW_ENOMEM, "hipMalloc(%zu) for the batched BFS failed", it.bytes);
+      st = fail(GSW_ENOMEM, "hipMalloc(%zu) for the batched BFS failed", it.bytes);
+      break;
     }
     m->bytes += it.bytes;
   }
-  GSW_HIP(hipMemset(m->stats, 0, (size_t)kMsStats * kMsStatStride * sizeof(u64)));
-  GSW_HIP(hipHostMalloc((void**)&m->h_stats, 64 * sizeof(u64),
-                        hipHostMallocMapped | hipHostMallocCoherent));
-  GSW_HIP(hipHostGetDevicePointer((void**)&m->d_hstats, m->h_stats, 0));
-  return GSW_OK;
-}
-
-gsw_status ms_wait(MsWorkspace* m, hipStream_t s, u64* nv, u64* ne) {
-  volatile u64* f = m->h_stats;
-  for (uint64_t it = 0;; ++it) {
-    const u64 v = f[0];
-    if (v != ~0ull) {
-      *nv = v;
-      *ne = f[1];
-      return GSW_OK;
-    }
-    if ((it & 4095u) == 4095u) {
-      const hipError_t e = hipStreamQuery(s);
-      if (e == hipSuccess) {
-        if (f[0] != ~0ull) continue;
-        return fail(GSW_EHIP, "batched level finished without reporting its statistics");
-      }
-      if (e != hipErrorNotReady) return fail(GSW_EHIP, "batched BFS: %s", hipGetErrorString(e));
-    }
-    __builtin_ia32_pause();
+  if (st == GSW_OK) st = stats_alloc(&m->st);
+  if (st != GSW_OK) {
+    ms_free(m);
+    m = nullptr;
+    return st;
   }
+  m->bytes += m->st.bytes;
+  return GSW_OK;
 }
 }  // namespace
 
@@ -517,10 +665,10 @@ gsw_status gsw_msbfs(const gsw_graph* cg, const int32_t* sources, int32_t n_sour
   GSW_HIP(hipSetDevice(g->device));
   const bool pull_ok = g->symmetric != 0;
   const int W = (n_sources + 63) / 64;
-  GSW_TRY(ms_ensure(g, W, W * 64));
+  GSW_TRY(ms_ensure(g, W));
   MsWorkspace* m = g->ms;
   const hipStream_t s = pick_stream(g, o->stream);
-  const int B = W * 64;  // level rows per vertex in the workspace
+  const int B = W * 64;  // level bytes per vertex in the workspace
   const int G = group_lanes(W);
   GSW_HIP(hipMemcpyAsync(m->src, sources, (size_t)n_sources * sizeof(int32_t), hipMemcpyHostToDevice, s));
   {
@@ -533,57 +681,39 @@ gsw_status gsw_msbfs(const gsw_graph* cg, const int32_t* sources, int32_t n_sour
     GSW_HIP(hipGetLastError());
   }
   MsArgs a;
+  std::memset(&a, 0, sizeof a);
   a.offs = g->offs;
   a.cols = g->cols;
   a.vis = m->vis;
+  a.nx = m->nx;
   a.lev = m->lev;
-  a.stats = m->stats;
-  a.dist = nullptr;
-  a.start = nullptr;
-  a.active = nullptr;
   a.n = g->n;
   a.W = W;
   a.B = B;
   u64* cur = m->fr;
   u64* nxt = m->frn;
-  // frontier statistics of depth 0 (for the direction choice)
-  u64 nf = 0, ef = 0;
-  {
-    std::vector<int32_t> uniq(sources, sources + n_sources);
-    std::sort(uniq.begin(), uniq.end());
-    uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
-    nf = uniq.size();
-  }
-  bool pull = false;
+  std::vector<u64> running((size_t)W, 0ull);
+  for (int32_t i = 0; i < n_sources; ++i) running[(size_t)(i >> 6)] |= 1ull << (i & 63);
+  Direction dir;
+  dir.reset(B);
   const double nnz = (double)std::max<int64_t>(g->nnz, 1);
   int32_t d = 0;
   for (;; ++d) {
-    // direction: pull once the frontier's edges are a large share of all
-    // arcs, back to push when the frontier is small again
-    if (pull_ok) {
-      if (!pull && ef > (u64)(o->push_to_pull * nnz)) pull = true;
-      else if (pull && ef < (u64)(o->pull_to_push * nnz)) pull = false;
-    }
+    dir.choose(running.data(), W, pull_ok, o->push_to_pull * nnz, o->pull_to_push * nnz, a.pmask, a.qmask);
     a.fr = cur;
     a.frn = nxt;
-    a.nx = m->nx;
     a.d = d;
-    m->h_stats[0] = ~0ull;
-    if (pull) {
-      hipLaunchKernelGGL(k_ms_pull, dim3(ms_grid(g->n, G)), dim3(kMsBlock), 0, s, a, G);
-    } else {
-      hipLaunchKernelGGL(k_ms_push, dim3(ms_grid(g->n, G)), dim3(kMsBlock), 0, s, a, G);
-      hipLaunchKernelGGL(k_ms_update, dim3(ms_grid(g->n, G)), dim3(kMsBlock), 0, s, a, G);
-    }
-    hipLaunchKernelGGL(k_ms_finalize, dim3(1), dim3(64), 0, s, m->stats, m->d_hstats);
-    GSW_HIP(hipGetLastError());
-    u64 nv = 0, ne = 0;
-    GSW_TRY(ms_wait(m, s, &nv, &ne));
-    if (nv == 0) break;
-    if (d + 1 > GSW_MSBFS_LEVEL_CAP)
+    m->st.h[0] = ~0ull;
+    GSW_TRY(launch_ms_level(a, m->st, G, n_sources, s));
+    GSW_TRY(stats_wait(m->st, s, "batched BFS"));
+    const volatile u64* h = m->st.h;
+    if (h[0] == 0) break;
+    if (d + 1 > GSW_MSBFS_LEVEL_CAP) {
+      (void)hipStreamSynchronize(s);
       return fail(GSW_ERANGE, "a source reaches depth %d > %d (int8 levels)", d + 1, GSW_MSBFS_LEVEL_CAP);
-    nf = nv;
-    ef = ne;
+    }
+    for (int j = 0; j < W; ++j) running[(size_t)j] = h[kHostActive + j];
+    for (int32_t k = 0; k < n_sources; ++k) dir.ef[(size_t)k] = h[kHostEf + k];
     std::swap(cur, nxt);
   }
   if (n_levels) *n_levels = d + 1;
@@ -604,7 +734,6 @@ gsw_status gsw_msbfs(const gsw_graph* cg, const int32_t* sources, int32_t n_sour
   }
   if (hipStreamSynchronize(s) != hipSuccess && st == GSW_OK) st = fail(GSW_EHIP, "stream synchronize failed");
   if (tmp) (void)hipFree(tmp);
-  (void)nf;
   return st;
 }
 
@@ -615,52 +744,38 @@ struct gsw_session {
   gsw_graph* g = nullptr;
   int W = 0, slots = 0;
   u64 *vis = nullptr, *fr = nullptr, *frn = nullptr, *nx = nullptr;
-  u64 *stats = nullptr, *active = nullptr, *masks = nullptr;  // masks: clr[W] then set[W]
+  u64* masks = nullptr;                                          // clr[kMaxWords] then set[kMaxWords]
   int32_t *dist = nullptr, *start_d = nullptr, *seed = nullptr;  // seed: src[slots] then slot[slots]
-  u64 *h_stats = nullptr, *d_hstats = nullptr;
-  std::vector<int32_t> start_h, source;
-  std::vector<int8_t> state;  // 0 free, 1 admitted (seeded at the next step), 2 running, 3 finished
-  std::vector<u64> freed;     // slots freed since the last step (made inert then)
-  int64_t it = 0;             // levels run by this session
-  u64 ef = 0;
-  bool pull = false;
+  LevelStats st;
+  // pinned staging for the per-level uploads: masks, then seed src/slot, then start
+  u64* h_masks = nullptr;
+  int32_t* h_seed = nullptr;
+  int32_t* h_start = nullptr;
+  std::vector<int32_t> source;
+  std::vector<int8_t> state;  // 0 free, 1 admitted (seeded at the next level boundary), 2 running, 3 finished
+  std::vector<u64> freed;     // slots freed since the last level (made inert then)
+  Direction dir;
+  int64_t it = 0;  // levels run by this session
   float push_to_pull = 0.05f, pull_to_push = 0.01f;
   hipStream_t stream = nullptr;
   size_t bytes = 0;
-  std::mutex mu;
+  std::mutex mu;     // host state shared with admit / fetch / info
+  std::mutex step_mu;  // one step or fetch at a time
 };
 
 namespace {
 
 void ss_free(gsw_session* ss) {
   if (!ss) return;
-  void* p[] = {ss->vis, ss->fr, ss->frn, ss->nx, ss->stats, ss->active, ss->masks, ss->dist,
-               ss->start_d, ss->seed};
+  void* p[] = {ss->vis, ss->fr, ss->frn, ss->nx, ss->masks, ss->dist, ss->start_d, ss->seed};
   for (void* x : p)
     if (x) (void)hipFree(x);
-  if (ss->h_stats) (void)hipHostFree(ss->h_stats);
+  stats_free(&ss->st);
+  void* hp[] = {ss->h_masks, ss->h_seed, ss->h_start};
+  for (void* x : hp)
+    if (x) (void)hipHostFree(x);
   if (ss->stream) (void)hipStreamDestroy(ss->stream);
   delete ss;
-}
-
-gsw_status ss_wait(gsw_session* ss, u64* nv, u64* ne) {
-  volatile u64* f = ss->h_stats;
-  for (uint64_t k = 0;; ++k) {
-    if (f[0] != ~0ull) {
-      *nv = f[0];
-      *ne = f[1];
-      return GSW_OK;
-    }
-    if ((k & 4095u) == 4095u) {
-      const hipError_t e = hipStreamQuery(ss->stream);
-      if (e == hipSuccess) {
-        if (f[0] != ~0ull) continue;
-        return fail(GSW_EHIP, "session level finished without reporting its statistics");
-      }
-      if (e != hipErrorNotReady) return fail(GSW_EHIP, "session: %s", hipGetErrorString(e));
-    }
-    __builtin_ia32_pause();
-  }
 }
 
 }  // namespace
@@ -690,8 +805,6 @@ gsw_status gsw_session_create(const gsw_graph* cg, int32_t max_slots, gsw_sessio
                {(void**)&ss->fr, mb},
                {(void**)&ss->frn, mb},
                {(void**)&ss->nx, mb},
-               {(void**)&ss->stats, (size_t)kMsStats * kMsStatStride * sizeof(u64)},
-               {(void**)&ss->active, (size_t)kMsStats * kMaxWords * sizeof(u64)},
                {(void**)&ss->masks, 2 * (size_t)kMaxWords * sizeof(u64)},
                {(void**)&ss->dist, (size_t)max_slots * n * sizeof(int32_t)},
                {(void**)&ss->start_d, (size_t)max_slots * sizeof(int32_t)},
@@ -705,18 +818,20 @@ gsw_status gsw_session_create(const gsw_graph* cg, int32_t max_slots, gsw_sessio
     }
     ss->bytes += it.bytes;
   }
-  gsw_status st = GSW_OK;
-  if (hipStreamCreateWithFlags(&ss->stream, hipStreamNonBlocking) != hipSuccess ||
-      hipHostMalloc((void**)&ss->h_stats, 64 * sizeof(u64), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
-      hipHostGetDevicePointer((void**)&ss->d_hstats, ss->h_stats, 0) != hipSuccess)
-    st = fail(GSW_EHIP, "session stream or mapped memory");
+  gsw_status st = stats_alloc(&ss->st);
+  if (st == GSW_OK) {
+    ss->bytes += ss->st.bytes;
+    if (hipStreamCreateWithFlags(&ss->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipHostMalloc((void**)&ss->h_masks, 2 * (size_t)kMaxWords * sizeof(u64), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&ss->h_seed, 2 * (size_t)max_slots * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&ss->h_start, (size_t)max_slots * sizeof(int32_t), hipHostMallocDefault) != hipSuccess)
+      st = fail(GSW_EHIP, "session stream or pinned staging memory");
+  }
   if (st == GSW_OK) {
     const hipStream_t s = ss->stream;
     // every slot starts inert: visited everywhere, in no frontier, levels -1
     if (hipMemsetAsync(ss->vis, 0xff, mb, s) != hipSuccess || hipMemsetAsync(ss->fr, 0, mb, s) != hipSuccess ||
         hipMemsetAsync(ss->frn, 0, mb, s) != hipSuccess || hipMemsetAsync(ss->nx, 0, mb, s) != hipSuccess ||
-        hipMemsetAsync(ss->stats, 0, (size_t)kMsStats * kMsStatStride * sizeof(u64), s) != hipSuccess ||
-        hipMemsetAsync(ss->active, 0, (size_t)kMsStats * kMaxWords * sizeof(u64), s) != hipSuccess ||
         hipMemsetAsync(ss->dist, 0xff, (size_t)max_slots * n * sizeof(int32_t), s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       st = fail(GSW_EHIP, "session initialisation failed");
@@ -725,10 +840,11 @@ gsw_status gsw_session_create(const gsw_graph* cg, int32_t max_slots, gsw_sessio
     ss_free(ss);
     return st;
   }
-  ss->start_h.assign((size_t)max_slots, 0);
+  std::memset(ss->h_start, 0, (size_t)max_slots * sizeof(int32_t));
   ss->source.assign((size_t)max_slots, -1);
   ss->state.assign((size_t)max_slots, 0);
   ss->freed.assign((size_t)ss->W, 0ull);
+  ss->dir.reset(max_slots);
   *out = ss;
   return GSW_OK;
 }
@@ -744,7 +860,6 @@ gsw_status gsw_session_admit(gsw_session* ss, int32_t source, int32_t* slot) {
     if (ss->state[(size_t)k] == 0) {
       ss->state[(size_t)k] = 1;
       ss->source[(size_t)k] = source;
-      ss->start_h[(size_t)k] = (int32_t)ss->it;
       *slot = k;
       return GSW_OK;
     }
@@ -758,91 +873,91 @@ gsw_status gsw_session_step(gsw_session* ss, int32_t max_levels, int32_t* finish
   if (n_finished) *n_finished = 0;
   if (levels_run) *levels_run = 0;
   if (!ss || max_levels < 1 || (finished_cap > 0 && !finished)) return fail(GSW_EINVAL, "bad step arguments");
-  std::lock_guard<std::mutex> lock(ss->mu);
+  std::lock_guard<std::mutex> step_lock(ss->step_mu);
   gsw_graph* g = ss->g;
   GSW_HIP(hipSetDevice(g->device));
   const hipStream_t s = ss->stream;
   const int W = ss->W;
   const int64_t n = g->n;
-  // admit: clear the admitted slots' bits, make freed slots inert, seed sources
-  std::vector<u64> msk(2 * (size_t)kMaxWords, 0ull);
-  std::vector<int32_t> seed_src, seed_slot;
-  for (int k = 0; k < ss->slots; ++k)
-    if (ss->state[(size_t)k] == 1) {
-      msk[(size_t)(k >> 6)] |= 1ull << (k & 63);
-      seed_src.push_back(ss->source[(size_t)k]);
-      seed_slot.push_back(k);
-    }
-  bool any_mask = !seed_src.empty();
-  for (int j = 0; j < W; ++j) {
-    msk[(size_t)kMaxWords + j] = ss->freed[(size_t)j] & ~msk[(size_t)j];
-    any_mask = any_mask || msk[(size_t)kMaxWords + j];
-    ss->freed[(size_t)j] = 0ull;
-  }
   const int G = group_lanes(W);
-  if (any_mask) {
-    GSW_HIP(hipMemcpyAsync(ss->masks, msk.data(), msk.size() * sizeof(u64), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_ss_masks, dim3((unsigned)std::min<int64_t>(cdiv(n * W, kMsBlock), 65536)),
-                       dim3(kMsBlock), 0, s, ss->vis, n, W, (const u64*)ss->masks,
-                       (const u64*)(ss->masks + kMaxWords));
-  }
-  if (!seed_src.empty()) {
-    const int c = (int)seed_src.size();
-    GSW_HIP(hipMemcpyAsync(ss->seed, seed_src.data(), c * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    GSW_HIP(hipMemcpyAsync(ss->seed + ss->slots, seed_slot.data(), c * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    GSW_HIP(hipMemcpyAsync(ss->start_d, ss->start_h.data(), ss->slots * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_ss_seed, dim3((unsigned)cdiv(c, 256)), dim3(256), 0, s, ss->vis, ss->fr, ss->dist, n,
-                       W, (const int32_t*)ss->seed, (const int32_t*)(ss->seed + ss->slots), c);
-    for (int32_t k : seed_slot) ss->state[(size_t)k] = 2;
-  }
-  GSW_HIP(hipGetLastError());
+  const bool pull_ok = g->symmetric != 0;
+  const double nnz = (double)std::max<int64_t>(g->nnz, 1);
   MsArgs a;
+  std::memset(&a, 0, sizeof a);
   a.offs = g->offs;
   a.cols = g->cols;
   a.vis = ss->vis;
   a.nx = ss->nx;
-  a.lev = nullptr;
-  a.stats = ss->stats;
   a.n = n;
   a.W = W;
   a.B = W * 64;
   a.dist = ss->dist;
   a.start = ss->start_d;
-  a.active = ss->active;
-  const bool pull_ok = g->symmetric != 0;
-  const double nnz = (double)std::max<int64_t>(g->nnz, 1);
   int32_t nfin = 0, run = 0;
+  std::vector<u64> running((size_t)W);
   for (; run < max_levels; ++run) {
-    bool running = false;
-    for (int k = 0; k < ss->slots && !running; ++k) running = ss->state[(size_t)k] == 2;
-    if (!running) break;
-    if (pull_ok) {
-      if (!ss->pull && ss->ef > (u64)(ss->push_to_pull * nnz)) ss->pull = true;
-      else if (ss->pull && ss->ef < (u64)(ss->pull_to_push * nnz)) ss->pull = false;
-    } else {
-      ss->pull = false;
+    // level boundary: take the queries admitted since the last level, make
+    // freed slots inert, pick each running slot's direction
+    int c = 0;
+    bool any_mask = false;
+    {
+      std::lock_guard<std::mutex> lock(ss->mu);
+      u64* clr = ss->h_masks;
+      u64* set = ss->h_masks + kMaxWords;
+      for (int j = 0; j < kMaxWords; ++j) clr[j] = set[j] = 0ull;
+      for (int k = 0; k < ss->slots; ++k)
+        if (ss->state[(size_t)k] == 1) {
+          clr[k >> 6] |= 1ull << (k & 63);
+          ss->h_seed[c] = ss->source[(size_t)k];
+          ss->h_seed[ss->slots + c] = k;
+          ss->h_start[k] = (int32_t)ss->it;
+          ss->state[(size_t)k] = 2;
+          ss->dir.start(k);
+          ++c;
+        }
+      for (int j = 0; j < W; ++j) {
+        set[j] = ss->freed[(size_t)j] & ~clr[j];
+        any_mask = any_mask || clr[j] || set[j];
+        ss->freed[(size_t)j] = 0ull;
+      }
+      std::fill(running.begin(), running.end(), 0ull);
+      for (int k = 0; k < ss->slots; ++k)
+        if (ss->state[(size_t)k] == 2) running[(size_t)(k >> 6)] |= 1ull << (k & 63);
     }
+    bool any_running = false;
+    for (u64 r : running) any_running = any_running || r;
+    if (any_mask) {
+      GSW_HIP(hipMemcpyAsync(ss->masks, ss->h_masks, 2 * (size_t)kMaxWords * sizeof(u64), hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_ss_masks, dim3((unsigned)std::min<int64_t>(cdiv(n * W, kMsBlock), 65536)),
+                         dim3(kMsBlock), 0, s, ss->vis, n, W, (const u64*)ss->masks,
+                         (const u64*)(ss->masks + kMaxWords));
+    }
+    if (c > 0) {
+      GSW_HIP(hipMemcpyAsync(ss->seed, ss->h_seed, 2 * (size_t)ss->slots * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      GSW_HIP(hipMemcpyAsync(ss->start_d, ss->h_start, ss->slots * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_ss_seed, dim3((unsigned)cdiv(c, 256)), dim3(256), 0, s, ss->vis, ss->fr, ss->dist, n,
+                         W, (const int32_t*)ss->seed, (const int32_t*)(ss->seed + ss->slots), c);
+    }
+    GSW_HIP(hipGetLastError());
+    if (!any_running) {
+      if (any_mask) GSW_HIP(hipStreamSynchronize(s));
+      break;
+    }
+    ss->dir.choose(running.data(), W, pull_ok, ss->push_to_pull * nnz, ss->pull_to_push * nnz, a.pmask, a.qmask);
     a.fr = ss->fr;
     a.frn = ss->frn;
     a.d = (int32_t)ss->it;
-    ss->h_stats[0] = ~0ull;
-    if (ss->pull) {
-      hipLaunchKernelGGL(k_ms_pull, dim3(ms_grid(n, G)), dim3(kMsBlock), 0, s, a, G);
-    } else {
-      hipLaunchKernelGGL(k_ms_push, dim3(ms_grid(n, G)), dim3(kMsBlock), 0, s, a, G);
-      hipLaunchKernelGGL(k_ms_update, dim3(ms_grid(n, G)), dim3(kMsBlock), 0, s, a, G);
-    }
-    hipLaunchKernelGGL(k_ss_finalize, dim3(1), dim3(64), 0, s, ss->stats, ss->active, W, ss->d_hstats);
-    GSW_HIP(hipGetLastError());
-    u64 nv = 0, ne = 0;
-    GSW_TRY(ss_wait(ss, &nv, &ne));
+    ss->st.h[0] = ~0ull;
+    GSW_TRY(launch_ms_level(a, ss->st, G, ss->slots, s));
+    GSW_TRY(stats_wait(ss->st, s, "session"));
     ss->it += 1;
-    ss->ef = ne;
     std::swap(ss->fr, ss->frn);
-    volatile u64* act = ss->h_stats + 2;
+    const volatile u64* h = ss->st.h;
+    std::lock_guard<std::mutex> lock(ss->mu);
     for (int k = 0; k < ss->slots; ++k) {
       if (ss->state[(size_t)k] != 2) continue;
-      if (((act[k >> 6] >> (k & 63)) & 1ull) == 0ull) {
+      ss->dir.ef[(size_t)k] = h[kHostEf + k];
+      if (((h[kHostActive + (k >> 6)] >> (k & 63)) & 1ull) == 0ull) {
         ss->state[(size_t)k] = 3;
         if (nfin < finished_cap) finished[nfin] = k;
         ++nfin;
@@ -861,9 +976,12 @@ gsw_status gsw_session_step(gsw_session* ss, int32_t max_levels, int32_t* finish
 gsw_status gsw_session_fetch(gsw_session* ss, int32_t slot, int32_t* levels, int32_t device_ptr) {
   clear_error();
   if (!ss || !levels) return fail(GSW_EINVAL, "null argument");
-  std::lock_guard<std::mutex> lock(ss->mu);
-  if (slot < 0 || slot >= ss->slots || ss->state[(size_t)slot] != 3)
-    return fail(GSW_EINVAL, "slot %d has no finished result", slot);
+  std::lock_guard<std::mutex> step_lock(ss->step_mu);
+  {
+    std::lock_guard<std::mutex> lock(ss->mu);
+    if (slot < 0 || slot >= ss->slots || ss->state[(size_t)slot] != 3)
+      return fail(GSW_EINVAL, "slot %d has no finished result", slot);
+  }
   GSW_HIP(hipSetDevice(ss->g->device));
   const hipStream_t s = ss->stream;
   const int64_t n = ss->g->n;
@@ -874,16 +992,19 @@ gsw_status gsw_session_fetch(gsw_session* ss, int32_t slot, int32_t* levels, int
                      s, row, n, -1);
   GSW_HIP(hipGetLastError());
   GSW_HIP(hipStreamSynchronize(s));
+  std::lock_guard<std::mutex> lock(ss->mu);
   ss->state[(size_t)slot] = 0;
   ss->source[(size_t)slot] = -1;
   ss->freed[(size_t)(slot >> 6)] |= 1ull << (slot & 63);
   return GSW_OK;
 }
 
-gsw_status gsw_session_info(const gsw_session* ss, int32_t* slots, int32_t* busy, int64_t* iteration,
+gsw_status gsw_session_info(const gsw_session* css, int32_t* slots, int32_t* busy, int64_t* iteration,
                             size_t* dev_bytes) {
   clear_error();
-  if (!ss) return fail(GSW_EINVAL, "session is null");
+  if (!css) return fail(GSW_EINVAL, "session is null");
+  gsw_session* ss = const_cast<gsw_session*>(css);
+  std::lock_guard<std::mutex> lock(ss->mu);
   if (slots) *slots = ss->slots;
   if (busy) {
     int32_t b = 0;
@@ -898,6 +1019,7 @@ gsw_status gsw_session_info(const gsw_session* ss, int32_t* slots, int32_t* busy
 gsw_status gsw_session_set_thresholds(gsw_session* ss, float push_to_pull, float pull_to_push) {
   clear_error();
   if (!ss) return fail(GSW_EINVAL, "session is null");
+  std::lock_guard<std::mutex> lock(ss->step_mu);
   ss->push_to_pull = push_to_pull;
   ss->pull_to_push = pull_to_push;
   return GSW_OK;

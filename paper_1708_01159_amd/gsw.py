@@ -445,7 +445,9 @@ class Session:
         return k.value
 
     def step(self, max_levels: int = 8):
-        """Runs levels until a slot finishes; returns (finished slots, levels run)."""
+        """Runs levels until a slot finishes, ``max_levels`` have run or nothing
+        is admitted or running; queries admitted meanwhile (from any thread)
+        join at level boundaries.  Returns (finished slots, levels run)."""
         nf, lr = ctypes.c_int32(0), ctypes.c_int32(0)
         _check(lib().gsw_session_step(self._h, max_levels, self._fin.ctypes.data, self.slots,
                                       ctypes.byref(nf), ctypes.byref(lr)))

@@ -90,8 +90,17 @@ def poisson_trace(rate_qps: float, duration_s: float, graphs, candidates, zipf_s
 
 
 class Server:
+    """Continuous batching over resident graphs.
+
+    The main loop admits arriving queries into free slots of their graph's
+    session at any time; a worker thread per session keeps stepping it (the
+    session takes new admissions at every level boundary inside its step),
+    fetches finished slots and records their completion time.  The worker
+    ends when its session has nothing admitted or running; the main loop
+    starts a new one when queries are admitted again."""
+
     def __init__(self, residents: dict, slots: int = 64, hbm_budget: int = None,
-                 levels_per_step: int = 4, keep_levels: bool = False, session_factory=None):
+                 levels_per_step: int = 1 << 20, keep_levels: bool = False, session_factory=None):
         self.res = residents
         self.new_session = session_factory or gsw.Session
         self.slots = slots
@@ -102,6 +111,9 @@ class Server:
         self.workers = {}           # graph -> single-thread executor
         self.used = 0
         self.evictions = 0
+        self._scratch_bufs = {}
+        self._live = {}             # graph -> future of its running worker
+        self._slot_mu = threading.Lock()
 
     def _ensure_session(self, name):
         if name in self.sessions:
@@ -110,7 +122,7 @@ class Server:
         if self.budget is not None:
             # make room by closing idle sessions of other graphs
             while self.used + need > self.budget:
-                idle = [g for g, s in self.sessions.items() if s.info()["busy"] == 0]
+                idle = [g for g, s in self.sessions.items() if s.info()["busy"] == 0 and g not in self._live]
                 if not idle:
                     return None
                 self._close(idle[0])
@@ -127,83 +139,88 @@ class Server:
         self.used -= session_bytes(self.res[name].graph.n, self.slots)
         s.close()
 
-    def _step(self, name, sess, slot_query):
-        """Worker: one step of a session and the fetch of its finished slots."""
-        fin, _ = sess.step(self.levels_per_step)
-        done = []
-        for k in fin:
-            out = np.empty(self.res[name].graph.n, dtype=np.int32) if self.keep else None
-            if out is None:
-                out = self._scratch(name)
-            sess.fetch(k, out)
-            done.append((k, out.copy() if self.keep else None))
-        return done
-
-    _scratch_bufs = {}
-
     def _scratch(self, name):
-        buf = self._scratch_bufs.get((id(self), name))
+        buf = self._scratch_bufs.get(name)
         if buf is None:
             import torch
 
             buf = torch.empty(self.res[name].graph.n, dtype=torch.int32, device="cuda")
-            self._scratch_bufs[(id(self), name)] = buf
+            self._scratch_bufs[name] = buf
         return buf
+
+    def _work(self, name, sess, slot_q, done_q, t0):
+        """Worker: step until nothing is admitted or running; each finished
+        slot is fetched (which frees it) after its query has been taken off
+        the slot map, so a new admission into that slot cannot be mistaken
+        for it."""
+        while True:
+            fin, run = sess.step(self.levels_per_step)
+            for k in fin:
+                with self._slot_mu:
+                    q = slot_q.pop(k)
+                out = np.empty(self.res[name].graph.n, dtype=np.int32) if self.keep else self._scratch(name)
+                sess.fetch(k, out)
+                q.t_done = time.perf_counter() - t0
+                q.levels = out if self.keep else None
+                done_q.append(q)
+            if run == 0 and not fin:
+                return
 
     def run(self, trace, timeout_s: float = 600.0):
         """Serves ``trace`` = [(t_arrival, graph, source)] in real time; returns
         the list of completed Query objects."""
         queries = [Query(i, g, s, t) for i, (t, g, s) in enumerate(sorted(trace))]
         pending = collections.defaultdict(collections.deque)
-        inflight = {}               # graph -> future
-        slot_q = collections.defaultdict(dict)  # graph -> slot -> Query
+        slot_q = collections.defaultdict(dict)  # graph -> slot -> Query (admitted, not yet fetched)
+        done_q = collections.deque()            # completed queries, appended by workers
+        self._live = {}                         # graph -> worker future
         nxt = 0
         done = 0
         t0 = time.perf_counter()
         while done < len(queries):
             now = time.perf_counter() - t0
             if now > timeout_s:
-                raise TimeoutError("serving run exceeded %.0f s" % timeout_s)
+                raise TimeoutError("serving run exceeded %.0f s: %d of %d done, %d waiting, %d in slots" % (
+                    timeout_s, done, len(queries), sum(map(len, pending.values())),
+                    sum(map(len, slot_q.values()))))
             while nxt < len(queries) and queries[nxt].t_arrival <= now:
                 pending[queries[nxt].graph].append(queries[nxt])
                 nxt += 1
+            while done_q:
+                done_q.popleft()
+                done += 1
+            for name, fut in list(self._live.items()):
+                if fut.done():
+                    del self._live[name]
+                    fut.result()  # re-raises a worker's error
             # admission: free slots of each graph's session (created under the budget)
             for name, dq in pending.items():
-                if not dq or name in inflight:
+                if not dq:
                     continue
                 sess = self._ensure_session(name)
                 if sess is None:
                     continue
                 while dq:
-                    k = sess.admit(dq[0].source)
-                    if k is None:
-                        break
-                    q = dq.popleft()
-                    q.t_admit = time.perf_counter() - t0
-                    slot_q[name][k] = q
-            # steps: every session with busy slots and no step in flight
+                    with self._slot_mu:  # the worker may finish the slot as soon as it is admitted
+                        k = sess.admit(dq[0].source)
+                        if k is None:
+                            break
+                        q = dq.popleft()
+                        q.t_admit = time.perf_counter() - t0
+                        slot_q[name][k] = q
+            # a worker for every session with admitted queries and none running
             for name, sess in list(self.sessions.items()):
-                if name not in inflight and slot_q[name]:
-                    inflight[name] = self.workers[name].submit(self._step, name, sess, slot_q[name])
-            # completions
-            progressed = False
-            for name, fut in list(inflight.items()):
-                if fut.done():
-                    del inflight[name]
-                    progressed = True
-                    t_done = time.perf_counter() - t0
-                    for k, lv in fut.result():
-                        q = slot_q[name].pop(k)
-                        q.t_done = t_done
-                        q.levels = lv
-                        done += 1
-            if not progressed:
-                until_next = queries[nxt].t_arrival - now if nxt < len(queries) else 0.01
-                if inflight:
-                    futures_wait(list(inflight.values()), timeout=max(0.0, min(until_next, 0.01)),
+                if name not in self._live and slot_q[name]:
+                    self._live[name] = self.workers[name].submit(self._work, name, sess, slot_q[name], done_q, t0)
+            if not done_q:
+                until_next = queries[nxt].t_arrival - now if nxt < len(queries) else 0.001
+                if self._live:
+                    futures_wait(list(self._live.values()), timeout=max(0.0, min(until_next, 0.0002)),
                                  return_when=FIRST_COMPLETED)
                 elif nxt < len(queries):
                     time.sleep(max(0.0, min(until_next, 0.001)))
+        for fut in self._live.values():
+            fut.result()
         for name in list(self.sessions):
             self._close(name)
         return queries

@@ -30,7 +30,7 @@ def expected(g, srcs):
 
 
 @pytest.mark.parametrize("name", ["rmat12", "er_ragged", "grid", "chunglu"])
-@pytest.mark.parametrize("nsrc", [1, 5, 64, 65, 200])
+@pytest.mark.parametrize("nsrc", [1, 5, 64, 65, 200, 300])
 def test_msbfs_matches_oracle(name, nsrc):
     g, G = graph(name)
     srcs = gg.pick_sources(g, nsrc, 1000 + nsrc)
@@ -49,6 +49,23 @@ def test_msbfs_directions(p2p):
     lv, _ = gsw.msbfs(G, srcs, push_to_pull=p2p[0], pull_to_push=p2p[1])
     exp = expected(g, srcs)
     assert np.array_equal(lv, exp)
+
+
+def test_msbfs_sources_in_different_directions():
+    # a deep grid and an R-MAT graph side by side: in the same level the
+    # R-MAT sources have large frontiers (bottom-up) while the grid sources
+    # still push, and the R-MAT hubs take the whole-wave row walk
+    a = gg.rmat(11, 16, seed=55)
+    b = gg.grid(50, 50, 0.0, seed=56)
+    src = np.concatenate([np.repeat(np.arange(a.n), a.degrees()), a.n + np.repeat(np.arange(b.n), b.degrees())])
+    dst = np.concatenate([a.cols, a.n + b.cols])
+    g = gg.from_edges(a.n + b.n, src, dst)
+    G = gsw.Graph.from_csr(g.offs, g.cols)
+    assert np.diff(g.offs).max() > 64
+    srcs = np.concatenate([gg.pick_sources(a, 70, 57), a.n + gg.pick_sources(b, 70, 58)])
+    for p2p in ((0.05, 0.01), (0.002, 0.0005)):
+        lv, _ = gsw.msbfs(G, srcs, push_to_pull=p2p[0], pull_to_push=p2p[1])
+        assert np.array_equal(lv, expected(g, srcs))
 
 
 def test_msbfs_1024_sources_device():

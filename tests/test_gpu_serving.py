@@ -94,6 +94,30 @@ def test_session_isolated_source_and_thresholds():
             assert np.array_equal(res[k], oracle.levels(g.offs, g.cols, s)), s
 
 
+def test_session_join_while_others_pull():
+    # queries admitted while the first ones are in their bottom-up levels run
+    # top-down themselves in the same passes, and still match the oracle
+    g, G = resident("rmat12")
+    sess = gsw.Session(G, slots=40)
+    first = gg.pick_sources(g, 16, 12).tolist()
+    later = gg.pick_sources(g, 16, 13).tolist()
+    slot_src = {sess.admit(s): s for s in first}
+    res = {}
+    fin, _ = sess.step(2)
+    for k in fin:
+        res[slot_src[k]] = sess.fetch(k)
+    for s in later:
+        slot_src[sess.admit(s)] = s
+    while len(res) < len(set(first + later)):
+        fin, run = sess.step(100)
+        assert run > 0 or fin
+        for k in fin:
+            res[slot_src.pop(k)] = sess.fetch(k)
+    for s, lv in res.items():
+        assert np.array_equal(lv, oracle.levels(g.offs, g.cols, s)), s
+    sess.close()
+
+
 def test_server_mix_equals_alone():
     names = ["rmat12", "grid", "er"]
     residents = {}

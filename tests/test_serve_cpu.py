@@ -1,6 +1,8 @@
 """Serving scheduler on the CPU: a stub session (answers from the oracle, one
 simulated level per step) exercises admission, slot reuse, the memory budget
 and eviction without a GPU."""
+import threading
+
 import numpy as np
 
 import oracle
@@ -15,55 +17,64 @@ class StubGraph:
 
 
 class StubSession:
+    """Same contract as gsw.Session: admit from any thread, step runs until a
+    slot finishes or nothing is admitted or running."""
+
     created = 0
 
     def __init__(self, graph, slots):
         StubSession.created += 1
         self.g = graph
         self.slots = slots
-        self.state = {}  # slot -> [source, start, depth]
+        self.state = {}  # slot -> [source, start, depth, levels]
         self.pending = {}
         self.it = 0
         self.finished = {}
+        self.mu = threading.Lock()
 
     def admit(self, source):
-        used = set(self.state) | set(self.pending) | set(self.finished)
-        free = [k for k in range(self.slots) if k not in used]
-        if not free:
-            return None
-        self.pending[free[0]] = source
-        return free[0]
+        with self.mu:
+            used = set(self.state) | set(self.pending) | set(self.finished)
+            free = [k for k in range(self.slots) if k not in used]
+            if not free:
+                return None
+            self.pending[free[0]] = source
+            return free[0]
 
     def step(self, max_levels):
-        for k, s in self.pending.items():
-            lv = oracle.levels(self.g.csr.offs, self.g.csr.cols, s)
-            self.state[k] = [s, self.it, int(lv.max()) + 1, lv]
-        self.pending = {}
         fin = []
         for run in range(max_levels):
+            with self.mu:  # level boundary: take new admissions
+                for k, s in self.pending.items():
+                    lv = oracle.levels(self.g.csr.offs, self.g.csr.cols, s)
+                    self.state[k] = [s, self.it, int(lv.max()) + 1, lv]
+                self.pending = {}
             if not self.state:
-                break
+                return fin, run
             self.it += 1
-            for k in list(self.state):
-                s, start, depth, lv = self.state[k]
-                if self.it - start >= depth:
-                    fin.append(k)
-                    self.finished[k] = lv
-                    del self.state[k]
+            with self.mu:
+                for k in list(self.state):
+                    s, start, depth, lv = self.state[k]
+                    if self.it - start >= depth:
+                        fin.append(k)
+                        self.finished[k] = lv
+                        del self.state[k]
             if fin:
                 return fin, run + 1
         return fin, max_levels
 
     def fetch(self, slot, out=None):
-        lv = self.finished.pop(slot)
+        with self.mu:
+            lv = self.finished.pop(slot)
         if out is not None:
             out[:] = lv
             return out
         return lv.copy()
 
     def info(self):
-        return dict(slots=self.slots, busy=len(self.state) + len(self.pending) + len(self.finished),
-                    iteration=self.it, dev_bytes=0)
+        with self.mu:
+            return dict(slots=self.slots, busy=len(self.state) + len(self.pending) + len(self.finished),
+                        iteration=self.it, dev_bytes=0)
 
     def close(self):
         pass
