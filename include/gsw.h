@@ -243,7 +243,7 @@ typedef struct {
   void *stream;        /* hipStream_t; NULL = library stream */
 } gsw_msbfs_opts;
 
-/* Fills opts: push_to_pull 0.05, pull_to_push 0.01, host pointers. */
+/* Fills opts: push_to_pull 0.002, pull_to_push 0.0005, host pointers. */
 void gsw_msbfs_opts_default(gsw_msbfs_opts *opts);
 
 /*
@@ -306,7 +306,7 @@ gsw_status gsw_session_fetch(gsw_session *ss, int32_t slot, int32_t *levels, int
 gsw_status gsw_session_info(const gsw_session *ss, int32_t *slots, int32_t *busy,
                             int64_t *iteration, size_t *dev_bytes);
 
-/* Direction thresholds as in gsw_msbfs_opts (defaults 0.05 / 0.01). */
+/* Direction thresholds as in gsw_msbfs_opts (defaults 0.002 / 0.0005). */
 gsw_status gsw_session_set_thresholds(gsw_session *ss, float push_to_pull, float pull_to_push);
 
 /* ------------------------------------------------------------------ misc */

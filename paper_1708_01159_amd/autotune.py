@@ -17,8 +17,8 @@ import numpy as np
 
 from . import gsw
 
-PUSH_TO_PULL = (0.002, 0.01, 0.05, 0.2)
-PULL_TO_PUSH = (0.0005, 0.005, 0.02)
+PUSH_TO_PULL = (0.0005, 0.002, 0.01, 0.05)
+PULL_TO_PUSH = (0.0001, 0.0005, 0.005)
 
 
 def signature(graph: gsw.Graph, batch: int) -> str:

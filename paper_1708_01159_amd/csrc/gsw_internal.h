@@ -83,6 +83,10 @@ struct gsw_graph {
   size_t csr_bytes = 0, origin_bytes = 0;
   gsw::Workspace ws;
   gsw::MsWorkspace* ms = nullptr; // batched BFS workspace, sized for the largest batch seen
+  // batched BFS: rows longer than the chunked-row limit as (vertex << 32 |
+  // chunk index) entries, built on first use; -1 = not built yet
+  unsigned long long* heavy = nullptr;
+  int64_t n_heavy = -1;
   hipStream_t stream = nullptr;   // library stream for this graph
   std::mutex mu;
 };

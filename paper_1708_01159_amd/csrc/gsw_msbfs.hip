@@ -19,11 +19,18 @@
 // Layout: masks are vertex-major ([n][W] words, one 128-byte line per vertex
 // at B = 1024), worked on by groups of G = W (rounded up to a power of two)
 // lanes, lane j of a group owning word j, so a vertex's masks are read and
-// written coalesced.  A row longer than kMsLong is walked by the whole wave,
-// each group taking every (64/G)-th edge, so one high-degree vertex does not
-// hold its wave for its whole row.  Levels are kept vertex-major ([n][B]
-// bytes, each lane updating its own 64-byte run word by word) and transposed
-// to [B][n] at the end.
+// written coalesced.  Beside the masks, three 1-bit-per-vertex bitmaps (512
+// KiB at 4M vertices, held in L2): the frontier of depth d and of depth d+1
+// (any source) and the vertices whose accumulator the top-down pass touched.
+// A wave works on one 64-vertex bitmap word at a time and only on the
+// vertices whose bits say there is work, so a level with a small frontier
+// costs little more than the bitmaps; bottom-up probes test the frontier bit
+// (L2) before loading a neighbour's mask.  Rows are walked by the vertex's
+// group up to kMsLong arcs, by the whole wave up to kMsHeavy arcs, and
+// beyond that in kMsChunk-arc chunks spread over the grid (top-down; a
+// bottom-up walk stops early and stays with one wave).  Levels are kept
+// vertex-major ([n][B] bytes, each lane updating its own 64-byte run word by
+// word) and transposed to [B][n] at the end.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,6 +49,8 @@ constexpr int kMsMaxGrid = 2048;
 constexpr int kMsStats = 8;        // stat counters, spread like the queue bins
 constexpr int kMsStatStride = 32;  // u64 words between counters
 constexpr int kMsLong = 32;        // rows longer than this are walked by the whole wave
+constexpr int kMsHeavy = 1024;     // top-down: rows longer than this go through the chunk list
+constexpr int kMsChunk = 256;      // arcs per chunk of a heavy row
 constexpr int kMaxWords = GSW_MSBFS_MAX_SOURCES / 64;  // mask words per vertex at most
 constexpr int kMaxSlots = GSW_MSBFS_MAX_SOURCES;
 
@@ -57,21 +66,28 @@ struct MsArgs {
   const int64_t* __restrict__ offs;
   const int32_t* __restrict__ cols;
   u64* vis;
-  const u64* __restrict__ fr;  // depth-d masks
-  u64* frn;                    // depth-(d+1) masks (written for every vertex)
-  u64* nx;                     // top-down accumulator, zero between levels
-  int8_t* lev;                 // [n][B] levels, vertex-major
-  u64* stats;                  // [kMsStats] rows: vertices with new bits, their degree sum
-  u64* slot_ef;                // [kMsStats][kMaxSlots]: per source, degree sum of its new frontier
-  u64* active;                 // [kMsStats][kMaxWords]: OR of the new frontier masks
-  // serving sessions: int32 levels per slot ([slots][n]), level = d + 1 -
-  // start[slot] where d is the session's iteration (null for the batch)
+  const u64* __restrict__ fr;   // depth-d masks
+  u64* frn;                     // depth-(d+1) masks; holds depth d-1's until rewritten
+  u64* nx;                      // top-down accumulator, zero between levels
+  const u64* __restrict__ fbm;  // bit v: v is in some source's depth-d frontier
+  u64* fbm_n;                   // the same for depth d+1 (holds depth d-1's until rewritten)
+  u64* tbm;                     // bit v: the top-down pass touched nx[v] (zero between levels)
+  const u64* __restrict__ heavy;  // chunk list of rows longer than kMsHeavy
+  int64_t n_heavy;
+  int8_t* lev;                  // [n][B] levels, vertex-major
+  u64* stats;                   // [kMsStats] rows: vertices with new bits, their degree sum
+  u64* slot_ef;                 // [kMsStats][kMaxSlots]: per source, degree sum of its new frontier
+  u64* active;                  // [kMsStats][kMaxWords]: OR of the new frontier masks
+  // serving sessions: int32 levels + 1 per slot ([slots][n], 0 = not
+  // reached), level = d + 1 - start[slot] where d is the session's iteration
+  // (null for the batch)
   int32_t* dist;
   const int32_t* start;
   int64_t n;
   int32_t W, B;  // words per vertex, level bytes per vertex
   int32_t d;
-  int32_t any_push;       // the top-down pass ran this level (nx holds its bits)
+  int32_t any_push;       // the top-down pass ran this level (nx and tbm hold its bits)
+  int32_t any_pull;       // some source expands bottom-up this level
   u64 pmask[kMaxWords];   // sources expanded top-down this level
   u64 qmask[kMaxWords];   // sources expanded bottom-up this level
 };
@@ -95,6 +111,23 @@ __device__ __forceinline__ u64 mask_word(const u64 (&m)[kMaxWords], int j) {
   return r;
 }
 
+// Position of the k-th (from 0) set bit of m; k < popcount(m).
+__device__ __forceinline__ int nth_set_bit(u64 m, int k) {
+  int pos = 0;
+  int c = __popc((unsigned)m);
+  if (k >= c) { k -= c; m >>= 32; pos += 32; }
+  c = __popc((unsigned)(m & 0xffffull));
+  if (k >= c) { k -= c; m >>= 16; pos += 16; }
+  c = __popc((unsigned)(m & 0xffull));
+  if (k >= c) { k -= c; m >>= 8; pos += 8; }
+  c = __popc((unsigned)(m & 0xfull));
+  if (k >= c) { k -= c; m >>= 4; pos += 4; }
+  c = __popc((unsigned)(m & 0x3ull));
+  if (k >= c) { k -= c; m >>= 2; pos += 2; }
+  if (k >= (int)(m & 1ull)) pos += 1;
+  return pos;
+}
+
 // 8 bits -> 8 bytes holding 0x01 where the bit is set.
 __device__ __forceinline__ u64 bits_to_bytes(u64 c) {
   c = (c | (c << 28)) & 0x0000000F0000000Full;
@@ -111,7 +144,7 @@ __device__ __forceinline__ void write_levels(const MsArgs& a, int64_t v, int j, 
       const int b = __ffsll((long long)m) - 1;
       m &= m - 1ull;
       const int slot = j * 64 + b;
-      a.dist[(int64_t)slot * a.n + v] = a.d + 1 - a.start[slot];
+      a.dist[(int64_t)slot * a.n + v] = a.d + 2 - a.start[slot];
     }
     return;
   }
@@ -165,33 +198,33 @@ __device__ __forceinline__ void add_active(const MsArgs& a, int j, u64 act) {
 }
 
 // Wave geometry: groups of G lanes (a power of two <= 16), one vertex per
-// group; a wave covers 64/G consecutive vertices per step.
+// group; the waves of the grid take 64-vertex bitmap words in turn.
 struct Wave {
-  int G, j, gi, gpw;
+  int G, j, gi, gpw, lane;
   u64 gmask;  // this lane's group within the wave
-  int64_t first, stride;
+  int64_t wave, nwaves;
 };
 
 __device__ __forceinline__ Wave wave_of(int G) {
   Wave w;
-  const int lane = lane_id();
+  w.lane = lane_id();
   w.G = G;
-  w.j = lane & (G - 1);
-  w.gi = lane / G;
+  w.j = w.lane & (G - 1);
+  w.gi = w.lane / G;
   w.gpw = 64 / G;
   w.gmask = G == 64 ? ~0ull : (((1ull << G) - 1ull) << (w.gi * G));
-  const int64_t wave = ((int64_t)blockIdx.x * kMsBlock + threadIdx.x) >> 6;
-  const int64_t nwaves = ((int64_t)gridDim.x * kMsBlock) >> 6;
-  w.first = wave * w.gpw;
-  w.stride = nwaves * w.gpw;
+  w.wave = ((int64_t)blockIdx.x * kMsBlock + threadIdx.x) >> 6;
+  w.nwaves = ((int64_t)gridDim.x * kMsBlock) >> 6;
   return w;
 }
 
 // ------------------------------------------------------------------ init
-// Masks of n vertices (bits of sources >= nsrc start visited) and levels
-// [n][brow] set to -1 (brow = 64 W, so rows are whole 8-byte words).
-__global__ void __launch_bounds__(kMsBlock) k_ms_init(u64* vis, u64* fr, u64* nx, int8_t* lev,
-                                                      int64_t n, int W, int nsrc, int brow) {
+// Masks of n vertices (bits of sources >= nsrc start visited), the bitmaps
+// and levels [n][brow] set to -1 (brow = 64 W, so rows are whole 8-byte
+// words).  Both frontier mask buffers start at zero: later levels rewrite a
+// vertex's next-frontier masks only where they are or were nonzero.
+__global__ void __launch_bounds__(kMsBlock) k_ms_init(u64* vis, u64* fr, u64* frn, u64* nx, u64* bms,
+                                                      int8_t* lev, int64_t n, int W, int nsrc, int brow) {
   const int64_t stride = (int64_t)gridDim.x * kMsBlock;
   const int64_t gid = (int64_t)blockIdx.x * kMsBlock + threadIdx.x;
   const int64_t words = n * W;
@@ -199,15 +232,18 @@ __global__ void __launch_bounds__(kMsBlock) k_ms_init(u64* vis, u64* fr, u64* nx
     const int j = (int)(i % W);
     vis[i] = ~valid_bits(j, W, nsrc);
     fr[i] = 0ull;
+    frn[i] = 0ull;
     nx[i] = 0ull;
   }
+  const int64_t nb = 3 * ((n + 63) / 64);
+  for (int64_t i = gid; i < nb; i += stride) bms[i] = 0ull;
   const int64_t lw = n * (int64_t)brow / 8;
   u64* l8 = reinterpret_cast<u64*>(lev);
   for (int64_t i = gid; i < lw; i += stride) l8[i] = ~0ull;
 }
 
 // Sources are set after init (a separate launch, so no ordering issue).
-__global__ void k_ms_sources(u64* vis, u64* fr, int8_t* lev, int W, int B,
+__global__ void k_ms_sources(u64* vis, u64* fr, u64* fbm, int8_t* lev, int W, int B,
                              const int32_t* __restrict__ src, int nsrc) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nsrc) return;
@@ -215,60 +251,129 @@ __global__ void k_ms_sources(u64* vis, u64* fr, int8_t* lev, int W, int B,
   const u64 bit = 1ull << (i & 63);
   atomicOr(vis + s * W + (i >> 6), bit);
   atomicOr(fr + s * W + (i >> 6), bit);
+  atomicOr(fbm + (s >> 6), 1ull << (s & 63));
   lev[s * (int64_t)B + i] = 0;
 }
 
+// Chunk list of the rows longer than kMsHeavy: entry (v << 32 | c) stands
+// for arcs [offs[v] + c kMsChunk, min(offs[v+1], offs[v] + (c+1) kMsChunk)).
+// With list == null only the total is added to *cursor.
+__global__ void __launch_bounds__(kMsBlock) k_heavy_build(const int64_t* __restrict__ offs, int64_t n,
+                                                          u64* list, u64* cursor) {
+  const Wave w = wave_of(1);
+  for (int64_t base = w.wave * 64; base < n; base += w.nwaves * 64) {
+    const int64_t v = base + w.lane;
+    long long nch = 0;
+    if (v < n) {
+      const int64_t d = offs[v + 1] - offs[v];
+      if (d > kMsHeavy) nch = (d + kMsChunk - 1) / kMsChunk;
+    }
+    long long inc = nch;  // inclusive scan over the wave
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const long long y = __shfl_up(inc, off);
+      if (w.lane >= off) inc += y;
+    }
+    const long long tot = __shfl(inc, 63);
+    if (tot == 0) continue;
+    u64 b0 = 0ull;
+    if (w.lane == 0) b0 = atomicAdd(cursor, (u64)tot);
+    b0 = __shfl(b0, 0);
+    if (list)
+      for (long long c = 0; c < nch; ++c) list[b0 + (u64)(inc - nch + c)] = ((u64)v << 32) | (u64)c;
+  }
+}
+
 // --------------------------------------------------------------- top-down
-// For each vertex u in the frontier of a top-down source: lane j ORs
-// fr[u][j] & pmask[j] & ~vis[v][j] into nx[v][j] for every neighbour v.
+// ORs f & ~vis[v][j] into nx[v][j] for the arcs beg, beg + step, ... < end;
+// the first writer of an accumulator word marks v in the touched bitmap.
+__device__ __forceinline__ void push_arcs(const MsArgs& a, u64 f, int j, int64_t beg, int64_t end,
+                                          int step) {
+  for (int64_t e = beg; e < end; e += step) {
+    const int64_t v = a.cols[e];
+    const u64 m = f & ~a.vis[v * a.W + j];
+    if (m) {
+      const u64 old = atomicOr(a.nx + v * a.W + j, m);
+      if (!old) atomicOr(a.tbm + (v >> 6), 1ull << (v & 63));
+    }
+  }
+}
+
+// Every frontier vertex u of a top-down source: lane j pushes
+// fr[u][j] & pmask[j] along u's arcs.
 __global__ void __launch_bounds__(kMsBlock) k_ms_push(MsArgs a, int G) {
   const Wave w = wave_of(G);
   const int j = w.j;
   const u64 pm = j < a.W ? mask_word(a.pmask, j) : 0ull;
-  for (int64_t base = w.first; base < a.n; base += w.stride) {
-    const int64_t u = base + w.gi;
-    const u64 f = (u < a.n && pm) ? (a.fr[u * a.W + j] & pm) : 0ull;
-    const bool act = (__ballot(f != 0ull) & w.gmask) != 0ull;
-    int64_t beg = 0, end = 0;
-    if (act) {
-      beg = a.offs[u];
-      end = a.offs[u + 1];
-    }
-    const bool lng = end - beg > kMsLong;
-    if (f && !lng) {
-      for (int64_t e = beg; e < end; ++e) {
-        const int64_t v = a.cols[e];
-        const u64 m = f & ~a.vis[v * a.W + j];
-        if (m) atomicOr(a.nx + v * a.W + j, m);
+  const int64_t nwords = (a.n + 63) / 64;
+  for (int64_t wd = w.wave; wd < nwords; wd += w.nwaves) {
+    const u64 word = a.fbm[wd];
+    if (!word) continue;
+    const int cnt = __popcll(word);
+    for (int r0 = 0; r0 < cnt; r0 += w.gpw) {
+      const int k = r0 + w.gi;
+      const bool has = k < cnt;
+      const int64_t u = wd * 64 + (has ? nth_set_bit(word, k) : 0);
+      const u64 f = (has && pm) ? (a.fr[u * a.W + j] & pm) : 0ull;
+      const bool act = (__ballot(f != 0ull) & w.gmask) != 0ull;
+      int64_t beg = 0, end = 0;
+      if (act) {
+        beg = a.offs[u];
+        end = a.offs[u + 1];
+      }
+      const int64_t deg = end - beg;
+      if (f && deg <= kMsLong) push_arcs(a, f, j, beg, end, 1);
+      // medium rows: the whole wave, group gi taking arcs gi, gi + 64/G, ...
+      u64 lm = __ballot(deg > kMsLong && deg <= kMsHeavy && j == 0);
+      while (lm) {
+        const int src = __ffsll((long long)lm) - 1;
+        lm &= lm - 1ull;
+        const int64_t b = __shfl((long long)beg, src);
+        const int64_t en = __shfl((long long)end, src);
+        const u64 fw = __shfl(f, src + j);
+        if (fw) push_arcs(a, fw, j, b + w.gi, en, w.gpw);
       }
     }
-    // long rows: the whole wave, group gi taking edges gi, gi + 64/G, ...
-    u64 lm = __ballot(lng && j == 0);
+  }
+  // heavy rows: one chunk per wave step, for the chunks whose vertex is in
+  // the frontier
+  for (int64_t c0 = w.wave * 64; c0 < a.n_heavy; c0 += w.nwaves * 64) {
+    const int64_t c = c0 + w.lane;
+    u64 ent = 0ull;
+    bool live = false;
+    if (c < a.n_heavy) {
+      ent = a.heavy[c];
+      const int64_t u = (int64_t)(ent >> 32);
+      live = ((a.fbm[u >> 6] >> (u & 63)) & 1ull) != 0ull;
+    }
+    u64 lm = __ballot(live);
     while (lm) {
       const int src = __ffsll((long long)lm) - 1;
       lm &= lm - 1ull;
-      const int64_t b = __shfl((long long)beg, src);
-      const int64_t en = __shfl((long long)end, src);
-      const u64 fw = __shfl(f, src + j);
-      if (fw) {
-        for (int64_t e = b + w.gi; e < en; e += w.gpw) {
-          const int64_t v = a.cols[e];
-          const u64 m = fw & ~a.vis[v * a.W + j];
-          if (m) atomicOr(a.nx + v * a.W + j, m);
-        }
-      }
+      const u64 e_ = __shfl(ent, src);
+      const int64_t u = (int64_t)(e_ >> 32);
+      const int64_t ci = (int64_t)(e_ & 0xffffffffull);
+      const u64 fw = pm ? (a.fr[u * a.W + j] & pm) : 0ull;
+      if (__ballot(fw != 0ull) == 0ull) continue;
+      const int64_t b = a.offs[u] + ci * kMsChunk;
+      const int64_t en = std::min<int64_t>(a.offs[u + 1], b + kMsChunk);
+      if (fw) push_arcs(a, fw, j, b + w.gi, en, w.gpw);
     }
   }
 }
 
 // ------------------------------------------------------ bottom-up + update
-// Every vertex v: the bottom-up sources it still needs (~vis & qmask) are
-// looked up in its neighbours' frontier masks, stopping once all are
-// covered; what the top-down pass left in nx (minus vis) joins them.  v's
-// group is the only writer of v's masks and levels.  Also accumulates the
-// level's statistics: vertices with new bits and their degrees, per source
-// the degree sum of its new frontier (sessions and the batch both steer
-// each source's direction by it), and the OR of the new frontier masks.
+// Each 64-vertex word: the vertices with possible work are all of them when
+// some source pulls, else those the top-down pass touched or whose stale
+// next-frontier masks must be cleared.  For such a vertex v: the bottom-up
+// sources it still needs (~vis & qmask) are looked up in the neighbours'
+// frontier masks (frontier bit first), stopping once all are covered; what
+// the top-down pass left in nx (minus vis) joins them.  v's group is the only
+// writer of v's masks and levels; the wave writes the word of the next
+// frontier bitmap whole.  Also accumulates the level's statistics: vertices
+// with new bits and their degrees, per source the degree sum of its new
+// frontier (each source's direction is steered by it), and the OR of the new
+// frontier masks.
 __global__ void __launch_bounds__(kMsBlock) k_ms_level(MsArgs a, int G) {
   __shared__ u64 s_ef[kMaxSlots];
   const Wave w = wave_of(G);
@@ -279,69 +384,92 @@ __global__ void __launch_bounds__(kMsBlock) k_ms_level(MsArgs a, int G) {
   for (int k = threadIdx.x; k < nslots; k += kMsBlock) s_ef[k] = 0ull;
   __syncthreads();
   u64 nv = 0, ne = 0, act = 0;
-  for (int64_t base = w.first; base < a.n; base += w.stride) {
-    const int64_t v = base + w.gi;
-    const bool in = v < a.n && lane_live;
-    const int64_t i = v * a.W + j;
-    const u64 s = in ? a.vis[i] : ~0ull;
-    const u64 x = (in && a.any_push) ? a.nx[i] : 0ull;
-    const u64 need = ~s & qm;
-    const bool want = (__ballot(need != 0ull) & w.gmask) != 0ull;
-    int64_t beg = 0, end = 0;
-    if (want) {
-      beg = a.offs[v];
-      end = a.offs[v + 1];
-    }
-    const bool lng = end - beg > kMsLong;
-    u64 acc = 0ull;
-    if (want && !lng) {
-      for (int64_t e = beg; e < end; ++e) {
-        const int64_t u = a.cols[e];
-        if (need) acc |= a.fr[u * a.W + j] & need;
-        if ((__ballot(acc == need) & w.gmask) == w.gmask) break;
+  const int64_t nwords = (a.n + 63) / 64;
+  for (int64_t wd = w.wave; wd < nwords; wd += w.nwaves) {
+    const int64_t base = wd * 64;
+    const u64 valid = base + 64 <= a.n ? ~0ull : ((1ull << (a.n - base)) - 1ull);
+    const u64 stale = a.fbm_n[wd];
+    const u64 touched = a.any_push ? a.tbm[wd] : 0ull;
+    const u64 work = (a.any_pull ? ~0ull : (touched | stale)) & valid;
+    u64 nbits = 0ull;
+    const int cnt = __popcll(work);
+    for (int r0 = 0; r0 < cnt; r0 += w.gpw) {
+      const int k = r0 + w.gi;
+      const bool has = k < cnt;
+      const int bit = has ? nth_set_bit(work, k) : 0;
+      const int64_t v = base + bit;
+      const bool in = has && lane_live;
+      const int64_t i = v * a.W + j;
+      const u64 x = (in && ((touched >> bit) & 1ull)) ? a.nx[i] : 0ull;
+      const u64 s = (in && (x || qm)) ? a.vis[i] : ~0ull;
+      const u64 need = ~s & qm;
+      const bool want = (__ballot(need != 0ull) & w.gmask) != 0ull;
+      int64_t beg = 0, end = 0;
+      if (want) {
+        beg = a.offs[v];
+        end = a.offs[v + 1];
       }
-    }
-    u64 lm = __ballot(lng && j == 0);
-    while (lm) {
-      const int src = __ffsll((long long)lm) - 1;
-      lm &= lm - 1ull;
-      const int64_t b = __shfl((long long)beg, src);
-      const int64_t en = __shfl((long long)end, src);
-      const u64 nw = __shfl(need, src + j);
-      u64 c = 0ull;
-      for (int64_t e0 = b; e0 < en; e0 += w.gpw) {  // same trip count on every lane
-        const int64_t e = e0 + w.gi;
-        if (e < en && nw) c |= a.fr[(int64_t)a.cols[e] * a.W + j] & nw;
-        for (int off = G; off < 64; off <<= 1) c |= __shfl_xor(c, off);
-        if (__all(c == nw)) break;
-      }
-      if (w.gi * G == src) acc = c;
-    }
-    const u64 nb = (x & ~s) | acc;  // acc is within ~s
-    const bool grp_new = (__ballot(nb != 0ull) & w.gmask) != 0ull;
-    if (grp_new && !want) {
-      beg = a.offs[v];
-      end = a.offs[v + 1];
-    }
-    const u64 deg = (u64)(end - beg);
-    if (in) {
-      if (x) a.nx[i] = 0ull;
-      if (nb) {
-        a.vis[i] = s | nb;
-        write_levels(a, v, j, nb);
-        u64 m = nb;
-        while (m) {
-          const int bt = __ffsll((long long)m) - 1;
-          m &= m - 1ull;
-          atomicAdd(&s_ef[j * 64 + bt], deg);
+      const bool lng = end - beg > kMsLong;
+      u64 acc = 0ull;
+      if (want && !lng) {
+        for (int64_t e = beg; e < end; ++e) {
+          const int64_t u = a.cols[e];
+          if (need && ((a.fbm[u >> 6] >> (u & 63)) & 1ull)) acc |= a.fr[u * a.W + j] & need;
+          if ((__ballot(acc == need) & w.gmask) == w.gmask) break;
         }
       }
-      a.frn[i] = nb;
-      act |= nb;
+      u64 lm = __ballot(lng && j == 0);
+      while (lm) {
+        const int src = __ffsll((long long)lm) - 1;
+        lm &= lm - 1ull;
+        const int64_t b = __shfl((long long)beg, src);
+        const int64_t en = __shfl((long long)end, src);
+        const u64 nw = __shfl(need, src + j);
+        u64 c = 0ull;
+        for (int64_t e0 = b; e0 < en; e0 += w.gpw) {  // same trip count on every lane
+          const int64_t e = e0 + w.gi;
+          if (e < en && nw) {
+            const int64_t u = a.cols[e];
+            if ((a.fbm[u >> 6] >> (u & 63)) & 1ull) c |= a.fr[u * a.W + j] & nw;
+          }
+          for (int off = G; off < 64; off <<= 1) c |= __shfl_xor(c, off);
+          if (__all(c == nw)) break;
+        }
+        if (w.gi * G == src) acc = c;
+      }
+      const u64 nb = (x & ~s) | acc;  // acc is within ~s
+      const bool grp_new = (__ballot(nb != 0ull) & w.gmask) != 0ull;
+      if (grp_new && !want) {
+        beg = a.offs[v];
+        end = a.offs[v + 1];
+      }
+      const u64 deg = (u64)(end - beg);
+      if (in) {
+        if (x) a.nx[i] = 0ull;
+        if (nb) {
+          a.vis[i] = s | nb;
+          write_levels(a, v, j, nb);
+          u64 m = nb;
+          while (m) {
+            const int bt = __ffsll((long long)m) - 1;
+            m &= m - 1ull;
+            atomicAdd(&s_ef[j * 64 + bt], deg);
+          }
+        }
+        if (nb || ((stale >> bit) & 1ull)) a.frn[i] = nb;
+        act |= nb;
+      }
+      if (grp_new && j == 0) {
+        nv += 1;
+        ne += deg;
+        nbits |= 1ull << bit;
+      }
     }
-    if (grp_new && j == 0) {
-      nv += 1;
-      ne += deg;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) nbits |= __shfl_xor(nbits, off);
+    if (w.lane == 0) {
+      a.fbm_n[wd] = nbits;
+      if (touched) a.tbm[wd] = 0ull;
     }
   }
   add_stats(a, nv, ne);
@@ -429,10 +557,10 @@ __global__ void __launch_bounds__(kMsBlock) k_ss_masks(u64* vis, int64_t n, int 
   }
 }
 
-// Admitted slots: the source's bit in vis and in the current frontier, level 0.
-__global__ void k_ss_seed(u64* vis, u64* fr, int32_t* dist, int64_t n, int W,
-                          const int32_t* __restrict__ src, const int32_t* __restrict__ slot,
-                          int count) {
+// Admitted slots: the source's bit in vis, in the current frontier and its
+// bitmap, level 0 (stored as 1).
+__global__ void k_ss_seed(u64* vis, u64* fr, u64* fbm, int32_t* dist, int64_t n, int W,
+                          const int32_t* __restrict__ src, const int32_t* __restrict__ slot, int count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
   const int64_t s = src[i];
@@ -440,12 +568,18 @@ __global__ void k_ss_seed(u64* vis, u64* fr, int32_t* dist, int64_t n, int W,
   const u64 bit = 1ull << (k & 63);
   atomicOr(vis + s * W + (k >> 6), bit);
   atomicOr(fr + s * W + (k >> 6), bit);
-  dist[(int64_t)k * n + s] = 0;
+  atomicOr(fbm + (s >> 6), 1ull << (s & 63));
+  dist[(int64_t)k * n + s] = 1;
 }
 
-__global__ void __launch_bounds__(kMsBlock) k_ss_fill(int32_t* p, int64_t count, int32_t val) {
+// A finished slot's levels: out[v] = row[v] - 1 (-1 = not reached), and the
+// row is cleared for the slot's next query.
+__global__ void __launch_bounds__(kMsBlock) k_ss_take(int32_t* row, int32_t* __restrict__ out, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * kMsBlock;
-  for (int64_t i = (int64_t)blockIdx.x * kMsBlock + threadIdx.x; i < count; i += stride) p[i] = val;
+  for (int64_t i = (int64_t)blockIdx.x * kMsBlock + threadIdx.x; i < n; i += stride) {
+    out[i] = row[i] - 1;
+    row[i] = 0;
+  }
 }
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -456,9 +590,9 @@ inline int group_lanes(int W) {
   return G;  // W <= 16 -> G <= 16
 }
 
-// Enough waves for n vertices at 64/G per wave step, at most kMsMaxGrid blocks.
-inline unsigned ms_grid(int64_t n, int G) {
-  const int64_t blocks = cdiv(n * G, kMsBlock);
+// One wave per 64-vertex word for one pass, at most kMsMaxGrid blocks.
+inline unsigned ms_grid(int64_t n) {
+  const int64_t blocks = cdiv(cdiv(n, 64), kMsBlock / 64);
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks, kMsMaxGrid));
 }
 
@@ -550,16 +684,59 @@ struct Direction {
   }
 };
 
+// Builds the graph's chunk list of rows longer than kMsHeavy once (count,
+// allocate, fill); the caller holds the graph's lock.
+gsw_status ensure_heavy(gsw_graph* g) {
+  if (g->n_heavy >= 0) return GSW_OK;
+  u64* cur = nullptr;
+  GSW_HIP(hipMalloc((void**)&cur, sizeof(u64)));
+  gsw_status st = GSW_OK;
+  u64 total = 0;
+  const unsigned grid = ms_grid(g->n);
+  if (hipMemset(cur, 0, sizeof(u64)) != hipSuccess) st = fail(GSW_EHIP, "heavy-row count");
+  if (st == GSW_OK) {
+    hipLaunchKernelGGL(k_heavy_build, dim3(grid), dim3(kMsBlock), 0, 0, g->offs, g->n, (u64*)nullptr, cur);
+    if (hipGetLastError() != hipSuccess || hipMemcpy(&total, cur, sizeof(u64), hipMemcpyDeviceToHost) != hipSuccess)
+      st = fail(GSW_EHIP, "heavy-row count");
+  }
+  u64* list = nullptr;
+  if (st == GSW_OK && total > 0) {
+    if (hipMalloc((void**)&list, total * sizeof(u64)) != hipSuccess) {
+      (void)hipGetLastError();
+      st = fail(GSW_ENOMEM, "hipMalloc(%llu) for the heavy-row chunk list failed",
+                (unsigned long long)(total * sizeof(u64)));
+    } else if (hipMemset(cur, 0, sizeof(u64)) != hipSuccess) {
+      st = fail(GSW_EHIP, "heavy-row list");
+    } else {
+      hipLaunchKernelGGL(k_heavy_build, dim3(grid), dim3(kMsBlock), 0, 0, g->offs, g->n, list, cur);
+      if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+        st = fail(GSW_EHIP, "heavy-row list");
+    }
+  }
+  (void)hipFree(cur);
+  if (st != GSW_OK) {
+    if (list) (void)hipFree(list);
+    return st;
+  }
+  g->heavy = list;
+  g->n_heavy = (int64_t)total;
+  return GSW_OK;
+}
+
 // Launches one level: the top-down pass when some source pushes, then the
-// bottom-up + update pass and the finalize kernel.  a.pmask / a.qmask are
-// set by the caller.
+// bottom-up + update pass and the finalize kernel.  a.pmask / a.qmask and
+// the mask and bitmap pointers are set by the caller.
 gsw_status launch_ms_level(MsArgs& a, const LevelStats& st, int G, int nslots, hipStream_t s) {
   a.stats = st.stats;
   a.active = st.active;
   a.slot_ef = st.slot_ef;
   a.any_push = 0;
-  for (int j = 0; j < kMaxWords; ++j) a.any_push |= a.pmask[j] != 0ull;
-  const unsigned grid = ms_grid(a.n, G);
+  a.any_pull = 0;
+  for (int j = 0; j < kMaxWords; ++j) {
+    a.any_push |= a.pmask[j] != 0ull;
+    a.any_pull |= a.qmask[j] != 0ull;
+  }
+  const unsigned grid = ms_grid(a.n);
   if (a.any_push) hipLaunchKernelGGL(k_ms_push, dim3(grid), dim3(kMsBlock), 0, s, a, G);
   hipLaunchKernelGGL(k_ms_level, dim3(grid), dim3(kMsBlock), 0, s, a, G);
   hipLaunchKernelGGL(k_ms_finalize, dim3(1), dim3(256), 0, s, st.stats, st.active, st.slot_ef, a.W, nslots,
@@ -574,6 +751,7 @@ struct MsWorkspace {
   int64_t n = 0;
   int W = 0, B = 0;
   u64 *vis = nullptr, *fr = nullptr, *frn = nullptr, *nx = nullptr;
+  u64* bms = nullptr;  // 3 bitmaps of ceil(n/64) words: frontier d, frontier d+1, touched
   int8_t* lev = nullptr;
   int32_t* src = nullptr;
   LevelStats st;
@@ -583,7 +761,7 @@ struct MsWorkspace {
 namespace {
 void ms_free(MsWorkspace* m) {
   if (!m) return;
-  void* p[] = {m->vis, m->fr, m->frn, m->nx, m->lev, m->src};
+  void* p[] = {m->vis, m->fr, m->frn, m->nx, m->bms, m->lev, m->src};
   for (void* x : p)
     if (x) (void)hipFree(x);
   stats_free(&m->st);
@@ -591,6 +769,7 @@ void ms_free(MsWorkspace* m) {
 }
 
 gsw_status ms_ensure(gsw_graph* g, int W) {
+  GSW_TRY(ensure_heavy(g));
   MsWorkspace*& m = g->ms;
   if (m && m->W >= W) return GSW_OK;
   ms_free(m);
@@ -607,6 +786,7 @@ gsw_status ms_ensure(gsw_graph* g, int W) {
                {(void**)&m->fr, mb},
                {(void**)&m->frn, mb},
                {(void**)&m->nx, mb},
+               {(void**)&m->bms, 3 * (size_t)cdiv(g->n, 64) * sizeof(u64)},
                {(void**)&m->lev, (size_t)g->n * m->B},
                {(void**)&m->src, (size_t)m->B * sizeof(int32_t)}};
   gsw_status st = GSW_OK;
@@ -632,6 +812,9 @@ gsw_status ms_ensure(gsw_graph* g, int W) {
 void ms_release(gsw_graph* g) {
   ms_free(g->ms);
   g->ms = nullptr;
+  if (g->heavy) (void)hipFree(g->heavy);
+  g->heavy = nullptr;
+  g->n_heavy = -1;
 }
 
 }  // namespace gsw
@@ -643,8 +826,8 @@ extern "C" {
 void gsw_msbfs_opts_default(gsw_msbfs_opts* o) {
   if (!o) return;
   std::memset(o, 0, sizeof *o);
-  o->push_to_pull = 0.05f;
-  o->pull_to_push = 0.01f;
+  o->push_to_pull = 0.002f;
+  o->pull_to_push = 0.0005f;
 }
 
 gsw_status gsw_msbfs(const gsw_graph* cg, const int32_t* sources, int32_t n_sources, int8_t* levels,
@@ -670,14 +853,16 @@ gsw_status gsw_msbfs(const gsw_graph* cg, const int32_t* sources, int32_t n_sour
   const hipStream_t s = pick_stream(g, o->stream);
   const int B = W * 64;  // level bytes per vertex in the workspace
   const int G = group_lanes(W);
+  const int64_t nw = cdiv(g->n, 64);
+  u64* fbm[2] = {m->bms, m->bms + nw};
   GSW_HIP(hipMemcpyAsync(m->src, sources, (size_t)n_sources * sizeof(int32_t), hipMemcpyHostToDevice, s));
   {
     const int64_t work = std::max<int64_t>(g->n * W, g->n * (int64_t)B / 8);
     const unsigned grid = (unsigned)std::min<int64_t>(cdiv(work, kMsBlock), 65536);
-    hipLaunchKernelGGL(k_ms_init, dim3(grid), dim3(kMsBlock), 0, s, m->vis, m->fr, m->nx, m->lev,
-                       g->n, W, n_sources, B);
+    hipLaunchKernelGGL(k_ms_init, dim3(grid), dim3(kMsBlock), 0, s, m->vis, m->fr, m->frn, m->nx, m->bms,
+                       m->lev, g->n, W, n_sources, B);
     hipLaunchKernelGGL(k_ms_sources, dim3((unsigned)cdiv(n_sources, 256)), dim3(256), 0, s, m->vis,
-                       m->fr, m->lev, W, B, (const int32_t*)m->src, n_sources);
+                       m->fr, fbm[0], m->lev, W, B, (const int32_t*)m->src, n_sources);
     GSW_HIP(hipGetLastError());
   }
   MsArgs a;
@@ -686,6 +871,9 @@ gsw_status gsw_msbfs(const gsw_graph* cg, const int32_t* sources, int32_t n_sour
   a.cols = g->cols;
   a.vis = m->vis;
   a.nx = m->nx;
+  a.tbm = m->bms + 2 * nw;
+  a.heavy = g->heavy;
+  a.n_heavy = g->n_heavy;
   a.lev = m->lev;
   a.n = g->n;
   a.W = W;
@@ -702,6 +890,8 @@ gsw_status gsw_msbfs(const gsw_graph* cg, const int32_t* sources, int32_t n_sour
     dir.choose(running.data(), W, pull_ok, o->push_to_pull * nnz, o->pull_to_push * nnz, a.pmask, a.qmask);
     a.fr = cur;
     a.frn = nxt;
+    a.fbm = fbm[d & 1];
+    a.fbm_n = fbm[(d + 1) & 1];
     a.d = d;
     m->st.h[0] = ~0ull;
     GSW_TRY(launch_ms_level(a, m->st, G, n_sources, s));
@@ -744,8 +934,11 @@ struct gsw_session {
   gsw_graph* g = nullptr;
   int W = 0, slots = 0;
   u64 *vis = nullptr, *fr = nullptr, *frn = nullptr, *nx = nullptr;
-  u64* masks = nullptr;                                          // clr[kMaxWords] then set[kMaxWords]
+  u64* bms = nullptr;     // frontier bitmaps (depth d, d+1) and the touched bitmap
+  u64* fbm[2] = {};       // fbm[0] pairs with fr, fbm[1] with frn (swapped together)
+  u64* masks = nullptr;   // clr[kMaxWords] then set[kMaxWords]
   int32_t *dist = nullptr, *start_d = nullptr, *seed = nullptr;  // seed: src[slots] then slot[slots]
+  int32_t* take = nullptr;  // device staging for fetches into host memory
   LevelStats st;
   // pinned staging for the per-level uploads: masks, then seed src/slot, then start
   u64* h_masks = nullptr;
@@ -756,10 +949,10 @@ struct gsw_session {
   std::vector<u64> freed;     // slots freed since the last level (made inert then)
   Direction dir;
   int64_t it = 0;  // levels run by this session
-  float push_to_pull = 0.05f, pull_to_push = 0.01f;
+  float push_to_pull = 0.002f, pull_to_push = 0.0005f;
   hipStream_t stream = nullptr;
   size_t bytes = 0;
-  std::mutex mu;     // host state shared with admit / fetch / info
+  std::mutex mu;       // host state shared with admit / fetch / info
   std::mutex step_mu;  // one step or fetch at a time
 };
 
@@ -767,7 +960,7 @@ namespace {
 
 void ss_free(gsw_session* ss) {
   if (!ss) return;
-  void* p[] = {ss->vis, ss->fr, ss->frn, ss->nx, ss->masks, ss->dist, ss->start_d, ss->seed};
+  void* p[] = {ss->vis, ss->fr, ss->frn, ss->nx, ss->bms, ss->masks, ss->dist, ss->start_d, ss->seed, ss->take};
   for (void* x : p)
     if (x) (void)hipFree(x);
   stats_free(&ss->st);
@@ -791,13 +984,19 @@ gsw_status gsw_session_create(const gsw_graph* cg, int32_t max_slots, gsw_sessio
     return fail(GSW_EINVAL, "max_slots=%d out of [1, %d]", max_slots, GSW_MSBFS_MAX_SOURCES);
   gsw_graph* g = const_cast<gsw_graph*>(cg);
   GSW_HIP(hipSetDevice(g->device));
+  {
+    std::lock_guard<std::mutex> lock(g->mu);
+    GSW_TRY(ensure_heavy(g));
+  }
   gsw_session* ss = new (std::nothrow) gsw_session();
   if (!ss) return fail(GSW_ENOMEM, "host allocation failed");
   ss->g = g;
   ss->W = (max_slots + 63) / 64;
   ss->slots = max_slots;
   const int64_t n = g->n;
+  const int64_t nw = cdiv(n, 64);
   const size_t mb = (size_t)n * ss->W * sizeof(u64);
+  const size_t bb = 3 * (size_t)nw * sizeof(u64);
   struct Item {
     void** p;
     size_t bytes;
@@ -805,10 +1004,12 @@ gsw_status gsw_session_create(const gsw_graph* cg, int32_t max_slots, gsw_sessio
                {(void**)&ss->fr, mb},
                {(void**)&ss->frn, mb},
                {(void**)&ss->nx, mb},
+               {(void**)&ss->bms, bb},
                {(void**)&ss->masks, 2 * (size_t)kMaxWords * sizeof(u64)},
                {(void**)&ss->dist, (size_t)max_slots * n * sizeof(int32_t)},
                {(void**)&ss->start_d, (size_t)max_slots * sizeof(int32_t)},
-               {(void**)&ss->seed, 2 * (size_t)max_slots * sizeof(int32_t)}};
+               {(void**)&ss->seed, 2 * (size_t)max_slots * sizeof(int32_t)},
+               {(void**)&ss->take, (size_t)n * sizeof(int32_t)}};
   for (auto& it : items) {
     hipError_t e = hipMalloc(it.p, it.bytes);
     if (e != hipSuccess) {
@@ -818,6 +1019,8 @@ gsw_status gsw_session_create(const gsw_graph* cg, int32_t max_slots, gsw_sessio
     }
     ss->bytes += it.bytes;
   }
+  ss->fbm[0] = ss->bms;
+  ss->fbm[1] = ss->bms + nw;
   gsw_status st = stats_alloc(&ss->st);
   if (st == GSW_OK) {
     ss->bytes += ss->st.bytes;
@@ -829,10 +1032,11 @@ gsw_status gsw_session_create(const gsw_graph* cg, int32_t max_slots, gsw_sessio
   }
   if (st == GSW_OK) {
     const hipStream_t s = ss->stream;
-    // every slot starts inert: visited everywhere, in no frontier, levels -1
+    // every slot starts inert: visited everywhere, in no frontier, not reached
     if (hipMemsetAsync(ss->vis, 0xff, mb, s) != hipSuccess || hipMemsetAsync(ss->fr, 0, mb, s) != hipSuccess ||
         hipMemsetAsync(ss->frn, 0, mb, s) != hipSuccess || hipMemsetAsync(ss->nx, 0, mb, s) != hipSuccess ||
-        hipMemsetAsync(ss->dist, 0xff, (size_t)max_slots * n * sizeof(int32_t), s) != hipSuccess ||
+        hipMemsetAsync(ss->bms, 0, bb, s) != hipSuccess ||
+        hipMemsetAsync(ss->dist, 0, (size_t)max_slots * n * sizeof(int32_t), s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       st = fail(GSW_EHIP, "session initialisation failed");
   }
@@ -888,6 +1092,9 @@ gsw_status gsw_session_step(gsw_session* ss, int32_t max_levels, int32_t* finish
   a.cols = g->cols;
   a.vis = ss->vis;
   a.nx = ss->nx;
+  a.tbm = ss->bms + 2 * cdiv(n, 64);
+  a.heavy = g->heavy;
+  a.n_heavy = g->n_heavy;
   a.n = n;
   a.W = W;
   a.B = W * 64;
@@ -935,8 +1142,8 @@ gsw_status gsw_session_step(gsw_session* ss, int32_t max_levels, int32_t* finish
     if (c > 0) {
       GSW_HIP(hipMemcpyAsync(ss->seed, ss->h_seed, 2 * (size_t)ss->slots * sizeof(int32_t), hipMemcpyHostToDevice, s));
       GSW_HIP(hipMemcpyAsync(ss->start_d, ss->h_start, ss->slots * sizeof(int32_t), hipMemcpyHostToDevice, s));
-      hipLaunchKernelGGL(k_ss_seed, dim3((unsigned)cdiv(c, 256)), dim3(256), 0, s, ss->vis, ss->fr, ss->dist, n,
-                         W, (const int32_t*)ss->seed, (const int32_t*)(ss->seed + ss->slots), c);
+      hipLaunchKernelGGL(k_ss_seed, dim3((unsigned)cdiv(c, 256)), dim3(256), 0, s, ss->vis, ss->fr, ss->fbm[0],
+                         ss->dist, n, W, (const int32_t*)ss->seed, (const int32_t*)(ss->seed + ss->slots), c);
     }
     GSW_HIP(hipGetLastError());
     if (!any_running) {
@@ -946,12 +1153,15 @@ gsw_status gsw_session_step(gsw_session* ss, int32_t max_levels, int32_t* finish
     ss->dir.choose(running.data(), W, pull_ok, ss->push_to_pull * nnz, ss->pull_to_push * nnz, a.pmask, a.qmask);
     a.fr = ss->fr;
     a.frn = ss->frn;
+    a.fbm = ss->fbm[0];
+    a.fbm_n = ss->fbm[1];
     a.d = (int32_t)ss->it;
     ss->st.h[0] = ~0ull;
     GSW_TRY(launch_ms_level(a, ss->st, G, ss->slots, s));
     GSW_TRY(stats_wait(ss->st, s, "session"));
     ss->it += 1;
     std::swap(ss->fr, ss->frn);
+    std::swap(ss->fbm[0], ss->fbm[1]);
     const volatile u64* h = ss->st.h;
     std::lock_guard<std::mutex> lock(ss->mu);
     for (int k = 0; k < ss->slots; ++k) {
@@ -986,11 +1196,12 @@ gsw_status gsw_session_fetch(gsw_session* ss, int32_t slot, int32_t* levels, int
   const hipStream_t s = ss->stream;
   const int64_t n = ss->g->n;
   int32_t* row = ss->dist + (int64_t)slot * n;
-  GSW_HIP(hipMemcpyAsync(levels, row, (size_t)n * sizeof(int32_t),
-                         device_ptr ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
-  hipLaunchKernelGGL(k_ss_fill, dim3((unsigned)std::min<int64_t>(cdiv(n, kMsBlock), 65536)), dim3(kMsBlock), 0,
-                     s, row, n, -1);
+  int32_t* dst = device_ptr ? levels : ss->take;
+  hipLaunchKernelGGL(k_ss_take, dim3((unsigned)std::min<int64_t>(cdiv(n, kMsBlock), 65536)), dim3(kMsBlock), 0, s,
+                     row, dst, n);
   GSW_HIP(hipGetLastError());
+  if (!device_ptr)
+    GSW_HIP(hipMemcpyAsync(levels, ss->take, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   GSW_HIP(hipStreamSynchronize(s));
   std::lock_guard<std::mutex> lock(ss->mu);
   ss->state[(size_t)slot] = 0;

@@ -68,6 +68,41 @@ def test_msbfs_sources_in_different_directions():
         assert np.array_equal(lv, expected(g, srcs))
 
 
+def hub_graph():
+    # R-MAT plus three hubs of 2500-3000 arcs: rows past the whole-wave limit
+    # go through the chunk list when pushed
+    a = gg.rmat(12, 16, seed=59)
+    rng = np.random.default_rng(60)
+    hs, hd = [], []
+    for h, deg in zip(range(3), (2500, 2800, 3000)):
+        nb = rng.choice(a.n, size=deg, replace=False)
+        hs.append(np.full(deg, a.n + h))
+        hd.append(nb)
+    src = np.concatenate([np.repeat(np.arange(a.n), a.degrees())] + hs)
+    dst = np.concatenate([a.cols] + hd)
+    return gg.from_edges(a.n + 3, src, dst)
+
+
+@pytest.mark.parametrize("p2p", [(1e9, 1e9), (0.002, 0.0005), (0.0, 0.0)])
+def test_msbfs_heavy_rows(p2p):
+    g = hub_graph()
+    G = gsw.Graph.from_csr(g.offs, g.cols)
+    assert np.diff(g.offs).max() > 1024
+    hubs = np.arange(g.n - 3, g.n)
+    srcs = np.concatenate([hubs, gg.pick_sources(g, 100, 61), [int(g.cols[g.offs[g.n - 1]])]])
+    lv, _ = gsw.msbfs(G, srcs, push_to_pull=p2p[0], pull_to_push=p2p[1])
+    assert np.array_equal(lv, expected(g, srcs))
+    G.close()
+
+
+def test_msbfs_tiny_graph():
+    g = gg.from_edges(5, np.array([0, 1, 2]), np.array([1, 2, 3]))  # path 0-1-2-3, vertex 4 alone
+    G = gsw.Graph.from_csr(g.offs, g.cols)
+    lv, nl = gsw.msbfs(G, [0, 3, 4, 2])
+    assert np.array_equal(lv, expected(g, [0, 3, 4, 2]))
+    G.close()
+
+
 def test_msbfs_1024_sources_device():
     import torch
 

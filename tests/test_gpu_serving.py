@@ -118,6 +118,34 @@ def test_session_join_while_others_pull():
     sess.close()
 
 
+def test_session_heavy_rows_all_push_and_default():
+    from test_gpu_msbfs import hub_graph
+
+    g = hub_graph()
+    G = gsw.Graph.from_csr(g.offs, g.cols)
+    hubs = list(range(g.n - 3, g.n))
+    srcs = hubs + gg.pick_sources(g, 30, 62).tolist()
+    for p2p in ((1e9, 1e9), None):
+        sess = gsw.Session(G, slots=16)
+        if p2p:
+            sess.set_thresholds(*p2p)
+        todo = list(srcs)
+        slot_src, res = {}, {}
+        while len(res) < len(set(srcs)):
+            while todo:
+                k = sess.admit(todo[0])
+                if k is None:
+                    break
+                slot_src[k] = todo.pop(0)
+            fin, _ = sess.step(3)
+            for k in fin:
+                res[slot_src.pop(k)] = sess.fetch(k)
+        for s in srcs:
+            assert np.array_equal(res[s], oracle.levels(g.offs, g.cols, s)), s
+        sess.close()
+    G.close()
+
+
 def test_server_mix_equals_alone():
     names = ["rmat12", "grid", "er"]
     residents = {}
