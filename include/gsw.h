@@ -239,11 +239,11 @@ typedef struct {
                           exceed this fraction of all arcs ... */
   float pull_to_push;  /* ... and back to top-down below this fraction */
   int32_t device_ptrs; /* 1: levels is device memory; 0: host */
-  int32_t reserved0;
+  int32_t graph;       /* 1: replay a captured two-level HIP graph; 0: launch each kernel */
   void *stream;        /* hipStream_t; NULL = library stream */
 } gsw_msbfs_opts;
 
-/* Fills opts: push_to_pull 0.002, pull_to_push 0.0005, host pointers. */
+/* Fills opts: push_to_pull 0.002, pull_to_push 0.0005, graph 1, host pointers. */
 void gsw_msbfs_opts_default(gsw_msbfs_opts *opts);
 
 /*

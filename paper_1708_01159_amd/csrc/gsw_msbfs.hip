@@ -54,13 +54,28 @@ constexpr int kMsChunk = 256;      // arcs per chunk of a heavy row
 constexpr int kMaxWords = GSW_MSBFS_MAX_SOURCES / 64;  // mask words per vertex at most
 constexpr int kMaxSlots = GSW_MSBFS_MAX_SOURCES;
 
-// Mapped host words written by the finalize kernel: [0] vertices with new
-// bits (stored last, ~0 while the level runs), [1] their degree sum,
-// [kHostActive + j] OR of the new frontier's word j, [kHostEf + k] source k's
-// new frontier edges.
-constexpr int kHostActive = 2;
-constexpr int kHostEf = 32;
-constexpr int kHostWords = kHostEf + kMaxSlots;
+// Per-level records in mapped host memory, a ring of kRing: the record of
+// level d sits at (d % kRing) * kRecWords: [0] d + 1 (stored last), [1]
+// vertices with new bits, [2] their degree sum, [kRecActive + j] OR of the
+// new frontier's word j (which sources are still running).
+constexpr int kRing = 8;
+constexpr int kRecWords = 32;
+constexpr int kRecActive = 3;
+
+// Level control in device memory.  The finalize kernel of level d writes it
+// for level d+1 (and a session's seeding kernel adds new sources); the
+// level's kernels read it.  So the host need not see a level's result before
+// it queues the next level.
+struct MsCtl {
+  u64 pmask[kMaxWords];  // sources expanded top-down this level
+  u64 qmask[kMaxWords];  // sources expanded bottom-up this level
+  u64 a_arcs, b_arcs;    // direction thresholds in arcs
+  int32_t any_push, any_pull;
+  int32_t d;             // this level's index
+  int32_t pull_ok;       // bottom-up allowed (symmetric graph)
+  int32_t nslots, W;
+  uint8_t pull[kMaxSlots];  // per source: expanded bottom-up at its last level
+};
 
 struct MsArgs {
   const int64_t* __restrict__ offs;
@@ -83,13 +98,9 @@ struct MsArgs {
   // (null for the batch)
   int32_t* dist;
   const int32_t* start;
+  MsCtl* ctl;
   int64_t n;
   int32_t W, B;  // words per vertex, level bytes per vertex
-  int32_t d;
-  int32_t any_push;       // the top-down pass ran this level (nx and tbm hold its bits)
-  int32_t any_pull;       // some source expands bottom-up this level
-  u64 pmask[kMaxWords];   // sources expanded top-down this level
-  u64 qmask[kMaxWords];   // sources expanded bottom-up this level
 };
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
@@ -99,16 +110,6 @@ __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 __device__ __forceinline__ u64 valid_bits(int j, int W, int B) {
   if (j < W - 1 || (B & 63) == 0) return ~0ull;
   return (1ull << (B & 63)) - 1ull;
-}
-
-// Word j of a per-source mask held in the kernel arguments (uniform loads,
-// then a per-lane select).
-__device__ __forceinline__ u64 mask_word(const u64 (&m)[kMaxWords], int j) {
-  u64 r = 0ull;
-#pragma unroll
-  for (int w = 0; w < kMaxWords; ++w)
-    if (w == j) r = m[w];
-  return r;
 }
 
 // Position of the k-th (from 0) set bit of m; k < popcount(m).
@@ -138,18 +139,18 @@ __device__ __forceinline__ u64 bits_to_bytes(u64 c) {
 
 // Levels d+1 for the sources in `m` (word j) at vertex v.  Only v's group
 // writes v's levels, so the batch's 8-byte read-modify-writes need no atomics.
-__device__ __forceinline__ void write_levels(const MsArgs& a, int64_t v, int j, u64 m) {
+__device__ __forceinline__ void write_levels(const MsArgs& a, int d, int64_t v, int j, u64 m) {
   if (a.dist) {
     while (m) {
       const int b = __ffsll((long long)m) - 1;
       m &= m - 1ull;
       const int slot = j * 64 + b;
-      a.dist[(int64_t)slot * a.n + v] = a.d + 2 - a.start[slot];
+      a.dist[(int64_t)slot * a.n + v] = d + 2 - a.start[slot];
     }
     return;
   }
   u64* row = reinterpret_cast<u64*>(a.lev + v * (int64_t)a.B + (int64_t)j * 64);
-  const u64 val = (u64)(uint8_t)(a.d + 1 > 127 ? 127 : a.d + 1) * 0x0101010101010101ull;
+  const u64 val = (u64)(uint8_t)(d + 1 > 127 ? 127 : d + 1) * 0x0101010101010101ull;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const u64 c = (m >> (8 * k)) & 0xffull;
@@ -302,9 +303,10 @@ __device__ __forceinline__ void push_arcs(const MsArgs& a, u64 f, int j, int64_t
 // Every frontier vertex u of a top-down source: lane j pushes
 // fr[u][j] & pmask[j] along u's arcs.
 __global__ void __launch_bounds__(kMsBlock) k_ms_push(MsArgs a, int G) {
+  if (!a.ctl->any_push) return;
   const Wave w = wave_of(G);
   const int j = w.j;
-  const u64 pm = j < a.W ? mask_word(a.pmask, j) : 0ull;
+  const u64 pm = j < a.W ? a.ctl->pmask[j] : 0ull;
   const int64_t nwords = (a.n + 63) / 64;
   for (int64_t wd = w.wave; wd < nwords; wd += w.nwaves) {
     const u64 word = a.fbm[wd];
@@ -379,7 +381,10 @@ __global__ void __launch_bounds__(kMsBlock) k_ms_level(MsArgs a, int G) {
   const Wave w = wave_of(G);
   const int j = w.j;
   const bool lane_live = j < a.W;
-  const u64 qm = lane_live ? mask_word(a.qmask, j) : 0ull;
+  const MsCtl* ctl = a.ctl;
+  const int d = ctl->d;
+  const bool any_push = ctl->any_push != 0, any_pull = ctl->any_pull != 0;
+  const u64 qm = lane_live ? ctl->qmask[j] : 0ull;
   const int nslots = a.W * 64;
   for (int k = threadIdx.x; k < nslots; k += kMsBlock) s_ef[k] = 0ull;
   __syncthreads();
@@ -389,8 +394,8 @@ __global__ void __launch_bounds__(kMsBlock) k_ms_level(MsArgs a, int G) {
     const int64_t base = wd * 64;
     const u64 valid = base + 64 <= a.n ? ~0ull : ((1ull << (a.n - base)) - 1ull);
     const u64 stale = a.fbm_n[wd];
-    const u64 touched = a.any_push ? a.tbm[wd] : 0ull;
-    const u64 work = (a.any_pull ? ~0ull : (touched | stale)) & valid;
+    const u64 touched = any_push ? a.tbm[wd] : 0ull;
+    const u64 work = (any_pull ? ~0ull : (touched | stale)) & valid;
     u64 nbits = 0ull;
     const int cnt = __popcll(work);
     for (int r0 = 0; r0 < cnt; r0 += w.gpw) {
@@ -448,7 +453,7 @@ __global__ void __launch_bounds__(kMsBlock) k_ms_level(MsArgs a, int G) {
         if (x) a.nx[i] = 0ull;
         if (nb) {
           a.vis[i] = s | nb;
-          write_levels(a, v, j, nb);
+          write_levels(a, d, v, j, nb);
           u64 m = nb;
           while (m) {
             const int bt = __ffsll((long long)m) - 1;
@@ -480,29 +485,30 @@ __global__ void __launch_bounds__(kMsBlock) k_ms_level(MsArgs a, int G) {
     if (s_ef[k]) atomicAdd(row + k, s_ef[k]);
 }
 
-// Sums the spread counters into mapped host memory (layout at kHostEf), then
-// zeroes them.  Word 0 is stored last, after every other word is visible.
-__global__ void __launch_bounds__(256) k_ms_finalize(u64* stats, u64* active, u64* slot_ef, int W,
-                                                     int nslots, u64* host) {
+// End of level d: sums the spread counters, sets each running source's
+// direction for level d+1 (the single-source rule on its own frontier's
+// arcs) and the masks, advances ctl->d, and publishes the level's record to
+// the host ring (its first word last).  The counters are zeroed for the next
+// level.
+__global__ void __launch_bounds__(256) k_ms_finalize(MsCtl* ctl, u64* stats, u64* active, u64* slot_ef,
+                                                     u64* ring) {
+  __shared__ u64 s_act[kMaxWords], s_p[kMaxWords], s_q[kMaxWords];
+  __shared__ u64 s_v, s_e;
   const int t = threadIdx.x;
-  for (int k = t; k < nslots; k += 256) {
+  const int W = ctl->W, nslots = ctl->nslots, d = ctl->d;
+  if (t < kMaxWords) {
     u64 x = 0ull;
-    for (int r = 0; r < kMsStats; ++r) {
-      x += slot_ef[r * kMaxSlots + k];
-      slot_ef[r * kMaxSlots + k] = 0ull;
-    }
-    __hip_atomic_store(host + kHostEf + k, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (t < W)
+      for (int r = 0; r < kMsStats; ++r) {
+        x |= active[r * kMaxWords + t];
+        active[r * kMaxWords + t] = 0ull;
+      }
+    s_act[t] = x;
+    s_p[t] = 0ull;
+    s_q[t] = 0ull;
   }
-  if (t < W) {
-    u64 x = 0ull;
-    for (int r = 0; r < kMsStats; ++r) {
-      x |= active[r * kMaxWords + t];
-      active[r * kMaxWords + t] = 0ull;
-    }
-    __hip_atomic_store(host + kHostActive + t, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  }
-  u64 v = 0, e = 0;
   if (t < 64) {  // wave 0
+    u64 v = 0, e = 0;
     if (t < kMsStats) {
       v = stats[t * kMsStatStride];
       e = stats[t * kMsStatStride + 1];
@@ -514,13 +520,51 @@ __global__ void __launch_bounds__(256) k_ms_finalize(u64* stats, u64* active, u6
       v += __shfl_xor(v, off);
       e += __shfl_xor(e, off);
     }
+    if (t == 0) {
+      s_v = v;
+      s_e = e;
+    }
+  }
+  __syncthreads();
+  const u64 a_arcs = ctl->a_arcs, b_arcs = ctl->b_arcs;
+  const bool pull_ok = ctl->pull_ok != 0;
+  for (int k = t; k < nslots; k += 256) {
+    u64 ef = 0ull;
+    for (int r = 0; r < kMsStats; ++r) {
+      ef += slot_ef[r * kMaxSlots + k];
+      slot_ef[r * kMaxSlots + k] = 0ull;
+    }
+    if ((s_act[k >> 6] >> (k & 63)) & 1ull) {
+      uint8_t p = ctl->pull[k];
+      if (!pull_ok) p = 0;
+      else if (!p && ef > a_arcs) p = 1;
+      else if (p && ef < b_arcs) p = 0;
+      ctl->pull[k] = p;
+      atomicOr(p ? &s_q[k >> 6] : &s_p[k >> 6], 1ull << (k & 63));
+    }
+  }
+  __syncthreads();
+  u64* rec = ring + (size_t)(d % kRing) * kRecWords;
+  if (t < kMaxWords) {
+    ctl->pmask[t] = s_p[t];
+    ctl->qmask[t] = s_q[t];
+    if (t < W) __hip_atomic_store(rec + kRecActive + t, s_act[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+  if (t == 0) {
+    u64 p = 0ull, q = 0ull;
+    for (int j = 0; j < kMaxWords; ++j) {
+      p |= s_p[j];
+      q |= s_q[j];
+    }
+    ctl->any_push = p != 0ull;
+    ctl->any_pull = q != 0ull;
+    ctl->d = d + 1;
+    __hip_atomic_store(rec + 1, s_v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(rec + 2, s_e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
   __threadfence_system();
   __syncthreads();
-  if (t == 0) {
-    __hip_atomic_store(host + 1, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(host, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-  }
+  if (t == 0) __hip_atomic_store(rec, (u64)d + 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // [n][B] -> [nsrc][n] levels through 64x64-byte LDS tiles.
@@ -558,8 +602,8 @@ __global__ void __launch_bounds__(kMsBlock) k_ss_masks(u64* vis, int64_t n, int 
 }
 
 // Admitted slots: the source's bit in vis, in the current frontier and its
-// bitmap, level 0 (stored as 1).
-__global__ void k_ss_seed(u64* vis, u64* fr, u64* fbm, int32_t* dist, int64_t n, int W,
+// bitmap, level 0 (stored as 1), and the slot joins the next level top-down.
+__global__ void k_ss_seed(u64* vis, u64* fr, u64* fbm, int32_t* dist, MsCtl* ctl, int64_t n, int W,
                           const int32_t* __restrict__ src, const int32_t* __restrict__ slot, int count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
@@ -570,6 +614,18 @@ __global__ void k_ss_seed(u64* vis, u64* fr, u64* fbm, int32_t* dist, int64_t n,
   atomicOr(fr + s * W + (k >> 6), bit);
   atomicOr(fbm + (s >> 6), 1ull << (s & 63));
   dist[(int64_t)k * n + s] = 1;
+  ctl->pull[k] = 0;
+  atomicOr(&ctl->pmask[k >> 6], bit);
+  atomicAnd(&ctl->qmask[k >> 6], ~bit);
+  ctl->any_push = 1;
+}
+
+// Direction thresholds of a session, in stream order with its levels.
+__global__ void k_ss_thresholds(MsCtl* ctl, u64 a_arcs, u64 b_arcs) {
+  if (threadIdx.x == 0) {
+    ctl->a_arcs = a_arcs;
+    ctl->b_arcs = b_arcs;
+  }
 }
 
 // A finished slot's levels: out[v] = row[v] - 1 (-1 = not reached), and the
@@ -596,10 +652,13 @@ inline unsigned ms_grid(int64_t n) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks, kMsMaxGrid));
 }
 
-// Spread statistics counters and the mapped host words of one traversal.
+// Spread statistics counters, the level control block and the host ring of
+// one traversal.
 struct LevelStats {
   u64 *stats = nullptr, *active = nullptr, *slot_ef = nullptr;
-  u64 *h = nullptr, *d_h = nullptr;  // mapped host memory (kHostWords)
+  MsCtl* ctl = nullptr;    // device
+  MsCtl* h_ctl = nullptr;  // pinned staging for uploads of the control block
+  u64 *ring = nullptr, *d_ring = nullptr;  // mapped host memory (kRing records)
   size_t bytes = 0;
 };
 
@@ -607,9 +666,10 @@ gsw_status stats_alloc(LevelStats* st) {
   const size_t sb = (size_t)kMsStats * kMsStatStride * sizeof(u64);
   const size_t ab = (size_t)kMsStats * kMaxWords * sizeof(u64);
   const size_t eb = (size_t)kMsStats * kMaxSlots * sizeof(u64);
-  void** ps[] = {(void**)&st->stats, (void**)&st->active, (void**)&st->slot_ef};
-  const size_t bs[] = {sb, ab, eb};
-  for (int k = 0; k < 3; ++k) {
+  const size_t cb = sizeof(MsCtl);
+  void** ps[] = {(void**)&st->stats, (void**)&st->active, (void**)&st->slot_ef, (void**)&st->ctl};
+  const size_t bs[] = {sb, ab, eb, cb};
+  for (int k = 0; k < 4; ++k) {
     if (hipMalloc(ps[k], bs[k]) != hipSuccess) {
       (void)hipGetLastError();
       return fail(GSW_ENOMEM, "hipMalloc(%zu) for level statistics failed", bs[k]);
@@ -617,30 +677,39 @@ gsw_status stats_alloc(LevelStats* st) {
     st->bytes += bs[k];
     GSW_HIP(hipMemset(*ps[k], 0, bs[k]));
   }
-  GSW_HIP(hipHostMalloc((void**)&st->h, kHostWords * sizeof(u64), hipHostMallocMapped | hipHostMallocCoherent));
-  GSW_HIP(hipHostGetDevicePointer((void**)&st->d_h, st->h, 0));
+  GSW_HIP(hipHostMalloc((void**)&st->h_ctl, sizeof(MsCtl), hipHostMallocDefault));
+  std::memset(st->h_ctl, 0, sizeof(MsCtl));
+  GSW_HIP(hipHostMalloc((void**)&st->ring, (size_t)kRing * kRecWords * sizeof(u64),
+                        hipHostMallocMapped | hipHostMallocCoherent));
+  std::memset(st->ring, 0, (size_t)kRing * kRecWords * sizeof(u64));
+  GSW_HIP(hipHostGetDevicePointer((void**)&st->d_ring, st->ring, 0));
   return GSW_OK;
 }
 
 void stats_free(LevelStats* st) {
-  void* p[] = {st->stats, st->active, st->slot_ef};
+  void* p[] = {st->stats, st->active, st->slot_ef, st->ctl};
   for (void* x : p)
     if (x) (void)hipFree(x);
-  if (st->h) (void)hipHostFree(st->h);
+  if (st->h_ctl) (void)hipHostFree(st->h_ctl);
+  if (st->ring) (void)hipHostFree(st->ring);
   *st = LevelStats();
 }
 
-// Spins until the level's finalize kernel has published word 0, polling the
-// stream for errors now and then.
-gsw_status stats_wait(const LevelStats& st, hipStream_t s, const char* who) {
-  volatile u64* f = st.h;
+// Spins until level d's record is in the ring, polling the stream for
+// errors now and then; returns its words through *rec.
+gsw_status wait_record(const LevelStats& st, int64_t d, hipStream_t s, const char* who,
+                       const volatile u64** rec) {
+  const volatile u64* r = st.ring + (size_t)(d % kRing) * kRecWords;
   for (uint64_t it = 0;; ++it) {
-    if (f[0] != ~0ull) return GSW_OK;
+    if (r[0] == (u64)d + 1ull) {
+      *rec = r;
+      return GSW_OK;
+    }
     if ((it & 4095u) == 4095u) {
       const hipError_t e = hipStreamQuery(s);
       if (e == hipSuccess) {
-        if (f[0] != ~0ull) continue;
-        return fail(GSW_EHIP, "%s: level finished without reporting its statistics", who);
+        if (r[0] == (u64)d + 1ull) continue;
+        return fail(GSW_EHIP, "%s: level %lld finished without reporting", who, (long long)d);
       }
       if (e != hipErrorNotReady) return fail(GSW_EHIP, "%s: %s", who, hipGetErrorString(e));
     }
@@ -648,41 +717,18 @@ gsw_status stats_wait(const LevelStats& st, hipStream_t s, const char* who) {
   }
 }
 
-// Per-source direction, the single-source rule applied to each source:
-// bottom-up once its frontier's edges exceed push_to_pull of all arcs, back
-// to top-down below pull_to_push.  Sources not running are in neither mask.
-struct Direction {
-  std::vector<uint8_t> pull;
-  std::vector<u64> ef;
-  void reset(int slots) {
-    pull.assign((size_t)slots, 0);
-    ef.assign((size_t)slots, 0ull);
-  }
-  void start(int k) {
-    pull[(size_t)k] = 0;
-    ef[(size_t)k] = 0ull;
-  }
-  // running: W words; fills pm/qm (kMaxWords words each)
-  void choose(const u64* running, int W, bool pull_ok, double a_arcs, double b_arcs, u64* pm,
-              u64* qm) {
-    for (int j = 0; j < kMaxWords; ++j) pm[j] = qm[j] = 0ull;
-    for (int j = 0; j < W; ++j) {
-      u64 r = running[j];
-      while (r) {
-        const int b = __builtin_ctzll(r);
-        r &= r - 1ull;
-        const size_t k = (size_t)j * 64 + b;
-        if (pull_ok) {
-          if (!pull[k] && (double)ef[k] > a_arcs) pull[k] = 1;
-          else if (pull[k] && (double)ef[k] < b_arcs) pull[k] = 0;
-        } else {
-          pull[k] = 0;
-        }
-        (pull[k] ? qm : pm)[j] |= 1ull << b;
-      }
-    }
-  }
-};
+// Fills the staging control block for a traversal whose first level expands
+// the sources in `first` top-down.
+void ctl_reset(MsCtl* c, const u64* first, int W, int nslots, bool pull_ok, double a_arcs, double b_arcs) {
+  std::memset(c, 0, sizeof *c);
+  for (int j = 0; j < W; ++j) c->pmask[j] = first ? first[j] : 0ull;
+  for (int j = 0; j < W; ++j) c->any_push |= c->pmask[j] != 0ull;
+  c->a_arcs = (u64)a_arcs;
+  c->b_arcs = (u64)b_arcs;
+  c->pull_ok = pull_ok ? 1 : 0;
+  c->nslots = nslots;
+  c->W = W;
+}
 
 // Builds the graph's chunk list of rows longer than kMsHeavy once (count,
 // allocate, fill); the caller holds the graph's lock.
@@ -723,25 +769,28 @@ gsw_status ensure_heavy(gsw_graph* g) {
   return GSW_OK;
 }
 
-// Launches one level: the top-down pass when some source pushes, then the
-// bottom-up + update pass and the finalize kernel.  a.pmask / a.qmask and
-// the mask and bitmap pointers are set by the caller.
-gsw_status launch_ms_level(MsArgs& a, const LevelStats& st, int G, int nslots, hipStream_t s) {
+// Queues one level: the top-down pass (it returns at once when no source
+// pushes), the bottom-up + update pass and the finalize kernel.  The
+// statistics pointers of the arguments are taken from `st`.
+gsw_status launch_ms_level(MsArgs a, const LevelStats& st, int G, hipStream_t s) {
   a.stats = st.stats;
   a.active = st.active;
   a.slot_ef = st.slot_ef;
-  a.any_push = 0;
-  a.any_pull = 0;
-  for (int j = 0; j < kMaxWords; ++j) {
-    a.any_push |= a.pmask[j] != 0ull;
-    a.any_pull |= a.qmask[j] != 0ull;
-  }
+  a.ctl = st.ctl;
+  // every buffer the kernels touch must be there: a missing one would be a
+  // device fault, so it is an error here
+  const void* need[] = {a.offs, a.cols, a.vis, a.fr, a.frn, a.nx, a.fbm, a.fbm_n, a.tbm,
+                        a.stats, a.active, a.slot_ef, a.ctl, st.d_ring};
+  for (const void* p : need)
+    if (!p) return fail(GSW_EINVAL, "batched level launched with a missing buffer");
+  if ((!a.dist && !a.lev) || (a.dist && !a.start) || (a.n_heavy > 0 && !a.heavy) || a.W < 1 ||
+      a.W > kMaxWords || a.B != 64 * a.W || G < a.W || G > 16 || (G & (G - 1)) != 0)
+    return fail(GSW_EINVAL, "batched level launched with inconsistent arguments");
   const unsigned grid = ms_grid(a.n);
-  if (a.any_push) hipLaunchKernelGGL(k_ms_push, dim3(grid), dim3(kMsBlock), 0, s, a, G);
+  hipLaunchKernelGGL(k_ms_push, dim3(grid), dim3(kMsBlock), 0, s, a, G);
   hipLaunchKernelGGL(k_ms_level, dim3(grid), dim3(kMsBlock), 0, s, a, G);
-  hipLaunchKernelGGL(k_ms_finalize, dim3(1), dim3(256), 0, s, st.stats, st.active, st.slot_ef, a.W, nslots,
-                     st.d_h);
-  GSW_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_ms_finalize, dim3(1), dim3(256), 0, s, st.ctl, st.stats, st.active, st.slot_ef,
+                     st.d_ring);
   return GSW_OK;
 }
 
@@ -751,16 +800,24 @@ struct MsWorkspace {
   int64_t n = 0;
   int W = 0, B = 0;
   u64 *vis = nullptr, *fr = nullptr, *frn = nullptr, *nx = nullptr;
-  u64* bms = nullptr;  // 3 bitmaps of ceil(n/64) words: frontier d, frontier d+1, touched
+  u64* bms = nullptr;  // 3 bitmaps of ceil(n/64) words: frontier (two) and touched
   int8_t* lev = nullptr;
   int32_t* src = nullptr;
   LevelStats st;
+  // two levels (even, odd: the mask and bitmap buffers swap roles) captured
+  // once as a graph and replayed
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
   size_t bytes = 0;
 };
 
 namespace {
 void ms_free(MsWorkspace* m) {
   if (!m) return;
+  if (m->exec) (void)hipGraphExecDestroy(m->exec);
+  if (m->graph) (void)hipGraphDestroy(m->graph);
+  if (m->cap) (void)hipStreamDestroy(m->cap);
   void* p[] = {m->vis, m->fr, m->frn, m->nx, m->bms, m->lev, m->src};
   for (void* x : p)
     if (x) (void)hipFree(x);
@@ -771,7 +828,7 @@ void ms_free(MsWorkspace* m) {
 gsw_status ms_ensure(gsw_graph* g, int W) {
   GSW_TRY(ensure_heavy(g));
   MsWorkspace*& m = g->ms;
-  if (m && m->W >= W) return GSW_OK;
+  if (m && m->W == W) return GSW_OK;
   ms_free(m);
   m = new (std::nothrow) MsWorkspace();
   if (!m) return fail(GSW_ENOMEM, "host allocation failed");
@@ -807,6 +864,56 @@ gsw_status ms_ensure(gsw_graph* g, int W) {
   m->bytes += m->st.bytes;
   return GSW_OK;
 }
+
+// Level arguments of the batch; `odd` swaps the frontier buffers.
+MsArgs ms_args(const gsw_graph* g, const MsWorkspace* m, bool odd) {
+  MsArgs a;
+  std::memset(&a, 0, sizeof a);
+  const int64_t nw = cdiv(g->n, 64);
+  a.offs = g->offs;
+  a.cols = g->cols;
+  a.vis = m->vis;
+  a.fr = odd ? m->frn : m->fr;
+  a.frn = odd ? m->fr : m->frn;
+  a.nx = m->nx;
+  a.fbm = m->bms + (odd ? nw : 0);
+  a.fbm_n = m->bms + (odd ? 0 : nw);
+  a.tbm = m->bms + 2 * nw;
+  a.heavy = g->heavy;
+  a.n_heavy = g->n_heavy;
+  a.lev = m->lev;
+  a.ctl = m->st.ctl;
+  a.n = g->n;
+  a.W = m->W;
+  a.B = m->B;
+  return a;
+}
+
+// Captures the even and the odd level as one graph (once per workspace).
+gsw_status ms_capture(gsw_graph* g, MsWorkspace* m, int G) {
+  if (m->exec) return GSW_OK;
+  if (!m->cap) GSW_HIP(hipStreamCreateWithFlags(&m->cap, hipStreamNonBlocking));
+  GSW_HIP(hipStreamBeginCapture(m->cap, hipStreamCaptureModeRelaxed));
+  gsw_status ls = launch_ms_level(ms_args(g, m, false), m->st, G, m->cap);
+  if (ls == GSW_OK) ls = launch_ms_level(ms_args(g, m, true), m->st, G, m->cap);
+  const hipError_t e1 = hipGetLastError();
+  hipGraph_t graph = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(m->cap, &graph);
+  if (ls != GSW_OK || e1 != hipSuccess || e2 != hipSuccess || !graph) {
+    if (graph) (void)hipGraphDestroy(graph);
+    if (ls != GSW_OK) return ls;
+    return fail(GSW_EHIP, "capturing the batched level graph failed: %s",
+                hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+  }
+  hipGraphExec_t exec = nullptr;
+  if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return fail(GSW_EHIP, "instantiating the batched level graph failed");
+  }
+  m->graph = graph;
+  m->exec = exec;
+  return GSW_OK;
+}
 }  // namespace
 
 void ms_release(gsw_graph* g) {
@@ -828,6 +935,7 @@ void gsw_msbfs_opts_default(gsw_msbfs_opts* o) {
   std::memset(o, 0, sizeof *o);
   o->push_to_pull = 0.002f;
   o->pull_to_push = 0.0005f;
+  o->graph = 1;
 }
 
 gsw_status gsw_msbfs(const gsw_graph* cg, const int32_t* sources, int32_t n_sources, int8_t* levels,
@@ -846,7 +954,6 @@ gsw_status gsw_msbfs(const gsw_graph* cg, const int32_t* sources, int32_t n_sour
       return fail(GSW_EINVAL, "source %d (index %d) out of [0, %lld)", sources[i], i, (long long)g->n);
   std::lock_guard<std::mutex> lock(g->mu);
   GSW_HIP(hipSetDevice(g->device));
-  const bool pull_ok = g->symmetric != 0;
   const int W = (n_sources + 63) / 64;
   GSW_TRY(ms_ensure(g, W));
   MsWorkspace* m = g->ms;
@@ -854,7 +961,15 @@ gsw_status gsw_msbfs(const gsw_graph* cg, const int32_t* sources, int32_t n_sour
   const int B = W * 64;  // level bytes per vertex in the workspace
   const int G = group_lanes(W);
   const int64_t nw = cdiv(g->n, 64);
-  u64* fbm[2] = {m->bms, m->bms + nw};
+  if (o->graph) GSW_TRY(ms_capture(g, m, G));
+  // the ring must not hold records of an earlier call with the same level numbers
+  std::memset(m->st.ring, 0, (size_t)kRing * kRecWords * sizeof(u64));
+  std::vector<u64> first((size_t)W, 0ull);
+  for (int32_t i = 0; i < n_sources; ++i) first[(size_t)(i >> 6)] |= 1ull << (i & 63);
+  const double nnz = (double)std::max<int64_t>(g->nnz, 1);
+  ctl_reset(m->st.h_ctl, first.data(), W, n_sources, g->symmetric != 0, o->push_to_pull * nnz,
+            o->pull_to_push * nnz);
+  GSW_HIP(hipMemcpyAsync(m->st.ctl, m->st.h_ctl, sizeof(MsCtl), hipMemcpyHostToDevice, s));
   GSW_HIP(hipMemcpyAsync(m->src, sources, (size_t)n_sources * sizeof(int32_t), hipMemcpyHostToDevice, s));
   {
     const int64_t work = std::max<int64_t>(g->n * W, g->n * (int64_t)B / 8);
@@ -862,61 +977,60 @@ gsw_status gsw_msbfs(const gsw_graph* cg, const int32_t* sources, int32_t n_sour
     hipLaunchKernelGGL(k_ms_init, dim3(grid), dim3(kMsBlock), 0, s, m->vis, m->fr, m->frn, m->nx, m->bms,
                        m->lev, g->n, W, n_sources, B);
     hipLaunchKernelGGL(k_ms_sources, dim3((unsigned)cdiv(n_sources, 256)), dim3(256), 0, s, m->vis,
-                       m->fr, fbm[0], m->lev, W, B, (const int32_t*)m->src, n_sources);
+                       m->fr, m->bms, m->lev, W, B, (const int32_t*)m->src, n_sources);
     GSW_HIP(hipGetLastError());
   }
-  MsArgs a;
-  std::memset(&a, 0, sizeof a);
-  a.offs = g->offs;
-  a.cols = g->cols;
-  a.vis = m->vis;
-  a.nx = m->nx;
-  a.tbm = m->bms + 2 * nw;
-  a.heavy = g->heavy;
-  a.n_heavy = g->n_heavy;
-  a.lev = m->lev;
-  a.n = g->n;
-  a.W = W;
-  a.B = B;
-  u64* cur = m->fr;
-  u64* nxt = m->frn;
-  std::vector<u64> running((size_t)W, 0ull);
-  for (int32_t i = 0; i < n_sources; ++i) running[(size_t)(i >> 6)] |= 1ull << (i & 63);
-  Direction dir;
-  dir.reset(B);
-  const double nnz = (double)std::max<int64_t>(g->nnz, 1);
-  int32_t d = 0;
-  for (;; ++d) {
-    dir.choose(running.data(), W, pull_ok, o->push_to_pull * nnz, o->pull_to_push * nnz, a.pmask, a.qmask);
-    a.fr = cur;
-    a.frn = nxt;
-    a.fbm = fbm[d & 1];
-    a.fbm_n = fbm[(d + 1) & 1];
-    a.d = d;
-    m->st.h[0] = ~0ull;
-    GSW_TRY(launch_ms_level(a, m->st, G, n_sources, s));
-    GSW_TRY(stats_wait(m->st, s, "batched BFS"));
-    const volatile u64* h = m->st.h;
-    if (h[0] == 0) break;
-    if (d + 1 > GSW_MSBFS_LEVEL_CAP) {
-      (void)hipStreamSynchronize(s);
-      return fail(GSW_ERANGE, "a source reaches depth %d > %d (int8 levels)", d + 1, GSW_MSBFS_LEVEL_CAP);
+  (void)nw;
+  // Levels are queued up to kAhead beyond the last one whose record the host
+  // has read; levels after the last productive one find nothing and change
+  // nothing.  The captured graph queues two levels per launch.
+  constexpr int64_t kAhead = 2;
+  int64_t queued = 0, d = 0;
+  gsw_status st = GSW_OK;
+  for (;;) {
+    while (queued - d < kAhead) {
+      if (o->graph) {
+        if (hipGraphLaunch(m->exec, s) != hipSuccess) {
+          st = fail(GSW_EHIP, "launching the batched level graph failed");
+          break;
+        }
+        queued += 2;
+      } else {
+        st = launch_ms_level(ms_args(g, m, (queued & 1) != 0), m->st, G, s);
+        if (st != GSW_OK) break;
+        queued += 1;
+      }
     }
-    for (int j = 0; j < W; ++j) running[(size_t)j] = h[kHostActive + j];
-    for (int32_t k = 0; k < n_sources; ++k) dir.ef[(size_t)k] = h[kHostEf + k];
-    std::swap(cur, nxt);
+    if (st == GSW_OK && hipGetLastError() != hipSuccess) st = fail(GSW_EHIP, "batched level launch failed");
+    if (st != GSW_OK) break;
+    const volatile u64* rec = nullptr;
+    st = wait_record(m->st, d, s, "batched BFS", &rec);
+    if (st != GSW_OK) break;
+    if (rec[1] == 0) break;  // level d found nothing: d + 1 levels ran
+    if (d + 1 > GSW_MSBFS_LEVEL_CAP) {
+      st = fail(GSW_ERANGE, "a source reaches depth %lld > %d (int8 levels)", (long long)d + 1,
+                GSW_MSBFS_LEVEL_CAP);
+      break;
+    }
+    ++d;
   }
-  if (n_levels) *n_levels = d + 1;
+  if (st != GSW_OK) {
+    (void)hipStreamSynchronize(s);
+    return st;
+  }
+  if (n_levels) *n_levels = (int32_t)(d + 1);
   // [n][B] -> [n_sources][n]
   int8_t* out = levels;
   int8_t* tmp = nullptr;
   if (!o->device_ptrs) {
-    GSW_HIP(hipMalloc((void**)&tmp, (size_t)n_sources * g->n));
+    if (hipMalloc((void**)&tmp, (size_t)n_sources * g->n) != hipSuccess) {
+      (void)hipStreamSynchronize(s);
+      return fail(GSW_ENOMEM, "hipMalloc for the level copy-back failed");
+    }
     out = tmp;
   }
   hipLaunchKernelGGL(k_ms_transpose, dim3((unsigned)cdiv(g->n, 64), (unsigned)cdiv(n_sources, 64)),
                      dim3(256), 0, s, (const int8_t*)m->lev, out, g->n, B, n_sources);
-  gsw_status st = GSW_OK;
   if (hipGetLastError() != hipSuccess) st = fail(GSW_EHIP, "transpose launch failed");
   if (st == GSW_OK && tmp) {
     if (hipMemcpyAsync(levels, tmp, (size_t)n_sources * g->n, hipMemcpyDeviceToHost, s) != hipSuccess)
@@ -940,15 +1054,16 @@ struct gsw_session {
   int32_t *dist = nullptr, *start_d = nullptr, *seed = nullptr;  // seed: src[slots] then slot[slots]
   int32_t* take = nullptr;  // device staging for fetches into host memory
   LevelStats st;
-  // pinned staging for the per-level uploads: masks, then seed src/slot, then start
+  // pinned staging for the per-boundary uploads: masks, then seed src/slot, then start
   u64* h_masks = nullptr;
   int32_t* h_seed = nullptr;
   int32_t* h_start = nullptr;
   std::vector<int32_t> source;
-  std::vector<int8_t> state;  // 0 free, 1 admitted (seeded at the next level boundary), 2 running, 3 finished
-  std::vector<u64> freed;     // slots freed since the last level (made inert then)
-  Direction dir;
-  int64_t it = 0;  // levels run by this session
+  std::vector<int64_t> start;  // level at which a running slot was seeded
+  std::vector<int8_t> state;   // 0 free, 1 admitted (seeded at the next level boundary), 2 running, 3 finished
+  std::vector<u64> freed;      // slots freed since the last boundary (made inert then)
+  int64_t queued = 0;          // levels queued on the stream
+  int64_t done = 0;            // levels whose record has been read
   float push_to_pull = 0.002f, pull_to_push = 0.0005f;
   hipStream_t stream = nullptr;
   size_t bytes = 0;
@@ -960,6 +1075,7 @@ namespace {
 
 void ss_free(gsw_session* ss) {
   if (!ss) return;
+  if (ss->stream) (void)hipStreamSynchronize(ss->stream);  // a level may still be queued
   void* p[] = {ss->vis, ss->fr, ss->frn, ss->nx, ss->bms, ss->masks, ss->dist, ss->start_d, ss->seed, ss->take};
   for (void* x : p)
     if (x) (void)hipFree(x);
@@ -1032,11 +1148,15 @@ gsw_status gsw_session_create(const gsw_graph* cg, int32_t max_slots, gsw_sessio
   }
   if (st == GSW_OK) {
     const hipStream_t s = ss->stream;
+    const double nnz = (double)std::max<int64_t>(g->nnz, 1);
+    ctl_reset(ss->st.h_ctl, nullptr, ss->W, max_slots, g->symmetric != 0, ss->push_to_pull * nnz,
+              ss->pull_to_push * nnz);
     // every slot starts inert: visited everywhere, in no frontier, not reached
     if (hipMemsetAsync(ss->vis, 0xff, mb, s) != hipSuccess || hipMemsetAsync(ss->fr, 0, mb, s) != hipSuccess ||
         hipMemsetAsync(ss->frn, 0, mb, s) != hipSuccess || hipMemsetAsync(ss->nx, 0, mb, s) != hipSuccess ||
         hipMemsetAsync(ss->bms, 0, bb, s) != hipSuccess ||
         hipMemsetAsync(ss->dist, 0, (size_t)max_slots * n * sizeof(int32_t), s) != hipSuccess ||
+        hipMemcpyAsync(ss->st.ctl, ss->st.h_ctl, sizeof(MsCtl), hipMemcpyHostToDevice, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       st = fail(GSW_EHIP, "session initialisation failed");
   }
@@ -1046,9 +1166,9 @@ gsw_status gsw_session_create(const gsw_graph* cg, int32_t max_slots, gsw_sessio
   }
   std::memset(ss->h_start, 0, (size_t)max_slots * sizeof(int32_t));
   ss->source.assign((size_t)max_slots, -1);
+  ss->start.assign((size_t)max_slots, 0);
   ss->state.assign((size_t)max_slots, 0);
   ss->freed.assign((size_t)ss->W, 0ull);
-  ss->dir.reset(max_slots);
   *out = ss;
   return GSW_OK;
 }
@@ -1071,6 +1191,92 @@ gsw_status gsw_session_admit(gsw_session* ss, int32_t source, int32_t* slot) {
   return fail(GSW_EBUSY, "all %d slots are in use", ss->slots);
 }
 
+namespace {
+
+// Level boundary of a session: seeds the queries admitted since the last
+// one (they join level ss->queued), makes freed slots inert and queues the
+// level.  Returns false through *queued when no slot is running or waiting.
+gsw_status ss_queue_level(gsw_session* ss, bool* queued_one) {
+  *queued_one = false;
+  gsw_graph* g = ss->g;
+  const hipStream_t s = ss->stream;
+  const int W = ss->W;
+  const int64_t n = g->n;
+  int c = 0;
+  bool any_mask = false, running = false;
+  {
+    std::lock_guard<std::mutex> lock(ss->mu);
+    u64* clr = ss->h_masks;
+    u64* set = ss->h_masks + kMaxWords;
+    for (int j = 0; j < kMaxWords; ++j) clr[j] = set[j] = 0ull;
+    for (int k = 0; k < ss->slots; ++k) {
+      if (ss->state[(size_t)k] == 1) {
+        clr[k >> 6] |= 1ull << (k & 63);
+        ss->h_seed[c] = ss->source[(size_t)k];
+        ss->h_seed[ss->slots + c] = k;
+        ss->h_start[k] = (int32_t)ss->queued;
+        ss->start[(size_t)k] = ss->queued;
+        ss->state[(size_t)k] = 2;
+        ++c;
+      }
+      running = running || ss->state[(size_t)k] == 2;
+    }
+    for (int j = 0; j < W; ++j) {
+      set[j] = ss->freed[(size_t)j] & ~clr[j];
+      any_mask = any_mask || clr[j] || set[j];
+      ss->freed[(size_t)j] = 0ull;
+    }
+  }
+  if (any_mask) {
+    GSW_HIP(hipMemcpyAsync(ss->masks, ss->h_masks, 2 * (size_t)kMaxWords * sizeof(u64), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_ss_masks, dim3((unsigned)std::min<int64_t>(cdiv(n * W, kMsBlock), 65536)),
+                       dim3(kMsBlock), 0, s, ss->vis, n, W, (const u64*)ss->masks,
+                       (const u64*)(ss->masks + kMaxWords));
+  }
+  if (c > 0) {
+    GSW_HIP(hipMemcpyAsync(ss->seed, ss->h_seed, 2 * (size_t)ss->slots * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    GSW_HIP(hipMemcpyAsync(ss->start_d, ss->h_start, ss->slots * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_ss_seed, dim3((unsigned)cdiv(c, 256)), dim3(256), 0, s, ss->vis, ss->fr, ss->fbm[0],
+                       ss->dist, ss->st.ctl, n, W, (const int32_t*)ss->seed, (const int32_t*)(ss->seed + ss->slots),
+                       c);
+  }
+  GSW_HIP(hipGetLastError());
+  if (!running) {
+    // nothing to run; the pinned staging must not be rewritten before the
+    // copies above are done
+    if (any_mask) GSW_HIP(hipStreamSynchronize(s));
+    return GSW_OK;
+  }
+  MsArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.offs = g->offs;
+  a.cols = g->cols;
+  a.vis = ss->vis;
+  a.fr = ss->fr;
+  a.frn = ss->frn;
+  a.nx = ss->nx;
+  a.fbm = ss->fbm[0];
+  a.fbm_n = ss->fbm[1];
+  a.tbm = ss->bms + 2 * cdiv(n, 64);
+  a.heavy = g->heavy;
+  a.n_heavy = g->n_heavy;
+  a.dist = ss->dist;
+  a.start = ss->start_d;
+  a.ctl = ss->st.ctl;
+  a.n = n;
+  a.W = W;
+  a.B = W * 64;
+  GSW_TRY(launch_ms_level(a, ss->st, group_lanes(W), s));
+  GSW_HIP(hipGetLastError());
+  std::swap(ss->fr, ss->frn);
+  std::swap(ss->fbm[0], ss->fbm[1]);
+  ss->queued += 1;
+  *queued_one = true;
+  return GSW_OK;
+}
+
+}  // namespace
+
 gsw_status gsw_session_step(gsw_session* ss, int32_t max_levels, int32_t* finished, int32_t finished_cap,
                             int32_t* n_finished, int32_t* levels_run) {
   clear_error();
@@ -1078,105 +1284,32 @@ gsw_status gsw_session_step(gsw_session* ss, int32_t max_levels, int32_t* finish
   if (levels_run) *levels_run = 0;
   if (!ss || max_levels < 1 || (finished_cap > 0 && !finished)) return fail(GSW_EINVAL, "bad step arguments");
   std::lock_guard<std::mutex> step_lock(ss->step_mu);
-  gsw_graph* g = ss->g;
-  GSW_HIP(hipSetDevice(g->device));
-  const hipStream_t s = ss->stream;
-  const int W = ss->W;
-  const int64_t n = g->n;
-  const int G = group_lanes(W);
-  const bool pull_ok = g->symmetric != 0;
-  const double nnz = (double)std::max<int64_t>(g->nnz, 1);
-  MsArgs a;
-  std::memset(&a, 0, sizeof a);
-  a.offs = g->offs;
-  a.cols = g->cols;
-  a.vis = ss->vis;
-  a.nx = ss->nx;
-  a.tbm = ss->bms + 2 * cdiv(n, 64);
-  a.heavy = g->heavy;
-  a.n_heavy = g->n_heavy;
-  a.n = n;
-  a.W = W;
-  a.B = W * 64;
-  a.dist = ss->dist;
-  a.start = ss->start_d;
+  GSW_HIP(hipSetDevice(ss->g->device));
+  // One level is kept queued beyond the one being waited for, so the device
+  // goes from level to level without waiting for the host; queries admitted
+  // meanwhile join at the next boundary the host reaches.
   int32_t nfin = 0, run = 0;
-  std::vector<u64> running((size_t)W);
-  for (; run < max_levels; ++run) {
-    // level boundary: take the queries admitted since the last level, make
-    // freed slots inert, pick each running slot's direction
-    int c = 0;
-    bool any_mask = false;
-    {
-      std::lock_guard<std::mutex> lock(ss->mu);
-      u64* clr = ss->h_masks;
-      u64* set = ss->h_masks + kMaxWords;
-      for (int j = 0; j < kMaxWords; ++j) clr[j] = set[j] = 0ull;
-      for (int k = 0; k < ss->slots; ++k)
-        if (ss->state[(size_t)k] == 1) {
-          clr[k >> 6] |= 1ull << (k & 63);
-          ss->h_seed[c] = ss->source[(size_t)k];
-          ss->h_seed[ss->slots + c] = k;
-          ss->h_start[k] = (int32_t)ss->it;
-          ss->state[(size_t)k] = 2;
-          ss->dir.start(k);
-          ++c;
-        }
-      for (int j = 0; j < W; ++j) {
-        set[j] = ss->freed[(size_t)j] & ~clr[j];
-        any_mask = any_mask || clr[j] || set[j];
-        ss->freed[(size_t)j] = 0ull;
-      }
-      std::fill(running.begin(), running.end(), 0ull);
-      for (int k = 0; k < ss->slots; ++k)
-        if (ss->state[(size_t)k] == 2) running[(size_t)(k >> 6)] |= 1ull << (k & 63);
+  while (run < max_levels) {
+    if (ss->queued - ss->done < 2) {
+      bool q = false;
+      GSW_TRY(ss_queue_level(ss, &q));
+      if (!q && ss->queued == ss->done) break;  // nothing queued, nothing running
     }
-    bool any_running = false;
-    for (u64 r : running) any_running = any_running || r;
-    if (any_mask) {
-      GSW_HIP(hipMemcpyAsync(ss->masks, ss->h_masks, 2 * (size_t)kMaxWords * sizeof(u64), hipMemcpyHostToDevice, s));
-      hipLaunchKernelGGL(k_ss_masks, dim3((unsigned)std::min<int64_t>(cdiv(n * W, kMsBlock), 65536)),
-                         dim3(kMsBlock), 0, s, ss->vis, n, W, (const u64*)ss->masks,
-                         (const u64*)(ss->masks + kMaxWords));
-    }
-    if (c > 0) {
-      GSW_HIP(hipMemcpyAsync(ss->seed, ss->h_seed, 2 * (size_t)ss->slots * sizeof(int32_t), hipMemcpyHostToDevice, s));
-      GSW_HIP(hipMemcpyAsync(ss->start_d, ss->h_start, ss->slots * sizeof(int32_t), hipMemcpyHostToDevice, s));
-      hipLaunchKernelGGL(k_ss_seed, dim3((unsigned)cdiv(c, 256)), dim3(256), 0, s, ss->vis, ss->fr, ss->fbm[0],
-                         ss->dist, n, W, (const int32_t*)ss->seed, (const int32_t*)(ss->seed + ss->slots), c);
-    }
-    GSW_HIP(hipGetLastError());
-    if (!any_running) {
-      if (any_mask) GSW_HIP(hipStreamSynchronize(s));
-      break;
-    }
-    ss->dir.choose(running.data(), W, pull_ok, ss->push_to_pull * nnz, ss->pull_to_push * nnz, a.pmask, a.qmask);
-    a.fr = ss->fr;
-    a.frn = ss->frn;
-    a.fbm = ss->fbm[0];
-    a.fbm_n = ss->fbm[1];
-    a.d = (int32_t)ss->it;
-    ss->st.h[0] = ~0ull;
-    GSW_TRY(launch_ms_level(a, ss->st, G, ss->slots, s));
-    GSW_TRY(stats_wait(ss->st, s, "session"));
-    ss->it += 1;
-    std::swap(ss->fr, ss->frn);
-    std::swap(ss->fbm[0], ss->fbm[1]);
-    const volatile u64* h = ss->st.h;
+    const volatile u64* rec = nullptr;
+    GSW_TRY(wait_record(ss->st, ss->done, ss->stream, "session", &rec));
+    const int64_t d = ss->done;
+    ss->done += 1;
+    ++run;
     std::lock_guard<std::mutex> lock(ss->mu);
     for (int k = 0; k < ss->slots; ++k) {
-      if (ss->state[(size_t)k] != 2) continue;
-      ss->dir.ef[(size_t)k] = h[kHostEf + k];
-      if (((h[kHostActive + (k >> 6)] >> (k & 63)) & 1ull) == 0ull) {
+      if (ss->state[(size_t)k] != 2 || ss->start[(size_t)k] > d) continue;
+      if (((rec[kRecActive + (k >> 6)] >> (k & 63)) & 1ull) == 0ull) {
         ss->state[(size_t)k] = 3;
         if (nfin < finished_cap) finished[nfin] = k;
         ++nfin;
       }
     }
-    if (nfin > 0) {
-      ++run;
-      break;
-    }
+    if (nfin > 0) break;
   }
   if (n_finished) *n_finished = nfin;
   if (levels_run) *levels_run = run;
@@ -1222,7 +1355,7 @@ gsw_status gsw_session_info(const gsw_session* css, int32_t* slots, int32_t* bus
     for (int8_t x : ss->state) b += x != 0;
     *busy = b;
   }
-  if (iteration) *iteration = ss->it;
+  if (iteration) *iteration = ss->done;
   if (dev_bytes) *dev_bytes = ss->bytes;
   return GSW_OK;
 }
@@ -1233,6 +1366,11 @@ gsw_status gsw_session_set_thresholds(gsw_session* ss, float push_to_pull, float
   std::lock_guard<std::mutex> lock(ss->step_mu);
   ss->push_to_pull = push_to_pull;
   ss->pull_to_push = pull_to_push;
+  const double nnz = (double)std::max<int64_t>(ss->g->nnz, 1);
+  GSW_HIP(hipSetDevice(ss->g->device));
+  hipLaunchKernelGGL(k_ss_thresholds, dim3(1), dim3(64), 0, ss->stream, ss->st.ctl,
+                     (u64)(push_to_pull * nnz), (u64)(pull_to_push * nnz));
+  GSW_HIP(hipGetLastError());
   return GSW_OK;
 }
 

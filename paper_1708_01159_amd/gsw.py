@@ -60,7 +60,7 @@ class BfsOpts(ctypes.Structure):
 
 class MsbfsOpts(ctypes.Structure):
     _fields_ = [("push_to_pull", ctypes.c_float), ("pull_to_push", ctypes.c_float),
-                ("device_ptrs", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("device_ptrs", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("stream", ctypes.c_void_p)]
 
 
@@ -398,13 +398,16 @@ class Runner:
 
 
 def msbfs(graph: Graph, sources, push_to_pull: float = None, pull_to_push: float = None,
-          device: bool = False, stream=None, out=None):
+          device: bool = False, stream=None, out=None, use_graph: bool = True):
     """Batched BFS of up to 1024 sources.  Returns ``(levels int8 [S][n], n_levels)``;
-    levels are a torch CUDA tensor when ``device`` (or ``out`` is given)."""
+    levels are a torch CUDA tensor when ``device`` (or ``out`` is given).
+    ``use_graph`` replays the captured two-level HIP graph instead of
+    launching each kernel."""
     src = np.ascontiguousarray(np.atleast_1d(np.asarray(sources)), dtype=np.int32)
     S, n = src.shape[0], graph.n
     o = MsbfsOpts()
     lib().gsw_msbfs_opts_default(ctypes.byref(o))
+    o.graph = 1 if use_graph else 0
     if push_to_pull is not None:
         o.push_to_pull = push_to_pull
     if pull_to_push is not None:

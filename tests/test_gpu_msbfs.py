@@ -83,16 +83,28 @@ def hub_graph():
     return gg.from_edges(a.n + 3, src, dst)
 
 
+@pytest.mark.parametrize("use_graph", [True, False])
 @pytest.mark.parametrize("p2p", [(1e9, 1e9), (0.002, 0.0005), (0.0, 0.0)])
-def test_msbfs_heavy_rows(p2p):
+def test_msbfs_heavy_rows(p2p, use_graph):
     g = hub_graph()
     G = gsw.Graph.from_csr(g.offs, g.cols)
     assert np.diff(g.offs).max() > 1024
     hubs = np.arange(g.n - 3, g.n)
     srcs = np.concatenate([hubs, gg.pick_sources(g, 100, 61), [int(g.cols[g.offs[g.n - 1]])]])
-    lv, _ = gsw.msbfs(G, srcs, push_to_pull=p2p[0], pull_to_push=p2p[1])
+    lv, _ = gsw.msbfs(G, srcs, push_to_pull=p2p[0], pull_to_push=p2p[1], use_graph=use_graph)
     assert np.array_equal(lv, expected(g, srcs))
     G.close()
+
+
+def test_msbfs_graph_replays_across_calls():
+    # the captured two-level graph is reused by later calls of the same width
+    # and recaptured when the width changes; direct launches interleave
+    g, G = graph("chunglu")
+    for i, (nsrc, use_graph) in enumerate([(64, True), (40, True), (64, False), (130, True), (3, True),
+                                           (64, True)]):
+        srcs = gg.pick_sources(g, nsrc, 300 + i)
+        lv, nl = gsw.msbfs(G, srcs, use_graph=use_graph)
+        assert np.array_equal(lv, expected(g, srcs)), (nsrc, use_graph)
 
 
 def test_msbfs_tiny_graph():
