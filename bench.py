@@ -132,11 +132,10 @@ def bench_batched(log, batches=(64, 256, 1024)):
     single = gsw.Runner(G, lv1, None, policy="tree", tree=tree)
     single.run(int(srcs[0]))
     t_single = np.array([timed(single, s, sync) for s in srcs])
-    p2p, p2s, table = autotune.tune(G, srcs[:256], log=None)
-    log("batched: autotuned push_to_pull=%g pull_to_push=%g" % (p2p, p2s))
     out = {}
     for B in batches:
         src = srcs[:B]
+        p2p, p2s, table = autotune.tune(G, src, log=None)
         lvB = torch.empty((B, g.n), dtype=torch.int8, device="cuda")
         gsw.msbfs(G, src, p2p, p2s, out=lvB)
         ts = []
@@ -149,14 +148,15 @@ def bench_batched(log, batches=(64, 256, 1024)):
         edges = int(ce[src].sum())
         one = float(t_single[:B].sum())
         out[str(B)] = {"ms": round(t * 1e3, 3), "gteps": round(edges / t / 1e9, 2),
+                       "push_to_pull": p2p, "pull_to_push": p2s,
                        "one_at_a_time_ms": round(one * 1e3, 3),
                        "one_at_a_time_gteps": round(edges / one / 1e9, 2),
                        "speedup": round(one / t, 2), "levels": nl}
-        log("batched B=%d: %.2f ms (%.1f GTEPS) vs one at a time %.2f ms (%.1f GTEPS)"
-            % (B, t * 1e3, edges / t / 1e9, one * 1e3, edges / one / 1e9))
+        log("batched B=%d: %.2f ms (%.1f GTEPS) vs one at a time %.2f ms (%.1f GTEPS); thresholds %g/%g"
+            % (B, t * 1e3, edges / t / 1e9, one * 1e3, edges / one / 1e9, p2p, p2s))
     G.close()
     return {"workload": "R-MAT scale 20 (1,048,576 vertices), edgefactor 16, seed 6; sources seed 106",
-            "push_to_pull": p2p, "pull_to_push": p2s, "level_type": "int8", "batches": out}
+            "level_type": "int8", "thresholds": "autotuned per batch size", "batches": out}
 
 
 def bench_sweep(tree, args, log):
@@ -224,7 +224,7 @@ def bench_serving(args, tree, log, preloaded):
     else:
         specs = [("rmat22", None), ("rmat20", lambda: gg.rmat(20, 16, seed=9)),
                  ("er20", lambda: gg.erdos_renyi(1 << 20, 4 << 20, seed=14))]
-        rates, duration, slots = (500, 2000), 2.0, 64
+        rates, duration, slots = (500, 2000, 6000), 2.0, 64
         budget = 16 << 30
     residents, cands = {}, {}
     for name, make in specs:
@@ -237,20 +237,24 @@ def bench_serving(args, tree, log, preloaded):
         cands[name] = np.flatnonzero(g.degrees() > 0)
     names = [s[0] for s in specs]
     runs = []
+    fmt = lambda r: "p50 %.2f p99 %.2f ms %.1f GTEPS" % (r["p50_ms"], r["p99_ms"], r["gteps"])
     for rate in rates:
         trace = serve.poisson_trace(rate, duration, names, cands, seed=107 + rate)
-        srv = serve.Server(residents, slots=slots, hbm_budget=budget)
-        qb = srv.run(trace, timeout_s=120)
-        sb = serve.summarize(qb, residents, "continuous batching")
-        row = {"rate_qps": rate, "batched": sb}
+        row = {"rate_qps": rate}
+        for key, solo in (("batched", False), ("batched_solo_lane", True)):
+            srv = serve.Server(residents, slots=slots, hbm_budget=budget, solo=solo, solo_factory=None)
+            qb = srv.run(trace, timeout_s=120)
+            row[key] = serve.summarize(qb, residents, "continuous batching" +
+                                       (" + single-source lane" if solo else ""))
+            if solo:
+                row[key]["solo_served"] = srv.solo_served
         if not args.serving_full or rate <= 500:
             qo = serve.serve_one_at_a_time(residents, trace, tree, timeout_s=120)
             row["one_at_a_time"] = serve.summarize(qo, residents, "one at a time")
         runs.append(row)
-        log("serving %d QPS: batched p50 %.2f ms p99 %.2f ms %.1f GTEPS; one-at-a-time %s"
-            % (rate, sb["p50_ms"], sb["p99_ms"], sb["gteps"],
-               "p50 %.2f p99 %.2f %.1f GTEPS" % (row["one_at_a_time"]["p50_ms"], row["one_at_a_time"]["p99_ms"],
-                                                   row["one_at_a_time"]["gteps"]) if "one_at_a_time" in row else "-"))
+        log("serving %d QPS: batched %s; + solo lane %s; one at a time %s"
+            % (rate, fmt(row["batched"]), fmt(row["batched_solo_lane"]),
+               fmt(row["one_at_a_time"]) if "one_at_a_time" in row else "-"))
     return {"graphs": names, "zipf": 1.1, "duration_s": duration, "slots": slots,
             "hbm_budget_bytes": budget, "runs": runs}
 

@@ -235,15 +235,15 @@ gsw_status gsw_bfs_profile(const gsw_graph *g, int32_t source, const int32_t *ke
 #define GSW_MSBFS_LEVEL_CAP 127 /* int8 levels */
 
 typedef struct {
-  float push_to_pull;  /* per source: switch it to bottom-up when its frontier's edges
-                          exceed this fraction of all arcs ... */
-  float pull_to_push;  /* ... and back to top-down below this fraction */
+  float push_to_pull;  /* per source: switch it to bottom-up when its frontier's arcs exceed
+                          this fraction of the arcs it has not reached yet ... */
+  float pull_to_push;  /* ... and back to top-down when they fall below this fraction of all arcs */
   int32_t device_ptrs; /* 1: levels is device memory; 0: host */
   int32_t graph;       /* 1: replay a captured two-level HIP graph; 0: launch each kernel */
   void *stream;        /* hipStream_t; NULL = library stream */
 } gsw_msbfs_opts;
 
-/* Fills opts: push_to_pull 0.002, pull_to_push 0.0005, graph 1, host pointers. */
+/* Fills opts: push_to_pull 0.07, pull_to_push 0.01, graph 1, host pointers. */
 void gsw_msbfs_opts_default(gsw_msbfs_opts *opts);
 
 /*
@@ -306,7 +306,7 @@ gsw_status gsw_session_fetch(gsw_session *ss, int32_t slot, int32_t *levels, int
 gsw_status gsw_session_info(const gsw_session *ss, int32_t *slots, int32_t *busy,
                             int64_t *iteration, size_t *dev_bytes);
 
-/* Direction thresholds as in gsw_msbfs_opts (defaults 0.002 / 0.0005). */
+/* Direction thresholds as in gsw_msbfs_opts (defaults 0.07 / 0.01). */
 gsw_status gsw_session_set_thresholds(gsw_session *ss, float push_to_pull, float pull_to_push);
 
 /* ------------------------------------------------------------------ misc */

@@ -1,8 +1,8 @@
 """Autotuner for the batched BFS's direction thresholds.
 
-The batched traversal switches from top-down to bottom-up when the frontier's
-edges exceed ``push_to_pull`` of all arcs and back when they drop below
-``pull_to_push``.  The best pair depends on the graph and the batch size, so
+The batched traversal switches a source from top-down to bottom-up when its
+frontier's arcs exceed ``push_to_pull`` of the arcs it has not reached yet,
+and back when they drop below ``pull_to_push`` of all arcs.  The best pair depends on the graph and the batch size, so
 it is measured: every candidate pair runs the same sample batch and the
 fastest is kept.  Results are cached per (graph signature, batch size) in a
 JSON file when a path is given.
@@ -17,8 +17,8 @@ import numpy as np
 
 from . import gsw
 
-PUSH_TO_PULL = (0.0005, 0.002, 0.01, 0.05)
-PULL_TO_PUSH = (0.0001, 0.0005, 0.005)
+PUSH_TO_PULL = (0.001, 0.003, 0.01, 0.03, 0.07, 0.2)
+PULL_TO_PUSH = (0.0001, 0.001, 0.01)
 
 
 def signature(graph: gsw.Graph, batch: int) -> str:

@@ -69,12 +69,15 @@ constexpr int kRecActive = 3;
 struct MsCtl {
   u64 pmask[kMaxWords];  // sources expanded top-down this level
   u64 qmask[kMaxWords];  // sources expanded bottom-up this level
-  u64 a_arcs, b_arcs;    // direction thresholds in arcs
+  double to_pull;        // bottom-up once frontier arcs > to_pull x the source's unexplored arcs
+  double to_push;        // top-down again once frontier arcs < to_push x all arcs
+  u64 arcs;              // arcs of the graph
   int32_t any_push, any_pull;
   int32_t d;             // this level's index
   int32_t pull_ok;       // bottom-up allowed (symmetric graph)
   int32_t nslots, W;
-  uint8_t pull[kMaxSlots];  // per source: expanded bottom-up at its last level
+  uint8_t pull[kMaxSlots];    // per source: expanded bottom-up at its last level
+  u64 explored[kMaxSlots];    // per source: arcs of the vertices it has reached
 };
 
 struct MsArgs {
@@ -486,10 +489,14 @@ __global__ void __launch_bounds__(kMsBlock) k_ms_level(MsArgs a, int G) {
 }
 
 // End of level d: sums the spread counters, sets each running source's
-// direction for level d+1 (the single-source rule on its own frontier's
-// arcs) and the masks, advances ctl->d, and publishes the level's record to
-// the host ring (its first word last).  The counters are zeroed for the next
-// level.
+// direction for level d+1 and the masks, advances ctl->d, and publishes the
+// level's record to the host ring (its first word last).  The counters are
+// zeroed for the next level.  Direction, per source as in direction-
+// optimising BFS: bottom-up once the new frontier's arcs exceed to_pull of
+// the arcs the source has not reached yet (a bottom-up pass is shared by all
+// pulling sources, and one with a small frontier would make every vertex
+// scan its whole row), top-down again once they fall below to_push of all
+// arcs.
 __global__ void __launch_bounds__(256) k_ms_finalize(MsCtl* ctl, u64* stats, u64* active, u64* slot_ef,
                                                      u64* ring) {
   __shared__ u64 s_act[kMaxWords], s_p[kMaxWords], s_q[kMaxWords];
@@ -526,7 +533,8 @@ __global__ void __launch_bounds__(256) k_ms_finalize(MsCtl* ctl, u64* stats, u64
     }
   }
   __syncthreads();
-  const u64 a_arcs = ctl->a_arcs, b_arcs = ctl->b_arcs;
+  const double to_pull = ctl->to_pull, to_push = ctl->to_push;
+  const u64 arcs = ctl->arcs;
   const bool pull_ok = ctl->pull_ok != 0;
   for (int k = t; k < nslots; k += 256) {
     u64 ef = 0ull;
@@ -535,10 +543,13 @@ __global__ void __launch_bounds__(256) k_ms_finalize(MsCtl* ctl, u64* stats, u64
       slot_ef[r * kMaxSlots + k] = 0ull;
     }
     if ((s_act[k >> 6] >> (k & 63)) & 1ull) {
+      const u64 ex = ctl->explored[k] + ef;
+      ctl->explored[k] = ex;
+      const double unexplored = ex < arcs ? (double)(arcs - ex) : 0.0;
       uint8_t p = ctl->pull[k];
       if (!pull_ok) p = 0;
-      else if (!p && ef > a_arcs) p = 1;
-      else if (p && ef < b_arcs) p = 0;
+      else if (!p && (double)ef > to_pull * unexplored) p = 1;
+      else if (p && (double)ef < to_push * (double)arcs) p = 0;
       ctl->pull[k] = p;
       atomicOr(p ? &s_q[k >> 6] : &s_p[k >> 6], 1ull << (k & 63));
     }
@@ -615,16 +626,17 @@ __global__ void k_ss_seed(u64* vis, u64* fr, u64* fbm, int32_t* dist, MsCtl* ctl
   atomicOr(fbm + (s >> 6), 1ull << (s & 63));
   dist[(int64_t)k * n + s] = 1;
   ctl->pull[k] = 0;
+  ctl->explored[k] = 0ull;
   atomicOr(&ctl->pmask[k >> 6], bit);
   atomicAnd(&ctl->qmask[k >> 6], ~bit);
   ctl->any_push = 1;
 }
 
 // Direction thresholds of a session, in stream order with its levels.
-__global__ void k_ss_thresholds(MsCtl* ctl, u64 a_arcs, u64 b_arcs) {
+__global__ void k_ss_thresholds(MsCtl* ctl, double to_pull, double to_push) {
   if (threadIdx.x == 0) {
-    ctl->a_arcs = a_arcs;
-    ctl->b_arcs = b_arcs;
+    ctl->to_pull = to_pull;
+    ctl->to_push = to_push;
   }
 }
 
@@ -719,12 +731,14 @@ gsw_status wait_record(const LevelStats& st, int64_t d, hipStream_t s, const cha
 
 // Fills the staging control block for a traversal whose first level expands
 // the sources in `first` top-down.
-void ctl_reset(MsCtl* c, const u64* first, int W, int nslots, bool pull_ok, double a_arcs, double b_arcs) {
+void ctl_reset(MsCtl* c, const u64* first, int W, int nslots, bool pull_ok, int64_t arcs, double to_pull,
+               double to_push) {
   std::memset(c, 0, sizeof *c);
   for (int j = 0; j < W; ++j) c->pmask[j] = first ? first[j] : 0ull;
   for (int j = 0; j < W; ++j) c->any_push |= c->pmask[j] != 0ull;
-  c->a_arcs = (u64)a_arcs;
-  c->b_arcs = (u64)b_arcs;
+  c->to_pull = to_pull;
+  c->to_push = to_push;
+  c->arcs = (u64)arcs;
   c->pull_ok = pull_ok ? 1 : 0;
   c->nslots = nslots;
   c->W = W;
@@ -933,8 +947,8 @@ extern "C" {
 void gsw_msbfs_opts_default(gsw_msbfs_opts* o) {
   if (!o) return;
   std::memset(o, 0, sizeof *o);
-  o->push_to_pull = 0.002f;
-  o->pull_to_push = 0.0005f;
+  o->push_to_pull = 0.07f;
+  o->pull_to_push = 0.01f;
   o->graph = 1;
 }
 
@@ -966,9 +980,8 @@ gsw_status gsw_msbfs(const gsw_graph* cg, const int32_t* sources, int32_t n_sour
   std::memset(m->st.ring, 0, (size_t)kRing * kRecWords * sizeof(u64));
   std::vector<u64> first((size_t)W, 0ull);
   for (int32_t i = 0; i < n_sources; ++i) first[(size_t)(i >> 6)] |= 1ull << (i & 63);
-  const double nnz = (double)std::max<int64_t>(g->nnz, 1);
-  ctl_reset(m->st.h_ctl, first.data(), W, n_sources, g->symmetric != 0, o->push_to_pull * nnz,
-            o->pull_to_push * nnz);
+  ctl_reset(m->st.h_ctl, first.data(), W, n_sources, g->symmetric != 0, g->nnz, o->push_to_pull,
+            o->pull_to_push);
   GSW_HIP(hipMemcpyAsync(m->st.ctl, m->st.h_ctl, sizeof(MsCtl), hipMemcpyHostToDevice, s));
   GSW_HIP(hipMemcpyAsync(m->src, sources, (size_t)n_sources * sizeof(int32_t), hipMemcpyHostToDevice, s));
   {
@@ -1054,17 +1067,23 @@ struct gsw_session {
   int32_t *dist = nullptr, *start_d = nullptr, *seed = nullptr;  // seed: src[slots] then slot[slots]
   int32_t* take = nullptr;  // device staging for fetches into host memory
   LevelStats st;
-  // pinned staging for the per-boundary uploads: masks, then seed src/slot, then start
-  u64* h_masks = nullptr;
-  int32_t* h_seed = nullptr;
-  int32_t* h_start = nullptr;
+  // pinned staging for the per-boundary uploads (masks; seed src/slot; start
+  // of every slot), kStage sets used in turn: an async copy reads its set
+  // when it runs on the stream, and with up to two levels queued beyond the
+  // one the host waits for, a set is rewritten only after the level it fed
+  // has finished
+  static constexpr int kStage = 4;
+  u64* h_masks = nullptr;    // [kStage][2 kMaxWords]
+  int32_t* h_seed = nullptr;   // [kStage][2 slots]
+  int32_t* h_start = nullptr;  // [kStage][slots]
+  std::vector<int32_t> start32;  // start level of every slot, as uploaded
   std::vector<int32_t> source;
   std::vector<int64_t> start;  // level at which a running slot was seeded
   std::vector<int8_t> state;   // 0 free, 1 admitted (seeded at the next level boundary), 2 running, 3 finished
   std::vector<u64> freed;      // slots freed since the last boundary (made inert then)
   int64_t queued = 0;          // levels queued on the stream
   int64_t done = 0;            // levels whose record has been read
-  float push_to_pull = 0.002f, pull_to_push = 0.0005f;
+  float push_to_pull = 0.07f, pull_to_push = 0.01f;
   hipStream_t stream = nullptr;
   size_t bytes = 0;
   std::mutex mu;       // host state shared with admit / fetch / info
@@ -1141,16 +1160,18 @@ gsw_status gsw_session_create(const gsw_graph* cg, int32_t max_slots, gsw_sessio
   if (st == GSW_OK) {
     ss->bytes += ss->st.bytes;
     if (hipStreamCreateWithFlags(&ss->stream, hipStreamNonBlocking) != hipSuccess ||
-        hipHostMalloc((void**)&ss->h_masks, 2 * (size_t)kMaxWords * sizeof(u64), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&ss->h_seed, 2 * (size_t)max_slots * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&ss->h_start, (size_t)max_slots * sizeof(int32_t), hipHostMallocDefault) != hipSuccess)
+        hipHostMalloc((void**)&ss->h_masks, gsw_session::kStage * 2 * (size_t)kMaxWords * sizeof(u64),
+                      hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&ss->h_seed, gsw_session::kStage * 2 * (size_t)max_slots * sizeof(int32_t),
+                      hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&ss->h_start, gsw_session::kStage * (size_t)max_slots * sizeof(int32_t),
+                      hipHostMallocDefault) != hipSuccess)
       st = fail(GSW_EHIP, "session stream or pinned staging memory");
   }
   if (st == GSW_OK) {
     const hipStream_t s = ss->stream;
-    const double nnz = (double)std::max<int64_t>(g->nnz, 1);
-    ctl_reset(ss->st.h_ctl, nullptr, ss->W, max_slots, g->symmetric != 0, ss->push_to_pull * nnz,
-              ss->pull_to_push * nnz);
+    ctl_reset(ss->st.h_ctl, nullptr, ss->W, max_slots, g->symmetric != 0, g->nnz, ss->push_to_pull,
+              ss->pull_to_push);
     // every slot starts inert: visited everywhere, in no frontier, not reached
     if (hipMemsetAsync(ss->vis, 0xff, mb, s) != hipSuccess || hipMemsetAsync(ss->fr, 0, mb, s) != hipSuccess ||
         hipMemsetAsync(ss->frn, 0, mb, s) != hipSuccess || hipMemsetAsync(ss->nx, 0, mb, s) != hipSuccess ||
@@ -1164,7 +1185,7 @@ gsw_status gsw_session_create(const gsw_graph* cg, int32_t max_slots, gsw_sessio
     ss_free(ss);
     return st;
   }
-  std::memset(ss->h_start, 0, (size_t)max_slots * sizeof(int32_t));
+  ss->start32.assign((size_t)max_slots, 0);
   ss->source.assign((size_t)max_slots, -1);
   ss->start.assign((size_t)max_slots, 0);
   ss->state.assign((size_t)max_slots, 0);
@@ -1204,17 +1225,21 @@ gsw_status ss_queue_level(gsw_session* ss, bool* queued_one) {
   const int64_t n = g->n;
   int c = 0;
   bool any_mask = false, running = false;
+  const int si = (int)(ss->queued % gsw_session::kStage);
+  u64* h_masks = ss->h_masks + (size_t)si * 2 * kMaxWords;
+  int32_t* h_seed = ss->h_seed + (size_t)si * 2 * ss->slots;
+  int32_t* h_start = ss->h_start + (size_t)si * ss->slots;
   {
     std::lock_guard<std::mutex> lock(ss->mu);
-    u64* clr = ss->h_masks;
-    u64* set = ss->h_masks + kMaxWords;
+    u64* clr = h_masks;
+    u64* set = h_masks + kMaxWords;
     for (int j = 0; j < kMaxWords; ++j) clr[j] = set[j] = 0ull;
     for (int k = 0; k < ss->slots; ++k) {
       if (ss->state[(size_t)k] == 1) {
         clr[k >> 6] |= 1ull << (k & 63);
-        ss->h_seed[c] = ss->source[(size_t)k];
-        ss->h_seed[ss->slots + c] = k;
-        ss->h_start[k] = (int32_t)ss->queued;
+        h_seed[c] = ss->source[(size_t)k];
+        h_seed[ss->slots + c] = k;
+        ss->start32[(size_t)k] = (int32_t)ss->queued;
         ss->start[(size_t)k] = ss->queued;
         ss->state[(size_t)k] = 2;
         ++c;
@@ -1228,22 +1253,23 @@ gsw_status ss_queue_level(gsw_session* ss, bool* queued_one) {
     }
   }
   if (any_mask) {
-    GSW_HIP(hipMemcpyAsync(ss->masks, ss->h_masks, 2 * (size_t)kMaxWords * sizeof(u64), hipMemcpyHostToDevice, s));
+    GSW_HIP(hipMemcpyAsync(ss->masks, h_masks, 2 * (size_t)kMaxWords * sizeof(u64), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_ss_masks, dim3((unsigned)std::min<int64_t>(cdiv(n * W, kMsBlock), 65536)),
                        dim3(kMsBlock), 0, s, ss->vis, n, W, (const u64*)ss->masks,
                        (const u64*)(ss->masks + kMaxWords));
   }
   if (c > 0) {
-    GSW_HIP(hipMemcpyAsync(ss->seed, ss->h_seed, 2 * (size_t)ss->slots * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    GSW_HIP(hipMemcpyAsync(ss->start_d, ss->h_start, ss->slots * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    std::memcpy(h_start, ss->start32.data(), (size_t)ss->slots * sizeof(int32_t));
+    GSW_HIP(hipMemcpyAsync(ss->seed, h_seed, 2 * (size_t)ss->slots * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    GSW_HIP(hipMemcpyAsync(ss->start_d, h_start, ss->slots * sizeof(int32_t), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_ss_seed, dim3((unsigned)cdiv(c, 256)), dim3(256), 0, s, ss->vis, ss->fr, ss->fbm[0],
                        ss->dist, ss->st.ctl, n, W, (const int32_t*)ss->seed, (const int32_t*)(ss->seed + ss->slots),
                        c);
   }
   GSW_HIP(hipGetLastError());
   if (!running) {
-    // nothing to run; the pinned staging must not be rewritten before the
-    // copies above are done
+    // nothing to run: no level will be queued after these copies, so wait
+    // for them before the staging set can come round again
     if (any_mask) GSW_HIP(hipStreamSynchronize(s));
     return GSW_OK;
   }
@@ -1290,11 +1316,12 @@ gsw_status gsw_session_step(gsw_session* ss, int32_t max_levels, int32_t* finish
   // meanwhile join at the next boundary the host reaches.
   int32_t nfin = 0, run = 0;
   while (run < max_levels) {
-    if (ss->queued - ss->done < 2) {
+    while (ss->queued - ss->done < 2) {
       bool q = false;
       GSW_TRY(ss_queue_level(ss, &q));
-      if (!q && ss->queued == ss->done) break;  // nothing queued, nothing running
+      if (!q) break;
     }
+    if (ss->queued == ss->done) break;  // nothing queued, nothing running
     const volatile u64* rec = nullptr;
     GSW_TRY(wait_record(ss->st, ss->done, ss->stream, "session", &rec));
     const int64_t d = ss->done;
@@ -1366,10 +1393,9 @@ gsw_status gsw_session_set_thresholds(gsw_session* ss, float push_to_pull, float
   std::lock_guard<std::mutex> lock(ss->step_mu);
   ss->push_to_pull = push_to_pull;
   ss->pull_to_push = pull_to_push;
-  const double nnz = (double)std::max<int64_t>(ss->g->nnz, 1);
   GSW_HIP(hipSetDevice(ss->g->device));
-  hipLaunchKernelGGL(k_ss_thresholds, dim3(1), dim3(64), 0, ss->stream, ss->st.ctl,
-                     (u64)(push_to_pull * nnz), (u64)(pull_to_push * nnz));
+  hipLaunchKernelGGL(k_ss_thresholds, dim3(1), dim3(64), 0, ss->stream, ss->st.ctl, (double)push_to_pull,
+                     (double)pull_to_push);
   GSW_HIP(hipGetLastError());
   return GSW_OK;
 }

@@ -10,6 +10,12 @@ budget; an idle session (no slot in use) is destroyed to make room for
 another graph's.  Each session is stepped by its own worker thread on its own
 HIP stream, so the work of different graphs overlaps on the device.
 
+Optionally each graph also has a single-source lane: a query that finds its
+graph's session and lane both idle runs through the tree-switched
+single-source path (bitmap frontiers, fastest for one query), and everything
+that arrives meanwhile joins the session.  At low load queries see
+single-source latency; under load the session batches them.
+
 Latency of a query = completion time - arrival time.  Throughput = sum over
 queries of the undirected edges of the source's component / makespan.
 
@@ -89,6 +95,26 @@ def poisson_trace(rate_qps: float, duration_s: float, graphs, candidates, zipf_s
     return out
 
 
+class SoloLane:
+    """One tree-switched single-source BFS at a time on one graph, on its own
+    stream (the session of the same graph runs beside it)."""
+
+    def __init__(self, graph: gsw.Graph, tree=None):
+        import torch
+
+        from . import trees
+
+        self.stream = torch.cuda.Stream()
+        self.levels = torch.empty((1, graph.n), dtype=torch.int32, device="cuda")
+        self.runner = gsw.Runner(graph, self.levels, None, policy="tree",
+                                 tree=tree if tree is not None else trees.load_default(),
+                                 stream=self.stream.cuda_stream)
+
+    def run(self, source: int, keep: bool):
+        self.runner.run(int(source))
+        return self.levels[0].cpu().numpy() if keep else None
+
+
 class Server:
     """Continuous batching over resident graphs.
 
@@ -100,9 +126,14 @@ class Server:
     starts a new one when queries are admitted again."""
 
     def __init__(self, residents: dict, slots: int = 64, hbm_budget: int = None,
-                 levels_per_step: int = 1 << 20, keep_levels: bool = False, session_factory=None):
+                 levels_per_step: int = 1 << 20, keep_levels: bool = False, session_factory=None,
+                 solo: bool = False, solo_factory=None):
         self.res = residents
         self.new_session = session_factory or gsw.Session
+        self.solo = solo
+        self.new_solo = solo_factory or SoloLane
+        self._solo_lanes = {}       # graph -> (lane, single-thread executor)
+        self.solo_served = 0
         self.slots = slots
         self.budget = hbm_budget
         self.levels_per_step = levels_per_step
@@ -166,6 +197,16 @@ class Server:
             if run == 0 and not fin:
                 return
 
+    def _solo_run(self, name, lane, q, done_q, t0):
+        q.levels = lane.run(q.source, self.keep)
+        q.t_done = time.perf_counter() - t0
+        done_q.append(q)
+
+    def _solo_lane(self, name):
+        if name not in self._solo_lanes:
+            self._solo_lanes[name] = (self.new_solo(self.res[name].graph), ThreadPoolExecutor(max_workers=1))
+        return self._solo_lanes[name]
+
     def run(self, trace, timeout_s: float = 600.0):
         """Serves ``trace`` = [(t_arrival, graph, source)] in real time; returns
         the list of completed Query objects."""
@@ -174,6 +215,7 @@ class Server:
         slot_q = collections.defaultdict(dict)  # graph -> slot -> Query (admitted, not yet fetched)
         done_q = collections.deque()            # completed queries, appended by workers
         self._live = {}                         # graph -> worker future
+        solo_busy = {}                          # graph -> future of its single-source lane
         nxt = 0
         done = 0
         t0 = time.perf_counter()
@@ -193,10 +235,23 @@ class Server:
                 if fut.done():
                     del self._live[name]
                     fut.result()  # re-raises a worker's error
-            # admission: free slots of each graph's session (created under the budget)
+            for name, fut in list(solo_busy.items()):
+                if fut.done():
+                    del solo_busy[name]
+                    fut.result()
+            # admission: the single-source lane when the graph has nothing in
+            # flight, else free slots of the graph's session (created under the budget)
             for name, dq in pending.items():
                 if not dq:
                     continue
+                if self.solo and name not in solo_busy and not slot_q[name]:
+                    lane, ex = self._solo_lane(name)
+                    q = dq.popleft()
+                    q.t_admit = time.perf_counter() - t0
+                    solo_busy[name] = ex.submit(self._solo_run, name, lane, q, done_q, t0)
+                    self.solo_served += 1
+                    if not dq:
+                        continue
                 sess = self._ensure_session(name)
                 if sess is None:
                     continue
@@ -214,15 +269,18 @@ class Server:
                     self._live[name] = self.workers[name].submit(self._work, name, sess, slot_q[name], done_q, t0)
             if not done_q:
                 until_next = queries[nxt].t_arrival - now if nxt < len(queries) else 0.001
-                if self._live:
-                    futures_wait(list(self._live.values()), timeout=max(0.0, min(until_next, 0.0002)),
-                                 return_when=FIRST_COMPLETED)
+                busy = list(self._live.values()) + list(solo_busy.values())
+                if busy:
+                    futures_wait(busy, timeout=max(0.0, min(until_next, 0.0002)), return_when=FIRST_COMPLETED)
                 elif nxt < len(queries):
                     time.sleep(max(0.0, min(until_next, 0.001)))
-        for fut in self._live.values():
+        for fut in list(self._live.values()) + list(solo_busy.values()):
             fut.result()
         for name in list(self.sessions):
             self._close(name)
+        for lane, ex in self._solo_lanes.values():
+            ex.shutdown(wait=True)
+        self._solo_lanes = {}
         return queries
 
 

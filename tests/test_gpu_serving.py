@@ -146,7 +146,8 @@ def test_session_heavy_rows_all_push_and_default():
     G.close()
 
 
-def test_server_mix_equals_alone():
+@pytest.mark.parametrize("solo", [False, True])
+def test_server_mix_equals_alone(solo):
     names = ["rmat12", "grid", "er"]
     residents = {}
     cands = {}
@@ -157,8 +158,9 @@ def test_server_mix_equals_alone():
     # 96 queries arriving within 30 ms: they overlap on the device
     trace = serve.poisson_trace(3200.0, 0.03, names, cands, seed=5)
     assert len(trace) >= 64 and len({t[1] for t in trace}) == 3
-    srv = serve.Server(residents, slots=64, levels_per_step=3, keep_levels=True)
+    srv = serve.Server(residents, slots=64, levels_per_step=3, keep_levels=True, solo=solo)
     qs = srv.run(trace)
+    assert (srv.solo_served > 0) == solo
     assert all(q.t_done >= q.t_arrival for q in qs)
     for q in qs:
         g, G = resident(q.graph)

@@ -80,6 +80,17 @@ class StubSession:
         pass
 
 
+class StubSolo:
+    """Single-source lane answered by the oracle."""
+
+    def __init__(self, graph):
+        self.g = graph
+
+    def run(self, source, keep):
+        lv = oracle.levels(self.g.csr.offs, self.g.csr.cols, source)
+        return lv if keep else None
+
+
 def make(names):
     res, cands = {}, {}
     graphs = {"a": gg.rmat(9, 8, seed=1), "b": gg.grid(12, 9, 0.0, seed=1), "c": gg.erdos_renyi(700, 900, seed=2)}
@@ -102,6 +113,22 @@ def test_scheduler_answers_every_query_correctly():
         assert q.t_admit >= q.t_arrival and q.t_done >= q.t_admit
     st = serve.summarize(qs, res, "stub")
     assert st["queries"] == len(trace) and st["p99_ms"] >= st["p50_ms"]
+
+
+def test_solo_lane_takes_queries_of_idle_graphs():
+    res, cands = make(["a", "b", "c"])
+    # sparse arrivals: most queries find their graph idle; a burst at the end
+    # overlaps and goes to the sessions
+    trace = serve.poisson_trace(300.0, 0.05, ["a", "b", "c"], cands, seed=8)
+    trace += [(0.06, "a", int(cands["a"][i])) for i in range(12)]
+    srv = serve.Server(res, slots=4, keep_levels=True, session_factory=StubSession, solo=True,
+                       solo_factory=StubSolo)
+    qs = srv.run(trace, timeout_s=60)
+    assert len(qs) == len(trace)
+    for q in qs:
+        g = res[q.graph].graph.csr
+        assert np.array_equal(q.levels, oracle.levels(g.offs, g.cols, q.source))
+    assert 0 < srv.solo_served < len(trace)
 
 
 def test_budget_forces_eviction_and_queueing():
