@@ -219,7 +219,7 @@ def bench_serving(args, tree, log, preloaded):
                  ("rmat24", lambda: gg.rmat(24, 16, seed=11)), ("grid4096", lambda: gg.grid(4096, 4096, 0.0, seed=12)),
                  ("chunglu23", lambda: gg.chung_lu(1 << 23, 2.1, 20.0, seed=13)),
                  ("er24", lambda: gg.erdos_renyi(1 << 24, 4 << 24, seed=14))]
-        rates, duration, slots = (100, 500, 1000, 2000, 5000), 5.0, 64
+        rates, duration, slots = (100, 500, 1000, 2000, 5000, 12000), 5.0, 64
         budget = 48 << 30
     else:
         specs = [("rmat22", None), ("rmat20", lambda: gg.rmat(20, 16, seed=9)),

@@ -10,10 +10,12 @@ budget; an idle session (no slot in use) is destroyed to make room for
 another graph's.  Each session is stepped by its own worker thread on its own
 HIP stream, so the work of different graphs overlaps on the device.
 
-Optionally each graph also has a single-source lane: a query that finds its
-graph's session and lane both idle runs through the tree-switched
-single-source path (bitmap frontiers, fastest for one query), and everything
-that arrives meanwhile joins the session.  At low load queries see
+Optionally each graph also has a single-source lane running the
+tree-switched single-source path (bitmap frontiers, the fastest way to
+answer one query).  A waiting query takes the lane when it is free; the
+queue goes to the session once it is long enough that waiting for the lane
+one query at a time would take longer than a session query (both latencies
+are tracked as moving averages per graph).  At low load queries see
 single-source latency; under load the session batches them.
 
 Latency of a query = completion time - arrival time.  Throughput = sum over
@@ -45,6 +47,7 @@ class Query:
     t_admit: float = -1.0
     t_done: float = -1.0
     levels: object = None
+    path: str = ""  # "solo" or "session"
 
 
 @dataclass
@@ -193,6 +196,7 @@ class Server:
                 sess.fetch(k, out)
                 q.t_done = time.perf_counter() - t0
                 q.levels = out if self.keep else None
+                q.path = "session"
                 done_q.append(q)
             if run == 0 and not fin:
                 return
@@ -200,6 +204,7 @@ class Server:
     def _solo_run(self, name, lane, q, done_q, t0):
         q.levels = lane.run(q.source, self.keep)
         q.t_done = time.perf_counter() - t0
+        q.path = "solo"
         done_q.append(q)
 
     def _solo_lane(self, name):
@@ -216,6 +221,7 @@ class Server:
         done_q = collections.deque()            # completed queries, appended by workers
         self._live = {}                         # graph -> worker future
         solo_busy = {}                          # graph -> future of its single-source lane
+        est = collections.defaultdict(lambda: {"solo": 0.5e-3, "session": 1.0e-3})  # s, moving averages
         nxt = 0
         done = 0
         t0 = time.perf_counter()
@@ -229,7 +235,9 @@ class Server:
                 pending[queries[nxt].graph].append(queries[nxt])
                 nxt += 1
             while done_q:
-                done_q.popleft()
+                q = done_q.popleft()
+                e = est[q.graph]
+                e[q.path] = 0.8 * e[q.path] + 0.2 * (q.t_done - q.t_admit)
                 done += 1
             for name, fut in list(self._live.items()):
                 if fut.done():
@@ -244,13 +252,16 @@ class Server:
             for name, dq in pending.items():
                 if not dq:
                     continue
-                if self.solo and name not in solo_busy and not slot_q[name]:
-                    lane, ex = self._solo_lane(name)
-                    q = dq.popleft()
-                    q.t_admit = time.perf_counter() - t0
-                    solo_busy[name] = ex.submit(self._solo_run, name, lane, q, done_q, t0)
-                    self.solo_served += 1
-                    if not dq:
+                if self.solo:
+                    if name not in solo_busy:
+                        lane, ex = self._solo_lane(name)
+                        q = dq.popleft()
+                        q.t_admit = time.perf_counter() - t0
+                        solo_busy[name] = ex.submit(self._solo_run, name, lane, q, done_q, t0)
+                        self.solo_served += 1
+                    # the rest waits for the lane unless the session would be quicker
+                    e = est[name]
+                    if not dq or len(dq) * e["solo"] < e["session"]:
                         continue
                 sess = self._ensure_session(name)
                 if sess is None:
