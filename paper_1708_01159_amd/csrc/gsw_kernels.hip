@@ -38,6 +38,7 @@ constexpr int kScanTile = kBlock * kScanItems;   // entries per scan block
 constexpr int kEdgeTile = 1024;                  // push_edge: edges per tile
 constexpr int kEdgeWin = kEdgeTile;              // push_edge: queue entries staged per tile
 constexpr int kPullEager = 8;                    // pull: neighbours probed per lane up front
+constexpr int kPullChunk = 8;                    // pull: visited words (512 vertices) per wave step
 
 typedef unsigned long long u64;
 
@@ -437,84 +438,147 @@ __global__ void __launch_bounds__(kBlock) k_edge_expand(Args a, const int64_t* _
   stamp_end(a);
 }
 
-// ------------------------------------------- pull_bitmap (wave / 64-vertex word)
-// Each lane owns one vertex of the word.  An unvisited vertex looks for a
-// neighbour in the frontier bitmap, in row order, and stops at the first one
-// (Section III-A, vertex pull).  Phase 1: every lane probes the first
-// kPullEager neighbours of its row with independent loads (many misses in
-// flight instead of one dependent chain).  Phase 2: rows that are longer and
-// still unresolved are scanned by the whole wavefront, 64 neighbours per step,
-// one row at a time -- a high-degree row no longer stalls its wave for
-// deg(v) dependent steps.  Every word of the depth-(d+1) bitmap is written.
+// ------------------------------------------ pull_bitmap (wave / 512 vertices)
+// A wave takes kPullChunk visited words (512 vertices) at a time and puts
+// their unvisited vertices on its lanes, 64 per round, in vertex order: a
+// level with few unvisited vertices costs one short round per 512 vertices
+// instead of one dependent load chain per 64.  Each lane looks for a
+// neighbour of its vertex in the frontier bitmap, in row order, and stops at
+// the first one (Section III-A, vertex pull).  Phase 1: every lane probes the
+// first kPullEager neighbours of its row with independent loads (many misses
+// in flight instead of one dependent chain).  Phase 2: rows that are longer
+// and still unresolved are scanned by the whole wavefront, 64 neighbours per
+// step, one row at a time -- a high-degree row does not stall its wave for
+// deg(v) dependent steps.  Discoveries are ORed into the wave's own LDS copy
+// of its words' next-frontier bits; every word of the depth-(d+1) bitmap is
+// written.
+__device__ __forceinline__ u64 readlane64(u64 x, int i) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, i);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), i);
+  return ((u64)hi << 32) | lo;
+}
+
+// Position of the k-th (from 0) set bit of m; k < popcount(m).
+__device__ __forceinline__ int nth_set_bit(u64 m, int k) {
+  int pos = 0;
+  int c = __popc((unsigned)m);
+  if (k >= c) { k -= c; m >>= 32; pos += 32; }
+  c = __popc((unsigned)(m & 0xffffull));
+  if (k >= c) { k -= c; m >>= 16; pos += 16; }
+  c = __popc((unsigned)(m & 0xffull));
+  if (k >= c) { k -= c; m >>= 8; pos += 8; }
+  c = __popc((unsigned)(m & 0xfull));
+  if (k >= c) { k -= c; m >>= 4; pos += 4; }
+  c = __popc((unsigned)(m & 0x3ull));
+  if (k >= c) { k -= c; m >>= 2; pos += 2; }
+  if (k >= (int)(m & 1ull)) pos += 1;
+  return pos;
+}
+
 __global__ void __launch_bounds__(kBlock) k_pull(Args a) {
   stamp_begin(a);
   __shared__ Stage st;
+  __shared__ u64 s_found[kWaves][kPullChunk];
   clear_ahead(a);
   stage_init(st);
   const int lane = lane_id();
+  u64* found_w = s_found[threadIdx.x >> 6];
   const int64_t nwaves = (int64_t)gridDim.x * kWaves;
-  int64_t w = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
-  u64 next_seen = w < a.nw ? a.vis[w] : ~0ull;
-  for (; w < a.nw; w += nwaves) {
-    const u64 seen = next_seen;
-    // the next word's visited mask is fetched while this word is worked on
-    if (w + nwaves < a.nw) next_seen = a.vis[w + nwaves];
-    const u64 todo = ~seen;
-    if (todo == 0ull) {  // whole wave
-      if (lane == 0) a.nx[w] = 0ull;
+  const int64_t nchunks = (a.nw + kPullChunk - 1) / kPullChunk;
+  for (int64_t c = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6; c < nchunks; c += nwaves) {
+    const int64_t w0 = c * kPullChunk;
+    const bool word_lane = lane < kPullChunk && w0 + lane < a.nw;
+    const u64 seen = word_lane ? a.vis[w0 + lane] : ~0ull;
+    // inclusive prefix of the unvisited counts of the chunk's words (lanes 0..7)
+    int inc = __popcll(~seen);
+#pragma unroll
+    for (int off = 1; off < kPullChunk; off <<= 1) {
+      const int y = __shfl_up(inc, off);
+      if (lane >= off) inc += y;
+    }
+    const int total = __builtin_amdgcn_readlane(inc, kPullChunk - 1);
+    if (word_lane) found_w[lane] = 0ull;
+    if (total == 0) {
+      if (word_lane) a.nx[w0 + lane] = 0ull;
       continue;
     }
-    const int32_t v = (int32_t)(w * 64 + lane);
-    const bool mine = (todo >> lane) & 1ull;
-    int64_t beg = 0, end = 0;
-    if (mine) {
-      beg = a.offs[v];
-      end = a.offs[v + 1];
+    u64 todo[kPullChunk];
+    int first[kPullChunk];  // compacted index of each word's first unvisited vertex
+#pragma unroll
+    for (int i = 0; i < kPullChunk; ++i) {
+      todo[i] = ~readlane64(seen, i);
+      first[i] = __builtin_amdgcn_readlane(inc, i) - __popcll(todo[i]);
     }
-    int32_t u[kPullEager];
-    u64 fw[kPullEager];
+    for (int r0 = 0; r0 < total; r0 += 64) {
+      const int k = r0 + lane;
+      const bool mine = k < total;
+      int kw = 0;
 #pragma unroll
-    for (int k = 0; k < kPullEager; ++k) u[k] = beg + k < end ? a.cols[beg + k] : -1;
+      for (int i = 1; i < kPullChunk; ++i) kw += k >= first[i] ? 1 : 0;
+      u64 t = 0ull;
+      int f0 = 0;
 #pragma unroll
-    for (int k = 0; k < kPullEager; ++k) fw[k] = u[k] >= 0 ? a.fr[u[k] >> 6] : 0ull;
-    int32_t par = -1;
-#pragma unroll
-    for (int k = kPullEager - 1; k >= 0; --k)
-      if (u[k] >= 0 && ((fw[k] >> (u[k] & 63)) & 1ull)) par = u[k];
-    u64 rest = __ballot(mine && par < 0 && end - beg > kPullEager);
-    while (rest != 0ull) {
-      const int owner = __ffsll((long long)rest) - 1;
-      rest &= rest - 1ull;
-      const int64_t lo = __shfl(beg, owner) + kPullEager;
-      const int64_t hi = __shfl(end, owner);
-      int32_t hit = -1;
-      for (int64_t c = lo; c < hi; c += 64) {
-        const int64_t e = c + lane;
-        int32_t x = -1;
-        bool h = false;
-        if (e < hi) {
-          x = a.cols[e];
-          h = (a.fr[x >> 6] >> (x & 63)) & 1ull;
+      for (int i = 0; i < kPullChunk; ++i)
+        if (i == kw) {
+          t = todo[i];
+          f0 = first[i];
         }
-        const u64 hm = __ballot(h);
-        if (hm != 0ull) {
-          hit = __shfl(x, __ffsll((long long)hm) - 1);
-          break;
-        }
+      const int bit = mine ? nth_set_bit(t, k - f0) : 0;
+      const int32_t v = (int32_t)((w0 + kw) * 64 + bit);
+      int64_t beg = 0, end = 0;
+      if (mine) {
+        beg = a.offs[v];
+        end = a.offs[v + 1];
       }
-      if (lane == owner) par = hit;
+      int32_t u[kPullEager];
+      u64 fw[kPullEager];
+#pragma unroll
+      for (int q = 0; q < kPullEager; ++q) u[q] = beg + q < end ? a.cols[beg + q] : -1;
+#pragma unroll
+      for (int q = 0; q < kPullEager; ++q) fw[q] = u[q] >= 0 ? a.fr[u[q] >> 6] : 0ull;
+      int32_t par = -1;
+#pragma unroll
+      for (int q = kPullEager - 1; q >= 0; --q)
+        if (u[q] >= 0 && ((fw[q] >> (u[q] & 63)) & 1ull)) par = u[q];
+      u64 rest = __ballot(mine && par < 0 && end - beg > kPullEager);
+      while (rest != 0ull) {
+        const int owner = __ffsll((long long)rest) - 1;
+        rest &= rest - 1ull;
+        const int64_t lo = __shfl(beg, owner) + kPullEager;
+        const int64_t hi = __shfl(end, owner);
+        int32_t hit = -1;
+        for (int64_t cc = lo; cc < hi; cc += 64) {
+          const int64_t e = cc + lane;
+          int32_t x = -1;
+          bool h = false;
+          if (e < hi) {
+            x = a.cols[e];
+            h = (a.fr[x >> 6] >> (x & 63)) & 1ull;
+          }
+          const u64 hm = __ballot(h);
+          if (hm != 0ull) {
+            hit = __shfl(x, __ffsll((long long)hm) - 1);
+            break;
+          }
+        }
+        if (lane == owner) par = hit;
+      }
+      const bool found = par >= 0;
+      if (found) {
+        a.level[v] = a.d + 1;
+        if (a.parent) a.parent[v] = par;
+        atomicOr(&found_w[kw], 1ull << bit);
+      }
+      stage_push(st, a, found, v);
     }
-    const bool found = par >= 0;
-    const u64 fm = __ballot(found);
-    if (found) {
-      a.level[v] = a.d + 1;
-      if (a.parent) a.parent[v] = par;
+    // the LDS words are this wave's alone and its LDS operations complete in
+    // order; the barrier only keeps the compiler from moving the reads up
+    __builtin_amdgcn_wave_barrier();
+    if (word_lane) {
+      const u64 fm = found_w[lane];
+      a.nx[w0 + lane] = fm;
+      if (fm) a.vis[w0 + lane] = seen | fm;  // this wave is the word's only writer in a pull level
     }
-    if (lane == 0) {
-      a.nx[w] = fm;
-      if (fm) a.vis[w] = seen | fm;  // this wave is the word's only writer in a pull level
-    }
-    stage_push(st, a, found, v);
   }
   stage_flush(st, a);
   stamp_end(a);
@@ -727,7 +791,7 @@ gsw_status launch_level(const gsw_graph* g, int kernel, const LevelLaunch& l, hi
       break;
     }
     case GSW_K_PULL_BITMAP:
-      hipLaunchKernelGGL(k_pull, dim3(persistent_grid(cdiv(a.nw, kWaves))), dim3(kBlock), 0, s, a);
+      hipLaunchKernelGGL(k_pull, dim3(persistent_grid(cdiv(cdiv(a.nw, kPullChunk), kWaves))), dim3(kBlock), 0, s, a);
       break;
     case GSW_K_VERTEX_SCAN:
       hipLaunchKernelGGL(k_vertex_scan, dim3(persistent_grid(cdiv(a.n, kBlock))), dim3(kBlock), 0,

@@ -20,7 +20,9 @@ vertices, nw = ceil(n/64) bitmap words):
                  (16 row offsets + p_v*(4 column + 8 frontier word))
                  + 16 per word holding a discovery (visited and next words),
                  where p_v counts the neighbours read up to the first one in
-                 the frontier (all of them when none is).
+                 the frontier (all of them when none is).  On a symmetric
+                 graph degree-0 vertices start visited (the search marks them
+                 at init), so they cost only their visited bit.
 """
 from __future__ import annotations
 
@@ -47,12 +49,16 @@ def level_sizes(offs, level):
     return nf, ef
 
 
-def pull_probes(offs, cols, level, d: int):
-    """(sum of p_v, unvisited count, words with a discovery) for a pull at level d."""
+def pull_probes(offs, cols, level, d: int, skip_isolated: bool = True):
+    """(sum of p_v, unvisited count, words with a discovery) for a pull at
+    level d; degree-0 vertices are left out when ``skip_isolated``."""
     offs = np.asarray(offs, dtype=np.int64)
     lv = np.asarray(level)
     n = lv.shape[0]
-    unv = np.flatnonzero((lv == -1) | (lv > d))
+    unvisited = (lv == -1) | (lv > d)
+    if skip_isolated:
+        unvisited &= offs[1:] > offs[:-1]
+    unv = np.flatnonzero(unvisited)
     if unv.shape[0] == 0:
         return 0, 0, 0
     deg = offs[unv + 1] - offs[unv]
@@ -75,8 +81,9 @@ def pull_probes(offs, cols, level, d: int):
     return int(probes.sum()), int(unv.shape[0]), int(found_words)
 
 
-def level_bytes(kernel: int, offs, cols, level, d: int, nf=None, ef=None) -> int:
-    """Algorithmic bytes of running ``kernel`` at level d (see module doc)."""
+def level_bytes(kernel: int, offs, cols, level, d: int, nf=None, ef=None, skip_isolated: bool = True) -> int:
+    """Algorithmic bytes of running ``kernel`` at level d (see module doc);
+    ``skip_isolated``: the graph is symmetric, degree-0 vertices start visited."""
     offs = np.asarray(offs, dtype=np.int64)
     lv = np.asarray(level)
     n = lv.shape[0]
@@ -89,7 +96,7 @@ def level_bytes(kernel: int, offs, cols, level, d: int, nf=None, ef=None) -> int
     n_x = int(nf[d + 1]) if d + 1 < nf.shape[0] else 0
     b = nw * 8 + n_x * 12
     if kernel == PULL:
-        p, nu, words = pull_probes(offs, cols, lv, d)
+        p, nu, words = pull_probes(offs, cols, lv, d, skip_isolated)
         return b + nw * 8 + nu * 16 + p * 12 + words * 16
     b += e_f * 12 + n_x * 8
     if kernel in PUSH_FAMILY:
