@@ -1,7 +1,11 @@
-// Host-driven level loop: per level, read the new frontier size, build the
-// feature vector, pick the next kernel (tree, fixed or scheduled policy) and
-// launch it.  Also the per-level profiler that measures every kernel from the
-// same saved state (the training data of the decision tree).
+// Level loop of the single-source BFS.  The device picks each next level's
+// kernel itself (the last workgroup of a level applies the policy and
+// writes the level control block) and posts a record per level to a ring in
+// mapped host memory; the host keeps a few level launches queued, reads the
+// records in order for the trace and the end of the search, and launches the
+// three push_edge kernels itself for the levels the device gives to
+// push_edge.  Also the per-level profiler that measures every kernel from
+// the same saved state (the training data of the decision tree).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -13,11 +17,19 @@
 namespace gsw {
 namespace {
 
+// Level launches queued beyond the last level whose record the host has
+// read; each runs one level or, when the device has named push_edge or
+// ended the search, nothing.
+constexpr int kAhead = 2;
+
 struct Policy {
   const gsw_bfs_opts* o;
   bool symmetric;
-  // Kernel for level d; *flags gets bit0 when the tree leaf was undecided,
-  // bit1 when a pull choice was replaced on a non-symmetric graph.
+  bool has_origin;
+  // Kernel for level d on the host (only level 0 is chosen here); the device
+  // applies the same rules to every later level.  *flags gets bit0 when the
+  // tree leaf was undecided, bit1 when a pull choice was replaced on a
+  // non-symmetric graph.
   int choose(const gsw_graph* g, int32_t d, int64_t nf, int64_t disc, int prev, int32_t* flags) const {
     *flags = 0;
     int k = GSW_DEFAULT_KERNEL;
@@ -42,88 +54,10 @@ struct Policy {
       k = GSW_DEFAULT_KERNEL;
       *flags |= 2;
     }
+    if (k == GSW_K_EDGE_SCAN && !has_origin) k = GSW_DEFAULT_KERNEL;
     return k;
   }
 };
-
-// Buffers of level d: queue q[d&1] with counter slot d&3 in, q[(d+1)&1] and
-// slot (d+1)&3 out, slot (d+2)&3 zeroed for the level after next; frontier
-// bitmap bm[d&1] in (pull), bm[(d+1)&1] out (pull).
-LevelLaunch level_args(const gsw_graph* g, int32_t* lv, int32_t* pa, int32_t d, uint32_t nf) {
-  const Workspace& w = g->ws;
-  LevelLaunch l;
-  l.offs = g->offs;
-  l.cols = g->cols;
-  l.origin = g->origin;
-  l.level = lv;
-  l.parent = pa;
-  l.vis = w.vis;
-  l.fr = w.bm[d & 1];
-  l.nx = w.bm[(d + 1) & 1];
-  l.qin = w.q[d & 1];
-  l.cin = w.ctr + (size_t)(d & 3) * kCtrSlot;
-  l.qout = w.q[(d + 1) & 1];
-  l.cout = w.ctr + (size_t)((d + 1) & 3) * kCtrSlot;
-  l.cclr = w.ctr + (size_t)((d + 2) & 3) * kCtrSlot;
-  l.tst = nullptr;
-  l.n = g->n;
-  l.nw = w.nw;
-  l.nnz = g->nnz;
-  l.n_in = nf;
-  l.d = d;
-  return l;
-}
-
-// Size of the depth-(d+1) queue (sum over its segments); bins[] receives the
-// per-segment counts when non-null.
-gsw_status read_next(const gsw_graph* g, int32_t d, hipStream_t s, int64_t* nn, uint32_t* bins) {
-  const Workspace& w = g->ws;
-  GSW_HIP(hipMemcpyAsync(w.h_ctr, w.ctr + (size_t)((d + 1) & 3) * kCtrSlot,
-                         kCtrSlot * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  GSW_HIP(hipStreamSynchronize(s));
-  int64_t t = 0;
-  for (int b = 0; b < kQueueBins; ++b) {
-    t += w.h_ctr[b * kCtrStride];
-    if (bins) bins[b] = w.h_ctr[b * kCtrStride];
-  }
-  *nn = t;
-  return GSW_OK;
-}
-
-// Waits until the device has stored level d's next-frontier size in host
-// memory (k_finalize).  Polls the stream for errors now and then so a failed
-// launch cannot leave the host spinning.
-gsw_status wait_next(const gsw_graph* g, int32_t d, hipStream_t s, int64_t* nn) {
-  volatile uint32_t* f = g->ws.h_flag + (size_t)(d % kFlagSlots) * 64;
-  for (uint64_t it = 0;; ++it) {
-    const uint32_t v = *f;
-    if (v != kNotReady) {
-      *nn = (int64_t)v;
-      return GSW_OK;
-    }
-    if ((it & 4095u) == 4095u) {
-      const hipError_t e = hipStreamQuery(s);
-      if (e == hipSuccess) {
-        const uint32_t v2 = *f;
-        if (v2 != kNotReady) {
-          *nn = (int64_t)v2;
-          return GSW_OK;
-        }
-        return fail(GSW_EHIP, "level %d finished without reporting its frontier size", d);
-      }
-      if (e != hipErrorNotReady) return fail(GSW_EHIP, "level %d: %s", d, hipGetErrorString(e));
-    }
-    __builtin_ia32_pause();
-  }
-}
-
-// One level: the frontier bitmap is rebuilt first when pull follows a
-// top-down level (its input bitmap is otherwise stale).
-gsw_status run_level(const gsw_graph* g, int k, const LevelLaunch& l, bool fr_valid, hipStream_t s) {
-  if (kernel_is_pull(k) && !fr_valid)
-    GSW_TRY(launch_frontier_bitmap(g, l.level, l.d, const_cast<unsigned long long*>(l.fr), s));
-  return launch_level(g, k, l, s);
-}
 
 gsw_status check_kernel(const gsw_graph* g, int k) {
   if (k < 0 || k >= GSW_N_KERNELS) return fail(GSW_EINVAL, "unknown kernel id %d", k);
@@ -132,67 +66,166 @@ gsw_status check_kernel(const gsw_graph* g, int k) {
   return GSW_OK;
 }
 
-gsw_status run_one(gsw_graph* g, const Policy& pol, int32_t src_idx, int32_t src, int32_t* lv,
-                   int32_t* pa, gsw_level_trace* trace, int32_t trace_cap, int32_t* rows,
-                   hipStream_t s) {
+// Device copy of the tree, uploaded once per (workspace, tree).
+gsw_status ensure_tree(gsw_graph* g, const gsw_tree* t) {
+  Workspace& w = g->ws;
+  if (w.tree_id == t->id) return GSW_OK;
+  if (w.tree_cap < t->n_nodes) {
+    if (w.d_tree) (void)hipFree(w.d_tree);
+    if (w.d_thr) (void)hipFree(w.d_thr);
+    w.d_tree = nullptr;
+    w.d_thr = nullptr;
+    w.tree_cap = 0;
+    if (hipMalloc((void**)&w.d_tree, (size_t)t->n_nodes * 4 * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc((void**)&w.d_thr, (size_t)t->n_nodes * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(GSW_ENOMEM, "hipMalloc for the device copy of the tree failed");
+    }
+    w.tree_cap = t->n_nodes;
+  }
+  std::vector<int32_t> nodes((size_t)t->n_nodes * 4);
+  for (int32_t i = 0; i < t->n_nodes; ++i) {
+    nodes[(size_t)i * 4 + 0] = t->feature[(size_t)i];
+    nodes[(size_t)i * 4 + 1] = t->left[(size_t)i];
+    nodes[(size_t)i * 4 + 2] = t->right[(size_t)i];
+    nodes[(size_t)i * 4 + 3] = t->leaf_kernel[(size_t)i];
+  }
+  GSW_HIP(hipMemcpy(w.d_tree, nodes.data(), nodes.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  GSW_HIP(hipMemcpy(w.d_thr, t->threshold.data(), (size_t)t->n_nodes * sizeof(double), hipMemcpyHostToDevice));
+  w.tree_id = t->id;
+  return GSW_OK;
+}
+
+// Device copy of a schedule; re-uploaded only when its contents change.
+gsw_status ensure_schedule(gsw_graph* g, const int32_t* sched, int32_t len) {
+  Workspace& w = g->ws;
+  std::vector<int32_t>* cached = &w.sched_host;
+  if (w.d_sched && (int32_t)cached->size() == len && std::equal(cached->begin(), cached->end(), sched))
+    return GSW_OK;
+  if (w.sched_cap < len) {
+    if (w.d_sched) (void)hipFree(w.d_sched);
+    w.d_sched = nullptr;
+    w.sched_cap = 0;
+    if (hipMalloc((void**)&w.d_sched, (size_t)len * sizeof(int32_t)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(GSW_ENOMEM, "hipMalloc for the device copy of the schedule failed");
+    }
+    w.sched_cap = len;
+  }
+  GSW_HIP(hipMemcpy(w.d_sched, sched, (size_t)len * sizeof(int32_t), hipMemcpyHostToDevice));
+  cached->assign(sched, sched + len);
+  return GSW_OK;
+}
+
+BfsPolicy device_policy(const gsw_graph* g, const gsw_bfs_opts* o, bool has_origin) {
+  BfsPolicy p;
+  std::memset(&p, 0, sizeof p);
+  p.policy = o->policy;
+  p.fixed = o->fixed_kernel;
+  p.sched_len = o->policy == GSW_POLICY_SCHEDULE ? o->schedule_len : 0;
+  p.symmetric = g->symmetric != 0;
+  p.has_origin = has_origin ? 1 : 0;
+  p.sched = g->ws.d_sched;
+  p.t_node = g->ws.d_tree;
+  p.t_thr = g->ws.d_thr;
+  p.t_nodes = o->policy == GSW_POLICY_TREE && o->tree ? o->tree->n_nodes : 0;
+  p.feat[0] = (double)g->n;
+  p.feat[1] = (double)g->nnz;
+  for (int i = 0; i < 6; ++i) p.feat[2 + i] = g->deg_stats[i];
+  return p;
+}
+
+BfsBase make_base(const gsw_graph* g, int32_t* lv, int32_t* pa, bool timed) {
+  const Workspace& w = g->ws;
+  BfsBase b;
+  std::memset(&b, 0, sizeof b);
+  b.offs = g->offs;
+  b.cols = g->cols;
+  b.origin = g->origin;
+  b.level = lv;
+  b.parent = pa;
+  b.vis = w.vis;
+  for (int i = 0; i < 3; ++i) b.bm[i] = w.bm[i];
+  b.q[0] = w.q[0];
+  b.q[1] = w.q[1];
+  b.ctr = w.ctr;
+  b.done = w.done;
+  b.ring = w.d_ring;
+  b.ctl = w.ctl;
+  b.n = g->n;
+  b.nw = w.nw;
+  b.nnz = g->nnz;
+  b.timed = timed ? 1 : 0;
+  b.grid_max = level_kernel_grid(g->n, w.nw);
+  return b;
+}
+
+// Waits until level d's record is in the ring.  Polls the stream for errors
+// now and then so a failed launch cannot leave the host spinning.
+gsw_status wait_record(const gsw_graph* g, int64_t d, hipStream_t s, const volatile unsigned long long** rec) {
+  const volatile unsigned long long* r = g->ws.ring + (size_t)(d % kBfsRing) * kBfsRec;
+  for (uint64_t it = 0;; ++it) {
+    if (r[kRecSeq] == (unsigned long long)d + 1ull) {
+      *rec = r;
+      return GSW_OK;
+    }
+    if ((it & 4095u) == 4095u) {
+      const hipError_t e = hipStreamQuery(s);
+      if (e == hipSuccess) {
+        if (r[kRecSeq] == (unsigned long long)d + 1ull) continue;
+        return fail(GSW_EHIP, "level %lld finished without posting its record", (long long)d);
+      }
+      if (e != hipErrorNotReady) return fail(GSW_EHIP, "level %lld: %s", (long long)d, hipGetErrorString(e));
+    }
+    __builtin_ia32_pause();
+  }
+}
+
+gsw_status run_levels(gsw_graph* g, const Policy& pol, const BfsPolicy& dp, int32_t src_idx, int32_t src,
+                      int32_t* lv, int32_t* pa, gsw_level_trace* trace, int32_t trace_cap, int32_t* rows,
+                      hipStream_t s) {
   Workspace& w = g->ws;
   const gsw_bfs_opts* o = pol.o;
-  GSW_TRY(launch_init(g, lv, pa, src, s));
-  int64_t nf = 1, disc = 1;
-  int prev = GSW_DEFAULT_KERNEL;
-  bool fr_valid = true;  // init wrote the depth-0 bitmap
-  const int32_t row0 = *rows;
-  int32_t timed = 0;  // levels bracketed by events (read after the last level)
-  for (int32_t d = 0;; ++d) {
-    int32_t flags = 0;
-    const int k = pol.choose(g, d, nf, disc, prev, &flags);
-    if (k == GSW_K_EDGE_SCAN) GSW_TRY(ensure_origin(g));
-    const LevelLaunch l = level_args(g, lv, pa, d, (uint32_t)nf);
-    const size_t slot = (size_t)(d % kFlagSlots) * 64;
-    w.h_flag[slot] = kNotReady;
-    const bool timing = o->time_levels && d < kMaxTimedLevels && *rows < trace_cap;
-    // the bitmap rebuild before a pull that follows a top-down level stays
-    // outside the timed bracket: trace ms is the expansion kernel(s) only
-    if (kernel_is_pull(k) && !fr_valid)
-      GSW_TRY(launch_frontier_bitmap(g, l.level, l.d, const_cast<unsigned long long*>(l.fr), s));
-    LevelLaunch lt = l;
-    if (timing) {
-      lt.tst = w.tst;
-      timed = d + 1;
+  const bool timed = o->time_levels != 0;
+  std::memset(w.ring, 0, (size_t)kBfsRing * kBfsRec * sizeof(unsigned long long));
+  int32_t flags0 = 0;
+  const int k0 = pol.choose(g, 0, 1, 1, GSW_DEFAULT_KERNEL, &flags0);
+  const BfsBase b = make_base(g, lv, pa, timed);
+  GSW_TRY(launch_init(g, b, src, k0, flags0, s));
+  int ahead = 0;
+  if (k0 == GSW_K_PUSH_EDGE) GSW_TRY(launch_level_edge(g, b, dp, 0, 1u, false, s));
+  for (int64_t d = 0;; ++d) {
+    while (ahead < kAhead) {
+      GSW_TRY(launch_level_auto(g, b, dp, s));
+      ++ahead;
     }
-    GSW_TRY(launch_level(g, k, lt, s));
-    GSW_TRY(launch_finalize(l.cout, w.d_flag + slot, timing ? w.tst : nullptr,
-                            timing ? w.lvl_ticks + d : nullptr, s));
-    fr_valid = kernel_is_pull(k);
-    int64_t nn = 0;
-    GSW_TRY(wait_next(g, d, s, &nn));
+    const volatile unsigned long long* r = nullptr;
+    GSW_TRY(wait_record(g, d, s, &r));
+    const int k = (int)(long long)r[kRecKernel];
+    const int64_t nn = (int64_t)r[kRecNext];
+    const int nk = (int)(long long)r[kRecNextKernel];
     if (trace && *rows < trace_cap) {
       gsw_level_trace& t = trace[*rows];
       t.source_idx = src_idx;
-      t.level = d;
+      t.level = (int32_t)d;
       t.kernel = k;
-      t.flags = flags;
-      t.n_frontier = nf;
-      t.discovered = disc;
+      t.flags = (int32_t)r[kRecFlags];
+      t.n_frontier = (int64_t)r[kRecNf];
+      t.discovered = (int64_t)r[kRecDisc];
       t.n_next = nn;
-      t.ms = -1.0f;
+      t.ms = timed ? (float)((double)r[kRecTicks] * w.tick_ms) : -1.0f;
       t.reserved = 0;
     }
     ++*rows;
+    if (k != GSW_K_PUSH_EDGE) --ahead;  // the oldest queued level launch ran this level
     if (nn == 0) break;
-    nf = nn;
-    disc += nn;
-    prev = k;
+    if (nk == GSW_K_PUSH_EDGE) {
+      // the queued launches will find push_edge named and do nothing
+      ahead = 0;
+      GSW_TRY(launch_level_edge(g, b, dp, (int32_t)(d + 1), (uint32_t)nn, false, s));
+    }
   }
   if (o->canonical_parents && pa) GSW_TRY(launch_canonical_parents(g, lv, pa, s));
-  GSW_HIP(hipStreamSynchronize(s));
-  if (timed > 0 && trace) {
-    GSW_HIP(hipMemcpyAsync(w.h_ticks, w.lvl_ticks, (size_t)timed * sizeof(unsigned long long),
-                           hipMemcpyDeviceToHost, s));
-    GSW_HIP(hipStreamSynchronize(s));
-    for (int32_t d = 0; d < timed && row0 + d < trace_cap; ++d)
-      trace[row0 + d].ms = (float)((double)w.h_ticks[d] * w.tick_ms);
-  }
   return GSW_OK;
 }
 
@@ -211,6 +244,22 @@ gsw_status dalloc(DevBuf& b, size_t bytes) {
     return fail(GSW_ENOMEM, "hipMalloc(%zu) failed", bytes);
   }
   return GSW_OK;
+}
+
+// Whether the policy can ever name edge_scan (it needs the origin array).
+bool may_pick_edge_scan(const gsw_bfs_opts* o) {
+  switch (o->policy) {
+    case GSW_POLICY_FIXED:
+      return o->fixed_kernel == GSW_K_EDGE_SCAN;
+    case GSW_POLICY_SCHEDULE:
+      for (int32_t i = 0; i < o->schedule_len; ++i)
+        if (o->schedule[i] == GSW_K_EDGE_SCAN) return true;
+      return false;
+    default:
+      for (int32_t k : o->tree->class_kernel)
+        if (k == GSW_K_EDGE_SCAN) return true;
+      return false;
+  }
 }
 
 }  // namespace
@@ -251,23 +300,32 @@ gsw_status gsw_bfs(const gsw_graph* cg, const int32_t* sources, int32_t n_source
   std::lock_guard<std::mutex> lock(g->mu);
   GSW_HIP(hipSetDevice(g->device));
   GSW_TRY(ensure_workspace(g));
+  if (may_pick_edge_scan(o)) GSW_TRY(ensure_origin(g));
+  if (o->policy == GSW_POLICY_TREE) GSW_TRY(ensure_tree(g, o->tree));
+  if (o->policy == GSW_POLICY_SCHEDULE) GSW_TRY(ensure_schedule(g, o->schedule, o->schedule_len));
   const hipStream_t s = pick_stream(g, o->stream);
-  const Policy pol{o, g->symmetric != 0};
+  const bool has_origin = g->origin != nullptr || g->nnz == 0;
+  const Policy pol{o, g->symmetric != 0, has_origin};
+  const BfsPolicy dp = device_policy(g, o, has_origin);
   const int64_t n = g->n;
   int32_t rows = 0;
   for (int32_t i = 0; i < n_sources; ++i) {
     int32_t* lv = o->device_ptrs ? levels + (size_t)i * n : g->ws.lvl_tmp;
     int32_t* pa = parents ? (o->device_ptrs ? parents + (size_t)i * n : g->ws.par_tmp) : nullptr;
-    GSW_TRY(run_one(g, pol, i, sources[i], lv, pa, trace, trace_cap, &rows, s));
+    const gsw_status st = run_levels(g, pol, dp, i, sources[i], lv, pa, trace, trace_cap, &rows, s);
+    if (st != GSW_OK) {
+      (void)hipStreamSynchronize(s);
+      return st;
+    }
     if (!o->device_ptrs) {
       GSW_HIP(hipMemcpyAsync(levels + (size_t)i * n, lv, (size_t)n * sizeof(int32_t),
                              hipMemcpyDeviceToHost, s));
       if (pa)
         GSW_HIP(hipMemcpyAsync(parents + (size_t)i * n, pa, (size_t)n * sizeof(int32_t),
                                hipMemcpyDeviceToHost, s));
-      GSW_HIP(hipStreamSynchronize(s));
     }
   }
+  GSW_HIP(hipStreamSynchronize(s));
   if (trace_len) *trace_len = rows;
   return GSW_OK;
 }
@@ -299,24 +357,35 @@ gsw_status gsw_bfs_profile(const gsw_graph* cg, int32_t source, const int32_t* k
   GSW_TRY(dalloc(s_lv, vb));
   GSW_TRY(dalloc(s_pa, vb));
   GSW_TRY(dalloc(s_vis, bb));
-  GSW_TRY(dalloc(s_bm, 2 * bb));
+  GSW_TRY(dalloc(s_bm, 3 * bb));
   GSW_TRY(dalloc(s_q, (size_t)kQueueBins * vb));
   GSW_TRY(dalloc(s_ctr, cb));
   int32_t* lv = w.lvl_tmp;
   int32_t* pa = w.par_tmp;
-  GSW_TRY(launch_init(g, lv, pa, source, s));
+  // every level is run with a named kernel: a fixed policy whose choices the
+  // profiler overwrites in the control block before each run
+  gsw_bfs_opts fo;
+  gsw_bfs_opts_default(&fo);
+  fo.policy = GSW_POLICY_FIXED;
+  fo.fixed_kernel = GSW_DEFAULT_KERNEL;
+  const bool has_origin = g->origin != nullptr || g->nnz == 0;
+  const BfsPolicy dp = device_policy(g, &fo, has_origin);
+  const BfsBase b = make_base(g, lv, pa, false);
+  std::memset(w.ring, 0, (size_t)kBfsRing * kBfsRec * sizeof(unsigned long long));
+  GSW_TRY(launch_init(g, b, source, GSW_DEFAULT_KERNEL, 0, s));
+  GSW_HIP(hipStreamSynchronize(s));
   int64_t nf = 1;
   uint32_t bins[kQueueBins] = {1};  // segment sizes of the current queue
-  bool fr_valid = true;
   std::vector<float> samples((size_t)reps);
+  BfsCtl saved_ctl;
   for (int32_t d = 0;; ++d) {
     if (d >= max_levels) return fail(GSW_ERANGE, "BFS longer than max_levels=%d", max_levels);
     int32_t* qin = w.q[d & 1];
     // copies queue segments of the current frontier only
     auto copy_queue = [&](int32_t* dst, const int32_t* src) -> gsw_status {
-      for (int b = 0; b < kQueueBins; ++b)
-        if (bins[b])
-          GSW_HIP(hipMemcpyAsync(dst + (size_t)b * n, src + (size_t)b * n, bins[b] * sizeof(int32_t),
+      for (int bi = 0; bi < kQueueBins; ++bi)
+        if (bins[bi])
+          GSW_HIP(hipMemcpyAsync(dst + (size_t)bi * n, src + (size_t)bi * n, bins[bi] * sizeof(int32_t),
                                  hipMemcpyDeviceToDevice, s));
       return GSW_OK;
     };
@@ -324,24 +393,44 @@ gsw_status gsw_bfs_profile(const gsw_graph* cg, int32_t source, const int32_t* k
       GSW_HIP(hipMemcpyAsync(s_lv.p, lv, vb, hipMemcpyDeviceToDevice, s));
       GSW_HIP(hipMemcpyAsync(s_pa.p, pa, vb, hipMemcpyDeviceToDevice, s));
       GSW_HIP(hipMemcpyAsync(s_vis.p, w.vis, bb, hipMemcpyDeviceToDevice, s));
-      for (int b = 0; b < 2; ++b)
-        GSW_HIP(hipMemcpyAsync((char*)s_bm.p + b * bb, w.bm[b], bb, hipMemcpyDeviceToDevice, s));
+      for (int i = 0; i < 3; ++i)
+        GSW_HIP(hipMemcpyAsync((char*)s_bm.p + i * bb, w.bm[i], bb, hipMemcpyDeviceToDevice, s));
       GSW_TRY(copy_queue((int32_t*)s_q.p, qin));
       GSW_HIP(hipMemcpyAsync(s_ctr.p, w.ctr, cb, hipMemcpyDeviceToDevice, s));
+      GSW_HIP(hipMemcpyAsync(w.h_ctl, w.ctl, sizeof(BfsCtl), hipMemcpyDeviceToHost, s));
+      GSW_HIP(hipStreamSynchronize(s));
+      saved_ctl = *w.h_ctl;
       return GSW_OK;
     };
-    auto restore = [&]() -> gsw_status {
+    // restores the saved state with kernel k named for level d
+    auto restore = [&](int k) -> gsw_status {
       GSW_HIP(hipMemcpyAsync(lv, s_lv.p, vb, hipMemcpyDeviceToDevice, s));
       GSW_HIP(hipMemcpyAsync(pa, s_pa.p, vb, hipMemcpyDeviceToDevice, s));
       GSW_HIP(hipMemcpyAsync(w.vis, s_vis.p, bb, hipMemcpyDeviceToDevice, s));
-      for (int b = 0; b < 2; ++b)
-        GSW_HIP(hipMemcpyAsync(w.bm[b], (char*)s_bm.p + b * bb, bb, hipMemcpyDeviceToDevice, s));
+      for (int i = 0; i < 3; ++i)
+        GSW_HIP(hipMemcpyAsync(w.bm[i], (char*)s_bm.p + i * bb, bb, hipMemcpyDeviceToDevice, s));
       GSW_TRY(copy_queue(qin, (const int32_t*)s_q.p));
       GSW_HIP(hipMemcpyAsync(w.ctr, s_ctr.p, cb, hipMemcpyDeviceToDevice, s));
+      *w.h_ctl = saved_ctl;
+      w.h_ctl->kernel = k;
+      w.h_ctl->grid = level_participants(k, nf, b);
+      w.h_ctl->done_blocks = 0u;
+      GSW_HIP(hipMemcpyAsync(w.ctl, w.h_ctl, sizeof(BfsCtl), hipMemcpyHostToDevice, s));
+      GSW_HIP(hipStreamSynchronize(s));  // the staging copy is reused by the next restore
+      return GSW_OK;
+    };
+    // one level with kernel k; after push_edge the next level's bitmap is
+    // rebuilt (outside the timed bracket) so any kernel can follow
+    auto run = [&](int k, bool timed_bracket) -> gsw_status {
+      if (timed_bracket) GSW_HIP(hipEventRecord(w.ev[0], s));
+      if (k == GSW_K_PUSH_EDGE)
+        GSW_TRY(launch_level_edge(g, b, dp, d, (uint32_t)nf, false, s));
+      else
+        GSW_TRY(launch_level_auto(g, b, dp, s));
+      if (timed_bracket) GSW_HIP(hipEventRecord(w.ev[1], s));
       return GSW_OK;
     };
     GSW_TRY(save());
-    const LevelLaunch l = level_args(g, lv, pa, d, (uint32_t)nf);
     for (int32_t ki = 0; ki < n_kernels; ++ki) {
       const int k = kernels[ki];
       if (kernel_is_pull(k) && !g->symmetric) {
@@ -349,10 +438,8 @@ gsw_status gsw_bfs_profile(const gsw_graph* cg, int32_t source, const int32_t* k
         continue;
       }
       for (int32_t r = 0; r < reps; ++r) {
-        GSW_TRY(restore());
-        GSW_HIP(hipEventRecord(w.ev[0], s));
-        GSW_TRY(run_level(g, k, l, fr_valid, s));
-        GSW_HIP(hipEventRecord(w.ev[1], s));
+        GSW_TRY(restore(k));
+        GSW_TRY(run(k, true));
         GSW_HIP(hipEventSynchronize(w.ev[1]));
         GSW_HIP(hipEventElapsedTime(&samples[(size_t)r], w.ev[0], w.ev[1]));
       }
@@ -371,11 +458,19 @@ gsw_status gsw_bfs_profile(const gsw_graph* cg, int32_t source, const int32_t* k
         }
       }
     }
-    GSW_TRY(restore());
-    GSW_TRY(run_level(g, adv, l, fr_valid, s));
-    fr_valid = kernel_is_pull(adv);
-    int64_t nn = 0;
-    GSW_TRY(read_next(g, d, s, &nn, bins));
+    GSW_TRY(restore(adv));
+    GSW_TRY(run(adv, false));
+    if (adv == GSW_K_PUSH_EDGE) {
+      // make the next level's bitmap valid whatever kernel runs it
+      GSW_TRY(launch_rebuild_bitmap(g, b, s));
+    }
+    GSW_HIP(hipStreamSynchronize(s));
+    const volatile unsigned long long* r = nullptr;
+    GSW_TRY(wait_record(g, d, s, &r));
+    const int64_t nn = (int64_t)r[kRecNext];
+    GSW_HIP(hipMemcpy(w.h_ctr, w.ctr + (size_t)((d + 1) & 3) * kCtrSlot, kCtrSlot * sizeof(uint32_t),
+                      hipMemcpyDeviceToHost));
+    for (int bi = 0; bi < kQueueBins; ++bi) bins[bi] = w.h_ctr[bi * kCtrStride];
     if (frontier) frontier[d] = nf;
     if (n_levels) *n_levels = d + 1;
     if (nn == 0) break;

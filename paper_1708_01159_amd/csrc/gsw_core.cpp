@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -149,6 +150,9 @@ gsw_status ensure_workspace(gsw_graph* g) {
       {(void**)&w.vis, bmb},
       {(void**)&w.bm[0], bmb},
       {(void**)&w.bm[1], bmb},
+      {(void**)&w.bm[2], bmb},
+      {(void**)&w.ctl, sizeof(BfsCtl)},
+      {(void**)&w.done, (size_t)kDoneGroups * kCtrStride * sizeof(uint32_t)},
       {(void**)&w.q[0], (size_t)kQueueBins * n * sizeof(int32_t)},
       {(void**)&w.q[1], (size_t)kQueueBins * n * sizeof(int32_t)},
       {(void**)&w.ctr, 4 * kCtrSlot * sizeof(uint32_t)},
@@ -169,9 +173,11 @@ gsw_status ensure_workspace(gsw_graph* g) {
     w.bytes += it.bytes;
   }
   GSW_HIP(hipHostMalloc((void**)&w.h_ctr, kCtrSlot * sizeof(uint32_t), hipHostMallocDefault));
-  GSW_HIP(hipHostMalloc((void**)&w.h_flag, kFlagSlots * 64 * sizeof(uint32_t),
+  GSW_HIP(hipHostMalloc((void**)&w.h_ctl, sizeof(BfsCtl), hipHostMallocDefault));
+  GSW_HIP(hipHostMalloc((void**)&w.ring, (size_t)kBfsRing * kBfsRec * sizeof(unsigned long long),
                         hipHostMallocMapped | hipHostMallocCoherent));
-  GSW_HIP(hipHostGetDevicePointer((void**)&w.d_flag, w.h_flag, 0));
+  std::memset(w.ring, 0, (size_t)kBfsRing * kBfsRec * sizeof(unsigned long long));
+  GSW_HIP(hipHostGetDevicePointer((void**)&w.d_ring, w.ring, 0));
   if (g->symmetric && !g->iso) {
     const size_t ib = (size_t)w.nw * sizeof(unsigned long long);
     hipError_t e = hipMalloc((void**)&g->iso, ib);
@@ -187,23 +193,6 @@ gsw_status ensure_workspace(gsw_graph* g) {
   GSW_HIP(hipEventCreate(&w.ev[0]));
   GSW_HIP(hipEventCreate(&w.ev[1]));
   {
-    // level timing: per-workgroup stamp slots (start = max, end = 0 when unused)
-    std::vector<unsigned long long> init(2 * (size_t)kStampBlocks);
-    for (size_t i = 0; i < init.size(); i += 2) {
-      init[i] = ~0ull;
-      init[i + 1] = 0ull;
-    }
-    const size_t tb = init.size() * sizeof(unsigned long long);
-    const size_t lb = (size_t)kMaxTimedLevels * sizeof(unsigned long long);
-    hipError_t e1 = hipMalloc((void**)&w.tst, tb);
-    hipError_t e2 = e1 == hipSuccess ? hipMalloc((void**)&w.lvl_ticks, lb) : e1;
-    if (e1 != hipSuccess || e2 != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(GSW_ENOMEM, "hipMalloc for the level timers failed");
-    }
-    w.bytes += tb + lb;
-    GSW_HIP(hipMemcpy(w.tst, init.data(), tb, hipMemcpyHostToDevice));
-    GSW_HIP(hipHostMalloc((void**)&w.h_ticks, lb, hipHostMallocDefault));
     int khz = 0;
     GSW_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, g->device));
     w.tick_ms = khz > 0 ? 1.0 / (double)khz : 0.0;
@@ -235,18 +224,16 @@ namespace {
 void free_graph(gsw_graph* g) {
   if (!g) return;
   Workspace& w = g->ws;
-  void* dev[] = {w.vis, w.bm[0], w.bm[1], w.q[0], w.q[1], w.ctr, w.scan, w.ebeg,
-                 w.bsum, w.etot, w.lvl_tmp, w.par_tmp, g->origin};
+  void* dev[] = {w.vis, w.bm[0], w.bm[1], w.bm[2], w.ctl, w.done, w.q[0], w.q[1], w.ctr, w.scan, w.ebeg,
+                 w.bsum, w.etot, w.lvl_tmp, w.par_tmp, w.d_tree, w.d_thr, w.d_sched, g->origin};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   if (w.h_ctr) (void)hipHostFree(w.h_ctr);
-  if (w.h_flag) (void)hipHostFree(w.h_flag);
+  if (w.h_ctl) (void)hipHostFree(w.h_ctl);
+  if (w.ring) (void)hipHostFree(w.ring);
   if (g->iso) (void)hipFree(g->iso);
   for (hipEvent_t ev : w.ev)
     if (ev) (void)hipEventDestroy(ev);
-  if (w.tst) (void)hipFree(w.tst);
-  if (w.lvl_ticks) (void)hipFree(w.lvl_ticks);
-  if (w.h_ticks) (void)hipHostFree(w.h_ticks);
   if (g->owns_csr) {
     if (g->offs) (void)hipFree((void*)g->offs);
     if (g->cols) (void)hipFree((void*)g->cols);
@@ -431,6 +418,24 @@ gsw_status gsw_tree_create(int32_t n_nodes, int32_t n_classes, const int32_t* fe
   t->right.assign(right, right + n_nodes);
   t->value.assign(value, value + (size_t)n_nodes * n_classes);
   t->class_kernel.assign(class_kernel, class_kernel + n_classes);
+  // each leaf's decision, with gsw_tree_predict's tie rule (-1: undecided)
+  t->leaf_kernel.assign((size_t)n_nodes, -1);
+  for (int32_t i = 0; i < n_nodes; ++i) {
+    if (left[i] != -1) continue;
+    const double* v = value + (size_t)i * n_classes;
+    int32_t best = 0, ties = 1;
+    for (int32_t c = 1; c < n_classes; ++c) {
+      if (v[c] > v[best]) {
+        best = c;
+        ties = 1;
+      } else if (v[c] == v[best]) {
+        ++ties;
+      }
+    }
+    t->leaf_kernel[(size_t)i] = ties == 1 ? class_kernel[best] : -1;
+  }
+  static std::atomic<uint64_t> next_id{1};
+  t->id = next_id++;
   *out = t;
   return GSW_OK;
 }

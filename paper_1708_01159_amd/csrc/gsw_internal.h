@@ -43,10 +43,12 @@ constexpr int kCtrSlot = kQueueBins * kCtrStride;  // words per level in the cou
 // Device state of one BFS in flight.  Bitmaps are 64-bit words, bit (v & 63)
 // of word v >> 6; the last word's bits beyond n are set in `vis` so they are
 // never treated as unvisited.
+struct BfsCtl;
+
 struct Workspace {
   int64_t n = 0, nw = 0;
   unsigned long long* vis = nullptr;     // visited
-  unsigned long long* bm[2] = {};        // frontier bitmaps (depth d and d+1)
+  unsigned long long* bm[3] = {};        // frontier bitmaps, depth d in bm[d % 3]
   int32_t* q[2] = {};                    // frontier queues, kQueueBins segments of n
   uint32_t* ctr = nullptr;               // ring of 4 levels x kCtrSlot words
   int64_t* scan = nullptr;               // push_edge: per-entry exclusive degree scan
@@ -56,13 +58,20 @@ struct Workspace {
   int32_t* lvl_tmp = nullptr;            // levels when the caller passes host memory
   int32_t* par_tmp = nullptr;            // parents when the caller passes host memory
   uint32_t* h_ctr = nullptr;             // pinned host copy of one counter slot
-  uint32_t* h_flag = nullptr;            // mapped host memory: frontier size per level slot
-  uint32_t* d_flag = nullptr;            // the same memory as seen by the device
+  BfsCtl* ctl = nullptr;                 // device level control
+  uint32_t* done = nullptr;              // finished-workgroup counters of the running level
+  BfsCtl* h_ctl = nullptr;               // pinned staging for control-block uploads (profiling)
+  unsigned long long* ring = nullptr;    // mapped host memory: per-level records
+  unsigned long long* d_ring = nullptr;  // the same memory as seen by the device
+  int32_t* d_tree = nullptr;             // device copy of the tree's nodes (4 ints each) ...
+  double* d_thr = nullptr;               // ... and thresholds
+  int32_t tree_cap = 0;                  // nodes the device copy has room for
+  uint64_t tree_id = 0;                  // tree currently uploaded (0: none)
+  int32_t* d_sched = nullptr;            // device copy of a schedule
+  int32_t sched_cap = 0;
+  std::vector<int32_t> sched_host;       // the schedule that d_sched holds
   hipEvent_t ev[2] = {};
-  unsigned long long* tst = nullptr;     // per-workgroup start/end wall-clock stamps of a level
-  unsigned long long* lvl_ticks = nullptr;  // per-level kernel duration in wall-clock ticks
-  unsigned long long* h_ticks = nullptr;    // pinned host copy of lvl_ticks
-  double tick_ms = 0.0;                     // milliseconds per wall-clock tick
+  double tick_ms = 0.0;                  // milliseconds per wall-clock tick
   size_t bytes = 0;
 };
 
@@ -95,39 +104,98 @@ struct gsw_tree {
   int32_t n_nodes = 0, n_classes = 0;
   std::vector<int32_t> feature, left, right, class_kernel;
   std::vector<double> threshold, value;
+  std::vector<int32_t> leaf_kernel;  // per node: the leaf's kernel, -1 when undecided (tie)
+  uint64_t id = 0;                   // unique per created tree (device copies are keyed by it)
 };
 
 namespace gsw {
 
-// Kernel launchers (gsw_kernels.hip).
-struct LevelLaunch {
+// Single-source level control in device memory: set by the init kernel and,
+// for every next level, by the last workgroup of the current level's kernel.
+struct BfsCtl {
+  int32_t d;        // level to run next
+  int32_t kernel;   // its kernel (kCtlDone once a level found nothing)
+  int32_t prev;     // kernel of level d-1
+  int32_t flags;    // trace flags of that choice (bit0 undecided leaf, bit1 pull replaced)
+  long long nf;     // frontier size of level d
+  long long disc;   // vertices discovered through depth d
+  unsigned int done_blocks;  // groups of workgroups of the running level that have finished
+  int32_t pad;
+  unsigned long long t_begin;  // wall clock at the start of the running level (timed levels)
+  int32_t grid;                // workgroups that run level d (the rest of the launch exits)
+  int32_t pad2;
+};
+// Workgroups count themselves finished in kDoneGroups counters (by index
+// modulo kDoneGroups, kCtrStride words apart); the last of each group then
+// counts its group in BfsCtl::done_blocks.  Same-address atomics serialise,
+// so 2048 workgroups on one counter would cost about 20 us per level.
+constexpr int kDoneGroups = 16;
+constexpr int32_t kCtlDone = -1;
+
+// How the device picks the next level's kernel (a kernel argument): the same
+// policies and rules as the host's choice for level 0.
+struct BfsPolicy {
+  int32_t policy, fixed, sched_len, symmetric;
+  int32_t has_origin;        // edge_scan can run (its origin array exists)
+  int32_t pad;
+  const int32_t* sched;      // device copy of the schedule
+  const int32_t* t_node;     // tree nodes: feature, left, right, leaf kernel (-1 undecided)
+  const double* t_thr;       // tree thresholds
+  int32_t t_nodes;           // nodes of the tree
+  int32_t pad2;
+  double feat[8];            // n, arcs, degree min, Q1, median, Q3, max, std
+};
+
+// Buffers of one single-source BFS (a kernel argument of the level kernels).
+struct BfsBase {
   const int64_t* offs;
   const int32_t* cols;
   const int32_t* origin;
   int32_t* level;
-  int32_t* parent;          // may be null
+  int32_t* parent;                 // may be null
   unsigned long long* vis;
-  const unsigned long long* fr;  // frontier bitmap of depth d (pull only)
-  unsigned long long* nx;        // depth d+1 bitmap, written whole by pull
-  const int32_t* qin;       // queue of depth d (kQueueBins segments)
-  const uint32_t* cin;      // its segment counts (a counter slot)
-  int32_t* qout;            // queue of depth d+1
-  uint32_t* cout;           // its segment counters (zero on entry)
-  uint32_t* cclr;           // counter slot to zero for the level after next
-  unsigned long long* tst;  // wall-clock stamps per workgroup (null: not timed)
+  unsigned long long* bm[3];
+  int32_t* q[2];
+  uint32_t* ctr;
+  uint32_t* done;                  // kDoneGroups workgroup counters, kCtrStride words apart
+  unsigned long long* ring;        // device address of the host record ring
+  BfsCtl* ctl;
   int64_t n, nw, nnz;
-  uint32_t n_in;
-  int32_t d;
+  int32_t timed;                   // record each level's duration
+  int32_t grid_max;                // workgroups of a level-kernel launch
 };
 
-gsw_status launch_init(const gsw_graph* g, int32_t* level, int32_t* parent, int32_t source,
+// Host ring of per-level records: record of level d at (d % kBfsRing) * kBfsRec.
+constexpr int kBfsRing = 8;
+constexpr int kBfsRec = 16;
+enum : int {
+  kRecSeq = 0,      // d + 1, stored last
+  kRecKernel = 1,   // kernel that ran level d
+  kRecFlags = 2,    // its trace flags
+  kRecNf = 3,       // frontier size of level d
+  kRecDisc = 4,     // discovered through depth d
+  kRecNext = 5,     // size of the depth-(d+1) frontier
+  kRecTicks = 6,    // wall-clock ticks of the level (timed levels)
+  kRecNextKernel = 7  // kernel chosen for level d+1 (kCtlDone when none)
+};
+
+// Kernel launchers (gsw_kernels.hip).
+gsw_status launch_init(const gsw_graph* g, const BfsBase& b, int32_t source, int32_t k0, int32_t flags0,
                        hipStream_t s);
-gsw_status launch_level(const gsw_graph* g, int kernel, const LevelLaunch& a, hipStream_t s);
-gsw_status launch_frontier_bitmap(const gsw_graph* g, const int32_t* level, int32_t d,
-                                  unsigned long long* bm, hipStream_t s);
+// One level run by the kernel that the control block names, unless that is
+// push_edge or none (then the launch does nothing).
+gsw_status launch_level_auto(const gsw_graph* g, const BfsBase& b, const BfsPolicy& p, hipStream_t s);
+// One push_edge level (three kernels); afterwards the frontier bitmap of the
+// next level is rebuilt when the next kernel is pull (or always with force).
+gsw_status launch_level_edge(const gsw_graph* g, const BfsBase& b, const BfsPolicy& p, int32_t d,
+                             uint32_t n_in, bool force_bitmap, hipStream_t s);
+// Workgroups of a level-kernel launch on a graph of n vertices (nw bitmap words).
+int32_t level_kernel_grid(int64_t n, int64_t nw);
+// Workgroups of that launch that run a level of `kernel` with n_in frontier entries.
+int32_t level_participants(int kernel, int64_t n_in, const BfsBase& b);
+// Frontier bitmap of the control block's level rebuilt from the level array.
+gsw_status launch_rebuild_bitmap(const gsw_graph* g, const BfsBase& b, hipStream_t s);
 gsw_status launch_isolated(const gsw_graph* g, unsigned long long* iso, hipStream_t s);
-gsw_status launch_finalize(const uint32_t* cslot, uint32_t* d_flag, unsigned long long* tst,
-                           unsigned long long* ticks, hipStream_t s);
 gsw_status launch_canonical_parents(const gsw_graph* g, const int32_t* level, int32_t* parent,
                                     hipStream_t s);
 gsw_status launch_build_origin(const gsw_graph* g, int32_t* origin, hipStream_t s);
@@ -139,13 +207,5 @@ hipStream_t pick_stream(gsw_graph* g, void* user_stream);
 bool kernel_is_pull(int k);
 void ms_release(gsw_graph* g);
 
-// Marker of a level-size slot in host memory that the device has not written.
-constexpr uint32_t kNotReady = 0xffffffffu;
-constexpr int kFlagSlots = 4;
-// Levels of one BFS whose kernel time time_levels records (later levels get -1).
-constexpr int kMaxTimedLevels = 8192;
-// Workgroups whose start/end stamps time a level (larger grids stamp from
-// their first kStampBlocks workgroups).
-constexpr int kStampBlocks = 4096;
 
 }  // namespace gsw

@@ -2,11 +2,25 @@
 //
 // Every kernel performs one whole BFS level d (Section III-A): it finds the
 // unvisited vertices adjacent to depth-d vertices, gives each depth d+1 and a
-// parent at depth d, and appends it to the depth-(d+1) queue.  The bottom-up
-// kernel also writes the depth-(d+1) frontier bitmap in full; after a top-down
-// level that bitmap is rebuilt from the level array only if the next level is
-// bottom-up.  Any kernel can therefore run the next level; only the queue's
-// order and the parent choice depend on the kernel, never the levels.
+// parent at depth d, and appends it to the depth-(d+1) queue.  The frontier
+// bitmaps rotate over three buffers (depth d in bm[d % 3]): the bottom-up
+// kernel writes the depth-(d+1) bitmap in full, the top-down kernels set the
+// bits of the vertices they discover (push_edge leaves it to a rebuild from
+// the level array, run only when the next level is bottom-up), and every
+// level zeroes the buffer of the level after next.  Any kernel can therefore
+// run the next level; only the queue's order and the parent choice depend on
+// the kernel, never the levels.
+//
+// The choice of the next level's kernel is made on the device: the last
+// workgroup of a level to finish sums the next frontier's size, forms the
+// feature vector, applies the policy (the decision tree walked with the same
+// float32-against-float64 rule as the host, a fixed kernel or a schedule),
+// stores it in the level control block and posts the level's record to a
+// ring in mapped host memory.  One kernel, k_level_auto, runs whichever
+// variant the control block names, so the host can queue levels ahead
+// without waiting for their results; push_edge, whose prefix sum needs a
+// grid-wide step, is launched by the host as three kernels when the device
+// names it.
 //
 // Ownership of a new vertex v is decided by atomicOr on its 64-bit visited
 // word: exactly one lane sees the bit clear and becomes the writer of v's
@@ -42,6 +56,7 @@ constexpr int kPullChunk = 8;                    // pull: visited words (512 ver
 
 typedef unsigned long long u64;
 
+// One level's view of the buffers.
 struct Args {
   const int64_t* __restrict__ offs;
   const int32_t* __restrict__ cols;
@@ -49,18 +64,70 @@ struct Args {
   int32_t* __restrict__ level;
   int32_t* __restrict__ parent;
   u64* vis;
-  const u64* __restrict__ fr;
-  u64* nx;
+  const u64* __restrict__ fr;  // depth-d frontier bitmap
+  u64* nx;                     // depth-(d+1) bitmap
+  u64* bclr;                   // bitmap of the level after next, zeroed here
   const int32_t* __restrict__ qin;
   const uint32_t* cin;
   int32_t* __restrict__ qout;
   uint32_t* cout;
   uint32_t* cclr;
-  u64* tst;
+  BfsCtl* ctl;
+  uint32_t* done;
   int64_t n, nw, nnz;
   uint32_t n_in;
   int32_t d;
+  int32_t set_nx;  // top-down kernels set the discovered vertices' bits in nx
+  int32_t timed;
+  int32_t grid;    // workgroups taking part in the level (grid-stride loops use it)
 };
+
+__host__ __device__ inline Args make_args(const BfsBase& b, int32_t d, uint32_t n_in, int32_t set_nx,
+                                          int32_t grid) {
+  Args a;
+  a.offs = b.offs;
+  a.cols = b.cols;
+  a.origin = b.origin;
+  a.level = b.level;
+  a.parent = b.parent;
+  a.vis = b.vis;
+  a.fr = b.bm[d % 3];
+  a.nx = b.bm[(d + 1) % 3];
+  a.bclr = b.bm[(d + 2) % 3];
+  a.qin = b.q[d & 1];
+  a.cin = b.ctr + (size_t)(d & 3) * kCtrSlot;
+  a.qout = b.q[(d + 1) & 1];
+  a.cout = b.ctr + (size_t)((d + 1) & 3) * kCtrSlot;
+  a.cclr = b.ctr + (size_t)((d + 2) & 3) * kCtrSlot;
+  a.ctl = b.ctl;
+  a.done = b.done;
+  a.n = b.n;
+  a.nw = b.nw;
+  a.nnz = b.nnz;
+  a.n_in = n_in;
+  a.d = d;
+  a.set_nx = set_nx;
+  a.timed = b.timed;
+  a.grid = grid;
+  return a;
+}
+
+__host__ __device__ inline int64_t div_up(int64_t x, int64_t y) { return (x + y - 1) / y; }
+
+// Workgroups that run a level of kernel k with n_in frontier entries: a lane
+// per entry for the queue-driven top-down kernels, a lane per vertex or arc
+// for the all-vertex and all-arc ones, the whole launch for pull.
+__host__ __device__ inline int32_t level_grid(int k, int64_t n_in, const BfsBase& b) {
+  int64_t need;
+  switch (k) {
+    case GSW_K_PULL_BITMAP: need = b.grid_max; break;
+    case GSW_K_VERTEX_SCAN: need = div_up(b.n, kBlock); break;
+    case GSW_K_EDGE_SCAN: need = div_up(b.nnz, kBlock); break;
+    default: need = div_up(n_in, kBlock); break;
+  }
+  if (need < 1) need = 1;
+  return (int32_t)(need < b.grid_max ? need : b.grid_max);
+}
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
@@ -68,25 +135,25 @@ __device__ __forceinline__ u64 lanes_below(int lane) { return (1ull << lane) - 1
 
 __device__ __forceinline__ int my_bin() { return (int)(blockIdx.x % kQueueBins); }
 
-// Level timing (only when a.tst is set): the first kStampBlocks workgroups
-// stamp the constant-rate wall clock at entry and exit; k_finalize reduces
-// the stamps to the level's duration.
-__device__ __forceinline__ void stamp_begin(const Args& a) {
-  if (a.tst && threadIdx.x == 0 && blockIdx.x < kStampBlocks)
-    a.tst[2 * blockIdx.x] = (u64)wall_clock64();
-}
-
-__device__ __forceinline__ void stamp_end(const Args& a) {
-  if (a.tst) {
-    __syncthreads();
-    if (threadIdx.x == 0 && blockIdx.x < kStampBlocks)
-      a.tst[2 * blockIdx.x + 1] = (u64)wall_clock64();
-  }
+// Level timing: workgroup 0 of the level's first kernel stamps the
+// constant-rate wall clock; the level's last workgroup to finish reads it at
+// the end.  (Workgroups are dispatched in index order.)
+__device__ __forceinline__ void level_begin(const Args& a) {
+  if (a.timed && blockIdx.x == 0 && threadIdx.x == 0)
+    __hip_atomic_store(&a.ctl->t_begin, (u64)wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Zero the counter slot that the level after next appends to.
 __device__ __forceinline__ void clear_ahead(const Args& a) {
   if (blockIdx.x == 0 && threadIdx.x < kQueueBins) a.cclr[threadIdx.x * kCtrStride] = 0u;
+}
+
+// Zero the frontier bitmap of the level after next, spread over every
+// workgroup of the launch (also those that take no part in the level: the
+// buffer is next written two launches later).
+__device__ __forceinline__ void clear_bitmap(u64* bclr, int64_t nw) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nw; i += stride) bclr[i] = 0ull;
 }
 
 // ----------------------------------------------------------- queue input
@@ -115,8 +182,8 @@ __device__ __forceinline__ int32_t queue_at(const Args& a, const QueueIn& q, uin
 }
 
 // ---------------------------------------------------------- queue output
-struct Stage {
-  int32_t buf[kStage];
+struct alignas(16) Stage {
+  int32_t buf[kStage];  // also the last workgroup's copy of the tree (16-byte nodes first)
   uint32_t n;      // entries reserved (may exceed kStage once it overflowed)
   uint32_t valid;  // reservations at or past this position went to global memory
   uint32_t base;
@@ -182,6 +249,7 @@ __device__ __forceinline__ bool claim(u64* vis, int32_t v) {
 __device__ __forceinline__ void settle(const Args& a, int32_t v, int32_t u) {
   a.level[v] = a.d + 1;
   if (a.parent) a.parent[v] = u;
+  if (a.set_nx) atomicOr(a.nx + (v >> 6), 1ull << (v & 63));
 }
 
 __device__ __forceinline__ void visit(Stage& s, const Args& a, int32_t v, int32_t u) {
@@ -190,42 +258,187 @@ __device__ __forceinline__ void visit(Stage& s, const Args& a, int32_t v, int32_
   stage_push(s, a, win, v);
 }
 
+// ------------------------------------------------- next-kernel choice
+// Feature i of level d+1's vector (Section IV-A list; the order of
+// gsw_level_features).
+__device__ __forceinline__ double feature(const BfsPolicy& p, int i, double nf, double disc) {
+  switch (i) {
+    case 8: return nf;
+    case 9: return nf / p.feat[0];
+    case 10: return disc;
+    case 11: return disc / p.feat[0];
+    default: return p.feat[i < 8 ? i : 0];
+  }
+}
+
+// Kernel for level d (d >= 1) with frontier nf and nf + earlier discoveries
+// = disc; prev = kernel of level d-1.  The same rules as the host's choice.
+__device__ int choose_next(const BfsPolicy& p, const int32_t* t_node, const double* t_thr, int32_t d,
+                           long long nf, long long disc, int prev, int32_t* flags) {
+  *flags = 0;
+  int k = GSW_DEFAULT_KERNEL;
+  if (p.policy == GSW_POLICY_FIXED) {
+    k = p.fixed;
+  } else if (p.policy == GSW_POLICY_SCHEDULE) {
+    k = p.sched[d < p.sched_len ? d : p.sched_len - 1];
+  } else {
+    int node = 0;
+    for (;;) {
+      const int32_t* nd = t_node + 4 * node;
+      if (nd[1] == -1) break;
+      const double xv = (double)(float)feature(p, nd[0], (double)nf, (double)disc);
+      node = xv <= t_thr[node] ? nd[1] : nd[2];
+    }
+    const int leaf = t_node[4 * node + 3];
+    if (leaf >= 0) {
+      k = leaf;
+    } else {
+      k = prev;  // undecided leaf: repeat the previous level's kernel (d >= 1)
+      *flags |= 1;
+    }
+  }
+  if (k == GSW_K_PULL_BITMAP && !p.symmetric) {
+    k = GSW_DEFAULT_KERNEL;
+    *flags |= 2;
+  }
+  if (k == GSW_K_EDGE_SCAN && !p.has_origin) k = GSW_DEFAULT_KERNEL;
+  return k;
+}
+
+// End of a level, called by every thread of every workgroup of the level's
+// last kernel: the last workgroup to finish sums the next frontier's
+// segments, picks the next kernel, posts the level's record to the host
+// ring (its first word last) and rewrites the control block.  Each
+// workgroup's queue-segment atomics have returned before it counts itself
+// finished, so the last one sees every segment's final size.  That
+// workgroup first copies the tree into `lds` (lds_bytes of LDS free by now,
+// the flushed append stage) with all its threads, so the walk does not pay
+// a global-memory round trip per node.
+__device__ void level_end(const Args& a, const BfsBase* base, const BfsPolicy& p, u64* ring, int k_run,
+                          void* lds, int lds_bytes) {
+  __shared__ uint32_t s_last;
+  __shared__ uint32_t s_nn;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_s_waitcnt(0);
+    const uint32_t grid = (uint32_t)a.grid;
+    uint32_t last = 1u;  // a level of one workgroup needs no count
+    if (grid > (unsigned)kDoneGroups) {
+      const uint32_t gidx = blockIdx.x % (unsigned)kDoneGroups;
+      const uint32_t in_group = grid / kDoneGroups + (gidx < grid % kDoneGroups ? 1u : 0u);
+      last = 0u;
+      if (atomicAdd(a.done + gidx * kCtrStride, 1u) == in_group - 1u)
+        last = atomicAdd(&a.ctl->done_blocks, 1u) == (unsigned)kDoneGroups - 1u ? 1u : 0u;
+    } else if (grid > 1u) {
+      last = atomicAdd(&a.ctl->done_blocks, 1u) == grid - 1u ? 1u : 0u;
+    }
+    s_last = last;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  const int tid = threadIdx.x;
+  const bool tree_lds = p.policy == GSW_POLICY_TREE && p.t_nodes * 24 <= lds_bytes;
+  int32_t* l_node = reinterpret_cast<int32_t*>(lds);
+  double* l_thr = reinterpret_cast<double*>(l_node + 4 * (tree_lds ? p.t_nodes : 0));
+  if (tree_lds) {
+    for (int i = tid; i < p.t_nodes; i += kBlock) {
+      const int4 nd = reinterpret_cast<const int4*>(p.t_node)[i];
+      reinterpret_cast<int4*>(l_node)[i] = nd;
+      l_thr[i] = p.t_thr[i];
+    }
+  }
+  if (tid < 64) {  // wave 0: the next frontier's segments
+    uint32_t x = tid < kQueueBins
+                     ? __hip_atomic_load(a.cout + tid * kCtrStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                     : 0u;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += (uint32_t)__shfl_xor((int)x, off);
+    if (tid == 0) s_nn = x;
+  }
+  if (tid < kDoneGroups) a.done[tid * kCtrStride] = 0u;
+  __syncthreads();
+  if (tid != 0) return;
+  BfsCtl* c = a.ctl;
+  const uint32_t nn = s_nn;
+  u64 ticks = 0ull;
+  if (a.timed) {
+    const u64 t0 = __hip_atomic_load(&c->t_begin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const u64 t1 = (u64)wall_clock64();
+    ticks = t1 > t0 ? t1 - t0 : 0ull;
+  }
+  const int32_t d = a.d;
+  const long long nf = c->nf, disc = c->disc, ndisc = disc + (long long)nn;
+  int32_t nflags = 0;
+  const int32_t next = nn > 0 ? choose_next(p, tree_lds ? l_node : p.t_node, tree_lds ? l_thr : p.t_thr, d + 1,
+                                             (long long)nn, ndisc, k_run, &nflags)
+                               : kCtlDone;
+  u64* r = ring + (size_t)(d % kBfsRing) * kBfsRec;
+  __hip_atomic_store(r + kRecKernel, (u64)k_run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(r + kRecFlags, (u64)c->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(r + kRecNf, (u64)nf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(r + kRecDisc, (u64)disc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(r + kRecNext, (u64)nn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(r + kRecTicks, ticks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(r + kRecNextKernel, (u64)(long long)next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  c->d = d + 1;
+  c->kernel = next;
+  c->grid = next >= 0 ? level_grid(next, (int64_t)nn, *base) : 1;
+  c->prev = k_run;
+  c->flags = nflags;
+  c->nf = (long long)nn;
+  c->disc = ndisc;
+  c->done_blocks = 0u;
+  // the host reads only the record: its other words are stored (system
+  // scope, to host memory) before the first word, no cache writeback needed
+  __builtin_amdgcn_s_waitcnt(0);
+  __hip_atomic_store(r + kRecSeq, (u64)d + 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // ---------------------------------------------------------------- init
-// Degree-0 vertices of a symmetric graph can never be reached (except as
-// the source): they start out marked visited so pull never scans them.
-__global__ void __launch_bounds__(kBlock) k_init(int32_t* __restrict__ level,
-                                                 int32_t* __restrict__ parent, u64* vis, u64* fr,
-                                                 const u64* __restrict__ iso, int32_t* q0,
-                                                 uint32_t* ctr, int64_t n, int64_t nw, int32_t s) {
+// Levels and parents, visited (source, padding and -- on a symmetric graph --
+// degree-0 vertices, which can never be reached), the three frontier
+// bitmaps (depth 0 = the source), the depth-0 queue, the counter ring and
+// the control block for level 0.
+__global__ void __launch_bounds__(kBlock) k_init(BfsBase b, const u64* __restrict__ iso, int32_t s,
+                                                 int32_t k0, int32_t flags0) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (int64_t i = gid; i < n; i += stride) {
-    level[i] = i == s ? 0 : -1;
-    if (parent) parent[i] = i == s ? s : -1;
+  for (int64_t i = gid; i < b.n; i += stride) {
+    b.level[i] = i == s ? 0 : -1;
+    if (b.parent) b.parent[i] = i == s ? s : -1;
   }
   const int64_t sw = s >> 6;
   const u64 sbit = 1ull << (s & 63);
-  const int tail = (int)(n & 63);
-  for (int64_t w = gid; w < nw; w += stride) {
+  const int tail = (int)(b.n & 63);
+  for (int64_t w = gid; w < b.nw; w += stride) {
     u64 pad = 0ull;
-    if (w == nw - 1 && tail) pad = ~0ull << tail;  // bits beyond n count as visited
+    if (w == b.nw - 1 && tail) pad = ~0ull << tail;  // bits beyond n count as visited
     const u64 here = w == sw ? sbit : 0ull;
-    vis[w] = here | pad | (iso ? iso[w] : 0ull);
-    fr[w] = here;
+    b.vis[w] = here | pad | (iso ? iso[w] : 0ull);
+    b.bm[0][w] = here;
+    b.bm[1][w] = 0ull;
+    b.bm[2][w] = 0ull;
   }
-  if (gid == 0) q0[0] = s;  // segment 0 of the depth-0 queue
-  if (gid < 4 * kCtrSlot) ctr[gid] = gid == 0 ? 1u : 0u;
+  if (gid == 0) {
+    b.q[0][0] = s;  // segment 0 of the depth-0 queue
+    BfsCtl* c = b.ctl;
+    c->d = 0;
+    c->kernel = k0;
+    c->prev = GSW_DEFAULT_KERNEL;
+    c->flags = flags0;
+    c->nf = 1;
+    c->disc = 1;
+    c->done_blocks = 0u;
+    c->t_begin = 0ull;
+    c->grid = level_grid(k0, 1, b);
+  }
+  if (gid < 4 * kCtrSlot) b.ctr[gid] = gid == 0 ? 1u : 0u;
+  if (gid < kDoneGroups) b.done[gid * kCtrStride] = 0u;
 }
 
 // ------------------------------------------------- push_vertex (lane / vertex)
-__global__ void __launch_bounds__(kBlock) k_push_vertex(Args a) {
-  stamp_begin(a);
-  __shared__ Stage st;
-  __shared__ QueueIn qi;
-  clear_ahead(a);
-  stage_init(st);
-  queue_in_load(a, qi);
-  const uint32_t stride = gridDim.x * kBlock;
+__device__ __forceinline__ void body_push_vertex(const Args& a, Stage& st, const QueueIn& qi) {
+  const uint32_t stride = (uint32_t)a.grid * kBlock;
   for (uint32_t base = blockIdx.x * kBlock; base < a.n_in; base += stride) {
     const uint32_t i = base + threadIdx.x;
     int32_t u = 0;
@@ -237,8 +450,6 @@ __global__ void __launch_bounds__(kBlock) k_push_vertex(Args a) {
     }
     for (int64_t e = beg; e < end; ++e) visit(st, a, a.cols[e], u);
   }
-  stage_flush(st, a);
-  stamp_end(a);
 }
 
 // ------------------------------------- push_wave<W> (W lanes / vertex, W vertices / group)
@@ -246,17 +457,11 @@ __global__ void __launch_bounds__(kBlock) k_push_vertex(Args a) {
 // lanes takes W frontier vertices and walks their rows one after another,
 // the W lanes striding over each row together.
 template <int W>
-__global__ void __launch_bounds__(kBlock) k_push_wave(Args a) {
-  stamp_begin(a);
-  __shared__ Stage st;
-  __shared__ QueueIn qi;
-  clear_ahead(a);
-  stage_init(st);
-  queue_in_load(a, qi);
+__device__ __forceinline__ void body_push_wave(const Args& a, Stage& st, const QueueIn& qi) {
   const int lane = lane_id();
   const int sub = lane & (W - 1);
   const int first = lane & ~(W - 1);
-  const uint32_t stride = gridDim.x * kBlock;
+  const uint32_t stride = (uint32_t)a.grid * kBlock;
   for (uint32_t base = blockIdx.x * kBlock; base < a.n_in; base += stride) {
     const uint32_t i = base + threadIdx.x;  // this lane's own entry
     int32_t u = 0;
@@ -274,8 +479,6 @@ __global__ void __launch_bounds__(kBlock) k_push_wave(Args a) {
       for (int64_t e = bj + sub; e < ej; e += W) visit(st, a, a.cols[e], uj);
     }
   }
-  stage_flush(st, a);
-  stamp_end(a);
 }
 
 // ------------------------------------------------ push_edge (lane / frontier edge)
@@ -283,7 +486,7 @@ __global__ void __launch_bounds__(kBlock) k_push_wave(Args a) {
 __global__ void __launch_bounds__(kBlock) k_edge_scan_local(Args a, int64_t* __restrict__ scan,
                                                             int64_t* __restrict__ ebeg,
                                                             int64_t* __restrict__ bsum) {
-  stamp_begin(a);
+  level_begin(a);
   __shared__ int64_t wsum[kWaves];
   __shared__ QueueIn qi;
   clear_ahead(a);
@@ -374,13 +577,15 @@ __device__ __forceinline__ int64_t find_entry(const int64_t* scan, const int64_t
 __global__ void __launch_bounds__(kBlock) k_edge_expand(Args a, const int64_t* __restrict__ scan,
                                                         const int64_t* __restrict__ ebeg,
                                                         const int64_t* __restrict__ bsum,
-                                                        const u64* __restrict__ etot) {
+                                                        const u64* __restrict__ etot, BfsPolicy p,
+                                                        BfsBase b) {
   __shared__ int64_t s_start[kEdgeWin + 1];
   __shared__ int64_t s_beg[kEdgeWin];
   __shared__ int32_t s_u[kEdgeWin];
   __shared__ int64_t s_range[2];
   __shared__ Stage st;
   __shared__ QueueIn qi;
+  clear_bitmap(a.bclr, a.nw);
   stage_init(st);
   queue_in_load(a, qi);
   const int64_t total = (int64_t)*etot;
@@ -435,7 +640,7 @@ __global__ void __launch_bounds__(kBlock) k_edge_expand(Args a, const int64_t* _
     __syncthreads();
   }
   stage_flush(st, a);
-  stamp_end(a);
+  level_end(a, &b, p, b.ring, GSW_K_PUSH_EDGE, st.buf, (int)sizeof(st.buf));
 }
 
 // ------------------------------------------ pull_bitmap (wave / 512 vertices)
@@ -475,15 +680,10 @@ __device__ __forceinline__ int nth_set_bit(u64 m, int k) {
   return pos;
 }
 
-__global__ void __launch_bounds__(kBlock) k_pull(Args a) {
-  stamp_begin(a);
-  __shared__ Stage st;
-  __shared__ u64 s_found[kWaves][kPullChunk];
-  clear_ahead(a);
-  stage_init(st);
+__device__ __forceinline__ void body_pull(const Args& a, Stage& st, u64 (*s_found)[kPullChunk]) {
   const int lane = lane_id();
   u64* found_w = s_found[threadIdx.x >> 6];
-  const int64_t nwaves = (int64_t)gridDim.x * kWaves;
+  const int64_t nwaves = (int64_t)a.grid * kWaves;
   const int64_t nchunks = (a.nw + kPullChunk - 1) / kPullChunk;
   for (int64_t c = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6; c < nchunks; c += nwaves) {
     const int64_t w0 = c * kPullChunk;
@@ -580,17 +780,11 @@ __global__ void __launch_bounds__(kBlock) k_pull(Args a) {
       if (fm) a.vis[w0 + lane] = seen | fm;  // this wave is the word's only writer in a pull level
     }
   }
-  stage_flush(st, a);
-  stamp_end(a);
 }
 
 // ------------------------------------------ vertex_scan (lane / vertex, all n)
-__global__ void __launch_bounds__(kBlock) k_vertex_scan(Args a) {
-  stamp_begin(a);
-  __shared__ Stage st;
-  clear_ahead(a);
-  stage_init(st);
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
+__device__ __forceinline__ void body_vertex_scan(const Args& a, Stage& st) {
+  const int64_t stride = (int64_t)a.grid * kBlock;
   for (int64_t base = (int64_t)blockIdx.x * kBlock; base < a.n; base += stride) {
     const int64_t v = base + threadIdx.x;
     int64_t beg = 0, end = 0;
@@ -600,17 +794,11 @@ __global__ void __launch_bounds__(kBlock) k_vertex_scan(Args a) {
     }
     for (int64_t e = beg; e < end; ++e) visit(st, a, a.cols[e], (int32_t)v);
   }
-  stage_flush(st, a);
-  stamp_end(a);
 }
 
 // -------------------------------------------- edge_scan (lane / arc, all arcs)
-__global__ void __launch_bounds__(kBlock) k_edge_scan(Args a) {
-  stamp_begin(a);
-  __shared__ Stage st;
-  clear_ahead(a);
-  stage_init(st);
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
+__device__ __forceinline__ void body_edge_scan(const Args& a, Stage& st) {
+  const int64_t stride = (int64_t)a.grid * kBlock;
   // uniform trip count so every lane of a wave reaches the ballots together
   const int64_t rounds = (a.nnz + stride - 1) / stride;
   int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -627,8 +815,58 @@ __global__ void __launch_bounds__(kBlock) k_edge_scan(Args a) {
     }
     stage_push(st, a, win, v);
   }
+}
+
+// ------------------------------------------------ one level, any variant
+// Runs level ctl->d with the kernel ctl->kernel names; does nothing when that
+// is push_edge (launched by the host) or when the search has ended.
+__global__ void __launch_bounds__(kBlock) k_level_auto(BfsBase b, BfsPolicy p) {
+  __shared__ Stage st;
+  __shared__ QueueIn qi;
+  __shared__ u64 s_found[kWaves][kPullChunk];
+  const int k = b.ctl->kernel;
+  if (k < 0 || k >= GSW_N_KERNELS || k == GSW_K_PUSH_EDGE) return;
+  const int32_t d = b.ctl->d;
+  const int32_t grid = b.ctl->grid;
+  clear_bitmap(b.bm[(d + 2) % 3], b.nw);
+  if ((int32_t)blockIdx.x >= grid) return;  // not needed for this level (grid <= the launch)
+  Args a = make_args(b, d, 0u, 1, grid);
+  level_begin(a);
+  clear_ahead(a);
+  stage_init(st);
+  if (k != GSW_K_PULL_BITMAP && k != GSW_K_VERTEX_SCAN && k != GSW_K_EDGE_SCAN) {
+    queue_in_load(a, qi);
+    a.n_in = qi.pre[kQueueBins];
+  }
+  switch (k) {
+    case GSW_K_PUSH_VERTEX: body_push_vertex(a, st, qi); break;
+    case GSW_K_PUSH_WAVE4: body_push_wave<4>(a, st, qi); break;
+    case GSW_K_PUSH_WAVE8: body_push_wave<8>(a, st, qi); break;
+    case GSW_K_PUSH_WAVE16: body_push_wave<16>(a, st, qi); break;
+    case GSW_K_PUSH_WAVE32: body_push_wave<32>(a, st, qi); break;
+    case GSW_K_PUSH_WAVE64: body_push_wave<64>(a, st, qi); break;
+    case GSW_K_PULL_BITMAP: body_pull(a, st, s_found); break;
+    case GSW_K_VERTEX_SCAN: body_vertex_scan(a, st); break;
+    default: body_edge_scan(a, st); break;
+  }
   stage_flush(st, a);
-  stamp_end(a);
+  level_end(a, &b, p, b.ring, k, st.buf, (int)sizeof(st.buf));
+}
+
+// Frontier bitmap of depth ctl->d from the level array, after a push_edge
+// level when the next level is bottom-up (or always with force).
+__global__ void __launch_bounds__(kBlock) k_rebuild_bitmap(BfsBase b, int32_t force) {
+  const BfsCtl* c = b.ctl;
+  if (!force && c->kernel != GSW_K_PULL_BITMAP) return;
+  const int32_t d = c->d;
+  u64* bm = b.bm[d % 3];
+  const int lane = lane_id();
+  const int64_t nwaves = (int64_t)gridDim.x * kWaves;
+  for (int64_t w = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6; w < b.nw; w += nwaves) {
+    const int64_t v = w * 64 + lane;
+    const u64 m = __ballot(v < b.n && b.level[v] == d);
+    if (lane == 0) bm[w] = m;
+  }
 }
 
 // ------------------------------------------------------------ helpers
@@ -640,50 +878,6 @@ __global__ void __launch_bounds__(kBlock) k_isolated(const int64_t* __restrict__
     const int64_t v = w * 64 + lane;
     const u64 m = __ballot(v < n && offs[v + 1] == offs[v]);
     if (lane == 0) iso[w] = m;
-  }
-}
-
-// Sum of a counter slot's segments, stored to host memory for the level loop;
-// with timing on, also the level's duration (latest end stamp minus earliest
-// start stamp), after which the stamp slots are reset.
-__global__ void __launch_bounds__(64) k_finalize(const uint32_t* __restrict__ cslot,
-                                                 uint32_t* host_flag, u64* tst, u64* ticks) {
-  const int lane = lane_id();
-  uint32_t x = lane < kQueueBins ? cslot[lane * kCtrStride] : 0u;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x += (uint32_t)__shfl_xor((int)x, off);
-  if (tst) {
-    u64 lo = ~0ull, hi = 0ull;
-    for (int b = lane; b < kStampBlocks; b += 64) {
-      const u64 s0 = tst[2 * b], s1 = tst[2 * b + 1];
-      lo = s0 < lo ? s0 : lo;
-      hi = s1 > hi ? s1 : hi;
-      tst[2 * b] = ~0ull;
-      tst[2 * b + 1] = 0ull;
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const u64 l2 = __shfl_xor(lo, off);
-      const u64 h2 = __shfl_xor(hi, off);
-      lo = l2 < lo ? l2 : lo;
-      hi = h2 > hi ? h2 : hi;
-    }
-    if (lane == 0) *ticks = hi > lo ? hi - lo : 0ull;
-  }
-  if (lane == 0) __hip_atomic_store(host_flag, x, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-
-// Frontier bitmap of depth d from the level array (before a pull level that
-// follows a top-down level).
-__global__ void __launch_bounds__(kBlock) k_frontier_bitmap(const int32_t* __restrict__ level,
-                                                            int32_t d, u64* __restrict__ bm,
-                                                            int64_t n, int64_t nw) {
-  const int lane = lane_id();
-  const int64_t nwaves = (int64_t)gridDim.x * kWaves;
-  for (int64_t w = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6; w < nw; w += nwaves) {
-    const int64_t v = w * 64 + lane;
-    const u64 m = __ballot(v < n && level[v] == d);
-    if (lane == 0) bm[w] = m;
   }
 }
 
@@ -713,30 +907,6 @@ __global__ void __launch_bounds__(kBlock) k_build_origin(const int64_t* __restri
   for (int64_t e = offs[v] + lane; e < offs[v + 1]; e += 64) origin[e] = (int32_t)v;
 }
 
-Args to_args(const LevelLaunch& l) {
-  Args a;
-  a.offs = l.offs;
-  a.cols = l.cols;
-  a.origin = l.origin;
-  a.level = l.level;
-  a.parent = l.parent;
-  a.vis = l.vis;
-  a.fr = l.fr;
-  a.nx = l.nx;
-  a.qin = l.qin;
-  a.cin = l.cin;
-  a.qout = l.qout;
-  a.cout = l.cout;
-  a.cclr = l.cclr;
-  a.tst = l.tst;
-  a.n = l.n;
-  a.nw = l.nw;
-  a.nnz = l.nnz;
-  a.n_in = l.n_in;
-  a.d = l.d;
-  return a;
-}
-
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 inline unsigned persistent_grid(int64_t work_blocks) {
@@ -744,75 +914,55 @@ inline unsigned persistent_grid(int64_t work_blocks) {
   return (unsigned)(work_blocks < kMaxGrid ? work_blocks : kMaxGrid);
 }
 
-template <int W>
-void push_wave_launch(const Args& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_push_wave<W>, dim3(persistent_grid(cdiv(a.n_in, kBlock))), dim3(kBlock), 0,
-                     s, a);
-}
-
 }  // namespace
+
+int32_t level_participants(int kernel, int64_t n_in, const BfsBase& b) { return level_grid(kernel, n_in, b); }
+
+// Grid of the any-variant level kernel: enough workgroups for a pull over all
+// bitmap words and for a lane per vertex, at most kMaxGrid.
+int32_t level_kernel_grid(int64_t n, int64_t nw) {
+  const int64_t pull_blocks = cdiv(cdiv(nw, kPullChunk), kWaves);
+  const int64_t vert_blocks = cdiv(n, kBlock);
+  return (int32_t)persistent_grid(pull_blocks > vert_blocks ? pull_blocks : vert_blocks);
+}
 
 bool kernel_is_pull(int k) { return k == GSW_K_PULL_BITMAP; }
 
-gsw_status launch_init(const gsw_graph* g, int32_t* level, int32_t* parent, int32_t source,
+gsw_status launch_init(const gsw_graph* g, const BfsBase& b, int32_t source, int32_t k0, int32_t flags0,
                        hipStream_t s) {
-  const Workspace& w = g->ws;
   int64_t blocks = cdiv(g->n, kBlock * 4);
   if (blocks < cdiv(4 * kCtrSlot, kBlock)) blocks = cdiv(4 * kCtrSlot, kBlock);
   const unsigned grid = (unsigned)(blocks > 65536 ? 65536 : blocks);
-  hipLaunchKernelGGL(k_init, dim3(grid), dim3(kBlock), 0, s, level, parent, w.vis, w.bm[0], g->iso,
-                     w.q[0], w.ctr, g->n, w.nw, source);
+  hipLaunchKernelGGL(k_init, dim3(grid), dim3(kBlock), 0, s, b, (const u64*)g->iso, source, k0, flags0);
   GSW_HIP(hipGetLastError());
   return GSW_OK;
 }
 
-// With l.tst set, the level's kernels stamp their workgroups' start and end
-// (push_edge: its first phase starts, its last phase ends the interval).
-gsw_status launch_level(const gsw_graph* g, int kernel, const LevelLaunch& l, hipStream_t s) {
-  const Args a = to_args(l);
-  switch (kernel) {
-    case GSW_K_PUSH_VERTEX:
-      hipLaunchKernelGGL(k_push_vertex, dim3(persistent_grid(cdiv(a.n_in, kBlock))), dim3(kBlock),
-                         0, s, a);
-      break;
-    case GSW_K_PUSH_WAVE4: push_wave_launch<4>(a, s); break;
-    case GSW_K_PUSH_WAVE8: push_wave_launch<8>(a, s); break;
-    case GSW_K_PUSH_WAVE16: push_wave_launch<16>(a, s); break;
-    case GSW_K_PUSH_WAVE32: push_wave_launch<32>(a, s); break;
-    case GSW_K_PUSH_WAVE64: push_wave_launch<64>(a, s); break;
-    case GSW_K_PUSH_EDGE: {
-      const Workspace& w = g->ws;
-      const int64_t nb = cdiv(a.n_in, kScanTile);
-      hipLaunchKernelGGL(k_edge_scan_local, dim3((unsigned)nb), dim3(kBlock), 0, s, a, w.scan,
-                         w.ebeg, w.bsum);
-      hipLaunchKernelGGL(k_edge_scan_blocks, dim3(1), dim3(1024), 0, s, w.bsum, nb, w.etot);
-      hipLaunchKernelGGL(k_edge_expand, dim3(kMaxGrid), dim3(kBlock), 0, s, a, w.scan, w.ebeg,
-                         w.bsum, w.etot);
-      break;
-    }
-    case GSW_K_PULL_BITMAP:
-      hipLaunchKernelGGL(k_pull, dim3(persistent_grid(cdiv(cdiv(a.nw, kPullChunk), kWaves))), dim3(kBlock), 0, s, a);
-      break;
-    case GSW_K_VERTEX_SCAN:
-      hipLaunchKernelGGL(k_vertex_scan, dim3(persistent_grid(cdiv(a.n, kBlock))), dim3(kBlock), 0,
-                         s, a);
-      break;
-    case GSW_K_EDGE_SCAN:
-      hipLaunchKernelGGL(k_edge_scan, dim3(persistent_grid(cdiv(a.nnz, kBlock))), dim3(kBlock), 0,
-                         s, a);
-      break;
-    default:
-      return fail(GSW_EINVAL, "unknown kernel id %d", kernel);
-  }
+gsw_status launch_level_auto(const gsw_graph* g, const BfsBase& b, const BfsPolicy& p, hipStream_t s) {
+  (void)g;
+  hipLaunchKernelGGL(k_level_auto, dim3((unsigned)b.grid_max), dim3(kBlock), 0, s, b, p);
   GSW_HIP(hipGetLastError());
   return GSW_OK;
 }
 
-gsw_status launch_frontier_bitmap(const gsw_graph* g, const int32_t* level, int32_t d,
-                                  unsigned long long* bm, hipStream_t s) {
-  const int64_t nw = g->ws.nw;
-  hipLaunchKernelGGL(k_frontier_bitmap, dim3(persistent_grid(cdiv(nw, kWaves))), dim3(kBlock), 0, s,
-                     level, d, bm, g->n, nw);
+gsw_status launch_level_edge(const gsw_graph* g, const BfsBase& b, const BfsPolicy& p, int32_t d,
+                             uint32_t n_in, bool force_bitmap, hipStream_t s) {
+  const Workspace& w = g->ws;
+  Args a = make_args(b, d, n_in, 0, kMaxGrid);
+  const int64_t nb = cdiv(n_in, kScanTile) > 0 ? cdiv(n_in, kScanTile) : 1;
+  hipLaunchKernelGGL(k_edge_scan_local, dim3((unsigned)nb), dim3(kBlock), 0, s, a, w.scan, w.ebeg, w.bsum);
+  hipLaunchKernelGGL(k_edge_scan_blocks, dim3(1), dim3(1024), 0, s, w.bsum, nb, w.etot);
+  hipLaunchKernelGGL(k_edge_expand, dim3(kMaxGrid), dim3(kBlock), 0, s, a, (const int64_t*)w.scan,
+                     (const int64_t*)w.ebeg, (const int64_t*)w.bsum, (const u64*)w.etot, p, b);
+  hipLaunchKernelGGL(k_rebuild_bitmap, dim3(persistent_grid(cdiv(b.nw, kWaves))), dim3(kBlock), 0, s, b,
+                     force_bitmap ? 1 : 0);
+  GSW_HIP(hipGetLastError());
+  return GSW_OK;
+}
+
+gsw_status launch_rebuild_bitmap(const gsw_graph* g, const BfsBase& b, hipStream_t s) {
+  (void)g;
+  hipLaunchKernelGGL(k_rebuild_bitmap, dim3(persistent_grid(cdiv(b.nw, kWaves))), dim3(kBlock), 0, s, b, 1);
   GSW_HIP(hipGetLastError());
   return GSW_OK;
 }
@@ -821,13 +971,6 @@ gsw_status launch_isolated(const gsw_graph* g, unsigned long long* iso, hipStrea
   const int64_t nw = (g->n + 63) / 64;
   hipLaunchKernelGGL(k_isolated, dim3(persistent_grid(cdiv(nw, kWaves))), dim3(kBlock), 0, s,
                      g->offs, iso, g->n, nw);
-  GSW_HIP(hipGetLastError());
-  return GSW_OK;
-}
-
-gsw_status launch_finalize(const uint32_t* cslot, uint32_t* d_flag, unsigned long long* tst,
-                           unsigned long long* ticks, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, cslot, d_flag, tst, ticks);
   GSW_HIP(hipGetLastError());
   return GSW_OK;
 }
