@@ -207,8 +207,12 @@ gsw_status gsw_tree_predict(const gsw_tree *t, const double x[GSW_N_FEATURES], i
  *   trace    host array of trace_cap rows or NULL; *trace_len (may be NULL)
  *            receives the number of rows produced, which can exceed
  *            trace_cap (extra rows are dropped).
- * The host drives the level loop: after each level it reads the new frontier
- * size, computes the features and asks the policy for the next kernel.
+ * The policy is applied on the device: at the end of each level the last
+ * workgroup computes the features of the next level, picks its kernel and
+ * posts a record (the trace row) to mapped host memory, so the host queues
+ * levels ahead; it launches the push_edge levels itself.  The policy, the
+ * unknown rule and the float32 feature comparison are those of
+ * gsw_tree_predict.
  */
 gsw_status gsw_bfs(const gsw_graph *g, const int32_t *sources, int32_t n_sources, int32_t *levels,
                    int32_t *parents, gsw_level_trace *trace, int32_t trace_cap,
@@ -218,7 +222,9 @@ gsw_status gsw_bfs(const gsw_graph *g, const int32_t *sources, int32_t n_sources
  * Per-level timing of every listed kernel from the same BFS state (the
  * training data of Section IV-A).  At each level the state is saved, each
  * kernel in kernels[0..n_kernels) runs `reps` times from the saved state and
- * times[level*n_kernels + k] receives the median kernel time in ms; then the
+ * times[level*n_kernels + k] receives the median level time in ms (for
+ * push_edge, from the device waiting for the host's launch, as gsw_bfs runs
+ * it; the other kernels' levels are queued ahead there); then the
  * BFS advances one level with advance_kernel (or, when advance_kernel < 0,
  * with the fastest kernel just measured).  frontier[level] receives
  * n_f(level).  Stops at max_levels rows (GSW_ERANGE if the BFS is longer).

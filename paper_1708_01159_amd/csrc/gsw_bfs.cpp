@@ -70,27 +70,27 @@ gsw_status check_kernel(const gsw_graph* g, int k) {
 gsw_status ensure_tree(gsw_graph* g, const gsw_tree* t) {
   Workspace& w = g->ws;
   if (w.tree_id == t->id) return GSW_OK;
+  if (t->n_nodes > kMaxTreeNodes) return fail(GSW_EINVAL, "tree of %d nodes: at most %d", t->n_nodes, kMaxTreeNodes);
   if (w.tree_cap < t->n_nodes) {
     if (w.d_tree) (void)hipFree(w.d_tree);
     if (w.d_thr) (void)hipFree(w.d_thr);
     w.d_tree = nullptr;
     w.d_thr = nullptr;
     w.tree_cap = 0;
-    if (hipMalloc((void**)&w.d_tree, (size_t)t->n_nodes * 4 * sizeof(int32_t)) != hipSuccess ||
+    if (hipMalloc((void**)&w.d_tree, (size_t)t->n_nodes * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc((void**)&w.d_thr, (size_t)t->n_nodes * sizeof(double)) != hipSuccess) {
       (void)hipGetLastError();
       return fail(GSW_ENOMEM, "hipMalloc for the device copy of the tree failed");
     }
     w.tree_cap = t->n_nodes;
   }
-  std::vector<int32_t> nodes((size_t)t->n_nodes * 4);
+  std::vector<unsigned long long> nodes((size_t)t->n_nodes);
   for (int32_t i = 0; i < t->n_nodes; ++i) {
-    nodes[(size_t)i * 4 + 0] = t->feature[(size_t)i];
-    nodes[(size_t)i * 4 + 1] = t->left[(size_t)i];
-    nodes[(size_t)i * 4 + 2] = t->right[(size_t)i];
-    nodes[(size_t)i * 4 + 3] = t->leaf_kernel[(size_t)i];
+    const bool leaf = t->left[(size_t)i] == -1;
+    nodes[(size_t)i] = tree_node_pack(t->left[(size_t)i], t->right[(size_t)i], leaf ? 0 : t->feature[(size_t)i],
+                                      t->leaf_kernel[(size_t)i]);
   }
-  GSW_HIP(hipMemcpy(w.d_tree, nodes.data(), nodes.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  GSW_HIP(hipMemcpy(w.d_tree, nodes.data(), nodes.size() * sizeof(unsigned long long), hipMemcpyHostToDevice));
   GSW_HIP(hipMemcpy(w.d_thr, t->threshold.data(), (size_t)t->n_nodes * sizeof(double), hipMemcpyHostToDevice));
   w.tree_id = t->id;
   return GSW_OK;
@@ -419,10 +419,15 @@ gsw_status gsw_bfs_profile(const gsw_graph* cg, int32_t source, const int32_t* k
       GSW_HIP(hipStreamSynchronize(s));  // the staging copy is reused by the next restore
       return GSW_OK;
     };
-    // one level with kernel k; after push_edge the next level's bitmap is
-    // rebuilt (outside the timed bracket) so any kernel can follow
+    // one level with kernel k, timed as the level loop runs it: the other
+    // kernels' levels are queued ahead of time, while a push_edge level is
+    // launched by the host after the previous level's record, so its
+    // bracket starts with the device idle and includes the launch latency
     auto run = [&](int k, bool timed_bracket) -> gsw_status {
-      if (timed_bracket) GSW_HIP(hipEventRecord(w.ev[0], s));
+      if (timed_bracket) {
+        GSW_HIP(hipEventRecord(w.ev[0], s));
+        if (k == GSW_K_PUSH_EDGE) GSW_HIP(hipEventSynchronize(w.ev[0]));
+      }
       if (k == GSW_K_PUSH_EDGE)
         GSW_TRY(launch_level_edge(g, b, dp, d, (uint32_t)nf, false, s));
       else

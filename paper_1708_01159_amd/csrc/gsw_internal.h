@@ -63,7 +63,7 @@ struct Workspace {
   BfsCtl* h_ctl = nullptr;               // pinned staging for control-block uploads (profiling)
   unsigned long long* ring = nullptr;    // mapped host memory: per-level records
   unsigned long long* d_ring = nullptr;  // the same memory as seen by the device
-  int32_t* d_tree = nullptr;             // device copy of the tree's nodes (4 ints each) ...
+  unsigned long long* d_tree = nullptr;  // device copy of the tree's nodes (packed) ...
   double* d_thr = nullptr;               // ... and thresholds
   int32_t tree_cap = 0;                  // nodes the device copy has room for
   uint64_t tree_id = 0;                  // tree currently uploaded (0: none)
@@ -139,7 +139,7 @@ struct BfsPolicy {
   int32_t has_origin;        // edge_scan can run (its origin array exists)
   int32_t pad;
   const int32_t* sched;      // device copy of the schedule
-  const int32_t* t_node;     // tree nodes: feature, left, right, leaf kernel (-1 undecided)
+  const unsigned long long* t_node;  // tree nodes, packed (see tree_node_pack)
   const double* t_thr;       // tree thresholds
   int32_t t_nodes;           // nodes of the tree
   int32_t pad2;
@@ -164,6 +164,15 @@ struct BfsBase {
   int32_t timed;                   // record each level's duration
   int32_t grid_max;                // workgroups of a level-kernel launch
 };
+
+// A tree node in 8 bytes for the device walk: left and right child (int16,
+// -1 at a leaf), feature index, leaf kernel + 1 (0 when the leaf's classes
+// tie).  Trees of up to 32767 nodes.
+inline unsigned long long tree_node_pack(int32_t left, int32_t right, int32_t feature, int32_t leaf_kernel) {
+  return (unsigned long long)(uint16_t)(int16_t)left | ((unsigned long long)(uint16_t)(int16_t)right << 16) |
+         ((unsigned long long)(uint8_t)feature << 32) | ((unsigned long long)(uint8_t)(leaf_kernel + 1) << 40);
+}
+constexpr int32_t kMaxTreeNodes = 32767;
 
 // Host ring of per-level records: record of level d at (d % kBfsRing) * kBfsRec.
 constexpr int kBfsRing = 8;

@@ -252,10 +252,42 @@ __device__ __forceinline__ void settle(const Args& a, int32_t v, int32_t u) {
   if (a.set_nx) atomicOr(a.nx + (v >> 6), 1ull << (v & 63));
 }
 
-__device__ __forceinline__ void visit(Stage& s, const Args& a, int32_t v, int32_t u) {
-  const bool win = claim(a.vis, v);
-  if (win) settle(a, v, u);
-  stage_push(s, a, win, v);
+// Arcs a lane keeps in flight: the column loads, visited-word loads and
+// claiming atomics of kBatch arcs are issued before any result is used, so a
+// lane walking a short row pays the memory latency once per batch instead of
+// once per arc.
+constexpr int kBatch = 4;
+
+// Visits the pairs (v[q], u[q]) with v[q] >= 0.  Every active lane of the
+// wave calls it with the same control flow.
+__device__ __forceinline__ void visit_batch(Stage& s, const Args& a, const int32_t (&v)[kBatch],
+                                            const int32_t (&u)[kBatch]) {
+  u64 w[kBatch], old[kBatch];
+#pragma unroll
+  for (int q = 0; q < kBatch; ++q) w[q] = v[q] >= 0 ? a.vis[v[q] >> 6] : ~0ull;
+#pragma unroll
+  for (int q = 0; q < kBatch; ++q) {
+    const u64 bit = 1ull << (v[q] & 63);
+    old[q] = (w[q] & bit) ? bit : atomicOr(a.vis + (v[q] >> 6), bit);
+  }
+#pragma unroll
+  for (int q = 0; q < kBatch; ++q) {
+    const bool win = v[q] >= 0 && !(old[q] & (1ull << (v[q] & 63)));
+    if (win) settle(a, v[q], u[q]);
+    stage_push(s, a, win, v[q]);
+  }
+}
+
+// Arcs e0, e0 + step, ... below e1 of row u.
+__device__ __forceinline__ void visit_row(Stage& s, const Args& a, int64_t e0, int64_t e1, int64_t step,
+                                          int32_t u) {
+  const int32_t us[kBatch] = {u, u, u, u};
+  for (int64_t e = e0; e < e1; e += kBatch * step) {
+    int32_t v[kBatch];
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) v[q] = e + q * step < e1 ? a.cols[e + q * step] : -1;
+    visit_batch(s, a, v, us);
+  }
 }
 
 // ------------------------------------------------- next-kernel choice
@@ -273,7 +305,7 @@ __device__ __forceinline__ double feature(const BfsPolicy& p, int i, double nf, 
 
 // Kernel for level d (d >= 1) with frontier nf and nf + earlier discoveries
 // = disc; prev = kernel of level d-1.  The same rules as the host's choice.
-__device__ int choose_next(const BfsPolicy& p, const int32_t* t_node, const double* t_thr, int32_t d,
+__device__ __forceinline__ int choose_next(const BfsPolicy& p, const u64* t_node, const double* t_thr, int32_t d,
                            long long nf, long long disc, int prev, int32_t* flags) {
   *flags = 0;
   int k = GSW_DEFAULT_KERNEL;
@@ -283,13 +315,16 @@ __device__ int choose_next(const BfsPolicy& p, const int32_t* t_node, const doub
     k = p.sched[d < p.sched_len ? d : p.sched_len - 1];
   } else {
     int node = 0;
+    u64 nd = t_node[0];
     for (;;) {
-      const int32_t* nd = t_node + 4 * node;
-      if (nd[1] == -1) break;
-      const double xv = (double)(float)feature(p, nd[0], (double)nf, (double)disc);
-      node = xv <= t_thr[node] ? nd[1] : nd[2];
+      const int left = (int)(int16_t)(uint16_t)(nd & 0xffffull);
+      if (left == -1) break;
+      const int right = (int)(int16_t)(uint16_t)((nd >> 16) & 0xffffull);
+      const double xv = (double)(float)feature(p, (int)((nd >> 32) & 0xffull), (double)nf, (double)disc);
+      node = xv <= t_thr[node] ? left : right;
+      nd = t_node[node];
     }
-    const int leaf = t_node[4 * node + 3];
+    const int leaf = (int)((nd >> 40) & 0xffull) - 1;
     if (leaf >= 0) {
       k = leaf;
     } else {
@@ -313,8 +348,9 @@ __device__ int choose_next(const BfsPolicy& p, const int32_t* t_node, const doub
 // finished, so the last one sees every segment's final size.  That
 // workgroup first copies the tree into `lds` (lds_bytes of LDS free by now,
 // the flushed append stage) with all its threads, so the walk does not pay
-// a global-memory round trip per node.
-__device__ void level_end(const Args& a, const BfsBase* base, const BfsPolicy& p, u64* ring, int k_run,
+// a global-memory round trip per node (8 bytes and a threshold per node:
+// 512 nodes fit the 8 KiB stage).
+__device__ __forceinline__ void level_end(const Args& a, const BfsBase* base, const BfsPolicy& p, u64* ring, int k_run,
                           void* lds, int lds_bytes) {
   __shared__ uint32_t s_last;
   __shared__ uint32_t s_nn;
@@ -337,13 +373,12 @@ __device__ void level_end(const Args& a, const BfsBase* base, const BfsPolicy& p
   __syncthreads();
   if (!s_last) return;
   const int tid = threadIdx.x;
-  const bool tree_lds = p.policy == GSW_POLICY_TREE && p.t_nodes * 24 <= lds_bytes;
-  int32_t* l_node = reinterpret_cast<int32_t*>(lds);
-  double* l_thr = reinterpret_cast<double*>(l_node + 4 * (tree_lds ? p.t_nodes : 0));
+  const bool tree_lds = p.policy == GSW_POLICY_TREE && p.t_nodes * 16 <= lds_bytes;
+  u64* l_node = reinterpret_cast<u64*>(lds);
+  double* l_thr = reinterpret_cast<double*>(l_node + (tree_lds ? p.t_nodes : 0));
   if (tree_lds) {
     for (int i = tid; i < p.t_nodes; i += kBlock) {
-      const int4 nd = reinterpret_cast<const int4*>(p.t_node)[i];
-      reinterpret_cast<int4*>(l_node)[i] = nd;
+      l_node[i] = p.t_node[i];
       l_thr[i] = p.t_thr[i];
     }
   }
@@ -436,10 +471,105 @@ __global__ void __launch_bounds__(kBlock) k_init(BfsBase b, const u64* __restric
   if (gid < kDoneGroups) b.done[gid * kCtrStride] = 0u;
 }
 
+// ------------------------------------------------------------ long rows
+// The queue- and vertex-driven variants give a frontier row to one lane (or
+// to W lanes).  A row that would take that walk more than kLongTrips trips is
+// set aside instead and, at the end of the round, walked by the whole
+// workgroup: its kBlock lanes spread over the arcs of every set-aside row
+// (an LDS prefix sum over their lengths, then a binary search per arc).  A
+// hub in the frontier then costs a workgroup's pass over its arcs rather
+// than one lane's serial walk; rows within the limit are walked as the
+// variant defines.
+constexpr int kLongTrips = 32;
+
+struct LongRows {
+  int64_t beg[kBlock];
+  int64_t pre[kBlock + 1];  // row lengths, then their exclusive prefix sum
+  int64_t wsum[kWaves];
+  int32_t u[kBlock];
+  uint32_t n[3];  // set-aside count of round r in n[r % 3]
+};
+
+// Every thread of the workgroup calls it once before the first round.
+__device__ __forceinline__ void long_init(LongRows& L) {
+  if (threadIdx.x < 3) L.n[threadIdx.x] = 0u;
+  __syncthreads();
+}
+
+// Round r's counter is n[r % 3]; thread 0 zeroes n[(r + 1) % 3] at the start
+// of round r.  Its last readers (round r - 2) passed round r - 1's barrier
+// before thread 0 did, and its next writers (round r + 1) come after round
+// r's barrier, so no other barrier is needed when nothing was set aside.
+__device__ __forceinline__ void long_round_begin(LongRows& L, uint32_t r) {
+  if (threadIdx.x == 0) L.n[(r + 1) % 3] = 0u;
+}
+
+// Sets row [beg, end) of u aside when it is longer than limit arcs; each
+// thread sets aside at most one row per round.
+__device__ __forceinline__ bool long_defer(LongRows& L, uint32_t r, int32_t u, int64_t beg, int64_t end,
+                                           int64_t limit) {
+  if (end - beg <= limit) return false;
+  const uint32_t k = atomicAdd(&L.n[r % 3], 1u);
+  L.u[k] = u;
+  L.beg[k] = beg;
+  L.pre[k] = end - beg;
+  return true;
+}
+
+// Walks round r's set-aside rows with the whole workgroup.  Every thread
+// calls it (uniform control flow).
+__device__ __forceinline__ void long_walk(LongRows& L, uint32_t r, Stage& st, const Args& a) {
+  __syncthreads();
+  const uint32_t n = L.n[r % 3];
+  if (n == 0u) return;
+  const int t = threadIdx.x;
+  const int lane = lane_id();
+  const int wave = t >> 6;
+  const int64_t len = (uint32_t)t < n ? L.pre[t] : 0;
+  int64_t inc = len;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t y = __shfl_up(inc, off);
+    if (lane >= off) inc += y;
+  }
+  if (lane == 63) L.wsum[wave] = inc;
+  __syncthreads();  // every length is read before the prefix sums overwrite them
+  int64_t below = 0, total = 0;
+  for (int w = 0; w < kWaves; ++w) {
+    below += w < wave ? L.wsum[w] : 0;
+    total += L.wsum[w];
+  }
+  if ((uint32_t)t < n) L.pre[t + 1] = below + inc;
+  if (t == 0) L.pre[0] = 0;
+  __syncthreads();
+  for (int64_t e0 = t; e0 < total; e0 += kBatch * kBlock) {
+    int32_t v[kBatch], u[kBatch];
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      const int64_t e = e0 + (int64_t)q * kBlock;
+      v[q] = -1;
+      u[q] = 0;
+      if (e < total) {
+        uint32_t lo = 0, hi = n;  // last row whose prefix is <= e
+        while (hi - lo > 1u) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (L.pre[mid] <= e) lo = mid; else hi = mid;
+        }
+        v[q] = a.cols[L.beg[lo] + (e - L.pre[lo])];
+        u[q] = L.u[lo];
+      }
+    }
+    visit_batch(st, a, v, u);
+  }
+  __syncthreads();  // the rows are read before the next round sets new ones aside
+}
+
 // ------------------------------------------------- push_vertex (lane / vertex)
-__device__ __forceinline__ void body_push_vertex(const Args& a, Stage& st, const QueueIn& qi) {
+__device__ __forceinline__ void body_push_vertex(const Args& a, Stage& st, const QueueIn& qi, LongRows& L) {
   const uint32_t stride = (uint32_t)a.grid * kBlock;
-  for (uint32_t base = blockIdx.x * kBlock; base < a.n_in; base += stride) {
+  long_init(L);
+  uint32_t r = 0;
+  for (uint32_t base = blockIdx.x * kBlock; base < a.n_in; base += stride, ++r) {
+    long_round_begin(L, r);
     const uint32_t i = base + threadIdx.x;
     int32_t u = 0;
     int64_t beg = 0, end = 0;
@@ -447,8 +577,10 @@ __device__ __forceinline__ void body_push_vertex(const Args& a, Stage& st, const
       u = queue_at(a, qi, i);
       beg = a.offs[u];
       end = a.offs[u + 1];
+      if (long_defer(L, r, u, beg, end, kLongTrips)) end = beg;
     }
-    for (int64_t e = beg; e < end; ++e) visit(st, a, a.cols[e], u);
+    visit_row(st, a, beg, end, 1, u);
+    long_walk(L, r, st, a);
   }
 }
 
@@ -457,12 +589,15 @@ __device__ __forceinline__ void body_push_vertex(const Args& a, Stage& st, const
 // lanes takes W frontier vertices and walks their rows one after another,
 // the W lanes striding over each row together.
 template <int W>
-__device__ __forceinline__ void body_push_wave(const Args& a, Stage& st, const QueueIn& qi) {
+__device__ __forceinline__ void body_push_wave(const Args& a, Stage& st, const QueueIn& qi, LongRows& L) {
   const int lane = lane_id();
   const int sub = lane & (W - 1);
   const int first = lane & ~(W - 1);
   const uint32_t stride = (uint32_t)a.grid * kBlock;
-  for (uint32_t base = blockIdx.x * kBlock; base < a.n_in; base += stride) {
+  long_init(L);
+  uint32_t r = 0;
+  for (uint32_t base = blockIdx.x * kBlock; base < a.n_in; base += stride, ++r) {
+    long_round_begin(L, r);
     const uint32_t i = base + threadIdx.x;  // this lane's own entry
     int32_t u = 0;
     int64_t beg = 0, end = 0;
@@ -470,14 +605,16 @@ __device__ __forceinline__ void body_push_wave(const Args& a, Stage& st, const Q
       u = queue_at(a, qi, i);
       beg = a.offs[u];
       end = a.offs[u + 1];
+      if (long_defer(L, r, u, beg, end, (int64_t)kLongTrips * W)) end = beg;
     }
     for (int j = 0; j < W; ++j) {
       const int src = first + j;
       const int32_t uj = __shfl(u, src);
       const int64_t bj = __shfl(beg, src);
       const int64_t ej = __shfl(end, src);
-      for (int64_t e = bj + sub; e < ej; e += W) visit(st, a, a.cols[e], uj);
+      visit_row(st, a, bj + sub, ej, W, uj);
     }
+    long_walk(L, r, st, a);
   }
 }
 
@@ -783,16 +920,21 @@ __device__ __forceinline__ void body_pull(const Args& a, Stage& st, u64 (*s_foun
 }
 
 // ------------------------------------------ vertex_scan (lane / vertex, all n)
-__device__ __forceinline__ void body_vertex_scan(const Args& a, Stage& st) {
+__device__ __forceinline__ void body_vertex_scan(const Args& a, Stage& st, LongRows& L) {
   const int64_t stride = (int64_t)a.grid * kBlock;
-  for (int64_t base = (int64_t)blockIdx.x * kBlock; base < a.n; base += stride) {
+  long_init(L);
+  uint32_t r = 0;
+  for (int64_t base = (int64_t)blockIdx.x * kBlock; base < a.n; base += stride, ++r) {
+    long_round_begin(L, r);
     const int64_t v = base + threadIdx.x;
     int64_t beg = 0, end = 0;
     if (v < a.n && a.level[v] == a.d) {
       beg = a.offs[v];
       end = a.offs[v + 1];
+      if (long_defer(L, r, (int32_t)v, beg, end, kLongTrips)) end = beg;
     }
-    for (int64_t e = beg; e < end; ++e) visit(st, a, a.cols[e], (int32_t)v);
+    visit_row(st, a, beg, end, 1, (int32_t)v);
+    long_walk(L, r, st, a);
   }
 }
 
@@ -824,6 +966,7 @@ __global__ void __launch_bounds__(kBlock) k_level_auto(BfsBase b, BfsPolicy p) {
   __shared__ Stage st;
   __shared__ QueueIn qi;
   __shared__ u64 s_found[kWaves][kPullChunk];
+  __shared__ LongRows lr;
   const int k = b.ctl->kernel;
   if (k < 0 || k >= GSW_N_KERNELS || k == GSW_K_PUSH_EDGE) return;
   const int32_t d = b.ctl->d;
@@ -839,14 +982,14 @@ __global__ void __launch_bounds__(kBlock) k_level_auto(BfsBase b, BfsPolicy p) {
     a.n_in = qi.pre[kQueueBins];
   }
   switch (k) {
-    case GSW_K_PUSH_VERTEX: body_push_vertex(a, st, qi); break;
-    case GSW_K_PUSH_WAVE4: body_push_wave<4>(a, st, qi); break;
-    case GSW_K_PUSH_WAVE8: body_push_wave<8>(a, st, qi); break;
-    case GSW_K_PUSH_WAVE16: body_push_wave<16>(a, st, qi); break;
-    case GSW_K_PUSH_WAVE32: body_push_wave<32>(a, st, qi); break;
-    case GSW_K_PUSH_WAVE64: body_push_wave<64>(a, st, qi); break;
+    case GSW_K_PUSH_VERTEX: body_push_vertex(a, st, qi, lr); break;
+    case GSW_K_PUSH_WAVE4: body_push_wave<4>(a, st, qi, lr); break;
+    case GSW_K_PUSH_WAVE8: body_push_wave<8>(a, st, qi, lr); break;
+    case GSW_K_PUSH_WAVE16: body_push_wave<16>(a, st, qi, lr); break;
+    case GSW_K_PUSH_WAVE32: body_push_wave<32>(a, st, qi, lr); break;
+    case GSW_K_PUSH_WAVE64: body_push_wave<64>(a, st, qi, lr); break;
     case GSW_K_PULL_BITMAP: body_pull(a, st, s_found); break;
-    case GSW_K_VERTEX_SCAN: body_vertex_scan(a, st); break;
+    case GSW_K_VERTEX_SCAN: body_vertex_scan(a, st, lr); break;
     default: body_edge_scan(a, st); break;
   }
   stage_flush(st, a);

@@ -39,29 +39,30 @@ FEATURES = gsw.FEATURE_NAMES
 
 # (name, maker, sources) -- other seeds / sizes than the evaluated workloads
 TRAIN_GRAPHS = [
-    ("rmat16_s100", lambda: gg.rmat(16, 16, seed=100), 8),
-    ("rmat18_s101", lambda: gg.rmat(18, 16, seed=101), 8),
-    ("rmat20_s102", lambda: gg.rmat(20, 16, seed=102), 8),
-    ("rmat21_ef8_s103", lambda: gg.rmat(21, 8, seed=103), 8),
-    ("rmat21_s104", lambda: gg.rmat(21, 16, seed=104), 8),
-    ("rmat19_ef32_s105", lambda: gg.rmat(19, 32, seed=105), 8),
-    ("rmat20_flat_s106", lambda: gg.rmat(20, 16, 0.45, 0.22, 0.22, seed=106), 8),
+    ("rmat16_s100", lambda: gg.rmat(16, 16, seed=100), 12),
+    ("rmat18_s101", lambda: gg.rmat(18, 16, seed=101), 12),
+    ("rmat20_s102", lambda: gg.rmat(20, 16, seed=102), 16),
+    ("rmat21_ef8_s103", lambda: gg.rmat(21, 8, seed=103), 16),
+    ("rmat21_s104", lambda: gg.rmat(21, 16, seed=104), 16),
+    ("rmat19_ef32_s105", lambda: gg.rmat(19, 32, seed=105), 12),
+    ("rmat20_flat_s106", lambda: gg.rmat(20, 16, 0.45, 0.22, 0.22, seed=106), 12),
     ("grid256_del5_s200", lambda: gg.grid(256, 256, 0.05, seed=200), 3),
     ("grid512x256_del2_s201", lambda: gg.grid(512, 256, 0.02, seed=201), 2),
     ("grid1024_del5_s202", lambda: gg.grid(1024, 1024, 0.05, seed=202), 2),
-    ("chunglu18_s300", lambda: gg.chung_lu(1 << 18, 2.1, 20.0, seed=300), 8),
-    ("chunglu20_s301", lambda: gg.chung_lu(1 << 20, 2.1, 20.0, seed=301), 8),
-    ("chunglu21_g25_s302", lambda: gg.chung_lu(1 << 21, 2.5, 10.0, seed=302), 8),
-    ("er18_d8_s400", lambda: gg.erdos_renyi(1 << 18, 4 << 18, seed=400), 8),
-    ("er20_d8_s401", lambda: gg.erdos_renyi(1 << 20, 4 << 20, seed=401), 8),
-    ("er21_d4_s402", lambda: gg.erdos_renyi(1 << 21, 2 << 21, seed=402), 8),
-    ("er20_d32_s403", lambda: gg.erdos_renyi(1 << 20, 16 << 20, seed=403), 8),
+    ("chunglu18_s300", lambda: gg.chung_lu(1 << 18, 2.1, 20.0, seed=300), 12),
+    ("chunglu20_s301", lambda: gg.chung_lu(1 << 20, 2.1, 20.0, seed=301), 12),
+    ("chunglu21_g25_s302", lambda: gg.chung_lu(1 << 21, 2.5, 10.0, seed=302), 12),
+    ("er18_d8_s400", lambda: gg.erdos_renyi(1 << 18, 4 << 18, seed=400), 16),
+    ("er20_d8_s401", lambda: gg.erdos_renyi(1 << 20, 4 << 20, seed=401), 16),
+    ("er21_d4_s402", lambda: gg.erdos_renyi(1 << 21, 2 << 21, seed=402), 16),
+    ("er20_d32_s403", lambda: gg.erdos_renyi(1 << 20, 16 << 20, seed=403), 16),
     # the evaluated sizes, at other seeds
-    ("rmat22_s200", lambda: gg.rmat(22, 16, seed=200), 12),
-    ("rmat22_s201", lambda: gg.rmat(22, 16, seed=201), 12),
+    ("rmat22_s200", lambda: gg.rmat(22, 16, seed=200), 32),
+    ("rmat22_s201", lambda: gg.rmat(22, 16, seed=201), 32),
+    ("rmat22_s202", lambda: gg.rmat(22, 16, seed=202), 32),
     ("grid2048_del5_s210", lambda: gg.grid(2048, 2048, 0.05, seed=210), 2),
-    ("chunglu23_s220", lambda: gg.chung_lu(1 << 23, 2.1, 20.0, seed=220), 8),
-    ("er22_d8_s230", lambda: gg.erdos_renyi(1 << 22, 4 << 22, seed=230), 8),
+    ("chunglu23_s220", lambda: gg.chung_lu(1 << 23, 2.1, 20.0, seed=220), 16),
+    ("er22_d8_s230", lambda: gg.erdos_renyi(1 << 22, 4 << 22, seed=230), 24),
 ]
 
 

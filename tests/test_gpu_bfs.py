@@ -141,6 +141,63 @@ def test_tree_policy_matches_oracle_walk(name):
             prev = k
 
 
+def _big_tree(depth=9, seed=17):
+    # complete binary tree (children 2i+1, 2i+2) on random features and
+    # thresholds near the features' ranges; leaves with a random class, a few tied
+    rng = np.random.default_rng(seed)
+    n_int = 2 ** depth - 1
+    n = 2 ** (depth + 1) - 1
+    left = [2 * i + 1 if i < n_int else -1 for i in range(n)]
+    right = [2 * i + 2 if i < n_int else -1 for i in range(n)]
+    feature = [int(rng.choice([8, 9, 10, 11])) if i < n_int else -2 for i in range(n)]
+    thr = []
+    for i in range(n):
+        f = feature[i]
+        thr.append(-2.0 if i >= n_int else float(rng.uniform(0, 1) if f in (9, 11) else rng.uniform(0, 3000)))
+    kernels = [gsw.PUSH_VERTEX, gsw.PUSH_WAVE8, gsw.PUSH_EDGE, gsw.PULL_BITMAP]
+    value = []
+    for i in range(n):
+        v = [0.0] * len(kernels)
+        if i >= n_int:
+            v[int(rng.integers(len(kernels)))] = 3.0
+            if rng.random() < 0.1:
+                v[(int(np.argmax(v)) + 1) % len(kernels)] = 3.0
+        else:
+            v = [1.0] * len(kernels)
+        value.append(v)
+    return dict(left=left, right=right, feature=feature, threshold=thr, value=value, class_kernel=kernels)
+
+
+@pytest.mark.parametrize("which", ["shipped", "big"])
+@pytest.mark.parametrize("name", ["rmat14", "grid", "chunglu"])
+def test_device_tree_walk_matches_oracle(name, which):
+    # the device walks the tree in LDS (up to 512 nodes) or in global memory
+    # (the 1023-node tree); every level's choice equals the oracle's walk
+    import json
+
+    g, G, srcs, refs, comp = case(name)
+    if which == "shipped":
+        from paper_1708_01159_amd import trees
+
+        T = json.load(open(trees.default_path()))
+        tree = trees.load_default()
+    else:
+        T = _big_tree()
+        tree = gsw.Tree(T)
+    assert len(T["left"]) > (512 if which == "big" else 100)
+    lv, pa, trace = gsw.bfs(G, srcs, policy="tree", tree=tree)
+    _check_result(g, srcs, refs, comp, lv, pa, trace)
+    gf = ofeat.graph_features(g.offs)
+    for i in range(len(srcs)):
+        hist = refs[i][2]
+        prev = gsw.DEFAULT_KERNEL
+        for t in [t for t in trace if t.source_idx == i]:
+            x = ofeat.level_features(g.offs, hist, t.level, gf)
+            k, unknown = otree.predict(T, x, prev, t.level, gsw.DEFAULT_KERNEL)
+            assert t.kernel == k and bool(t.flags & 1) == unknown, (t.level, t.kernel, k)
+            prev = k
+
+
 def test_level_features_match_oracle():
     g, G, srcs, refs, comp = case("rmat14")
     hist = refs[0][2]
