@@ -210,7 +210,8 @@ gsw_status gsw_tree_predict(const gsw_tree *t, const double x[GSW_N_FEATURES], i
  * The policy is applied on the device: at the end of each level the last
  * workgroup computes the features of the next level, picks its kernel and
  * posts a record (the trace row) to mapped host memory, so the host queues
- * levels ahead; it launches the push_edge levels itself.  The policy, the
+ * levels ahead (a push_edge level takes two launches of the level kernel:
+ * its prefix sum, then its expansion).  The policy, the
  * unknown rule and the float32 feature comparison are those of
  * gsw_tree_predict.
  */
@@ -222,9 +223,8 @@ gsw_status gsw_bfs(const gsw_graph *g, const int32_t *sources, int32_t n_sources
  * Per-level timing of every listed kernel from the same BFS state (the
  * training data of Section IV-A).  At each level the state is saved, each
  * kernel in kernels[0..n_kernels) runs `reps` times from the saved state and
- * times[level*n_kernels + k] receives the median level time in ms (for
- * push_edge, from the device waiting for the host's launch, as gsw_bfs runs
- * it; the other kernels' levels are queued ahead there); then the
+ * times[level*n_kernels + k] receives the median level time in ms (the
+ * level's launches as gsw_bfs queues them: two for push_edge); then the
  * BFS advances one level with advance_kernel (or, when advance_kernel < 0,
  * with the fastest kernel just measured).  frontier[level] receives
  * n_f(level).  Stops at max_levels rows (GSW_ERANGE if the BFS is longer).

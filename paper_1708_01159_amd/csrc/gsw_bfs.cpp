@@ -1,11 +1,11 @@
 // Level loop of the single-source BFS.  The device picks each next level's
 // kernel itself (the last workgroup of a level applies the policy and
-// writes the level control block) and posts a record per level to a ring in
-// mapped host memory; the host keeps a few level launches queued, reads the
-// records in order for the trace and the end of the search, and launches the
-// three push_edge kernels itself for the levels the device gives to
-// push_edge.  Also the per-level profiler that measures every kernel from
-// the same saved state (the training data of the decision tree).
+// writes the next launch's control slot) and posts a record per level to a
+// ring in mapped host memory; the host keeps a few launches of the level
+// kernel queued and reads the records in order for the trace and the end of
+// the search.  A push_edge level takes two launches, any other one.  Also
+// the per-level profiler that measures every kernel from the same saved
+// state (the training data of the decision tree).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -17,10 +17,10 @@
 namespace gsw {
 namespace {
 
-// Level launches queued beyond the last level whose record the host has
-// read; each runs one level or, when the device has named push_edge or
-// ended the search, nothing.
-constexpr int kAhead = 2;
+// Launches of the level kernel queued beyond those that the levels read so
+// far have used, plus one more when the next level is push_edge (two
+// launches).  Launches queued past the end of the search do nothing.
+constexpr int kAhead = 3;
 
 struct Policy {
   const gsw_bfs_opts* o;
@@ -150,6 +150,9 @@ BfsBase make_base(const gsw_graph* g, int32_t* lv, int32_t* pa, bool timed) {
   b.q[1] = w.q[1];
   b.ctr = w.ctr;
   b.done = w.done;
+  b.scan = w.scan;
+  b.ebeg = w.ebeg;
+  b.bsum = w.bsum;
   b.ring = w.d_ring;
   b.ctl = w.ctl;
   b.n = g->n;
@@ -160,19 +163,42 @@ BfsBase make_base(const gsw_graph* g, int32_t* lv, int32_t* pa, bool timed) {
   return b;
 }
 
+// A level's record, decoded.
+struct Record {
+  int kernel;
+  int32_t flags;
+  int64_t nf, disc, next;
+  unsigned long long ticks;
+  int next_kernel;  // kCtlDone when the search ended
+};
+
 // Waits until level d's record is in the ring.  Polls the stream for errors
 // now and then so a failed launch cannot leave the host spinning.
-gsw_status wait_record(const gsw_graph* g, int64_t d, hipStream_t s, const volatile unsigned long long** rec) {
+gsw_status wait_record(const gsw_graph* g, int64_t d, hipStream_t s, Record* rec) {
   const volatile unsigned long long* r = g->ws.ring + (size_t)(d % kBfsRing) * kBfsRec;
-  for (uint64_t it = 0;; ++it) {
-    if (r[kRecSeq] == (unsigned long long)d + 1ull) {
-      *rec = r;
-      return GSW_OK;
+  const unsigned long long tag = rec_tag(d);
+  auto take = [&]() -> bool {
+    unsigned long long v[kBfsRecWords];
+    for (int i = 0; i < kBfsRecWords; ++i) {
+      v[i] = r[i];
+      if ((v[i] & ~kRecValueMask) != tag) return false;
+      v[i] &= kRecValueMask;
     }
+    rec->kernel = (int)v[kRecKernel];
+    rec->flags = (int32_t)v[kRecFlags];
+    rec->nf = (int64_t)v[kRecNf];
+    rec->disc = (int64_t)v[kRecDisc];
+    rec->next = (int64_t)v[kRecNext];
+    rec->ticks = v[kRecTicks];
+    rec->next_kernel = (int)v[kRecNextKernel] - 1;
+    return true;
+  };
+  for (uint64_t it = 0;; ++it) {
+    if (take()) return GSW_OK;
     if ((it & 4095u) == 4095u) {
       const hipError_t e = hipStreamQuery(s);
       if (e == hipSuccess) {
-        if (r[kRecSeq] == (unsigned long long)d + 1ull) continue;
+        if (take()) return GSW_OK;
         return fail(GSW_EHIP, "level %lld finished without posting its record", (long long)d);
       }
       if (e != hipErrorNotReady) return fail(GSW_EHIP, "level %lld: %s", (long long)d, hipGetErrorString(e));
@@ -192,38 +218,35 @@ gsw_status run_levels(gsw_graph* g, const Policy& pol, const BfsPolicy& dp, int3
   const int k0 = pol.choose(g, 0, 1, 1, GSW_DEFAULT_KERNEL, &flags0);
   const BfsBase b = make_base(g, lv, pa, timed);
   GSW_TRY(launch_init(g, b, src, k0, flags0, s));
-  int ahead = 0;
-  if (k0 == GSW_K_PUSH_EDGE) GSW_TRY(launch_level_edge(g, b, dp, 0, 1u, false, s));
+  int32_t j = 0;     // launches of the level kernel so far
+  int ahead = 0;     // of those, not yet used by a level whose record was read
+  int want = kAhead + (k0 == GSW_K_PUSH_EDGE ? 1 : 0);
   for (int64_t d = 0;; ++d) {
-    while (ahead < kAhead) {
-      GSW_TRY(launch_level_auto(g, b, dp, s));
+    while (ahead < want) {
+      GSW_TRY(launch_level_auto(g, b, dp, j++, s));
       ++ahead;
     }
-    const volatile unsigned long long* r = nullptr;
+    Record r;
     GSW_TRY(wait_record(g, d, s, &r));
-    const int k = (int)(long long)r[kRecKernel];
-    const int64_t nn = (int64_t)r[kRecNext];
-    const int nk = (int)(long long)r[kRecNextKernel];
+    const int k = r.kernel;
+    const int64_t nn = r.next;
+    const int nk = r.next_kernel;
     if (trace && *rows < trace_cap) {
       gsw_level_trace& t = trace[*rows];
       t.source_idx = src_idx;
       t.level = (int32_t)d;
       t.kernel = k;
-      t.flags = (int32_t)r[kRecFlags];
-      t.n_frontier = (int64_t)r[kRecNf];
-      t.discovered = (int64_t)r[kRecDisc];
+      t.flags = r.flags;
+      t.n_frontier = r.nf;
+      t.discovered = r.disc;
       t.n_next = nn;
-      t.ms = timed ? (float)((double)r[kRecTicks] * w.tick_ms) : -1.0f;
+      t.ms = timed ? (float)((double)r.ticks * w.tick_ms) : -1.0f;
       t.reserved = 0;
     }
     ++*rows;
-    if (k != GSW_K_PUSH_EDGE) --ahead;  // the oldest queued level launch ran this level
+    ahead -= k == GSW_K_PUSH_EDGE ? 2 : 1;
     if (nn == 0) break;
-    if (nk == GSW_K_PUSH_EDGE) {
-      // the queued launches will find push_edge named and do nothing
-      ahead = 0;
-      GSW_TRY(launch_level_edge(g, b, dp, (int32_t)(d + 1), (uint32_t)nn, false, s));
-    }
+    want = kAhead + (nk == GSW_K_PUSH_EDGE ? 1 : 0);
   }
   if (o->canonical_parents && pa) GSW_TRY(launch_canonical_parents(g, lv, pa, s));
   return GSW_OK;
@@ -378,6 +401,7 @@ gsw_status gsw_bfs_profile(const gsw_graph* cg, int32_t source, const int32_t* k
   uint32_t bins[kQueueBins] = {1};  // segment sizes of the current queue
   std::vector<float> samples((size_t)reps);
   BfsCtl saved_ctl;
+  int cur = 0;  // control slot holding the next level's state
   for (int32_t d = 0;; ++d) {
     if (d >= max_levels) return fail(GSW_ERANGE, "BFS longer than max_levels=%d", max_levels);
     int32_t* qin = w.q[d & 1];
@@ -397,12 +421,13 @@ gsw_status gsw_bfs_profile(const gsw_graph* cg, int32_t source, const int32_t* k
         GSW_HIP(hipMemcpyAsync((char*)s_bm.p + i * bb, w.bm[i], bb, hipMemcpyDeviceToDevice, s));
       GSW_TRY(copy_queue((int32_t*)s_q.p, qin));
       GSW_HIP(hipMemcpyAsync(s_ctr.p, w.ctr, cb, hipMemcpyDeviceToDevice, s));
-      GSW_HIP(hipMemcpyAsync(w.h_ctl, w.ctl, sizeof(BfsCtl), hipMemcpyDeviceToHost, s));
+      GSW_HIP(hipMemcpyAsync(w.h_ctl, w.ctl + cur, sizeof(BfsCtl), hipMemcpyDeviceToHost, s));
       GSW_HIP(hipStreamSynchronize(s));
       saved_ctl = *w.h_ctl;
       return GSW_OK;
     };
-    // restores the saved state with kernel k named for level d
+    // restores the saved state with kernel k named for level d, in slot 0
+    // (the next launch is counted as launch 0)
     auto restore = [&](int k) -> gsw_status {
       GSW_HIP(hipMemcpyAsync(lv, s_lv.p, vb, hipMemcpyDeviceToDevice, s));
       GSW_HIP(hipMemcpyAsync(pa, s_pa.p, vb, hipMemcpyDeviceToDevice, s));
@@ -415,23 +440,17 @@ gsw_status gsw_bfs_profile(const gsw_graph* cg, int32_t source, const int32_t* k
       w.h_ctl->kernel = k;
       w.h_ctl->grid = level_participants(k, nf, b);
       w.h_ctl->done_blocks = 0u;
+      w.h_ctl->phase = 0;
       GSW_HIP(hipMemcpyAsync(w.ctl, w.h_ctl, sizeof(BfsCtl), hipMemcpyHostToDevice, s));
       GSW_HIP(hipStreamSynchronize(s));  // the staging copy is reused by the next restore
       return GSW_OK;
     };
-    // one level with kernel k, timed as the level loop runs it: the other
-    // kernels' levels are queued ahead of time, while a push_edge level is
-    // launched by the host after the previous level's record, so its
-    // bracket starts with the device idle and includes the launch latency
+    // one level with kernel k as the level loop runs it: one launch of the
+    // level kernel, two for push_edge
     auto run = [&](int k, bool timed_bracket) -> gsw_status {
-      if (timed_bracket) {
-        GSW_HIP(hipEventRecord(w.ev[0], s));
-        if (k == GSW_K_PUSH_EDGE) GSW_HIP(hipEventSynchronize(w.ev[0]));
-      }
-      if (k == GSW_K_PUSH_EDGE)
-        GSW_TRY(launch_level_edge(g, b, dp, d, (uint32_t)nf, false, s));
-      else
-        GSW_TRY(launch_level_auto(g, b, dp, s));
+      if (timed_bracket) GSW_HIP(hipEventRecord(w.ev[0], s));
+      GSW_TRY(launch_level_auto(g, b, dp, 0, s));
+      if (k == GSW_K_PUSH_EDGE) GSW_TRY(launch_level_auto(g, b, dp, 1, s));
       if (timed_bracket) GSW_HIP(hipEventRecord(w.ev[1], s));
       return GSW_OK;
     };
@@ -465,14 +484,11 @@ gsw_status gsw_bfs_profile(const gsw_graph* cg, int32_t source, const int32_t* k
     }
     GSW_TRY(restore(adv));
     GSW_TRY(run(adv, false));
-    if (adv == GSW_K_PUSH_EDGE) {
-      // make the next level's bitmap valid whatever kernel runs it
-      GSW_TRY(launch_rebuild_bitmap(g, b, s));
-    }
+    cur = adv == GSW_K_PUSH_EDGE ? 0 : 1;
     GSW_HIP(hipStreamSynchronize(s));
-    const volatile unsigned long long* r = nullptr;
+    Record r;
     GSW_TRY(wait_record(g, d, s, &r));
-    const int64_t nn = (int64_t)r[kRecNext];
+    const int64_t nn = r.next;
     GSW_HIP(hipMemcpy(w.h_ctr, w.ctr + (size_t)((d + 1) & 3) * kCtrSlot, kCtrSlot * sizeof(uint32_t),
                       hipMemcpyDeviceToHost));
     for (int bi = 0; bi < kQueueBins; ++bi) bins[bi] = w.h_ctr[bi * kCtrStride];

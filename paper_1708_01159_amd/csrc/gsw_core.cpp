@@ -151,7 +151,7 @@ gsw_status ensure_workspace(gsw_graph* g) {
       {(void**)&w.bm[0], bmb},
       {(void**)&w.bm[1], bmb},
       {(void**)&w.bm[2], bmb},
-      {(void**)&w.ctl, sizeof(BfsCtl)},
+      {(void**)&w.ctl, 2 * sizeof(BfsCtl)},
       {(void**)&w.done, (size_t)kDoneGroups * kCtrStride * sizeof(uint32_t)},
       {(void**)&w.q[0], (size_t)kQueueBins * n * sizeof(int32_t)},
       {(void**)&w.q[1], (size_t)kQueueBins * n * sizeof(int32_t)},
@@ -159,7 +159,6 @@ gsw_status ensure_workspace(gsw_graph* g) {
       {(void**)&w.scan, (size_t)n * sizeof(int64_t)},
       {(void**)&w.ebeg, (size_t)n * sizeof(int64_t)},
       {(void**)&w.bsum, (size_t)nb * sizeof(int64_t)},
-      {(void**)&w.etot, sizeof(unsigned long long)},
       {(void**)&w.lvl_tmp, (size_t)n * sizeof(int32_t)},
       {(void**)&w.par_tmp, (size_t)n * sizeof(int32_t)},
   };
@@ -225,7 +224,7 @@ void free_graph(gsw_graph* g) {
   if (!g) return;
   Workspace& w = g->ws;
   void* dev[] = {w.vis, w.bm[0], w.bm[1], w.bm[2], w.ctl, w.done, w.q[0], w.q[1], w.ctr, w.scan, w.ebeg,
-                 w.bsum, w.etot, w.lvl_tmp, w.par_tmp, w.d_tree, w.d_thr, w.d_sched, g->origin};
+                 w.bsum, w.lvl_tmp, w.par_tmp, w.d_tree, w.d_thr, w.d_sched, g->origin};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   if (w.h_ctr) (void)hipHostFree(w.h_ctr);

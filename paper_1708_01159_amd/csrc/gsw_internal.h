@@ -54,7 +54,6 @@ struct Workspace {
   int64_t* scan = nullptr;               // push_edge: per-entry exclusive degree scan
   int64_t* ebeg = nullptr;               // push_edge: row start per queue entry
   int64_t* bsum = nullptr;               // push_edge: per-block sums
-  unsigned long long* etot = nullptr;    // push_edge: total frontier edges
   int32_t* lvl_tmp = nullptr;            // levels when the caller passes host memory
   int32_t* par_tmp = nullptr;            // parents when the caller passes host memory
   uint32_t* h_ctr = nullptr;             // pinned host copy of one counter slot
@@ -119,11 +118,12 @@ struct BfsCtl {
   int32_t flags;    // trace flags of that choice (bit0 undecided leaf, bit1 pull replaced)
   long long nf;     // frontier size of level d
   long long disc;   // vertices discovered through depth d
-  unsigned int done_blocks;  // groups of workgroups of the running level that have finished
-  int32_t pad;
+  unsigned int done_blocks;  // groups of workgroups of the running launch that have finished
+  int32_t phase;             // push_edge levels take two launches: 0 = scan, 1 = expand
   unsigned long long t_begin;  // wall clock at the start of the running level (timed levels)
-  int32_t grid;                // workgroups that run level d (the rest of the launch exits)
+  int32_t grid;                // workgroups that run this launch of level d (the rest exit)
   int32_t pad2;
+  long long etot;              // push_edge: arcs of the frontier (set by the scan launch)
 };
 // Workgroups count themselves finished in kDoneGroups counters (by index
 // modulo kDoneGroups, kCtrStride words apart); the last of each group then
@@ -158,8 +158,11 @@ struct BfsBase {
   int32_t* q[2];
   uint32_t* ctr;
   uint32_t* done;                  // kDoneGroups workgroup counters, kCtrStride words apart
+  int64_t* scan;                   // push_edge: block-local exclusive arc offsets per queue entry
+  int64_t* ebeg;                   // push_edge: row start per queue entry
+  int64_t* bsum;                   // push_edge: arcs per scan block, then their exclusive prefix
   unsigned long long* ring;        // device address of the host record ring
-  BfsCtl* ctl;
+  BfsCtl* ctl;                     // two slots: launch j reads j % 2, writes the other
   int64_t n, nw, nnz;
   int32_t timed;                   // record each level's duration
   int32_t grid_max;                // workgroups of a level-kernel launch
@@ -175,35 +178,40 @@ inline unsigned long long tree_node_pack(int32_t left, int32_t right, int32_t fe
 constexpr int32_t kMaxTreeNodes = 32767;
 
 // Host ring of per-level records: record of level d at (d % kBfsRing) * kBfsRec.
+// Every word carries the level's tag (rec_tag) in its top 16 bits and a
+// value below 2^48 in the rest, so the host takes a record once all its
+// words bear the tag, whatever order their stores arrive in, and the device
+// never waits for them.
 constexpr int kBfsRing = 8;
 constexpr int kBfsRec = 16;
 enum : int {
-  kRecSeq = 0,      // d + 1, stored last
-  kRecKernel = 1,   // kernel that ran level d
-  kRecFlags = 2,    // its trace flags
-  kRecNf = 3,       // frontier size of level d
-  kRecDisc = 4,     // discovered through depth d
-  kRecNext = 5,     // size of the depth-(d+1) frontier
-  kRecTicks = 6,    // wall-clock ticks of the level (timed levels)
-  kRecNextKernel = 7  // kernel chosen for level d+1 (kCtlDone when none)
+  kRecKernel = 0,   // kernel that ran level d
+  kRecFlags = 1,    // its trace flags
+  kRecNf = 2,       // frontier size of level d
+  kRecDisc = 3,     // discovered through depth d
+  kRecNext = 4,     // size of the depth-(d+1) frontier
+  kRecTicks = 5,    // wall-clock ticks of the level (timed levels)
+  kRecNextKernel = 6,  // kernel chosen for level d+1, plus one (0: none)
+  kBfsRecWords = 7
 };
+constexpr unsigned long long kRecValueMask = (1ull << 48) - 1ull;
+// Never zero (the cleared ring) and different for the 8 levels sharing a slot.
+__host__ __device__ inline unsigned long long rec_tag(long long d) {
+  return (unsigned long long)(((d + 1) & 0x7fff) | 0x8000) << 48;
+}
 
 // Kernel launchers (gsw_kernels.hip).
 gsw_status launch_init(const gsw_graph* g, const BfsBase& b, int32_t source, int32_t k0, int32_t flags0,
                        hipStream_t s);
-// One level run by the kernel that the control block names, unless that is
-// push_edge or none (then the launch does nothing).
-gsw_status launch_level_auto(const gsw_graph* g, const BfsBase& b, const BfsPolicy& p, hipStream_t s);
-// One push_edge level (three kernels); afterwards the frontier bitmap of the
-// next level is rebuilt when the next kernel is pull (or always with force).
-gsw_status launch_level_edge(const gsw_graph* g, const BfsBase& b, const BfsPolicy& p, int32_t d,
-                             uint32_t n_in, bool force_bitmap, hipStream_t s);
+// Launch j (counted from 0 after launch_init) of the level kernel: runs what
+// control slot j % 2 names -- a level, or the scan or the expansion of a
+// push_edge level -- or nothing once the search has ended.
+gsw_status launch_level_auto(const gsw_graph* g, const BfsBase& b, const BfsPolicy& p, int32_t j,
+                             hipStream_t s);
 // Workgroups of a level-kernel launch on a graph of n vertices (nw bitmap words).
 int32_t level_kernel_grid(int64_t n, int64_t nw);
 // Workgroups of that launch that run a level of `kernel` with n_in frontier entries.
 int32_t level_participants(int kernel, int64_t n_in, const BfsBase& b);
-// Frontier bitmap of the control block's level rebuilt from the level array.
-gsw_status launch_rebuild_bitmap(const gsw_graph* g, const BfsBase& b, hipStream_t s);
 gsw_status launch_isolated(const gsw_graph* g, unsigned long long* iso, hipStream_t s);
 gsw_status launch_canonical_parents(const gsw_graph* g, const int32_t* level, int32_t* parent,
                                     hipStream_t s);

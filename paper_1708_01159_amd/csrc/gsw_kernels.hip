@@ -5,9 +5,8 @@
 // parent at depth d, and appends it to the depth-(d+1) queue.  The frontier
 // bitmaps rotate over three buffers (depth d in bm[d % 3]): the bottom-up
 // kernel writes the depth-(d+1) bitmap in full, the top-down kernels set the
-// bits of the vertices they discover (push_edge leaves it to a rebuild from
-// the level array, run only when the next level is bottom-up), and every
-// level zeroes the buffer of the level after next.  Any kernel can therefore
+// bits of the vertices they discover, and every level zeroes the buffer of
+// the level after next.  Any kernel can therefore
 // run the next level; only the queue's order and the parent choice depend on
 // the kernel, never the levels.
 //
@@ -18,9 +17,9 @@
 // stores it in the level control block and posts the level's record to a
 // ring in mapped host memory.  One kernel, k_level_auto, runs whichever
 // variant the control block names, so the host can queue levels ahead
-// without waiting for their results; push_edge, whose prefix sum needs a
-// grid-wide step, is launched by the host as three kernels when the device
-// names it.
+// without waiting for their results.  push_edge, whose prefix sum needs a
+// grid-wide step, takes two of those launches: a scan whose last workgroup
+// scans the block sums, then the expansion.
 //
 // Ownership of a new vertex v is decided by atomicOr on its 64-bit visited
 // word: exactly one lane sees the bit clear and becomes the writer of v's
@@ -49,8 +48,8 @@ constexpr int kMaxGrid = 2048;                   // persistent producer grids (8
 constexpr int kStage = 2048;                     // LDS-staged queue entries per workgroup
 constexpr int kScanItems = 4;                    // push_edge: entries per thread in the scan
 constexpr int kScanTile = kBlock * kScanItems;   // entries per scan block
-constexpr int kEdgeTile = 1024;                  // push_edge: edges per tile
-constexpr int kEdgeWin = kEdgeTile;              // push_edge: queue entries staged per tile
+constexpr int kEdgeChunk = 1024;                 // push_edge: arcs per chunk (4 per lane)
+constexpr int kEdgeWin = 512;                    // push_edge: queue entries a chunk stages in LDS
 constexpr int kPullEager = 8;                    // pull: neighbours probed per lane up front
 constexpr int kPullChunk = 8;                    // pull: visited words (512 vertices) per wave step
 
@@ -72,7 +71,8 @@ struct Args {
   int32_t* __restrict__ qout;
   uint32_t* cout;
   uint32_t* cclr;
-  BfsCtl* ctl;
+  BfsCtl* ctl;       // this launch's control slot
+  BfsCtl* ctl_next;  // the next launch's
   uint32_t* done;
   int64_t n, nw, nnz;
   uint32_t n_in;
@@ -82,7 +82,7 @@ struct Args {
   int32_t grid;    // workgroups taking part in the level (grid-stride loops use it)
 };
 
-__host__ __device__ inline Args make_args(const BfsBase& b, int32_t d, uint32_t n_in, int32_t set_nx,
+__host__ __device__ inline Args make_args(const BfsBase& b, int32_t j, int32_t d, uint32_t n_in, int32_t set_nx,
                                           int32_t grid) {
   Args a;
   a.offs = b.offs;
@@ -99,7 +99,8 @@ __host__ __device__ inline Args make_args(const BfsBase& b, int32_t d, uint32_t 
   a.qout = b.q[(d + 1) & 1];
   a.cout = b.ctr + (size_t)((d + 1) & 3) * kCtrSlot;
   a.cclr = b.ctr + (size_t)((d + 2) & 3) * kCtrSlot;
-  a.ctl = b.ctl;
+  a.ctl = b.ctl + (j & 1);
+  a.ctl_next = b.ctl + ((j + 1) & 1);
   a.done = b.done;
   a.n = b.n;
   a.nw = b.nw;
@@ -123,6 +124,7 @@ __host__ __device__ inline int32_t level_grid(int k, int64_t n_in, const BfsBase
     case GSW_K_PULL_BITMAP: need = b.grid_max; break;
     case GSW_K_VERTEX_SCAN: need = div_up(b.n, kBlock); break;
     case GSW_K_EDGE_SCAN: need = div_up(b.nnz, kBlock); break;
+    case GSW_K_PUSH_EDGE: need = div_up(n_in, kScanTile); break;  // its scan launch
     default: need = div_up(n_in, kBlock); break;
   }
   if (need < 1) need = 1;
@@ -291,46 +293,36 @@ __device__ __forceinline__ void visit_row(Stage& s, const Args& a, int64_t e0, i
 }
 
 // ------------------------------------------------- next-kernel choice
-// Feature i of level d+1's vector (Section IV-A list; the order of
-// gsw_level_features).
-__device__ __forceinline__ double feature(const BfsPolicy& p, int i, double nf, double disc) {
-  switch (i) {
-    case 8: return nf;
-    case 9: return nf / p.feat[0];
-    case 10: return disc;
-    case 11: return disc / p.feat[0];
-    default: return p.feat[i < 8 ? i : 0];
+// Child of tree node nd (packed as tree_node_pack) for the feature vector of
+// a level with nf frontier vertices and disc discovered ones (Section IV-A
+// list, in the order of gsw_level_features: feat holds the graph's eight,
+// then frontier, its fraction of n, discovered, its fraction of n), or, for
+// a leaf, -(leaf kernel + 2) (-1: undecided leaf).  The feature is rounded
+// to float and compared with the double threshold, as the host does.
+__device__ __forceinline__ int32_t tree_step(u64 nd, double thr, const double* feat, double nf, double disc) {
+  const int left = (int)(int16_t)(uint16_t)(nd & 0xffffull);
+  if (left == -1) return -((int32_t)((nd >> 40) & 0xffull) - 1) - 2;
+  const int right = (int)(int16_t)(uint16_t)((nd >> 16) & 0xffffull);
+  const int f = (int)((nd >> 32) & 0xffull);
+  double x;
+  switch (f) {
+    case 8: x = nf; break;
+    case 9: x = nf / feat[0]; break;
+    case 10: x = disc; break;
+    case 11: x = disc / feat[0]; break;
+    default: x = feat[f < 8 ? f : 0]; break;
   }
+  return (double)(float)x <= thr ? left : right;
 }
 
-// Kernel for level d (d >= 1) with frontier nf and nf + earlier discoveries
-// = disc; prev = kernel of level d-1.  The same rules as the host's choice.
-__device__ __forceinline__ int choose_next(const BfsPolicy& p, const u64* t_node, const double* t_thr, int32_t d,
-                           long long nf, long long disc, int prev, int32_t* flags) {
+// Kernel for a tree leaf (-1: undecided, repeat prev, the previous level's
+// kernel) or any other policy's pick, after the fixups every choice gets:
+// bottom-up needs a symmetric graph, edge_scan the origin array.
+__device__ __forceinline__ int choose_leaf(const BfsPolicy& p, int k, int prev, int32_t* flags) {
   *flags = 0;
-  int k = GSW_DEFAULT_KERNEL;
-  if (p.policy == GSW_POLICY_FIXED) {
-    k = p.fixed;
-  } else if (p.policy == GSW_POLICY_SCHEDULE) {
-    k = p.sched[d < p.sched_len ? d : p.sched_len - 1];
-  } else {
-    int node = 0;
-    u64 nd = t_node[0];
-    for (;;) {
-      const int left = (int)(int16_t)(uint16_t)(nd & 0xffffull);
-      if (left == -1) break;
-      const int right = (int)(int16_t)(uint16_t)((nd >> 16) & 0xffffull);
-      const double xv = (double)(float)feature(p, (int)((nd >> 32) & 0xffull), (double)nf, (double)disc);
-      node = xv <= t_thr[node] ? left : right;
-      nd = t_node[node];
-    }
-    const int leaf = (int)((nd >> 40) & 0xffull) - 1;
-    if (leaf >= 0) {
-      k = leaf;
-    } else {
-      k = prev;  // undecided leaf: repeat the previous level's kernel (d >= 1)
-      *flags |= 1;
-    }
+  if (k < 0) {
+    k = prev;
+    *flags |= 1;
   }
   if (k == GSW_K_PULL_BITMAP && !p.symmetric) {
     k = GSW_DEFAULT_KERNEL;
@@ -340,25 +332,48 @@ __device__ __forceinline__ int choose_next(const BfsPolicy& p, const u64* t_node
   return k;
 }
 
+// Kernel for level d (d >= 1) with frontier nf and nf + earlier discoveries
+// = disc; prev = kernel of level d-1.  The same rules as the host's choice;
+// a tree is walked here from global memory one node at a time (the level's
+// end evaluates trees that fit its LDS table in parallel instead).
+__device__ __forceinline__ int choose_next(const BfsPolicy& p, int32_t d, long long nf, long long disc, int prev,
+                                           int32_t* flags) {
+  int k = GSW_DEFAULT_KERNEL;
+  if (p.policy == GSW_POLICY_FIXED) {
+    k = p.fixed;
+  } else if (p.policy == GSW_POLICY_SCHEDULE) {
+    k = p.sched[d < p.sched_len ? d : p.sched_len - 1];
+  } else {
+    int32_t x = 0;
+    do {
+      x = tree_step(p.t_node[x], p.t_thr[x], p.feat, (double)nf, (double)disc);
+    } while (x >= 0);
+    k = x == -1 ? -1 : -x - 2;
+  }
+  return choose_leaf(p, k, prev, flags);
+}
+
 // End of a level, called by every thread of every workgroup of the level's
 // last kernel: the last workgroup to finish sums the next frontier's
 // segments, picks the next kernel, posts the level's record to the host
 // ring (its first word last) and rewrites the control block.  Each
 // workgroup's queue-segment atomics have returned before it counts itself
-// finished, so the last one sees every segment's final size.  That
-// workgroup first copies the tree into `lds` (lds_bytes of LDS free by now,
-// the flushed append stage) with all its threads, so the walk does not pay
-// a global-memory round trip per node (8 bytes and a threshold per node:
-// 512 nodes fit the 8 KiB stage).
-__device__ __forceinline__ void level_end(const Args& a, const BfsBase* base, const BfsPolicy& p, u64* ring, int k_run,
-                          void* lds, int lds_bytes) {
+// finished, so the last one sees every segment's final size.  With the tree
+// policy that workgroup evaluates every node's split at once, one node per
+// thread and round, into a child table in `lds` (lds_bytes of LDS free by
+// now, the flushed append stage; 4 bytes per node), and one thread then
+// follows the table from the root: a chain of LDS reads instead of a global
+// load per node.  Its first two nodes per thread are loaded before the
+// segment sum, so that their latency overlaps it.
+// True (in every thread) in the last workgroup of the launch to get here;
+// called by every thread of every participating workgroup.  The last one
+// resets the counters (before the launch ends, for the next one).
+__device__ __forceinline__ bool launch_last(const Args& a) {
   __shared__ uint32_t s_last;
-  __shared__ uint32_t s_nn;
   __syncthreads();
   if (threadIdx.x == 0) {
-    __builtin_amdgcn_s_waitcnt(0);
     const uint32_t grid = (uint32_t)a.grid;
-    uint32_t last = 1u;  // a level of one workgroup needs no count
+    uint32_t last = 1u;  // a launch of one workgroup needs no count
     if (grid > (unsigned)kDoneGroups) {
       const uint32_t gidx = blockIdx.x % (unsigned)kDoneGroups;
       const uint32_t in_group = grid / kDoneGroups + (gidx < grid % kDoneGroups ? 1u : 0u);
@@ -371,17 +386,37 @@ __device__ __forceinline__ void level_end(const Args& a, const BfsBase* base, co
     s_last = last;
   }
   __syncthreads();
-  if (!s_last) return;
-  const int tid = threadIdx.x;
-  const bool tree_lds = p.policy == GSW_POLICY_TREE && p.t_nodes * 16 <= lds_bytes;
-  u64* l_node = reinterpret_cast<u64*>(lds);
-  double* l_thr = reinterpret_cast<double*>(l_node + (tree_lds ? p.t_nodes : 0));
-  if (tree_lds) {
-    for (int i = tid; i < p.t_nodes; i += kBlock) {
-      l_node[i] = p.t_node[i];
-      l_thr[i] = p.t_thr[i];
-    }
+  const bool last = s_last != 0u;
+  if (last) {
+    if (threadIdx.x < kDoneGroups) a.done[threadIdx.x * kCtrStride] = 0u;
+    if (threadIdx.x == 0) a.ctl->done_blocks = 0u;
   }
+  return last;
+}
+
+__device__ __forceinline__ void level_end(const Args& a, const BfsBase* base, const BfsPolicy& p, u64* ring,
+                                          int k_run, void* lds, int lds_bytes) {
+  __shared__ uint32_t s_nn;
+  __shared__ double s_feat[8];
+  if (!launch_last(a)) return;
+  const int tid = threadIdx.x;
+  BfsCtl* c = a.ctl;
+  const bool tree_par = p.policy == GSW_POLICY_TREE && (long long)p.t_nodes * 4 <= (long long)lds_bytes;
+  int32_t* l_next = reinterpret_cast<int32_t*>(lds);
+  u64 nd0 = 0ull, nd1 = 0ull;
+  double th0 = 0.0, th1 = 0.0;
+  if (tree_par) {
+    if (tid < p.t_nodes) {
+      nd0 = p.t_node[tid];
+      th0 = p.t_thr[tid];
+    }
+    if (tid + kBlock < p.t_nodes) {
+      nd1 = p.t_node[tid + kBlock];
+      th1 = p.t_thr[tid + kBlock];
+    }
+    if (tid < 8) s_feat[tid] = p.feat[tid];
+  }
+  const long long disc0 = c->disc;
   if (tid < 64) {  // wave 0: the next frontier's segments
     uint32_t x = tid < kQueueBins
                      ? __hip_atomic_load(a.cout + tid * kCtrStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
@@ -390,11 +425,17 @@ __device__ __forceinline__ void level_end(const Args& a, const BfsBase* base, co
     for (int off = 32; off > 0; off >>= 1) x += (uint32_t)__shfl_xor((int)x, off);
     if (tid == 0) s_nn = x;
   }
-  if (tid < kDoneGroups) a.done[tid * kCtrStride] = 0u;
   __syncthreads();
-  if (tid != 0) return;
-  BfsCtl* c = a.ctl;
   const uint32_t nn = s_nn;
+  const long long ndisc = disc0 + (long long)nn;
+  if (tree_par && nn > 0) {
+    if (tid < p.t_nodes) l_next[tid] = tree_step(nd0, th0, s_feat, (double)nn, (double)ndisc);
+    if (tid + kBlock < p.t_nodes) l_next[tid + kBlock] = tree_step(nd1, th1, s_feat, (double)nn, (double)ndisc);
+    for (int i = tid + 2 * kBlock; i < p.t_nodes; i += kBlock)
+      l_next[i] = tree_step(p.t_node[i], p.t_thr[i], s_feat, (double)nn, (double)ndisc);
+    __syncthreads();
+  }
+  if (tid != 0) return;
   u64 ticks = 0ull;
   if (a.timed) {
     const u64 t0 = __hip_atomic_load(&c->t_begin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -402,31 +443,37 @@ __device__ __forceinline__ void level_end(const Args& a, const BfsBase* base, co
     ticks = t1 > t0 ? t1 - t0 : 0ull;
   }
   const int32_t d = a.d;
-  const long long nf = c->nf, disc = c->disc, ndisc = disc + (long long)nn;
+  const long long nf = c->nf, disc = disc0;
   int32_t nflags = 0;
-  const int32_t next = nn > 0 ? choose_next(p, tree_lds ? l_node : p.t_node, tree_lds ? l_thr : p.t_thr, d + 1,
-                                             (long long)nn, ndisc, k_run, &nflags)
-                               : kCtlDone;
+  int32_t next = kCtlDone;
+  if (nn > 0) {
+    if (tree_par) {
+      int32_t x = l_next[0];
+      while (x >= 0) x = l_next[x];
+      next = choose_leaf(p, x == -1 ? -1 : -x - 2, k_run, &nflags);
+    } else {
+      next = choose_next(p, d + 1, (long long)nn, ndisc, k_run, &nflags);
+    }
+  }
   u64* r = ring + (size_t)(d % kBfsRing) * kBfsRec;
-  __hip_atomic_store(r + kRecKernel, (u64)k_run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  __hip_atomic_store(r + kRecFlags, (u64)c->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  __hip_atomic_store(r + kRecNf, (u64)nf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  __hip_atomic_store(r + kRecDisc, (u64)disc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  __hip_atomic_store(r + kRecNext, (u64)nn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  __hip_atomic_store(r + kRecTicks, ticks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  __hip_atomic_store(r + kRecNextKernel, (u64)(long long)next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  c->d = d + 1;
-  c->kernel = next;
-  c->grid = next >= 0 ? level_grid(next, (int64_t)nn, *base) : 1;
-  c->prev = k_run;
-  c->flags = nflags;
-  c->nf = (long long)nn;
-  c->disc = ndisc;
-  c->done_blocks = 0u;
-  // the host reads only the record: its other words are stored (system
-  // scope, to host memory) before the first word, no cache writeback needed
-  __builtin_amdgcn_s_waitcnt(0);
-  __hip_atomic_store(r + kRecSeq, (u64)d + 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  const u64 tag = rec_tag(d);
+  const u64 rec[kBfsRecWords] = {(u64)k_run, (u64)c->flags, (u64)nf, (u64)disc, (u64)nn, ticks & kRecValueMask,
+                              (u64)(next + 1)};
+#pragma unroll
+  for (int i = 0; i < kBfsRecWords; ++i)
+    __hip_atomic_store(r + i, tag | rec[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  BfsCtl* cn = a.ctl_next;
+  cn->d = d + 1;
+  cn->kernel = next;
+  cn->prev = k_run;
+  cn->flags = nflags;
+  cn->nf = (long long)nn;
+  cn->disc = ndisc;
+  cn->done_blocks = 0u;
+  cn->phase = 0;
+  cn->t_begin = 0ull;
+  cn->grid = next >= 0 ? level_grid(next, (int64_t)nn, *base) : 1;
+  cn->etot = 0;
 }
 
 // ---------------------------------------------------------------- init
@@ -464,8 +511,10 @@ __global__ void __launch_bounds__(kBlock) k_init(BfsBase b, const u64* __restric
     c->nf = 1;
     c->disc = 1;
     c->done_blocks = 0u;
+    c->phase = 0;
     c->t_begin = 0ull;
     c->grid = level_grid(k0, 1, b);
+    c->etot = 0;
   }
   if (gid < 4 * kCtrSlot) b.ctr[gid] = gid == 0 ? 1u : 0u;
   if (gid < kDoneGroups) b.done[gid * kCtrStride] = 0u;
@@ -618,64 +667,131 @@ __device__ __forceinline__ void body_push_wave(const Args& a, Stage& st, const Q
   }
 }
 
-// ------------------------------------------------ push_edge (lane / frontier edge)
-// Phase 1: per-entry degree and row start, block-local exclusive scan.
-__global__ void __launch_bounds__(kBlock) k_edge_scan_local(Args a, int64_t* __restrict__ scan,
-                                                            int64_t* __restrict__ ebeg,
-                                                            int64_t* __restrict__ bsum) {
-  level_begin(a);
-  __shared__ int64_t wsum[kWaves];
-  __shared__ QueueIn qi;
-  clear_ahead(a);
-  queue_in_load(a, qi);
-  const int lane = lane_id();
-  const int wid = threadIdx.x >> 6;
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-  int64_t deg[kScanItems];
-  int64_t tot = 0;
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t i = base + k;
-    deg[k] = 0;
-    if (i < a.n_in) {
-      const int32_t u = queue_at(a, qi, (uint32_t)i);
-      const int64_t b = a.offs[u];
-      ebeg[i] = b;
-      deg[k] = a.offs[u + 1] - b;
-    }
-    tot += deg[k];
-  }
-  int64_t inc = tot;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int64_t y = __shfl_up(inc, off);
-    if (lane >= off) inc += y;
-  }
-  if (lane == 63) wsum[wid] = inc;
-  __syncthreads();
-  int64_t run = inc - tot;
-  for (int k = 0; k < wid; ++k) run += wsum[k];
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t i = base + k;
-    if (i < a.n_in) scan[i] = run;
-    run += deg[k];
-  }
-  if (threadIdx.x == kBlock - 1 && (int64_t)blockIdx.x * kScanTile < (int64_t)a.n_in)
-    bsum[blockIdx.x] = run;
+// ------------------------------------------------ push_edge (lane / frontier arc)
+// Section III-A, edge push: every arc leaving the frontier gets a lane.  The
+// frontier's arcs are numbered by an exclusive prefix sum of the queue
+// entries' degrees, computed by the level's first launch (block-local scans
+// of kScanTile entries; the launch's last workgroup scans the block sums).
+// The second launch splits the arc range evenly over its workgroups; each
+// finds the entry holding its first arc with a cooperative search, then
+// walks its range in chunks of kEdgeChunk arcs, staging the entries a chunk
+// spans in LDS so that each lane finds its arc's entry there.
+struct EdgeScan {
+  const int64_t* scan;
+  const int64_t* ebeg;
+  const int64_t* bsum;
+};
+
+// Arc offset of queue entry i.
+__device__ __forceinline__ int64_t gscan(const EdgeScan& es, int64_t i) {
+  return es.scan[i] + es.bsum[i / kScanTile];
 }
 
-// Phase 2: exclusive scan of the block sums (one workgroup), total -> etot.
-__global__ void __launch_bounds__(1024) k_edge_scan_blocks(int64_t* __restrict__ bsum, int64_t nb,
-                                                           u64* __restrict__ etot) {
-  __shared__ int64_t wsum[1024 / 64];
+// Last entry i in [lo, hi] with gscan(i) <= t, given gscan(lo) <= t; one lane.
+__device__ __forceinline__ int64_t find_entry(const EdgeScan& es, int64_t lo, int64_t hi, int64_t t) {
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo + 1) / 2;
+    if (gscan(es, mid) <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+struct EdgeLds {
+  int64_t start[kEdgeWin];  // arc offset of each staged entry
+  int64_t beg[kEdgeWin];    // its row start
+  int32_t u[kEdgeWin];      // its vertex
+  int32_t cnt[kWaves];
+};
+
+// Number of workgroup lanes with pred set (every thread calls it).
+__device__ __forceinline__ int block_count(bool pred, int32_t* cnt) {
+  const u64 m = __ballot(pred);
+  if (lane_id() == 0) cnt[threadIdx.x >> 6] = __popcll(m);
+  __syncthreads();
+  int c = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) c += cnt[w];
+  __syncthreads();  // cnt is rewritten by the next call
+  return c;
+}
+
+// The same search by the whole workgroup: each round probes kBlock evenly
+// spaced entries at once and keeps the interval between the last probe at
+// or below t and the next one (two rounds up to 65536 entries).
+__device__ __forceinline__ int64_t find_entry_block(const EdgeScan& es, int64_t lo, int64_t hi, int64_t t,
+                                                    int32_t* cnt) {
+  while (hi > lo) {
+    const int64_t step = (hi - lo + kBlock) / kBlock;  // ceil((hi - lo + 1) / kBlock)
+    const int64_t q = lo + (int64_t)threadIdx.x * step;
+    const int c = block_count(q <= hi && gscan(es, q) <= t, cnt);  // probes true form a prefix, c >= 1
+    lo += (int64_t)(c - 1) * step;
+    hi = lo + step - 1 < hi ? lo + step - 1 : hi;
+  }
+  return lo;
+}
+
+// First launch: degree and row start per entry, block-local exclusive scan,
+// block sums.  Scan blocks are spread over the launch's workgroups.
+__device__ __forceinline__ void body_edge_prefix(const Args& a, const QueueIn& qi, const BfsBase& b,
+                                                 int64_t* wsum) {
   const int lane = lane_id();
   const int wid = threadIdx.x >> 6;
-  const int64_t per = (nb + 1023) / 1024;
+  const int64_t nb = div_up((int64_t)a.n_in, kScanTile);
+  for (int64_t blk = blockIdx.x; blk < nb; blk += a.grid) {
+    const int64_t base = blk * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int64_t deg[kScanItems];
+    int64_t tot = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      const int64_t i = base + k;
+      deg[k] = 0;
+      if (i < a.n_in) {
+        const int32_t u = queue_at(a, qi, (uint32_t)i);
+        const int64_t rb = a.offs[u];
+        b.ebeg[i] = rb;
+        deg[k] = a.offs[u + 1] - rb;
+      }
+      tot += deg[k];
+    }
+    int64_t inc = tot;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int64_t y = __shfl_up(inc, off);
+      if (lane >= off) inc += y;
+    }
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    int64_t run = inc - tot;
+    for (int k = 0; k < wid; ++k) run += wsum[k];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      const int64_t i = base + k;
+      if (i < a.n_in) b.scan[i] = run;
+      run += deg[k];
+    }
+    if (threadIdx.x == kBlock - 1) {
+      // read by this launch's last workgroup, maybe on another XCD: a
+      // device-coherent store, complete before this workgroup counts itself
+      __hip_atomic_store(b.bsum + blk, run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_s_waitcnt(0);
+    }
+    __syncthreads();  // wsum is rewritten by the next block
+  }
+}
+
+// End of the first launch: its last workgroup turns the block sums into
+// their exclusive prefix, stores the arc total and names the second launch.
+__device__ __forceinline__ void edge_prefix_end(const Args& a, const BfsBase& b, int64_t* wsum) {
+  if (!launch_last(a)) return;
+  const int lane = lane_id();
+  const int wid = threadIdx.x >> 6;
+  const int64_t nb = div_up((int64_t)a.n_in, kScanTile);
+  const int64_t per = div_up(nb, kBlock);
   const int64_t lo = (int64_t)threadIdx.x * per;
   const int64_t hi = lo + per < nb ? lo + per : nb;
   int64_t tot = 0;
-  for (int64_t i = lo; i < hi; ++i) tot += bsum[i];
+  for (int64_t i = lo; i < hi; ++i)
+    tot += __hip_atomic_load(b.bsum + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   int64_t inc = tot;
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
@@ -687,97 +803,88 @@ __global__ void __launch_bounds__(1024) k_edge_scan_blocks(int64_t* __restrict__
   int64_t run = inc - tot;
   for (int k = 0; k < wid; ++k) run += wsum[k];
   for (int64_t i = lo; i < hi; ++i) {
-    const int64_t x = bsum[i];
-    bsum[i] = run;
+    const int64_t x = __hip_atomic_load(b.bsum + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    b.bsum[i] = run;
     run += x;
   }
-  if (threadIdx.x == 1023) *etot = (u64)run;
-}
-
-__device__ __forceinline__ int64_t gscan(const int64_t* scan, const int64_t* bsum, int64_t i) {
-  return scan[i] + bsum[i / kScanTile];
-}
-
-// Largest entry index i in [lo, hi] with gscan(i) <= t (gscan(lo) <= t holds).
-__device__ __forceinline__ int64_t find_entry(const int64_t* scan, const int64_t* bsum, int64_t lo,
-                                              int64_t hi, int64_t t) {
-  while (lo < hi) {
-    const int64_t mid = lo + (hi - lo + 1) / 2;
-    if (gscan(scan, bsum, mid) <= t) lo = mid; else hi = mid - 1;
+  if (threadIdx.x == kBlock - 1) {
+    const BfsCtl* c = a.ctl;
+    BfsCtl* cn = a.ctl_next;
+    const int64_t chunks = div_up(run, kEdgeChunk);
+    cn->d = c->d;
+    cn->kernel = c->kernel;
+    cn->prev = c->prev;
+    cn->flags = c->flags;
+    cn->nf = c->nf;
+    cn->disc = c->disc;
+    cn->done_blocks = 0u;
+    cn->phase = 1;
+    cn->t_begin = __hip_atomic_load(&c->t_begin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    cn->grid = (int32_t)(chunks < 1 ? 1 : (chunks < b.grid_max ? chunks : b.grid_max));
+    cn->etot = run;
   }
-  return lo;
 }
 
-// Phase 3: tiles of kEdgeTile consecutive frontier edges; the queue entries a
-// tile spans are staged in LDS and each lane locates its edge's entry by
-// binary search there.
-__global__ void __launch_bounds__(kBlock) k_edge_expand(Args a, const int64_t* __restrict__ scan,
-                                                        const int64_t* __restrict__ ebeg,
-                                                        const int64_t* __restrict__ bsum,
-                                                        const u64* __restrict__ etot, BfsPolicy p,
-                                                        BfsBase b) {
-  __shared__ int64_t s_start[kEdgeWin + 1];
-  __shared__ int64_t s_beg[kEdgeWin];
-  __shared__ int32_t s_u[kEdgeWin];
-  __shared__ int64_t s_range[2];
-  __shared__ Stage st;
-  __shared__ QueueIn qi;
-  clear_bitmap(a.bclr, a.nw);
-  stage_init(st);
-  queue_in_load(a, qi);
-  const int64_t total = (int64_t)*etot;
-  const int64_t ntiles = (total + kEdgeTile - 1) / kEdgeTile;
+// Second launch: workgroup w takes arcs [etot*w/G, etot*(w+1)/G).
+__device__ __forceinline__ void body_edge_expand(const Args& a, Stage& st, const QueueIn& qi, const EdgeScan& es,
+                                                 EdgeLds& L, int64_t total) {
+  const int64_t G = a.grid;
+  const int64_t e_lo = total * (int64_t)blockIdx.x / G;
+  const int64_t e_hi = total * ((int64_t)blockIdx.x + 1) / G;
+  if (e_lo >= e_hi) return;
   const int64_t last = (int64_t)a.n_in - 1;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int64_t t0 = tile * kEdgeTile;
-    const int64_t t1 = (t0 + kEdgeTile < total ? t0 + kEdgeTile : total) - 1;
-    if (threadIdx.x < 2) s_range[threadIdx.x] = find_entry(scan, bsum, 0, last, threadIdx.x ? t1 : t0);
-    __syncthreads();
-    const int64_t i0 = s_range[0], i1 = s_range[1];
-    const int64_t span = i1 - i0 + 1;
-    const bool staged = span <= kEdgeWin;
+  const int tid = threadIdx.x;
+  int64_t i0 = find_entry_block(es, 0, last, e_lo, L.cnt);
+  for (int64_t c0 = e_lo; c0 < e_hi; c0 += kEdgeChunk) {
+    const int64_t c1 = (c0 + kEdgeChunk < e_hi ? c0 + kEdgeChunk : e_hi) - 1;
+    // entries from i0 whose arcs start by c1: m of them (a prefix), staged
+    // when they fit the window
+    int m = 0;
+    for (int g = 0; g < kEdgeWin; g += kBlock) {
+      const int64_t i = i0 + g + tid;
+      const int64_t sv = i <= last ? gscan(es, i) : INT64_MAX;
+      L.start[g + tid] = sv;
+      const int c = block_count(sv <= c1, L.cnt);
+      m += c;
+      if (c < kBlock) break;
+    }
+    const bool staged = m < kEdgeWin;
     if (staged) {
-      for (int64_t k = threadIdx.x; k < span; k += kBlock) {
-        s_start[k] = gscan(scan, bsum, i0 + k);
-        s_beg[k] = ebeg[i0 + k];
-        s_u[k] = queue_at(a, qi, (uint32_t)(i0 + k));
+      for (int k = tid; k < m; k += kBlock) {
+        L.beg[k] = es.ebeg[i0 + k];
+        L.u[k] = queue_at(a, qi, (uint32_t)(i0 + k));
       }
     }
     __syncthreads();
-    for (int r = 0; r < kEdgeTile / kBlock; ++r) {
-      const int64_t t = t0 + r * kBlock + threadIdx.x;
-      const bool live = t <= t1;
-      int32_t v = 0, u = 0;
-      if (live) {
-        int64_t st0, eb;
+    int32_t v[kBatch], u[kBatch];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      const int64_t t = c0 + (int64_t)j * kBlock + tid;
+      v[j] = -1;
+      u[j] = 0;
+      if (t <= c1) {
         if (staged) {
-          int64_t lo = 0, hi = span - 1;
+          int lo = 0, hi = m - 1;
           while (lo < hi) {
-            const int64_t mid = lo + (hi - lo + 1) / 2;
-            if (s_start[mid] <= t) lo = mid; else hi = mid - 1;
+            const int mid = (lo + hi + 1) >> 1;
+            if (L.start[mid] <= t) lo = mid; else hi = mid - 1;
           }
-          st0 = s_start[lo];
-          eb = s_beg[lo];
-          u = s_u[lo];
+          v[j] = a.cols[L.beg[lo] + (t - L.start[lo])];
+          u[j] = L.u[lo];
         } else {
-          const int64_t j = find_entry(scan, bsum, i0, i1, t);
-          st0 = gscan(scan, bsum, j);
-          eb = ebeg[j];
-          u = queue_at(a, qi, (uint32_t)j);
+          const int64_t k = find_entry(es, i0, last, t);
+          v[j] = a.cols[es.ebeg[k] + (t - gscan(es, k))];
+          u[j] = queue_at(a, qi, (uint32_t)k);
         }
-        v = a.cols[eb + (t - st0)];
       }
-      bool win = false;
-      if (live) {
-        win = claim(a.vis, v);
-        if (win) settle(a, v, u);
-      }
-      stage_push(st, a, win, v);
     }
-    __syncthreads();
+    visit_batch(st, a, v, u);
+    __syncthreads();  // the window is rewritten by the next chunk
+    if (c1 + 1 < e_hi) {
+      // the entry holding arc c1 + 1 is at or after the one holding c1
+      i0 = staged ? i0 + m - 1 : find_entry_block(es, i0, last, c1 + 1, L.cnt);
+    }
   }
-  stage_flush(st, a);
-  level_end(a, &b, p, b.ring, GSW_K_PUSH_EDGE, st.buf, (int)sizeof(st.buf));
 }
 
 // ------------------------------------------ pull_bitmap (wave / 512 vertices)
@@ -960,56 +1067,66 @@ __device__ __forceinline__ void body_edge_scan(const Args& a, Stage& st) {
 }
 
 // ------------------------------------------------ one level, any variant
-// Runs level ctl->d with the kernel ctl->kernel names; does nothing when that
-// is push_edge (launched by the host) or when the search has ended.
-__global__ void __launch_bounds__(kBlock) k_level_auto(BfsBase b, BfsPolicy p) {
+// Launch j of a search runs what control slot j % 2 names: level ctl->d with
+// kernel ctl->kernel (push_edge: its scan or, in the next launch, its
+// expansion), and writes slot (j + 1) % 2 for the next launch.  Late
+// workgroups of a launch therefore never see the next launch's state.  Once
+// the search has ended a launch does nothing but pass that on.
+union LevelLds {
+  LongRows lr;
+  u64 found[kWaves][kPullChunk];
+  EdgeLds edge;
+  int64_t wsum[kWaves];
+};
+
+__global__ void __launch_bounds__(kBlock) k_level_auto(BfsBase b, BfsPolicy p, int32_t j) {
   __shared__ Stage st;
   __shared__ QueueIn qi;
-  __shared__ u64 s_found[kWaves][kPullChunk];
-  __shared__ LongRows lr;
-  const int k = b.ctl->kernel;
-  if (k < 0 || k >= GSW_N_KERNELS || k == GSW_K_PUSH_EDGE) return;
-  const int32_t d = b.ctl->d;
-  const int32_t grid = b.ctl->grid;
-  clear_bitmap(b.bm[(d + 2) % 3], b.nw);
-  if ((int32_t)blockIdx.x >= grid) return;  // not needed for this level (grid <= the launch)
-  Args a = make_args(b, d, 0u, 1, grid);
-  level_begin(a);
-  clear_ahead(a);
+  __shared__ LevelLds lds;
+  const BfsCtl* c = b.ctl + (j & 1);
+  const int k = c->kernel;
+  if (k < 0 || k >= GSW_N_KERNELS) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) b.ctl[(j + 1) & 1].kernel = kCtlDone;
+    return;
+  }
+  const int32_t d = c->d;
+  const int32_t grid = c->grid;
+  const int32_t phase = k == GSW_K_PUSH_EDGE ? c->phase : 0;
+  if (phase == 0) clear_bitmap(b.bm[(d + 2) % 3], b.nw);
+  if ((int32_t)blockIdx.x >= grid) return;  // not needed for this launch (grid <= the launch)
+  Args a = make_args(b, j, d, 0u, 1, grid);
+  if (phase == 0) {
+    level_begin(a);
+    clear_ahead(a);
+  }
   stage_init(st);
   if (k != GSW_K_PULL_BITMAP && k != GSW_K_VERTEX_SCAN && k != GSW_K_EDGE_SCAN) {
     queue_in_load(a, qi);
     a.n_in = qi.pre[kQueueBins];
   }
+  if (k == GSW_K_PUSH_EDGE && phase == 0) {
+    body_edge_prefix(a, qi, b, lds.wsum);
+    edge_prefix_end(a, b, lds.wsum);
+    return;
+  }
   switch (k) {
-    case GSW_K_PUSH_VERTEX: body_push_vertex(a, st, qi, lr); break;
-    case GSW_K_PUSH_WAVE4: body_push_wave<4>(a, st, qi, lr); break;
-    case GSW_K_PUSH_WAVE8: body_push_wave<8>(a, st, qi, lr); break;
-    case GSW_K_PUSH_WAVE16: body_push_wave<16>(a, st, qi, lr); break;
-    case GSW_K_PUSH_WAVE32: body_push_wave<32>(a, st, qi, lr); break;
-    case GSW_K_PUSH_WAVE64: body_push_wave<64>(a, st, qi, lr); break;
-    case GSW_K_PULL_BITMAP: body_pull(a, st, s_found); break;
-    case GSW_K_VERTEX_SCAN: body_vertex_scan(a, st, lr); break;
+    case GSW_K_PUSH_VERTEX: body_push_vertex(a, st, qi, lds.lr); break;
+    case GSW_K_PUSH_WAVE4: body_push_wave<4>(a, st, qi, lds.lr); break;
+    case GSW_K_PUSH_WAVE8: body_push_wave<8>(a, st, qi, lds.lr); break;
+    case GSW_K_PUSH_WAVE16: body_push_wave<16>(a, st, qi, lds.lr); break;
+    case GSW_K_PUSH_WAVE32: body_push_wave<32>(a, st, qi, lds.lr); break;
+    case GSW_K_PUSH_WAVE64: body_push_wave<64>(a, st, qi, lds.lr); break;
+    case GSW_K_PUSH_EDGE: {
+      const EdgeScan es{b.scan, b.ebeg, b.bsum};
+      body_edge_expand(a, st, qi, es, lds.edge, c->etot);
+      break;
+    }
+    case GSW_K_PULL_BITMAP: body_pull(a, st, lds.found); break;
+    case GSW_K_VERTEX_SCAN: body_vertex_scan(a, st, lds.lr); break;
     default: body_edge_scan(a, st); break;
   }
   stage_flush(st, a);
   level_end(a, &b, p, b.ring, k, st.buf, (int)sizeof(st.buf));
-}
-
-// Frontier bitmap of depth ctl->d from the level array, after a push_edge
-// level when the next level is bottom-up (or always with force).
-__global__ void __launch_bounds__(kBlock) k_rebuild_bitmap(BfsBase b, int32_t force) {
-  const BfsCtl* c = b.ctl;
-  if (!force && c->kernel != GSW_K_PULL_BITMAP) return;
-  const int32_t d = c->d;
-  u64* bm = b.bm[d % 3];
-  const int lane = lane_id();
-  const int64_t nwaves = (int64_t)gridDim.x * kWaves;
-  for (int64_t w = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6; w < b.nw; w += nwaves) {
-    const int64_t v = w * 64 + lane;
-    const u64 m = __ballot(v < b.n && b.level[v] == d);
-    if (lane == 0) bm[w] = m;
-  }
 }
 
 // ------------------------------------------------------------ helpers
@@ -1081,31 +1198,10 @@ gsw_status launch_init(const gsw_graph* g, const BfsBase& b, int32_t source, int
   return GSW_OK;
 }
 
-gsw_status launch_level_auto(const gsw_graph* g, const BfsBase& b, const BfsPolicy& p, hipStream_t s) {
+gsw_status launch_level_auto(const gsw_graph* g, const BfsBase& b, const BfsPolicy& p, int32_t j,
+                             hipStream_t s) {
   (void)g;
-  hipLaunchKernelGGL(k_level_auto, dim3((unsigned)b.grid_max), dim3(kBlock), 0, s, b, p);
-  GSW_HIP(hipGetLastError());
-  return GSW_OK;
-}
-
-gsw_status launch_level_edge(const gsw_graph* g, const BfsBase& b, const BfsPolicy& p, int32_t d,
-                             uint32_t n_in, bool force_bitmap, hipStream_t s) {
-  const Workspace& w = g->ws;
-  Args a = make_args(b, d, n_in, 0, kMaxGrid);
-  const int64_t nb = cdiv(n_in, kScanTile) > 0 ? cdiv(n_in, kScanTile) : 1;
-  hipLaunchKernelGGL(k_edge_scan_local, dim3((unsigned)nb), dim3(kBlock), 0, s, a, w.scan, w.ebeg, w.bsum);
-  hipLaunchKernelGGL(k_edge_scan_blocks, dim3(1), dim3(1024), 0, s, w.bsum, nb, w.etot);
-  hipLaunchKernelGGL(k_edge_expand, dim3(kMaxGrid), dim3(kBlock), 0, s, a, (const int64_t*)w.scan,
-                     (const int64_t*)w.ebeg, (const int64_t*)w.bsum, (const u64*)w.etot, p, b);
-  hipLaunchKernelGGL(k_rebuild_bitmap, dim3(persistent_grid(cdiv(b.nw, kWaves))), dim3(kBlock), 0, s, b,
-                     force_bitmap ? 1 : 0);
-  GSW_HIP(hipGetLastError());
-  return GSW_OK;
-}
-
-gsw_status launch_rebuild_bitmap(const gsw_graph* g, const BfsBase& b, hipStream_t s) {
-  (void)g;
-  hipLaunchKernelGGL(k_rebuild_bitmap, dim3(persistent_grid(cdiv(b.nw, kWaves))), dim3(kBlock), 0, s, b, 1);
+  hipLaunchKernelGGL(k_level_auto, dim3((unsigned)b.grid_max), dim3(kBlock), 0, s, b, p, j);
   GSW_HIP(hipGetLastError());
   return GSW_OK;
 }

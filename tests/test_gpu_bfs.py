@@ -318,3 +318,25 @@ def test_graph_info():
     assert info["n"] == g.n and info["nnz"] == g.nnz
     np.testing.assert_allclose(info["deg_stats"], ofeat.graph_features(g.offs)[2:8], rtol=1e-12)
     assert info["dev_bytes"] >= 8 * (g.n + 1) + 4 * g.nnz
+
+
+def test_push_edge_empty_and_long_rows():
+    # directed: the source reaches 3000 vertices, most without out-arcs and
+    # every 300th with a row of 2000, so push_edge's chunks span runs of
+    # empty queue entries and rows longer than a chunk; then the same graph
+    # made symmetric (its 3000-entry frontier of mostly one-arc rows spans
+    # more entries per chunk than the staging window holds)
+    hubs = list(range(1, 3001, 300))
+    src = [0] * 3000 + [h for h in hubs for _ in range(2000)]
+    dst = list(range(1, 3001)) + [3001 + i * 2000 + j for i in range(len(hubs)) for j in range(2000)]
+    n = 3001 + 2000 * len(hubs)
+    for sym in (False, True):
+        d = gg.from_edges(n, src, dst, symmetrize=sym)
+        G = gsw.Graph.from_csr(d.offs, d.cols, flags=gsw.ASSUME_SYMMETRIC if sym else 0)
+        for s in (0, 1):
+            ref = oracle.levels(d.offs, d.cols, s)
+            lv, pa, _ = gsw.bfs(G, [s], policy="fixed", kernel=gsw.PUSH_EDGE)
+            assert np.array_equal(lv[0], ref), (sym, s)
+            if sym:
+                checks.check_bfs(d.offs, d.cols, s, lv[0], pa[0], checks.components(d.n, d.offs, d.cols))
+        G.close()
