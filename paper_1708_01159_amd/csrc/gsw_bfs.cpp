@@ -66,32 +66,65 @@ gsw_status check_kernel(const gsw_graph* g, int k) {
   return GSW_OK;
 }
 
-// Device copy of the tree, uploaded once per (workspace, tree).
+// Device copy of the tree, uploaded once per (workspace, tree) and
+// specialised to the graph: a split on one of the graph's own features
+// (constant for the graph) is decided here, with the same float rounding
+// as every other comparison, so the copy holds only the nodes reachable
+// through splits on the level features.  The walk's outcome is unchanged.
+// Nodes are renumbered in preorder, so children still follow their parent.
 gsw_status ensure_tree(gsw_graph* g, const gsw_tree* t) {
   Workspace& w = g->ws;
   if (w.tree_id == t->id) return GSW_OK;
   if (t->n_nodes > kMaxTreeNodes) return fail(GSW_EINVAL, "tree of %d nodes: at most %d", t->n_nodes, kMaxTreeNodes);
-  if (w.tree_cap < t->n_nodes) {
+  double gf[GSW_N_FEATURES];
+  GSW_TRY(gsw_level_features(g, 0, 0, gf));
+  auto resolve = [&](int32_t i) {
+    while (t->left[(size_t)i] != -1 && t->feature[(size_t)i] < 8) {
+      const double xv = (double)(float)gf[t->feature[(size_t)i]];
+      i = xv <= t->threshold[(size_t)i] ? t->left[(size_t)i] : t->right[(size_t)i];
+    }
+    return i;
+  };
+  std::vector<int32_t> order;  // kept nodes (old ids) in preorder
+  std::vector<int32_t> newid((size_t)t->n_nodes, -1);
+  std::vector<int32_t> stack{resolve(0)};
+  while (!stack.empty()) {
+    const int32_t i = stack.back();
+    stack.pop_back();
+    newid[(size_t)i] = (int32_t)order.size();
+    order.push_back(i);
+    if (t->left[(size_t)i] != -1) {
+      stack.push_back(resolve(t->right[(size_t)i]));
+      stack.push_back(resolve(t->left[(size_t)i]));
+    }
+  }
+  const int32_t m = (int32_t)order.size();
+  if (w.tree_cap < m) {
     if (w.d_tree) (void)hipFree(w.d_tree);
     if (w.d_thr) (void)hipFree(w.d_thr);
     w.d_tree = nullptr;
     w.d_thr = nullptr;
     w.tree_cap = 0;
-    if (hipMalloc((void**)&w.d_tree, (size_t)t->n_nodes * sizeof(unsigned long long)) != hipSuccess ||
-        hipMalloc((void**)&w.d_thr, (size_t)t->n_nodes * sizeof(double)) != hipSuccess) {
+    if (hipMalloc((void**)&w.d_tree, (size_t)m * sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc((void**)&w.d_thr, (size_t)m * sizeof(double)) != hipSuccess) {
       (void)hipGetLastError();
       return fail(GSW_ENOMEM, "hipMalloc for the device copy of the tree failed");
     }
-    w.tree_cap = t->n_nodes;
+    w.tree_cap = m;
   }
-  std::vector<unsigned long long> nodes((size_t)t->n_nodes);
-  for (int32_t i = 0; i < t->n_nodes; ++i) {
+  std::vector<unsigned long long> nodes((size_t)m);
+  std::vector<double> thr((size_t)m);
+  for (int32_t k = 0; k < m; ++k) {
+    const int32_t i = order[(size_t)k];
     const bool leaf = t->left[(size_t)i] == -1;
-    nodes[(size_t)i] = tree_node_pack(t->left[(size_t)i], t->right[(size_t)i], leaf ? 0 : t->feature[(size_t)i],
-                                      t->leaf_kernel[(size_t)i]);
+    const int32_t l = leaf ? -1 : newid[(size_t)resolve(t->left[(size_t)i])];
+    const int32_t r = leaf ? -1 : newid[(size_t)resolve(t->right[(size_t)i])];
+    nodes[(size_t)k] = tree_node_pack(l, r, leaf ? 0 : t->feature[(size_t)i], t->leaf_kernel[(size_t)i]);
+    thr[(size_t)k] = t->threshold[(size_t)i];
   }
   GSW_HIP(hipMemcpy(w.d_tree, nodes.data(), nodes.size() * sizeof(unsigned long long), hipMemcpyHostToDevice));
-  GSW_HIP(hipMemcpy(w.d_thr, t->threshold.data(), (size_t)t->n_nodes * sizeof(double), hipMemcpyHostToDevice));
+  GSW_HIP(hipMemcpy(w.d_thr, thr.data(), thr.size() * sizeof(double), hipMemcpyHostToDevice));
+  w.tree_nodes = m;
   w.tree_id = t->id;
   return GSW_OK;
 }
@@ -128,7 +161,7 @@ BfsPolicy device_policy(const gsw_graph* g, const gsw_bfs_opts* o, bool has_orig
   p.sched = g->ws.d_sched;
   p.t_node = g->ws.d_tree;
   p.t_thr = g->ws.d_thr;
-  p.t_nodes = o->policy == GSW_POLICY_TREE && o->tree ? o->tree->n_nodes : 0;
+  p.t_nodes = o->policy == GSW_POLICY_TREE && o->tree ? g->ws.tree_nodes : 0;
   p.feat[0] = (double)g->n;
   p.feat[1] = (double)g->nnz;
   for (int i = 0; i < 6; ++i) p.feat[2 + i] = g->deg_stats[i];

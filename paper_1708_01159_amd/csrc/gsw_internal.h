@@ -65,6 +65,7 @@ struct Workspace {
   unsigned long long* d_tree = nullptr;  // device copy of the tree's nodes (packed) ...
   double* d_thr = nullptr;               // ... and thresholds
   int32_t tree_cap = 0;                  // nodes the device copy has room for
+  int32_t tree_nodes = 0;                // nodes of the device copy (specialised to this graph)
   uint64_t tree_id = 0;                  // tree currently uploaded (0: none)
   int32_t* d_sched = nullptr;            // device copy of a schedule
   int32_t sched_cap = 0;

@@ -353,18 +353,6 @@ __device__ __forceinline__ int choose_next(const BfsPolicy& p, int32_t d, long l
   return choose_leaf(p, k, prev, flags);
 }
 
-// End of a level, called by every thread of every workgroup of the level's
-// last kernel: the last workgroup to finish sums the next frontier's
-// segments, picks the next kernel, posts the level's record to the host
-// ring (its first word last) and rewrites the control block.  Each
-// workgroup's queue-segment atomics have returned before it counts itself
-// finished, so the last one sees every segment's final size.  With the tree
-// policy that workgroup evaluates every node's split at once, one node per
-// thread and round, into a child table in `lds` (lds_bytes of LDS free by
-// now, the flushed append stage; 4 bytes per node), and one thread then
-// follows the table from the root: a chain of LDS reads instead of a global
-// load per node.  Its first two nodes per thread are loaded before the
-// segment sum, so that their latency overlaps it.
 // True (in every thread) in the last workgroup of the launch to get here;
 // called by every thread of every participating workgroup.  The last one
 // resets the counters (before the launch ends, for the next one).
@@ -394,14 +382,35 @@ __device__ __forceinline__ bool launch_last(const Args& a) {
   return last;
 }
 
+// End of a level, called by every thread of every workgroup of the level's
+// last launch: the last workgroup to finish sums the next frontier's
+// segments, picks the next kernel, posts the level's record to the host
+// ring and writes the next launch's control slot.  Each workgroup's
+// queue-segment atomics have returned before it counts itself finished, so
+// the last one sees every segment's final size.  The device copy of a tree
+// is specialised to the graph (only splits on the level features remain):
+// when it has at most 64 nodes, wave 0 of every workgroup loads one node
+// per lane before the count, and the last one evaluates every node's split
+// at once and follows the children with lane shuffles.  A larger tree is
+// evaluated the same way by the whole last workgroup into a child table in
+// `lds` (lds_bytes of LDS free by now, the flushed append stage; 4 bytes per
+// node); one beyond that is walked from global memory.
 __device__ __forceinline__ void level_end(const Args& a, const BfsBase* base, const BfsPolicy& p, u64* ring,
                                           int k_run, void* lds, int lds_bytes) {
   __shared__ uint32_t s_nn;
   __shared__ double s_feat[8];
-  if (!launch_last(a)) return;
   const int tid = threadIdx.x;
+  const bool tree = p.policy == GSW_POLICY_TREE;
+  const bool tree_wave = tree && p.t_nodes <= 64;
+  const bool tree_par = tree && !tree_wave && (long long)p.t_nodes * 4 <= (long long)lds_bytes;
+  u64 wnd = 0ull;
+  double wth = 0.0;
+  if (tree_wave && tid < p.t_nodes) {
+    wnd = p.t_node[tid];
+    wth = p.t_thr[tid];
+  }
+  if (!launch_last(a)) return;
   BfsCtl* c = a.ctl;
-  const bool tree_par = p.policy == GSW_POLICY_TREE && (long long)p.t_nodes * 4 <= (long long)lds_bytes;
   int32_t* l_next = reinterpret_cast<int32_t*>(lds);
   u64 nd0 = 0ull, nd1 = 0ull;
   double th0 = 0.0, th1 = 0.0;
@@ -415,25 +424,49 @@ __device__ __forceinline__ void level_end(const Args& a, const BfsBase* base, co
       th1 = p.t_thr[tid + kBlock];
     }
     if (tid < 8) s_feat[tid] = p.feat[tid];
+  } else if (tid >= 64) {
+    return;  // wave 0 finishes the level
   }
   const long long disc0 = c->disc;
+  uint32_t nn = 0u;
   if (tid < 64) {  // wave 0: the next frontier's segments
     uint32_t x = tid < kQueueBins
                      ? __hip_atomic_load(a.cout + tid * kCtrStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                      : 0u;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) x += (uint32_t)__shfl_xor((int)x, off);
-    if (tid == 0) s_nn = x;
+    nn = x;
   }
-  __syncthreads();
-  const uint32_t nn = s_nn;
-  const long long ndisc = disc0 + (long long)nn;
-  if (tree_par && nn > 0) {
-    if (tid < p.t_nodes) l_next[tid] = tree_step(nd0, th0, s_feat, (double)nn, (double)ndisc);
-    if (tid + kBlock < p.t_nodes) l_next[tid + kBlock] = tree_step(nd1, th1, s_feat, (double)nn, (double)ndisc);
-    for (int i = tid + 2 * kBlock; i < p.t_nodes; i += kBlock)
-      l_next[i] = tree_step(p.t_node[i], p.t_thr[i], s_feat, (double)nn, (double)ndisc);
+  if (tree_par) {
+    if (tid == 0) s_nn = nn;
     __syncthreads();
+    nn = s_nn;
+    const long long nd = disc0 + (long long)nn;
+    if (nn > 0) {
+      if (tid < p.t_nodes) l_next[tid] = tree_step(nd0, th0, s_feat, (double)nn, (double)nd);
+      if (tid + kBlock < p.t_nodes) l_next[tid + kBlock] = tree_step(nd1, th1, s_feat, (double)nn, (double)nd);
+      for (int i = tid + 2 * kBlock; i < p.t_nodes; i += kBlock)
+        l_next[i] = tree_step(p.t_node[i], p.t_thr[i], s_feat, (double)nn, (double)nd);
+    }
+    __syncthreads();
+    if (tid >= 64) return;
+  }
+  const long long ndisc = disc0 + (long long)nn;
+  int32_t nflags = 0;
+  int32_t next = kCtlDone;
+  if (nn > 0) {
+    if (tree_wave) {
+      const int32_t ch = tid < p.t_nodes ? tree_step(wnd, wth, p.feat, (double)nn, (double)ndisc) : 0;
+      int32_t x = __shfl(ch, 0);
+      while (x >= 0) x = __shfl(ch, x);
+      next = choose_leaf(p, x == -1 ? -1 : -x - 2, k_run, &nflags);
+    } else if (tree_par) {
+      int32_t x = l_next[0];
+      while (x >= 0) x = l_next[x];
+      next = choose_leaf(p, x == -1 ? -1 : -x - 2, k_run, &nflags);
+    } else {
+      next = choose_next(p, a.d + 1, (long long)nn, ndisc, k_run, &nflags);
+    }
   }
   if (tid != 0) return;
   u64 ticks = 0ull;
@@ -444,17 +477,6 @@ __device__ __forceinline__ void level_end(const Args& a, const BfsBase* base, co
   }
   const int32_t d = a.d;
   const long long nf = c->nf, disc = disc0;
-  int32_t nflags = 0;
-  int32_t next = kCtlDone;
-  if (nn > 0) {
-    if (tree_par) {
-      int32_t x = l_next[0];
-      while (x >= 0) x = l_next[x];
-      next = choose_leaf(p, x == -1 ? -1 : -x - 2, k_run, &nflags);
-    } else {
-      next = choose_next(p, d + 1, (long long)nn, ndisc, k_run, &nflags);
-    }
-  }
   u64* r = ring + (size_t)(d % kBfsRing) * kBfsRec;
   const u64 tag = rec_tag(d);
   const u64 rec[kBfsRecWords] = {(u64)k_run, (u64)c->flags, (u64)nf, (u64)disc, (u64)nn, ticks & kRecValueMask,
