@@ -3,7 +3,8 @@
 // writes the next launch's control slot) and posts a record per level to a
 // ring in mapped host memory; the host keeps a few launches of the level
 // kernel queued and reads the records in order for the trace and the end of
-// the search.  A push_edge level takes two launches, any other one.  Also
+// the search.  A push_edge level on more than kEdgeFuse entries takes two
+// launches, any other level one.  Also
 // the per-level profiler that measures every kernel from the same saved
 // state (the training data of the decision tree).
 #include <hip/hip_runtime.h>
@@ -253,7 +254,7 @@ gsw_status run_levels(gsw_graph* g, const Policy& pol, const BfsPolicy& dp, int3
   GSW_TRY(launch_init(g, b, src, k0, flags0, s));
   int32_t j = 0;     // launches of the level kernel so far
   int ahead = 0;     // of those, not yet used by a level whose record was read
-  int want = kAhead + (k0 == GSW_K_PUSH_EDGE ? 1 : 0);
+  int want = kAhead + level_launches(k0, 1) - 1;
   for (int64_t d = 0;; ++d) {
     while (ahead < want) {
       GSW_TRY(launch_level_auto(g, b, dp, j++, s));
@@ -277,9 +278,9 @@ gsw_status run_levels(gsw_graph* g, const Policy& pol, const BfsPolicy& dp, int3
       t.reserved = 0;
     }
     ++*rows;
-    ahead -= k == GSW_K_PUSH_EDGE ? 2 : 1;
+    ahead -= level_launches(k, r.nf);
     if (nn == 0) break;
-    want = kAhead + (nk == GSW_K_PUSH_EDGE ? 1 : 0);
+    want = kAhead + level_launches(nk, nn) - 1;
   }
   if (o->canonical_parents && pa) GSW_TRY(launch_canonical_parents(g, lv, pa, s));
   return GSW_OK;
@@ -473,17 +474,17 @@ gsw_status gsw_bfs_profile(const gsw_graph* cg, int32_t source, const int32_t* k
       w.h_ctl->kernel = k;
       w.h_ctl->grid = level_participants(k, nf, b);
       w.h_ctl->done_blocks = 0u;
-      w.h_ctl->phase = 0;
+      w.h_ctl->phase = level_first_phase(k, nf);
       GSW_HIP(hipMemcpyAsync(w.ctl, w.h_ctl, sizeof(BfsCtl), hipMemcpyHostToDevice, s));
       GSW_HIP(hipStreamSynchronize(s));  // the staging copy is reused by the next restore
       return GSW_OK;
     };
     // one level with kernel k as the level loop runs it: one launch of the
-    // level kernel, two for push_edge
+    // level kernel, two for push_edge on more than kEdgeFuse entries
     auto run = [&](int k, bool timed_bracket) -> gsw_status {
       if (timed_bracket) GSW_HIP(hipEventRecord(w.ev[0], s));
       GSW_TRY(launch_level_auto(g, b, dp, 0, s));
-      if (k == GSW_K_PUSH_EDGE) GSW_TRY(launch_level_auto(g, b, dp, 1, s));
+      if (level_launches(k, nf) == 2) GSW_TRY(launch_level_auto(g, b, dp, 1, s));
       if (timed_bracket) GSW_HIP(hipEventRecord(w.ev[1], s));
       return GSW_OK;
     };
@@ -517,7 +518,7 @@ gsw_status gsw_bfs_profile(const gsw_graph* cg, int32_t source, const int32_t* k
     }
     GSW_TRY(restore(adv));
     GSW_TRY(run(adv, false));
-    cur = adv == GSW_K_PUSH_EDGE ? 0 : 1;
+    cur = level_launches(adv, nf) & 1;  // slot written by the last launch
     GSW_HIP(hipStreamSynchronize(s));
     Record r;
     GSW_TRY(wait_record(g, d, s, &r));

@@ -120,7 +120,7 @@ struct BfsCtl {
   long long nf;     // frontier size of level d
   long long disc;   // vertices discovered through depth d
   unsigned int done_blocks;  // groups of workgroups of the running launch that have finished
-  int32_t phase;             // push_edge levels take two launches: 0 = scan, 1 = expand
+  int32_t phase;             // push_edge: 0 = prefix launch, 1 = expansion launch, 2 = both in one
   unsigned long long t_begin;  // wall clock at the start of the running level (timed levels)
   int32_t grid;                // workgroups that run this launch of level d (the rest exit)
   int32_t pad2;
@@ -129,9 +129,19 @@ struct BfsCtl {
 // Workgroups count themselves finished in kDoneGroups counters (by index
 // modulo kDoneGroups, kCtrStride words apart); the last of each group then
 // counts its group in BfsCtl::done_blocks.  Same-address atomics serialise,
-// so 2048 workgroups on one counter would cost about 20 us per level.
+// so a full launch on one counter would cost about 15 us per level.
 constexpr int kDoneGroups = 16;
 constexpr int32_t kCtlDone = -1;
+
+// push_edge with at most kEdgeFuse frontier entries runs in one launch
+// (every workgroup scans the whole queue in LDS); a larger one takes two.
+constexpr int64_t kEdgeFuse = 512;
+__host__ __device__ inline int32_t level_first_phase(int kernel, int64_t nf) {
+  return kernel == GSW_K_PUSH_EDGE ? (nf <= kEdgeFuse ? 2 : 0) : 0;
+}
+__host__ __device__ inline int level_launches(int kernel, int64_t nf) {
+  return kernel == GSW_K_PUSH_EDGE && nf > kEdgeFuse ? 2 : 1;
+}
 
 // How the device picks the next level's kernel (a kernel argument): the same
 // policies and rules as the host's choice for level 0.

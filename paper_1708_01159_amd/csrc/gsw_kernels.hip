@@ -44,7 +44,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
-constexpr int kMaxGrid = 2048;                   // persistent producer grids (8 per CU)
+constexpr int kMaxGrid = 1536;                   // persistent producer grids (6 per CU; measured best)
 constexpr int kStage = 2048;                     // LDS-staged queue entries per workgroup
 constexpr int kScanItems = 4;                    // push_edge: entries per thread in the scan
 constexpr int kScanTile = kBlock * kScanItems;   // entries per scan block
@@ -124,7 +124,9 @@ __host__ __device__ inline int32_t level_grid(int k, int64_t n_in, const BfsBase
     case GSW_K_PULL_BITMAP: need = b.grid_max; break;
     case GSW_K_VERTEX_SCAN: need = div_up(b.n, kBlock); break;
     case GSW_K_EDGE_SCAN: need = div_up(b.nnz, kBlock); break;
-    case GSW_K_PUSH_EDGE: need = div_up(n_in, kScanTile); break;  // its scan launch
+    case GSW_K_PUSH_EDGE:  // its prefix launch, or every workgroup when fused
+      need = level_first_phase(k, n_in) == 2 ? (int64_t)b.grid_max : div_up(n_in, kScanTile);
+      break;
     default: need = div_up(n_in, kBlock); break;
   }
   if (need < 1) need = 1;
@@ -492,7 +494,7 @@ __device__ __forceinline__ void level_end(const Args& a, const BfsBase* base, co
   cn->nf = (long long)nn;
   cn->disc = ndisc;
   cn->done_blocks = 0u;
-  cn->phase = 0;
+  cn->phase = level_first_phase(next, (int64_t)nn);
   cn->t_begin = 0ull;
   cn->grid = next >= 0 ? level_grid(next, (int64_t)nn, *base) : 1;
   cn->etot = 0;
@@ -533,7 +535,7 @@ __global__ void __launch_bounds__(kBlock) k_init(BfsBase b, const u64* __restric
     c->nf = 1;
     c->disc = 1;
     c->done_blocks = 0u;
-    c->phase = 0;
+    c->phase = level_first_phase(k0, 1);
     c->t_begin = 0ull;
     c->grid = level_grid(k0, 1, b);
     c->etot = 0;
@@ -722,8 +724,10 @@ struct EdgeLds {
   int64_t start[kEdgeWin];  // arc offset of each staged entry
   int64_t beg[kEdgeWin];    // its row start
   int32_t u[kEdgeWin];      // its vertex
+  int64_t wsum[kWaves];
   int32_t cnt[kWaves];
 };
+static_assert(kEdgeFuse <= kEdgeWin && kEdgeFuse <= 2 * kBlock, "fused push_edge stages every entry");
 
 // Number of workgroup lanes with pred set (every thread calls it).
 __device__ __forceinline__ int block_count(bool pred, int32_t* cnt) {
@@ -907,6 +911,74 @@ __device__ __forceinline__ void body_edge_expand(const Args& a, Stage& st, const
       i0 = staged ? i0 + m - 1 : find_entry_block(es, i0, last, c1 + 1, L.cnt);
     }
   }
+}
+
+// Both launches in one, for at most kEdgeFuse entries: every workgroup of
+// the launch reads the whole queue and scans its degrees in LDS, so each
+// knows the arc total and needs no search; workgroups beyond the number
+// the total calls for leave (returns false) and a.grid becomes that number.
+__device__ __forceinline__ bool body_edge_fused(Args& a, Stage& st, const QueueIn& qi, EdgeLds& L) {
+  int64_t* wsum = L.wsum;
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wid = tid >> 6;
+  const int n_in = (int)(a.n_in < (uint32_t)kEdgeFuse ? a.n_in : (uint32_t)kEdgeFuse);  // == a.n_in
+  int64_t deg[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int i = 2 * tid + q;
+    deg[q] = 0;
+    if (i < n_in) {
+      const int32_t u = queue_at(a, qi, (uint32_t)i);
+      const int64_t rb = a.offs[u];
+      deg[q] = a.offs[u + 1] - rb;
+      L.u[i] = u;
+      L.beg[i] = rb;
+    }
+  }
+  const int64_t tot = deg[0] + deg[1];
+  int64_t inc = tot;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t y = __shfl_up(inc, off);
+    if (lane >= off) inc += y;
+  }
+  if (lane == 63) wsum[wid] = inc;
+  __syncthreads();
+  int64_t run = inc - tot, total = 0;
+  for (int w = 0; w < kWaves; ++w) {
+    run += w < wid ? wsum[w] : 0;
+    total += wsum[w];
+  }
+  if (2 * tid < n_in) L.start[2 * tid] = run;
+  if (2 * tid + 1 < n_in) L.start[2 * tid + 1] = run + deg[0];
+  __syncthreads();
+  const int64_t chunks = div_up(total, kEdgeChunk);
+  const int64_t G = chunks < 1 ? 1 : (chunks < a.grid ? chunks : a.grid);
+  if ((int64_t)blockIdx.x >= G) return false;
+  a.grid = (int32_t)G;
+  const int64_t e_lo = total * (int64_t)blockIdx.x / G;
+  const int64_t e_hi = total * ((int64_t)blockIdx.x + 1) / G;
+  for (int64_t c0 = e_lo; c0 < e_hi; c0 += kEdgeChunk) {
+    int32_t v[kBatch], u[kBatch];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      const int64_t t = c0 + (int64_t)j * kBlock + tid;
+      v[j] = -1;
+      u[j] = 0;
+      if (t < e_hi) {
+        int lo = 0, hi = n_in - 1;  // last entry whose arcs start at or before t
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (L.start[mid] <= t) lo = mid; else hi = mid - 1;
+        }
+        v[j] = a.cols[L.beg[lo] + (t - L.start[lo])];
+        u[j] = L.u[lo];
+      }
+    }
+    visit_batch(st, a, v, u);
+  }
+  return true;
 }
 
 // ------------------------------------------ pull_bitmap (wave / 512 vertices)
@@ -1114,10 +1186,10 @@ __global__ void __launch_bounds__(kBlock) k_level_auto(BfsBase b, BfsPolicy p, i
   const int32_t d = c->d;
   const int32_t grid = c->grid;
   const int32_t phase = k == GSW_K_PUSH_EDGE ? c->phase : 0;
-  if (phase == 0) clear_bitmap(b.bm[(d + 2) % 3], b.nw);
+  if (phase != 1) clear_bitmap(b.bm[(d + 2) % 3], b.nw);
   if ((int32_t)blockIdx.x >= grid) return;  // not needed for this launch (grid <= the launch)
   Args a = make_args(b, j, d, 0u, 1, grid);
-  if (phase == 0) {
+  if (phase != 1) {
     level_begin(a);
     clear_ahead(a);
   }
@@ -1129,6 +1201,12 @@ __global__ void __launch_bounds__(kBlock) k_level_auto(BfsBase b, BfsPolicy p, i
   if (k == GSW_K_PUSH_EDGE && phase == 0) {
     body_edge_prefix(a, qi, b, lds.wsum);
     edge_prefix_end(a, b, lds.wsum);
+    return;
+  }
+  if (k == GSW_K_PUSH_EDGE && phase == 2) {
+    if (!body_edge_fused(a, st, qi, lds.edge)) return;
+    stage_flush(st, a);
+    level_end(a, &b, p, b.ring, k, st.buf, (int)sizeof(st.buf));
     return;
   }
   switch (k) {

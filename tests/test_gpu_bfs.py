@@ -322,16 +322,18 @@ def test_graph_info():
     assert info["dev_bytes"] >= 8 * (g.n + 1) + 4 * g.nnz
 
 
-def test_push_edge_empty_and_long_rows():
-    # directed: the source reaches 3000 vertices, most without out-arcs and
-    # every 300th with a row of 2000, so push_edge's chunks span runs of
-    # empty queue entries and rows longer than a chunk; then the same graph
-    # made symmetric (its 3000-entry frontier of mostly one-arc rows spans
-    # more entries per chunk than the staging window holds)
-    hubs = list(range(1, 3001, 300))
-    src = [0] * 3000 + [h for h in hubs for _ in range(2000)]
-    dst = list(range(1, 3001)) + [3001 + i * 2000 + j for i in range(len(hubs)) for j in range(2000)]
-    n = 3001 + 2000 * len(hubs)
+@pytest.mark.parametrize("width", [3000, 300])
+def test_push_edge_empty_and_long_rows(width):
+    # directed: the source reaches `width` vertices, most without out-arcs
+    # and every (width/10)-th with a row of 2000, so push_edge's chunks span
+    # runs of empty queue entries and rows longer than a chunk; then the same
+    # graph made symmetric (a 3000-entry frontier of mostly one-arc rows spans
+    # more entries per chunk than the staging window holds).  300 entries
+    # take the one-launch form, 3000 the two-launch one.
+    hubs = list(range(1, width + 1, width // 10))
+    src = [0] * width + [h for h in hubs for _ in range(2000)]
+    dst = list(range(1, width + 1)) + [width + 1 + i * 2000 + j for i in range(len(hubs)) for j in range(2000)]
+    n = width + 1 + 2000 * len(hubs)
     for sym in (False, True):
         d = gg.from_edges(n, src, dst, symmetrize=sym)
         G = gsw.Graph.from_csr(d.offs, d.cols, flags=gsw.ASSUME_SYMMETRIC if sym else 0)
