@@ -16,14 +16,24 @@ Prints ONE JSON line.  Besides the contract fields:
   tree_agreement   share of levels where the tree picked that fastest kernel
   roofline         the dominant kernel of the switched path: algorithmic bytes
                    per launch / mean launch time, the time taken from the
-                   library's per-level device timers (every workgroup of the
-                   level's kernel stamps the GPU's constant-rate wall clock at
-                   entry and exit; the level lasts from the first entry to the
-                   last exit) in one instrumented pass over the same sources
-                   right after the timed steps; traffic = HBM bytes per launch
-                   from the committed rocprofv3 counter summary, while the
-                   kernel source it was taken on is unchanged
+                   library's per-level device timers (the level's first
+                   workgroup stamps the GPU's constant-rate wall clock when it
+                   starts, the level's last workgroup reads it when it ends)
+                   in one instrumented pass over the same sources right after
+                   the timed steps; traffic = HBM bytes per launch from the
+                   committed rocprofv3 counter summary, while the kernel
+                   source it was taken on is unchanged
   cpu_baseline     the CPU oracle on a bounded sample of the same sources
+
+Profiling: every expansion variant runs inside one kernel (k_level_auto),
+so rocprofv3's per-kernel view cannot tell them apart.  ``--dispatch-log``
+records, for every BFS call, the kernel and frontier size of each level;
+``--summarize-profile DIR`` (no GPU) aligns the per-dispatch rows of the
+kernel trace and of the FETCH_SIZE / WRITE_SIZE counter runs in DIR with
+that log -- each call starts with one k_init dispatch, then each level takes
+one k_level_auto launch (two for push_edge on more than 512 entries), the
+rest of the call's launches find the search ended -- and prints the
+per-variant summary kept under profiles/.
 """
 from __future__ import annotations
 
@@ -259,6 +269,135 @@ def bench_serving(args, tree, log, preloaded):
             "hbm_budget_bytes": budget, "runs": runs}
 
 
+EDGE_FUSE = 512  # the library's one-launch limit for push_edge frontiers
+PROFILE_CMD = ("python3 -u bench.py --steps 2 --warmup 1 --no-compare --copy-calib --cpu-budget 1 "
+               "--dispatch-log gpurun_out/prof/dispatch_log.json")
+
+
+def _csv_rows(path):
+    import csv
+
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def _short(name):
+    name = name.replace("gsw::(anonymous namespace)::", "").replace("void ", "")
+    return name.split("(")[0][:48]
+
+
+def _align(dispatches, calls, names):
+    """Label each dispatch (in start order) with the variant it ran."""
+    labels = ["" for _ in dispatches]
+    starts = [i for i, d in enumerate(dispatches) if _short(d[0]) == "k_init"]
+    if len(starts) != len(calls):
+        raise SystemExit("profile has %d k_init dispatches, the dispatch log %d calls" % (len(starts), len(calls)))
+    for c, (i0, call) in enumerate(zip(starts, calls)):
+        i1 = starts[c + 1] if c + 1 < len(starts) else len(dispatches)
+        mine = [i for i in range(i0 + 1, i1) if _short(dispatches[i][0]) == "k_level_auto"]
+        want = []
+        for k, nf in call["levels"]:
+            if k == 6 and nf > EDGE_FUSE:
+                want += ["push_edge (prefix)", "push_edge (expand)"]
+            else:
+                want.append(names[k])
+        if len(want) > len(mine):
+            raise SystemExit("call %d: %d level launches logged, %d dispatched" % (c, len(want), len(mine)))
+        for j, i in enumerate(mine):
+            labels[i] = want[j] if j < len(want) else "(search ended)"
+    return labels
+
+
+def summarize_profile(d):
+    """Per-variant summary of a profiled run (see the module docstring)."""
+    import hashlib
+
+    from paper_1708_01159_amd import gsw
+
+    calls = json.load(open(os.path.join(d, "dispatch_log.json")))
+    bench_line = json.loads(open(os.path.join(d, "trace_bench.json")).read().strip().splitlines()[-1])
+    tr = sorted(_csv_rows(os.path.join(d, "trace", "run_kernel_trace.csv")), key=lambda r: int(r["Start_Timestamp"]))
+    disp = [(r["Kernel_Name"], (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3) for r in tr]
+    lab = _align(disp, calls, gsw.KERNEL_NAMES)
+
+    def counters(sub, name):
+        rows = [r for r in _csv_rows(os.path.join(d, sub, "run_counter_collection.csv")) if r["Counter_Name"] == name]
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        vals = [(r["Kernel_Name"], float(r["Counter_Value"])) for r in rows]
+        return vals, _align(vals, calls, gsw.KERNEL_NAMES)
+
+    fe, fe_lab = counters("fetch", "FETCH_SIZE")
+    wr, wr_lab = counters("write", "WRITE_SIZE")
+    GiB = 1 << 30
+    copy_f = sorted(v for n, v in fe if "copyBuffer" in n)[-2:]
+    copy_w = sorted(v for n, v in wr if "copyBuffer" in n)[-2:]
+    f_scale = GiB / (np.mean(copy_f) * 1024)
+    w_scale = GiB / (np.mean(copy_w) * 1024)
+
+    def key(name, label):
+        return label if label else _short(name)
+
+    stat = {}
+    for (n, t), l in zip(disp, lab):
+        stat.setdefault(key(n, l), {"t": [], "f": [], "w": []})["t"].append(t)
+    for (n, v), l in zip(fe, fe_lab):
+        stat.setdefault(key(n, l), {"t": [], "f": [], "w": []})["f"].append(v)
+    for (n, v), l in zip(wr, wr_lab):
+        stat.setdefault(key(n, l), {"t": [], "f": [], "w": []})["w"].append(v)
+    L = ["# pull_bitmap on R-MAT scale 22 (64 sources, tree-switched path)", "",
+         "Commands (from the repository root, `TMPDIR=/tmp`; the trace run's stdout is `trace_bench.json`):", "",
+         "```",
+         "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof/trace -o run -- " + PROFILE_CMD,
+         "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof/fetch -o run -- " + PROFILE_CMD,
+         "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof/write -o run -- " + PROFILE_CMD,
+         "python3 bench.py --summarize-profile gpurun_out/prof", "```", "",
+         "Every dispatch of the command (warm-up, 2 timed steps, the instrumented pass), under the profiler. "
+         "The level kernel's dispatches are attributed to the variant each ran from the dispatch log:", "",
+         "| kernel / variant | dispatches | avg us | total us | FETCH_SIZE avg KB | WRITE_SIZE avg KB |",
+         "|---|---:|---:|---:|---:|---:|"]
+    for k in sorted(stat, key=lambda k: -sum(stat[k]["t"])):
+        st = stat[k]
+        L.append("| %s | %d | %.2f | %.1f | %.1f | %.1f |" % (
+            k, len(st["t"]), np.mean(st["t"]) if st["t"] else 0, np.sum(st["t"]),
+            np.mean(st["f"]) if st["f"] else 0, np.mean(st["w"]) if st["w"] else 0))
+    pull = stat["pull_bitmap"]
+    traffic = np.mean(pull["f"]) * 1024 * f_scale + np.mean(pull["w"]) * 1024 * w_scale
+    rl = bench_line["roofline"]
+    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_1708_01159_amd", "csrc", "gsw_kernels.hip"), "rb")
+                         .read()).hexdigest()
+    L += ["", "Counter scale from the plain 1 GiB device copy (`__amd_rocclr_copyBuffer`, 1 GiB read + "
+          "1 GiB written): FETCH_SIZE x %.3f, WRITE_SIZE x %.3f." % (f_scale, w_scale), "",
+          "pull_bitmap per launch:", "",
+          "* HBM traffic (scaled counters): %.1f MB fetched + %.1f MB written = **%.1f MB**" % (
+              np.mean(pull["f"]) * 1024 * f_scale / 1e6, np.mean(pull["w"]) * 1024 * w_scale / 1e6, traffic / 1e6),
+          "* algorithmic bytes (bench byte model, sampled launches): %.1f MB; traffic / algorithmic = %.2f" % (
+              rl["bytes_per_launch"] / 1e6, traffic / rl["bytes_per_launch"]),
+          "* mean duration: rocprofv3 %.2f us over %d dispatches; bench (device wall-clock stamps, same run) "
+          "%.2f us over %d launches" % (np.mean(pull["t"]), len(pull["t"]), rl["mean_launch_ms_all"] * 1e3,
+                                        rl["launches_all"]),
+          "* bench line of this run: value %.1f GTEPS (under the profiler), roofline achieved %.0f GB/s "
+          "(frac %.3f)" % (bench_line["value"], rl["achieved"], rl["frac"]), "",
+          "Machine-readable (read by bench.py while the kernel source is unchanged):", "", "```",
+          "traffic_bytes_per_launch: %d" % traffic, "kernel: pull_bitmap", "kernel_source_sha256: %s" % sha, "```"]
+    print("\n".join(L))
+
+
+def _logged(runner, tag, calls):
+    """Runner whose every call appends its levels' (kernel, frontier) to calls."""
+    if calls is None:
+        return runner
+    run = runner.run
+
+    def logged_run(source):
+        n = run(source)
+        calls.append({"tag": tag, "source": int(source),
+                      "levels": [[r.kernel, r.n_frontier] for r in runner.rows()]})
+        return n
+
+    runner.run = logged_run
+    return runner
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -281,7 +420,15 @@ def main():
                     help="also the structure sweep: grid 2048^2 (5%% deleted), Chung-Lu 2^23, ER 2^22")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (scale for HBM byte counters)")
+    ap.add_argument("--dispatch-log", default=None,
+                    help="write every BFS call's (kernel, frontier) per level to this JSON file")
+    ap.add_argument("--summarize-profile", default=None, metavar="DIR",
+                    help="no GPU: per-variant summary of the rocprofv3 runs in DIR, then exit")
     args = ap.parse_args()
+
+    if args.summarize_profile:
+        summarize_profile(args.summarize_profile)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -317,10 +464,12 @@ def main():
     out_lv = torch.empty((1, n), dtype=torch.int32, device="cuda")
     out_pa = torch.empty((1, n), dtype=torch.int32, device="cuda")
     deg = g.degrees()
-    sw = gsw.Runner(G, out_lv, out_pa, policy="tree", tree=tree)
-    # the same path with HIP events around every level's kernels (about 6 us
-    # of host time per level, so it is kept out of the timed steps)
-    sw_ev = gsw.Runner(G, out_lv, out_pa, policy="tree", tree=tree, time_levels=True)
+    calls = [] if args.dispatch_log else None
+    sw = _logged(gsw.Runner(G, out_lv, out_pa, policy="tree", tree=tree), "switched", calls)
+    # the same path with the per-level device timers on (kept out of the
+    # timed steps)
+    sw_ev = _logged(gsw.Runner(G, out_lv, out_pa, policy="tree", tree=tree, time_levels=True), "timed levels",
+                    calls)
 
     # warm-up (also: component sizes from the GPU's own levels, and the level
     # arrays of the first few sources for the byte model)
@@ -470,6 +619,9 @@ def main():
         "gteps_median_source": round(float(np.median(gteps_src)), 3),
     }
     line.update(extra)
+    if calls is not None:
+        with open(args.dispatch_log, "w") as f:
+            json.dump(calls, f)
     print(json.dumps(line), flush=True)
 
 
