@@ -509,7 +509,23 @@ __global__ void __launch_bounds__(kBlock) k_init(BfsBase b, const u64* __restric
                                                  int32_t k0, int32_t flags0) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (int64_t i = gid; i < b.n; i += stride) {
+  // 16-byte stores where both arrays allow them; every element is written by
+  // exactly one thread, the source's with its own values
+  const bool vec = ((uintptr_t)b.level & 15u) == 0u && ((uintptr_t)b.parent & 15u) == 0u;
+  const int64_t n4 = vec ? b.n >> 2 : 0;
+  int4* l4 = reinterpret_cast<int4*>(b.level);
+  int4* p4 = reinterpret_cast<int4*>(b.parent);
+  for (int64_t i = gid; i < n4; i += stride) {
+    int4 lv = make_int4(-1, -1, -1, -1), pv = lv;
+    if (i == (int64_t)(s >> 2)) {
+      const int k = s & 3;
+      lv.x = k == 0 ? 0 : lv.x; lv.y = k == 1 ? 0 : lv.y; lv.z = k == 2 ? 0 : lv.z; lv.w = k == 3 ? 0 : lv.w;
+      pv.x = k == 0 ? s : pv.x; pv.y = k == 1 ? s : pv.y; pv.z = k == 2 ? s : pv.z; pv.w = k == 3 ? s : pv.w;
+    }
+    l4[i] = lv;
+    if (b.parent) p4[i] = pv;
+  }
+  for (int64_t i = 4 * n4 + gid; i < b.n; i += stride) {
     b.level[i] = i == s ? 0 : -1;
     if (b.parent) b.parent[i] = i == s ? s : -1;
   }
@@ -1186,7 +1202,7 @@ __global__ void __launch_bounds__(kBlock) k_level_auto(BfsBase b, BfsPolicy p, i
   const int32_t d = c->d;
   const int32_t grid = c->grid;
   const int32_t phase = k == GSW_K_PUSH_EDGE ? c->phase : 0;
-  if (phase != 1) clear_bitmap(b.bm[(d + 2) % 3], b.nw);
+  if (phase != 1 && d > 0) clear_bitmap(b.bm[(d + 2) % 3], b.nw);  // k_init zeroed it for level 0
   if ((int32_t)blockIdx.x >= grid) return;  // not needed for this launch (grid <= the launch)
   Args a = make_args(b, j, d, 0u, 1, grid);
   if (phase != 1) {
@@ -1292,7 +1308,7 @@ gsw_status launch_init(const gsw_graph* g, const BfsBase& b, int32_t source, int
                        hipStream_t s) {
   int64_t blocks = cdiv(g->n, kBlock * 4);
   if (blocks < cdiv(4 * kCtrSlot, kBlock)) blocks = cdiv(4 * kCtrSlot, kBlock);
-  const unsigned grid = (unsigned)(blocks > 65536 ? 65536 : blocks);
+  const unsigned grid = (unsigned)(blocks > kMaxGrid ? kMaxGrid : blocks);
   hipLaunchKernelGGL(k_init, dim3(grid), dim3(kBlock), 0, s, b, (const u64*)g->iso, source, k0, flags0);
   GSW_HIP(hipGetLastError());
   return GSW_OK;
