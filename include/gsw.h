@@ -106,9 +106,10 @@ typedef struct {
   int64_t n_frontier;   /* n_f(d): vertices at depth d */
   int64_t discovered;   /* vertices at depths 0..d */
   int64_t n_next;       /* vertices found at depth d+1 (0 on the last row) */
-  float ms;             /* time of this level's expansion kernel(s) (device wall
-                           clock, see time_levels; a frontier-bitmap rebuild
-                           before a pull is not included), or -1 when not timed */
+  float ms;             /* time of this level (device wall clock from its first
+                           workgroup's start to its last one's end, both
+                           launches of a two-launch push_edge level; see
+                           time_levels), or -1 when not timed */
   int32_t reserved;
 } gsw_level_trace;
 
@@ -120,11 +121,11 @@ typedef struct {
   const int32_t *schedule;   /* GSW_POLICY_SCHEDULE: kernel per level (host array); */
   int32_t schedule_len;      /*   levels beyond the end repeat the last entry */
   const gsw_tree *tree;      /* GSW_POLICY_TREE */
-  int32_t time_levels;       /* 1: fill gsw_level_trace.ms with each level's kernel time:
-                                every workgroup of the level's expansion kernel stamps
-                                the GPU's constant-rate wall clock at entry and exit, the
-                                level lasts from the first entry to the last exit (first
-                                8192 levels; read once the BFS has finished) */
+  int32_t time_levels;       /* 1: fill gsw_level_trace.ms with each level's time: the
+                                level's first workgroup stamps the GPU's constant-rate
+                                wall clock when it starts, its last workgroup reads the
+                                clock when it ends and posts the difference in the
+                                level's record */
   int32_t canonical_parents; /* 1: parent[v] = smallest neighbour one level up */
   int32_t device_ptrs;       /* 1: levels/parents are device pointers; 0: host */
   int32_t reserved0;
