@@ -68,11 +68,16 @@ gsw_status check_kernel(const gsw_graph* g, int k) {
 }
 
 // Device copy of the tree, uploaded once per (workspace, tree) and
-// specialised to the graph: a split on one of the graph's own features
-// (constant for the graph) is decided here, with the same float rounding
-// as every other comparison, so the copy holds only the nodes reachable
-// through splits on the level features.  The walk's outcome is unchanged.
-// Nodes are renumbered in preorder, so children still follow their parent.
+// specialised to the graph.  A split on one of the graph's own features
+// (constant for the graph) is decided here, with the host's float rounding,
+// so the copy holds only the nodes reachable through splits on the four
+// level features.  Each of those is a non-decreasing function of an integer
+// count c in [0, n] -- the next frontier size (features 8, 9 = c, c/n) or
+// the vertices discovered through the next depth (10, 11) -- so its test,
+// float(feature) <= threshold, holds exactly for c <= T; T is found here by
+// bisection with the host's own arithmetic and the device compares counts.
+// The outcome of every walk is unchanged.  Nodes are renumbered in preorder,
+// so children still follow their parent.
 gsw_status ensure_tree(gsw_graph* g, const gsw_tree* t) {
   Workspace& w = g->ws;
   if (w.tree_id == t->id) return GSW_OK;
@@ -85,6 +90,23 @@ gsw_status ensure_tree(gsw_graph* g, const gsw_tree* t) {
       i = xv <= t->threshold[(size_t)i] ? t->left[(size_t)i] : t->right[(size_t)i];
     }
     return i;
+  };
+  // largest count c in [-1, n] whose feature value passes node i's test
+  auto count_threshold = [&](int32_t i) -> int32_t {
+    const int f = t->feature[(size_t)i];
+    const double thr = t->threshold[(size_t)i];
+    auto holds = [&](int64_t c) {
+      double x[GSW_N_FEATURES];
+      (void)gsw_level_features(g, c, c, x);
+      return (double)(float)x[f] <= thr;
+    };
+    int64_t lo = -1, hi = g->n;  // holds(lo) (or lo = -1), !holds(hi + 1)
+    if (holds(hi)) return (int32_t)hi;
+    while (hi - lo > 1) {  // holds(lo) or lo == -1, !holds(hi)
+      const int64_t mid = lo + (hi - lo) / 2;
+      if (holds(mid)) lo = mid; else hi = mid;
+    }
+    return (int32_t)lo;
   };
   std::vector<int32_t> order;  // kept nodes (old ids) in preorder
   std::vector<int32_t> newid((size_t)t->n_nodes, -1);
@@ -107,24 +129,25 @@ gsw_status ensure_tree(gsw_graph* g, const gsw_tree* t) {
     w.d_thr = nullptr;
     w.tree_cap = 0;
     if (hipMalloc((void**)&w.d_tree, (size_t)m * sizeof(unsigned long long)) != hipSuccess ||
-        hipMalloc((void**)&w.d_thr, (size_t)m * sizeof(double)) != hipSuccess) {
+        hipMalloc((void**)&w.d_thr, (size_t)m * sizeof(int32_t)) != hipSuccess) {
       (void)hipGetLastError();
       return fail(GSW_ENOMEM, "hipMalloc for the device copy of the tree failed");
     }
     w.tree_cap = m;
   }
   std::vector<unsigned long long> nodes((size_t)m);
-  std::vector<double> thr((size_t)m);
+  std::vector<int32_t> thr((size_t)m, 0);
   for (int32_t k = 0; k < m; ++k) {
     const int32_t i = order[(size_t)k];
     const bool leaf = t->left[(size_t)i] == -1;
     const int32_t l = leaf ? -1 : newid[(size_t)resolve(t->left[(size_t)i])];
     const int32_t r = leaf ? -1 : newid[(size_t)resolve(t->right[(size_t)i])];
-    nodes[(size_t)k] = tree_node_pack(l, r, leaf ? 0 : t->feature[(size_t)i], t->leaf_kernel[(size_t)i]);
-    thr[(size_t)k] = t->threshold[(size_t)i];
+    const int32_t count = !leaf && t->feature[(size_t)i] >= 10 ? 1 : 0;  // discovered : frontier
+    nodes[(size_t)k] = tree_node_pack(l, r, count, t->leaf_kernel[(size_t)i]);
+    if (!leaf) thr[(size_t)k] = count_threshold(i);
   }
   GSW_HIP(hipMemcpy(w.d_tree, nodes.data(), nodes.size() * sizeof(unsigned long long), hipMemcpyHostToDevice));
-  GSW_HIP(hipMemcpy(w.d_thr, thr.data(), thr.size() * sizeof(double), hipMemcpyHostToDevice));
+  GSW_HIP(hipMemcpy(w.d_thr, thr.data(), thr.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   w.tree_nodes = m;
   w.tree_id = t->id;
   return GSW_OK;
@@ -163,9 +186,6 @@ BfsPolicy device_policy(const gsw_graph* g, const gsw_bfs_opts* o, bool has_orig
   p.t_node = g->ws.d_tree;
   p.t_thr = g->ws.d_thr;
   p.t_nodes = o->policy == GSW_POLICY_TREE && o->tree ? g->ws.tree_nodes : 0;
-  p.feat[0] = (double)g->n;
-  p.feat[1] = (double)g->nnz;
-  for (int i = 0; i < 6; ++i) p.feat[2 + i] = g->deg_stats[i];
   return p;
 }
 

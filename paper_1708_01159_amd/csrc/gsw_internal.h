@@ -63,7 +63,7 @@ struct Workspace {
   unsigned long long* ring = nullptr;    // mapped host memory: per-level records
   unsigned long long* d_ring = nullptr;  // the same memory as seen by the device
   unsigned long long* d_tree = nullptr;  // device copy of the tree's nodes (packed) ...
-  double* d_thr = nullptr;               // ... and thresholds
+  int32_t* d_thr = nullptr;              // ... and integer thresholds
   int32_t tree_cap = 0;                  // nodes the device copy has room for
   int32_t tree_nodes = 0;                // nodes of the device copy (specialised to this graph)
   uint64_t tree_id = 0;                  // tree currently uploaded (0: none)
@@ -151,10 +151,9 @@ struct BfsPolicy {
   int32_t pad;
   const int32_t* sched;      // device copy of the schedule
   const unsigned long long* t_node;  // tree nodes, packed (see tree_node_pack)
-  const double* t_thr;       // tree thresholds
+  const int32_t* t_thr;      // per node: the split holds when its count is <= t_thr
   int32_t t_nodes;           // nodes of the tree
   int32_t pad2;
-  double feat[8];            // n, arcs, degree min, Q1, median, Q3, max, std
 };
 
 // Buffers of one single-source BFS (a kernel argument of the level kernels).
@@ -180,11 +179,12 @@ struct BfsBase {
 };
 
 // A tree node in 8 bytes for the device walk: left and right child (int16,
-// -1 at a leaf), feature index, leaf kernel + 1 (0 when the leaf's classes
-// tie).  Trees of up to 32767 nodes.
-inline unsigned long long tree_node_pack(int32_t left, int32_t right, int32_t feature, int32_t leaf_kernel) {
+// -1 at a leaf), the count the split tests (0: next frontier size,
+// 1: vertices discovered through the next depth), leaf kernel + 1 (0 when
+// the leaf's classes tie).  Trees of up to 32767 nodes.
+inline unsigned long long tree_node_pack(int32_t left, int32_t right, int32_t count, int32_t leaf_kernel) {
   return (unsigned long long)(uint16_t)(int16_t)left | ((unsigned long long)(uint16_t)(int16_t)right << 16) |
-         ((unsigned long long)(uint8_t)feature << 32) | ((unsigned long long)(uint8_t)(leaf_kernel + 1) << 40);
+         ((unsigned long long)(uint8_t)count << 32) | ((unsigned long long)(uint8_t)(leaf_kernel + 1) << 40);
 }
 constexpr int32_t kMaxTreeNodes = 32767;
 

@@ -52,6 +52,7 @@ constexpr int kEdgeChunk = 1024;                 // push_edge: arcs per chunk (4
 constexpr int kEdgeWin = 512;                    // push_edge: queue entries a chunk stages in LDS
 constexpr int kPullEager = 8;                    // pull: neighbours probed per lane up front
 constexpr int kPullChunk = 8;                    // pull: visited words (512 vertices) per wave step
+constexpr int kTreeLaneNodes = 4;                // level end: tree nodes per lane of one wave (256)
 
 typedef unsigned long long u64;
 
@@ -295,26 +296,18 @@ __device__ __forceinline__ void visit_row(Stage& s, const Args& a, int64_t e0, i
 }
 
 // ------------------------------------------------- next-kernel choice
-// Child of tree node nd (packed as tree_node_pack) for the feature vector of
-// a level with nf frontier vertices and disc discovered ones (Section IV-A
-// list, in the order of gsw_level_features: feat holds the graph's eight,
-// then frontier, its fraction of n, discovered, its fraction of n), or, for
-// a leaf, -(leaf kernel + 2) (-1: undecided leaf).  The feature is rounded
-// to float and compared with the double threshold, as the host does.
-__device__ __forceinline__ int32_t tree_step(u64 nd, double thr, const double* feat, double nf, double disc) {
+// Child of tree node nd (packed as tree_node_pack) for a level whose next
+// frontier has nf vertices and which has discovered disc vertices through
+// the next depth, or, for a leaf, -(leaf kernel + 2) (-1: undecided leaf).
+// The device copy of the tree is specialised to the graph on upload: its
+// splits compare one of those two counts with an integer threshold that
+// decides exactly as the host's float comparison of the feature does.
+__device__ __forceinline__ int32_t tree_step(u64 nd, int32_t thr, int32_t nf, int32_t disc) {
   const int left = (int)(int16_t)(uint16_t)(nd & 0xffffull);
   if (left == -1) return -((int32_t)((nd >> 40) & 0xffull) - 1) - 2;
   const int right = (int)(int16_t)(uint16_t)((nd >> 16) & 0xffffull);
-  const int f = (int)((nd >> 32) & 0xffull);
-  double x;
-  switch (f) {
-    case 8: x = nf; break;
-    case 9: x = nf / feat[0]; break;
-    case 10: x = disc; break;
-    case 11: x = disc / feat[0]; break;
-    default: x = feat[f < 8 ? f : 0]; break;
-  }
-  return (double)(float)x <= thr ? left : right;
+  const int32_t c = ((nd >> 32) & 1ull) ? disc : nf;
+  return c <= thr ? left : right;
 }
 
 // Kernel for a tree leaf (-1: undecided, repeat prev, the previous level's
@@ -348,7 +341,7 @@ __device__ __forceinline__ int choose_next(const BfsPolicy& p, int32_t d, long l
   } else {
     int32_t x = 0;
     do {
-      x = tree_step(p.t_node[x], p.t_thr[x], p.feat, (double)nf, (double)disc);
+      x = tree_step(p.t_node[x], p.t_thr[x], (int32_t)nf, (int32_t)disc);
     } while (x >= 0);
     k = x == -1 ? -1 : -x - 2;
   }
@@ -391,31 +384,37 @@ __device__ __forceinline__ bool launch_last(const Args& a) {
 // queue-segment atomics have returned before it counts itself finished, so
 // the last one sees every segment's final size.  The device copy of a tree
 // is specialised to the graph (only splits on the level features remain):
-// when it has at most 64 nodes, wave 0 of every workgroup loads one node
-// per lane before the count, and the last one evaluates every node's split
-// at once and follows the children with lane shuffles.  A larger tree is
+// when it has at most 64 * kTreeLaneNodes nodes, wave 0 of every workgroup
+// loads them (node i on lane i % 64) before the count, and the last one
+// evaluates every node's split at once and follows the children with lane
+// shuffles.  A larger tree is
 // evaluated the same way by the whole last workgroup into a child table in
 // `lds` (lds_bytes of LDS free by now, the flushed append stage; 4 bytes per
 // node); one beyond that is walked from global memory.
 __device__ __forceinline__ void level_end(const Args& a, const BfsBase* base, const BfsPolicy& p, u64* ring,
                                           int k_run, void* lds, int lds_bytes) {
   __shared__ uint32_t s_nn;
-  __shared__ double s_feat[8];
   const int tid = threadIdx.x;
   const bool tree = p.policy == GSW_POLICY_TREE;
-  const bool tree_wave = tree && p.t_nodes <= 64;
+  const bool tree_wave = tree && p.t_nodes <= 64 * kTreeLaneNodes;
   const bool tree_par = tree && !tree_wave && (long long)p.t_nodes * 4 <= (long long)lds_bytes;
-  u64 wnd = 0ull;
-  double wth = 0.0;
-  if (tree_wave && tid < p.t_nodes) {
-    wnd = p.t_node[tid];
-    wth = p.t_thr[tid];
+  u64 wnd[kTreeLaneNodes];
+  int32_t wth[kTreeLaneNodes];
+#pragma unroll
+  for (int q = 0; q < kTreeLaneNodes; ++q) {
+    const int i = tid + 64 * q;  // node i on lane i % 64, slot i / 64
+    wnd[q] = 0ull;
+    wth[q] = 0;
+    if (tree_wave && tid < 64 && i < p.t_nodes) {
+      wnd[q] = p.t_node[i];
+      wth[q] = p.t_thr[i];
+    }
   }
   if (!launch_last(a)) return;
   BfsCtl* c = a.ctl;
   int32_t* l_next = reinterpret_cast<int32_t*>(lds);
   u64 nd0 = 0ull, nd1 = 0ull;
-  double th0 = 0.0, th1 = 0.0;
+  int32_t th0 = 0, th1 = 0;
   if (tree_par) {
     if (tid < p.t_nodes) {
       nd0 = p.t_node[tid];
@@ -425,7 +424,6 @@ __device__ __forceinline__ void level_end(const Args& a, const BfsBase* base, co
       nd1 = p.t_node[tid + kBlock];
       th1 = p.t_thr[tid + kBlock];
     }
-    if (tid < 8) s_feat[tid] = p.feat[tid];
   } else if (tid >= 64) {
     return;  // wave 0 finishes the level
   }
@@ -445,10 +443,10 @@ __device__ __forceinline__ void level_end(const Args& a, const BfsBase* base, co
     nn = s_nn;
     const long long nd = disc0 + (long long)nn;
     if (nn > 0) {
-      if (tid < p.t_nodes) l_next[tid] = tree_step(nd0, th0, s_feat, (double)nn, (double)nd);
-      if (tid + kBlock < p.t_nodes) l_next[tid + kBlock] = tree_step(nd1, th1, s_feat, (double)nn, (double)nd);
-      for (int i = tid + 2 * kBlock; i < p.t_nodes; i += kBlock)
-        l_next[i] = tree_step(p.t_node[i], p.t_thr[i], s_feat, (double)nn, (double)nd);
+      const int32_t cf = (int32_t)nn, cd = (int32_t)nd;
+      if (tid < p.t_nodes) l_next[tid] = tree_step(nd0, th0, cf, cd);
+      if (tid + kBlock < p.t_nodes) l_next[tid + kBlock] = tree_step(nd1, th1, cf, cd);
+      for (int i = tid + 2 * kBlock; i < p.t_nodes; i += kBlock) l_next[i] = tree_step(p.t_node[i], p.t_thr[i], cf, cd);
     }
     __syncthreads();
     if (tid >= 64) return;
@@ -458,9 +456,21 @@ __device__ __forceinline__ void level_end(const Args& a, const BfsBase* base, co
   int32_t next = kCtlDone;
   if (nn > 0) {
     if (tree_wave) {
-      const int32_t ch = tid < p.t_nodes ? tree_step(wnd, wth, p.feat, (double)nn, (double)ndisc) : 0;
-      int32_t x = __shfl(ch, 0);
-      while (x >= 0) x = __shfl(ch, x);
+      const int slots = (p.t_nodes + 63) >> 6;
+      int32_t ch[kTreeLaneNodes];
+#pragma unroll
+      for (int q = 0; q < kTreeLaneNodes; ++q)
+        ch[q] = q < slots ? tree_step(wnd[q], wth[q], (int32_t)nn, (int32_t)ndisc) : 0;
+      // follow the children from the root: the node index is uniform, so each
+      // step is a register read across lanes
+      int32_t x = __builtin_amdgcn_readlane(ch[0], 0);
+      while (x >= 0) {
+        const int slot = x >> 6;
+        int32_t c = ch[0];
+#pragma unroll
+        for (int q = 1; q < kTreeLaneNodes; ++q) c = slot == q ? ch[q] : c;
+        x = __builtin_amdgcn_readlane(c, x & 63);
+      }
       next = choose_leaf(p, x == -1 ? -1 : -x - 2, k_run, &nflags);
     } else if (tree_par) {
       int32_t x = l_next[0];

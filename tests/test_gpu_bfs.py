@@ -168,13 +168,14 @@ def _big_tree(depth=9, seed=17):
     return dict(left=left, right=right, feature=feature, threshold=thr, value=value, class_kernel=kernels)
 
 
-@pytest.mark.parametrize("which", ["shipped", "big", "huge"])
+@pytest.mark.parametrize("which", ["shipped", "mid", "big", "huge"])
 @pytest.mark.parametrize("name", ["rmat14", "grid", "chunglu"])
 def test_device_tree_walk_matches_oracle(name, which):
     # the device copy of the tree is specialised to the graph and evaluated
-    # by one wave (up to 64 nodes), by the last workgroup into an LDS table
-    # (up to 2048) or walked in global memory (the 4095-node tree); every
-    # level's choice equals the oracle's walk of the whole tree
+    # by one wave (up to 256 nodes, four per lane: the 255-node tree), by the
+    # last workgroup into an LDS table (up to 2048: the 1023-node tree) or
+    # walked in global memory (the 4095-node tree); every level's choice
+    # equals the oracle's walk of the whole tree
     import json
 
     g, G, srcs, refs, comp = case(name)
@@ -184,9 +185,9 @@ def test_device_tree_walk_matches_oracle(name, which):
         T = json.load(open(trees.default_path()))
         tree = trees.load_default()
     else:
-        T = _big_tree(depth=9 if which == "big" else 11)
+        T = _big_tree(depth={"mid": 7, "big": 9, "huge": 11}[which])
         tree = gsw.Tree(T)
-    assert len(T["left"]) > {"shipped": 100, "big": 512, "huge": 2048}[which]
+    assert len(T["left"]) > {"shipped": 100, "mid": 192, "big": 512, "huge": 2048}[which]
     lv, pa, trace = gsw.bfs(G, srcs, policy="tree", tree=tree)
     _check_result(g, srcs, refs, comp, lv, pa, trace)
     gf = ofeat.graph_features(g.offs)
