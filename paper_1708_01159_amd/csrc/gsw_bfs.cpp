@@ -23,6 +23,20 @@ namespace {
 // launches).  Launches queued past the end of the search do nothing.
 constexpr int kAhead = 3;
 
+// Launch size for queued levels: the full grid, or kSmallLaunch workgroups
+// while the search is in a quiet phase -- the latest frontier the host knows
+// of is at most kSmallFrontier and goes to a queue-driven push kernel (the
+// all-vertex kernels want the full grid at any frontier size), neither of
+// the last two frontiers grew more than twofold, and at least 1% of the
+// vertices are discovered -- such as a
+// tail or the slowly moving front of a high-diameter graph, whose levels
+// need a few workgroups (dispatching the rest of a full launch costs ~1.5 us
+// per level).  A scale-free frontier can grow a thousandfold in one level
+// early on, which the conditions exclude.  Any size is correct: a level that
+// asks for more workgroups than its launch has strides over its work.
+constexpr int32_t kSmallLaunch = 64;
+constexpr int64_t kSmallFrontier = 4096;
+
 struct Policy {
   const gsw_bfs_opts* o;
   bool symmetric;
@@ -275,9 +289,11 @@ gsw_status run_levels(gsw_graph* g, const Policy& pol, const BfsPolicy& dp, int3
   int32_t j = 0;     // launches of the level kernel so far
   int ahead = 0;     // of those, not yet used by a level whose record was read
   int want = kAhead + level_launches(k0, 1) - 1;
+  int32_t size = b.grid_max;
+  int64_t nf_prev = 0;  // frontier of the level before the latest record's
   for (int64_t d = 0;; ++d) {
     while (ahead < want) {
-      GSW_TRY(launch_level_auto(g, b, dp, j++, s));
+      GSW_TRY(launch_level_auto(g, b, dp, j++, size, s));
       ++ahead;
     }
     Record r;
@@ -301,6 +317,11 @@ gsw_status run_levels(gsw_graph* g, const Policy& pol, const BfsPolicy& dp, int3
     ahead -= level_launches(k, r.nf);
     if (nn == 0) break;
     want = kAhead + level_launches(nk, nn) - 1;
+    const bool queue_push = nk != GSW_K_PULL_BITMAP && nk != GSW_K_VERTEX_SCAN && nk != GSW_K_EDGE_SCAN;
+    const bool quiet = queue_push && nn <= kSmallFrontier && nn <= 2 * r.nf && d > 0 && r.nf <= 2 * nf_prev &&
+                       (r.disc + nn) * 100 >= g->n;
+    size = quiet ? kSmallLaunch : b.grid_max;
+    nf_prev = r.nf;
   }
   if (o->canonical_parents && pa) GSW_TRY(launch_canonical_parents(g, lv, pa, s));
   return GSW_OK;
@@ -503,8 +524,8 @@ gsw_status gsw_bfs_profile(const gsw_graph* cg, int32_t source, const int32_t* k
     // level kernel, two for push_edge on more than kEdgeFuse entries
     auto run = [&](int k, bool timed_bracket) -> gsw_status {
       if (timed_bracket) GSW_HIP(hipEventRecord(w.ev[0], s));
-      GSW_TRY(launch_level_auto(g, b, dp, 0, s));
-      if (level_launches(k, nf) == 2) GSW_TRY(launch_level_auto(g, b, dp, 1, s));
+      GSW_TRY(launch_level_auto(g, b, dp, 0, b.grid_max, s));
+      if (level_launches(k, nf) == 2) GSW_TRY(launch_level_auto(g, b, dp, 1, b.grid_max, s));
       if (timed_bracket) GSW_HIP(hipEventRecord(w.ev[1], s));
       return GSW_OK;
     };

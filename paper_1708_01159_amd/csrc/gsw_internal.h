@@ -216,9 +216,11 @@ gsw_status launch_init(const gsw_graph* g, const BfsBase& b, int32_t source, int
                        hipStream_t s);
 // Launch j (counted from 0 after launch_init) of the level kernel: runs what
 // control slot j % 2 names -- a level, or the scan or the expansion of a
-// push_edge level -- or nothing once the search has ended.
+// push_edge level -- or nothing once the search has ended.  `workgroups`
+// (clamped to [1, b.grid_max]) is the launch size; a level that asks for
+// more workgroups than the launch has runs on the launch's, striding.
 gsw_status launch_level_auto(const gsw_graph* g, const BfsBase& b, const BfsPolicy& p, int32_t j,
-                             hipStream_t s);
+                             int32_t workgroups, hipStream_t s);
 // Workgroups of a level-kernel launch on a graph of n vertices (nw bitmap words).
 int32_t level_kernel_grid(int64_t n, int64_t nw);
 // Workgroups of that launch that run a level of `kernel` with n_in frontier entries.

@@ -1210,7 +1210,9 @@ __global__ void __launch_bounds__(kBlock) k_level_auto(BfsBase b, BfsPolicy p, i
     return;
   }
   const int32_t d = c->d;
-  const int32_t grid = c->grid;
+  // the launch may be smaller than the level asks for: its workgroups then
+  // stride over the work
+  const int32_t grid = c->grid < (int32_t)gridDim.x ? c->grid : (int32_t)gridDim.x;
   const int32_t phase = k == GSW_K_PUSH_EDGE ? c->phase : 0;
   if (phase != 1 && d > 0) clear_bitmap(b.bm[(d + 2) % 3], b.nw);  // k_init zeroed it for level 0
   if ((int32_t)blockIdx.x >= grid) return;  // not needed for this launch (grid <= the launch)
@@ -1325,9 +1327,10 @@ gsw_status launch_init(const gsw_graph* g, const BfsBase& b, int32_t source, int
 }
 
 gsw_status launch_level_auto(const gsw_graph* g, const BfsBase& b, const BfsPolicy& p, int32_t j,
-                             hipStream_t s) {
+                             int32_t workgroups, hipStream_t s) {
   (void)g;
-  hipLaunchKernelGGL(k_level_auto, dim3((unsigned)b.grid_max), dim3(kBlock), 0, s, b, p, j);
+  const int32_t wg = workgroups < 1 ? 1 : (workgroups < b.grid_max ? workgroups : b.grid_max);
+  hipLaunchKernelGGL(k_level_auto, dim3((unsigned)wg), dim3(kBlock), 0, s, b, p, j);
   GSW_HIP(hipGetLastError());
   return GSW_OK;
 }
