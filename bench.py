@@ -401,7 +401,7 @@ def _logged(runner, tag, calls):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat22")
     ap.add_argument("--sources", type=int, default=None, help="override the source count")
