@@ -128,7 +128,9 @@ typedef struct {
                                 level's record */
   int32_t canonical_parents; /* 1: parent[v] = smallest neighbour one level up */
   int32_t device_ptrs;       /* 1: levels/parents are device pointers; 0: host */
-  int32_t reserved0;
+  int32_t max_workgroups;    /* > 0: cap on every level-kernel launch's workgroups (levels
+                                that ask for more stride over their work; results are
+                                the same); 0: the library sizes each launch */
   void *stream;              /* hipStream_t for the work; NULL = library stream */
 } gsw_bfs_opts;
 

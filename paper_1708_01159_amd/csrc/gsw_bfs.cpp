@@ -289,7 +289,8 @@ gsw_status run_levels(gsw_graph* g, const Policy& pol, const BfsPolicy& dp, int3
   int32_t j = 0;     // launches of the level kernel so far
   int ahead = 0;     // of those, not yet used by a level whose record was read
   int want = kAhead + level_launches(k0, 1) - 1;
-  int32_t size = b.grid_max;
+  const int32_t cap = o->max_workgroups > 0 && o->max_workgroups < b.grid_max ? o->max_workgroups : b.grid_max;
+  int32_t size = cap;
   int64_t nf_prev = 0;  // frontier of the level before the latest record's
   for (int64_t d = 0;; ++d) {
     while (ahead < want) {
@@ -320,7 +321,7 @@ gsw_status run_levels(gsw_graph* g, const Policy& pol, const BfsPolicy& dp, int3
     const bool queue_push = nk != GSW_K_PULL_BITMAP && nk != GSW_K_VERTEX_SCAN && nk != GSW_K_EDGE_SCAN;
     const bool quiet = queue_push && nn <= kSmallFrontier && nn <= 2 * r.nf && d > 0 && r.nf <= 2 * nf_prev &&
                        (r.disc + nn) * 100 >= g->n;
-    size = quiet ? kSmallLaunch : b.grid_max;
+    size = quiet && kSmallLaunch < cap ? kSmallLaunch : cap;
     nf_prev = r.nf;
   }
   if (o->canonical_parents && pa) GSW_TRY(launch_canonical_parents(g, lv, pa, s));

@@ -55,7 +55,7 @@ class BfsOpts(ctypes.Structure):
                 ("schedule", ctypes.c_void_p), ("schedule_len", ctypes.c_int32),
                 ("tree", ctypes.c_void_p), ("time_levels", ctypes.c_int32),
                 ("canonical_parents", ctypes.c_int32), ("device_ptrs", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("max_workgroups", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class MsbfsOpts(ctypes.Structure):
@@ -317,13 +317,15 @@ def _opts(policy, kernel, schedule, tree, time_levels, canonical_parents, device
 def bfs(graph: Graph, sources, policy: str = "tree", kernel: int = PUSH_VERTEX, schedule=None,
         tree: Tree = None, parents: bool = True, time_levels: bool = False,
         canonical_parents: bool = False, device: bool = False, stream=None, out=None,
-        trace_cap: int = None):
+        trace_cap: int = None, max_workgroups: int = 0):
     """Level-switched BFS from each source.
 
     Returns ``(levels, parents, trace)``: ``levels`` is ``[len(sources), n]``
     int32 (numpy on the host, or a torch CUDA tensor when ``device``),
     ``parents`` likewise or None, ``trace`` a list of TraceRow.
     ``out`` may supply preallocated ``(levels, parents)`` device tensors.
+    ``max_workgroups`` > 0 caps every level launch (for tests of the
+    striding paths; 0 lets the library size launches).
     """
     src = np.ascontiguousarray(np.atleast_1d(np.asarray(sources)), dtype=np.int32)
     S, n = src.shape[0], graph.n
@@ -341,6 +343,7 @@ def bfs(graph: Graph, sources, policy: str = "tree", kernel: int = PUSH_VERTEX, 
         lv = np.empty((S, n), dtype=np.int32)
         pa = np.empty((S, n), dtype=np.int32) if parents else None
     o, keep = _opts(policy, kernel, schedule, tree, time_levels, canonical_parents, device, stream)
+    o.max_workgroups = int(max_workgroups)
     cap = trace_cap if trace_cap is not None else 64 * max(S, 1)
     while True:
         tr = (LevelTrace * max(cap, 1))()

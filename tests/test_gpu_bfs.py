@@ -345,3 +345,20 @@ def test_push_edge_empty_and_long_rows(width):
             if sym:
                 checks.check_bfs(d.offs, d.cols, s, lv[0], pa[0], checks.components(d.n, d.offs, d.cols))
         G.close()
+
+
+@pytest.mark.parametrize("cap", [1, 3])
+@pytest.mark.parametrize("name", ["rmat14", "star", "er_ragged"])
+def test_launches_smaller_than_levels(name, cap):
+    # every level launch capped at 1 or 3 workgroups: each kernel's levels
+    # then ask for more workgroups than they get and stride over their work
+    # (pull over all words, push_edge's prefix blocks and arc slices, the
+    # queue-driven kernels' rounds); results are unchanged
+    g, G, srcs, refs, comp = case(name)
+    for k in ALL_KERNELS:
+        lv, pa, trace = gsw.bfs(G, srcs[:2], policy="fixed", kernel=k, max_workgroups=cap)
+        _check_result(g, srcs[:2], refs[:2], comp, lv, pa, trace)
+    from paper_1708_01159_amd import trees
+
+    lv, pa, trace = gsw.bfs(G, srcs[:2], policy="tree", tree=trees.load_default(), max_workgroups=cap)
+    _check_result(g, srcs[:2], refs[:2], comp, lv, pa, trace)
