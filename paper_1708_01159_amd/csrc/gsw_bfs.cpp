@@ -515,7 +515,7 @@ gsw_status gsw_bfs_profile(const gsw_graph* cg, int32_t source, const int32_t* k
       *w.h_ctl = saved_ctl;
       w.h_ctl->kernel = k;
       w.h_ctl->grid = level_participants(k, nf, b);
-      w.h_ctl->done_blocks = 0u;
+      w.h_ctl->done = 0ull;
       w.h_ctl->phase = level_first_phase(k, nf);
       GSW_HIP(hipMemcpyAsync(w.ctl, w.h_ctl, sizeof(BfsCtl), hipMemcpyHostToDevice, s));
       GSW_HIP(hipStreamSynchronize(s));  // the staging copy is reused by the next restore

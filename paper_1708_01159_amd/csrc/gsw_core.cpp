@@ -152,7 +152,7 @@ gsw_status ensure_workspace(gsw_graph* g) {
       {(void**)&w.bm[1], bmb},
       {(void**)&w.bm[2], bmb},
       {(void**)&w.ctl, 2 * sizeof(BfsCtl)},
-      {(void**)&w.done, (size_t)kDoneGroups * kCtrStride * sizeof(uint32_t)},
+      {(void**)&w.done, (size_t)kDoneGroups * kCtrStride * sizeof(unsigned long long)},
       {(void**)&w.q[0], (size_t)kQueueBins * n * sizeof(int32_t)},
       {(void**)&w.q[1], (size_t)kQueueBins * n * sizeof(int32_t)},
       {(void**)&w.ctr, 4 * kCtrSlot * sizeof(uint32_t)},

@@ -58,7 +58,7 @@ struct Workspace {
   int32_t* par_tmp = nullptr;            // parents when the caller passes host memory
   uint32_t* h_ctr = nullptr;             // pinned host copy of one counter slot
   BfsCtl* ctl = nullptr;                 // device level control
-  uint32_t* done = nullptr;              // finished-workgroup counters of the running level
+  unsigned long long* done = nullptr;    // finished-workgroup counters of the running launch
   BfsCtl* h_ctl = nullptr;               // pinned staging for control-block uploads (profiling)
   unsigned long long* ring = nullptr;    // mapped host memory: per-level records
   unsigned long long* d_ring = nullptr;  // the same memory as seen by the device
@@ -119,17 +119,18 @@ struct BfsCtl {
   int32_t flags;    // trace flags of that choice (bit0 undecided leaf, bit1 pull replaced)
   long long nf;     // frontier size of level d
   long long disc;   // vertices discovered through depth d
-  unsigned int done_blocks;  // groups of workgroups of the running launch that have finished
+  unsigned long long done;   // running launch: finished groups << 40 | queue entries they appended
   int32_t phase;             // push_edge: 0 = prefix launch, 1 = expansion launch, 2 = both in one
+  int32_t grid;              // workgroups that run this launch of level d (the rest exit)
   unsigned long long t_begin;  // wall clock at the start of the running level (timed levels)
-  int32_t grid;                // workgroups that run this launch of level d (the rest exit)
-  int32_t pad2;
-  long long etot;              // push_edge: arcs of the frontier (set by the scan launch)
+  long long etot;              // push_edge: arcs of the frontier (set by the prefix launch)
 };
-// Workgroups count themselves finished in kDoneGroups counters (by index
-// modulo kDoneGroups, kCtrStride words apart); the last of each group then
-// counts its group in BfsCtl::done_blocks.  Same-address atomics serialise,
-// so a full launch on one counter would cost about 15 us per level.
+// Workgroups count themselves finished, together with the queue entries they
+// appended, in kDoneGroups 64-bit counters (by index modulo kDoneGroups,
+// kCtrStride words apart); the last of each group then adds its group's sums
+// to BfsCtl::done, so the launch's last workgroup learns the next frontier's
+// size from its own atomic.  Same-address atomics serialise, so a full
+// launch on one counter would cost about 15 us per level.
 constexpr int kDoneGroups = 16;
 constexpr int32_t kCtlDone = -1;
 
@@ -167,7 +168,7 @@ struct BfsBase {
   unsigned long long* bm[3];
   int32_t* q[2];
   uint32_t* ctr;
-  uint32_t* done;                  // kDoneGroups workgroup counters, kCtrStride words apart
+  unsigned long long* done;        // kDoneGroups workgroup counters, kCtrStride words apart
   int64_t* scan;                   // push_edge: block-local exclusive arc offsets per queue entry
   int64_t* ebeg;                   // push_edge: row start per queue entry
   int64_t* bsum;                   // push_edge: arcs per scan block, then their exclusive prefix

@@ -74,7 +74,7 @@ struct Args {
   uint32_t* cclr;
   BfsCtl* ctl;       // this launch's control slot
   BfsCtl* ctl_next;  // the next launch's
-  uint32_t* done;
+  u64* done;
   int64_t n, nw, nnz;
   uint32_t n_in;
   int32_t d;
@@ -349,30 +349,47 @@ __device__ __forceinline__ int choose_next(const BfsPolicy& p, int32_t d, long l
 }
 
 // True (in every thread) in the last workgroup of the launch to get here;
-// called by every thread of every participating workgroup.  The last one
-// resets the counters (before the launch ends, for the next one).
-__device__ __forceinline__ bool launch_last(const Args& a) {
+// called by every thread of every participating workgroup with the number of
+// queue entries its workgroup appended.  *total (every thread) receives the
+// launch's sum of those in the last workgroup.  The last one resets the
+// counters (before the launch ends, for the next one).
+constexpr u64 kDoneOne = 1ull << 40;  // one finished workgroup (or group)
+constexpr u64 kDoneMask = kDoneOne - 1ull;
+
+__device__ __forceinline__ bool launch_last(const Args& a, uint32_t appended, u64* total) {
+  __shared__ u64 s_total;
   __shared__ uint32_t s_last;
   __syncthreads();
   if (threadIdx.x == 0) {
     const uint32_t grid = (uint32_t)a.grid;
+    const u64 mine = kDoneOne | (u64)appended;
     uint32_t last = 1u;  // a launch of one workgroup needs no count
+    u64 sum = (u64)appended;
     if (grid > (unsigned)kDoneGroups) {
       const uint32_t gidx = blockIdx.x % (unsigned)kDoneGroups;
       const uint32_t in_group = grid / kDoneGroups + (gidx < grid % kDoneGroups ? 1u : 0u);
       last = 0u;
-      if (atomicAdd(a.done + gidx * kCtrStride, 1u) == in_group - 1u)
-        last = atomicAdd(&a.ctl->done_blocks, 1u) == (unsigned)kDoneGroups - 1u ? 1u : 0u;
+      const u64 g_old = atomicAdd(a.done + gidx * kCtrStride, mine);
+      if ((g_old >> 40) == in_group - 1u) {
+        const u64 group = (g_old + mine) & kDoneMask;
+        const u64 old = atomicAdd(&a.ctl->done, kDoneOne | group);
+        last = (old >> 40) == (unsigned)kDoneGroups - 1u ? 1u : 0u;
+        sum = (old & kDoneMask) + group;
+      }
     } else if (grid > 1u) {
-      last = atomicAdd(&a.ctl->done_blocks, 1u) == grid - 1u ? 1u : 0u;
+      const u64 old = atomicAdd(&a.ctl->done, mine);
+      last = (old >> 40) == grid - 1u ? 1u : 0u;
+      sum = (old & kDoneMask) + (u64)appended;
     }
     s_last = last;
+    s_total = sum;
   }
   __syncthreads();
   const bool last = s_last != 0u;
+  *total = s_total;
   if (last) {
-    if (threadIdx.x < kDoneGroups) a.done[threadIdx.x * kCtrStride] = 0u;
-    if (threadIdx.x == 0) a.ctl->done_blocks = 0u;
+    if (threadIdx.x < kDoneGroups) a.done[threadIdx.x * kCtrStride] = 0ull;
+    if (threadIdx.x == 0) a.ctl->done = 0ull;
   }
   return last;
 }
@@ -392,8 +409,7 @@ __device__ __forceinline__ bool launch_last(const Args& a) {
 // `lds` (lds_bytes of LDS free by now, the flushed append stage; 4 bytes per
 // node); one beyond that is walked from global memory.
 __device__ __forceinline__ void level_end(const Args& a, const BfsBase* base, const BfsPolicy& p, u64* ring,
-                                          int k_run, void* lds, int lds_bytes) {
-  __shared__ uint32_t s_nn;
+                                          int k_run, void* lds, int lds_bytes, uint32_t appended) {
   const int tid = threadIdx.x;
   const bool tree = p.policy == GSW_POLICY_TREE;
   const bool tree_wave = tree && p.t_nodes <= 64 * kTreeLaneNodes;
@@ -410,7 +426,8 @@ __device__ __forceinline__ void level_end(const Args& a, const BfsBase* base, co
       wth[q] = p.t_thr[i];
     }
   }
-  if (!launch_last(a)) return;
+  u64 total = 0ull;
+  if (!launch_last(a, appended, &total)) return;
   BfsCtl* c = a.ctl;
   int32_t* l_next = reinterpret_cast<int32_t*>(lds);
   u64 nd0 = 0ull, nd1 = 0ull;
@@ -428,19 +445,8 @@ __device__ __forceinline__ void level_end(const Args& a, const BfsBase* base, co
     return;  // wave 0 finishes the level
   }
   const long long disc0 = c->disc;
-  uint32_t nn = 0u;
-  if (tid < 64) {  // wave 0: the next frontier's segments
-    uint32_t x = tid < kQueueBins
-                     ? __hip_atomic_load(a.cout + tid * kCtrStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                     : 0u;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += (uint32_t)__shfl_xor((int)x, off);
-    nn = x;
-  }
+  const uint32_t nn = (uint32_t)total;  // the next frontier: every workgroup's appends
   if (tree_par) {
-    if (tid == 0) s_nn = nn;
-    __syncthreads();
-    nn = s_nn;
     const long long nd = disc0 + (long long)nn;
     if (nn > 0) {
       const int32_t cf = (int32_t)nn, cd = (int32_t)nd;
@@ -503,7 +509,7 @@ __device__ __forceinline__ void level_end(const Args& a, const BfsBase* base, co
   cn->flags = nflags;
   cn->nf = (long long)nn;
   cn->disc = ndisc;
-  cn->done_blocks = 0u;
+  cn->done = 0ull;
   cn->phase = level_first_phase(next, (int64_t)nn);
   cn->t_begin = 0ull;
   cn->grid = next >= 0 ? level_grid(next, (int64_t)nn, *base) : 1;
@@ -560,14 +566,14 @@ __global__ void __launch_bounds__(kBlock) k_init(BfsBase b, const u64* __restric
     c->flags = flags0;
     c->nf = 1;
     c->disc = 1;
-    c->done_blocks = 0u;
+    c->done = 0ull;
     c->phase = level_first_phase(k0, 1);
     c->t_begin = 0ull;
     c->grid = level_grid(k0, 1, b);
     c->etot = 0;
   }
   if (gid < 4 * kCtrSlot) b.ctr[gid] = gid == 0 ? 1u : 0u;
-  if (gid < kDoneGroups) b.done[gid * kCtrStride] = 0u;
+  if (gid < kDoneGroups) b.done[gid * kCtrStride] = 0ull;
 }
 
 // ------------------------------------------------------------ long rows
@@ -834,7 +840,8 @@ __device__ __forceinline__ void body_edge_prefix(const Args& a, const QueueIn& q
 // End of the first launch: its last workgroup turns the block sums into
 // their exclusive prefix, stores the arc total and names the second launch.
 __device__ __forceinline__ void edge_prefix_end(const Args& a, const BfsBase& b, int64_t* wsum) {
-  if (!launch_last(a)) return;
+  u64 none = 0ull;
+  if (!launch_last(a, 0u, &none)) return;
   const int lane = lane_id();
   const int wid = threadIdx.x >> 6;
   const int64_t nb = div_up((int64_t)a.n_in, kScanTile);
@@ -869,7 +876,7 @@ __device__ __forceinline__ void edge_prefix_end(const Args& a, const BfsBase& b,
     cn->flags = c->flags;
     cn->nf = c->nf;
     cn->disc = c->disc;
-    cn->done_blocks = 0u;
+    cn->done = 0ull;
     cn->phase = 1;
     cn->t_begin = __hip_atomic_load(&c->t_begin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     cn->grid = (int32_t)(chunks < 1 ? 1 : (chunks < b.grid_max ? chunks : b.grid_max));
@@ -1234,7 +1241,7 @@ __global__ void __launch_bounds__(kBlock) k_level_auto(BfsBase b, BfsPolicy p, i
   if (k == GSW_K_PUSH_EDGE && phase == 2) {
     if (!body_edge_fused(a, st, qi, lds.edge)) return;
     stage_flush(st, a);
-    level_end(a, &b, p, b.ring, k, st.buf, (int)sizeof(st.buf));
+    level_end(a, &b, p, b.ring, k, st.buf, (int)sizeof(st.buf), st.n);
     return;
   }
   switch (k) {
@@ -1254,7 +1261,7 @@ __global__ void __launch_bounds__(kBlock) k_level_auto(BfsBase b, BfsPolicy p, i
     default: body_edge_scan(a, st); break;
   }
   stage_flush(st, a);
-  level_end(a, &b, p, b.ring, k, st.buf, (int)sizeof(st.buf));
+  level_end(a, &b, p, b.ring, k, st.buf, (int)sizeof(st.buf), st.n);
 }
 
 // ------------------------------------------------------------ helpers
