@@ -167,14 +167,29 @@ struct QueueIn {
   uint32_t pre[kQueueBins + 1];
 };
 
-__device__ __forceinline__ void queue_in_load(const Args& a, QueueIn& q) {
-  if (threadIdx.x == 0) {
-    uint32_t acc = 0;
-    for (int b = 0; b < kQueueBins; ++b) {
-      q.pre[b] = acc;
-      acc += a.cin[b * kCtrStride];
+// Counters of all four slots, one per lane of wave 0 (lane = slot * 8 + bin),
+// loaded at the start of a launch beside the control slot, before the level
+// (and so the slot it reads) is known.
+__device__ __forceinline__ uint32_t counters_prefetch(const uint32_t* ctr) {
+  const int t = threadIdx.x;
+  return t < 4 * kQueueBins ? ctr[(size_t)(t / kQueueBins) * kCtrSlot + (t % kQueueBins) * kCtrStride] : 0u;
+}
+
+// Segment offsets of the input queue from counter slot `slot`.  Every thread
+// calls it.
+__device__ __forceinline__ void queue_in_load(uint32_t cpre, int slot, QueueIn& q) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const int bin = lane % kQueueBins;
+    const uint32_t v = (uint32_t)__shfl((int)cpre, slot * kQueueBins + bin);
+    uint32_t inc = v;
+#pragma unroll
+    for (int off = 1; off < kQueueBins; off <<= 1) {
+      const uint32_t y = (uint32_t)__shfl_up((int)inc, off);
+      if (bin >= off) inc += y;
     }
-    q.pre[kQueueBins] = acc;
+    if (lane < kQueueBins) q.pre[lane] = inc - v;
+    if (lane == kQueueBins - 1) q.pre[kQueueBins] = inc;
   }
   __syncthreads();
 }
@@ -228,19 +243,68 @@ __device__ __forceinline__ void stage_push(Stage& s, const Args& a, bool win, in
   }
 }
 
-// Copies the staged entries to the workgroup's queue segment.  Every thread
-// of the workgroup must call it.
-__device__ __forceinline__ void stage_flush(Stage& s, const Args& a) {
+// The launch's "finished" count: each workgroup adds (1 << 40 | entries it
+// appended) to its group's counter, the group's last adds the group's sums to
+// the launch counter (see BfsCtl::done).
+constexpr u64 kDoneOne = 1ull << 40;  // one finished workgroup (or group)
+constexpr u64 kDoneMask = kDoneOne - 1ull;
+
+// Thread 0's part of the finish count: adds (one workgroup, `appended`
+// entries) and returns whether this workgroup is the launch's last; *total
+// then holds every participating workgroup's appends.
+__device__ __forceinline__ bool count_finished(const Args& a, uint32_t appended, u64* total) {
+  const uint32_t grid = (uint32_t)a.grid;
+  const u64 mine = kDoneOne | (u64)appended;
+  *total = (u64)appended;
+  if (grid > (unsigned)kDoneGroups) {
+    const uint32_t gidx = blockIdx.x % (unsigned)kDoneGroups;
+    const uint32_t in_group = grid / kDoneGroups + (gidx < grid % kDoneGroups ? 1u : 0u);
+    const u64 g_old = atomicAdd(a.done + gidx * kCtrStride, mine);
+    if ((g_old >> 40) != in_group - 1u) return false;
+    const u64 group = (g_old + mine) & kDoneMask;
+    const u64 old = atomicAdd(&a.ctl->done, kDoneOne | group);
+    *total = (old & kDoneMask) + group;
+    return (old >> 40) == (unsigned)kDoneGroups - 1u;
+  }
+  if (grid > 1u) {
+    const u64 old = atomicAdd(&a.ctl->done, mine);
+    *total = (old & kDoneMask) + (u64)appended;
+    return (old >> 40) == grid - 1u;
+  }
+  return true;  // a launch of one workgroup needs no count
+}
+
+// The last workgroup resets the finish counters for the next launch.
+__device__ __forceinline__ void reset_finished(const Args& a) {
+  if (threadIdx.x < kDoneGroups) a.done[threadIdx.x * kCtrStride] = 0ull;
+  if (threadIdx.x == 0) a.ctl->done = 0ull;
+}
+
+// The staged entries' flush and the finish count in one step: thread 0 issues the queue
+// reservation and the count together (the level's end needs only the
+// count; the entries are read by the next launch).  Every thread calls it;
+// returns (in every thread) whether this is the launch's last workgroup.
+__device__ __forceinline__ bool stage_flush_finish(Stage& s, const Args& a, u64* total) {
+  __shared__ u64 s_total;
+  __shared__ uint32_t s_last;
   __syncthreads();
   if (threadIdx.x == 0) {
     const uint32_t cnt = s.n < s.valid ? s.n : s.valid;
     s.valid = cnt;
-    s.base = cnt ? atomicAdd(a.cout + my_bin() * kCtrStride, cnt) : 0u;
+    const uint32_t base = cnt ? atomicAdd(a.cout + my_bin() * kCtrStride, cnt) : 0u;
+    u64 tot = 0ull;
+    s_last = count_finished(a, s.n, &tot) ? 1u : 0u;
+    s_total = tot;
+    s.base = base;
   }
   __syncthreads();
   const uint32_t cnt = s.valid;
   int32_t* dst = a.qout + (int64_t)my_bin() * a.n + s.base;
   for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) dst[i] = s.buf[i];
+  *total = s_total;
+  const bool last = s_last != 0u;
+  if (last) reset_finished(a);
+  return last;
 }
 
 // True for the one lane (device-wide) that first sets v's visited bit.
@@ -348,58 +412,52 @@ __device__ __forceinline__ int choose_next(const BfsPolicy& p, int32_t d, long l
   return choose_leaf(p, k, prev, flags);
 }
 
-// True (in every thread) in the last workgroup of the launch to get here;
-// called by every thread of every participating workgroup with the number of
-// queue entries its workgroup appended.  *total (every thread) receives the
-// launch's sum of those in the last workgroup.  The last one resets the
-// counters (before the launch ends, for the next one).
-constexpr u64 kDoneOne = 1ull << 40;  // one finished workgroup (or group)
-constexpr u64 kDoneMask = kDoneOne - 1ull;
-
-__device__ __forceinline__ bool launch_last(const Args& a, uint32_t appended, u64* total) {
-  __shared__ u64 s_total;
+// True (in every thread) in the last workgroup of the launch to get here,
+// for a launch that appends nothing (push_edge's prefix launch).  Called by
+// every thread of every participating workgroup.
+__device__ __forceinline__ bool launch_last(const Args& a) {
   __shared__ uint32_t s_last;
   __syncthreads();
   if (threadIdx.x == 0) {
-    const uint32_t grid = (uint32_t)a.grid;
-    const u64 mine = kDoneOne | (u64)appended;
-    uint32_t last = 1u;  // a launch of one workgroup needs no count
-    u64 sum = (u64)appended;
-    if (grid > (unsigned)kDoneGroups) {
-      const uint32_t gidx = blockIdx.x % (unsigned)kDoneGroups;
-      const uint32_t in_group = grid / kDoneGroups + (gidx < grid % kDoneGroups ? 1u : 0u);
-      last = 0u;
-      const u64 g_old = atomicAdd(a.done + gidx * kCtrStride, mine);
-      if ((g_old >> 40) == in_group - 1u) {
-        const u64 group = (g_old + mine) & kDoneMask;
-        const u64 old = atomicAdd(&a.ctl->done, kDoneOne | group);
-        last = (old >> 40) == (unsigned)kDoneGroups - 1u ? 1u : 0u;
-        sum = (old & kDoneMask) + group;
-      }
-    } else if (grid > 1u) {
-      const u64 old = atomicAdd(&a.ctl->done, mine);
-      last = (old >> 40) == grid - 1u ? 1u : 0u;
-      sum = (old & kDoneMask) + (u64)appended;
-    }
-    s_last = last;
-    s_total = sum;
+    u64 none = 0ull;
+    s_last = count_finished(a, 0u, &none) ? 1u : 0u;
   }
   __syncthreads();
   const bool last = s_last != 0u;
-  *total = s_total;
-  if (last) {
-    if (threadIdx.x < kDoneGroups) a.done[threadIdx.x * kCtrStride] = 0ull;
-    if (threadIdx.x == 0) a.ctl->done = 0ull;
-  }
+  if (last) reset_finished(a);
   return last;
 }
 
+// Tree nodes of a specialised tree of up to 64 * kTreeLaneNodes nodes, in
+// wave 0's registers (node i on lane i % 64, slot i / 64), loaded by every
+// workgroup before it counts itself finished so that the last one has them.
+struct TreeLanes {
+  u64 nd[kTreeLaneNodes];
+  int32_t thr[kTreeLaneNodes];
+};
+
+__device__ __forceinline__ TreeLanes tree_prefetch(const BfsPolicy& p) {
+  TreeLanes t;
+  const int tid = threadIdx.x;
+  const bool wave = p.policy == GSW_POLICY_TREE && p.t_nodes <= 64 * kTreeLaneNodes;
+#pragma unroll
+  for (int q = 0; q < kTreeLaneNodes; ++q) {
+    const int i = tid + 64 * q;
+    t.nd[q] = 0ull;
+    t.thr[q] = 0;
+    if (wave && tid < 64 && i < p.t_nodes) {
+      t.nd[q] = p.t_node[i];
+      t.thr[q] = p.t_thr[i];
+    }
+  }
+  return t;
+}
+
 // End of a level, called by every thread of every workgroup of the level's
-// last launch: the last workgroup to finish sums the next frontier's
-// segments, picks the next kernel, posts the level's record to the host
-// ring and writes the next launch's control slot.  Each workgroup's
-// queue-segment atomics have returned before it counts itself finished, so
-// the last one sees every segment's final size.  The device copy of a tree
+// last launch after stage_flush_finish: the last workgroup to finish, which
+// has the next frontier's size from the finish count, picks the next
+// kernel, posts the level's record to the host ring and writes the next
+// launch's control slot.  The device copy of a tree
 // is specialised to the graph (only splits on the level features remain):
 // when it has at most 64 * kTreeLaneNodes nodes, wave 0 of every workgroup
 // loads them (node i on lane i % 64) before the count, and the last one
@@ -409,25 +467,13 @@ __device__ __forceinline__ bool launch_last(const Args& a, uint32_t appended, u6
 // `lds` (lds_bytes of LDS free by now, the flushed append stage; 4 bytes per
 // node); one beyond that is walked from global memory.
 __device__ __forceinline__ void level_end(const Args& a, const BfsBase* base, const BfsPolicy& p, u64* ring,
-                                          int k_run, void* lds, int lds_bytes, uint32_t appended) {
+                                          int k_run, void* lds, int lds_bytes, const TreeLanes& tl, bool last,
+                                          u64 total) {
   const int tid = threadIdx.x;
   const bool tree = p.policy == GSW_POLICY_TREE;
   const bool tree_wave = tree && p.t_nodes <= 64 * kTreeLaneNodes;
   const bool tree_par = tree && !tree_wave && (long long)p.t_nodes * 4 <= (long long)lds_bytes;
-  u64 wnd[kTreeLaneNodes];
-  int32_t wth[kTreeLaneNodes];
-#pragma unroll
-  for (int q = 0; q < kTreeLaneNodes; ++q) {
-    const int i = tid + 64 * q;  // node i on lane i % 64, slot i / 64
-    wnd[q] = 0ull;
-    wth[q] = 0;
-    if (tree_wave && tid < 64 && i < p.t_nodes) {
-      wnd[q] = p.t_node[i];
-      wth[q] = p.t_thr[i];
-    }
-  }
-  u64 total = 0ull;
-  if (!launch_last(a, appended, &total)) return;
+  if (!last) return;
   BfsCtl* c = a.ctl;
   int32_t* l_next = reinterpret_cast<int32_t*>(lds);
   u64 nd0 = 0ull, nd1 = 0ull;
@@ -466,7 +512,7 @@ __device__ __forceinline__ void level_end(const Args& a, const BfsBase* base, co
       int32_t ch[kTreeLaneNodes];
 #pragma unroll
       for (int q = 0; q < kTreeLaneNodes; ++q)
-        ch[q] = q < slots ? tree_step(wnd[q], wth[q], (int32_t)nn, (int32_t)ndisc) : 0;
+        ch[q] = q < slots ? tree_step(tl.nd[q], tl.thr[q], (int32_t)nn, (int32_t)ndisc) : 0;
       // follow the children from the root: the node index is uniform, so each
       // step is a register read across lanes
       int32_t x = __builtin_amdgcn_readlane(ch[0], 0);
@@ -840,8 +886,7 @@ __device__ __forceinline__ void body_edge_prefix(const Args& a, const QueueIn& q
 // End of the first launch: its last workgroup turns the block sums into
 // their exclusive prefix, stores the arc total and names the second launch.
 __device__ __forceinline__ void edge_prefix_end(const Args& a, const BfsBase& b, int64_t* wsum) {
-  u64 none = 0ull;
-  if (!launch_last(a, 0u, &none)) return;
+  if (!launch_last(a)) return;
   const int lane = lane_id();
   const int wid = threadIdx.x >> 6;
   const int64_t nb = div_up((int64_t)a.n_in, kScanTile);
@@ -1210,6 +1255,7 @@ __global__ void __launch_bounds__(kBlock) k_level_auto(BfsBase b, BfsPolicy p, i
   __shared__ Stage st;
   __shared__ QueueIn qi;
   __shared__ LevelLds lds;
+  const uint32_t cpre = counters_prefetch(b.ctr);
   const BfsCtl* c = b.ctl + (j & 1);
   const int k = c->kernel;
   if (k < 0 || k >= GSW_N_KERNELS) {
@@ -1230,7 +1276,7 @@ __global__ void __launch_bounds__(kBlock) k_level_auto(BfsBase b, BfsPolicy p, i
   }
   stage_init(st);
   if (k != GSW_K_PULL_BITMAP && k != GSW_K_VERTEX_SCAN && k != GSW_K_EDGE_SCAN) {
-    queue_in_load(a, qi);
+    queue_in_load(cpre, d & 3, qi);
     a.n_in = qi.pre[kQueueBins];
   }
   if (k == GSW_K_PUSH_EDGE && phase == 0) {
@@ -1240,8 +1286,10 @@ __global__ void __launch_bounds__(kBlock) k_level_auto(BfsBase b, BfsPolicy p, i
   }
   if (k == GSW_K_PUSH_EDGE && phase == 2) {
     if (!body_edge_fused(a, st, qi, lds.edge)) return;
-    stage_flush(st, a);
-    level_end(a, &b, p, b.ring, k, st.buf, (int)sizeof(st.buf), st.n);
+    const TreeLanes tl = tree_prefetch(p);
+    u64 total = 0ull;
+    const bool last = stage_flush_finish(st, a, &total);
+    level_end(a, &b, p, b.ring, k, st.buf, (int)sizeof(st.buf), tl, last, total);
     return;
   }
   switch (k) {
@@ -1260,8 +1308,10 @@ __global__ void __launch_bounds__(kBlock) k_level_auto(BfsBase b, BfsPolicy p, i
     case GSW_K_VERTEX_SCAN: body_vertex_scan(a, st, lds.lr); break;
     default: body_edge_scan(a, st); break;
   }
-  stage_flush(st, a);
-  level_end(a, &b, p, b.ring, k, st.buf, (int)sizeof(st.buf), st.n);
+  const TreeLanes tl = tree_prefetch(p);
+  u64 total = 0ull;
+  const bool last = stage_flush_finish(st, a, &total);
+  level_end(a, &b, p, b.ring, k, st.buf, (int)sizeof(st.buf), tl, last, total);
 }
 
 // ------------------------------------------------------------ helpers
