@@ -271,7 +271,7 @@ def bench_serving(args, tree, log, preloaded):
 
 EDGE_FUSE = 512  # the library's one-launch limit for push_edge frontiers
 PROFILE_CMD = ("python3 -u bench.py --steps 2 --warmup 1 --no-compare --copy-calib --cpu-budget 1 "
-               "--dispatch-log gpurun_out/prof/dispatch_log.json")
+               "--dispatch-log {d}/dispatch_log.json")
 
 
 def _csv_rows(path):
@@ -347,10 +347,11 @@ def summarize_profile(d):
     L = ["# pull_bitmap on R-MAT scale 22 (64 sources, tree-switched path)", "",
          "Commands (from the repository root, `TMPDIR=/tmp`; the trace run's stdout is `trace_bench.json`):", "",
          "```",
-         "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof/trace -o run -- " + PROFILE_CMD,
-         "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof/fetch -o run -- " + PROFILE_CMD,
-         "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof/write -o run -- " + PROFILE_CMD,
-         "python3 bench.py --summarize-profile gpurun_out/prof", "```", "",
+         "rocprofv3 --kernel-trace --stats --output-format csv -d {d}/trace -o run -- ".format(d=d)
+         + PROFILE_CMD.format(d=d),
+         "rocprofv3 --pmc FETCH_SIZE --output-format csv -d {d}/fetch -o run -- ".format(d=d) + PROFILE_CMD.format(d=d),
+         "rocprofv3 --pmc WRITE_SIZE --output-format csv -d {d}/write -o run -- ".format(d=d) + PROFILE_CMD.format(d=d),
+         "python3 bench.py --summarize-profile " + d, "```", "",
          "Every dispatch of the command (warm-up, 2 timed steps, the instrumented pass), under the profiler. "
          "The level kernel's dispatches are attributed to the variant each ran from the dispatch log:", "",
          "| kernel / variant | dispatches | avg us | total us | FETCH_SIZE avg KB | WRITE_SIZE avg KB |",
