@@ -291,15 +291,24 @@ __global__ void __launch_bounds__(kMsBlock) k_heavy_build(const int64_t* __restr
 // --------------------------------------------------------------- top-down
 // ORs f & ~vis[v][j] into nx[v][j] for the arcs beg, beg + step, ... < end;
 // the first writer of an accumulator word marks v in the touched bitmap.
+// Four arcs at a time: their column loads, visited-word loads and atomics
+// are each issued before any result is used.
+constexpr int kMsBatch = 4;
+
 __device__ __forceinline__ void push_arcs(const MsArgs& a, u64 f, int j, int64_t beg, int64_t end,
                                           int step) {
-  for (int64_t e = beg; e < end; e += step) {
-    const int64_t v = a.cols[e];
-    const u64 m = f & ~a.vis[v * a.W + j];
-    if (m) {
-      const u64 old = atomicOr(a.nx + v * a.W + j, m);
-      if (!old) atomicOr(a.tbm + (v >> 6), 1ull << (v & 63));
-    }
+  for (int64_t e = beg; e < end; e += kMsBatch * step) {
+    int64_t v[kMsBatch];
+    u64 m[kMsBatch], old[kMsBatch];
+#pragma unroll
+    for (int q = 0; q < kMsBatch; ++q) v[q] = e + q * step < end ? (int64_t)a.cols[e + q * step] : -1;
+#pragma unroll
+    for (int q = 0; q < kMsBatch; ++q) m[q] = v[q] >= 0 ? f & ~a.vis[v[q] * a.W + j] : 0ull;
+#pragma unroll
+    for (int q = 0; q < kMsBatch; ++q) old[q] = m[q] ? atomicOr(a.nx + v[q] * a.W + j, m[q]) : ~0ull;
+#pragma unroll
+    for (int q = 0; q < kMsBatch; ++q)
+      if (!old[q]) atomicOr(a.tbm + (v[q] >> 6), 1ull << (v[q] & 63));
   }
 }
 
@@ -340,30 +349,18 @@ __global__ void __launch_bounds__(kMsBlock) k_ms_push(MsArgs a, int G) {
       }
     }
   }
-  // heavy rows: one chunk per wave step, for the chunks whose vertex is in
-  // the frontier
-  for (int64_t c0 = w.wave * 64; c0 < a.n_heavy; c0 += w.nwaves * 64) {
-    const int64_t c = c0 + w.lane;
-    u64 ent = 0ull;
-    bool live = false;
-    if (c < a.n_heavy) {
-      ent = a.heavy[c];
-      const int64_t u = (int64_t)(ent >> 32);
-      live = ((a.fbm[u >> 6] >> (u & 63)) & 1ull) != 0ull;
-    }
-    u64 lm = __ballot(live);
-    while (lm) {
-      const int src = __ffsll((long long)lm) - 1;
-      lm &= lm - 1ull;
-      const u64 e_ = __shfl(ent, src);
-      const int64_t u = (int64_t)(e_ >> 32);
-      const int64_t ci = (int64_t)(e_ & 0xffffffffull);
-      const u64 fw = pm ? (a.fr[u * a.W + j] & pm) : 0ull;
-      if (__ballot(fw != 0ull) == 0ull) continue;
-      const int64_t b = a.offs[u] + ci * kMsChunk;
-      const int64_t en = std::min<int64_t>(a.offs[u + 1], b + kMsChunk);
-      if (fw) push_arcs(a, fw, j, b + w.gi, en, w.gpw);
-    }
+  // heavy rows: the chunk list dealt out one entry per wave, so that the
+  // consecutive chunks of one hub's row go to different waves
+  for (int64_t c = w.wave; c < a.n_heavy; c += w.nwaves) {
+    const u64 ent = a.heavy[c];
+    const int64_t u = (int64_t)(ent >> 32);
+    if (!((a.fbm[u >> 6] >> (u & 63)) & 1ull)) continue;
+    const int64_t ci = (int64_t)(ent & 0xffffffffull);
+    const u64 fw = pm ? (a.fr[u * a.W + j] & pm) : 0ull;
+    if (__ballot(fw != 0ull) == 0ull) continue;
+    const int64_t b = a.offs[u] + ci * kMsChunk;
+    const int64_t en = std::min<int64_t>(a.offs[u + 1], b + kMsChunk);
+    if (fw) push_arcs(a, fw, j, b + w.gi, en, w.gpw);
   }
 }
 
