@@ -576,23 +576,42 @@ __global__ void __launch_bounds__(256) k_ms_finalize(MsCtl* ctl, u64* stats, u64
 }
 
 // [n][B] -> [nsrc][n] levels through 64x64-byte LDS tiles.
+// A 128-vertex x 128-source tile moved as 4-byte words, so both the reads
+// (128 source bytes of a vertex) and the writes (128 vertex bytes of a
+// source) cover whole 128-byte lines.  B is a multiple of 64, so every input
+// word is whole and aligned; with B = 64 the upper half of the tile is empty.
+constexpr int kTr = 128;
 __global__ void __launch_bounds__(256) k_ms_transpose(const int8_t* __restrict__ in,
                                                       int8_t* __restrict__ out, int64_t n, int B,
                                                       int nsrc) {
-  __shared__ int8_t tile[64][65];
-  const int64_t v0 = (int64_t)blockIdx.x * 64;
-  const int s0 = blockIdx.y * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
-  for (int r = ty; r < 64; r += 4) {
+  constexpr int kW = kTr / 4;  // words per tile row
+  __shared__ uint32_t tile[kTr][kW + 1];  // [vertex][word of 4 sources], padded
+  const int64_t v0 = (int64_t)blockIdx.x * kTr;
+  const int s0 = blockIdx.y * kTr;
+  for (int i = threadIdx.x; i < kTr * kW; i += 256) {
+    const int r = i / kW, wd = i % kW;
     const int64_t v = v0 + r;
-    const int s = s0 + tx;
-    tile[r][tx] = (v < n && s < B) ? in[v * B + s] : (int8_t)-1;
+    const int s = s0 + 4 * wd;
+    tile[r][wd] = v < n && s < B ? *reinterpret_cast<const uint32_t*>(in + v * B + s) : 0xffffffffu;
   }
   __syncthreads();
-  for (int r = ty; r < 64; r += 4) {
-    const int s = s0 + r;
-    const int64_t v = v0 + tx;
-    if (s < nsrc && v < n) out[(int64_t)s * n + v] = tile[tx][r];
+  for (int i = threadIdx.x; i < kTr * kW; i += 256) {
+    const int sr = i / kW, wd = i % kW;  // source s0 + sr, vertices v0 + 4 wd .. + 3
+    const int s = s0 + sr;
+    if (s >= nsrc) continue;
+    const int sh = 8 * (sr & 3);
+    uint32_t x = 0u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x |= ((tile[4 * wd + k][sr >> 2] >> sh) & 0xffu) << (8 * k);
+    const int64_t v = v0 + 4 * wd;
+    int8_t* dst = out + (int64_t)s * n + v;
+    if (v + 3 < n && (reinterpret_cast<uintptr_t>(dst) & 3u) == 0u) {
+      *reinterpret_cast<uint32_t*>(dst) = x;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (v + k < n) dst[k] = (int8_t)((x >> (8 * k)) & 0xffu);
+    }
   }
 }
 
@@ -1039,7 +1058,7 @@ gsw_status gsw_msbfs(const gsw_graph* cg, const int32_t* sources, int32_t n_sour
     }
     out = tmp;
   }
-  hipLaunchKernelGGL(k_ms_transpose, dim3((unsigned)cdiv(g->n, 64), (unsigned)cdiv(n_sources, 64)),
+  hipLaunchKernelGGL(k_ms_transpose, dim3((unsigned)cdiv(g->n, kTr), (unsigned)cdiv(n_sources, kTr)),
                      dim3(256), 0, s, (const int8_t*)m->lev, out, g->n, B, n_sources);
   if (hipGetLastError() != hipSuccess) st = fail(GSW_EHIP, "transpose launch failed");
   if (st == GSW_OK && tmp) {
