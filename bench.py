@@ -33,7 +33,8 @@ kernel trace and of the FETCH_SIZE / WRITE_SIZE counter runs in DIR with
 that log -- each call starts with one k_init dispatch, then each level takes
 one k_level_auto launch (two for push_edge on more than 512 entries), the
 rest of the call's launches find the search ended -- and prints the
-per-variant summary kept under profiles/.
+per-variant summary kept under profiles/.  ``--batched-only 1024`` runs only
+the batched section (for a kernel-trace profile of the batched kernels).
 """
 from __future__ import annotations
 
@@ -423,6 +424,8 @@ def main():
                     help="also run a plain 1 GiB device copy (scale for HBM byte counters)")
     ap.add_argument("--dispatch-log", default=None,
                     help="write every BFS call's (kernel, frontier) per level to this JSON file")
+    ap.add_argument("--batched-only", default=None, metavar="B[,B...]",
+                    help="only the batched section at these batch sizes (one JSON line; for profiling)")
     ap.add_argument("--summarize-profile", default=None, metavar="DIR",
                     help="no GPU: per-variant summary of the rocprofv3 runs in DIR, then exit")
     args = ap.parse_args()
@@ -449,6 +452,11 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     torch.cuda.set_device(0)
     sync = torch.cuda.synchronize
+
+    if args.batched_only:
+        sizes = tuple(int(x) for x in args.batched_only.split(","))
+        print(json.dumps({"batched": bench_batched(log, sizes)}), flush=True)
+        return
 
     t = time.perf_counter()
     g = gg.workload(args.workload)
