@@ -259,6 +259,7 @@ def bench_serving(args, tree, log, preloaded):
                                        (" + single-source lane" if solo else ""))
             if solo:
                 row[key]["solo_served"] = srv.solo_served
+            log("serving %d QPS, %s done" % (rate, key))  # one line per mode: a long drain still reports
         if not args.serving_full or rate <= 500:
             qo = serve.serve_one_at_a_time(residents, trace, tree, timeout_s=120)
             row["one_at_a_time"] = serve.summarize(qo, residents, "one at a time")

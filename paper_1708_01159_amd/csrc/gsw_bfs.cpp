@@ -210,6 +210,7 @@ BfsBase make_base(const gsw_graph* g, int32_t* lv, int32_t* pa, bool timed) {
   b.offs = g->offs;
   b.cols = g->cols;
   b.origin = g->origin;
+  b.head = w.head;
   b.level = lv;
   b.parent = pa;
   b.vis = w.vis;

@@ -161,6 +161,7 @@ gsw_status ensure_workspace(gsw_graph* g) {
       {(void**)&w.bsum, (size_t)nb * sizeof(int64_t)},
       {(void**)&w.lvl_tmp, (size_t)n * sizeof(int32_t)},
       {(void**)&w.par_tmp, (size_t)n * sizeof(int32_t)},
+      {(void**)&w.head, (size_t)n * kHeadArcs * sizeof(int32_t)},
   };
   for (auto& it : items) {
     hipError_t e = hipMalloc(it.p, it.bytes);
@@ -177,6 +178,10 @@ gsw_status ensure_workspace(gsw_graph* g) {
                         hipHostMallocMapped | hipHostMallocCoherent));
   std::memset(w.ring, 0, (size_t)kBfsRing * kBfsRec * sizeof(unsigned long long));
   GSW_HIP(hipHostGetDevicePointer((void**)&w.d_ring, w.ring, 0));
+  if (n > 0) {
+    GSW_TRY(launch_build_head(g, w.head, g->stream));
+    GSW_HIP(hipStreamSynchronize(g->stream));
+  }
   if (g->symmetric && !g->iso) {
     const size_t ib = (size_t)w.nw * sizeof(unsigned long long);
     hipError_t e = hipMalloc((void**)&g->iso, ib);
@@ -224,7 +229,7 @@ void free_graph(gsw_graph* g) {
   if (!g) return;
   Workspace& w = g->ws;
   void* dev[] = {w.vis, w.bm[0], w.bm[1], w.bm[2], w.ctl, w.done, w.q[0], w.q[1], w.ctr, w.scan, w.ebeg,
-                 w.bsum, w.lvl_tmp, w.par_tmp, w.d_tree, w.d_thr, w.d_sched, g->origin};
+                 w.bsum, w.lvl_tmp, w.par_tmp, w.head, w.d_tree, w.d_thr, w.d_sched, g->origin};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   if (w.h_ctr) (void)hipHostFree(w.h_ctr);

@@ -45,6 +45,13 @@ constexpr int kCtrSlot = kQueueBins * kCtrStride;  // words per level in the cou
 // never treated as unvisited.
 struct BfsCtl;
 
+// Bottom-up probes start from a dense copy of the first kHeadArcs arcs of
+// every row ([n][kHeadArcs], -1 past the row's end): a wave's unvisited
+// vertices read theirs as consecutive 16-byte records instead of one
+// scattered cache line per row, and only rows still unresolved after them
+// are read in the CSR.
+constexpr int kHeadArcs = 4;
+
 struct Workspace {
   int64_t n = 0, nw = 0;
   unsigned long long* vis = nullptr;     // visited
@@ -54,6 +61,7 @@ struct Workspace {
   int64_t* scan = nullptr;               // push_edge: per-entry exclusive degree scan
   int64_t* ebeg = nullptr;               // push_edge: row start per queue entry
   int64_t* bsum = nullptr;               // push_edge: per-block sums
+  int32_t* head = nullptr;               // pull: first kHeadArcs arcs of every row
   int32_t* lvl_tmp = nullptr;            // levels when the caller passes host memory
   int32_t* par_tmp = nullptr;            // parents when the caller passes host memory
   uint32_t* h_ctr = nullptr;             // pinned host copy of one counter slot
@@ -162,6 +170,7 @@ struct BfsBase {
   const int64_t* offs;
   const int32_t* cols;
   const int32_t* origin;
+  const int32_t* head;             // first kHeadArcs arcs of every row, -1 padded
   int32_t* level;
   int32_t* parent;                 // may be null
   unsigned long long* vis;
@@ -230,6 +239,7 @@ gsw_status launch_isolated(const gsw_graph* g, unsigned long long* iso, hipStrea
 gsw_status launch_canonical_parents(const gsw_graph* g, const int32_t* level, int32_t* parent,
                                     hipStream_t s);
 gsw_status launch_build_origin(const gsw_graph* g, int32_t* origin, hipStream_t s);
+gsw_status launch_build_head(const gsw_graph* g, int32_t* head, hipStream_t s);
 
 gsw_status ensure_workspace(gsw_graph* g);
 gsw_status ensure_origin(gsw_graph* g);

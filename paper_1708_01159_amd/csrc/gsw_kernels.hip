@@ -61,6 +61,7 @@ struct Args {
   const int64_t* __restrict__ offs;
   const int32_t* __restrict__ cols;
   const int32_t* __restrict__ origin;
+  const int32_t* __restrict__ head;  // first kHeadArcs arcs of every row, -1 padded
   int32_t* __restrict__ level;
   int32_t* __restrict__ parent;
   u64* vis;
@@ -89,6 +90,7 @@ __host__ __device__ inline Args make_args(const BfsBase& b, int32_t j, int32_t d
   a.offs = b.offs;
   a.cols = b.cols;
   a.origin = b.origin;
+  a.head = b.head;
   a.level = b.level;
   a.parent = b.parent;
   a.vis = b.vis;
@@ -1066,7 +1068,10 @@ __device__ __forceinline__ bool body_edge_fused(Args& a, Stage& st, const QueueI
 // instead of one dependent load chain per 64.  Each lane looks for a
 // neighbour of its vertex in the frontier bitmap, in row order, and stops at
 // the first one (Section III-A, vertex pull).  Phase 1: every lane probes the
-// first kPullEager neighbours of its row with independent loads (many misses
+// first kHeadArcs neighbours of its row from the dense head copy (the lanes'
+// records are consecutive, so most vertices, which find a frontier
+// neighbour among their first few, never touch their CSR row), then, if
+// still unresolved, the next kPullEager with independent loads (many misses
 // in flight instead of one dependent chain).  Phase 2: rows that are longer
 // and still unresolved are scanned by the whole wavefront, 64 neighbours per
 // step, one row at a time -- a high-degree row does not stall its wave for
@@ -1141,26 +1146,41 @@ __device__ __forceinline__ void body_pull(const Args& a, Stage& st, u64 (*s_foun
         }
       const int bit = mine ? nth_set_bit(t, k - f0) : 0;
       const int32_t v = (int32_t)((w0 + kw) * 64 + bit);
+      // the row's first kHeadArcs arcs from the dense copy, its bounds beside
       int64_t beg = 0, end = 0;
+      int4 h = make_int4(-1, -1, -1, -1);
       if (mine) {
+        h = reinterpret_cast<const int4*>(a.head)[v];
         beg = a.offs[v];
         end = a.offs[v + 1];
       }
-      int32_t u[kPullEager];
-      u64 fw[kPullEager];
+      const int32_t hu[kHeadArcs] = {h.x, h.y, h.z, h.w};
+      u64 hw[kHeadArcs];
 #pragma unroll
-      for (int q = 0; q < kPullEager; ++q) u[q] = beg + q < end ? a.cols[beg + q] : -1;
-#pragma unroll
-      for (int q = 0; q < kPullEager; ++q) fw[q] = u[q] >= 0 ? a.fr[u[q] >> 6] : 0ull;
+      for (int q = 0; q < kHeadArcs; ++q) hw[q] = hu[q] >= 0 ? a.fr[hu[q] >> 6] : 0ull;
       int32_t par = -1;
 #pragma unroll
-      for (int q = kPullEager - 1; q >= 0; --q)
-        if (u[q] >= 0 && ((fw[q] >> (u[q] & 63)) & 1ull)) par = u[q];
-      u64 rest = __ballot(mine && par < 0 && end - beg > kPullEager);
+      for (int q = kHeadArcs - 1; q >= 0; --q)
+        if (hu[q] >= 0 && ((hw[q] >> (hu[q] & 63)) & 1ull)) par = hu[q];
+      // unresolved longer rows: the next kPullEager arcs with independent loads
+      constexpr int kProbed = kHeadArcs + kPullEager;
+      if (mine && par < 0 && end - beg > kHeadArcs) {
+        int32_t u[kPullEager];
+        u64 fw[kPullEager];
+#pragma unroll
+        for (int q = 0; q < kPullEager; ++q)
+          u[q] = beg + kHeadArcs + q < end ? a.cols[beg + kHeadArcs + q] : -1;
+#pragma unroll
+        for (int q = 0; q < kPullEager; ++q) fw[q] = u[q] >= 0 ? a.fr[u[q] >> 6] : 0ull;
+#pragma unroll
+        for (int q = kPullEager - 1; q >= 0; --q)
+          if (u[q] >= 0 && ((fw[q] >> (u[q] & 63)) & 1ull)) par = u[q];
+      }
+      u64 rest = __ballot(mine && par < 0 && end - beg > kProbed);
       while (rest != 0ull) {
         const int owner = __ffsll((long long)rest) - 1;
         rest &= rest - 1ull;
-        const int64_t lo = __shfl(beg, owner) + kPullEager;
+        const int64_t lo = __shfl(beg, owner) + kProbed;
         const int64_t hi = __shfl(end, owner);
         int32_t hit = -1;
         for (int64_t cc = lo; cc < hi; cc += 64) {
@@ -1326,6 +1346,21 @@ __global__ void __launch_bounds__(kBlock) k_isolated(const int64_t* __restrict__
   }
 }
 
+__global__ void __launch_bounds__(kBlock) k_build_head(const int64_t* __restrict__ offs,
+                                                       const int32_t* __restrict__ cols,
+                                                       int4* __restrict__ head, int64_t n) {
+  static_assert(kHeadArcs == 4, "one int4 per row");
+  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
+    const int64_t beg = offs[v], deg = offs[v + 1] - beg;
+    int4 h;
+    h.x = deg > 0 ? cols[beg] : -1;
+    h.y = deg > 1 ? cols[beg + 1] : -1;
+    h.z = deg > 2 ? cols[beg + 2] : -1;
+    h.w = deg > 3 ? cols[beg + 3] : -1;
+    head[v] = h;
+  }
+}
+
 __global__ void __launch_bounds__(kBlock) k_canonical_parents(const int64_t* __restrict__ offs,
                                                               const int32_t* __restrict__ cols,
                                                               const int32_t* __restrict__ level,
@@ -1388,6 +1423,13 @@ gsw_status launch_level_auto(const gsw_graph* g, const BfsBase& b, const BfsPoli
   (void)g;
   const int32_t wg = workgroups < 1 ? 1 : (workgroups < b.grid_max ? workgroups : b.grid_max);
   hipLaunchKernelGGL(k_level_auto, dim3((unsigned)wg), dim3(kBlock), 0, s, b, p, j);
+  GSW_HIP(hipGetLastError());
+  return GSW_OK;
+}
+
+gsw_status launch_build_head(const gsw_graph* g, int32_t* head, hipStream_t s) {
+  hipLaunchKernelGGL(k_build_head, dim3(persistent_grid(cdiv(g->n, kBlock))), dim3(kBlock), 0, s, g->offs,
+                     g->cols, reinterpret_cast<int4*>(head), g->n);
   GSW_HIP(hipGetLastError());
   return GSW_OK;
 }
