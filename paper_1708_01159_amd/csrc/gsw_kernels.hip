@@ -1148,13 +1148,24 @@ __device__ __forceinline__ void body_pull(const Args& a, Stage& st, u64 (*s_foun
       const int32_t v = (int32_t)((w0 + kw) * 64 + bit);
       // the row's first kHeadArcs arcs from the dense copy, its bounds beside
       int64_t beg = 0, end = 0;
-      int4 h = make_int4(-1, -1, -1, -1);
+      int4 h[kHeadArcs / 4];
+#pragma unroll
+      for (int r = 0; r < kHeadArcs / 4; ++r) h[r] = make_int4(-1, -1, -1, -1);
       if (mine) {
-        h = reinterpret_cast<const int4*>(a.head)[v];
+#pragma unroll
+        for (int r = 0; r < kHeadArcs / 4; ++r)
+          h[r] = reinterpret_cast<const int4*>(a.head)[(int64_t)v * (kHeadArcs / 4) + r];
         beg = a.offs[v];
         end = a.offs[v + 1];
       }
-      const int32_t hu[kHeadArcs] = {h.x, h.y, h.z, h.w};
+      int32_t hu[kHeadArcs];
+#pragma unroll
+      for (int r = 0; r < kHeadArcs / 4; ++r) {
+        hu[4 * r] = h[r].x;
+        hu[4 * r + 1] = h[r].y;
+        hu[4 * r + 2] = h[r].z;
+        hu[4 * r + 3] = h[r].w;
+      }
       u64 hw[kHeadArcs];
 #pragma unroll
       for (int q = 0; q < kHeadArcs; ++q) hw[q] = hu[q] >= 0 ? a.fr[hu[q] >> 6] : 0ull;
@@ -1349,15 +1360,18 @@ __global__ void __launch_bounds__(kBlock) k_isolated(const int64_t* __restrict__
 __global__ void __launch_bounds__(kBlock) k_build_head(const int64_t* __restrict__ offs,
                                                        const int32_t* __restrict__ cols,
                                                        int4* __restrict__ head, int64_t n) {
-  static_assert(kHeadArcs == 4, "one int4 per row");
+  static_assert(kHeadArcs % 4 == 0, "whole int4 records per row");
   for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
     const int64_t beg = offs[v], deg = offs[v + 1] - beg;
-    int4 h;
-    h.x = deg > 0 ? cols[beg] : -1;
-    h.y = deg > 1 ? cols[beg + 1] : -1;
-    h.z = deg > 2 ? cols[beg + 2] : -1;
-    h.w = deg > 3 ? cols[beg + 3] : -1;
-    head[v] = h;
+#pragma unroll
+    for (int r = 0; r < kHeadArcs / 4; ++r) {
+      int4 h;
+      h.x = deg > 4 * r ? cols[beg + 4 * r] : -1;
+      h.y = deg > 4 * r + 1 ? cols[beg + 4 * r + 1] : -1;
+      h.z = deg > 4 * r + 2 ? cols[beg + 4 * r + 2] : -1;
+      h.w = deg > 4 * r + 3 ? cols[beg + 4 * r + 3] : -1;
+      head[v * (kHeadArcs / 4) + r] = h;
+    }
   }
 }
 
