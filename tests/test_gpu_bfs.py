@@ -233,6 +233,45 @@ def test_canonical_parents_exact(name):
             assert np.array_equal(pa[i], _canonical(g, refs[i][0]))
 
 
+def _probe_positions_graph():
+    # source 0 -> frontier F = 1000..1099 (depth 1) -> targets 2000 + k
+    # (depth 2).  Target k's sorted row holds k fillers (ids 1..k, reached only
+    # through targets), then two members of F, then five trailing fillers
+    # (ids 3000..3004): its first frontier neighbour sits at row position k,
+    # across the head copy (4 arcs), the eager probes (next 8) and the wave
+    # scan's 64-arc chunks that follow.
+    src, dst = [], []
+    for f in range(1000, 1100):
+        src.append(0), dst.append(f)
+    for k in range(150):
+        t = 2000 + k
+        for j in range(1, k + 1):
+            src.append(t), dst.append(j)
+        for f in (1000 + k % 100, 1000 + (k + 7) % 100):
+            src.append(t), dst.append(f)
+        for j in range(3000, 3005):
+            src.append(t), dst.append(j)
+    return gg.from_edges(3005, src, dst, symmetrize=True, name="probe_positions")
+
+
+@pytest.mark.parametrize("name", ["probe_positions", "rmat14", "chunglu", "er_ragged", "grid", "disjoint"])
+def test_pull_parent_is_first_frontier_neighbour(name):
+    # rows are sorted, so a bottom-up level that stops at the first neighbour
+    # in the frontier (Section III-A) gives exactly the smallest neighbour one
+    # level up: with pull at every level, parents equal the canonical ones
+    if name == "probe_positions":
+        g = _probe_positions_graph()
+        G = gsw.Graph.from_csr(g.offs, g.cols)
+        srcs = np.array([0, 2077], dtype=np.int32)
+        refs = [oracle.bfs(g.offs, g.cols, int(s)) for s in srcs]
+    else:
+        g, G, srcs, refs, comp = case(name)
+    lv, pa, _ = gsw.bfs(G, srcs, policy="fixed", kernel=gsw.PULL_BITMAP)
+    for i in range(len(srcs)):
+        assert np.array_equal(lv[i], refs[i][0])
+        assert np.array_equal(pa[i], _canonical(g, refs[i][0])), (name, int(srcs[i]))
+
+
 def test_device_pointers_and_torch_stream():
     import torch
 
