@@ -1146,7 +1146,8 @@ __device__ __forceinline__ void body_pull(const Args& a, Stage& st, u64 (*s_foun
         }
       const int bit = mine ? nth_set_bit(t, k - f0) : 0;
       const int32_t v = (int32_t)((w0 + kw) * 64 + bit);
-      // the row's first kHeadArcs arcs from the dense copy, its bounds beside
+      // the row's first kHeadArcs arcs from the dense copy; the row's bounds
+      // only when it may go on past them and they found nothing
       int64_t beg = 0, end = 0;
       int4 h[kHeadArcs / 4];
 #pragma unroll
@@ -1155,8 +1156,6 @@ __device__ __forceinline__ void body_pull(const Args& a, Stage& st, u64 (*s_foun
 #pragma unroll
         for (int r = 0; r < kHeadArcs / 4; ++r)
           h[r] = reinterpret_cast<const int4*>(a.head)[(int64_t)v * (kHeadArcs / 4) + r];
-        beg = a.offs[v];
-        end = a.offs[v + 1];
       }
       int32_t hu[kHeadArcs];
 #pragma unroll
@@ -1175,6 +1174,10 @@ __device__ __forceinline__ void body_pull(const Args& a, Stage& st, u64 (*s_foun
         if (hu[q] >= 0 && ((hw[q] >> (hu[q] & 63)) & 1ull)) par = hu[q];
       // unresolved longer rows: the next kPullEager arcs with independent loads
       constexpr int kProbed = kHeadArcs + kPullEager;
+      if (mine && par < 0 && hu[kHeadArcs - 1] >= 0) {
+        beg = a.offs[v];
+        end = a.offs[v + 1];
+      }
       if (mine && par < 0 && end - beg > kHeadArcs) {
         int32_t u[kPullEager];
         u64 fw[kPullEager];
