@@ -137,7 +137,9 @@ hipStream_t pick_stream(gsw_graph* g, void* user_stream) {
 
 gsw_status ensure_workspace(gsw_graph* g) {
   Workspace& w = g->ws;
-  if (w.vis) return GSW_OK;
+  if (w.ready) return GSW_OK;
+  // every step below is skipped once done, so a call after a failed one
+  // resumes where that one stopped instead of using half-built buffers
   const int64_t n = g->n;
   w.n = n;
   w.nw = (n + 63) / 64;
@@ -164,6 +166,7 @@ gsw_status ensure_workspace(gsw_graph* g) {
       {(void**)&w.head, (size_t)n * kHeadArcs * sizeof(int32_t)},
   };
   for (auto& it : items) {
+    if (*it.p) continue;
     hipError_t e = hipMalloc(it.p, it.bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
@@ -172,15 +175,20 @@ gsw_status ensure_workspace(gsw_graph* g) {
     }
     w.bytes += it.bytes;
   }
-  GSW_HIP(hipHostMalloc((void**)&w.h_ctr, kCtrSlot * sizeof(uint32_t), hipHostMallocDefault));
-  GSW_HIP(hipHostMalloc((void**)&w.h_ctl, sizeof(BfsCtl), hipHostMallocDefault));
-  GSW_HIP(hipHostMalloc((void**)&w.ring, (size_t)kBfsRing * kBfsRec * sizeof(unsigned long long),
-                        hipHostMallocMapped | hipHostMallocCoherent));
-  std::memset(w.ring, 0, (size_t)kBfsRing * kBfsRec * sizeof(unsigned long long));
-  GSW_HIP(hipHostGetDevicePointer((void**)&w.d_ring, w.ring, 0));
-  if (n > 0) {
-    GSW_TRY(launch_build_head(g, w.head, g->stream));
-    GSW_HIP(hipStreamSynchronize(g->stream));
+  if (!w.h_ctr) GSW_HIP(hipHostMalloc((void**)&w.h_ctr, kCtrSlot * sizeof(uint32_t), hipHostMallocDefault));
+  if (!w.h_ctl) GSW_HIP(hipHostMalloc((void**)&w.h_ctl, sizeof(BfsCtl), hipHostMallocDefault));
+  if (!w.ring) {
+    GSW_HIP(hipHostMalloc((void**)&w.ring, (size_t)kBfsRing * kBfsRec * sizeof(unsigned long long),
+                          hipHostMallocMapped | hipHostMallocCoherent));
+    std::memset(w.ring, 0, (size_t)kBfsRing * kBfsRec * sizeof(unsigned long long));
+  }
+  if (!w.d_ring) GSW_HIP(hipHostGetDevicePointer((void**)&w.d_ring, w.ring, 0));
+  if (!w.head_built) {
+    if (n > 0) {
+      GSW_TRY(launch_build_head(g, w.head, g->stream));
+      GSW_HIP(hipStreamSynchronize(g->stream));
+    }
+    w.head_built = true;
   }
   if (g->symmetric && !g->iso) {
     const size_t ib = (size_t)w.nw * sizeof(unsigned long long);
@@ -191,16 +199,24 @@ gsw_status ensure_workspace(gsw_graph* g) {
       return fail(GSW_ENOMEM, "hipMalloc(%zu) for the isolated-vertex bitmap failed", ib);
     }
     w.bytes += ib;
-    GSW_TRY(launch_isolated(g, g->iso, g->stream));
-    GSW_HIP(hipStreamSynchronize(g->stream));
+    gsw_status st = launch_isolated(g, g->iso, g->stream);
+    if (st == GSW_OK && hipStreamSynchronize(g->stream) != hipSuccess)
+      st = fail(GSW_EHIP, "building the isolated-vertex bitmap failed");
+    if (st != GSW_OK) {  // rebuilt by the next call
+      (void)hipFree(g->iso);
+      g->iso = nullptr;
+      w.bytes -= ib;
+      return st;
+    }
   }
-  GSW_HIP(hipEventCreate(&w.ev[0]));
-  GSW_HIP(hipEventCreate(&w.ev[1]));
+  if (!w.ev[0]) GSW_HIP(hipEventCreate(&w.ev[0]));
+  if (!w.ev[1]) GSW_HIP(hipEventCreate(&w.ev[1]));
   {
     int khz = 0;
     GSW_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, g->device));
     w.tick_ms = khz > 0 ? 1.0 / (double)khz : 0.0;
   }
+  w.ready = true;
   return GSW_OK;
 }
 

@@ -81,6 +81,8 @@ struct Workspace {
   hipEvent_t ev[2] = {};
   double tick_ms = 0.0;                  // milliseconds per wall-clock tick
   size_t bytes = 0;
+  bool head_built = false;               // head holds the graph's rows
+  bool ready = false;                    // every buffer allocated and built
 };
 
 struct MsWorkspace;  // batched BFS state (gsw_msbfs.hip)
