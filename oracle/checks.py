@@ -129,6 +129,63 @@ def check_bfs(offs, cols, source: int, level, parent=None, comp=None) -> None:
         raise InvariantError("I5: vertex %d reached=%s in-component=%s" % (v, reached[v], incomp[v]))
 
 
+def reachable(offs, cols, source: int) -> np.ndarray:
+    """Vertices reachable from ``source`` along arcs (scipy's traversal, a
+    library routine independent of the FIFO oracle)."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import breadth_first_order
+
+    offs = np.asarray(offs, dtype=np.int64)
+    n = offs.shape[0] - 1
+    a = sp.csr_matrix((np.ones(len(cols), dtype=np.int8), np.asarray(cols, dtype=np.int64), offs), shape=(n, n))
+    order = breadth_first_order(a, int(source), directed=True, return_predecessors=False)
+    out = np.zeros(n, dtype=bool)
+    out[order] = True
+    return out
+
+
+def check_bfs_directed(offs, cols, source: int, level, parent=None) -> None:
+    """The invariants for a directed graph (row u lists the arcs u -> v):
+
+      D1  L[s] == 0 and P[s] == s;
+      D2  every arc (u, v) with L[u] >= 0 has L[v] >= 0 and L[v] <= L[u] + 1;
+      D3  every reached v != s has an arc P[v] -> v with L[P[v]] == L[v] - 1;
+      D4  L[v] == -1 exactly when P[v] == -1;
+      D5  the reached set equals the set reachable from s.
+
+    D3 gives a path of length L[v] (distance <= L[v]); along a shortest path
+    D2 raises L by at most one per arc (L[v] <= distance)."""
+    offs = np.asarray(offs, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    level = np.asarray(level, dtype=np.int64)
+    n = offs.shape[0] - 1
+    s = int(source)
+    if level[s] != 0:
+        raise InvariantError("D1: level[source]=%d" % level[s])
+    rows = _rows(offs)
+    lu, lv = level[rows], level[cols]
+    live = lu >= 0
+    if np.any(lv[live] < 0) or np.any(lv[live] > lu[live] + 1):
+        e = int(np.flatnonzero(live & ((lv < 0) | (lv > lu + 1)))[0])
+        raise InvariantError("D2: arc (%d,%d) has levels %d,%d" % (rows[e], cols[e], lu[e], lv[e]))
+    if parent is not None:
+        parent = np.asarray(parent, dtype=np.int64)
+        if parent[s] != s:
+            raise InvariantError("D1: parent[source]=%d" % parent[s])
+        if np.any((level == -1) != (parent == -1)):
+            raise InvariantError("D4: reached and parent disagree")
+        vs = np.flatnonzero(level > 0)
+        ps = parent[vs]
+        if np.any((ps < 0) | (ps >= n)) or np.any(level[ps] != level[vs] - 1):
+            raise InvariantError("D3: a parent is not one level up")
+        arcs = set((rows * n + cols).tolist())
+        for v, p in zip(vs.tolist(), ps.tolist()):
+            if p * n + v not in arcs:
+                raise InvariantError("D3: no arc %d -> %d" % (p, v))
+    if np.any((level >= 0) != reachable(offs, cols, s)):
+        raise InvariantError("D5: reached set differs from the reachable set")
+
+
 def is_symmetric(offs, cols) -> bool:
     offs = np.asarray(offs, dtype=np.int64)
     cols = np.asarray(cols, dtype=np.int64)

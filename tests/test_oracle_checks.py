@@ -113,3 +113,58 @@ def test_is_symmetric():
     offs = np.array([0, 1, 1], dtype=np.int64)
     cols = np.array([1], dtype=np.int32)
     assert not checks.is_symmetric(offs, cols)
+
+
+def _directed_graph():
+    # a random directed graph with cycles, one-way and reciprocated arcs
+    rng = np.random.default_rng(9)
+    n, m = 300, 900
+    src, dst = rng.integers(0, n, m), rng.integers(0, n, m)
+    return gg.from_edges(n, src, dst, symmetrize=False, name="dir300")
+
+
+def test_directed_invariants_accept_the_oracle():
+    g = _directed_graph()
+    assert not checks.is_symmetric(g.offs, g.cols)
+    for s in gg.pick_sources(g, 5, 3):
+        lv, pa, _, _ = oracle.bfs(g.offs, g.cols, int(s))
+        checks.check_bfs_directed(g.offs, g.cols, int(s), lv, pa)
+        # and the oracle equals scipy's directed shortest paths
+        import scipy.sparse as sp
+        from scipy.sparse.csgraph import shortest_path
+
+        a = sp.csr_matrix((np.ones(g.nnz), g.cols, g.offs), shape=(g.n, g.n))
+        d = shortest_path(a, directed=True, unweighted=True, indices=int(s))
+        assert np.array_equal(np.where(np.isinf(d), -1, d).astype(np.int64), lv)
+
+
+def test_directed_invariants_reject_planted_mistakes():
+    g = _directed_graph()
+    s = int(gg.pick_sources(g, 1, 4)[0])
+    lv, pa, _, _ = oracle.bfs(g.offs, g.cols, s)
+    deep = int(np.flatnonzero(lv == lv.max())[0])
+    bad = lv.copy()
+    bad[deep] += 1  # one level too deep: its parent's arc spans two levels
+    with pytest.raises(checks.InvariantError):
+        checks.check_bfs_directed(g.offs, g.cols, s, bad, pa)
+    # a parent one level up that has no arc into the vertex (only a reverse one or none)
+    rows = np.repeat(np.arange(g.n), g.degrees())
+    v = deep
+    ins = set(rows[g.cols == v].tolist())
+    cands = [u for u in np.flatnonzero(lv == lv[v] - 1).tolist() if u not in ins]
+    if cands:
+        p2 = pa.copy()
+        p2[v] = cands[0]
+        with pytest.raises(checks.InvariantError):
+            checks.check_bfs_directed(g.offs, g.cols, s, lv, p2)
+    # an unreachable vertex reported reached
+    un = np.flatnonzero(lv < 0)
+    if un.size:
+        l3, p3 = lv.copy(), pa.copy()
+        l3[un[0]], p3[un[0]] = lv.max() + 1, deep
+        with pytest.raises(checks.InvariantError):
+            checks.check_bfs_directed(g.offs, g.cols, s, l3, p3)
+    # the symmetric checker's I2 would reject a correct directed result (an
+    # arc pointing back up more than one level is fine when directed)
+    span = (lv[rows] >= 0) & (lv[g.cols] >= 0) & (lv[rows] - lv[g.cols] > 1)
+    assert span.any()

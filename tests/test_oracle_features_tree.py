@@ -30,7 +30,33 @@ def test_level_features():
     hist = np.array([1, 2, 1])
     x = features.level_features(offs, hist, 1)
     assert x.shape == (features.N_FEATURES,)
-    assert x[8:].tolist() == [2.0, 0.5, 3.0, 0.75]
+    assert x[20:].tolist() == [2.0, 0.5, 3.0, 0.75]
+    # symmetric: in- and absolute-degree summaries repeat the out-degree one
+    assert x[8:14].tolist() == x[2:8].tolist() == x[14:20].tolist()
+
+
+def test_directed_degree_features_by_hand():
+    """Arcs 0->1, 0->2, 0->3, 1->0.  out = (3,1,0,0), in = (1,1,1,1), absolute
+    (distinct neighbours ignoring direction) = (3,1,1,1)."""
+    offs = np.array([0, 3, 4, 4, 4], dtype=np.int64)
+    cols = np.array([1, 2, 3, 0], dtype=np.int32)
+    out, ind, ab = features.degrees(offs, cols)
+    assert out.tolist() == [3, 1, 0, 0] and ind.tolist() == [1, 1, 1, 1] and ab.tolist() == [3, 1, 1, 1]
+    f = features.graph_features(offs, cols)
+    # out sorted 0,0,1,3: q1 at 0.75 -> 0, median at 1.5 -> 0.5, q3 at 2.25 -> 1.5; mean 1, var 1.5
+    assert f[:8].tolist() == pytest.approx([4, 4, 0, 0, 0.5, 1.5, 3, np.sqrt(1.5)])
+    assert f[8:14].tolist() == [1, 1, 1, 1, 1, 0]
+    # absolute sorted 1,1,1,3: q3 at 2.25 -> 1.5; mean 1.5, var 0.75
+    assert f[14:20].tolist() == pytest.approx([1, 1, 1, 1.5, 3, np.sqrt(0.75)])
+    # a reciprocated pair, a self-loop and a repeated arc: 0->0, 0->1, 0->1, 1->0, 1->2
+    offs = np.array([0, 3, 5, 5], dtype=np.int64)
+    cols = np.array([0, 1, 1, 0, 2], dtype=np.int32)
+    out, ind, ab = features.degrees(offs, cols)
+    # in: v0 from rows 0,1 -> 2; v1 twice from row 0 -> 2; v2 once -> 1
+    assert out.tolist() == [3, 2, 0] and ind.tolist() == [2, 2, 1]
+    # row 0 entries whose reverse exists: 0 (0->0), 1, 1 (1->0): all 3 -> abs 3 + 2 - 3 = 2
+    # row 1 entries: 0 (0->1 exists), 2 (2->1 no) -> 1 -> abs 2 + 2 - 1 = 3; v2: 0 + 1 = 1
+    assert ab.tolist() == [2, 3, 1]
 
 
 def _export(clf, class_kernel):
