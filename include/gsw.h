@@ -16,9 +16,12 @@
  * (Section IV-A), with the paper's rule for undecided leaves.
  *
  * Graph convention: CSR with int64 row offsets and int32 column ids,
- * 1 <= n < 2^31 vertices.  Row v lists the neighbours of v.  Self-loops and
- * repeated entries are tolerated and do not change any result.  Bottom-up
- * (pull) expansion needs every arc (u,v) to have its reverse (v,u).
+ * 1 <= n < 2^31 vertices.  Row v lists the out-neighbours of v (the arcs
+ * v -> u); an undirected graph stores every edge as two arcs.  Self-loops and
+ * repeated entries are tolerated and do not change any result.  A graph whose
+ * arcs do not all have their reverse is directed: the library then also
+ * keeps the transpose (the in-arcs of every vertex), over which the
+ * bottom-up and reverse-edge-list kernels run.
  *
  * Ownership: the caller owns every buffer it passes and the library never
  * frees them.  Objects returned through gsw_*_create are owned by the caller
@@ -37,7 +40,7 @@
 extern "C" {
 #endif
 
-#define GSW_ABI_VERSION 1
+#define GSW_ABI_VERSION 2
 
 typedef enum {
   GSW_OK = 0,
@@ -47,7 +50,7 @@ typedef enum {
   GSW_ERANGE = -4,   /* a result does not fit its type (int8 levels > 127) */
   GSW_EBUSY = -5,    /* no free slot */
   GSW_ENOTREE = -6,  /* tree policy without a tree */
-  GSW_ENOTSYM = -7   /* bottom-up expansion asked for on a non-symmetric graph */
+  GSW_ENOTSYM = -7   /* reserved (bottom-up kernels run on directed graphs over in-arcs) */
 } gsw_status;
 
 /*
@@ -68,31 +71,61 @@ enum {
   GSW_K_PULL_BITMAP = 7,  /* bottom-up, one lane per unvisited vertex, early exit
                              on the first neighbour in the frontier bitmap ("vertex pull") */
   GSW_K_VERTEX_SCAN = 8,  /* vertex push over all n vertices, testing depth == d */
-  GSW_K_EDGE_SCAN = 9,    /* edge list: one lane per arc over all arcs, testing the
-                             depth of the arc's origin (needs the origin array) */
-  GSW_N_KERNELS = 10
+  GSW_K_EDGE_SCAN = 9,    /* edge list: one lane per arc over all arcs in source order,
+                             testing the depth of the arc's origin (needs the origin array) */
+  GSW_K_REV_EDGE_SCAN = 10, /* reverse edge list: one lane per arc over all arcs in
+                             destination order (every vertex's in-arcs), testing the depth
+                             of the arc's source (needs the in-arcs' origin array) */
+  GSW_N_BASE_KERNELS = 11
 };
+
+/*
+ * Frontier-count variants (Section III-A, "Variants"): how the lanes that
+ * discover vertices add them to the next frontier, whose size is the level's
+ * count.  WORKGROUP stages a workgroup's discoveries in LDS and reserves
+ * their queue places with one global atomic per workgroup; WAVE with one per
+ * wavefront (ballot and popcount); THREAD with one per discovering lane.  The
+ * global counters are spread over 8 queue segments in every variant.  A
+ * kernel id combines a base kernel and a variant; the plain GSW_K_* ids are
+ * the WORKGROUP variant.
+ */
+enum { GSW_COUNT_WORKGROUP = 0, GSW_COUNT_WAVE = 1, GSW_COUNT_THREAD = 2, GSW_N_COUNT_VARIANTS = 3 };
+#define GSW_N_KERNELS (GSW_N_BASE_KERNELS * GSW_N_COUNT_VARIANTS)
+#define GSW_KERNEL_ID(base, variant) ((base) + GSW_N_BASE_KERNELS * (variant))
+#define GSW_KERNEL_BASE(k) ((k) % GSW_N_BASE_KERNELS)
+#define GSW_KERNEL_COUNT(k) ((k) / GSW_N_BASE_KERNELS)
 
 /* Kernel used when the tree cannot decide at the first level (Section IV-A:
  * the edge-centric implementation, as the least likely to be very slow). */
 #define GSW_DEFAULT_KERNEL GSW_K_PUSH_EDGE
 
 /* Graph creation flags. */
-#define GSW_ASSUME_SYMMETRIC 0x1u /* skip the symmetry check; caller vouches for it */
+#define GSW_ASSUME_SYMMETRIC 0x1u /* skip the symmetry check; caller vouches that every arc
+                                     has its reverse */
 #define GSW_WITH_ORIGIN 0x2u      /* build the per-arc origin array now, not on first use */
 #define GSW_TRUSTED 0x4u          /* skip validation of offsets and columns */
 
 /*
- * Per-level feature vector fed to the tree (Section IV-A feature list; the
- * paper's best model uses graph size, fraction discovered, the out-degree
- * distribution and the frontier's vertex count, Section IV-B):
- *   0 n vertices            4 degree median          8 frontier vertices n_f(d)
- *   1 arcs (CSR entries)    5 degree third quartile  9 n_f(d) / n
- *   2 degree minimum        6 degree maximum        10 discovered (depths 0..d)
- *   3 degree first quartile 7 degree std (ddof 0)   11 discovered / n
- * Quartiles interpolate linearly between order statistics.
+ * Per-level feature vector fed to the tree (Section IV-A feature list: graph
+ * size, the 5-number summary and standard deviation of the out-, in- and
+ * absolute degrees, frontier size and discovered count, each absolute and as
+ * a fraction of n; the paper's best model uses graph size, fraction
+ * discovered, the out-degree distribution and the frontier's vertex count,
+ * Section IV-B):
+ *    0 n vertices     2.. 7 out-degree {min, Q1, median, Q3, max, std}
+ *    1 arcs (CSR      8..13 in-degree  {min, Q1, median, Q3, max, std}
+ *      entries)      14..19 absolute degree {min, Q1, median, Q3, max, std}
+ *   20 frontier vertices n_f(d)      22 discovered (depths 0..d)
+ *   21 n_f(d) / n                    23 discovered / n
+ * Quartiles interpolate linearly between order statistics; std is the
+ * population one (ddof 0).  The absolute degree of v counts the arcs that
+ * enter or leave v, an arc and its reverse once: out(v) + in(v) minus the
+ * arcs v -> u whose reverse u -> v exists.  On a symmetric graph the three
+ * distributions equal the degree distribution.  Features 0..19 are constant
+ * for a graph.
  */
-#define GSW_N_FEATURES 12
+#define GSW_N_FEATURES 24
+#define GSW_N_GRAPH_FEATURES 20
 
 typedef struct gsw_graph gsw_graph;
 typedef struct gsw_tree gsw_tree;
@@ -101,11 +134,13 @@ typedef struct gsw_tree gsw_tree;
 typedef struct {
   int32_t source_idx;   /* index into the sources array */
   int32_t level;        /* d: this row expanded the depth-d vertices */
-  int32_t kernel;       /* GSW_K_* that ran */
+  int32_t kernel;       /* kernel id (GSW_KERNEL_ID) that ran */
   int32_t flags;        /* bit0: tree leaf undecided, fallback rule applied */
   int64_t n_frontier;   /* n_f(d): vertices at depth d */
   int64_t discovered;   /* vertices at depths 0..d */
   int64_t n_next;       /* vertices found at depth d+1 (0 on the last row) */
+  int64_t e_frontier;   /* e_f(d): arcs leaving the depth-d vertices (sum of their
+                           out-degrees), or -1 unless gsw_bfs_opts.count_arcs */
   float ms;             /* time of this level (device wall clock from its first
                            workgroup's start to its last one's end, both
                            launches of a two-launch push_edge level; see
@@ -131,6 +166,9 @@ typedef struct {
   int32_t max_workgroups;    /* > 0: cap on every level-kernel launch's workgroups (levels
                                 that ask for more stride over their work; results are
                                 the same); 0: the library sizes each launch */
+  int32_t count_arcs;        /* 1: fill gsw_level_trace.e_frontier: the lanes that discover
+                                a vertex add its out-degree to per-level counters (16
+                                more bytes read per discovered vertex) */
   void *stream;              /* hipStream_t for the work; NULL = library stream */
 } gsw_bfs_opts;
 
@@ -160,14 +198,30 @@ gsw_status gsw_graph_create_device(int64_t n, int64_t nnz, const int64_t *d_offs
 
 void gsw_graph_destroy(gsw_graph *g);
 
-/* n, nnz, deg_stats = {min, q1, median, q3, max, std}, device bytes held by
- * the graph (CSR, origin array, BFS workspace).  Any output may be NULL. */
+/* n, nnz, out-degree deg_stats = {min, q1, median, q3, max, std}, device
+ * bytes held by the graph (CSR, transpose of a directed graph, origin
+ * arrays, BFS workspace).  Any output may be NULL. */
 gsw_status gsw_graph_info(const gsw_graph *g, int64_t *n, int64_t *nnz, double deg_stats[6],
                           size_t *dev_bytes);
 
-/* Degree statistics of a host CSR, as used in the feature vector:
+/* 1 when every arc has its reverse (checked, or vouched for with
+ * GSW_ASSUME_SYMMETRIC), else 0. */
+int32_t gsw_graph_symmetric(const gsw_graph *g);
+
+/* Device bytes of the single-source BFS workspace of g (allocated by the
+ * first gsw_bfs or gsw_bfs_profile call and held until gsw_graph_destroy),
+ * whether allocated yet or not: what a server must budget before it runs
+ * single-source queries on g. */
+size_t gsw_graph_workspace_bytes(const gsw_graph *g);
+
+/* Out-degree statistics of a host CSR, as used in the feature vector:
  * {min, q1, median, q3, max, std}.  Host only; needs no GPU. */
 gsw_status gsw_degree_stats(int64_t n, const int64_t *offs, double out[6]);
+
+/* The 20 graph features (see GSW_N_FEATURES: n, arcs, out-, in- and
+ * absolute-degree statistics) of a host CSR.  Host only; needs no GPU. */
+gsw_status gsw_graph_features_host(int64_t n, int64_t nnz, const int64_t *offs, const int32_t *cols,
+                                   double out[GSW_N_GRAPH_FEATURES]);
 
 /* The tree's feature vector (see GSW_N_FEATURES) for a level whose frontier
  * has n_frontier vertices after `discovered` vertices have depths 0..d. */
@@ -187,6 +241,19 @@ gsw_status gsw_tree_create(int32_t n_nodes, int32_t n_classes, const int32_t *fe
                            const double *threshold, const int32_t *left, const int32_t *right,
                            const double *value, const int32_t *class_kernel, gsw_tree **out);
 void gsw_tree_destroy(gsw_tree *t);
+
+/* Reads a tree from the JSON export of a fitted CART tree: an object with
+ * the arrays "feature", "threshold", "left", "right" (one entry per node;
+ * -1 children at leaves), "value" (per node, the class weights) and
+ * "class_kernel" (the kernel id of each class), as gsw_tree_create takes
+ * them.  When the object has "feature_names" it must list this library's
+ * GSW_N_FEATURES feature names in order (guards against a tree trained on
+ * another feature layout).  Other keys are ignored.  GSW_EINVAL on a
+ * malformed file. */
+gsw_status gsw_tree_load(const char *json_path, gsw_tree **out);
+
+/* Name of feature i (as in the JSON export), "?" out of range. */
+const char *gsw_feature_name(int32_t i);
 
 /* Host-side prediction for one feature vector.  An undecided leaf repeats
  * prev_kernel when level > 0 and gives GSW_DEFAULT_KERNEL at level 0
@@ -231,8 +298,8 @@ gsw_status gsw_bfs(const gsw_graph *g, const int32_t *sources, int32_t n_sources
  * BFS advances one level with advance_kernel (or, when advance_kernel < 0,
  * with the fastest kernel just measured).  frontier[level] receives
  * n_f(level).  Stops at max_levels rows (GSW_ERANGE if the BFS is longer).
- * Kernels that cannot run on this graph (pull on a non-symmetric graph) get
- * a time of -1.
+ * Kernels that cannot run (none since directed graphs keep their transpose)
+ * would get a time of -1.
  */
 gsw_status gsw_bfs_profile(const gsw_graph *g, int32_t source, const int32_t *kernels,
                            int32_t n_kernels, int32_t reps, int32_t advance_kernel, float *times,
@@ -247,12 +314,26 @@ typedef struct {
   float push_to_pull;  /* per source: switch it to bottom-up when its frontier's arcs exceed
                           this fraction of the arcs it has not reached yet ... */
   float pull_to_push;  /* ... and back to top-down when they fall below this fraction of all arcs */
-  int32_t device_ptrs; /* 1: levels is device memory; 0: host */
+  int32_t device_ptrs; /* 1: levels (and wide_levels) are device memory; 0: host */
   int32_t graph;       /* 1: replay a captured two-level HIP graph; 0: launch each kernel */
+  int32_t block_size;  /* threads per workgroup of the level kernels: 128, 256 or 512
+                          (0 = 256); an autotuned knob, results do not depend on it */
+  int32_t fallback;    /* 1: sources still running after depth GSW_MSBFS_LEVEL_CAP are
+                          rerun one by one on the int32 single-source path (below);
+                          0: such a batch returns GSW_ERANGE */
+  int32_t *wide_levels;  /* fallback: [wide_cap][n] int32, receives the full hop distances
+                            of the rerun sources, in increasing source index */
+  int32_t *wide_index;   /* fallback: host int32[wide_cap], receives their source indices */
+  int32_t wide_cap;      /* fallback: rows wide_levels has room for */
+  int32_t *n_wide;       /* fallback, may be NULL: receives the number of rerun sources
+                            (GSW_ERANGE when it is above wide_cap) */
+  const gsw_tree *tree;  /* fallback: policy of the rerun (NULL: the default kernel at
+                            every level) */
   void *stream;        /* hipStream_t; NULL = library stream */
 } gsw_msbfs_opts;
 
-/* Fills opts: push_to_pull 0.07, pull_to_push 0.01, graph 1, host pointers. */
+/* Fills opts: push_to_pull 0.07, pull_to_push 0.01, graph 1, block size 256, no
+ * fallback, host pointers. */
 void gsw_msbfs_opts_default(gsw_msbfs_opts *opts);
 
 /*
@@ -266,9 +347,15 @@ void gsw_msbfs_opts_default(gsw_msbfs_opts *opts);
  *   levels    [n_sources][n] int8: hop distance from sources[i], -1 if
  *             unreachable.  Sources may repeat.
  *   n_levels  receives the number of levels run (may be NULL).
- * Returns GSW_ERANGE when some source reaches a depth above
- * GSW_MSBFS_LEVEL_CAP (int8 cannot hold it); levels are then unspecified --
- * run those sources through gsw_bfs instead.
+ * A source still running after discovering depth GSW_MSBFS_LEVEL_CAP has
+ * depths int8 cannot hold.  Without opts->fallback the call then returns
+ * GSW_ERANGE (levels unspecified).  With it, the batch stops at the cap and
+ * every such source is rerun on the single-source path (gsw_bfs with
+ * opts->tree, or the default kernel): its full int32 distances go to the
+ * next row of opts->wide_levels and its index to opts->wide_index, and its
+ * int8 row holds the distance where it is at most GSW_MSBFS_LEVEL_CAP and
+ * INT8_MIN (-128) where it is larger (-1 still means unreachable).  Levels
+ * are never truncated silently.
  */
 gsw_status gsw_msbfs(const gsw_graph *g, const int32_t *sources, int32_t n_sources, int8_t *levels,
                      int32_t *n_levels, const gsw_msbfs_opts *opts);
@@ -294,6 +381,10 @@ gsw_status gsw_msbfs(const gsw_graph *g, const int32_t *sources, int32_t n_sourc
  */
 typedef struct gsw_session gsw_session;
 
+/* Device memory a session of max_slots slots on g allocates (what a server
+ * must budget for it). */
+size_t gsw_session_bytes(const gsw_graph *g, int32_t max_slots);
+
 gsw_status gsw_session_create(const gsw_graph *g, int32_t max_slots, gsw_session **out);
 void gsw_session_destroy(gsw_session *ss);
 
@@ -315,13 +406,23 @@ gsw_status gsw_session_fetch(gsw_session *ss, int32_t slot, int32_t *levels, int
 gsw_status gsw_session_info(const gsw_session *ss, int32_t *slots, int32_t *busy,
                             int64_t *iteration, size_t *dev_bytes);
 
+/* Sets the session's level counter (the iteration that gsw_session_info
+ * reports and new queries record as their start) to `iteration`, in
+ * [0, 2^62].  Only while no query is running and no level is queued
+ * (GSW_EBUSY otherwise); admitted queries that have not started yet and
+ * finished ones that have not been fetched keep their results.  The counter
+ * is 64-bit and never wraps in practice; this call lets a long-lived server
+ * restart the numbering and lets tests start a session at any count. */
+gsw_status gsw_session_rebase(gsw_session *ss, int64_t iteration);
+
 /* Direction thresholds as in gsw_msbfs_opts (defaults 0.07 / 0.01). */
 gsw_status gsw_session_set_thresholds(gsw_session *ss, float push_to_pull, float pull_to_push);
 
 /* ------------------------------------------------------------------ misc */
 
 const char *gsw_last_error(void);
-const char *gsw_kernel_name(int32_t kernel_id); /* "?" for an unknown id */
+const char *gsw_kernel_name(int32_t kernel_id); /* base name, then ".wave" or ".thread" for
+                                                   those count variants; "?" for an unknown id */
 int32_t gsw_abi_version(void);
 
 #ifdef __cplusplus

@@ -39,12 +39,11 @@ constexpr int64_t kSmallFrontier = 4096;
 
 struct Policy {
   const gsw_bfs_opts* o;
-  bool symmetric;
   bool has_origin;
+  bool has_rorigin;
   // Kernel for level d on the host (only level 0 is chosen here); the device
   // applies the same rules to every later level.  *flags gets bit0 when the
-  // tree leaf was undecided, bit1 when a pull choice was replaced on a
-  // non-symmetric graph.
+  // tree leaf was undecided.
   int choose(const gsw_graph* g, int32_t d, int64_t nf, int64_t disc, int prev, int32_t* flags) const {
     *flags = 0;
     int k = GSW_DEFAULT_KERNEL;
@@ -65,19 +64,15 @@ struct Policy {
         break;
       }
     }
-    if (kernel_is_pull(k) && !symmetric) {
-      k = GSW_DEFAULT_KERNEL;
-      *flags |= 2;
-    }
-    if (k == GSW_K_EDGE_SCAN && !has_origin) k = GSW_DEFAULT_KERNEL;
+    if (kernel_base(k) == GSW_K_EDGE_SCAN && !has_origin) k = GSW_DEFAULT_KERNEL;
+    if (kernel_base(k) == GSW_K_REV_EDGE_SCAN && !has_rorigin) k = GSW_DEFAULT_KERNEL;
     return k;
   }
 };
 
 gsw_status check_kernel(const gsw_graph* g, int k) {
+  (void)g;
   if (k < 0 || k >= GSW_N_KERNELS) return fail(GSW_EINVAL, "unknown kernel id %d", k);
-  if (kernel_is_pull(k) && !g->symmetric)
-    return fail(GSW_ENOTSYM, "kernel %s needs a symmetric graph", gsw_kernel_name(k));
   return GSW_OK;
 }
 
@@ -86,8 +81,8 @@ gsw_status check_kernel(const gsw_graph* g, int k) {
 // (constant for the graph) is decided here, with the host's float rounding,
 // so the copy holds only the nodes reachable through splits on the four
 // level features.  Each of those is a non-decreasing function of an integer
-// count c in [0, n] -- the next frontier size (features 8, 9 = c, c/n) or
-// the vertices discovered through the next depth (10, 11) -- so its test,
+// count c in [0, n] -- the next frontier size (features 20, 21 = c, c/n) or
+// the vertices discovered through the next depth (22, 23) -- so its test,
 // float(feature) <= threshold, holds exactly for c <= T; T is found here by
 // bisection with the host's own arithmetic and the device compares counts.
 // The outcome of every walk is unchanged.  Nodes are renumbered in preorder,
@@ -99,7 +94,7 @@ gsw_status ensure_tree(gsw_graph* g, const gsw_tree* t) {
   double gf[GSW_N_FEATURES];
   GSW_TRY(gsw_level_features(g, 0, 0, gf));
   auto resolve = [&](int32_t i) {
-    while (t->left[(size_t)i] != -1 && t->feature[(size_t)i] < 8) {
+    while (t->left[(size_t)i] != -1 && t->feature[(size_t)i] < GSW_N_GRAPH_FEATURES) {
       const double xv = (double)(float)gf[t->feature[(size_t)i]];
       i = xv <= t->threshold[(size_t)i] ? t->left[(size_t)i] : t->right[(size_t)i];
     }
@@ -156,7 +151,7 @@ gsw_status ensure_tree(gsw_graph* g, const gsw_tree* t) {
     const bool leaf = t->left[(size_t)i] == -1;
     const int32_t l = leaf ? -1 : newid[(size_t)resolve(t->left[(size_t)i])];
     const int32_t r = leaf ? -1 : newid[(size_t)resolve(t->right[(size_t)i])];
-    const int32_t count = !leaf && t->feature[(size_t)i] >= 10 ? 1 : 0;  // discovered : frontier
+    const int32_t count = !leaf && t->feature[(size_t)i] >= 22 ? 1 : 0;  // discovered : frontier
     nodes[(size_t)k] = tree_node_pack(l, r, count, t->leaf_kernel[(size_t)i]);
     if (!leaf) thr[(size_t)k] = count_threshold(i);
   }
@@ -188,7 +183,7 @@ gsw_status ensure_schedule(gsw_graph* g, const int32_t* sched, int32_t len) {
   return GSW_OK;
 }
 
-BfsPolicy device_policy(const gsw_graph* g, const gsw_bfs_opts* o, bool has_origin) {
+BfsPolicy device_policy(const gsw_graph* g, const gsw_bfs_opts* o, bool has_origin, bool has_rorigin) {
   BfsPolicy p;
   std::memset(&p, 0, sizeof p);
   p.policy = o->policy;
@@ -196,6 +191,7 @@ BfsPolicy device_policy(const gsw_graph* g, const gsw_bfs_opts* o, bool has_orig
   p.sched_len = o->policy == GSW_POLICY_SCHEDULE ? o->schedule_len : 0;
   p.symmetric = g->symmetric != 0;
   p.has_origin = has_origin ? 1 : 0;
+  p.has_rorigin = has_rorigin ? 1 : 0;
   p.sched = g->ws.d_sched;
   p.t_node = g->ws.d_tree;
   p.t_thr = g->ws.d_thr;
@@ -203,13 +199,16 @@ BfsPolicy device_policy(const gsw_graph* g, const gsw_bfs_opts* o, bool has_orig
   return p;
 }
 
-BfsBase make_base(const gsw_graph* g, int32_t* lv, int32_t* pa, bool timed) {
+BfsBase make_base(const gsw_graph* g, int32_t* lv, int32_t* pa, bool timed, bool count_arcs) {
   const Workspace& w = g->ws;
   BfsBase b;
   std::memset(&b, 0, sizeof b);
   b.offs = g->offs;
   b.cols = g->cols;
   b.origin = g->origin;
+  b.roffs = g->roffs;
+  b.rcols = g->rcols;
+  b.rorigin = g->rorigin;
   b.head = w.head;
   b.level = lv;
   b.parent = pa;
@@ -218,6 +217,7 @@ BfsBase make_base(const gsw_graph* g, int32_t* lv, int32_t* pa, bool timed) {
   b.q[0] = w.q[0];
   b.q[1] = w.q[1];
   b.ctr = w.ctr;
+  b.actr = w.actr;
   b.done = w.done;
   b.scan = w.scan;
   b.ebeg = w.ebeg;
@@ -229,6 +229,7 @@ BfsBase make_base(const gsw_graph* g, int32_t* lv, int32_t* pa, bool timed) {
   b.nnz = g->nnz;
   b.timed = timed ? 1 : 0;
   b.grid_max = level_kernel_grid(g->n, w.nw);
+  b.count_arcs = count_arcs ? 1 : 0;
   return b;
 }
 
@@ -239,6 +240,7 @@ struct Record {
   int64_t nf, disc, next;
   unsigned long long ticks;
   int next_kernel;  // kCtlDone when the search ended
+  int64_t ef;       // arcs of the level's frontier, -1 when not counted
 };
 
 // Waits until level d's record is in the ring.  Polls the stream for errors
@@ -260,6 +262,7 @@ gsw_status wait_record(const gsw_graph* g, int64_t d, hipStream_t s, Record* rec
     rec->next = (int64_t)v[kRecNext];
     rec->ticks = v[kRecTicks];
     rec->next_kernel = (int)v[kRecNextKernel] - 1;
+    rec->ef = (int64_t)v[kRecEf] - 1;
     return true;
   };
   for (uint64_t it = 0;; ++it) {
@@ -285,7 +288,7 @@ gsw_status run_levels(gsw_graph* g, const Policy& pol, const BfsPolicy& dp, int3
   std::memset(w.ring, 0, (size_t)kBfsRing * kBfsRec * sizeof(unsigned long long));
   int32_t flags0 = 0;
   const int k0 = pol.choose(g, 0, 1, 1, GSW_DEFAULT_KERNEL, &flags0);
-  const BfsBase b = make_base(g, lv, pa, timed);
+  const BfsBase b = make_base(g, lv, pa, timed, o->count_arcs != 0);
   GSW_TRY(launch_init(g, b, src, k0, flags0, s));
   int32_t j = 0;     // launches of the level kernel so far
   int ahead = 0;     // of those, not yet used by a level whose record was read
@@ -312,6 +315,7 @@ gsw_status run_levels(gsw_graph* g, const Policy& pol, const BfsPolicy& dp, int3
       t.n_frontier = r.nf;
       t.discovered = r.disc;
       t.n_next = nn;
+      t.e_frontier = r.ef;
       t.ms = timed ? (float)((double)r.ticks * w.tick_ms) : -1.0f;
       t.reserved = 0;
     }
@@ -319,7 +323,9 @@ gsw_status run_levels(gsw_graph* g, const Policy& pol, const BfsPolicy& dp, int3
     ahead -= level_launches(k, r.nf);
     if (nn == 0) break;
     want = kAhead + level_launches(nk, nn) - 1;
-    const bool queue_push = nk != GSW_K_PULL_BITMAP && nk != GSW_K_VERTEX_SCAN && nk != GSW_K_EDGE_SCAN;
+    const int nb = nk >= 0 ? kernel_base(nk) : -1;
+    const bool queue_push = nb != GSW_K_PULL_BITMAP && nb != GSW_K_VERTEX_SCAN && nb != GSW_K_EDGE_SCAN &&
+                            nb != GSW_K_REV_EDGE_SCAN;
     const bool quiet = queue_push && nn <= kSmallFrontier && nn <= 2 * r.nf && d > 0 && r.nf <= 2 * nf_prev &&
                        (r.disc + nn) * 100 >= g->n;
     size = quiet && kSmallLaunch < cap ? kSmallLaunch : cap;
@@ -346,23 +352,78 @@ gsw_status dalloc(DevBuf& b, size_t bytes) {
   return GSW_OK;
 }
 
-// Whether the policy can ever name edge_scan (it needs the origin array).
-bool may_pick_edge_scan(const gsw_bfs_opts* o) {
+// Whether the policy can ever name a kernel of base `base` (the edge lists
+// need their origin arrays).
+bool may_pick(const gsw_bfs_opts* o, int base) {
   switch (o->policy) {
     case GSW_POLICY_FIXED:
-      return o->fixed_kernel == GSW_K_EDGE_SCAN;
+      return kernel_base(o->fixed_kernel) == base;
     case GSW_POLICY_SCHEDULE:
       for (int32_t i = 0; i < o->schedule_len; ++i)
-        if (o->schedule[i] == GSW_K_EDGE_SCAN) return true;
+        if (kernel_base(o->schedule[i]) == base) return true;
       return false;
     default:
       for (int32_t k : o->tree->class_kernel)
-        if (k == GSW_K_EDGE_SCAN) return true;
+        if (kernel_base(k) == base) return true;
       return false;
   }
 }
 
+// The per-source loop of gsw_bfs (the graph's lock held, options checked).
+gsw_status bfs_sources(gsw_graph* g, const gsw_bfs_opts* o, const int32_t* sources, int32_t n_sources,
+                       int32_t* levels, int32_t* parents, gsw_level_trace* trace, int32_t trace_cap,
+                       int32_t* rows) {
+  GSW_HIP(hipSetDevice(g->device));
+  GSW_TRY(ensure_workspace(g));
+  if (may_pick(o, GSW_K_EDGE_SCAN)) GSW_TRY(ensure_origin(g));
+  if (may_pick(o, GSW_K_REV_EDGE_SCAN)) GSW_TRY(ensure_rorigin(g));
+  if (o->policy == GSW_POLICY_TREE) GSW_TRY(ensure_tree(g, o->tree));
+  if (o->policy == GSW_POLICY_SCHEDULE) GSW_TRY(ensure_schedule(g, o->schedule, o->schedule_len));
+  const hipStream_t s = pick_stream(g, o->stream);
+  const bool has_origin = g->origin != nullptr || g->nnz == 0;
+  const bool has_rorigin = g->rorigin != nullptr || g->nnz == 0;
+  const Policy pol{o, has_origin, has_rorigin};
+  const BfsPolicy dp = device_policy(g, o, has_origin, has_rorigin);
+  const int64_t n = g->n;
+  for (int32_t i = 0; i < n_sources; ++i) {
+    int32_t* lv = o->device_ptrs ? levels + (size_t)i * n : g->ws.lvl_tmp;
+    int32_t* pa = parents ? (o->device_ptrs ? parents + (size_t)i * n : g->ws.par_tmp) : nullptr;
+    const gsw_status st = run_levels(g, pol, dp, i, sources[i], lv, pa, trace, trace_cap, rows, s);
+    if (st != GSW_OK) {
+      (void)hipStreamSynchronize(s);
+      return st;
+    }
+    if (!o->device_ptrs) {
+      GSW_HIP(hipMemcpyAsync(levels + (size_t)i * n, lv, (size_t)n * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, s));
+      if (pa)
+        GSW_HIP(hipMemcpyAsync(parents + (size_t)i * n, pa, (size_t)n * sizeof(int32_t),
+                               hipMemcpyDeviceToHost, s));
+    }
+  }
+  GSW_HIP(hipStreamSynchronize(s));
+  return GSW_OK;
+}
+
 }  // namespace
+
+gsw_status bfs_rows_locked(gsw_graph* g, const int32_t* sources, int32_t count, int32_t* d_levels,
+                           const gsw_tree* tree, hipStream_t s) {
+  gsw_bfs_opts o;
+  gsw_bfs_opts_default(&o);
+  if (tree) {
+    o.policy = GSW_POLICY_TREE;
+    o.tree = tree;
+  } else {
+    o.policy = GSW_POLICY_FIXED;
+    o.fixed_kernel = GSW_DEFAULT_KERNEL;
+  }
+  o.device_ptrs = 1;
+  o.stream = s;
+  int32_t rows = 0;
+  return bfs_sources(g, &o, sources, count, d_levels, nullptr, nullptr, 0, &rows);
+}
+
 }  // namespace gsw
 
 using namespace gsw;
@@ -398,34 +459,8 @@ gsw_status gsw_bfs(const gsw_graph* cg, const int32_t* sources, int32_t n_source
       return fail(GSW_EINVAL, "unknown policy %d", o->policy);
   }
   std::lock_guard<std::mutex> lock(g->mu);
-  GSW_HIP(hipSetDevice(g->device));
-  GSW_TRY(ensure_workspace(g));
-  if (may_pick_edge_scan(o)) GSW_TRY(ensure_origin(g));
-  if (o->policy == GSW_POLICY_TREE) GSW_TRY(ensure_tree(g, o->tree));
-  if (o->policy == GSW_POLICY_SCHEDULE) GSW_TRY(ensure_schedule(g, o->schedule, o->schedule_len));
-  const hipStream_t s = pick_stream(g, o->stream);
-  const bool has_origin = g->origin != nullptr || g->nnz == 0;
-  const Policy pol{o, g->symmetric != 0, has_origin};
-  const BfsPolicy dp = device_policy(g, o, has_origin);
-  const int64_t n = g->n;
   int32_t rows = 0;
-  for (int32_t i = 0; i < n_sources; ++i) {
-    int32_t* lv = o->device_ptrs ? levels + (size_t)i * n : g->ws.lvl_tmp;
-    int32_t* pa = parents ? (o->device_ptrs ? parents + (size_t)i * n : g->ws.par_tmp) : nullptr;
-    const gsw_status st = run_levels(g, pol, dp, i, sources[i], lv, pa, trace, trace_cap, &rows, s);
-    if (st != GSW_OK) {
-      (void)hipStreamSynchronize(s);
-      return st;
-    }
-    if (!o->device_ptrs) {
-      GSW_HIP(hipMemcpyAsync(levels + (size_t)i * n, lv, (size_t)n * sizeof(int32_t),
-                             hipMemcpyDeviceToHost, s));
-      if (pa)
-        GSW_HIP(hipMemcpyAsync(parents + (size_t)i * n, pa, (size_t)n * sizeof(int32_t),
-                               hipMemcpyDeviceToHost, s));
-    }
-  }
-  GSW_HIP(hipStreamSynchronize(s));
+  GSW_TRY(bfs_sources(g, o, sources, n_sources, levels, parents, trace, trace_cap, &rows));
   if (trace_len) *trace_len = rows;
   return GSW_OK;
 }
@@ -445,9 +480,12 @@ gsw_status gsw_bfs_profile(const gsw_graph* cg, int32_t source, const int32_t* k
   std::lock_guard<std::mutex> lock(g->mu);
   GSW_HIP(hipSetDevice(g->device));
   GSW_TRY(ensure_workspace(g));
-  for (int32_t i = 0; i < n_kernels; ++i)
-    if (kernels[i] == GSW_K_EDGE_SCAN) GSW_TRY(ensure_origin(g));
-  if (advance_kernel == GSW_K_EDGE_SCAN) GSW_TRY(ensure_origin(g));
+  for (int32_t i = 0; i < n_kernels; ++i) {
+    if (kernel_base(kernels[i]) == GSW_K_EDGE_SCAN) GSW_TRY(ensure_origin(g));
+    if (kernel_base(kernels[i]) == GSW_K_REV_EDGE_SCAN) GSW_TRY(ensure_rorigin(g));
+  }
+  if (advance_kernel >= 0 && kernel_base(advance_kernel) == GSW_K_EDGE_SCAN) GSW_TRY(ensure_origin(g));
+  if (advance_kernel >= 0 && kernel_base(advance_kernel) == GSW_K_REV_EDGE_SCAN) GSW_TRY(ensure_rorigin(g));
   Workspace& w = g->ws;
   const hipStream_t s = pick_stream(g, stream);
   const int64_t n = g->n;
@@ -469,8 +507,9 @@ gsw_status gsw_bfs_profile(const gsw_graph* cg, int32_t source, const int32_t* k
   fo.policy = GSW_POLICY_FIXED;
   fo.fixed_kernel = GSW_DEFAULT_KERNEL;
   const bool has_origin = g->origin != nullptr || g->nnz == 0;
-  const BfsPolicy dp = device_policy(g, &fo, has_origin);
-  const BfsBase b = make_base(g, lv, pa, false);
+  const bool has_rorigin = g->rorigin != nullptr || g->nnz == 0;
+  const BfsPolicy dp = device_policy(g, &fo, has_origin, has_rorigin);
+  const BfsBase b = make_base(g, lv, pa, false, false);
   std::memset(w.ring, 0, (size_t)kBfsRing * kBfsRec * sizeof(unsigned long long));
   GSW_TRY(launch_init(g, b, source, GSW_DEFAULT_KERNEL, 0, s));
   GSW_HIP(hipStreamSynchronize(s));
@@ -534,10 +573,6 @@ gsw_status gsw_bfs_profile(const gsw_graph* cg, int32_t source, const int32_t* k
     GSW_TRY(save());
     for (int32_t ki = 0; ki < n_kernels; ++ki) {
       const int k = kernels[ki];
-      if (kernel_is_pull(k) && !g->symmetric) {
-        times[(size_t)d * n_kernels + ki] = -1.0f;
-        continue;
-      }
       for (int32_t r = 0; r < reps; ++r) {
         GSW_TRY(restore(k));
         GSW_TRY(run(k, true));

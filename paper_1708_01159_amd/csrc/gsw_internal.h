@@ -45,12 +45,20 @@ constexpr int kCtrSlot = kQueueBins * kCtrStride;  // words per level in the cou
 // never treated as unvisited.
 struct BfsCtl;
 
-// Bottom-up probes start from a dense copy of the first kHeadArcs arcs of
-// every row ([n][kHeadArcs], -1 past the row's end): a wave's unvisited
+// Bottom-up probes start from a dense copy of the first kHeadArcs in-arcs of
+// every vertex ([n][kHeadArcs], -1 past the row's end): a wave's unvisited
 // vertices read theirs as consecutive 16-byte records instead of one
 // scattered cache line per row, and only rows still unresolved after them
 // are read in the CSR.
 constexpr int kHeadArcs = 4;
+
+// Per-level arc counters (gsw_bfs_opts.count_arcs): a ring of 4 levels of
+// kQueueBins 64-bit counters, kArcStride words apart.
+constexpr int kArcStride = 16;
+constexpr int kArcSlot = kQueueBins * kArcStride;
+
+__host__ __device__ inline int kernel_base(int k) { return k % GSW_N_BASE_KERNELS; }
+__host__ __device__ inline int kernel_count(int k) { return k / GSW_N_BASE_KERNELS; }
 
 struct Workspace {
   int64_t n = 0, nw = 0;
@@ -58,10 +66,11 @@ struct Workspace {
   unsigned long long* bm[3] = {};        // frontier bitmaps, depth d in bm[d % 3]
   int32_t* q[2] = {};                    // frontier queues, kQueueBins segments of n
   uint32_t* ctr = nullptr;               // ring of 4 levels x kCtrSlot words
+  unsigned long long* actr = nullptr;    // ring of 4 levels x kArcSlot arc counters
   int64_t* scan = nullptr;               // push_edge: per-entry exclusive degree scan
   int64_t* ebeg = nullptr;               // push_edge: row start per queue entry
   int64_t* bsum = nullptr;               // push_edge: per-block sums
-  int32_t* head = nullptr;               // pull: first kHeadArcs arcs of every row
+  int32_t* head = nullptr;               // pull: first kHeadArcs in-arcs of every vertex
   int32_t* lvl_tmp = nullptr;            // levels when the caller passes host memory
   int32_t* par_tmp = nullptr;            // parents when the caller passes host memory
   uint32_t* h_ctr = nullptr;             // pinned host copy of one counter slot
@@ -94,12 +103,18 @@ struct gsw_graph {
   int64_t n = 0, nnz = 0;
   const int64_t* offs = nullptr;  // device
   const int32_t* cols = nullptr;  // device
-  int32_t* origin = nullptr;      // device, built on demand (edge_scan)
-  unsigned long long* iso = nullptr;  // device bitmap of degree-0 vertices (symmetric graphs)
+  int32_t* origin = nullptr;      // device, built on demand (edge_scan): row of every arc
+  // in-arcs (the transpose): the same arrays as offs/cols on a symmetric
+  // graph, a library-owned copy on a directed one
+  const int64_t* roffs = nullptr;
+  const int32_t* rcols = nullptr;
+  int32_t* rorigin = nullptr;     // device, built on demand (rev_edge_scan): row of every in-arc
+  unsigned long long* iso = nullptr;  // device bitmap of vertices without in-arcs
   bool owns_csr = false;
   int symmetric = 0;              // 1 when checked or vouched for
-  double deg_stats[6] = {};       // min, q1, median, q3, max, std
-  size_t csr_bytes = 0, origin_bytes = 0;
+  double deg_stats[6] = {};       // out-degree: min, q1, median, q3, max, std
+  double gfeat[GSW_N_GRAPH_FEATURES] = {};  // graph features of the tree
+  size_t csr_bytes = 0, origin_bytes = 0, rcsr_bytes = 0;
   gsw::Workspace ws;
   gsw::MsWorkspace* ms = nullptr; // batched BFS workspace, sized for the largest batch seen
   // batched BFS: rows longer than the chunked-row limit as (vertex << 32 |
@@ -134,6 +149,7 @@ struct BfsCtl {
   int32_t grid;              // workgroups that run this launch of level d (the rest exit)
   unsigned long long t_begin;  // wall clock at the start of the running level (timed levels)
   long long etot;              // push_edge: arcs of the frontier (set by the prefix launch)
+  long long ef;                // arcs of the depth-d frontier (count_arcs), else -1
 };
 // Workgroups count themselves finished, together with the queue entries they
 // appended, in kDoneGroups 64-bit counters (by index modulo kDoneGroups,
@@ -148,10 +164,10 @@ constexpr int32_t kCtlDone = -1;
 // (every workgroup scans the whole queue in LDS); a larger one takes two.
 constexpr int64_t kEdgeFuse = 512;
 __host__ __device__ inline int32_t level_first_phase(int kernel, int64_t nf) {
-  return kernel == GSW_K_PUSH_EDGE ? (nf <= kEdgeFuse ? 2 : 0) : 0;
+  return kernel >= 0 && kernel_base(kernel) == GSW_K_PUSH_EDGE ? (nf <= kEdgeFuse ? 2 : 0) : 0;
 }
 __host__ __device__ inline int level_launches(int kernel, int64_t nf) {
-  return kernel == GSW_K_PUSH_EDGE && nf > kEdgeFuse ? 2 : 1;
+  return kernel >= 0 && kernel_base(kernel) == GSW_K_PUSH_EDGE && nf > kEdgeFuse ? 2 : 1;
 }
 
 // How the device picks the next level's kernel (a kernel argument): the same
@@ -159,7 +175,7 @@ __host__ __device__ inline int level_launches(int kernel, int64_t nf) {
 struct BfsPolicy {
   int32_t policy, fixed, sched_len, symmetric;
   int32_t has_origin;        // edge_scan can run (its origin array exists)
-  int32_t pad;
+  int32_t has_rorigin;       // rev_edge_scan can run (the in-arcs' origin array exists)
   const int32_t* sched;      // device copy of the schedule
   const unsigned long long* t_node;  // tree nodes, packed (see tree_node_pack)
   const int32_t* t_thr;      // per node: the split holds when its count is <= t_thr
@@ -172,13 +188,17 @@ struct BfsBase {
   const int64_t* offs;
   const int32_t* cols;
   const int32_t* origin;
-  const int32_t* head;             // first kHeadArcs arcs of every row, -1 padded
+  const int64_t* roffs;            // in-arcs (== offs/cols on a symmetric graph)
+  const int32_t* rcols;
+  const int32_t* rorigin;
+  const int32_t* head;             // first kHeadArcs in-arcs of every vertex, -1 padded
   int32_t* level;
   int32_t* parent;                 // may be null
   unsigned long long* vis;
   unsigned long long* bm[3];
   int32_t* q[2];
   uint32_t* ctr;
+  unsigned long long* actr;        // arc counters (count_arcs)
   unsigned long long* done;        // kDoneGroups workgroup counters, kCtrStride words apart
   int64_t* scan;                   // push_edge: block-local exclusive arc offsets per queue entry
   int64_t* ebeg;                   // push_edge: row start per queue entry
@@ -188,12 +208,15 @@ struct BfsBase {
   int64_t n, nw, nnz;
   int32_t timed;                   // record each level's duration
   int32_t grid_max;                // workgroups of a level-kernel launch
+  int32_t count_arcs;              // accumulate the next frontier's out-degrees
+  int32_t pad;
 };
 
 // A tree node in 8 bytes for the device walk: left and right child (int16,
 // -1 at a leaf), the count the split tests (0: next frontier size,
 // 1: vertices discovered through the next depth), leaf kernel + 1 (0 when
-// the leaf's classes tie).  Trees of up to 32767 nodes.
+// the leaf's classes tie; kernel ids fit the byte).  Trees of up to 32767
+// nodes.
 inline unsigned long long tree_node_pack(int32_t left, int32_t right, int32_t count, int32_t leaf_kernel) {
   return (unsigned long long)(uint16_t)(int16_t)left | ((unsigned long long)(uint16_t)(int16_t)right << 16) |
          ((unsigned long long)(uint8_t)count << 32) | ((unsigned long long)(uint8_t)(leaf_kernel + 1) << 40);
@@ -215,7 +238,8 @@ enum : int {
   kRecNext = 4,     // size of the depth-(d+1) frontier
   kRecTicks = 5,    // wall-clock ticks of the level (timed levels)
   kRecNextKernel = 6,  // kernel chosen for level d+1, plus one (0: none)
-  kBfsRecWords = 7
+  kRecEf = 7,          // arcs of the depth-d frontier plus one (0: not counted)
+  kBfsRecWords = 8
 };
 constexpr unsigned long long kRecValueMask = (1ull << 48) - 1ull;
 // Never zero (the cleared ring) and different for the 8 levels sharing a slot.
@@ -240,14 +264,23 @@ int32_t level_participants(int kernel, int64_t n_in, const BfsBase& b);
 gsw_status launch_isolated(const gsw_graph* g, unsigned long long* iso, hipStream_t s);
 gsw_status launch_canonical_parents(const gsw_graph* g, const int32_t* level, int32_t* parent,
                                     hipStream_t s);
-gsw_status launch_build_origin(const gsw_graph* g, int32_t* origin, hipStream_t s);
+gsw_status launch_build_origin(const int64_t* offs, int64_t n, int32_t* origin, hipStream_t s);
 gsw_status launch_build_head(const gsw_graph* g, int32_t* head, hipStream_t s);
 
 gsw_status ensure_workspace(gsw_graph* g);
+size_t workspace_bytes(const gsw_graph* g);  // what ensure_workspace allocates in all
 gsw_status ensure_origin(gsw_graph* g);
+gsw_status ensure_rorigin(gsw_graph* g);
+// Single-source BFS rows [count][n] int32 into device memory, with the graph's
+// lock already held (the batched path's fallback); policy from tree (NULL:
+// the default kernel at every level).
+gsw_status bfs_rows_locked(gsw_graph* g, const int32_t* sources, int32_t count, int32_t* d_levels,
+                           const gsw_tree* tree, hipStream_t s);
 hipStream_t pick_stream(gsw_graph* g, void* user_stream);
 
 bool kernel_is_pull(int k);
+// The kernel of base `base` and the count variant of k.
+inline int kernel_with_base(int k, int base) { return base + GSW_N_BASE_KERNELS * kernel_count(k); }
 void ms_release(gsw_graph* g);
 
 

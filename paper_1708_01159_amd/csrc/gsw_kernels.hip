@@ -27,16 +27,19 @@
 // vertices already visited (a stale read only costs an atomic, because bits
 // are only ever set).
 //
-// Appends are staged per workgroup in LDS (one LDS atomic per wavefront and
-// round) and flushed with one global atomic per workgroup into the queue
-// segment of its bin; a workgroup whose stage fills up appends further rounds
-// directly, one atomic per wavefront.  (The paper compared a global atomic
-// per thread with warp- and block-level reductions, Section III-A
-// "Variants"; here the aggregation is per workgroup because same-address
-// atomics serialise.)  Producer grids are persistent (at most kMaxGrid
+// Appends to the next frontier come in the paper's three count variants
+// (Section III-A, "Variants"), part of the kernel id: WORKGROUP stages a
+// workgroup's appends in LDS (one LDS atomic per wavefront and round) and
+// flushes them with one global atomic per workgroup into the queue segment
+// of its bin (a workgroup whose stage fills up appends further rounds
+// directly, one atomic per wavefront); WAVE reserves places with one global
+// atomic per wavefront and round; THREAD with one per discovering lane.
+// Same-address atomics serialise, so every variant spreads its counters over
+// kQueueBins segments.  Producer grids are persistent (at most kMaxGrid
 // workgroups, grid-stride loops) so that few workgroups flush.
 #include <hip/hip_runtime.h>
 
+#include "gsw_device.h"
 #include "gsw_internal.h"
 
 namespace gsw {
@@ -61,7 +64,10 @@ struct Args {
   const int64_t* __restrict__ offs;
   const int32_t* __restrict__ cols;
   const int32_t* __restrict__ origin;
-  const int32_t* __restrict__ head;  // first kHeadArcs arcs of every row, -1 padded
+  const int64_t* __restrict__ roffs;   // in-arcs (the same arrays as offs/cols when symmetric)
+  const int32_t* __restrict__ rcols;
+  const int32_t* __restrict__ rorigin;
+  const int32_t* __restrict__ head;  // first kHeadArcs in-arcs of every vertex, -1 padded
   int32_t* __restrict__ level;
   int32_t* __restrict__ parent;
   u64* vis;
@@ -73,6 +79,8 @@ struct Args {
   int32_t* __restrict__ qout;
   uint32_t* cout;
   uint32_t* cclr;
+  u64* aout;         // arc counters of the next frontier (count_arcs)
+  u64* aclr;         // those of the level after next, zeroed here
   BfsCtl* ctl;       // this launch's control slot
   BfsCtl* ctl_next;  // the next launch's
   u64* done;
@@ -82,6 +90,8 @@ struct Args {
   int32_t set_nx;  // top-down kernels set the discovered vertices' bits in nx
   int32_t timed;
   int32_t grid;    // workgroups taking part in the level (grid-stride loops use it)
+  int32_t cv;      // count variant (GSW_COUNT_*)
+  int32_t count_arcs;
 };
 
 __host__ __device__ inline Args make_args(const BfsBase& b, int32_t j, int32_t d, uint32_t n_in, int32_t set_nx,
@@ -90,6 +100,9 @@ __host__ __device__ inline Args make_args(const BfsBase& b, int32_t j, int32_t d
   a.offs = b.offs;
   a.cols = b.cols;
   a.origin = b.origin;
+  a.roffs = b.roffs;
+  a.rcols = b.rcols;
+  a.rorigin = b.rorigin;
   a.head = b.head;
   a.level = b.level;
   a.parent = b.parent;
@@ -102,6 +115,8 @@ __host__ __device__ inline Args make_args(const BfsBase& b, int32_t j, int32_t d
   a.qout = b.q[(d + 1) & 1];
   a.cout = b.ctr + (size_t)((d + 1) & 3) * kCtrSlot;
   a.cclr = b.ctr + (size_t)((d + 2) & 3) * kCtrSlot;
+  a.aout = b.actr + (size_t)((d + 1) & 3) * kArcSlot;
+  a.aclr = b.actr + (size_t)((d + 2) & 3) * kArcSlot;
   a.ctl = b.ctl + (j & 1);
   a.ctl_next = b.ctl + ((j + 1) & 1);
   a.done = b.done;
@@ -113,6 +128,8 @@ __host__ __device__ inline Args make_args(const BfsBase& b, int32_t j, int32_t d
   a.set_nx = set_nx;
   a.timed = b.timed;
   a.grid = grid;
+  a.cv = 0;
+  a.count_arcs = b.count_arcs;
   return a;
 }
 
@@ -123,10 +140,11 @@ __host__ __device__ inline int64_t div_up(int64_t x, int64_t y) { return (x + y 
 // for the all-vertex and all-arc ones, the whole launch for pull.
 __host__ __device__ inline int32_t level_grid(int k, int64_t n_in, const BfsBase& b) {
   int64_t need;
-  switch (k) {
+  switch (kernel_base(k)) {
     case GSW_K_PULL_BITMAP: need = b.grid_max; break;
     case GSW_K_VERTEX_SCAN: need = div_up(b.n, kBlock); break;
-    case GSW_K_EDGE_SCAN: need = div_up(b.nnz, kBlock); break;
+    case GSW_K_EDGE_SCAN:
+    case GSW_K_REV_EDGE_SCAN: need = div_up(b.nnz, kBlock); break;
     case GSW_K_PUSH_EDGE:  // its prefix launch, or every workgroup when fused
       need = level_first_phase(k, n_in) == 2 ? (int64_t)b.grid_max : div_up(n_in, kScanTile);
       break;
@@ -150,9 +168,12 @@ __device__ __forceinline__ void level_begin(const Args& a) {
     __hip_atomic_store(&a.ctl->t_begin, (u64)wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Zero the counter slot that the level after next appends to.
+// Zero the counter slots that the level after next appends to.
 __device__ __forceinline__ void clear_ahead(const Args& a) {
-  if (blockIdx.x == 0 && threadIdx.x < kQueueBins) a.cclr[threadIdx.x * kCtrStride] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x < kQueueBins) {
+    a.cclr[threadIdx.x * kCtrStride] = 0u;
+    a.aclr[threadIdx.x * kArcStride] = 0ull;
+  }
 }
 
 // Zero the frontier bitmap of the level after next, spread over every
@@ -206,6 +227,7 @@ __device__ __forceinline__ int32_t queue_at(const Args& a, const QueueIn& q, uin
 // ---------------------------------------------------------- queue output
 struct alignas(16) Stage {
   int32_t buf[kStage];  // also the last workgroup's copy of the tree (16-byte nodes first)
+  u64 arcs;        // out-degrees of the workgroup's discoveries (count_arcs)
   uint32_t n;      // entries reserved (may exceed kStage once it overflowed)
   uint32_t valid;  // reservations at or past this position went to global memory
   uint32_t base;
@@ -215,18 +237,35 @@ __device__ __forceinline__ void stage_init(Stage& s) {
   if (threadIdx.x == 0) {
     s.n = 0u;
     s.valid = kStage;
+    s.arcs = 0ull;
   }
   __syncthreads();
 }
 
-// Appends the winning lanes' vertices.  Called by every active lane of the
-// wave with the same control flow; no workgroup barrier inside.
+// Appends the winning lanes' vertices to the next frontier in the level's
+// count variant.  Called by every active lane of the wave with the same
+// control flow; no workgroup barrier inside.
 __device__ __forceinline__ void stage_push(Stage& s, const Args& a, bool win, int32_t v) {
+  if (a.count_arcs && win) atomicAdd(&s.arcs, (u64)(a.offs[v + 1] - a.offs[v]));
   const u64 m = __ballot(win);
   if (m == 0ull) return;
   const int lane = lane_id();
+  uint32_t* ctr = a.cout + my_bin() * kCtrStride;
+  int32_t* seg = a.qout + (int64_t)my_bin() * a.n;
+  if (a.cv == GSW_COUNT_THREAD) {  // one global atomic per discovering lane
+    if (win) seg[atomicAdd(ctr, 1u)] = v;
+    return;
+  }
   const int leader = __ffsll((long long)m) - 1;
   const uint32_t k = (uint32_t)__popcll(m);
+  const uint32_t r = (uint32_t)__popcll(m & lanes_below(lane));
+  if (a.cv == GSW_COUNT_WAVE) {  // one global atomic per wavefront
+    uint32_t pos = 0;
+    if (lane == leader) pos = atomicAdd(ctr, k);
+    pos = (uint32_t)__shfl((int)pos, leader);
+    if (win) seg[pos + r] = v;
+    return;
+  }
   uint32_t pos = 0;
   if (lane == leader) {
     pos = atomicAdd(&s.n, k);
@@ -236,12 +275,11 @@ __device__ __forceinline__ void stage_push(Stage& s, const Args& a, bool win, in
     }
   }
   pos = (uint32_t)__shfl((int)pos, leader);
-  const uint32_t r = (uint32_t)__popcll(m & lanes_below(lane));
   if (win) {
     if (pos < (uint32_t)kStage)
       s.buf[pos + r] = v;
     else
-      a.qout[(int64_t)my_bin() * a.n + (pos - (uint32_t)kStage) + r] = v;
+      seg[(pos - (uint32_t)kStage) + r] = v;
   }
 }
 
@@ -282,10 +320,32 @@ __device__ __forceinline__ void reset_finished(const Args& a) {
   if (threadIdx.x == 0) a.ctl->done = 0ull;
 }
 
+// Sum over the queue bins (or arc bins) of a level's 32-bit (64-bit)
+// counters, read at the device's coherence point by the launch's last
+// workgroup once every other one has counted itself finished.
+__device__ __forceinline__ u64 sum_bins32(uint32_t* c) {
+  u64 t = 0ull;
+#pragma unroll
+  for (int b = 0; b < kQueueBins; ++b) t += (u64)atomicAdd(c + b * kCtrStride, 0u);
+  return t;
+}
+__device__ __forceinline__ u64 sum_bins64(u64* c) {
+  u64 t = 0ull;
+#pragma unroll
+  for (int b = 0; b < kQueueBins; ++b) t += atomicAdd(c + b * kArcStride, 0ull);
+  return t;
+}
+
 // The staged entries' flush and the finish count in one step: thread 0 issues the queue
 // reservation and the count together (the level's end needs only the
-// count; the entries are read by the next launch).  Every thread calls it;
-// returns (in every thread) whether this is the launch's last workgroup.
+// count; the entries are read by the next launch).  In the WAVE and THREAD
+// variants the workgroup's appends went to the bin counters already (their
+// atomics returned before the barrier), so the count carries none and the
+// last workgroup sums the bin counters instead.  With count_arcs the
+// workgroup's arc sum goes to its bin's arc counter, acknowledged before
+// the finish count.  Every thread calls it; returns (in every thread)
+// whether this is the launch's last workgroup, and *total holds the next
+// frontier's size there.
 __device__ __forceinline__ bool stage_flush_finish(Stage& s, const Args& a, u64* total) {
   __shared__ u64 s_total;
   __shared__ uint32_t s_last;
@@ -294,8 +354,14 @@ __device__ __forceinline__ bool stage_flush_finish(Stage& s, const Args& a, u64*
     const uint32_t cnt = s.n < s.valid ? s.n : s.valid;
     s.valid = cnt;
     const uint32_t base = cnt ? atomicAdd(a.cout + my_bin() * kCtrStride, cnt) : 0u;
+    if (a.count_arcs && s.arcs) {
+      atomicAdd(a.aout + my_bin() * kArcStride, s.arcs);
+      __builtin_amdgcn_s_waitcnt(0);  // performed before this workgroup counts itself finished
+    }
     u64 tot = 0ull;
-    s_last = count_finished(a, s.n, &tot) ? 1u : 0u;
+    const bool last = count_finished(a, s.n, &tot);
+    if (last && a.cv != GSW_COUNT_WORKGROUP) tot = sum_bins32(a.cout);
+    s_last = last ? 1u : 0u;
     s_total = tot;
     s.base = base;
   }
@@ -377,19 +443,16 @@ __device__ __forceinline__ int32_t tree_step(u64 nd, int32_t thr, int32_t nf, in
 }
 
 // Kernel for a tree leaf (-1: undecided, repeat prev, the previous level's
-// kernel) or any other policy's pick, after the fixups every choice gets:
-// bottom-up needs a symmetric graph, edge_scan the origin array.
+// kernel) or any other policy's pick, after the fixup every choice gets:
+// the edge lists need their origin arrays.
 __device__ __forceinline__ int choose_leaf(const BfsPolicy& p, int k, int prev, int32_t* flags) {
   *flags = 0;
   if (k < 0) {
     k = prev;
     *flags |= 1;
   }
-  if (k == GSW_K_PULL_BITMAP && !p.symmetric) {
-    k = GSW_DEFAULT_KERNEL;
-    *flags |= 2;
-  }
-  if (k == GSW_K_EDGE_SCAN && !p.has_origin) k = GSW_DEFAULT_KERNEL;
+  if (kernel_base(k) == GSW_K_EDGE_SCAN && !p.has_origin) k = GSW_DEFAULT_KERNEL;
+  if (kernel_base(k) == GSW_K_REV_EDGE_SCAN && !p.has_rorigin) k = GSW_DEFAULT_KERNEL;
   return k;
 }
 
@@ -543,10 +606,11 @@ __device__ __forceinline__ void level_end(const Args& a, const BfsBase* base, co
   }
   const int32_t d = a.d;
   const long long nf = c->nf, disc = disc0;
+  const long long ef_next = a.count_arcs ? (long long)sum_bins64(a.aout) : -1;
   u64* r = ring + (size_t)(d % kBfsRing) * kBfsRec;
   const u64 tag = rec_tag(d);
   const u64 rec[kBfsRecWords] = {(u64)k_run, (u64)c->flags, (u64)nf, (u64)disc, (u64)nn, ticks & kRecValueMask,
-                              (u64)(next + 1)};
+                              (u64)(next + 1), (u64)(c->ef + 1) & kRecValueMask};
 #pragma unroll
   for (int i = 0; i < kBfsRecWords; ++i)
     __hip_atomic_store(r + i, tag | rec[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -562,6 +626,7 @@ __device__ __forceinline__ void level_end(const Args& a, const BfsBase* base, co
   cn->t_begin = 0ull;
   cn->grid = next >= 0 ? level_grid(next, (int64_t)nn, *base) : 1;
   cn->etot = 0;
+  cn->ef = ef_next;
 }
 
 // ---------------------------------------------------------------- init
@@ -619,8 +684,10 @@ __global__ void __launch_bounds__(kBlock) k_init(BfsBase b, const u64* __restric
     c->t_begin = 0ull;
     c->grid = level_grid(k0, 1, b);
     c->etot = 0;
+    c->ef = b.count_arcs ? (long long)(b.offs[s + 1] - b.offs[s]) : -1;
   }
   if (gid < 4 * kCtrSlot) b.ctr[gid] = gid == 0 ? 1u : 0u;
+  if (gid < 4 * kArcSlot) b.actr[gid] = 0ull;
   if (gid < kDoneGroups) b.done[gid * kCtrStride] = 0ull;
 }
 
@@ -928,6 +995,7 @@ __device__ __forceinline__ void edge_prefix_end(const Args& a, const BfsBase& b,
     cn->t_begin = __hip_atomic_load(&c->t_begin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     cn->grid = (int32_t)(chunks < 1 ? 1 : (chunks < b.grid_max ? chunks : b.grid_max));
     cn->etot = run;
+    cn->ef = c->ef;
   }
 }
 
@@ -1065,9 +1133,10 @@ __device__ __forceinline__ bool body_edge_fused(Args& a, Stage& st, const QueueI
 // A wave takes kPullChunk visited words (512 vertices) at a time and puts
 // their unvisited vertices on its lanes, 64 per round, in vertex order: a
 // level with few unvisited vertices costs one short round per 512 vertices
-// instead of one dependent load chain per 64.  Each lane looks for a
-// neighbour of its vertex in the frontier bitmap, in row order, and stops at
-// the first one (Section III-A, vertex pull).  Phase 1: every lane probes the
+// instead of one dependent load chain per 64.  Each lane looks for an
+// in-neighbour of its vertex (a u with an arc u -> v; on a symmetric graph
+// any neighbour) in the frontier bitmap, in row order, and stops at the
+// first one (Section III-A, vertex pull).  Phase 1: every lane probes the
 // first kHeadArcs neighbours of its row from the dense head copy (the lanes'
 // records are consecutive, so most vertices, which find a frontier
 // neighbour among their first few, never touch their CSR row), then, if
@@ -1084,22 +1153,6 @@ __device__ __forceinline__ u64 readlane64(u64 x, int i) {
   return ((u64)hi << 32) | lo;
 }
 
-// Position of the k-th (from 0) set bit of m; k < popcount(m).
-__device__ __forceinline__ int nth_set_bit(u64 m, int k) {
-  int pos = 0;
-  int c = __popc((unsigned)m);
-  if (k >= c) { k -= c; m >>= 32; pos += 32; }
-  c = __popc((unsigned)(m & 0xffffull));
-  if (k >= c) { k -= c; m >>= 16; pos += 16; }
-  c = __popc((unsigned)(m & 0xffull));
-  if (k >= c) { k -= c; m >>= 8; pos += 8; }
-  c = __popc((unsigned)(m & 0xfull));
-  if (k >= c) { k -= c; m >>= 4; pos += 4; }
-  c = __popc((unsigned)(m & 0x3ull));
-  if (k >= c) { k -= c; m >>= 2; pos += 2; }
-  if (k >= (int)(m & 1ull)) pos += 1;
-  return pos;
-}
 
 __device__ __forceinline__ void body_pull(const Args& a, Stage& st, u64 (*s_found)[kPullChunk]) {
   const int lane = lane_id();
@@ -1175,15 +1228,15 @@ __device__ __forceinline__ void body_pull(const Args& a, Stage& st, u64 (*s_foun
       // unresolved longer rows: the next kPullEager arcs with independent loads
       constexpr int kProbed = kHeadArcs + kPullEager;
       if (mine && par < 0 && hu[kHeadArcs - 1] >= 0) {
-        beg = a.offs[v];
-        end = a.offs[v + 1];
+        beg = a.roffs[v];
+        end = a.roffs[v + 1];
       }
       if (mine && par < 0 && end - beg > kHeadArcs) {
         int32_t u[kPullEager];
         u64 fw[kPullEager];
 #pragma unroll
         for (int q = 0; q < kPullEager; ++q)
-          u[q] = beg + kHeadArcs + q < end ? a.cols[beg + kHeadArcs + q] : -1;
+          u[q] = beg + kHeadArcs + q < end ? a.rcols[beg + kHeadArcs + q] : -1;
 #pragma unroll
         for (int q = 0; q < kPullEager; ++q) fw[q] = u[q] >= 0 ? a.fr[u[q] >> 6] : 0ull;
 #pragma unroll
@@ -1202,7 +1255,7 @@ __device__ __forceinline__ void body_pull(const Args& a, Stage& st, u64 (*s_foun
           int32_t x = -1;
           bool h = false;
           if (e < hi) {
-            x = a.cols[e];
+            x = a.rcols[e];
             h = (a.fr[x >> 6] >> (x & 63)) & 1ull;
           }
           const u64 hm = __ballot(h);
@@ -1272,6 +1325,32 @@ __device__ __forceinline__ void body_edge_scan(const Args& a, Stage& st) {
   }
 }
 
+// ------------------------------- rev_edge_scan (lane / arc, destination order)
+// The reverse edge list (Section III-A): a lane per arc of the in-arc lists,
+// whose rows are the arcs' destinations.  A lane whose destination v is
+// still unvisited (the visited word of consecutive lanes is mostly the same)
+// tests the depth of the arc's source u and, when it is d, claims v.
+__device__ __forceinline__ void body_rev_edge_scan(const Args& a, Stage& st) {
+  const int64_t stride = (int64_t)a.grid * kBlock;
+  const int64_t rounds = (a.nnz + stride - 1) / stride;
+  int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  for (int64_t r = 0; r < rounds; ++r, e += stride) {
+    bool win = false;
+    int32_t v = 0;
+    if (e < a.nnz) {
+      v = a.rorigin[e];
+      if (!((a.vis[v >> 6] >> (v & 63)) & 1ull)) {
+        const int32_t u = a.rcols[e];
+        if (a.level[u] == a.d) {
+          win = claim(a.vis, v);
+          if (win) settle(a, v, u);
+        }
+      }
+    }
+    stage_push(st, a, win, v);
+  }
+}
+
 // ------------------------------------------------ one level, any variant
 // Launch j of a search runs what control slot j % 2 names: level ctl->d with
 // kernel ctl->kernel (push_edge: its scan or, in the next launch, its
@@ -1291,11 +1370,12 @@ __global__ void __launch_bounds__(kBlock) k_level_auto(BfsBase b, BfsPolicy p, i
   __shared__ LevelLds lds;
   const uint32_t cpre = counters_prefetch(b.ctr);
   const BfsCtl* c = b.ctl + (j & 1);
-  const int k = c->kernel;
-  if (k < 0 || k >= GSW_N_KERNELS) {
+  const int k_id = c->kernel;  // the kernel id the level runs (base kernel and count variant)
+  if (k_id < 0 || k_id >= GSW_N_KERNELS) {
     if (blockIdx.x == 0 && threadIdx.x == 0) b.ctl[(j + 1) & 1].kernel = kCtlDone;
     return;
   }
+  const int k = kernel_base(k_id);
   const int32_t d = c->d;
   // the launch may be smaller than the level asks for: its workgroups then
   // stride over the work
@@ -1304,12 +1384,13 @@ __global__ void __launch_bounds__(kBlock) k_level_auto(BfsBase b, BfsPolicy p, i
   if (phase != 1 && d > 0) clear_bitmap(b.bm[(d + 2) % 3], b.nw);  // k_init zeroed it for level 0
   if ((int32_t)blockIdx.x >= grid) return;  // not needed for this launch (grid <= the launch)
   Args a = make_args(b, j, d, 0u, 1, grid);
+  a.cv = kernel_count(k_id);
   if (phase != 1) {
     level_begin(a);
     clear_ahead(a);
   }
   stage_init(st);
-  if (k != GSW_K_PULL_BITMAP && k != GSW_K_VERTEX_SCAN && k != GSW_K_EDGE_SCAN) {
+  if (k != GSW_K_PULL_BITMAP && k != GSW_K_VERTEX_SCAN && k != GSW_K_EDGE_SCAN && k != GSW_K_REV_EDGE_SCAN) {
     queue_in_load(cpre, d & 3, qi);
     a.n_in = qi.pre[kQueueBins];
   }
@@ -1323,7 +1404,7 @@ __global__ void __launch_bounds__(kBlock) k_level_auto(BfsBase b, BfsPolicy p, i
     const TreeLanes tl = tree_prefetch(p);
     u64 total = 0ull;
     const bool last = stage_flush_finish(st, a, &total);
-    level_end(a, &b, p, b.ring, k, st.buf, (int)sizeof(st.buf), tl, last, total);
+    level_end(a, &b, p, b.ring, k_id, st.buf, (int)sizeof(st.buf), tl, last, total);
     return;
   }
   switch (k) {
@@ -1340,15 +1421,17 @@ __global__ void __launch_bounds__(kBlock) k_level_auto(BfsBase b, BfsPolicy p, i
     }
     case GSW_K_PULL_BITMAP: body_pull(a, st, lds.found); break;
     case GSW_K_VERTEX_SCAN: body_vertex_scan(a, st, lds.lr); break;
+    case GSW_K_REV_EDGE_SCAN: body_rev_edge_scan(a, st); break;
     default: body_edge_scan(a, st); break;
   }
   const TreeLanes tl = tree_prefetch(p);
   u64 total = 0ull;
   const bool last = stage_flush_finish(st, a, &total);
-  level_end(a, &b, p, b.ring, k, st.buf, (int)sizeof(st.buf), tl, last, total);
+  level_end(a, &b, p, b.ring, k_id, st.buf, (int)sizeof(st.buf), tl, last, total);
 }
 
 // ------------------------------------------------------------ helpers
+// Bit v set when v has no in-arcs (only a source can reach depth 0 there).
 __global__ void __launch_bounds__(kBlock) k_isolated(const int64_t* __restrict__ offs,
                                                      u64* __restrict__ iso, int64_t n, int64_t nw) {
   const int lane = lane_id();
@@ -1378,6 +1461,8 @@ __global__ void __launch_bounds__(kBlock) k_build_head(const int64_t* __restrict
   }
 }
 
+// parent[v] = the smallest u with an arc u -> v one level up (rows of the
+// in-arcs, any order).
 __global__ void __launch_bounds__(kBlock) k_canonical_parents(const int64_t* __restrict__ offs,
                                                               const int32_t* __restrict__ cols,
                                                               const int32_t* __restrict__ level,
@@ -1423,7 +1508,7 @@ int32_t level_kernel_grid(int64_t n, int64_t nw) {
   return (int32_t)persistent_grid(pull_blocks > vert_blocks ? pull_blocks : vert_blocks);
 }
 
-bool kernel_is_pull(int k) { return k == GSW_K_PULL_BITMAP; }
+bool kernel_is_pull(int k) { return k >= 0 && kernel_base(k) == GSW_K_PULL_BITMAP; }
 
 gsw_status launch_init(const gsw_graph* g, const BfsBase& b, int32_t source, int32_t k0, int32_t flags0,
                        hipStream_t s) {
@@ -1445,8 +1530,8 @@ gsw_status launch_level_auto(const gsw_graph* g, const BfsBase& b, const BfsPoli
 }
 
 gsw_status launch_build_head(const gsw_graph* g, int32_t* head, hipStream_t s) {
-  hipLaunchKernelGGL(k_build_head, dim3(persistent_grid(cdiv(g->n, kBlock))), dim3(kBlock), 0, s, g->offs,
-                     g->cols, reinterpret_cast<int4*>(head), g->n);
+  hipLaunchKernelGGL(k_build_head, dim3(persistent_grid(cdiv(g->n, kBlock))), dim3(kBlock), 0, s, g->roffs,
+                     g->rcols, reinterpret_cast<int4*>(head), g->n);
   GSW_HIP(hipGetLastError());
   return GSW_OK;
 }
@@ -1454,7 +1539,7 @@ gsw_status launch_build_head(const gsw_graph* g, int32_t* head, hipStream_t s) {
 gsw_status launch_isolated(const gsw_graph* g, unsigned long long* iso, hipStream_t s) {
   const int64_t nw = (g->n + 63) / 64;
   hipLaunchKernelGGL(k_isolated, dim3(persistent_grid(cdiv(nw, kWaves))), dim3(kBlock), 0, s,
-                     g->offs, iso, g->n, nw);
+                     g->roffs, iso, g->n, nw);
   GSW_HIP(hipGetLastError());
   return GSW_OK;
 }
@@ -1462,14 +1547,13 @@ gsw_status launch_isolated(const gsw_graph* g, unsigned long long* iso, hipStrea
 gsw_status launch_canonical_parents(const gsw_graph* g, const int32_t* level, int32_t* parent,
                                     hipStream_t s) {
   hipLaunchKernelGGL(k_canonical_parents, dim3((unsigned)cdiv(g->n, kBlock)), dim3(kBlock), 0, s,
-                     g->offs, g->cols, level, parent, g->n);
+                     g->roffs, g->rcols, level, parent, g->n);
   GSW_HIP(hipGetLastError());
   return GSW_OK;
 }
 
-gsw_status launch_build_origin(const gsw_graph* g, int32_t* origin, hipStream_t s) {
-  hipLaunchKernelGGL(k_build_origin, dim3((unsigned)cdiv(g->n * 64, kBlock)), dim3(kBlock), 0, s,
-                     g->offs, origin, g->n);
+gsw_status launch_build_origin(const int64_t* offs, int64_t n, int32_t* origin, hipStream_t s) {
+  hipLaunchKernelGGL(k_build_origin, dim3((unsigned)cdiv(n * 64, kBlock)), dim3(kBlock), 0, s, offs, origin, n);
   GSW_HIP(hipGetLastError());
   return GSW_OK;
 }

@@ -37,6 +37,7 @@
 #include <cstring>
 #include <vector>
 
+#include "gsw_device.h"
 #include "gsw_internal.h"
 
 namespace gsw {
@@ -44,8 +45,9 @@ namespace {
 
 typedef unsigned long long u64;
 
-constexpr int kMsBlock = 256;
-constexpr int kMsMaxGrid = 2048;
+constexpr int kMsBlock = 256;     // workgroup size of the helper kernels, default of the level kernels
+constexpr int kMsMaxBlock = 512;  // level kernels: 128, 256 or 512 threads (gsw_msbfs_opts.block_size)
+constexpr int kMsMaxWaves = 8192; // level kernels: wavefronts per launch at most
 constexpr int kMsStats = 8;        // stat counters, spread like the queue bins
 constexpr int kMsStatStride = 32;  // u64 words between counters
 constexpr int kMsLong = 32;        // rows longer than this are walked by the whole wave
@@ -73,7 +75,7 @@ struct MsCtl {
   double to_push;        // top-down again once frontier arcs < to_push x all arcs
   u64 arcs;              // arcs of the graph
   int32_t any_push, any_pull;
-  int32_t d;             // this level's index
+  long long d;           // this level's index (a session counts levels for as long as it lives)
   int32_t pull_ok;       // bottom-up allowed (symmetric graph)
   int32_t nslots, W;
   uint8_t pull[kMaxSlots];    // per source: expanded bottom-up at its last level
@@ -100,7 +102,7 @@ struct MsArgs {
   // reached), level = d + 1 - start[slot] where d is the session's iteration
   // (null for the batch)
   int32_t* dist;
-  const int32_t* start;
+  const long long* start;
   MsCtl* ctl;
   int64_t n;
   int32_t W, B;  // words per vertex, level bytes per vertex
@@ -115,22 +117,6 @@ __device__ __forceinline__ u64 valid_bits(int j, int W, int B) {
   return (1ull << (B & 63)) - 1ull;
 }
 
-// Position of the k-th (from 0) set bit of m; k < popcount(m).
-__device__ __forceinline__ int nth_set_bit(u64 m, int k) {
-  int pos = 0;
-  int c = __popc((unsigned)m);
-  if (k >= c) { k -= c; m >>= 32; pos += 32; }
-  c = __popc((unsigned)(m & 0xffffull));
-  if (k >= c) { k -= c; m >>= 16; pos += 16; }
-  c = __popc((unsigned)(m & 0xffull));
-  if (k >= c) { k -= c; m >>= 8; pos += 8; }
-  c = __popc((unsigned)(m & 0xfull));
-  if (k >= c) { k -= c; m >>= 4; pos += 4; }
-  c = __popc((unsigned)(m & 0x3ull));
-  if (k >= c) { k -= c; m >>= 2; pos += 2; }
-  if (k >= (int)(m & 1ull)) pos += 1;
-  return pos;
-}
 
 // 8 bits -> 8 bytes holding 0x01 where the bit is set.
 __device__ __forceinline__ u64 bits_to_bytes(u64 c) {
@@ -142,13 +128,13 @@ __device__ __forceinline__ u64 bits_to_bytes(u64 c) {
 
 // Levels d+1 for the sources in `m` (word j) at vertex v.  Only v's group
 // writes v's levels, so the batch's 8-byte read-modify-writes need no atomics.
-__device__ __forceinline__ void write_levels(const MsArgs& a, int d, int64_t v, int j, u64 m) {
+__device__ __forceinline__ void write_levels(const MsArgs& a, long long d, int64_t v, int j, u64 m) {
   if (a.dist) {
     while (m) {
       const int b = __ffsll((long long)m) - 1;
       m &= m - 1ull;
       const int slot = j * 64 + b;
-      a.dist[(int64_t)slot * a.n + v] = d + 2 - a.start[slot];
+      a.dist[(int64_t)slot * a.n + v] = (int32_t)(d + 2 - a.start[slot]);
     }
     return;
   }
@@ -217,8 +203,8 @@ __device__ __forceinline__ Wave wave_of(int G) {
   w.gi = w.lane / G;
   w.gpw = 64 / G;
   w.gmask = G == 64 ? ~0ull : (((1ull << G) - 1ull) << (w.gi * G));
-  w.wave = ((int64_t)blockIdx.x * kMsBlock + threadIdx.x) >> 6;
-  w.nwaves = ((int64_t)gridDim.x * kMsBlock) >> 6;
+  w.wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  w.nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   return w;
 }
 
@@ -314,7 +300,7 @@ __device__ __forceinline__ void push_arcs(const MsArgs& a, u64 f, int j, int64_t
 
 // Every frontier vertex u of a top-down source: lane j pushes
 // fr[u][j] & pmask[j] along u's arcs.
-__global__ void __launch_bounds__(kMsBlock) k_ms_push(MsArgs a, int G) {
+__global__ void __launch_bounds__(kMsMaxBlock) k_ms_push(MsArgs a, int G) {
   if (!a.ctl->any_push) return;
   const Wave w = wave_of(G);
   const int j = w.j;
@@ -376,17 +362,17 @@ __global__ void __launch_bounds__(kMsBlock) k_ms_push(MsArgs a, int G) {
 // with new bits and their degrees, per source the degree sum of its new
 // frontier (each source's direction is steered by it), and the OR of the new
 // frontier masks.
-__global__ void __launch_bounds__(kMsBlock) k_ms_level(MsArgs a, int G) {
+__global__ void __launch_bounds__(kMsMaxBlock) k_ms_level(MsArgs a, int G) {
   __shared__ u64 s_ef[kMaxSlots];
   const Wave w = wave_of(G);
   const int j = w.j;
   const bool lane_live = j < a.W;
   const MsCtl* ctl = a.ctl;
-  const int d = ctl->d;
+  const long long d = ctl->d;
   const bool any_push = ctl->any_push != 0, any_pull = ctl->any_pull != 0;
   const u64 qm = lane_live ? ctl->qmask[j] : 0ull;
   const int nslots = a.W * 64;
-  for (int k = threadIdx.x; k < nslots; k += kMsBlock) s_ef[k] = 0ull;
+  for (int k = threadIdx.x; k < nslots; k += blockDim.x) s_ef[k] = 0ull;
   __syncthreads();
   u64 nv = 0, ne = 0, act = 0;
   const int64_t nwords = (a.n + 63) / 64;
@@ -481,7 +467,7 @@ __global__ void __launch_bounds__(kMsBlock) k_ms_level(MsArgs a, int G) {
   add_active(a, j, act);
   __syncthreads();
   u64* row = a.slot_ef + (size_t)(blockIdx.x % kMsStats) * kMaxSlots;
-  for (int k = threadIdx.x; k < nslots; k += kMsBlock)
+  for (int k = threadIdx.x; k < nslots; k += blockDim.x)
     if (s_ef[k]) atomicAdd(row + k, s_ef[k]);
 }
 
@@ -499,7 +485,8 @@ __global__ void __launch_bounds__(256) k_ms_finalize(MsCtl* ctl, u64* stats, u64
   __shared__ u64 s_act[kMaxWords], s_p[kMaxWords], s_q[kMaxWords];
   __shared__ u64 s_v, s_e;
   const int t = threadIdx.x;
-  const int W = ctl->W, nslots = ctl->nslots, d = ctl->d;
+  const int W = ctl->W, nslots = ctl->nslots;
+  const long long d = ctl->d;
   if (t < kMaxWords) {
     u64 x = 0ull;
     if (t < W)
@@ -648,6 +635,11 @@ __global__ void k_ss_seed(u64* vis, u64* fr, u64* fbm, int32_t* dist, MsCtl* ctl
   ctl->any_push = 1;
 }
 
+// Sets a session's level counter (in stream order with its levels).
+__global__ void k_ss_set_level(MsCtl* ctl, long long d) {
+  if (threadIdx.x == 0) ctl->d = d;
+}
+
 // Direction thresholds of a session, in stream order with its levels.
 __global__ void k_ss_thresholds(MsCtl* ctl, double to_pull, double to_push) {
   if (threadIdx.x == 0) {
@@ -674,10 +666,11 @@ inline int group_lanes(int W) {
   return G;  // W <= 16 -> G <= 16
 }
 
-// One wave per 64-vertex word for one pass, at most kMsMaxGrid blocks.
-inline unsigned ms_grid(int64_t n) {
-  const int64_t blocks = cdiv(cdiv(n, 64), kMsBlock / 64);
-  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks, kMsMaxGrid));
+// One wave per 64-vertex word for one pass, at most kMsMaxWaves waves, in
+// workgroups of bs threads.
+inline unsigned ms_grid(int64_t n, int bs = kMsBlock) {
+  const int64_t blocks = cdiv(cdiv(n, 64), bs / 64);
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks, (int64_t)kMsMaxWaves * 64 / bs));
 }
 
 // Spread statistics counters, the level control block and the host ring of
@@ -689,6 +682,12 @@ struct LevelStats {
   u64 *ring = nullptr, *d_ring = nullptr;  // mapped host memory (kRing records)
   size_t bytes = 0;
 };
+
+// Device bytes of a traversal's statistics counters and control block.
+size_t stats_bytes() {
+  return (size_t)kMsStats * kMsStatStride * sizeof(u64) + (size_t)kMsStats * kMaxWords * sizeof(u64) +
+         (size_t)kMsStats * kMaxSlots * sizeof(u64) + sizeof(MsCtl);
+}
 
 gsw_status stats_alloc(LevelStats* st) {
   const size_t sb = (size_t)kMsStats * kMsStatStride * sizeof(u64);
@@ -802,7 +801,7 @@ gsw_status ensure_heavy(gsw_graph* g) {
 // Queues one level: the top-down pass (it returns at once when no source
 // pushes), the bottom-up + update pass and the finalize kernel.  The
 // statistics pointers of the arguments are taken from `st`.
-gsw_status launch_ms_level(MsArgs a, const LevelStats& st, int G, hipStream_t s) {
+gsw_status launch_ms_level(MsArgs a, const LevelStats& st, int G, int bs, hipStream_t s) {
   a.stats = st.stats;
   a.active = st.active;
   a.slot_ef = st.slot_ef;
@@ -814,11 +813,12 @@ gsw_status launch_ms_level(MsArgs a, const LevelStats& st, int G, hipStream_t s)
   for (const void* p : need)
     if (!p) return fail(GSW_EINVAL, "batched level launched with a missing buffer");
   if ((!a.dist && !a.lev) || (a.dist && !a.start) || (a.n_heavy > 0 && !a.heavy) || a.W < 1 ||
-      a.W > kMaxWords || a.B != 64 * a.W || G < a.W || G > 16 || (G & (G - 1)) != 0)
+      a.W > kMaxWords || a.B != 64 * a.W || G < a.W || G > 16 || (G & (G - 1)) != 0 ||
+      (bs != 128 && bs != 256 && bs != 512))
     return fail(GSW_EINVAL, "batched level launched with inconsistent arguments");
-  const unsigned grid = ms_grid(a.n);
-  hipLaunchKernelGGL(k_ms_push, dim3(grid), dim3(kMsBlock), 0, s, a, G);
-  hipLaunchKernelGGL(k_ms_level, dim3(grid), dim3(kMsBlock), 0, s, a, G);
+  const unsigned grid = ms_grid(a.n, bs);
+  hipLaunchKernelGGL(k_ms_push, dim3(grid), dim3(bs), 0, s, a, G);
+  hipLaunchKernelGGL(k_ms_level, dim3(grid), dim3(bs), 0, s, a, G);
   hipLaunchKernelGGL(k_ms_finalize, dim3(1), dim3(256), 0, s, st.ctl, st.stats, st.active, st.slot_ef,
                      st.d_ring);
   return GSW_OK;
@@ -829,6 +829,7 @@ gsw_status launch_ms_level(MsArgs a, const LevelStats& st, int G, hipStream_t s)
 struct MsWorkspace {
   int64_t n = 0;
   int W = 0, B = 0;
+  int bs = 0;  // block size the captured graph was made with
   u64 *vis = nullptr, *fr = nullptr, *frn = nullptr, *nx = nullptr;
   u64* bms = nullptr;  // 3 bitmaps of ceil(n/64) words: frontier (two) and touched
   int8_t* lev = nullptr;
@@ -919,13 +920,18 @@ MsArgs ms_args(const gsw_graph* g, const MsWorkspace* m, bool odd) {
   return a;
 }
 
-// Captures the even and the odd level as one graph (once per workspace).
-gsw_status ms_capture(gsw_graph* g, MsWorkspace* m, int G) {
-  if (m->exec) return GSW_OK;
+// Captures the even and the odd level as one graph (once per workspace and
+// block size).
+gsw_status ms_capture(gsw_graph* g, MsWorkspace* m, int G, int bs) {
+  if (m->exec && m->bs == bs) return GSW_OK;
+  if (m->exec) (void)hipGraphExecDestroy(m->exec);
+  if (m->graph) (void)hipGraphDestroy(m->graph);
+  m->exec = nullptr;
+  m->graph = nullptr;
   if (!m->cap) GSW_HIP(hipStreamCreateWithFlags(&m->cap, hipStreamNonBlocking));
   GSW_HIP(hipStreamBeginCapture(m->cap, hipStreamCaptureModeRelaxed));
-  gsw_status ls = launch_ms_level(ms_args(g, m, false), m->st, G, m->cap);
-  if (ls == GSW_OK) ls = launch_ms_level(ms_args(g, m, true), m->st, G, m->cap);
+  gsw_status ls = launch_ms_level(ms_args(g, m, false), m->st, G, bs, m->cap);
+  if (ls == GSW_OK) ls = launch_ms_level(ms_args(g, m, true), m->st, G, bs, m->cap);
   const hipError_t e1 = hipGetLastError();
   hipGraph_t graph = nullptr;
   const hipError_t e2 = hipStreamEndCapture(m->cap, &graph);
@@ -942,7 +948,19 @@ gsw_status ms_capture(gsw_graph* g, MsWorkspace* m, int G) {
   }
   m->graph = graph;
   m->exec = exec;
+  m->bs = bs;
   return GSW_OK;
+}
+
+// int32 distances -> int8 row: the distance where it fits, INT8_MIN where it
+// is above the int8 cap, -1 where unreachable.
+__global__ void __launch_bounds__(kMsBlock) k_ms_narrow(const int32_t* __restrict__ wide, int8_t* __restrict__ row,
+                                                         int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * kMsBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kMsBlock + threadIdx.x; i < n; i += stride) {
+    const int32_t x = wide[i];
+    row[i] = (int8_t)(x > GSW_MSBFS_LEVEL_CAP ? -128 : x);
+  }
 }
 }  // namespace
 
@@ -966,6 +984,7 @@ void gsw_msbfs_opts_default(gsw_msbfs_opts* o) {
   o->push_to_pull = 0.07f;
   o->pull_to_push = 0.01f;
   o->graph = 1;
+  o->block_size = kMsBlock;
 }
 
 gsw_status gsw_msbfs(const gsw_graph* cg, const int32_t* sources, int32_t n_sources, int8_t* levels,
@@ -982,6 +1001,12 @@ gsw_status gsw_msbfs(const gsw_graph* cg, const int32_t* sources, int32_t n_sour
   for (int32_t i = 0; i < n_sources; ++i)
     if (sources[i] < 0 || sources[i] >= g->n)
       return fail(GSW_EINVAL, "source %d (index %d) out of [0, %lld)", sources[i], i, (long long)g->n);
+  const int bs = o->block_size == 0 ? kMsBlock : o->block_size;
+  if (bs != 128 && bs != 256 && bs != 512) return fail(GSW_EINVAL, "block_size %d: 128, 256 or 512", o->block_size);
+  if (o->fallback && o->n_wide) *o->n_wide = 0;
+  if (o->fallback && o->wide_cap < 0) return fail(GSW_EINVAL, "wide_cap %d is negative", o->wide_cap);
+  if (o->fallback && o->wide_cap > 0 && (!o->wide_levels || !o->wide_index))
+    return fail(GSW_EINVAL, "fallback with room for %d rows needs wide_levels and wide_index", o->wide_cap);
   std::lock_guard<std::mutex> lock(g->mu);
   GSW_HIP(hipSetDevice(g->device));
   const int W = (n_sources + 63) / 64;
@@ -991,7 +1016,7 @@ gsw_status gsw_msbfs(const gsw_graph* cg, const int32_t* sources, int32_t n_sour
   const int B = W * 64;  // level bytes per vertex in the workspace
   const int G = group_lanes(W);
   const int64_t nw = cdiv(g->n, 64);
-  if (o->graph) GSW_TRY(ms_capture(g, m, G));
+  if (o->graph) GSW_TRY(ms_capture(g, m, G, bs));
   // the ring must not hold records of an earlier call with the same level numbers
   std::memset(m->st.ring, 0, (size_t)kRing * kRecWords * sizeof(u64));
   std::vector<u64> first((size_t)W, 0ull);
@@ -1016,6 +1041,7 @@ gsw_status gsw_msbfs(const gsw_graph* cg, const int32_t* sources, int32_t n_sour
   constexpr int64_t kAhead = 2;
   int64_t queued = 0, d = 0;
   gsw_status st = GSW_OK;
+  std::vector<int32_t> wide;  // fallback: indices of the sources past the cap
   for (;;) {
     while (queued - d < kAhead) {
       if (o->graph) {
@@ -1025,7 +1051,7 @@ gsw_status gsw_msbfs(const gsw_graph* cg, const int32_t* sources, int32_t n_sour
         }
         queued += 2;
       } else {
-        st = launch_ms_level(ms_args(g, m, (queued & 1) != 0), m->st, G, s);
+        st = launch_ms_level(ms_args(g, m, (queued & 1) != 0), m->st, G, bs, s);
         if (st != GSW_OK) break;
         queued += 1;
       }
@@ -1037,11 +1063,23 @@ gsw_status gsw_msbfs(const gsw_graph* cg, const int32_t* sources, int32_t n_sour
     if (st != GSW_OK) break;
     if (rec[1] == 0) break;  // level d found nothing: d + 1 levels ran
     if (d + 1 > GSW_MSBFS_LEVEL_CAP) {
-      st = fail(GSW_ERANGE, "a source reaches depth %lld > %d (int8 levels)", (long long)d + 1,
-                GSW_MSBFS_LEVEL_CAP);
+      if (!o->fallback) {
+        st = fail(GSW_ERANGE, "a source reaches depth %lld > %d (int8 levels)", (long long)d + 1,
+                  GSW_MSBFS_LEVEL_CAP);
+        break;
+      }
+      // the sources that found vertices at depth cap + 1 are rerun in int32
+      for (int32_t i = 0; i < n_sources; ++i)
+        if ((rec[kRecActive + (i >> 6)] >> (i & 63)) & 1ull) wide.push_back(i);
       break;
     }
     ++d;
+  }
+  if (st == GSW_OK && !wide.empty()) {
+    if (o->n_wide) *o->n_wide = (int32_t)wide.size();
+    if ((int32_t)wide.size() > o->wide_cap)
+      st = fail(GSW_ERANGE, "%zu sources reach depths above %d, wide_levels has room for %d", wide.size(),
+                GSW_MSBFS_LEVEL_CAP, o->wide_cap);
   }
   if (st != GSW_OK) {
     (void)hipStreamSynchronize(s);
@@ -1061,6 +1099,35 @@ gsw_status gsw_msbfs(const gsw_graph* cg, const int32_t* sources, int32_t n_sour
   hipLaunchKernelGGL(k_ms_transpose, dim3((unsigned)cdiv(g->n, kTr), (unsigned)cdiv(n_sources, kTr)),
                      dim3(256), 0, s, (const int8_t*)m->lev, out, g->n, B, n_sources);
   if (hipGetLastError() != hipSuccess) st = fail(GSW_EHIP, "transpose launch failed");
+  if (st == GSW_OK && !wide.empty()) {
+    // the rerun, into the caller's rows (device) or a staging buffer (host)
+    const size_t wb = wide.size() * (size_t)g->n * sizeof(int32_t);
+    int32_t* dw = o->wide_levels;
+    int32_t* wtmp = nullptr;
+    if (!o->device_ptrs) {
+      if (hipMalloc((void**)&wtmp, wb) != hipSuccess) {
+        (void)hipGetLastError();
+        st = fail(GSW_ENOMEM, "hipMalloc(%zu) for the int32 rerun failed", wb);
+      }
+      dw = wtmp;
+    }
+    std::vector<int32_t> wsrc(wide.size());
+    for (size_t k = 0; k < wide.size(); ++k) wsrc[k] = sources[wide[k]];
+    if (st == GSW_OK) st = bfs_rows_locked(g, wsrc.data(), (int32_t)wide.size(), dw, o->tree, s);
+    for (size_t k = 0; st == GSW_OK && k < wide.size(); ++k) {
+      hipLaunchKernelGGL(k_ms_narrow, dim3((unsigned)std::min<int64_t>(cdiv(g->n, kMsBlock), 4096)), dim3(kMsBlock),
+                         0, s, (const int32_t*)(dw + k * g->n), out + (size_t)wide[k] * g->n, g->n);
+      if (hipGetLastError() != hipSuccess) st = fail(GSW_EHIP, "narrowing launch failed");
+      o->wide_index[k] = wide[k];
+    }
+    if (st == GSW_OK && wtmp &&
+        hipMemcpyAsync(o->wide_levels, wtmp, wb, hipMemcpyDeviceToHost, s) != hipSuccess)
+      st = fail(GSW_EHIP, "copying the int32 rerun to the host failed");
+    if (wtmp) {
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(wtmp);
+    }
+  }
   if (st == GSW_OK && tmp) {
     if (hipMemcpyAsync(levels, tmp, (size_t)n_sources * g->n, hipMemcpyDeviceToHost, s) != hipSuccess)
       st = fail(GSW_EHIP, "copying levels to the host failed");
@@ -1080,7 +1147,8 @@ struct gsw_session {
   u64* bms = nullptr;     // frontier bitmaps (depth d, d+1) and the touched bitmap
   u64* fbm[2] = {};       // fbm[0] pairs with fr, fbm[1] with frn (swapped together)
   u64* masks = nullptr;   // clr[kMaxWords] then set[kMaxWords]
-  int32_t *dist = nullptr, *start_d = nullptr, *seed = nullptr;  // seed: src[slots] then slot[slots]
+  int32_t *dist = nullptr, *seed = nullptr;  // seed: src[slots] then slot[slots]
+  long long* start_d = nullptr;             // start level of every slot (device)
   int32_t* take = nullptr;  // device staging for fetches into host memory
   LevelStats st;
   // pinned staging for the per-boundary uploads (masks; seed src/slot; start
@@ -1091,8 +1159,8 @@ struct gsw_session {
   static constexpr int kStage = 4;
   u64* h_masks = nullptr;    // [kStage][2 kMaxWords]
   int32_t* h_seed = nullptr;   // [kStage][2 slots]
-  int32_t* h_start = nullptr;  // [kStage][slots]
-  std::vector<int32_t> start32;  // start level of every slot, as uploaded
+  long long* h_start = nullptr;  // [kStage][slots]
+  std::vector<long long> start_up;  // start level of every slot, as uploaded
   std::vector<int32_t> source;
   std::vector<int64_t> start;  // level at which a running slot was seeded
   std::vector<int8_t> state;   // 0 free, 1 admitted (seeded at the next level boundary), 2 running, 3 finished
@@ -1126,6 +1194,16 @@ void ss_free(gsw_session* ss) {
 
 extern "C" {
 
+size_t gsw_session_bytes(const gsw_graph* g, int32_t max_slots) {
+  if (!g || max_slots < 1 || max_slots > GSW_MSBFS_MAX_SOURCES) return 0;
+  const int64_t n = g->n;
+  const size_t W = (size_t)(max_slots + 63) / 64;
+  const size_t words = (size_t)cdiv(n, 64);
+  return 4 * (size_t)n * W * sizeof(u64) + 3 * words * sizeof(u64) + 2 * (size_t)kMaxWords * sizeof(u64) +
+         (size_t)max_slots * n * sizeof(int32_t) + (size_t)max_slots * sizeof(long long) +
+         2 * (size_t)max_slots * sizeof(int32_t) + (size_t)n * sizeof(int32_t) + stats_bytes();
+}
+
 gsw_status gsw_session_create(const gsw_graph* cg, int32_t max_slots, gsw_session** out) {
   clear_error();
   if (!out) return fail(GSW_EINVAL, "out is null");
@@ -1158,7 +1236,7 @@ gsw_status gsw_session_create(const gsw_graph* cg, int32_t max_slots, gsw_sessio
                {(void**)&ss->bms, bb},
                {(void**)&ss->masks, 2 * (size_t)kMaxWords * sizeof(u64)},
                {(void**)&ss->dist, (size_t)max_slots * n * sizeof(int32_t)},
-               {(void**)&ss->start_d, (size_t)max_slots * sizeof(int32_t)},
+               {(void**)&ss->start_d, (size_t)max_slots * sizeof(long long)},
                {(void**)&ss->seed, 2 * (size_t)max_slots * sizeof(int32_t)},
                {(void**)&ss->take, (size_t)n * sizeof(int32_t)}};
   for (auto& it : items) {
@@ -1180,7 +1258,7 @@ gsw_status gsw_session_create(const gsw_graph* cg, int32_t max_slots, gsw_sessio
                       hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&ss->h_seed, gsw_session::kStage * 2 * (size_t)max_slots * sizeof(int32_t),
                       hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&ss->h_start, gsw_session::kStage * (size_t)max_slots * sizeof(int32_t),
+        hipHostMalloc((void**)&ss->h_start, gsw_session::kStage * (size_t)max_slots * sizeof(long long),
                       hipHostMallocDefault) != hipSuccess)
       st = fail(GSW_EHIP, "session stream or pinned staging memory");
   }
@@ -1201,7 +1279,7 @@ gsw_status gsw_session_create(const gsw_graph* cg, int32_t max_slots, gsw_sessio
     ss_free(ss);
     return st;
   }
-  ss->start32.assign((size_t)max_slots, 0);
+  ss->start_up.assign((size_t)max_slots, 0);
   ss->source.assign((size_t)max_slots, -1);
   ss->start.assign((size_t)max_slots, 0);
   ss->state.assign((size_t)max_slots, 0);
@@ -1244,7 +1322,7 @@ gsw_status ss_queue_level(gsw_session* ss, bool* queued_one) {
   const int si = (int)(ss->queued % gsw_session::kStage);
   u64* h_masks = ss->h_masks + (size_t)si * 2 * kMaxWords;
   int32_t* h_seed = ss->h_seed + (size_t)si * 2 * ss->slots;
-  int32_t* h_start = ss->h_start + (size_t)si * ss->slots;
+  long long* h_start = ss->h_start + (size_t)si * ss->slots;
   {
     std::lock_guard<std::mutex> lock(ss->mu);
     u64* clr = h_masks;
@@ -1255,7 +1333,7 @@ gsw_status ss_queue_level(gsw_session* ss, bool* queued_one) {
         clr[k >> 6] |= 1ull << (k & 63);
         h_seed[c] = ss->source[(size_t)k];
         h_seed[ss->slots + c] = k;
-        ss->start32[(size_t)k] = (int32_t)ss->queued;
+        ss->start_up[(size_t)k] = (long long)ss->queued;
         ss->start[(size_t)k] = ss->queued;
         ss->state[(size_t)k] = 2;
         ++c;
@@ -1275,9 +1353,9 @@ gsw_status ss_queue_level(gsw_session* ss, bool* queued_one) {
                        (const u64*)(ss->masks + kMaxWords));
   }
   if (c > 0) {
-    std::memcpy(h_start, ss->start32.data(), (size_t)ss->slots * sizeof(int32_t));
+    std::memcpy(h_start, ss->start_up.data(), (size_t)ss->slots * sizeof(long long));
     GSW_HIP(hipMemcpyAsync(ss->seed, h_seed, 2 * (size_t)ss->slots * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    GSW_HIP(hipMemcpyAsync(ss->start_d, h_start, ss->slots * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    GSW_HIP(hipMemcpyAsync(ss->start_d, h_start, ss->slots * sizeof(long long), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_ss_seed, dim3((unsigned)cdiv(c, 256)), dim3(256), 0, s, ss->vis, ss->fr, ss->fbm[0],
                        ss->dist, ss->st.ctl, n, W, (const int32_t*)ss->seed, (const int32_t*)(ss->seed + ss->slots),
                        c);
@@ -1308,7 +1386,7 @@ gsw_status ss_queue_level(gsw_session* ss, bool* queued_one) {
   a.n = n;
   a.W = W;
   a.B = W * 64;
-  GSW_TRY(launch_ms_level(a, ss->st, group_lanes(W), s));
+  GSW_TRY(launch_ms_level(a, ss->st, group_lanes(W), kMsBlock, s));
   GSW_HIP(hipGetLastError());
   std::swap(ss->fr, ss->frn);
   std::swap(ss->fbm[0], ss->fbm[1]);
@@ -1400,6 +1478,28 @@ gsw_status gsw_session_info(const gsw_session* css, int32_t* slots, int32_t* bus
   }
   if (iteration) *iteration = ss->done;
   if (dev_bytes) *dev_bytes = ss->bytes;
+  return GSW_OK;
+}
+
+gsw_status gsw_session_rebase(gsw_session* ss, int64_t iteration) {
+  clear_error();
+  if (!ss) return fail(GSW_EINVAL, "session is null");
+  if (iteration < 0 || iteration > ((int64_t)1 << 62))
+    return fail(GSW_EINVAL, "iteration %lld out of [0, 2^62]", (long long)iteration);
+  std::lock_guard<std::mutex> step_lock(ss->step_mu);
+  std::lock_guard<std::mutex> lock(ss->mu);
+  for (int k = 0; k < ss->slots; ++k)
+    if (ss->state[(size_t)k] == 2) return fail(GSW_EBUSY, "slot %d is running", k);
+  if (ss->queued != ss->done) return fail(GSW_EBUSY, "levels are still queued");
+  GSW_HIP(hipSetDevice(ss->g->device));
+  GSW_HIP(hipStreamSynchronize(ss->stream));
+  // records of earlier levels must not be mistaken for those of the new numbering
+  std::memset(ss->st.ring, 0, (size_t)kRing * kRecWords * sizeof(u64));
+  hipLaunchKernelGGL(k_ss_set_level, dim3(1), dim3(64), 0, ss->stream, ss->st.ctl, (long long)iteration);
+  GSW_HIP(hipGetLastError());
+  GSW_HIP(hipStreamSynchronize(ss->stream));
+  ss->queued = iteration;
+  ss->done = iteration;
   return GSW_OK;
 }
 

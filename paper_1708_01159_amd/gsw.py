@@ -22,16 +22,39 @@ OK, EINVAL, ENOMEM, EHIP, ERANGE, EBUSY, ENOTREE, ENOTSYM = 0, -1, -2, -3, -4, -
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ERANGE", -5: "EBUSY",
                 -6: "ENOTREE", -7: "ENOTSYM"}
 
-# kernels (values of GSW_K_* in include/gsw.h)
+# base kernels (values of GSW_K_* in include/gsw.h)
 PUSH_VERTEX, PUSH_WAVE4, PUSH_WAVE8, PUSH_WAVE16, PUSH_WAVE32, PUSH_WAVE64 = 0, 1, 2, 3, 4, 5
-PUSH_EDGE, PULL_BITMAP, VERTEX_SCAN, EDGE_SCAN = 6, 7, 8, 9
-N_KERNELS = 10
-KERNEL_NAMES = ("push_vertex", "push_wave4", "push_wave8", "push_wave16", "push_wave32",
-                "push_wave64", "push_edge", "pull_bitmap", "vertex_scan", "edge_scan")
+PUSH_EDGE, PULL_BITMAP, VERTEX_SCAN, EDGE_SCAN, REV_EDGE_SCAN = 6, 7, 8, 9, 10
+N_BASE_KERNELS = 11
+BASE_NAMES = ("push_vertex", "push_wave4", "push_wave8", "push_wave16", "push_wave32",
+              "push_wave64", "push_edge", "pull_bitmap", "vertex_scan", "edge_scan", "rev_edge_scan")
+# frontier-count variants (GSW_COUNT_*); a kernel id = base + N_BASE_KERNELS * variant
+COUNT_WORKGROUP, COUNT_WAVE, COUNT_THREAD = 0, 1, 2
+COUNT_NAMES = ("", ".wave", ".thread")
+N_KERNELS = N_BASE_KERNELS * 3
+KERNEL_NAMES = tuple(b + c for c in COUNT_NAMES for b in BASE_NAMES)
 DEFAULT_KERNEL = PUSH_EDGE
-N_FEATURES = 12
-FEATURE_NAMES = ("n_vertices", "n_edges", "deg_min", "deg_q1", "deg_median", "deg_q3", "deg_max",
-                 "deg_std", "frontier", "frontier_frac", "discovered", "discovered_frac")
+
+
+def kernel_id(base: int, variant: int = COUNT_WORKGROUP) -> int:
+    return base + N_BASE_KERNELS * variant
+
+
+def kernel_base(k: int) -> int:
+    return k % N_BASE_KERNELS
+
+
+def kernel_count(k: int) -> int:
+    return k // N_BASE_KERNELS
+
+
+N_FEATURES = 24
+N_GRAPH_FEATURES = 20
+FEATURE_NAMES = ("n_vertices", "n_edges",
+                 "out_deg_min", "out_deg_q1", "out_deg_median", "out_deg_q3", "out_deg_max", "out_deg_std",
+                 "in_deg_min", "in_deg_q1", "in_deg_median", "in_deg_q3", "in_deg_max", "in_deg_std",
+                 "abs_deg_min", "abs_deg_q1", "abs_deg_median", "abs_deg_q3", "abs_deg_max", "abs_deg_std",
+                 "frontier", "frontier_frac", "discovered", "discovered_frac")
 
 ASSUME_SYMMETRIC, WITH_ORIGIN, TRUSTED = 0x1, 0x2, 0x4
 POLICY_TREE, POLICY_FIXED, POLICY_SCHEDULE = 0, 1, 2
@@ -47,7 +70,8 @@ class LevelTrace(ctypes.Structure):
     _fields_ = [("source_idx", ctypes.c_int32), ("level", ctypes.c_int32),
                 ("kernel", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("n_frontier", ctypes.c_int64), ("discovered", ctypes.c_int64),
-                ("n_next", ctypes.c_int64), ("ms", ctypes.c_float), ("reserved", ctypes.c_int32)]
+                ("n_next", ctypes.c_int64), ("e_frontier", ctypes.c_int64),
+                ("ms", ctypes.c_float), ("reserved", ctypes.c_int32)]
 
 
 class BfsOpts(ctypes.Structure):
@@ -55,13 +79,17 @@ class BfsOpts(ctypes.Structure):
                 ("schedule", ctypes.c_void_p), ("schedule_len", ctypes.c_int32),
                 ("tree", ctypes.c_void_p), ("time_levels", ctypes.c_int32),
                 ("canonical_parents", ctypes.c_int32), ("device_ptrs", ctypes.c_int32),
-                ("max_workgroups", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("max_workgroups", ctypes.c_int32), ("count_arcs", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
 
 
 class MsbfsOpts(ctypes.Structure):
     _fields_ = [("push_to_pull", ctypes.c_float), ("pull_to_push", ctypes.c_float),
                 ("device_ptrs", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("block_size", ctypes.c_int32), ("fallback", ctypes.c_int32),
+                ("wide_levels", ctypes.c_void_p), ("wide_index", ctypes.c_void_p),
+                ("wide_cap", ctypes.c_int32), ("n_wide", ctypes.c_void_p),
+                ("tree", ctypes.c_void_p), ("stream", ctypes.c_void_p)]
 
 
 MSBFS_MAX_SOURCES = 1024
@@ -98,6 +126,13 @@ def lib():
         "gsw_graph_create_device": (i32, [i64, i64, vp, vp, u32, vp, P(vp)]),
         "gsw_graph_destroy": (None, [vp]),
         "gsw_graph_info": (i32, [vp, P(i64), P(i64), vp, P(ctypes.c_size_t)]),
+        "gsw_graph_symmetric": (i32, [vp]),
+        "gsw_graph_features_host": (i32, [i64, i64, vp, vp, vp]),
+        "gsw_feature_name": (ctypes.c_char_p, [i32]),
+        "gsw_tree_load": (i32, [ctypes.c_char_p, P(vp)]),
+        "gsw_session_bytes": (ctypes.c_size_t, [vp, i32]),
+        "gsw_graph_workspace_bytes": (ctypes.c_size_t, [vp]),
+        "gsw_session_rebase": (i32, [vp, i64]),
         "gsw_level_features": (i32, [vp, i64, i64, vp]),
         "gsw_degree_stats": (i32, [i64, vp, vp]),
         "gsw_tree_create": (i32, [i32, i32, vp, vp, vp, vp, vp, vp, P(vp)]),
@@ -141,6 +176,42 @@ def _ptr(a) -> int:
     if hasattr(a, "data_ptr"):
         return a.data_ptr()
     return a.ctypes.data
+
+
+_NP_DTYPES = {"int32": np.int32, "int8": np.int8}
+
+
+def check_out(t, dtype: str, numel: int, device: bool, what: str):
+    """Rejects an output buffer the library would write out of bounds or to the
+    wrong memory: a torch tensor must be a CUDA tensor (when ``device``) of
+    exactly ``dtype``, contiguous, with at least ``numel`` elements; a numpy
+    array (host output) likewise.  Raises ValueError."""
+    if t is None:
+        raise ValueError("%s: no buffer" % what)
+    if hasattr(t, "data_ptr"):  # torch
+        import torch
+
+        if not device:
+            raise ValueError("%s: a torch tensor was given for host output" % what)
+        if not t.is_cuda:
+            raise ValueError("%s: expected a CUDA tensor, got one on %s" % (what, t.device))
+        if t.dtype != getattr(torch, dtype):
+            raise ValueError("%s: expected torch.%s, got %s" % (what, dtype, t.dtype))
+        if not t.is_contiguous():
+            raise ValueError("%s: tensor is not contiguous" % what)
+        if t.numel() < numel:
+            raise ValueError("%s: %d elements, need %d" % (what, t.numel(), numel))
+        return
+    if device:
+        raise ValueError("%s: expected a CUDA tensor, got %s" % (what, type(t).__name__))
+    if not isinstance(t, np.ndarray):
+        raise ValueError("%s: expected a numpy array or torch tensor, got %s" % (what, type(t).__name__))
+    if t.dtype != _NP_DTYPES[dtype]:
+        raise ValueError("%s: expected %s, got %s" % (what, dtype, t.dtype))
+    if not t.flags["C_CONTIGUOUS"] or not t.flags["WRITEABLE"]:
+        raise ValueError("%s: array is not contiguous and writeable" % what)
+    if t.size < numel:
+        raise ValueError("%s: %d elements, need %d" % (what, t.size, numel))
 
 
 def validate(offs, cols):
@@ -207,6 +278,18 @@ class Graph:
         _check(lib().gsw_level_features(self._h, n_frontier, discovered, out.ctypes.data))
         return out
 
+    @property
+    def symmetric(self) -> bool:
+        return bool(lib().gsw_graph_symmetric(self._h))
+
+    def workspace_bytes(self) -> int:
+        """Device bytes of the single-source workspace (allocated on first use)."""
+        return int(lib().gsw_graph_workspace_bytes(self._h))
+
+    def session_bytes(self, slots: int) -> int:
+        """Device bytes a serving session of ``slots`` slots on this graph allocates."""
+        return int(lib().gsw_session_bytes(self._h, int(slots)))
+
     def close(self):
         if self._h is not None and self._h.value:
             lib().gsw_graph_destroy(self._h)
@@ -243,8 +326,17 @@ class Tree:
 
     @classmethod
     def load(cls, path: str) -> "Tree":
+        """Reads the JSON export with the library's own reader (gsw_tree_load)."""
         with open(path) as f:
-            return cls(json.load(f))
+            arrays = json.load(f)
+        out = ctypes.c_void_p()
+        _check(lib().gsw_tree_load(os.fsencode(path), ctypes.byref(out)))
+        t = cls.__new__(cls)
+        t.arrays = arrays
+        t._h = out
+        t.n_nodes = len(arrays["left"])
+        t.n_classes = len(arrays["class_kernel"])
+        return t
 
     @classmethod
     def constant(cls, kernel: int) -> "Tree":
@@ -282,10 +374,16 @@ class TraceRow:
     discovered: int
     n_next: int
     ms: float
+    e_frontier: int = -1
 
     @property
     def kernel_name(self):
         return KERNEL_NAMES[self.kernel]
+
+
+def _row(t):
+    return TraceRow(t.source_idx, t.level, t.kernel, t.flags, t.n_frontier, t.discovered, t.n_next, t.ms,
+                    t.e_frontier)
 
 
 def _opts(policy, kernel, schedule, tree, time_levels, canonical_parents, device_ptrs, stream):
@@ -317,7 +415,7 @@ def _opts(policy, kernel, schedule, tree, time_levels, canonical_parents, device
 def bfs(graph: Graph, sources, policy: str = "tree", kernel: int = PUSH_VERTEX, schedule=None,
         tree: Tree = None, parents: bool = True, time_levels: bool = False,
         canonical_parents: bool = False, device: bool = False, stream=None, out=None,
-        trace_cap: int = None, max_workgroups: int = 0):
+        trace_cap: int = None, max_workgroups: int = 0, count_arcs: bool = False):
     """Level-switched BFS from each source.
 
     Returns ``(levels, parents, trace)``: ``levels`` is ``[len(sources), n]``
@@ -325,7 +423,8 @@ def bfs(graph: Graph, sources, policy: str = "tree", kernel: int = PUSH_VERTEX, 
     ``parents`` likewise or None, ``trace`` a list of TraceRow.
     ``out`` may supply preallocated ``(levels, parents)`` device tensors.
     ``max_workgroups`` > 0 caps every level launch (for tests of the
-    striding paths; 0 lets the library size launches).
+    striding paths; 0 lets the library size launches).  ``count_arcs``
+    fills each trace row's ``e_frontier``.
     """
     src = np.ascontiguousarray(np.atleast_1d(np.asarray(sources)), dtype=np.int32)
     S, n = src.shape[0], graph.n
@@ -334,6 +433,9 @@ def bfs(graph: Graph, sources, policy: str = "tree", kernel: int = PUSH_VERTEX, 
 
         if out is not None:
             lv, pa = out
+            check_out(lv, "int32", S * n, True, "bfs levels")
+            if pa is not None:
+                check_out(pa, "int32", S * n, True, "bfs parents")
         else:
             lv = torch.empty((S, n), dtype=torch.int32, device="cuda")
             pa = torch.empty((S, n), dtype=torch.int32, device="cuda") if parents else None
@@ -344,6 +446,7 @@ def bfs(graph: Graph, sources, policy: str = "tree", kernel: int = PUSH_VERTEX, 
         pa = np.empty((S, n), dtype=np.int32) if parents else None
     o, keep = _opts(policy, kernel, schedule, tree, time_levels, canonical_parents, device, stream)
     o.max_workgroups = int(max_workgroups)
+    o.count_arcs = int(bool(count_arcs))
     cap = trace_cap if trace_cap is not None else 64 * max(S, 1)
     while True:
         tr = (LevelTrace * max(cap, 1))()
@@ -354,8 +457,7 @@ def bfs(graph: Graph, sources, policy: str = "tree", kernel: int = PUSH_VERTEX, 
         if tlen.value <= cap or trace_cap is not None:
             break
         cap = tlen.value  # rerun once with room for every row
-    rows = [TraceRow(t.source_idx, t.level, t.kernel, t.flags, t.n_frontier, t.discovered,
-                     t.n_next, t.ms) for t in tr[:min(tlen.value, cap)]]
+    rows = [_row(t) for t in tr[:min(tlen.value, cap)]]
     del keep
     return lv, pa, rows
 
@@ -375,6 +477,9 @@ class Runner:
 
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
+        check_out(levels, "int32", graph.n, True, "Runner levels")
+        if parents is not None:
+            check_out(parents, "int32", graph.n, True, "Runner parents")
         self.graph, self.levels, self.parents, self.tree = graph, levels, parents, tree
         self.opts, self._keep = _opts(policy, kernel, schedule, tree, time_levels, False, True, stream)
         self.trace = (LevelTrace * trace_cap)()
@@ -396,38 +501,67 @@ class Runner:
         return self.tlen.value
 
     def rows(self):
-        return [TraceRow(t.source_idx, t.level, t.kernel, t.flags, t.n_frontier, t.discovered,
-                         t.n_next, t.ms) for t in self.trace[:min(self.tlen.value, self.cap)]]
+        return [_row(t) for t in self.trace[:min(self.tlen.value, self.cap)]]
 
 
 def msbfs(graph: Graph, sources, push_to_pull: float = None, pull_to_push: float = None,
-          device: bool = False, stream=None, out=None, use_graph: bool = True):
+          device: bool = False, stream=None, out=None, use_graph: bool = True, block_size: int = 0,
+          fallback: bool = False, tree: Tree = None, wide_cap: int = None):
     """Batched BFS of up to 1024 sources.  Returns ``(levels int8 [S][n], n_levels)``;
     levels are a torch CUDA tensor when ``device`` (or ``out`` is given).
     ``use_graph`` replays the captured two-level HIP graph instead of
-    launching each kernel."""
+    launching each kernel; ``block_size`` (128/256/512, 0 = default) sets
+    the level kernels' workgroup size.  With ``fallback`` the result is
+    ``(levels, n_levels, wide)``, ``wide`` a dict {source index: int32 row}
+    of the sources rerun on the single-source path because they go deeper
+    than 127 (their int8 rows hold -128 beyond 127)."""
     src = np.ascontiguousarray(np.atleast_1d(np.asarray(sources)), dtype=np.int32)
     S, n = src.shape[0], graph.n
     o = MsbfsOpts()
     lib().gsw_msbfs_opts_default(ctypes.byref(o))
     o.graph = 1 if use_graph else 0
+    o.block_size = int(block_size)
     if push_to_pull is not None:
         o.push_to_pull = push_to_pull
     if pull_to_push is not None:
         o.pull_to_push = pull_to_push
-    if device or out is not None:
+    dev = bool(device or out is not None)
+    if dev:
         import torch
 
+        if out is not None:
+            check_out(out, "int8", S * n, True, "msbfs levels")
         lv = out if out is not None else torch.empty((S, n), dtype=torch.int8, device="cuda")
         o.device_ptrs = 1
         o.stream = stream if stream is not None else torch.cuda.current_stream().cuda_stream
     else:
         lv = np.empty((S, n), dtype=np.int8)
         o.stream = stream
+    keep = []
+    nw = ctypes.c_int32(0)
+    if fallback:
+        cap = S if wide_cap is None else int(wide_cap)
+        if dev:
+            import torch
+
+            wl = torch.empty((max(cap, 1), n), dtype=torch.int32, device="cuda")
+        else:
+            wl = np.empty((max(cap, 1), n), dtype=np.int32)
+        wi = np.zeros(max(cap, 1), dtype=np.int32)
+        keep += [wl, wi]
+        o.fallback = 1
+        o.wide_levels = _ptr(wl)
+        o.wide_index = wi.ctypes.data
+        o.wide_cap = cap
+        o.n_wide = ctypes.addressof(nw)
+        o.tree = tree.handle.value if tree is not None else None
     nl = ctypes.c_int32(0)
     _check(lib().gsw_msbfs(graph.handle, src.ctypes.data, S, _ptr(lv), ctypes.byref(nl),
                            ctypes.byref(o)))
-    return lv, nl.value
+    if not fallback:
+        return lv, nl.value
+    wide = {int(wi[k]): wl[k] for k in range(nw.value)}
+    return lv, nl.value, wide
 
 
 class Session:
@@ -465,8 +599,13 @@ class Session:
         if out is None:
             out = np.empty(self.graph.n, dtype=np.int32)
         dev = 1 if hasattr(out, "data_ptr") else 0
+        check_out(out, "int32", self.graph.n, bool(dev), "session fetch")
         _check(lib().gsw_session_fetch(self._h, int(slot), _ptr(out), dev))
         return out
+
+    def rebase(self, iteration: int):
+        """Sets the level counter (only while nothing runs; see gsw_session_rebase)."""
+        _check(lib().gsw_session_rebase(self._h, int(iteration)))
 
     def info(self):
         s, b, it, nb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64(), ctypes.c_size_t()
@@ -487,6 +626,16 @@ class Session:
             self.close()
         except Exception:
             pass
+
+
+def graph_features_host(offs, cols) -> np.ndarray:
+    """The library's 20 graph features of a host CSR (no GPU)."""
+    offs = np.ascontiguousarray(offs, dtype=np.int64)
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    out = np.empty(N_GRAPH_FEATURES, dtype=np.float64)
+    _check(lib().gsw_graph_features_host(offs.shape[0] - 1, cols.shape[0], offs.ctypes.data,
+                                         cols.ctypes.data, out.ctypes.data))
+    return out
 
 
 def bfs_profile(graph: Graph, source: int, kernels=None, reps: int = 5,

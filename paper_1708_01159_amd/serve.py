@@ -5,9 +5,12 @@ Each graph that has queries gets a gsw session (a continuously batched
 multi-source traversal with a fixed number of slots).  A query is admitted
 into a free slot of its graph's session as soon as one is free -- also while
 the session's other queries are mid-traversal; it joins at the next level
-boundary.  Sessions are created only while their device memory fits the
-budget; an idle session (no slot in use) is destroyed to make room for
-another graph's.  Each session is stepped by its own worker thread on its own
+boundary.  Sessions are created only while their device memory (as the
+library counts it, gsw_session_bytes) fits the budget; an idle session (no
+slot in use) is destroyed to make room for another graph's.  A graph's
+single-source lane is charged too: the graph's single-source workspace
+(held until the graph is destroyed) plus the lane's level buffer, once,
+when the lane is first opened.  Each session is stepped by its own worker thread on its own
 HIP stream, so the work of different graphs overlaps on the device.
 
 Optionally each graph also has a single-source lane running the
@@ -74,9 +77,15 @@ def component_edges(offs, cols) -> np.ndarray:
     return per[lab]
 
 
-def session_bytes(n: int, slots: int) -> int:
-    w = (slots + 63) // 64
-    return 4 * n * w * 8 + slots * n * 4
+def session_bytes(graph, slots: int) -> int:
+    """Device bytes a session of ``slots`` slots on ``graph`` allocates."""
+    return graph.session_bytes(slots)
+
+
+def lane_bytes(graph) -> int:
+    """Device bytes of a single-source lane's level row (the graph's
+    single-source workspace is charged separately, once per graph)."""
+    return 4 * graph.n
 
 
 def poisson_trace(rate_qps: float, duration_s: float, graphs, candidates, zipf_s: float = 1.1,
@@ -143,7 +152,9 @@ class Server:
         self.keep = keep_levels
         self.sessions = {}          # graph -> gsw.Session
         self.workers = {}           # graph -> single-thread executor
-        self.used = 0
+        self.used = 0               # device bytes charged: open sessions, open lanes, workspaces
+        self._ws_charged = set()    # graphs whose single-source workspace is charged (held for good)
+        self._held = 0              # bytes lanes hold: open lanes' rows and the charged workspaces
         self.evictions = 0
         self._scratch_bufs = {}
         self._live = {}             # graph -> future of its running worker
@@ -152,7 +163,7 @@ class Server:
     def _ensure_session(self, name):
         if name in self.sessions:
             return self.sessions[name]
-        need = session_bytes(self.res[name].graph.n, self.slots)
+        need = session_bytes(self.res[name].graph, self.slots)
         if self.budget is not None:
             # make room by closing idle sessions of other graphs
             while self.used + need > self.budget:
@@ -170,7 +181,7 @@ class Server:
     def _close(self, name):
         s = self.sessions.pop(name)
         self.workers.pop(name).shutdown(wait=True)
-        self.used -= session_bytes(self.res[name].graph.n, self.slots)
+        self.used -= session_bytes(self.res[name].graph, self.slots)
         s.close()
 
     def _scratch(self, name):
@@ -208,8 +219,24 @@ class Server:
         done_q.append(q)
 
     def _solo_lane(self, name):
+        """The graph's single-source lane, opened (and charged) on first use;
+        None when the budget has no room for it (its queries then go to the
+        session)."""
         if name not in self._solo_lanes:
-            self._solo_lanes[name] = (self.new_solo(self.res[name].graph), ThreadPoolExecutor(max_workers=1))
+            g = self.res[name].graph
+            need = lane_bytes(g) + (0 if name in self._ws_charged else g.workspace_bytes())
+            if self.budget is not None:
+                # lanes hold their bytes for the rest of the run (workspaces for
+                # good): open one only while the largest session still fits
+                # beside everything lanes hold, so no graph's queries can be
+                # locked out of a session
+                biggest = max(session_bytes(r.graph, self.slots) for r in self.res.values())
+                if self._held + need + biggest > self.budget:
+                    return None
+            self._solo_lanes[name] = (self.new_solo(g), ThreadPoolExecutor(max_workers=1))
+            self.used += need
+            self._held += need
+            self._ws_charged.add(name)
         return self._solo_lanes[name]
 
     def run(self, trace, timeout_s: float = 600.0):
@@ -252,12 +279,12 @@ class Server:
             for name, dq in pending.items():
                 if not dq:
                     continue
-                if self.solo:
+                lane = self._solo_lane(name) if self.solo else None
+                if lane is not None:
                     if name not in solo_busy:
-                        lane, ex = self._solo_lane(name)
                         q = dq.popleft()
                         q.t_admit = time.perf_counter() - t0
-                        solo_busy[name] = ex.submit(self._solo_run, name, lane, q, done_q, t0)
+                        solo_busy[name] = lane[1].submit(self._solo_run, name, lane[0], q, done_q, t0)
                         self.solo_served += 1
                     # the rest waits for the lane unless the session would be quicker
                     e = est[name]
@@ -289,8 +316,10 @@ class Server:
             fut.result()
         for name in list(self.sessions):
             self._close(name)
-        for lane, ex in self._solo_lanes.values():
+        for name, (lane, ex) in self._solo_lanes.items():
             ex.shutdown(wait=True)
+            self.used -= lane_bytes(self.res[name].graph)
+            self._held -= lane_bytes(self.res[name].graph)
         self._solo_lanes = {}
         return queries
 

@@ -39,11 +39,21 @@ def test_header_and_binding_agree_on_constants():
     text = open(os.path.join(ROOT, "include", "gsw.h")).read()
     consts = dict((m.group(1), int(m.group(2)))
                   for m in re.finditer(r"GSW_K_(\w+) = (\d+)", text))
-    for i, name in enumerate(gsw.KERNEL_NAMES):
+    for i, name in enumerate(gsw.BASE_NAMES):
         assert consts[name.upper()] == i
+    assert int(re.search(r"GSW_N_BASE_KERNELS = (\d+)", text).group(1)) == gsw.N_BASE_KERNELS
+    counts = dict((m.group(1), int(m.group(2))) for m in re.finditer(r"GSW_COUNT_(\w+) = (\d+)", text))
+    assert (counts["WORKGROUP"], counts["WAVE"], counts["THREAD"]) == (
+        gsw.COUNT_WORKGROUP, gsw.COUNT_WAVE, gsw.COUNT_THREAD)
+    assert len(gsw.KERNEL_NAMES) == gsw.N_KERNELS == 33
+    for i, name in enumerate(gsw.KERNEL_NAMES):
         assert gsw.kernel_name(i) == name
-    assert gsw.kernel_name(99) == "?"
+        assert gsw.kernel_id(gsw.kernel_base(i), gsw.kernel_count(i)) == i
+    assert gsw.kernel_name(gsw.N_KERNELS) == "?" and gsw.kernel_name(-1) == "?"
     assert int(re.search(r"GSW_N_FEATURES (\d+)", text).group(1)) == gsw.N_FEATURES == ofeat.N_FEATURES
+    assert int(re.search(r"GSW_N_GRAPH_FEATURES (\d+)", text).group(1)) == gsw.N_GRAPH_FEATURES
+    for i, name in enumerate(gsw.FEATURE_NAMES):
+        assert gsw.lib().gsw_feature_name(i).decode() == name == ofeat.NAMES[i]
     assert gsw.lib().gsw_abi_version() == int(re.search(r"GSW_ABI_VERSION (\d+)", text).group(1))
 
 
@@ -168,3 +178,139 @@ def test_graph_create_without_gpu_fails_loudly():
     with pytest.raises(gsw.GswError) as ei:
         gsw.Graph.from_csr(g.offs, g.cols)
     assert ei.value.status == gsw.EHIP
+
+
+def test_graph_features_host_match_oracle():
+    """The library's 20 graph features against the oracle's definitions, on
+    symmetric graphs and on directed ones (out-, in- and absolute degrees
+    differ there)."""
+    rng = np.random.default_rng(5)
+    cases = [gg.rmat(9, 8, seed=3), gg.from_edges(5, [0, 1, 2, 3], [1, 2, 3, 4])]
+    for k in range(6):  # random directed graphs with repeats, loops and some reciprocated arcs
+        n = int(rng.integers(2, 40))
+        m = int(rng.integers(1, 4 * n))
+        src = rng.integers(0, n, m)
+        dst = rng.integers(0, n, m)
+        order = np.lexsort((dst, src))
+        src, dst = src[order], dst[order]
+        offs = np.zeros(n + 1, dtype=np.int64)
+        np.add.at(offs, src + 1, 1)
+        cases.append(type("G", (), dict(offs=np.cumsum(offs), cols=dst.astype(np.int32)))())
+    for g in cases:
+        mine = gsw.graph_features_host(g.offs, g.cols)
+        ref = ofeat.graph_features(g.offs, g.cols)
+        np.testing.assert_allclose(mine, ref, rtol=1e-12, atol=0)
+
+
+def _write(tmp_path, name, obj):
+    import json
+
+    p = tmp_path / name
+    p.write_text(obj if isinstance(obj, str) else json.dumps(obj))
+    return str(p)
+
+
+def test_tree_load_matches_tree_create(tmp_path):
+    """gsw_tree_load reads the JSON export into the same tree that
+    gsw_tree_create builds from the arrays (and sklearn predicts)."""
+    from sklearn.tree import DecisionTreeClassifier
+
+    rng = np.random.default_rng(3)
+    X = np.abs(rng.normal(size=(500, gsw.N_FEATURES))) * 10.0 ** rng.integers(0, 6, gsw.N_FEATURES)
+    y = (X[:, 20] > np.median(X[:, 20])).astype(int) + 2 * (X[:, 3] > np.median(X[:, 3]))
+    clf = DecisionTreeClassifier(max_depth=5, random_state=0).fit(X, y)
+    T = _export(clf, [gsw.PULL_BITMAP, gsw.PUSH_EDGE, gsw.kernel_id(gsw.REV_EDGE_SCAN, gsw.COUNT_THREAD),
+                      gsw.PUSH_VERTEX])
+    T["feature_names"] = list(gsw.FEATURE_NAMES)
+    T["report"] = {"nested": [1, {"a": None, "b": True}], "text": "\u00e9\"x\""}
+    path = _write(tmp_path, "t.json", T)
+    loaded = gsw.Tree.load(path)
+    built = gsw.Tree(T)
+    for x in X[:200]:
+        for prev, lev in ((0, 0), (gsw.PUSH_WAVE8, 2)):
+            assert loaded.predict(x, prev, lev) == built.predict(x, prev, lev)
+
+
+@pytest.mark.parametrize("text,msg", [
+    ("{", "not a JSON object"),
+    ("[1, 2]", "not a JSON object"),
+    ('{"feature": [0], "threshold": [0.0], "left": [-1], "right": [-1], "value": [[1.0]]}', "class_kernel"),
+    ('{"feature": [0, 1], "threshold": [0.0], "left": [-1], "right": [-1], "value": [[1.0]], '
+     '"class_kernel": [0]}', "differ in length"),
+    ('{"feature": [0], "threshold": [0.0], "left": [-1], "right": [-1], "value": [[1.0, 2.0]], '
+     '"class_kernel": [0]}', "classes"),
+    ('{"feature": [0.5], "threshold": [0.0], "left": [-1], "right": [-1], "value": [[1.0]], '
+     '"class_kernel": [0]}', "non-integer"),
+    ('{"feature_names": ["deg_min"], "feature": [0], "threshold": [0.0], "left": [-1], "right": [-1], '
+     '"value": [[1.0]], "class_kernel": [0]}', "feature_names"),
+    ("[" * 100 + "]" * 100, "not a JSON object"),
+])
+def test_tree_load_rejects_malformed(tmp_path, text, msg):
+    path = _write(tmp_path, "bad.json", text)
+    with pytest.raises(gsw.GswError) as ei:
+        gsw.Tree.load(path) if not text.startswith("[") and text != "{" else _load_raw(path)
+    assert ei.value.status == gsw.EINVAL and msg in str(ei.value)
+
+
+def _load_raw(path):
+    import ctypes
+
+    out = ctypes.c_void_p()
+    gsw._check(gsw.lib().gsw_tree_load(os.fsencode(path), ctypes.byref(out)))
+
+
+def test_tree_load_missing_file(tmp_path):
+    with pytest.raises(gsw.GswError) as ei:
+        _load_raw(str(tmp_path / "nope.json"))
+    assert ei.value.status == gsw.EINVAL
+
+
+def test_shipped_trees_load():
+    from paper_1708_01159_amd import trees
+
+    for name in ("seed", "mi355x"):
+        t = gsw.Tree.load(trees.path(name))
+        assert t.n_nodes >= 1
+
+
+class _FakeGraph:
+    n = 10
+    handle = None
+
+
+@pytest.mark.parametrize("make,msg", [
+    (lambda torch: torch.zeros((1, 10), dtype=torch.int32), "CUDA tensor"),
+    (lambda torch: np.zeros((1, 10), dtype=np.int32), "CUDA tensor"),
+])
+def test_binding_rejects_bad_outputs(make, msg):
+    """Output buffers are checked before any C call: a CPU tensor, a numpy
+    array where device memory is expected, the wrong dtype, a strided or
+    short tensor would otherwise be written out of bounds by the GPU."""
+    import torch
+
+    with pytest.raises(ValueError) as ei:
+        gsw.check_out(make(torch), "int32", 10, True, "levels")
+    assert msg in str(ei.value)
+
+
+def test_check_out_rules():
+    import torch
+
+    ok = np.zeros(20, dtype=np.int32)
+    gsw.check_out(ok, "int32", 20, False, "x")
+    with pytest.raises(ValueError, match="int8"):
+        gsw.check_out(ok, "int8", 20, False, "x")
+    with pytest.raises(ValueError, match="need"):
+        gsw.check_out(ok, "int32", 21, False, "x")
+    with pytest.raises(ValueError, match="contiguous"):
+        gsw.check_out(np.zeros(40, dtype=np.int32)[::2], "int32", 20, False, "x")
+    with pytest.raises(ValueError, match="host output"):
+        gsw.check_out(torch.zeros(20, dtype=torch.int32), "int32", 20, False, "x")
+    with pytest.raises(ValueError, match="no buffer"):
+        gsw.check_out(None, "int32", 1, True, "x")
+    # the public entry points run the checks before touching the library
+    with pytest.raises(ValueError):
+        gsw.bfs(_FakeGraph(), [0], policy="fixed", kernel=0, device=True,
+                out=(torch.zeros((1, 10), dtype=torch.int32), None))
+    with pytest.raises(ValueError):
+        gsw.msbfs(_FakeGraph(), [0], out=torch.zeros((1, 10), dtype=torch.int8))

@@ -79,9 +79,12 @@ def case(name):
     return _cache[name]
 
 
-def _check_result(g, srcs, refs, comp, lv, pa, trace):
+def _check_result(g, srcs, refs, comp, lv, pa, trace, arcs=False):
+    """Levels bit-exact, parents valid, and the trace's per-level counts equal
+    the oracle's histograms: n_f, n_next, discovered and -- when the run
+    counted arcs -- e_f (the degree sum of each depth), else -1."""
     for i, s in enumerate(srcs):
-        ref_lv, _, hist, _ = refs[i]
+        ref_lv, _, hist, ehist = refs[i]
         assert np.array_equal(lv[i], ref_lv), "levels differ for source %d" % s
         checks.check_bfs(g.offs, g.cols, int(s), lv[i], pa[i], comp)
         rows = [t for t in trace if t.source_idx == i]
@@ -89,15 +92,17 @@ def _check_result(g, srcs, refs, comp, lv, pa, trace):
         assert [t.n_frontier for t in rows] == hist.tolist()
         assert [t.n_next for t in rows] == hist[1:].tolist() + [0]
         assert [t.discovered for t in rows] == np.cumsum(hist).tolist()
+        assert [t.e_frontier for t in rows] == (ehist.tolist() if arcs else [-1] * len(hist))
 
 
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("kernel", ALL_KERNELS, ids=gsw.KERNEL_NAMES)
 def test_fixed_kernel_parity(name, kernel):
     g, G, srcs, refs, comp = case(name)
-    lv, pa, trace = gsw.bfs(G, srcs, policy="fixed", kernel=kernel)
+    arcs = kernel % 2 == 0  # half the runs also count the frontier arcs
+    lv, pa, trace = gsw.bfs(G, srcs, policy="fixed", kernel=kernel, count_arcs=arcs)
     assert all(t.kernel == kernel for t in trace)
-    _check_result(g, srcs, refs, comp, lv, pa, trace)
+    _check_result(g, srcs, refs, comp, lv, pa, trace, arcs)
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -107,17 +112,18 @@ def test_random_schedules(name):
     depth = max(len(r[2]) for r in refs)
     for trial in range(6):
         sched = rng.integers(0, gsw.N_KERNELS, size=depth).astype(np.int32)
-        lv, pa, trace = gsw.bfs(G, srcs, policy="schedule", schedule=sched)
+        arcs = trial % 2 == 1
+        lv, pa, trace = gsw.bfs(G, srcs, policy="schedule", schedule=sched, count_arcs=arcs)
         for t in trace:
             assert t.kernel == sched[min(t.level, depth - 1)]
-        _check_result(g, srcs, refs, comp, lv, pa, trace)
+        _check_result(g, srcs, refs, comp, lv, pa, trace, arcs)
 
 
 def _handmade_tree():
     # split on the frontier fraction, then on the discovered fraction
     return dict(
         left=[1, 3, 5, -1, -1, -1, -1], right=[2, 4, 6, -1, -1, -1, -1],
-        feature=[9, 11, 11, -2, -2, -2, -2], threshold=[0.01, 0.5, 0.9, -2, -2, -2, -2],
+        feature=[21, 23, 23, -2, -2, -2, -2], threshold=[0.01, 0.5, 0.9, -2, -2, -2, -2],
         value=[[1, 1, 1, 1], [3, 1, 0, 0], [0, 0, 2, 1], [0, 4, 0, 0], [5, 0, 0, 0],
                [0, 0, 6, 0], [0, 0, 1, 1]],
         class_kernel=[gsw.PUSH_WAVE32, gsw.PUSH_VERTEX, gsw.PULL_BITMAP, gsw.PUSH_EDGE])
@@ -149,12 +155,13 @@ def _big_tree(depth=9, seed=17):
     n = 2 ** (depth + 1) - 1
     left = [2 * i + 1 if i < n_int else -1 for i in range(n)]
     right = [2 * i + 2 if i < n_int else -1 for i in range(n)]
-    feature = [int(rng.choice([8, 9, 10, 11])) if i < n_int else -2 for i in range(n)]
+    feature = [int(rng.choice([20, 21, 22, 23])) if i < n_int else -2 for i in range(n)]
     thr = []
     for i in range(n):
         f = feature[i]
-        thr.append(-2.0 if i >= n_int else float(rng.uniform(0, 1) if f in (9, 11) else rng.uniform(0, 3000)))
-    kernels = [gsw.PUSH_VERTEX, gsw.PUSH_WAVE8, gsw.PUSH_EDGE, gsw.PULL_BITMAP]
+        thr.append(-2.0 if i >= n_int else float(rng.uniform(0, 1) if f in (21, 23) else rng.uniform(0, 3000)))
+    kernels = [gsw.PUSH_VERTEX, gsw.PUSH_WAVE8, gsw.PUSH_EDGE, gsw.PULL_BITMAP,
+               gsw.kernel_id(gsw.REV_EDGE_SCAN), gsw.kernel_id(gsw.PUSH_VERTEX, gsw.COUNT_THREAD)]
     value = []
     for i in range(n):
         v = [0.0] * len(kernels)
@@ -209,7 +216,8 @@ def test_level_features_match_oracle():
         want = ofeat.level_features(g.offs, hist, d, gf)
         got = G.level_features(int(hist[d]), int(hist[: d + 1].sum()))
         np.testing.assert_allclose(got, want, rtol=1e-12)
-        assert np.array_equal(got[[0, 1, 2, 3, 4, 5, 6, 8, 10]], want[[0, 1, 2, 3, 4, 5, 6, 8, 10]])
+        exact = [0, 1, 2, 3, 4, 5, 6, 20, 22]
+        assert np.array_equal(got[exact], want[exact])
 
 
 def _canonical(g, lv):
@@ -291,6 +299,16 @@ def test_device_pointers_and_torch_stream():
     G2.close()
 
 
+def test_arc_counts_off_by_default():
+    g, G, srcs, refs, comp = case("rmat14")
+    lv, pa, trace = gsw.bfs(G, srcs, policy="fixed", kernel=gsw.PULL_BITMAP)
+    _check_result(g, srcs, refs, comp, lv, pa, trace, arcs=False)
+    from paper_1708_01159_amd import trees
+
+    lv, pa, trace = gsw.bfs(G, srcs, policy="tree", tree=trees.load_default(), count_arcs=True)
+    _check_result(g, srcs, refs, comp, lv, pa, trace, arcs=True)
+
+
 def test_time_levels_and_no_parents():
     g, G, srcs, refs, comp = case("rmat14")
     lv, pa, trace = gsw.bfs(G, srcs, policy="fixed", kernel=gsw.PUSH_WAVE16, parents=False,
@@ -301,25 +319,64 @@ def test_time_levels_and_no_parents():
         assert np.array_equal(lv[i], refs[i][0])
 
 
-def test_directed_graph_push_only():
+def _directed_cases():
     a = gg.rmat(10, 8, seed=40)
     rows = np.repeat(np.arange(a.n), a.degrees())
-    keep = rows < a.cols  # orient every edge from low id to high id
-    d = gg.from_edges(a.n, rows[keep], a.cols[keep], symmetrize=False)
+    keep = rows < a.cols  # orient every edge from low id to high id: a DAG
+    dag = gg.from_edges(a.n, rows[keep], a.cols[keep], symmetrize=False, name="dag")
+    # a random 60% of an R-MAT graph's arcs: cycles, reciprocated and one-way arcs
+    b = gg.rmat(12, 8, seed=41)
+    brow = np.repeat(np.arange(b.n), b.degrees())
+    keep = np.random.default_rng(41).random(b.nnz) < 0.6
+    r = gg.from_edges(b.n, brow[keep], b.cols[keep], symmetrize=False, name="rmat12_directed")
+    # directed cycle plus chords, ragged n
+    n = 1003
+    src = list(range(n)) + list(range(0, n, 7))
+    dst = [(i + 1) % n for i in range(n)] + [(i * 31 + 5) % n for i in range(0, n, 7)]
+    cyc = gg.from_edges(n, src, dst, symmetrize=False, name="cycle")
+    return [dag, r, cyc]
+
+
+@pytest.mark.parametrize("which", [0, 1, 2])
+def test_directed_graph_every_kernel(which):
+    """Directed graphs: the top-down kernels follow out-arcs, the bottom-up and
+    reverse-edge-list kernels the transpose the library keeps; every kernel
+    (and count variant) equals the oracle, parents pass the directed
+    invariants, and the trace's e_f equals the out-degree sums."""
+    d = _directed_cases()[which]
     G = gsw.Graph.from_csr(d.offs, d.cols)
-    s = int(np.flatnonzero(d.degrees() > 0)[0])
-    ref = oracle.levels(d.offs, d.cols, s)
-    for k in (gsw.PUSH_VERTEX, gsw.PUSH_WAVE8, gsw.PUSH_EDGE, gsw.VERTEX_SCAN, gsw.EDGE_SCAN):
-        lv, _, _ = gsw.bfs(G, [s], policy="fixed", kernel=k)
-        assert np.array_equal(lv[0], ref)
-    with pytest.raises(gsw.GswError) as ei:
-        gsw.bfs(G, [s], policy="fixed", kernel=gsw.PULL_BITMAP)
-    assert ei.value.status == gsw.ENOTSYM
-    # the tree may name pull: on a directed graph the driver substitutes the
-    # default kernel and flags the row
-    lv, _, trace = gsw.bfs(G, [s], policy="tree", tree=gsw.Tree.constant(gsw.PULL_BITMAP))
-    assert np.array_equal(lv[0], ref)
-    assert all(t.kernel == gsw.DEFAULT_KERNEL and t.flags & 2 for t in trace)
+    assert not G.symmetric
+    srcs = np.flatnonzero(d.degrees() > 0)[:2].astype(np.int32)
+    refs = [oracle.bfs(d.offs, d.cols, int(s)) for s in srcs]
+    for k in ALL_KERNELS:
+        lv, pa, trace = gsw.bfs(G, srcs, policy="fixed", kernel=k, count_arcs=True)
+        for i, s in enumerate(srcs):
+            assert np.array_equal(lv[i], refs[i][0]), (gsw.KERNEL_NAMES[k], int(s))
+            checks.check_bfs_directed(d.offs, d.cols, int(s), lv[i], pa[i])
+            rows = [t for t in trace if t.source_idx == i]
+            assert [t.e_frontier for t in rows] == refs[i][3].tolist()
+        # canonical parents on a directed graph: the smallest in-neighbour one level up
+        lv, pa, _ = gsw.bfs(G, srcs, policy="fixed", kernel=k, canonical_parents=True)
+        for i in range(len(srcs)):
+            assert np.array_equal(pa[i], _canonical_directed(d, refs[i][0]))
+    tr = gsw.Tree.constant(gsw.PULL_BITMAP)
+    lv, _, trace = gsw.bfs(G, srcs, policy="tree", tree=tr)
+    for i in range(len(srcs)):
+        assert np.array_equal(lv[i], refs[i][0])
+    assert all(t.kernel == gsw.PULL_BITMAP and not t.flags & 2 for t in trace)
+    G.close()
+
+
+def _canonical_directed(g, lv):
+    rows = np.repeat(np.arange(g.n), g.degrees())
+    par = np.full(g.n, -1, dtype=np.int64)
+    ok = (lv[rows] >= 0) & (lv[g.cols] == lv[rows] + 1)  # arc u -> v one level down
+    cand = np.full(g.n, np.iinfo(np.int64).max)
+    np.minimum.at(cand, g.cols[ok].astype(np.int64), rows[ok])
+    has = lv > 0
+    par[has] = cand[has]
+    par[lv == 0] = np.flatnonzero(lv == 0)
+    return par
 
 
 def test_error_paths():
@@ -346,7 +403,7 @@ def test_profile_api():
     s = int(srcs[0])
     times, frontier, ks = gsw.bfs_profile(G, s, reps=3)
     hist = refs[0][2]
-    assert times.shape == (len(hist), gsw.N_KERNELS)
+    assert times.shape == (len(hist), gsw.N_KERNELS)  # every base kernel in every count variant
     assert np.array_equal(frontier, hist)
     assert np.all(times > 0)
     # the profiled state is left consistent: a normal BFS afterwards is exact

@@ -172,3 +172,64 @@ def test_msbfs_bad_arguments():
         gsw.msbfs(G, np.arange(1025))
     with pytest.raises(gsw.GswError):
         gsw.msbfs(G, [g.n])
+
+
+@pytest.mark.parametrize("device", [False, True])
+def test_msbfs_fallback_reruns_deep_sources_in_int32(device):
+    """A 200-vertex path: sources near an end go deeper than 127.  With the
+    fallback they are rerun on the single-source path -- full int32 rows,
+    int8 rows holding -128 beyond 127 -- and the other sources keep their
+    batched result."""
+    import torch
+
+    n = 200
+    p = gg.from_edges(n, list(range(n - 1)), list(range(1, n)))
+    G = gsw.Graph.from_csr(p.offs, p.cols)
+    srcs = np.array([0, 100, 199, 90, 3, 150], dtype=np.int32)
+    for tree in (None, gsw.Tree.constant(gsw.PUSH_VERTEX)):
+        lv, nl, wide = gsw.msbfs(G, srcs, fallback=True, tree=tree, device=device)
+        if device:
+            torch.cuda.synchronize()
+            lv = lv.cpu().numpy()
+            wide = {k: v.cpu().numpy() for k, v in wide.items()}
+        assert sorted(wide) == [0, 2, 4]  # eccentricities 199, 199, 196
+        for i, s in enumerate(srcs):
+            ref = np.abs(np.arange(n) - int(s))
+            assert np.array_equal(ref, oracle.levels(p.offs, p.cols, int(s)))
+            if i in wide:
+                assert np.array_equal(wide[i], ref)
+                assert np.array_equal(lv[i].astype(np.int32), np.where(ref > 127, -128, ref))
+            else:
+                assert np.array_equal(lv[i].astype(np.int32), ref)
+    # too little room for the rerun rows is a range error, with the count
+    with pytest.raises(gsw.GswError) as ei:
+        gsw.msbfs(G, srcs, fallback=True, wide_cap=2)
+    assert ei.value.status == gsw.ERANGE
+    # nothing past the cap: no rerun
+    lv, nl, wide = gsw.msbfs(G, [100, 60], fallback=True)
+    assert wide == {} and np.array_equal(lv[0].astype(np.int32), np.abs(np.arange(n) - 100))
+    G.close()
+
+
+@pytest.mark.parametrize("bs", [128, 256, 512])
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_msbfs_block_sizes(bs, use_graph):
+    g = hub_graph()
+    G = gsw.Graph.from_csr(g.offs, g.cols)
+    srcs = gg.pick_sources(g, 150, 62)
+    for p2p in ((0.05, 0.01), (0.0, 0.0), (1e9, 1e9)):
+        lv, _ = gsw.msbfs(G, srcs, push_to_pull=p2p[0], pull_to_push=p2p[1], block_size=bs,
+                          use_graph=use_graph)
+        assert np.array_equal(lv, expected(g, srcs)), (bs, p2p)
+    with pytest.raises(gsw.GswError):
+        gsw.msbfs(G, srcs, block_size=64)
+    G.close()
+
+
+def test_msbfs_block_size_recapture():
+    # the captured graph is remade when the block size changes
+    g, G = graph("er_ragged")
+    for i, bs in enumerate((256, 512, 512, 128, 256)):
+        srcs = gg.pick_sources(g, 70, 400 + i)
+        lv, _ = gsw.msbfs(G, srcs, block_size=bs)
+        assert np.array_equal(lv, expected(g, srcs)), bs

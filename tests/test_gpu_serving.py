@@ -179,10 +179,65 @@ def test_server_tiny_budget_queues_instead_of_failing():
     cands = {nm: np.flatnonzero(resident(nm)[0].degrees() > 0) for nm in names}
     trace = serve.poisson_trace(2000.0, 0.02, names, cands, seed=6)
     # room for one session at a time: the other graph's queries wait for eviction
-    budget = max(serve.session_bytes(resident(nm)[1].n, 8) for nm in names) + 1
+    budget = max(serve.session_bytes(resident(nm)[1], 8) for nm in names) + 1
     srv = serve.Server(residents, slots=8, hbm_budget=budget, keep_levels=True)
     qs = srv.run(trace)
     for q in qs:
         g, _ = resident(q.graph)
         assert np.array_equal(q.levels, oracle.levels(g.offs, g.cols, q.source))
     assert srv.evictions >= 1
+
+
+def test_session_bytes_are_what_the_session_holds():
+    g, G = resident("er")
+    for slots in (1, 64, 65, 300):
+        sess = gsw.Session(G, slots=slots)
+        assert sess.info()["dev_bytes"] == G.session_bytes(slots)
+        sess.close()
+    before = G.info()["dev_bytes"]
+    if before < G.workspace_bytes():  # workspace not built yet on this graph
+        gsw.bfs(G, [0], policy="fixed", kernel=gsw.PUSH_EDGE)
+        assert G.info()["dev_bytes"] - before == G.workspace_bytes()
+
+
+def test_session_counter_past_2_31():
+    """The session's level counter is 64-bit: queries that start just below
+    2^31 and run across it keep exact levels (start and level arithmetic,
+    the record ring's slot and tag)."""
+    g, G = resident("grid")  # deep: ~100 levels per query
+    sess = gsw.Session(G, slots=8)
+    sess.rebase((1 << 31) - 40)
+    assert sess.info()["iteration"] == (1 << 31) - 40
+    srcs = gg.pick_sources(g, 12, 21).tolist()
+    todo, slot_src, res = list(srcs), {}, {}
+    while len(res) < len(set(srcs)):
+        while todo:
+            k = sess.admit(todo[0])
+            if k is None:
+                break
+            slot_src[k] = todo.pop(0)
+        fin, _ = sess.step(7)
+        for k in fin:
+            res[slot_src.pop(k)] = sess.fetch(k)
+    assert sess.info()["iteration"] > (1 << 31) + 20
+    for s, lv in res.items():
+        assert np.array_equal(lv, oracle.levels(g.offs, g.cols, s)), s
+    # rebase refuses while a query runs
+    k = sess.admit(srcs[0])
+    sess.step(1)
+    with pytest.raises(gsw.GswError) as ei:
+        sess.rebase(0)
+    assert ei.value.status == gsw.EBUSY
+    while True:
+        fin, _ = sess.step(50)
+        if fin:
+            break
+    sess.fetch(k)
+    sess.rebase(5)
+    k = sess.admit(srcs[1])
+    while True:
+        fin, _ = sess.step(50)
+        if fin:
+            break
+    assert np.array_equal(sess.fetch(k), oracle.levels(g.offs, g.cols, srcs[1]))
+    sess.close()

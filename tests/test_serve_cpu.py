@@ -15,6 +15,12 @@ class StubGraph:
         self.csr = csr
         self.n = csr.n
 
+    def session_bytes(self, slots):
+        return 32 * self.n * ((slots + 63) // 64) + 4 * self.n * slots
+
+    def workspace_bytes(self):
+        return 100 * self.n
+
 
 class StubSession:
     """Same contract as gsw.Session: admit from any thread, step runs until a
@@ -134,7 +140,7 @@ def test_solo_lane_takes_queries_of_idle_graphs():
 def test_budget_forces_eviction_and_queueing():
     res, cands = make(["a", "b"])
     trace = serve.poisson_trace(3000.0, 0.02, ["a", "b"], cands, seed=4)
-    budget = max(serve.session_bytes(r.graph.n, 2) for r in res.values())  # one session fits
+    budget = max(serve.session_bytes(r.graph, 2) for r in res.values())  # one session fits
     StubSession.created = 0
     srv = serve.Server(res, slots=2, hbm_budget=budget, keep_levels=True, session_factory=StubSession)
     qs = srv.run(trace, timeout_s=60)
@@ -154,6 +160,40 @@ def test_poisson_trace_shape():
         assert s in set(cands[g].tolist())
 
 
-def test_session_bytes():
-    assert serve.session_bytes(1000, 64) == 4 * 1000 * 8 + 64 * 1000 * 4
-    assert serve.session_bytes(1000, 65) == 4 * 1000 * 2 * 8 + 65 * 1000 * 4
+def test_budget_charges_sessions_lanes_and_workspaces():
+    """Server.used is what the sessions and lanes hold: every open session's
+    bytes, each open lane's level row, and each lane graph's single-source
+    workspace (kept after the lane closes); a lane that does not fit is not
+    opened and its queries go to the session."""
+    res, cands = make(["a", "b"])
+    trace = serve.poisson_trace(300.0, 0.05, ["a", "b"], cands, seed=8)
+    srv = serve.Server(res, slots=4, keep_levels=True, session_factory=StubSession, solo=True,
+                       solo_factory=StubSolo)
+    qs = srv.run(trace, timeout_s=60)
+    assert len(qs) == len(trace) and not srv.sessions
+    ws = sum(res[nm].graph.workspace_bytes() for nm in srv._ws_charged)
+    assert srv._ws_charged and srv.used == ws
+    # a budget without room for a lane beside the largest session: every
+    # query is served by a session
+    ga, gb = res["a"].graph, res["b"].graph
+    budget = max(ga.session_bytes(4), gb.session_bytes(4)) + 1
+    srv = serve.Server(res, slots=4, hbm_budget=budget, keep_levels=True, session_factory=StubSession,
+                       solo=True, solo_factory=StubSolo)
+    qs = srv.run(trace, timeout_s=60)
+    assert srv.solo_served == 0 and all(q.path == "session" for q in qs)
+    assert srv.used <= budget
+
+
+def test_lanes_never_lock_out_a_session():
+    # room for one lane beside the largest session, not two: the second
+    # graph's queries still run (in its session)
+    res, cands = make(["a", "b"])
+    trace = serve.poisson_trace(300.0, 0.05, ["a", "b"], cands, seed=8)
+    ga, gb = res["a"].graph, res["b"].graph
+    big = max(ga.session_bytes(4), gb.session_bytes(4))
+    lane_b = gb.workspace_bytes() + 4 * gb.n
+    srv = serve.Server(res, slots=4, hbm_budget=big + lane_b, keep_levels=True, session_factory=StubSession,
+                       solo=True, solo_factory=StubSolo)
+    qs = srv.run(trace, timeout_s=60)
+    assert len(qs) == len(trace) and srv.used <= big + lane_b
+    assert {q.graph for q in qs if q.path == "session"} and srv.solo_served > 0
