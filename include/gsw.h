@@ -156,11 +156,15 @@ typedef struct {
   const int32_t *schedule;   /* GSW_POLICY_SCHEDULE: kernel per level (host array); */
   int32_t schedule_len;      /*   levels beyond the end repeat the last entry */
   const gsw_tree *tree;      /* GSW_POLICY_TREE */
-  int32_t time_levels;       /* 1: fill gsw_level_trace.ms with each level's time: the
+  int32_t time_levels;       /* fill gsw_level_trace.ms with each level's time.  1: the
                                 level's first workgroup stamps the GPU's constant-rate
                                 wall clock when it starts, its last workgroup reads the
                                 clock when it ends and posts the difference in the
-                                level's record */
+                                level's record.  2: HIP events recorded on the stream
+                                after every launch of the level kernel; a level's time
+                                runs from the event before its first launch to the one
+                                after its last (what a kernel profiler reports for the
+                                launches, with the events' own small cost) */
   int32_t canonical_parents; /* 1: parent[v] = smallest neighbour one level up */
   int32_t device_ptrs;       /* 1: levels/parents are device pointers; 0: host */
   int32_t max_workgroups;    /* > 0: cap on every level-kernel launch's workgroups (levels

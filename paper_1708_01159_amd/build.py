@@ -53,11 +53,27 @@ def build_gsw() -> str:
     return LIB
 
 
+MODEL_LIB = os.path.join(HERE, "libgswmodel.so")
+
+
+def build_model() -> str:
+    """The host library of the benchmark's byte-model counts (g++, OpenMP)."""
+    tmp = MODEL_LIB + ".tmp%d" % os.getpid()
+    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-fopenmp", os.path.join(CSRC, "traffic_model.cpp"),
+           "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))
+    os.replace(tmp, MODEL_LIB)
+    return MODEL_LIB
+
+
 def build_all() -> None:
     from . import graphgen
 
     graphgen.build(force=True)
     build_gsw()
+    build_model()
 
 
 if __name__ == "__main__":

@@ -41,33 +41,6 @@ struct Policy {
   const gsw_bfs_opts* o;
   bool has_origin;
   bool has_rorigin;
-  // Kernel for level d on the host (only level 0 is chosen here); the device
-  // applies the same rules to every later level.  *flags gets bit0 when the
-  // tree leaf was undecided.
-  int choose(const gsw_graph* g, int32_t d, int64_t nf, int64_t disc, int prev, int32_t* flags) const {
-    *flags = 0;
-    int k = GSW_DEFAULT_KERNEL;
-    switch (o->policy) {
-      case GSW_POLICY_FIXED:
-        k = o->fixed_kernel;
-        break;
-      case GSW_POLICY_SCHEDULE:
-        k = o->schedule[d < o->schedule_len ? d : o->schedule_len - 1];
-        break;
-      default: {
-        double x[GSW_N_FEATURES];
-        gsw_level_features(g, nf, disc, x);
-        int32_t kk = GSW_DEFAULT_KERNEL, unk = 0;
-        gsw_tree_predict(o->tree, x, prev, d, &kk, &unk);
-        k = kk;
-        if (unk) *flags |= 1;
-        break;
-      }
-    }
-    if (kernel_base(k) == GSW_K_EDGE_SCAN && !has_origin) k = GSW_DEFAULT_KERNEL;
-    if (kernel_base(k) == GSW_K_REV_EDGE_SCAN && !has_rorigin) k = GSW_DEFAULT_KERNEL;
-    return k;
-  }
 };
 
 gsw_status check_kernel(const gsw_graph* g, int k) {
@@ -76,21 +49,44 @@ gsw_status check_kernel(const gsw_graph* g, int k) {
   return GSW_OK;
 }
 
-// Device copy of the tree, uploaded once per (workspace, tree) and
-// specialised to the graph.  A split on one of the graph's own features
-// (constant for the graph) is decided here, with the host's float rounding,
-// so the copy holds only the nodes reachable through splits on the four
-// level features.  Each of those is a non-decreasing function of an integer
-// count c in [0, n] -- the next frontier size (features 20, 21 = c, c/n) or
-// the vertices discovered through the next depth (22, 23) -- so its test,
-// float(feature) <= threshold, holds exactly for c <= T; T is found here by
-// bisection with the host's own arithmetic and the device compares counts.
-// The outcome of every walk is unchanged.  Nodes are renumbered in preorder,
-// so children still follow their parent.
-gsw_status ensure_tree(gsw_graph* g, const gsw_tree* t) {
-  Workspace& w = g->ws;
-  if (w.tree_id == t->id) return GSW_OK;
-  if (t->n_nodes > kMaxTreeNodes) return fail(GSW_EINVAL, "tree of %d nodes: at most %d", t->n_nodes, kMaxTreeNodes);
+}  // namespace
+
+int first_kernel(const gsw_graph* g, const gsw_bfs_opts* o, bool has_origin, bool has_rorigin, int32_t* flags) {
+  *flags = 0;
+  int k = GSW_DEFAULT_KERNEL;
+  switch (o->policy) {
+    case GSW_POLICY_FIXED:
+      k = o->fixed_kernel;
+      break;
+    case GSW_POLICY_SCHEDULE:
+      k = o->schedule[0];
+      break;
+    default: {
+      double x[GSW_N_FEATURES];
+      gsw_level_features(g, 1, 1, x);
+      int32_t kk = GSW_DEFAULT_KERNEL, unk = 0;
+      gsw_tree_predict(o->tree, x, GSW_DEFAULT_KERNEL, 0, &kk, &unk);
+      k = kk;
+      if (unk) *flags |= 1;
+      break;
+    }
+  }
+  if (kernel_base(k) == GSW_K_EDGE_SCAN && !has_origin) k = GSW_DEFAULT_KERNEL;
+  if (kernel_base(k) == GSW_K_REV_EDGE_SCAN && !has_rorigin) k = GSW_DEFAULT_KERNEL;
+  return k;
+}
+
+// The tree specialised to the graph.  A split on one of the graph's own
+// features (constant for the graph) is decided here, with the host's float
+// rounding, so the copy holds only the nodes reachable through splits on the
+// four level features.  Each of those is a non-decreasing function of an
+// integer count c in [0, n] -- the next frontier size (features 20, 21 =
+// c, c/n) or the vertices discovered through the next depth (22, 23) -- so
+// its test, float(feature) <= threshold, holds exactly for c <= T; T is
+// found here by bisection with the host's own arithmetic and the device
+// compares counts.  The outcome of every walk is unchanged.  Nodes are
+// renumbered in preorder, so children still follow their parent.
+int32_t specialise_tree(const gsw_graph* g, const gsw_tree* t, const TreeBuf& buf) {
   double gf[GSW_N_FEATURES];
   GSW_TRY(gsw_level_features(g, 0, 0, gf));
   auto resolve = [&](int32_t i) {
@@ -117,20 +113,45 @@ gsw_status ensure_tree(gsw_graph* g, const gsw_tree* t) {
     }
     return (int32_t)lo;
   };
-  std::vector<int32_t> order;  // kept nodes (old ids) in preorder
-  std::vector<int32_t> newid((size_t)t->n_nodes, -1);
-  std::vector<int32_t> stack{resolve(0)};
-  while (!stack.empty()) {
-    const int32_t i = stack.back();
-    stack.pop_back();
-    newid[(size_t)i] = (int32_t)order.size();
-    order.push_back(i);
+  int32_t* order = buf.order;  // kept nodes (old ids) in preorder
+  int32_t* newid = buf.newid;
+  int32_t* stack = buf.stack;  // a preorder walk keeps at most depth + 1 <= n_nodes entries
+  for (int32_t i = 0; i < t->n_nodes; ++i) newid[i] = -1;
+  int32_t m = 0, top = 0;
+  stack[top++] = resolve(0);
+  while (top > 0) {
+    const int32_t i = stack[--top];
+    newid[(size_t)i] = m;
+    order[m++] = i;
     if (t->left[(size_t)i] != -1) {
-      stack.push_back(resolve(t->right[(size_t)i]));
-      stack.push_back(resolve(t->left[(size_t)i]));
+      stack[top++] = resolve(t->right[(size_t)i]);
+      stack[top++] = resolve(t->left[(size_t)i]);
     }
   }
-  const int32_t m = (int32_t)order.size();
+  for (int32_t k = 0; k < m; ++k) {
+    const int32_t i = order[(size_t)k];
+    const bool leaf = t->left[(size_t)i] == -1;
+    const int32_t l = leaf ? -1 : newid[(size_t)resolve(t->left[(size_t)i])];
+    const int32_t r = leaf ? -1 : newid[(size_t)resolve(t->right[(size_t)i])];
+    const int32_t count = !leaf && t->feature[(size_t)i] >= 22 ? 1 : 0;  // discovered : frontier
+    buf.nodes[(size_t)k] = tree_node_pack(l, r, count, t->leaf_kernel[(size_t)i]);
+    buf.thr[(size_t)k] = leaf ? 0 : count_threshold(i);
+  }
+  return m;
+}
+
+namespace {
+
+// Device copy of the specialised tree, uploaded once per (workspace, tree).
+gsw_status ensure_tree(gsw_graph* g, const gsw_tree* t) {
+  Workspace& w = g->ws;
+  if (w.tree_id == t->id) return GSW_OK;
+  if (t->n_nodes > kMaxTreeNodes) return fail(GSW_EINVAL, "tree of %d nodes: at most %d", t->n_nodes, kMaxTreeNodes);
+  const size_t nn = (size_t)t->n_nodes;
+  std::vector<int32_t> order(nn), newid(nn), stack(nn + 1), thr(nn);
+  std::vector<unsigned long long> nodes(nn);
+  const TreeBuf buf{order.data(), newid.data(), stack.data(), nodes.data(), thr.data()};
+  const int32_t m = specialise_tree(g, t, buf);
   if (w.tree_cap < m) {
     if (w.d_tree) (void)hipFree(w.d_tree);
     if (w.d_thr) (void)hipFree(w.d_thr);
@@ -144,19 +165,8 @@ gsw_status ensure_tree(gsw_graph* g, const gsw_tree* t) {
     }
     w.tree_cap = m;
   }
-  std::vector<unsigned long long> nodes((size_t)m);
-  std::vector<int32_t> thr((size_t)m, 0);
-  for (int32_t k = 0; k < m; ++k) {
-    const int32_t i = order[(size_t)k];
-    const bool leaf = t->left[(size_t)i] == -1;
-    const int32_t l = leaf ? -1 : newid[(size_t)resolve(t->left[(size_t)i])];
-    const int32_t r = leaf ? -1 : newid[(size_t)resolve(t->right[(size_t)i])];
-    const int32_t count = !leaf && t->feature[(size_t)i] >= 22 ? 1 : 0;  // discovered : frontier
-    nodes[(size_t)k] = tree_node_pack(l, r, count, t->leaf_kernel[(size_t)i]);
-    if (!leaf) thr[(size_t)k] = count_threshold(i);
-  }
-  GSW_HIP(hipMemcpy(w.d_tree, nodes.data(), nodes.size() * sizeof(unsigned long long), hipMemcpyHostToDevice));
-  GSW_HIP(hipMemcpy(w.d_thr, thr.data(), thr.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  GSW_HIP(hipMemcpy(w.d_tree, nodes.data(), (size_t)m * sizeof(unsigned long long), hipMemcpyHostToDevice));
+  GSW_HIP(hipMemcpy(w.d_thr, thr.data(), (size_t)m * sizeof(int32_t), hipMemcpyHostToDevice));
   w.tree_nodes = m;
   w.tree_id = t->id;
   return GSW_OK;
@@ -183,7 +193,10 @@ gsw_status ensure_schedule(gsw_graph* g, const int32_t* sched, int32_t len) {
   return GSW_OK;
 }
 
-BfsPolicy device_policy(const gsw_graph* g, const gsw_bfs_opts* o, bool has_origin, bool has_rorigin) {
+}  // namespace
+
+BfsPolicy device_policy(const gsw_graph* g, const Workspace& w, const gsw_bfs_opts* o, bool has_origin,
+                        bool has_rorigin) {
   BfsPolicy p;
   std::memset(&p, 0, sizeof p);
   p.policy = o->policy;
@@ -192,15 +205,14 @@ BfsPolicy device_policy(const gsw_graph* g, const gsw_bfs_opts* o, bool has_orig
   p.symmetric = g->symmetric != 0;
   p.has_origin = has_origin ? 1 : 0;
   p.has_rorigin = has_rorigin ? 1 : 0;
-  p.sched = g->ws.d_sched;
-  p.t_node = g->ws.d_tree;
-  p.t_thr = g->ws.d_thr;
-  p.t_nodes = o->policy == GSW_POLICY_TREE && o->tree ? g->ws.tree_nodes : 0;
+  p.sched = w.d_sched;
+  p.t_node = w.d_tree;
+  p.t_thr = w.d_thr;
+  p.t_nodes = o->policy == GSW_POLICY_TREE && o->tree ? w.tree_nodes : 0;
   return p;
 }
 
-BfsBase make_base(const gsw_graph* g, int32_t* lv, int32_t* pa, bool timed, bool count_arcs) {
-  const Workspace& w = g->ws;
+BfsBase make_base(const gsw_graph* g, const Workspace& w, int32_t* lv, int32_t* pa, bool timed, bool count_arcs) {
   BfsBase b;
   std::memset(&b, 0, sizeof b);
   b.offs = g->offs;
@@ -233,38 +245,55 @@ BfsBase make_base(const gsw_graph* g, int32_t* lv, int32_t* pa, bool timed, bool
   return b;
 }
 
-// A level's record, decoded.
-struct Record {
-  int kernel;
-  int32_t flags;
-  int64_t nf, disc, next;
-  unsigned long long ticks;
-  int next_kernel;  // kCtlDone when the search ended
-  int64_t ef;       // arcs of the level's frontier, -1 when not counted
-};
+bool take_record(const volatile unsigned long long* ring, int64_t d, Record* rec) {
+  const volatile unsigned long long* r = ring + (size_t)(d % kBfsRing) * kBfsRec;
+  const unsigned long long tag = rec_tag(d);
+  unsigned long long v[kBfsRecWords];
+  for (int i = 0; i < kBfsRecWords; ++i) {
+    v[i] = r[i];
+    if ((v[i] & ~kRecValueMask) != tag) return false;
+    v[i] &= kRecValueMask;
+  }
+  rec->kernel = (int)v[kRecKernel];
+  rec->flags = (int32_t)v[kRecFlags];
+  rec->nf = (int64_t)v[kRecNf];
+  rec->disc = (int64_t)v[kRecDisc];
+  rec->next = (int64_t)v[kRecNext];
+  rec->ticks = v[kRecTicks];
+  rec->next_kernel = (int)v[kRecNextKernel] - 1;
+  rec->ef = (int64_t)v[kRecEf] - 1;
+  return true;
+}
+
+void trace_row(gsw_level_trace* t, int32_t src_idx, int64_t d, const Record& r, bool timed, double tick_ms) {
+  t->source_idx = src_idx;
+  t->level = (int32_t)d;
+  t->kernel = r.kernel;
+  t->flags = r.flags;
+  t->n_frontier = r.nf;
+  t->discovered = r.disc;
+  t->n_next = r.next;
+  t->e_frontier = r.ef;
+  t->ms = timed ? (float)((double)r.ticks * tick_ms) : -1.0f;
+  t->reserved = 0;
+}
+
+int32_t launch_size(int next_kernel, int64_t nn, int64_t nf, int64_t nf_prev, int64_t disc, int64_t d, int64_t n,
+                    int32_t cap) {
+  const int nb = next_kernel >= 0 ? kernel_base(next_kernel) : -1;
+  const bool queue_push = nb != GSW_K_PULL_BITMAP && nb != GSW_K_VERTEX_SCAN && nb != GSW_K_EDGE_SCAN &&
+                          nb != GSW_K_REV_EDGE_SCAN;
+  const bool quiet = queue_push && nn <= kSmallFrontier && nn <= 2 * nf && d > 0 && nf <= 2 * nf_prev &&
+                     (disc + nn) * 100 >= n;
+  return quiet && kSmallLaunch < cap ? kSmallLaunch : cap;
+}
+
+namespace {
 
 // Waits until level d's record is in the ring.  Polls the stream for errors
 // now and then so a failed launch cannot leave the host spinning.
 gsw_status wait_record(const gsw_graph* g, int64_t d, hipStream_t s, Record* rec) {
-  const volatile unsigned long long* r = g->ws.ring + (size_t)(d % kBfsRing) * kBfsRec;
-  const unsigned long long tag = rec_tag(d);
-  auto take = [&]() -> bool {
-    unsigned long long v[kBfsRecWords];
-    for (int i = 0; i < kBfsRecWords; ++i) {
-      v[i] = r[i];
-      if ((v[i] & ~kRecValueMask) != tag) return false;
-      v[i] &= kRecValueMask;
-    }
-    rec->kernel = (int)v[kRecKernel];
-    rec->flags = (int32_t)v[kRecFlags];
-    rec->nf = (int64_t)v[kRecNf];
-    rec->disc = (int64_t)v[kRecDisc];
-    rec->next = (int64_t)v[kRecNext];
-    rec->ticks = v[kRecTicks];
-    rec->next_kernel = (int)v[kRecNextKernel] - 1;
-    rec->ef = (int64_t)v[kRecEf] - 1;
-    return true;
-  };
+  auto take = [&]() -> bool { return take_record(g->ws.ring, d, rec); };
   for (uint64_t it = 0;; ++it) {
     if (take()) return GSW_OK;
     if ((it & 4095u) == 4095u) {
@@ -284,12 +313,21 @@ gsw_status run_levels(gsw_graph* g, const Policy& pol, const BfsPolicy& dp, int3
                       hipStream_t s) {
   Workspace& w = g->ws;
   const gsw_bfs_opts* o = pol.o;
-  const bool timed = o->time_levels != 0;
+  const bool events = o->time_levels == 2;  // per-launch HIP events
+  const bool timed = o->time_levels == 1;   // device wall-clock stamps
   std::memset(w.ring, 0, (size_t)kBfsRing * kBfsRec * sizeof(unsigned long long));
+  constexpr int kEv = Workspace::kLaunchEvents;
+  if (events)
+    for (hipEvent_t& e : w.lev)
+      if (!e) GSW_HIP(hipEventCreate(&e));
+  // event after launch j in slot (j + 1) % kEv; slot 0 follows the init kernel
+  auto ev_after = [&](int64_t jj) -> hipEvent_t& { return w.lev[(size_t)((jj + 1) % kEv)]; };
   int32_t flags0 = 0;
-  const int k0 = pol.choose(g, 0, 1, 1, GSW_DEFAULT_KERNEL, &flags0);
-  const BfsBase b = make_base(g, lv, pa, timed, o->count_arcs != 0);
-  GSW_TRY(launch_init(g, b, src, k0, flags0, s));
+  const int k0 = first_kernel(g, o, pol.has_origin, pol.has_rorigin, &flags0);
+  const BfsBase b = make_base(g, w, lv, pa, timed, o->count_arcs != 0);
+  GSW_TRY(launch_init(g, b, g->iso, src, k0, flags0, s));
+  if (events) GSW_HIP(hipEventRecord(ev_after(-1), s));
+  int64_t first_j = 0;  // first launch of the level whose record is read next
   int32_t j = 0;     // launches of the level kernel so far
   int ahead = 0;     // of those, not yet used by a level whose record was read
   int want = kAhead + level_launches(k0, 1) - 1;
@@ -299,6 +337,7 @@ gsw_status run_levels(gsw_graph* g, const Policy& pol, const BfsPolicy& dp, int3
   for (int64_t d = 0;; ++d) {
     while (ahead < want) {
       GSW_TRY(launch_level_auto(g, b, dp, j++, size, s));
+      if (events) GSW_HIP(hipEventRecord(ev_after(j - 1), s));
       ++ahead;
     }
     Record r;
@@ -306,29 +345,22 @@ gsw_status run_levels(gsw_graph* g, const Policy& pol, const BfsPolicy& dp, int3
     const int k = r.kernel;
     const int64_t nn = r.next;
     const int nk = r.next_kernel;
+    const int64_t last_j = first_j + level_launches(k, r.nf) - 1;
     if (trace && *rows < trace_cap) {
-      gsw_level_trace& t = trace[*rows];
-      t.source_idx = src_idx;
-      t.level = (int32_t)d;
-      t.kernel = k;
-      t.flags = r.flags;
-      t.n_frontier = r.nf;
-      t.discovered = r.disc;
-      t.n_next = nn;
-      t.e_frontier = r.ef;
-      t.ms = timed ? (float)((double)r.ticks * w.tick_ms) : -1.0f;
-      t.reserved = 0;
+      trace_row(&trace[*rows], src_idx, d, r, timed, w.tick_ms);
+      if (events) {
+        float ms = 0.0f;
+        GSW_HIP(hipEventSynchronize(ev_after(last_j)));
+        GSW_HIP(hipEventElapsedTime(&ms, ev_after(first_j - 1), ev_after(last_j)));
+        trace[*rows].ms = ms;
+      }
     }
+    first_j = last_j + 1;
     ++*rows;
     ahead -= level_launches(k, r.nf);
     if (nn == 0) break;
     want = kAhead + level_launches(nk, nn) - 1;
-    const int nb = nk >= 0 ? kernel_base(nk) : -1;
-    const bool queue_push = nb != GSW_K_PULL_BITMAP && nb != GSW_K_VERTEX_SCAN && nb != GSW_K_EDGE_SCAN &&
-                            nb != GSW_K_REV_EDGE_SCAN;
-    const bool quiet = queue_push && nn <= kSmallFrontier && nn <= 2 * r.nf && d > 0 && r.nf <= 2 * nf_prev &&
-                       (r.disc + nn) * 100 >= g->n;
-    size = quiet && kSmallLaunch < cap ? kSmallLaunch : cap;
+    size = launch_size(nk, nn, r.nf, nf_prev, r.disc, d, g->n, cap);
     nf_prev = r.nf;
   }
   if (o->canonical_parents && pa) GSW_TRY(launch_canonical_parents(g, lv, pa, s));
@@ -383,7 +415,7 @@ gsw_status bfs_sources(gsw_graph* g, const gsw_bfs_opts* o, const int32_t* sourc
   const bool has_origin = g->origin != nullptr || g->nnz == 0;
   const bool has_rorigin = g->rorigin != nullptr || g->nnz == 0;
   const Policy pol{o, has_origin, has_rorigin};
-  const BfsPolicy dp = device_policy(g, o, has_origin, has_rorigin);
+  const BfsPolicy dp = device_policy(g, g->ws, o, has_origin, has_rorigin);
   const int64_t n = g->n;
   for (int32_t i = 0; i < n_sources; ++i) {
     int32_t* lv = o->device_ptrs ? levels + (size_t)i * n : g->ws.lvl_tmp;
@@ -508,10 +540,10 @@ gsw_status gsw_bfs_profile(const gsw_graph* cg, int32_t source, const int32_t* k
   fo.fixed_kernel = GSW_DEFAULT_KERNEL;
   const bool has_origin = g->origin != nullptr || g->nnz == 0;
   const bool has_rorigin = g->rorigin != nullptr || g->nnz == 0;
-  const BfsPolicy dp = device_policy(g, &fo, has_origin, has_rorigin);
-  const BfsBase b = make_base(g, lv, pa, false, false);
+  const BfsPolicy dp = device_policy(g, w, &fo, has_origin, has_rorigin);
+  const BfsBase b = make_base(g, w, lv, pa, false, false);
   std::memset(w.ring, 0, (size_t)kBfsRing * kBfsRec * sizeof(unsigned long long));
-  GSW_TRY(launch_init(g, b, source, GSW_DEFAULT_KERNEL, 0, s));
+  GSW_TRY(launch_init(g, b, g->iso, source, GSW_DEFAULT_KERNEL, 0, s));
   GSW_HIP(hipStreamSynchronize(s));
   int64_t nf = 1;
   uint32_t bins[kQueueBins] = {1};  // segment sizes of the current queue

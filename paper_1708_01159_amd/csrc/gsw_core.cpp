@@ -380,6 +380,8 @@ void free_graph(gsw_graph* g) {
   if (g->iso) (void)hipFree(g->iso);
   for (hipEvent_t ev : w.ev)
     if (ev) (void)hipEventDestroy(ev);
+  for (hipEvent_t ev : w.lev)
+    if (ev) (void)hipEventDestroy(ev);
   if (g->owns_csr) {
     if (g->offs) (void)hipFree((void*)g->offs);
     if (g->cols) (void)hipFree((void*)g->cols);

@@ -88,6 +88,8 @@ struct Workspace {
   int32_t sched_cap = 0;
   std::vector<int32_t> sched_host;       // the schedule that d_sched holds
   hipEvent_t ev[2] = {};
+  static constexpr int kLaunchEvents = 16;  // ring of per-launch events (time_levels = 2)
+  hipEvent_t lev[kLaunchEvents] = {};
   double tick_ms = 0.0;                  // milliseconds per wall-clock tick
   size_t bytes = 0;
   bool head_built = false;               // head holds the graph's rows
@@ -248,8 +250,9 @@ __host__ __device__ inline unsigned long long rec_tag(long long d) {
 }
 
 // Kernel launchers (gsw_kernels.hip).
-gsw_status launch_init(const gsw_graph* g, const BfsBase& b, int32_t source, int32_t k0, int32_t flags0,
-                       hipStream_t s);
+// iso: bitmap of the vertices without in-arcs (they start visited), or null.
+gsw_status launch_init(const gsw_graph* g, const BfsBase& b, const unsigned long long* iso, int32_t source,
+                       int32_t k0, int32_t flags0, hipStream_t s);
 // Launch j (counted from 0 after launch_init) of the level kernel: runs what
 // control slot j % 2 names -- a level, or the scan or the expansion of a
 // push_edge level -- or nothing once the search has ended.  `workgroups`
@@ -266,6 +269,38 @@ gsw_status launch_canonical_parents(const gsw_graph* g, const int32_t* level, in
                                     hipStream_t s);
 gsw_status launch_build_origin(const int64_t* offs, int64_t n, int32_t* origin, hipStream_t s);
 gsw_status launch_build_head(const gsw_graph* g, int32_t* head, hipStream_t s);
+
+// ----- pieces of the single-source level loop (gsw_bfs.cpp)
+// A level's record, decoded.
+struct Record {
+  int kernel;
+  int32_t flags;
+  int64_t nf, disc, next;
+  unsigned long long ticks;
+  int next_kernel;  // kCtlDone when the search ended
+  int64_t ef;       // arcs of the level's frontier, -1 when not counted
+};
+// Level d's record from a ring (host memory), if all its words bear d's tag.
+bool take_record(const volatile unsigned long long* ring, int64_t d, Record* rec);
+void trace_row(gsw_level_trace* t, int32_t src_idx, int64_t d, const Record& r, bool timed, double tick_ms);
+// Workgroups for the launches queued after a record (quiet phases get few).
+int32_t launch_size(int next_kernel, int64_t nn, int64_t nf, int64_t nf_prev, int64_t disc, int64_t d, int64_t n,
+                    int32_t cap);
+// Level 0's kernel on the host (the device applies the same rules later).
+int first_kernel(const gsw_graph* g, const gsw_bfs_opts* o, bool has_origin, bool has_rorigin, int32_t* flags);
+// Buffers for specialise_tree, each with room for the tree's n_nodes
+// (stack: n_nodes + 1); nodes/thr receive the specialised tree.
+struct TreeBuf {
+  int32_t *order, *newid, *stack;
+  unsigned long long* nodes;
+  int32_t* thr;
+};
+// The tree specialised to the graph (splits on graph features decided, level
+// splits as integer count thresholds); returns its node count.
+int32_t specialise_tree(const gsw_graph* g, const gsw_tree* t, const TreeBuf& buf);
+BfsPolicy device_policy(const gsw_graph* g, const Workspace& w, const gsw_bfs_opts* o, bool has_origin,
+                        bool has_rorigin);
+BfsBase make_base(const gsw_graph* g, const Workspace& w, int32_t* lv, int32_t* pa, bool timed, bool count_arcs);
 
 gsw_status ensure_workspace(gsw_graph* g);
 size_t workspace_bytes(const gsw_graph* g);  // what ensure_workspace allocates in all

@@ -1510,12 +1510,12 @@ int32_t level_kernel_grid(int64_t n, int64_t nw) {
 
 bool kernel_is_pull(int k) { return k >= 0 && kernel_base(k) == GSW_K_PULL_BITMAP; }
 
-gsw_status launch_init(const gsw_graph* g, const BfsBase& b, int32_t source, int32_t k0, int32_t flags0,
-                       hipStream_t s) {
+gsw_status launch_init(const gsw_graph* g, const BfsBase& b, const unsigned long long* iso, int32_t source,
+                       int32_t k0, int32_t flags0, hipStream_t s) {
   int64_t blocks = cdiv(g->n, kBlock * 4);
   if (blocks < cdiv(4 * kCtrSlot, kBlock)) blocks = cdiv(4 * kCtrSlot, kBlock);
   const unsigned grid = (unsigned)(blocks > kMaxGrid ? kMaxGrid : blocks);
-  hipLaunchKernelGGL(k_init, dim3(grid), dim3(kBlock), 0, s, b, (const u64*)g->iso, source, k0, flags0);
+  hipLaunchKernelGGL(k_init, dim3(grid), dim3(kBlock), 0, s, b, (const u64*)iso, source, k0, flags0);
   GSW_HIP(hipGetLastError());
   return GSW_OK;
 }

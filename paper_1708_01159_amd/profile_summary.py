@@ -1,0 +1,156 @@
+"""Per-variant summary of a rocprofv3-profiled benchmark run (no GPU needed).
+
+Every expansion variant runs inside one kernel, k_level_auto, so the
+profiler's per-kernel rows cannot tell them apart.  The benchmark's
+``--dispatch-log`` records, for every BFS call, each level's kernel id,
+frontier size and algorithmic bytes (both byte models).  Each call starts
+with one k_init dispatch; each level then takes one k_level_auto launch (two
+for push_edge on more than 512 entries); the call's remaining launches find
+the search ended.  Aligning the dispatches in start order with that log
+labels every level-kernel dispatch with the variant it ran, for the kernel
+trace and for the FETCH_SIZE / WRITE_SIZE counter runs alike.
+
+The summary gives, for the dominant variant, the mean algorithmic bytes and
+the mean rocprofv3 duration over the same set of dispatches (every call of
+the profiled command: warm-up, timed steps and the instrumented pass over
+all sources), so its roofline fraction can be recomputed from the summary
+alone.  Counter bytes are scaled by what the same counters read for a plain
+1 GiB device copy in the same run.
+"""
+from __future__ import annotations
+
+import csv
+import hashlib
+import json
+import os
+
+import numpy as np
+
+EDGE_FUSE = 512  # the library's one-launch limit for push_edge frontiers
+N_BASE = 11
+PUSH_EDGE = 6
+PROFILE_CMD = ("python3 -u bench.py --steps 2 --warmup 1 --no-compare --copy-calib --cpu-budget 1 "
+               "--dispatch-log {d}/dispatch_log.json")
+HBM_PEAK_GBS = 8000.0
+
+
+def _csv_rows(path):
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def _short(name):
+    name = name.replace("gsw::(anonymous namespace)::", "").replace("void ", "")
+    return name.split("(")[0][:48]
+
+
+def _align(dispatches, calls, names):
+    """Label each dispatch (in start order) with (variant, bytes, literal bytes)."""
+    labels = [None for _ in dispatches]
+    starts = [i for i, d in enumerate(dispatches) if _short(d[0]) == "k_init"]
+    if len(starts) != len(calls):
+        raise SystemExit("profile has %d k_init dispatches, the dispatch log %d calls" % (len(starts), len(calls)))
+    for c, (i0, call) in enumerate(zip(starts, calls)):
+        i1 = starts[c + 1] if c + 1 < len(starts) else len(dispatches)
+        mine = [i for i in range(i0 + 1, i1) if _short(dispatches[i][0]) == "k_level_auto"]
+        want = []
+        for k, nf, b, lit in call["levels"]:
+            if k % N_BASE == PUSH_EDGE and nf > EDGE_FUSE:
+                want += [(names[k] + " (prefix)", None, None), (names[k] + " (expand)", b, None)]
+            else:
+                want.append((names[k], b, lit))
+        if len(want) > len(mine):
+            raise SystemExit("call %d: %d level launches logged, %d dispatched" % (c, len(want), len(mine)))
+        for j, i in enumerate(mine):
+            labels[i] = want[j] if j < len(want) else ("(search ended)", None, None)
+    return labels
+
+
+def summarize(d, root):
+    from . import gsw
+
+    calls = json.load(open(os.path.join(d, "dispatch_log.json")))
+    bench_line = json.loads(open(os.path.join(d, "trace_bench.json")).read().strip().splitlines()[-1])
+    tr = sorted(_csv_rows(os.path.join(d, "trace", "run_kernel_trace.csv")), key=lambda r: int(r["Start_Timestamp"]))
+    disp = [(r["Kernel_Name"], (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3) for r in tr]
+    lab = _align(disp, calls, gsw.KERNEL_NAMES)
+
+    def counters(sub, name):
+        rows = [r for r in _csv_rows(os.path.join(d, sub, "run_counter_collection.csv")) if r["Counter_Name"] == name]
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        vals = [(r["Kernel_Name"], float(r["Counter_Value"])) for r in rows]
+        return vals, _align(vals, calls, gsw.KERNEL_NAMES)
+
+    fe, fe_lab = counters("fetch", "FETCH_SIZE")
+    wr, wr_lab = counters("write", "WRITE_SIZE")
+    GiB = 1 << 30
+    copy_f = sorted(v for n, v in fe if "copyBuffer" in n)[-2:]
+    copy_w = sorted(v for n, v in wr if "copyBuffer" in n)[-2:]
+    f_scale = GiB / (np.mean(copy_f) * 1024)
+    w_scale = GiB / (np.mean(copy_w) * 1024)
+
+    def key(name, label):
+        return label[0] if label else _short(name)
+
+    stat = {}
+    for (n, t), l in zip(disp, lab):
+        st = stat.setdefault(key(n, l), {"t": [], "f": [], "w": [], "b": [], "lit": []})
+        st["t"].append(t)
+        if l and l[1] is not None:
+            st["b"].append(l[1])
+        if l and l[2] is not None:
+            st["lit"].append(l[2])
+    for (n, v), l in zip(fe, fe_lab):
+        stat.setdefault(key(n, l), {"t": [], "f": [], "w": [], "b": [], "lit": []})["f"].append(v)
+    for (n, v), l in zip(wr, wr_lab):
+        stat.setdefault(key(n, l), {"t": [], "f": [], "w": [], "b": [], "lit": []})["w"].append(v)
+    rl = bench_line["roofline"]
+    dom = rl["kernel"]
+    sha = hashlib.sha256(open(os.path.join(root, "paper_1708_01159_amd", "csrc", "gsw_kernels.hip"), "rb")
+                         .read()).hexdigest()
+    L = ["# %s on R-MAT scale 22 (%d sources, tree-switched path)" % (dom, rl["sources"]), "",
+         "Commands (from the repository root, `TMPDIR=/tmp`; the trace run's stdout is `trace_bench.json`):", "",
+         "```",
+         "rocprofv3 --kernel-trace --stats --output-format csv -d {d}/trace -o run -- ".format(d=d)
+         + PROFILE_CMD.format(d=d),
+         "rocprofv3 --pmc FETCH_SIZE --output-format csv -d {d}/fetch -o run -- ".format(d=d) + PROFILE_CMD.format(d=d),
+         "rocprofv3 --pmc WRITE_SIZE --output-format csv -d {d}/write -o run -- ".format(d=d) + PROFILE_CMD.format(d=d),
+         "python3 bench.py --summarize-profile " + d, "```", "",
+         "Every dispatch of the command (warm-up, 2 timed steps, the event-timed pass), under the profiler. "
+         "The level kernel's dispatches are attributed to the variant each ran from the dispatch log:", "",
+         "| kernel / variant | dispatches | avg us | total us | FETCH_SIZE avg KB | WRITE_SIZE avg KB | algorithmic MB avg |",
+         "|---|---:|---:|---:|---:|---:|---:|"]
+    for k in sorted(stat, key=lambda k: -sum(stat[k]["t"])):
+        st = stat[k]
+        L.append("| %s | %d | %.2f | %.1f | %.1f | %.1f | %s |" % (
+            k, len(st["t"]), np.mean(st["t"]) if st["t"] else 0, np.sum(st["t"]),
+            np.mean(st["f"]) if st["f"] else 0, np.mean(st["w"]) if st["w"] else 0,
+            "%.2f" % (np.mean(st["b"]) / 1e6) if st["b"] else "-"))
+    s = stat[dom]
+    fetched = np.mean(s["f"]) * 1024 * f_scale
+    written = np.mean(s["w"]) * 1024 * w_scale
+    traffic = fetched + written
+    alg = float(np.mean(s["b"]))
+    dur = float(np.mean(s["t"]))
+    achieved = alg / (dur * 1e-6) / 1e9
+    L += ["", "Counter scale from the plain 1 GiB device copy (`__amd_rocclr_copyBuffer`, 1 GiB read + "
+          "1 GiB written): FETCH_SIZE x %.3f, WRITE_SIZE x %.3f." % (f_scale, w_scale), "",
+          "%s per launch, over the same %d dispatches:" % (dom, len(s["t"])), "",
+          "* algorithmic bytes (library byte model): **%.2f MB**%s" % (
+              alg / 1e6, "; the scope table's literal pull formula: %.2f MB" % (np.mean(s["lit"]) / 1e6)
+              if s["lit"] else ""),
+          "* rocprofv3 mean duration: **%.2f us** -> %.0f GB/s = **%.3f** of %.0f GB/s%s" % (
+              dur, achieved, achieved / HBM_PEAK_GBS, HBM_PEAK_GBS,
+              " (literal formula: %.3f)" % (np.mean(s["lit"]) / (dur * 1e-6) / 1e9 / HBM_PEAK_GBS)
+              if s["lit"] else ""),
+          "* HBM traffic (scaled counters): %.1f MB fetched + %.1f MB written = **%.1f MB**; "
+          "traffic / algorithmic = %.2f" % (fetched / 1e6, written / 1e6, traffic / 1e6, traffic / alg),
+          "* the bench line of this run (event-timed pass, its own launches): %.2f MB per launch, %.2f us, "
+          "frac %.3f; value %.1f GTEPS (under the profiler)" % (
+              rl["bytes_per_launch"] / 1e6, rl["mean_launch_ms"] * 1e3, rl["frac"], bench_line["value"]), "",
+          "Machine-readable (read by bench.py while the kernel source is unchanged):", "", "```",
+          "kernel: %s" % dom, "dispatches: %d" % len(s["t"]),
+          "algorithmic_bytes_per_launch: %d" % alg, "mean_duration_us: %.3f" % dur,
+          "frac_of_8tbs: %.4f" % (achieved / HBM_PEAK_GBS),
+          "traffic_bytes_per_launch: %d" % traffic, "kernel_source_sha256: %s" % sha, "```"]
+    return "\n".join(L)

@@ -353,3 +353,11 @@ def summarize(queries, residents, label):
     return {"mode": label, "queries": len(queries), "p50_ms": round(float(np.percentile(lat, 50)), 3),
             "p99_ms": round(float(np.percentile(lat, 99)), 3), "mean_ms": round(float(lat.mean()), 3),
             "gteps": round(edges / span / 1e9, 3), "makespan_s": round(span, 3)}
+
+
+def per_graph_p99(queries):
+    """p99 latency (ms) of each graph's queries."""
+    by = {}
+    for q in queries:
+        by.setdefault(q.graph, []).append((q.t_done - q.t_arrival) * 1e3)
+    return {g: round(float(np.percentile(v, 99)), 3) for g, v in sorted(by.items())}

@@ -3,7 +3,9 @@
 Measurement arithmetic for the roofline: what each expansion kernel must move
 at level d, counted at the granularity it accesses (4-byte ids and levels,
 8-byte offsets, 64-bit bitmap words).  Computed exactly on the host from a
-level array (the GPU's own output) and the sorted CSR.
+level array (the GPU's own output) and the sorted CSR of a symmetric graph;
+the per-level counts come from one pass over the rows in C
+(``csrc/traffic_model.cpp``, OpenMP).
 
 Terms (n_f = depth-d vertices, e_f = sum of their degrees, n_x = depth-(d+1)
 vertices, nw = ceil(n/64) bitmap words):
@@ -16,20 +18,85 @@ vertices, nw = ceil(n/64) bitmap words):
     vertex_scan:             + n*4 (every level read) + n_f*16
     edge_scan:               + nnz*4 (origin of every arc) + n*4 (its level,
                                read once per origin run)
+    rev_edge_scan:           + nnz*4 (destination of every arc) + nw*8 (its
+                               visited word, read once per run of a word)
   pull_bitmap    + nw*8 (visited words) + sum over unvisited v of
                  (16 row offsets + p_v*(4 column + 8 frontier word))
                  + 16 per word holding a discovery (visited and next words),
                  where p_v counts the neighbours read up to the first one in
-                 the frontier (all of them when none is).  On a symmetric
-                 graph degree-0 vertices start visited (the search marks them
-                 at init), so they cost only their visited bit.
+                 the frontier (all of them when none is).  Degree-0 vertices
+                 start visited (the search marks them at init), so they cost
+                 only their visited bit.
+
+``pull_bytes_literal`` is the pull formula exactly as the scope table writes
+it -- (n/64)*8*3 for the visited, frontier and next words, 16 + p_v*12 for
+every unvisited vertex including the degree-0 ones, and n_x*12 -- reported
+beside the model above.
 """
 from __future__ import annotations
+
+import ctypes
+import os
 
 import numpy as np
 
 PUSH_FAMILY = (0, 1, 2, 3, 4, 5)
-PUSH_EDGE, PULL, VERTEX_SCAN, EDGE_SCAN = 6, 7, 8, 9
+PUSH_EDGE, PULL, VERTEX_SCAN, EDGE_SCAN, REV_EDGE_SCAN = 6, 7, 8, 9, 10
+N_BASE = 11
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libgswmodel.so")
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build
+
+            build.build_model()
+        L = ctypes.CDLL(_LIB_PATH)
+        L.tm_level_counts.restype = ctypes.c_int64
+        L.tm_level_counts.argtypes = [ctypes.c_int64] + [ctypes.c_void_p] * 3 + [ctypes.c_int64] + \
+            [ctypes.c_void_p] * 4
+        _lib = L
+    return _lib
+
+
+class Counts:
+    """Per-depth counts of one source's BFS (see ``csrc/traffic_model.cpp``)."""
+
+    def __init__(self, offs, cols, level, source: int):
+        offs = np.ascontiguousarray(offs, dtype=np.int64)
+        cols = np.ascontiguousarray(cols, dtype=np.int32)
+        level = np.ascontiguousarray(level, dtype=np.int32)
+        n = level.shape[0]
+        cap = int(level.max()) + 2
+        self.nf, self.ef, self.words, self.save = (np.zeros(cap, dtype=np.int64) for _ in range(4))
+        D = _load().tm_level_counts(n, offs.ctypes.data, cols.ctypes.data, level.ctypes.data, cap,
+                                    self.nf.ctypes.data, self.ef.ctypes.data, self.words.ctypes.data,
+                                    self.save.ctypes.data)
+        if D < 0:
+            raise ValueError("level array deeper than its own maximum")
+        self.D = int(D)
+        self.n = n
+        self.nnz = int(offs[-1])
+        self.nw = (n + 63) // 64
+        self.n_pos = int(np.count_nonzero(offs[1:] > offs[:-1]))  # vertices with arcs
+        self.src_isolated = int(offs[source + 1] == offs[source])
+        self.cum_nf = np.cumsum(self.nf)
+        self.cum_ef = np.cumsum(self.ef)
+
+    def at(self, a, d):
+        return int(a[d]) if 0 <= d < a.shape[0] else 0
+
+    def pull_terms(self, d: int):
+        """(probes, unvisited vertices with arcs, unvisited vertices) at level d."""
+        probes = self.nnz - self.at(self.cum_ef, d) - self.at(self.save, d)
+        reached = self.at(self.cum_nf, d)
+        unv_pos = self.n_pos - (reached - self.src_isolated)
+        return probes, unv_pos, self.n - reached
 
 
 def component_edges(offs, level) -> int:
@@ -49,18 +116,47 @@ def level_sizes(offs, level):
     return nf, ef
 
 
-def pull_probes(offs, cols, level, d: int, skip_isolated: bool = True):
-    """(sum of p_v, unvisited count, words with a discovery) for a pull at
-    level d; degree-0 vertices are left out when ``skip_isolated``."""
+def level_bytes(kernel: int, c: Counts, d: int) -> int:
+    """Algorithmic bytes of running ``kernel`` (a kernel id: the count
+    variant does not change them) at level d (see module doc)."""
+    k = kernel % N_BASE
+    n_f, e_f, n_x = c.at(c.nf, d), c.at(c.ef, d), c.at(c.nf, d + 1)
+    b = c.nw * 8 + n_x * 12
+    if k == PULL:
+        probes, unv_pos, _ = c.pull_terms(d)
+        return b + c.nw * 8 + unv_pos * 16 + probes * 12 + c.at(c.words, d + 1) * 16
+    b += e_f * 12 + n_x * 8
+    if k in PUSH_FAMILY:
+        return b + n_f * 20
+    if k == PUSH_EDGE:
+        return b + n_f * (20 + 16 + 20)
+    if k == VERTEX_SCAN:
+        return b + c.n * 4 + n_f * 16
+    if k == EDGE_SCAN:
+        return b + c.nnz * 4 + c.n * 4
+    if k == REV_EDGE_SCAN:
+        return b + c.nnz * 4 + c.nw * 8
+    raise ValueError("unknown kernel %r" % kernel)
+
+
+def pull_bytes_literal(c: Counts, d: int) -> int:
+    """The pull formula as the scope table writes it (degree-0 vertices
+    counted as unvisited, 24 bytes per bitmap word)."""
+    probes, _, unv_all = c.pull_terms(d)
+    return c.nw * 8 * 3 + unv_all * 16 + probes * 12 + c.at(c.nf, d + 1) * 12
+
+
+def pull_probes_reference(offs, cols, level, d: int, skip_isolated: bool = True):
+    """(sum of p_v, unvisited count) for a pull at level d, by walking every
+    unvisited row in numpy (slow; the check of ``Counts``)."""
     offs = np.asarray(offs, dtype=np.int64)
     lv = np.asarray(level)
-    n = lv.shape[0]
     unvisited = (lv == -1) | (lv > d)
     if skip_isolated:
         unvisited &= offs[1:] > offs[:-1]
     unv = np.flatnonzero(unvisited)
     if unv.shape[0] == 0:
-        return 0, 0, 0
+        return 0, 0
     deg = offs[unv + 1] - offs[unv]
     total = int(deg.sum())
     probes = deg.copy()
@@ -70,41 +166,10 @@ def pull_probes(offs, cols, level, d: int, skip_isolated: bool = True):
         row = np.repeat(np.arange(unv.shape[0], dtype=np.int64), deg)
         pos = np.arange(total, dtype=np.int64) - csum[row]
         hit = lv[cols[offs[unv][row] + pos]] == d
-        hr = row[hit]
-        hp = pos[hit]
+        hr, hp = row[hit], pos[hit]
         if hr.shape[0]:
             first = np.empty(hr.shape[0], dtype=bool)
             first[0] = True
             first[1:] = hr[1:] != hr[:-1]
             probes[hr[first]] = hp[first] + 1
-    found_words = np.unique(np.flatnonzero(lv == d + 1) >> 6).shape[0]
-    return int(probes.sum()), int(unv.shape[0]), int(found_words)
-
-
-def level_bytes(kernel: int, offs, cols, level, d: int, nf=None, ef=None, skip_isolated: bool = True) -> int:
-    """Algorithmic bytes of running ``kernel`` at level d (see module doc);
-    ``skip_isolated``: the graph is symmetric, degree-0 vertices start visited."""
-    offs = np.asarray(offs, dtype=np.int64)
-    lv = np.asarray(level)
-    n = lv.shape[0]
-    nnz = int(offs[-1])
-    nw = (n + 63) // 64
-    if nf is None or ef is None:
-        nf, ef = level_sizes(offs, lv)
-    n_f = int(nf[d]) if d < nf.shape[0] else 0
-    e_f = int(ef[d]) if d < ef.shape[0] else 0
-    n_x = int(nf[d + 1]) if d + 1 < nf.shape[0] else 0
-    b = nw * 8 + n_x * 12
-    if kernel == PULL:
-        p, nu, words = pull_probes(offs, cols, lv, d, skip_isolated)
-        return b + nw * 8 + nu * 16 + p * 12 + words * 16
-    b += e_f * 12 + n_x * 8
-    if kernel in PUSH_FAMILY:
-        return b + n_f * 20
-    if kernel == PUSH_EDGE:
-        return b + n_f * (20 + 16 + 20)
-    if kernel == VERTEX_SCAN:
-        return b + n * 4 + n_f * 16
-    if kernel == EDGE_SCAN:
-        return b + nnz * 4 + n * 4
-    raise ValueError("unknown kernel %r" % kernel)
+    return int(probes.sum()), int(unv.shape[0])

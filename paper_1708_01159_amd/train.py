@@ -1,4 +1,4 @@
-"""Training data, tree fitting and export (Sections IV-A and IV-D).
+"""Training data, tree fitting and export (Sections IV-A, IV-B and IV-D).
 
 The paper measures every implementation at every BFS level of many graphs
 and roots, labels each level with its fastest implementation, and fits a
@@ -7,20 +7,31 @@ it on the other 30%.  The tree is then exported to flat arrays for a C
 lookup.  Here:
 
   collect  per (graph, source, level): the library's feature vector and the
-           median time of every kernel from the same saved BFS state
+           median time of every kernel (33: eleven base kernels in three
+           frontier-count variants) from the same saved BFS state
            (gsw_bfs_profile); the BFS advances with the level's fastest kernel.
-  fit      DecisionTreeClassifier(criterion="gini") on the rows, with the
-           paper's random 70/30 row split and, as a harder check, a split
-           that holds out whole graphs; reports accuracy, the mean slowdown of
-           the predicted kernel against the fastest one, and Gini importance.
-  export   JSON with the flat node arrays gsw_tree_create() takes.
+  fit      DecisionTreeClassifier(criterion="gini").  Hyper-parameters (depth,
+           minimum leaf, row weights) are chosen by the total-time ratio on
+           VALIDATION graphs -- graphs of their own, disjoint from the
+           training graphs and from every evaluated workload -- and the
+           shipped tree is trained on the training graphs only.  The report
+           gives the paper's random 70/30 row split, a held-out-graph split of
+           the training graphs, the validation graphs, and Table II of the
+           paper computed on the validation traversals (slowdown against the
+           best-per-level traversal for the tree, the best fixed kernel per
+           graph, and every kernel).  The model variants the paper names as
+           future work are fitted on the same rows and reported beside it: a
+           regression tree per kernel (predict each kernel's level time, take
+           the smallest) and a random forest classifier.
+  export   JSON with the flat node arrays gsw_tree_load() reads.
 
-Workloads for training are synthetic graphs of the evaluated families at
-other seeds and sizes; the graphs and sources evaluated by the benchmark are
-never trained on.
+Every graph here is a synthetic family member at its own seed; the graphs and
+sources evaluated by the benchmark (R-MAT 22 seed 2, the sweep's grid, Chung-Lu
+and Erdos-Renyi graphs) are never trained or validated on.
 
     python -m paper_1708_01159_amd.train collect --out rows.npz
-    python -m paper_1708_01159_amd.train fit --rows rows.npz --out trees/mi355x.json
+    python -m paper_1708_01159_amd.train collect --set valid --out valid.npz
+    python -m paper_1708_01159_amd.train fit --rows rows.npz --valid valid.npz --out trees/mi355x.json
 """
 from __future__ import annotations
 
@@ -37,32 +48,53 @@ from . import gsw
 
 FEATURES = gsw.FEATURE_NAMES
 
+
+def _directed(make, keep: float, seed: int, name: str):
+    """A random ``keep`` share of a symmetric graph's arcs: one-way and
+    reciprocated arcs, so in-, out- and absolute degrees differ."""
+    def build():
+        g = make()
+        rows = np.repeat(np.arange(g.n), g.degrees())
+        m = np.random.default_rng(seed).random(g.nnz) < keep
+        return gg.from_edges(g.n, rows[m], g.cols[m], symmetrize=False, name=name)
+    return build
+
+
 # (name, maker, sources) -- other seeds / sizes than the evaluated workloads
 TRAIN_GRAPHS = [
     ("rmat16_s100", lambda: gg.rmat(16, 16, seed=100), 12),
     ("rmat18_s101", lambda: gg.rmat(18, 16, seed=101), 12),
-    ("rmat20_s102", lambda: gg.rmat(20, 16, seed=102), 16),
-    ("rmat21_ef8_s103", lambda: gg.rmat(21, 8, seed=103), 16),
-    ("rmat21_s104", lambda: gg.rmat(21, 16, seed=104), 16),
-    ("rmat19_ef32_s105", lambda: gg.rmat(19, 32, seed=105), 12),
-    ("rmat20_flat_s106", lambda: gg.rmat(20, 16, 0.45, 0.22, 0.22, seed=106), 12),
-    ("grid256_del5_s200", lambda: gg.grid(256, 256, 0.05, seed=200), 3),
+    ("rmat20_s102", lambda: gg.rmat(20, 16, seed=102), 12),
+    ("rmat21_ef8_s103", lambda: gg.rmat(21, 8, seed=103), 12),
+    ("rmat19_ef32_s105", lambda: gg.rmat(19, 32, seed=105), 8),
+    ("rmat20_flat_s106", lambda: gg.rmat(20, 16, 0.45, 0.22, 0.22, seed=106), 8),
+    ("rmat22_s200", lambda: gg.rmat(22, 16, seed=200), 16),
+    ("rmat22_s201", lambda: gg.rmat(22, 16, seed=201), 16),
+    ("grid256_del5_s200", lambda: gg.grid(256, 256, 0.05, seed=200), 2),
     ("grid512x256_del2_s201", lambda: gg.grid(512, 256, 0.02, seed=201), 2),
-    ("grid1024_del5_s202", lambda: gg.grid(1024, 1024, 0.05, seed=202), 2),
-    ("chunglu18_s300", lambda: gg.chung_lu(1 << 18, 2.1, 20.0, seed=300), 12),
-    ("chunglu20_s301", lambda: gg.chung_lu(1 << 20, 2.1, 20.0, seed=301), 12),
-    ("chunglu21_g25_s302", lambda: gg.chung_lu(1 << 21, 2.5, 10.0, seed=302), 12),
-    ("er18_d8_s400", lambda: gg.erdos_renyi(1 << 18, 4 << 18, seed=400), 16),
-    ("er20_d8_s401", lambda: gg.erdos_renyi(1 << 20, 4 << 20, seed=401), 16),
-    ("er21_d4_s402", lambda: gg.erdos_renyi(1 << 21, 2 << 21, seed=402), 16),
-    ("er20_d32_s403", lambda: gg.erdos_renyi(1 << 20, 16 << 20, seed=403), 16),
-    # the evaluated sizes, at other seeds
-    ("rmat22_s200", lambda: gg.rmat(22, 16, seed=200), 32),
-    ("rmat22_s201", lambda: gg.rmat(22, 16, seed=201), 32),
-    ("rmat22_s202", lambda: gg.rmat(22, 16, seed=202), 32),
-    ("grid2048_del5_s210", lambda: gg.grid(2048, 2048, 0.05, seed=210), 2),
-    ("chunglu23_s220", lambda: gg.chung_lu(1 << 23, 2.1, 20.0, seed=220), 16),
-    ("er22_d8_s230", lambda: gg.erdos_renyi(1 << 22, 4 << 22, seed=230), 24),
+    ("grid1024_del5_s202", lambda: gg.grid(1024, 1024, 0.05, seed=202), 1),
+    ("chunglu18_s300", lambda: gg.chung_lu(1 << 18, 2.1, 20.0, seed=300), 8),
+    ("chunglu20_s301", lambda: gg.chung_lu(1 << 20, 2.1, 20.0, seed=301), 8),
+    ("chunglu21_g25_s302", lambda: gg.chung_lu(1 << 21, 2.5, 10.0, seed=302), 8),
+    ("chunglu22_s303", lambda: gg.chung_lu(1 << 22, 2.1, 20.0, seed=303), 8),
+    ("er18_d8_s400", lambda: gg.erdos_renyi(1 << 18, 4 << 18, seed=400), 8),
+    ("er20_d8_s401", lambda: gg.erdos_renyi(1 << 20, 4 << 20, seed=401), 8),
+    ("er21_d4_s402", lambda: gg.erdos_renyi(1 << 21, 2 << 21, seed=402), 8),
+    ("er20_d32_s403", lambda: gg.erdos_renyi(1 << 20, 16 << 20, seed=403), 8),
+    ("er22_d8_s404", lambda: gg.erdos_renyi(1 << 22, 4 << 22, seed=404), 8),
+    ("rmat20_dir60_s500", _directed(lambda: gg.rmat(20, 16, seed=500), 0.6, 500, "rmat20_dir60_s500"), 8),
+    ("chunglu20_dir50_s501", _directed(lambda: gg.chung_lu(1 << 20, 2.1, 20.0, seed=501), 0.5, 501,
+                                       "chunglu20_dir50_s501"), 8),
+]
+
+# Validation graphs: hyper-parameters and model selection only (never trained on)
+VALID_GRAPHS = [
+    ("rmat21_s600", lambda: gg.rmat(21, 16, seed=600), 12),
+    ("rmat22_s601", lambda: gg.rmat(22, 16, seed=601), 12),
+    ("grid768_del5_s602", lambda: gg.grid(768, 768, 0.05, seed=602), 1),
+    ("chunglu21_s603", lambda: gg.chung_lu(1 << 21, 2.1, 20.0, seed=603), 8),
+    ("er21_d8_s604", lambda: gg.erdos_renyi(1 << 21, 4 << 21, seed=604), 8),
+    ("rmat19_dir70_s605", _directed(lambda: gg.rmat(19, 16, seed=605), 0.7, 605, "rmat19_dir70_s605"), 8),
 ]
 
 
@@ -75,9 +107,11 @@ def collect(graphs=None, reps: int = 3, kernels=None, log=print, source_seed: in
     for name, maker, nsrc in graphs or TRAIN_GRAPHS:
         t0 = time.time()
         g = maker()
-        G = gsw.Graph.from_csr(g.offs, g.cols, flags=gsw.ASSUME_SYMMETRIC | gsw.TRUSTED)
+        flags = gsw.TRUSTED | (0 if "_dir" in name else gsw.ASSUME_SYMMETRIC)
+        G = gsw.Graph.from_csr(g.offs, g.cols, flags=flags)
+        r = reps if g.n < (1 << 19) or "grid" not in name else max(1, reps - 1)
         for s in gg.pick_sources(g, nsrc, source_seed):
-            times, fr, _ = gsw.bfs_profile(G, int(s), kernels=ks, reps=reps, advance_kernel=-1)
+            times, fr, _ = gsw.bfs_profile(G, int(s), kernels=ks, reps=r, advance_kernel=-1)
             disc = np.cumsum(fr)
             for d in range(len(fr)):
                 X.append(G.level_features(int(fr[d]), int(disc[d])))
@@ -113,54 +147,154 @@ def _weights(T, graph, scheme: str):
     raise ValueError(scheme)
 
 
-def evaluate(clf, X, T, ks):
-    """(accuracy, mean slowdown of predicted/fastest per row, total-time ratio)."""
+def scores(chosen_col, T):
+    """(accuracy, mean per-row slowdown, total-time ratio) of choosing column
+    chosen_col[i] at row i."""
     t = np.where(T < 0, np.inf, T)
     best = t.min(axis=1)
-    pred = clf.predict(X.astype(np.float32))
-    col = np.searchsorted(clf.classes_, pred)
-    chosen = t[np.arange(len(t)), clf.classes_[col]]
-    acc = float(np.mean(clf.classes_[col] == labels(T)))
-    return acc, float(np.mean(chosen / best)), float(chosen.sum() / best.sum())
+    chosen = t[np.arange(len(t)), chosen_col]
+    return (float(np.mean(chosen_col == labels(T))), float(np.mean(chosen / best)),
+            float(chosen.sum() / best.sum()))
 
 
-def fit(rows, max_depth=8, min_samples_leaf=5, weights="regret", seed=0, log=print):
+def tree_columns(clf, X):
+    """Column (kernel index into the rows' kernel list) the classifier picks.
+    Features are compared in float32, as the library does."""
+    return clf.predict(X.astype(np.float32)).astype(np.int64)
+
+
+def evaluate(clf, X, T):
+    return scores(tree_columns(clf, X), T)
+
+
+def _named(t):
+    return dict(zip(("accuracy", "mean_slowdown", "time_ratio"), t))
+
+
+def table2(cols_by_model, T, graph, source, names):
+    """The paper's Table II on a set of traversals: for each model (a column
+    choice per row) and for every kernel used at every level, the traversal's
+    time over the best-per-level traversal's, summarised as the share of
+    traversals at the optimum (within 0.1%), within 1-2x, above 5x and above
+    20x, the mean and the worst; "best fixed" is the fastest single kernel of
+    each graph (the paper's "Oracle")."""
+    t = np.where(T < 0, np.inf, T)
+    best = t.min(axis=1)
+    keys = sorted(set(zip(graph.tolist(), source.tolist())))
+    idx = {k: i for i, k in enumerate(keys)}
+    trav = np.array([idx[(g, s)] for g, s in zip(graph.tolist(), source.tolist())])
+    opt = np.bincount(trav, weights=best, minlength=len(keys))
+
+    def summary(ratio):
+        ratio = np.asarray(ratio)
+        return {"optimal": round(float(np.mean(ratio <= 1.001)), 3),
+                "1-2x": round(float(np.mean((ratio > 1.001) & (ratio <= 2.0))), 3),
+                ">5x": round(float(np.mean(ratio > 5.0)), 3), ">20x": round(float(np.mean(ratio > 20.0)), 3),
+                "average": round(float(np.mean(ratio)), 3), "worst": round(float(np.max(ratio)), 3)}
+
+    out = {}
+    for name, cols in cols_by_model.items():
+        tt = np.bincount(trav, weights=t[np.arange(len(t)), cols], minlength=len(keys))
+        out[name] = summary(tt / opt)
+    per_k = {}
+    for k in range(t.shape[1]):
+        per_k[k] = np.bincount(trav, weights=t[:, k], minlength=len(keys)) / opt
+    # best fixed kernel per graph
+    gk = np.array([g for g, _ in keys])
+    oracle = np.empty(len(keys))
+    for gname in np.unique(gk):
+        m = gk == gname
+        tot = {k: np.sum(per_k[k][m] * opt[m]) for k in per_k}
+        kb = min(tot, key=tot.get)
+        oracle[m] = per_k[kb][m]
+    out["best fixed kernel per graph"] = summary(oracle)
+    for k in per_k:
+        if np.all(np.isfinite(per_k[k])):
+            out[names[k]] = summary(per_k[k])
+    return out
+
+
+def _model_variants(Xtr, Ttr, Xva, Tva, seed):
+    """The paper's future-work models on the same rows: a regression tree per
+    kernel (predict log level time, pick the smallest) and a random forest."""
+    from sklearn.ensemble import RandomForestClassifier
+    from sklearn.tree import DecisionTreeRegressor
+
+    t = np.where(Ttr < 0, np.nan, Ttr)
+    pred = np.full((len(Xva), Ttr.shape[1]), np.inf)
+    for k in range(Ttr.shape[1]):
+        ok = np.isfinite(t[:, k]) & (t[:, k] > 0)
+        if ok.sum() < 10:
+            continue
+        reg = DecisionTreeRegressor(max_depth=10, min_samples_leaf=5, random_state=seed)
+        reg.fit(Xtr[ok].astype(np.float32), np.log(t[ok, k]))
+        pred[:, k] = reg.predict(Xva.astype(np.float32))
+    reg_cols = np.argmin(pred, axis=1)
+    rf = RandomForestClassifier(n_estimators=64, max_depth=12, min_samples_leaf=5, random_state=seed, n_jobs=-1)
+    rf.fit(Xtr.astype(np.float32), labels(Ttr))
+    rf_cols = rf.predict(Xva.astype(np.float32)).astype(np.int64)
+    return reg_cols, rf_cols
+
+
+GRID = [(d, leaf, w) for d in (6, 8, 10, 12) for leaf in (1, 5, 20) for w in ("none", "regret")]
+
+
+def fit(rows, valid, seed=0, log=print, grid=GRID):
     from sklearn.tree import DecisionTreeClassifier
 
-    X, T, graph = rows["X"], rows["T"], rows["graph"]
+    X, T, graph, source = rows["X"], rows["T"], rows["graph"], rows["source"]
+    Xv, Tv, gv, sv = valid["X"], valid["T"], valid["graph"], valid["source"]
     ks = [int(k) for k in rows["kernels"]]
+    assert [int(k) for k in valid["kernels"]] == ks
     y = labels(T)
+
+    def make(depth, leaf):
+        return DecisionTreeClassifier(criterion="gini", max_depth=depth, min_samples_leaf=leaf, random_state=seed)
+
+    # hyper-parameters by the validation graphs' total-time ratio
+    sel = []
+    for depth, leaf, wscheme in grid:
+        w = _weights(T, graph, wscheme)
+        clf = make(depth, leaf).fit(X, y, sample_weight=w)
+        acc, slow, ratio = evaluate(clf, Xv, Tv)
+        sel.append(dict(max_depth=depth, min_samples_leaf=leaf, weights=wscheme, valid_time_ratio=round(ratio, 4),
+                        valid_accuracy=round(acc, 4), nodes=int(clf.tree_.node_count)))
+        log("depth %2d leaf %2d %-6s: validation time ratio %.4f, accuracy %.3f, %d nodes"
+            % (depth, leaf, wscheme, ratio, acc, clf.tree_.node_count))
+    best = min(sel, key=lambda r: (r["valid_time_ratio"], r["nodes"]))
+    depth, leaf, wscheme = best["max_depth"], best["min_samples_leaf"], best["weights"]
+    w = _weights(T, graph, wscheme)
+    final = make(depth, leaf).fit(X, y, sample_weight=w)
+    report = {"selection": {"chosen": best, "grid": sel, "by": "validation graphs' total-time ratio"}}
     rng = np.random.default_rng(seed)
-    # the paper's split: 70% of rows at random
+    # the paper's split: 70% of the training rows at random
     perm = rng.permutation(len(y))
     cut = int(0.7 * len(y))
     tr, te = perm[:cut], perm[cut:]
-    report = {}
-    w = _weights(T, graph, weights)
-
-    def make():
-        return DecisionTreeClassifier(criterion="gini", max_depth=max_depth,
-                                      min_samples_leaf=min_samples_leaf, random_state=seed)
-
-    clf = make().fit(X[tr], y[tr], sample_weight=None if w is None else w[tr])
-    report["row_split"] = dict(zip(("accuracy", "mean_slowdown", "time_ratio"),
-                                   evaluate(clf, X[te], T[te], ks)))
-    # held-out graphs
+    c1 = make(depth, leaf).fit(X[tr], y[tr], sample_weight=None if w is None else w[tr])
+    report["row_split"] = _named(evaluate(c1, X[te], T[te]))
+    # held-out training graphs
     names = np.unique(graph)
     hold = rng.choice(names, size=max(1, len(names) * 3 // 10), replace=False)
     m = np.isin(graph, hold)
-    if (~m).sum() and m.sum():
-        c2 = make().fit(X[~m], y[~m], sample_weight=None if w is None else w[~m])
-        report["graph_split"] = dict(zip(("accuracy", "mean_slowdown", "time_ratio"),
-                                         evaluate(c2, X[m], T[m], ks)), held_out=sorted(hold.tolist()))
-    # final tree on every row
-    final = make().fit(X, y, sample_weight=w)
-    report["train_all"] = dict(zip(("accuracy", "mean_slowdown", "time_ratio"), evaluate(final, X, T, ks)))
+    c2 = make(depth, leaf).fit(X[~m], y[~m], sample_weight=None if w is None else w[~m])
+    report["graph_split"] = dict(_named(evaluate(c2, X[m], T[m])), held_out=sorted(hold.tolist()))
+    report["validation"] = dict(_named(evaluate(final, Xv, Tv)), graphs=sorted(np.unique(gv).tolist()))
+    report["train_all"] = _named(evaluate(final, X, T))
+    reg_cols, rf_cols = _model_variants(X, T, Xv, Tv, seed)
+    report["model_variants_on_validation"] = {
+        "classification tree (shipped)": report["validation"],
+        "regression tree per kernel, argmin": _named(scores(reg_cols, Tv)),
+        "random forest (64 trees)": _named(scores(rf_cols, Tv)),
+    }
+    report["table2_validation"] = table2(
+        {"decision tree": tree_columns(final, Xv), "regression trees": reg_cols, "random forest": rf_cols},
+        Tv, gv, sv, [gsw.KERNEL_NAMES[k] for k in ks])
     report["gini_importance"] = {FEATURES[i]: round(float(v), 4)
                                  for i, v in enumerate(final.feature_importances_) if v > 0}
     report["nodes"] = int(final.tree_.node_count)
-    report["params"] = dict(max_depth=max_depth, min_samples_leaf=min_samples_leaf, weights=weights,
-                            seed=seed, rows=int(len(y)))
+    report["params"] = dict(max_depth=depth, min_samples_leaf=leaf, weights=wscheme, seed=seed,
+                            rows=int(len(y)), valid_rows=int(len(Tv)))
     return final, ks, report
 
 
@@ -185,36 +319,40 @@ def export(clf, ks, path: str, report=None, name="mi355x"):
     return arrays
 
 
+def _load_rows(paths):
+    parts = [dict(np.load(p, allow_pickle=False)) for p in paths]
+    rows = {k: np.concatenate([p[k] for p in parts]) for k in ("X", "T", "graph", "source", "level")}
+    rows["kernels"] = parts[0]["kernels"]
+    return rows
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(prog="python -m paper_1708_01159_amd.train")
     sub = ap.add_subparsers(dest="cmd", required=True)
     c = sub.add_parser("collect")
     c.add_argument("--out", required=True)
+    c.add_argument("--set", default="train", choices=["train", "valid"])
     c.add_argument("--reps", type=int, default=3)
     c.add_argument("--only", default=None, help="comma-separated graph names")
     f = sub.add_parser("fit")
     f.add_argument("--rows", required=True, nargs="+")
+    f.add_argument("--valid", required=True, nargs="+")
     f.add_argument("--out", required=True)
-    f.add_argument("--max-depth", type=int, default=8)
-    f.add_argument("--min-samples-leaf", type=int, default=5)
-    f.add_argument("--weights", default="regret", choices=["none", "regret", "graph"])
     f.add_argument("--seed", type=int, default=0)
     a = ap.parse_args(argv)
     if a.cmd == "collect":
-        graphs = TRAIN_GRAPHS
+        graphs = TRAIN_GRAPHS if a.set == "train" else VALID_GRAPHS
         if a.only:
             want = set(a.only.split(","))
-            graphs = [x for x in TRAIN_GRAPHS if x[0] in want]
+            graphs = [x for x in graphs if x[0] in want]
         rows = collect(graphs, reps=a.reps, log=lambda *x: print(*x, flush=True))
         np.savez_compressed(a.out, **rows)
         print("wrote", a.out, len(rows["X"]), "rows", flush=True)
     else:
-        parts = [dict(np.load(p, allow_pickle=False)) for p in a.rows]
-        rows = {k: np.concatenate([p[k] for p in parts]) for k in ("X", "T", "graph", "source", "level")}
-        rows["kernels"] = parts[0]["kernels"]
-        clf, ks, report = fit(rows, a.max_depth, a.min_samples_leaf, a.weights, a.seed)
+        clf, ks, report = fit(_load_rows(a.rows), _load_rows(a.valid), a.seed,
+                              log=lambda *x: print(*x, file=sys.stderr, flush=True))
         export(clf, ks, a.out, report)
-        print(json.dumps(report, indent=1))
+        print(json.dumps({k: v for k, v in report.items() if k not in ("selection", "table2_validation")}, indent=1))
 
 
 if __name__ == "__main__":

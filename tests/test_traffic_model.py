@@ -1,0 +1,36 @@
+"""The byte model's per-level counts (C, one pass over the rows) against a
+direct numpy walk of every unvisited row, and its totals by hand."""
+import numpy as np
+
+import oracle
+from paper_1708_01159_amd import graphgen as gg
+from paper_1708_01159_amd import traffic
+
+
+def test_pull_counts_match_row_walk():
+    for g in (gg.rmat(12, 16, seed=3), gg.grid(40, 31, 0.05, seed=4), gg.chung_lu(5000, 2.1, 8.0, seed=5),
+              gg.from_edges(300, [0, 1, 2, 5], [1, 2, 3, 6])):  # isolated vertices, a small component
+        for s in gg.pick_sources(g, 3, 6):
+            lv = oracle.levels(g.offs, g.cols, int(s))
+            c = traffic.Counts(g.offs, g.cols, lv, int(s))
+            nf, ef = traffic.level_sizes(g.offs, lv)
+            assert np.array_equal(c.nf[:len(nf)], nf) and np.array_equal(c.ef[:len(ef)], ef)
+            for d in range(len(nf)):
+                p, u = traffic.pull_probes_reference(g.offs, g.cols, lv, d)
+                probes, unv_pos, unv_all = c.pull_terms(d)
+                assert (probes, unv_pos) == (p, u), (g.name, int(s), d)
+                assert unv_all == int(np.count_nonzero((lv == -1) | (lv > d)))
+                words = np.unique(np.flatnonzero(lv == d + 1) >> 6).shape[0]
+                assert c.at(c.words, d + 1) == words
+
+
+def test_isolated_source_and_literal_formula():
+    g = gg.from_edges(10, [1, 2], [2, 3])  # vertex 0 isolated
+    lv = oracle.levels(g.offs, g.cols, 0)
+    c = traffic.Counts(g.offs, g.cols, lv, 0)
+    probes, unv_pos, unv_all = c.pull_terms(0)
+    assert (probes, unv_pos, unv_all) == (4, 3, 9)  # rows of 1,2,3: 1+2+1 arcs, none in the frontier
+    # literal: 1 word * 24 + 9 unvisited * 16 + 4 probes * 12 + 0 found
+    assert traffic.pull_bytes_literal(c, 0) == 24 + 9 * 16 + 48
+    # model: clear 8 + visited 8 + 3 * 16 + 4 * 12, no discoveries
+    assert traffic.level_bytes(traffic.PULL, c, 0) == 8 + 8 + 48 + 48

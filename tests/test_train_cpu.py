@@ -1,0 +1,73 @@
+"""CPU tests of the tree training: the labelling and its tie rule, the row
+weights, the scores, Table II on a hand-made set, and the export round trip
+(JSON -> gsw_tree_load -> the same choices as scikit-learn)."""
+import numpy as np
+import pytest
+
+from oracle import tree as otree
+from paper_1708_01159_amd import gsw, train
+
+
+def test_labels_take_the_fastest_lowest_on_ties_and_skip_unmeasured():
+    T = np.array([[3.0, 1.0, 2.0], [1.0, 1.0, 5.0], [-1.0, 4.0, 4.0], [2.0, -1.0, 1.5]])
+    assert train.labels(T).tolist() == [1, 0, 1, 2]
+
+
+def test_weights():
+    T = np.array([[1.0, 2.0, 3.0], [1.0, 1.0, 1.0], [5.0, 1.0, 9.0]])
+    g = np.array(["a", "a", "b"])
+    assert train._weights(T, g, "none") is None
+    w = train._weights(T, g, "regret")  # median - min, + 1e-4, normalised to mean 1
+    raw = np.array([1.0, 0.0, 4.0]) + 1e-4
+    np.testing.assert_allclose(w, raw / raw.mean())
+    w = train._weights(T, g, "graph")  # each graph weighs the same
+    assert w[0] == w[1] and w[2] == pytest.approx(2 * w[0])
+    with pytest.raises(ValueError):
+        train._weights(T, g, "bogus")
+
+
+def test_scores_by_hand():
+    T = np.array([[1.0, 2.0], [4.0, 2.0]])
+    acc, slow, ratio = train.scores(np.array([1, 1]), T)
+    assert acc == 0.5 and slow == pytest.approx((2.0 + 1.0) / 2) and ratio == pytest.approx(4.0 / 3.0)
+
+
+def test_table2_by_hand():
+    # two traversals of graph g (levels 2 and 1) and one of h; kernels 0 and 1
+    T = np.array([[1.0, 3.0], [2.0, 1.0], [1.0, 10.0], [4.0, 1.0]])
+    graph = np.array(["g", "g", "g", "h"])
+    source = np.array([0, 0, 1, 5])
+    # best per level: traversal (g,0) = 1 + 1 = 2, (g,1) = 1, (h,5) = 1
+    out = train.table2({"always 0": np.array([0, 0, 0, 0])}, T, graph, source, ["k0", "k1"])
+    # kernel 0: (g,0) 3/2, (g,1) 1/1, (h,5) 4/1
+    assert out["always 0"]["average"] == pytest.approx((1.5 + 1.0 + 4.0) / 3, abs=1e-3)
+    assert out["always 0"]["worst"] == 4.0 and out["always 0"]["optimal"] == pytest.approx(1 / 3, abs=1e-3)
+    assert out["k1"]["worst"] == 10.0
+    # best fixed kernel per graph: g -> kernel 0 (3 + 1 = 4 vs 4 + 10 = 14), h -> kernel 1
+    assert out["best fixed kernel per graph"]["average"] == pytest.approx((1.5 + 1.0 + 1.0) / 3, abs=1e-3)
+
+
+def test_fit_export_load_round_trip(tmp_path):
+    """A tree fitted on synthetic rows, exported, read back by the library's
+    JSON reader, chooses what scikit-learn and the oracle walk choose."""
+    rng = np.random.default_rng(0)
+    n, K = 600, 4
+    X = np.abs(rng.normal(size=(n, gsw.N_FEATURES))) * 10.0 ** rng.integers(0, 6, gsw.N_FEATURES)
+    base = np.stack([1 + (X[:, 20] > 300), 1 + (X[:, 21] < 0.3), np.full(n, 1.4), 2 - (X[:, 2] > 5)], 1)
+    T = base * rng.uniform(0.9, 1.1, size=(n, K))
+    rows = dict(X=X, T=T, graph=np.array(["g%d" % (i % 7) for i in range(n)]),
+                source=np.arange(n) % 5, level=np.zeros(n, dtype=int), kernels=np.array([0, 6, 7, 11 + 10]))
+    valid = dict(rows)
+    grid = [(4, 5, "regret"), (6, 1, "none")]
+    clf, ks, report = train.fit(rows, valid, grid=grid, log=lambda *a: None)
+    assert report["params"]["max_depth"] in (4, 6) and report["validation"]["time_ratio"] >= 1.0
+    assert set(report["model_variants_on_validation"]) >= {"random forest (64 trees)"}
+    path = str(tmp_path / "t.json")
+    arrays = train.export(clf, ks, path, report)
+    loaded = gsw.Tree.load(path)
+    for x in X[:150]:
+        k, unknown = loaded.predict(x, 0, 1)
+        k2, u2 = otree.predict(arrays, x, 0, 1, gsw.DEFAULT_KERNEL)
+        assert (k, unknown) == (k2, u2)
+        if not unknown:
+            assert k == ks[int(clf.predict(x.astype(np.float32).reshape(1, -1))[0])]
