@@ -406,6 +406,15 @@ gsw_status gsw_session_step(gsw_session *ss, int32_t max_levels, int32_t *finish
 /* Copies a finished slot's n levels (device or host memory) and frees it. */
 gsw_status gsw_session_fetch(gsw_session *ss, int32_t slot, int32_t *levels, int32_t device_ptr);
 
+/* Cancels the query in `slot` (for deadlines and client disconnects): one
+ * admitted but not started yet is dropped at once; a running one becomes
+ * inert at the next level boundary (it discovers nothing more) and, once
+ * its frontier is empty, gsw_session_step clears its partial levels on the
+ * device and frees the slot without reporting it.  Other queries are not
+ * affected.  GSW_EINVAL when the slot holds no admitted or running query
+ * (a finished one must be fetched). */
+gsw_status gsw_session_cancel(gsw_session *ss, int32_t slot);
+
 /* Slot count, slots in use, levels run so far, device bytes held. */
 gsw_status gsw_session_info(const gsw_session *ss, int32_t *slots, int32_t *busy,
                             int64_t *iteration, size_t *dev_bytes);

@@ -658,6 +658,12 @@ __global__ void __launch_bounds__(kMsBlock) k_ss_take(int32_t* row, int32_t* __r
   }
 }
 
+// A cancelled slot's row, cleared for its next query.
+__global__ void __launch_bounds__(kMsBlock) k_ss_clear(int32_t* row, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * kMsBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kMsBlock + threadIdx.x; i < n; i += stride) row[i] = 0;
+}
+
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 inline int group_lanes(int W) {
@@ -1163,7 +1169,8 @@ struct gsw_session {
   std::vector<long long> start_up;  // start level of every slot, as uploaded
   std::vector<int32_t> source;
   std::vector<int64_t> start;  // level at which a running slot was seeded
-  std::vector<int8_t> state;   // 0 free, 1 admitted (seeded at the next level boundary), 2 running, 3 finished
+  std::vector<int8_t> state;   // 0 free, 1 admitted (seeded at the next level boundary), 2 running, 3 finished,
+                               // 4 cancelled while running (inert from the next boundary; freed once its frontier is empty)
   std::vector<u64> freed;      // slots freed since the last boundary (made inert then)
   int64_t queued = 0;          // levels queued on the stream
   int64_t done = 0;            // levels whose record has been read
@@ -1338,7 +1345,7 @@ gsw_status ss_queue_level(gsw_session* ss, bool* queued_one) {
         ss->state[(size_t)k] = 2;
         ++c;
       }
-      running = running || ss->state[(size_t)k] == 2;
+      running = running || ss->state[(size_t)k] == 2 || ss->state[(size_t)k] == 4;
     }
     for (int j = 0; j < W; ++j) {
       set[j] = ss->freed[(size_t)j] & ~clr[j];
@@ -1423,11 +1430,22 @@ gsw_status gsw_session_step(gsw_session* ss, int32_t max_levels, int32_t* finish
     ++run;
     std::lock_guard<std::mutex> lock(ss->mu);
     for (int k = 0; k < ss->slots; ++k) {
-      if (ss->state[(size_t)k] != 2 || ss->start[(size_t)k] > d) continue;
-      if (((rec[kRecActive + (k >> 6)] >> (k & 63)) & 1ull) == 0ull) {
+      const int8_t stk = ss->state[(size_t)k];
+      if ((stk != 2 && stk != 4) || ss->start[(size_t)k] > d) continue;
+      if (((rec[kRecActive + (k >> 6)] >> (k & 63)) & 1ull) != 0ull) continue;
+      if (stk == 2) {
         ss->state[(size_t)k] = 3;
         if (nfin < finished_cap) finished[nfin] = k;
         ++nfin;
+      } else {
+        // a cancelled query whose frontier is empty: its partial levels are
+        // cleared (in stream order, after every level queued so far, none of
+        // which can write the row any more) and the slot is free again
+        hipLaunchKernelGGL(k_ss_clear, dim3((unsigned)std::min<int64_t>(cdiv(ss->g->n, kMsBlock), 65536)),
+                           dim3(kMsBlock), 0, ss->stream, ss->dist + (int64_t)k * ss->g->n, ss->g->n);
+        if (hipGetLastError() != hipSuccess) return fail(GSW_EHIP, "clearing a cancelled slot failed");
+        ss->state[(size_t)k] = 0;
+        ss->source[(size_t)k] = -1;
       }
     }
     if (nfin > 0) break;
@@ -1464,6 +1482,26 @@ gsw_status gsw_session_fetch(gsw_session* ss, int32_t slot, int32_t* levels, int
   return GSW_OK;
 }
 
+gsw_status gsw_session_cancel(gsw_session* ss, int32_t slot) {
+  clear_error();
+  if (!ss) return fail(GSW_EINVAL, "session is null");
+  std::lock_guard<std::mutex> lock(ss->mu);
+  if (slot < 0 || slot >= ss->slots) return fail(GSW_EINVAL, "slot %d out of [0, %d)", slot, ss->slots);
+  switch (ss->state[(size_t)slot]) {
+    case 1:  // not seeded yet: its bits are still inert
+      ss->state[(size_t)slot] = 0;
+      ss->source[(size_t)slot] = -1;
+      return GSW_OK;
+    case 2:  // inert from the next boundary; gsw_session_step frees it once its frontier is empty
+      ss->state[(size_t)slot] = 4;
+      ss->freed[(size_t)(slot >> 6)] |= 1ull << (slot & 63);
+      return GSW_OK;
+    default:
+      return fail(GSW_EINVAL, "slot %d holds no admitted or running query (state %d)", slot,
+                  (int)ss->state[(size_t)slot]);
+  }
+}
+
 gsw_status gsw_session_info(const gsw_session* css, int32_t* slots, int32_t* busy, int64_t* iteration,
                             size_t* dev_bytes) {
   clear_error();
@@ -1489,7 +1527,7 @@ gsw_status gsw_session_rebase(gsw_session* ss, int64_t iteration) {
   std::lock_guard<std::mutex> step_lock(ss->step_mu);
   std::lock_guard<std::mutex> lock(ss->mu);
   for (int k = 0; k < ss->slots; ++k)
-    if (ss->state[(size_t)k] == 2) return fail(GSW_EBUSY, "slot %d is running", k);
+    if (ss->state[(size_t)k] == 2 || ss->state[(size_t)k] == 4) return fail(GSW_EBUSY, "slot %d is running", k);
   if (ss->queued != ss->done) return fail(GSW_EBUSY, "levels are still queued");
   GSW_HIP(hipSetDevice(ss->g->device));
   GSW_HIP(hipStreamSynchronize(ss->stream));

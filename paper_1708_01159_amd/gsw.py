@@ -147,6 +147,7 @@ def lib():
         "gsw_session_admit": (i32, [vp, i32, P(i32)]),
         "gsw_session_step": (i32, [vp, i32, vp, i32, P(i32), P(i32)]),
         "gsw_session_fetch": (i32, [vp, i32, vp, i32]),
+        "gsw_session_cancel": (i32, [vp, i32]),
         "gsw_session_info": (i32, [vp, P(i32), P(i32), P(i64), P(ctypes.c_size_t)]),
         "gsw_session_set_thresholds": (i32, [vp, ctypes.c_float, ctypes.c_float]),
     }
@@ -451,9 +452,8 @@ def bfs(graph: Graph, sources, policy: str = "tree", kernel: int = PUSH_VERTEX, 
     while True:
         tr = (LevelTrace * max(cap, 1))()
         tlen = ctypes.c_int32(0)
-        _check(lib().gsw_bfs(graph.handle, src.ctypes.data, S, _ptr(lv),
-                             _ptr(pa) if pa is not None else None, tr, cap, ctypes.byref(tlen),
-                             ctypes.byref(o)))
+        _check(lib().gsw_bfs(graph.handle, src.ctypes.data, S, _ptr(lv), _ptr(pa) if pa is not None else None,
+                             tr, cap, ctypes.byref(tlen), ctypes.byref(o)))
         if tlen.value <= cap or trace_cap is not None:
             break
         cap = tlen.value  # rerun once with room for every row
@@ -602,6 +602,15 @@ class Session:
         check_out(out, "int32", self.graph.n, bool(dev), "session fetch")
         _check(lib().gsw_session_fetch(self._h, int(slot), _ptr(out), dev))
         return out
+
+    def cancel(self, slot: int) -> bool:
+        """Cancels the slot's admitted or running query (see gsw_session_cancel);
+        False when the slot holds none (e.g. its query already finished)."""
+        st = lib().gsw_session_cancel(self._h, int(slot))
+        if st == EINVAL:
+            return False
+        _check(st)
+        return True
 
     def rebase(self, iteration: int):
         """Sets the level counter (only while nothing runs; see gsw_session_rebase)."""

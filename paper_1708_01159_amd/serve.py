@@ -24,6 +24,16 @@ single-source latency; under load the session batches them.
 Latency of a query = completion time - arrival time.  Throughput = sum over
 queries of the undirected edges of the source's component / makespan.
 
+Failure handling: with a per-query deadline (seconds after arrival) a query
+still waiting when it passes is dropped ("expired") and one running in a
+session is cancelled ("cancelled": its slot stops at the next level boundary
+and is freed without a result); a query on the single-source lane, a few
+milliseconds long, always completes.  A session or lane whose device
+allocation fails (ENOMEM, out of memory) is not an error: its queries keep
+waiting, idle sessions of other graphs are closed to make room, and the
+failure is counted.  Latency percentiles and throughput count completed
+queries only; the summary gives the expired and cancelled counts beside them.
+
 The one-at-a-time reference serves the same arrival trace in FIFO order with
 one tree-switched gsw_bfs per query.
 """
@@ -51,6 +61,7 @@ class Query:
     t_done: float = -1.0
     levels: object = None
     path: str = ""  # "solo" or "session"
+    status: str = "done"  # "done", "expired" (dropped while waiting) or "cancelled" (stopped while running)
 
 
 @dataclass
@@ -86,6 +97,13 @@ def lane_bytes(graph) -> int:
     """Device bytes of a single-source lane's level row (the graph's
     single-source workspace is charged separately, once per graph)."""
     return 4 * graph.n
+
+
+def _is_oom(e: BaseException) -> bool:
+    """A device allocation failure: the library's ENOMEM or torch's out-of-memory."""
+    if isinstance(e, gsw.GswError):
+        return e.status == gsw.ENOMEM
+    return isinstance(e, MemoryError) or (isinstance(e, RuntimeError) and "out of memory" in str(e))
 
 
 def poisson_trace(rate_qps: float, duration_s: float, graphs, candidates, zipf_s: float = 1.1,
@@ -139,12 +157,13 @@ class Server:
 
     def __init__(self, residents: dict, slots: int = 64, hbm_budget: int = None,
                  levels_per_step: int = 1 << 20, keep_levels: bool = False, session_factory=None,
-                 solo: bool = False, solo_factory=None):
+                 solo: bool = False, solo_factory=None, deadline_s: float = None):
         self.res = residents
         self.new_session = session_factory or gsw.Session
         self.solo = solo
         self.new_solo = solo_factory or SoloLane
         self._solo_lanes = {}       # graph -> (lane, single-thread executor)
+        self._lane_failed = set()   # graphs whose lane could not be allocated (not tried again)
         self.solo_served = 0
         self.slots = slots
         self.budget = hbm_budget
@@ -156,6 +175,10 @@ class Server:
         self._ws_charged = set()    # graphs whose single-source workspace is charged (held for good)
         self._held = 0              # bytes lanes hold: open lanes' rows and the charged workspaces
         self.evictions = 0
+        self.deadline = deadline_s  # seconds after arrival, or None
+        self.expired = 0            # dropped while waiting
+        self.cancelled = 0          # stopped while running in a session
+        self.alloc_failures = 0     # sessions or lanes whose device allocation failed
         self._scratch_bufs = {}
         self._live = {}             # graph -> future of its running worker
         self._slot_mu = threading.Lock()
@@ -172,7 +195,19 @@ class Server:
                     return None
                 self._close(idle[0])
                 self.evictions += 1
-        s = self.new_session(self.res[name].graph, self.slots)
+        try:
+            s = self.new_session(self.res[name].graph, self.slots)
+        except Exception as e:  # noqa: BLE001 (only allocation failures are absorbed)
+            if not _is_oom(e):
+                raise
+            # the device is fuller than the budget says (other processes, fragmentation):
+            # close an idle session of another graph and try again later
+            self.alloc_failures += 1
+            idle = [g for g, x in self.sessions.items() if x.info()["busy"] == 0 and g not in self._live]
+            if idle:
+                self._close(idle[0])
+                self.evictions += 1
+            return None
         self.sessions[name] = s
         self.workers[name] = ThreadPoolExecutor(max_workers=1)
         self.used += need
@@ -222,6 +257,8 @@ class Server:
         """The graph's single-source lane, opened (and charged) on first use;
         None when the budget has no room for it (its queries then go to the
         session)."""
+        if name in self._lane_failed:
+            return None
         if name not in self._solo_lanes:
             g = self.res[name].graph
             need = lane_bytes(g) + (0 if name in self._ws_charged else g.workspace_bytes())
@@ -233,11 +270,42 @@ class Server:
                 biggest = max(session_bytes(r.graph, self.slots) for r in self.res.values())
                 if self._held + need + biggest > self.budget:
                     return None
-            self._solo_lanes[name] = (self.new_solo(g), ThreadPoolExecutor(max_workers=1))
+            try:
+                lane = self.new_solo(g)
+            except Exception as e:  # noqa: BLE001
+                if not _is_oom(e):
+                    raise
+                self.alloc_failures += 1
+                self._lane_failed.add(name)
+                return None
+            self._solo_lanes[name] = (lane, ThreadPoolExecutor(max_workers=1))
             self.used += need
             self._held += need
             self._ws_charged.add(name)
         return self._solo_lanes[name]
+
+    def _expire(self, pending, slot_q, now):
+        """Deadline pass: drops waiting queries past their deadline and cancels
+        those running in a session; returns how many ended here."""
+        ended = 0
+        for dq in pending.values():
+            while dq and now - dq[0].t_arrival > self.deadline:  # FIFO: oldest first
+                q = dq.popleft()
+                q.status, q.t_done = "expired", now
+                self.expired += 1
+                ended += 1
+        for name, slots in slot_q.items():
+            sess = self.sessions.get(name)
+            for k, q in list(slots.items()):
+                if now - q.t_arrival <= self.deadline or sess is None:
+                    continue
+                with self._slot_mu:  # a worker takes finished slots off the map under the same lock
+                    if slots.get(k) is q and sess.cancel(k):
+                        del slots[k]
+                        q.status, q.t_done = "cancelled", now
+                        self.cancelled += 1
+                        ended += 1
+        return ended
 
     def run(self, trace, timeout_s: float = 600.0):
         """Serves ``trace`` = [(t_arrival, graph, source)] in real time; returns
@@ -266,6 +334,8 @@ class Server:
                 e = est[q.graph]
                 e[q.path] = 0.8 * e[q.path] + 0.2 * (q.t_done - q.t_admit)
                 done += 1
+            if self.deadline is not None:
+                done += self._expire(pending, slot_q, now)
             for name, fut in list(self._live.items()):
                 if fut.done():
                     del self._live[name]
@@ -347,17 +417,28 @@ def serve_one_at_a_time(residents: dict, trace, tree, timeout_s: float = 600.0):
 
 
 def summarize(queries, residents, label):
-    lat = np.array([q.t_done - q.t_arrival for q in queries]) * 1e3
-    span = max(q.t_done for q in queries) - min(q.t_arrival for q in queries)
-    edges = sum(int(residents[q.graph].comp_edges[q.source]) for q in queries)
-    return {"mode": label, "queries": len(queries), "p50_ms": round(float(np.percentile(lat, 50)), 3),
-            "p99_ms": round(float(np.percentile(lat, 99)), 3), "mean_ms": round(float(lat.mean()), 3),
-            "gteps": round(edges / span / 1e9, 3), "makespan_s": round(span, 3)}
+    """Latency percentiles and throughput over the completed queries; counts of
+    the expired and cancelled ones."""
+    ok = [q for q in queries if q.status == "done"]
+    out = {"mode": label, "queries": len(queries), "completed": len(ok),
+           "expired": sum(q.status == "expired" for q in queries),
+           "cancelled": sum(q.status == "cancelled" for q in queries)}
+    if not ok:
+        return out
+    lat = np.array([q.t_done - q.t_arrival for q in ok]) * 1e3
+    span = max(q.t_done for q in ok) - min(q.t_arrival for q in ok)
+    edges = sum(int(residents[q.graph].comp_edges[q.source]) for q in ok)
+    out.update({"p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "mean_ms": round(float(lat.mean()), 3), "gteps": round(edges / span / 1e9, 3),
+                "makespan_s": round(span, 3)})
+    return out
 
 
 def per_graph_p99(queries):
-    """p99 latency (ms) of each graph's queries."""
+    """p99 latency (ms) of each graph's completed queries."""
     by = {}
     for q in queries:
+        if q.status != "done":
+            continue
         by.setdefault(q.graph, []).append((q.t_done - q.t_arrival) * 1e3)
     return {g: round(float(np.percentile(v, 99)), 3) for g, v in sorted(by.items())}

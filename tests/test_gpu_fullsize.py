@@ -1,8 +1,11 @@
 """Full-size parity in the launch configurations the benchmark times:
-R-MAT scale 22 with the shipped tree (sampled sources: levels bit-exact
-against the oracle, parents through the invariants), the batched search at
-scale 20 with 1024 sources (sampled rows), and one source of each
-structure-sweep graph."""
+R-MAT scale 22 with the shipped tree (8 of the 64 timed sources: levels
+bit-exact against the oracle, per-level counts against its histogram,
+parents through the invariants on two), every one of the 33 fixed kernels
+on one R-MAT 22 source, the batched search at scale 20 with 1024 sources
+(sampled rows), two sources of each structure-sweep graph, and served
+queries on the two largest serving graphs (R-MAT 24 and the full 4096 x 4096
+grid, whose 8,190-level queries need int32 slots)."""
 import numpy as np
 import pytest
 
@@ -32,7 +35,7 @@ def test_rmat22_tree_switched_sampled_sources(rmat22):
     pa = torch.empty((1, g.n), dtype=torch.int32, device="cuda")
     r = gsw.Runner(G, lv, pa, policy="tree", tree=trees.load_default(), time_levels=True)
     comp = None
-    for i in (0, 37):
+    for i in (0, 9, 18, 27, 37, 45, 54, 63):
         s = int(srcs[i])
         r.run(s)
         got = lv[0].cpu().numpy()
@@ -40,19 +43,31 @@ def test_rmat22_tree_switched_sampled_sources(rmat22):
         assert np.array_equal(got, ref), "source %d" % s
         rows = r.rows()
         assert [t.n_frontier for t in rows] == hist.tolist()
+        assert [t.discovered for t in rows] == np.cumsum(hist).tolist()
         assert len({t.kernel for t in rows}) >= 2  # the tree switched kernels
-        if i == 0:
-            comp = checks.components(g.n, g.offs, g.cols)
+        if i in (0, 37):
+            if comp is None:
+                comp = checks.components(g.n, g.offs, g.cols)
             checks.check_bfs(g.offs, g.cols, s, got, pa[0].cpu().numpy(), comp)
 
 
 def test_rmat22_every_fixed_kernel_one_source(rmat22):
+    """All 33 kernels (11 base kernels x 3 frontier-count variants) at every
+    level of one timed source, with the arc count on, in device tensors."""
+    import torch
+
     g, G = rmat22
     s = int(gg.pick_sources(g, 64, 102)[5])
-    ref = oracle.levels(g.offs, g.cols, s)
-    for k in (gsw.PUSH_EDGE, gsw.PULL_BITMAP, gsw.EDGE_SCAN, gsw.PUSH_WAVE64):
-        lv, _, _ = gsw.bfs(G, [s], policy="fixed", kernel=k, parents=False)
-        assert np.array_equal(lv[0], ref), gsw.KERNEL_NAMES[k]
+    ref, _, hist, ehist = oracle.bfs(g.offs, g.cols, s)
+    lv = torch.empty((1, g.n), dtype=torch.int32, device="cuda")
+    for k in range(gsw.N_KERNELS):
+        lv.fill_(-7)
+        _, _, tr = gsw.bfs(G, [s], policy="fixed", kernel=k, parents=False, device=True, out=(lv, None),
+                           count_arcs=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(lv[0].cpu().numpy(), ref), gsw.KERNEL_NAMES[k]
+        assert [t.n_frontier for t in tr] == hist.tolist(), gsw.KERNEL_NAMES[k]
+        assert [t.e_frontier for t in tr] == ehist.tolist(), gsw.KERNEL_NAMES[k]
 
 
 def test_rmat20_batched_1024_sampled_rows():
@@ -64,7 +79,7 @@ def test_rmat20_batched_1024_sampled_rows():
     out = torch.empty((1024, g.n), dtype=torch.int8, device="cuda")
     gsw.msbfs(G, srcs, out=out)
     torch.cuda.synchronize()
-    for i in (0, 63, 64, 511, 1023):
+    for i in (0, 1, 63, 64, 127, 300, 511, 512, 700, 959, 1000, 1023):
         ref = oracle.levels(g.offs, g.cols, int(srcs[i]))
         assert np.array_equal(out[i].cpu().numpy().astype(np.int32), ref), i
     G.close()
@@ -77,9 +92,39 @@ def test_sweep_graph_one_source(name):
     g = gg.workload(name)
     G = gsw.Graph.from_csr(g.offs, g.cols, flags=gsw.ASSUME_SYMMETRIC | gsw.TRUSTED)
     k, seed = gg.WORKLOAD_SOURCES[name]
-    s = int(gg.pick_sources(g, k, seed)[0])
     lv = torch.empty((1, g.n), dtype=torch.int32, device="cuda")
     r = gsw.Runner(G, lv, None, policy="tree", tree=trees.load_default(), trace_cap=1 << 16)
-    r.run(s)
-    assert np.array_equal(lv[0].cpu().numpy(), oracle.levels(g.offs, g.cols, s))
+    for s in gg.pick_sources(g, k, seed)[[0, k - 1]]:
+        r.run(int(s))
+        ref, _, hist, _ = oracle.bfs(g.offs, g.cols, int(s))
+        assert np.array_equal(lv[0].cpu().numpy(), ref), (name, int(s))
+        assert [t.n_frontier for t in r.rows()] == hist.tolist()
     G.close()
+
+
+def test_serving_largest_graphs_mix():
+    """Queries on R-MAT 24 and the full 4096 x 4096 grid served together by
+    continuously batched sessions (int32 slots; grid queries run 8,000+
+    levels): every result equals the oracle's."""
+    from paper_1708_01159_amd import serve
+
+    graphs = {"rmat24": gg.rmat(24, 16, seed=11), "grid4096": gg.grid(4096, 4096, 0.0, seed=12)}
+    residents, cands = {}, {}
+    for nm, g in graphs.items():
+        G = gsw.Graph.from_csr(g.offs, g.cols, flags=gsw.ASSUME_SYMMETRIC | gsw.TRUSTED)
+        residents[nm] = serve.Resident(nm, G)  # throughput is not measured here
+        cands[nm] = np.flatnonzero(g.degrees() > 0)
+    rng = np.random.default_rng(24)
+    trace = []
+    for i in range(10):  # arrivals 2 ms apart, alternating graphs, so they overlap on the device
+        nm = "rmat24" if i % 5 < 3 else "grid4096"
+        trace.append((0.002 * i, nm, int(cands[nm][rng.integers(0, cands[nm].shape[0])])))
+    srv = serve.Server(residents, slots=8, keep_levels=True)
+    qs = srv.run(trace, timeout_s=300)
+    assert len(qs) == len(trace)
+    for q in qs:
+        g = graphs[q.graph]
+        assert np.array_equal(q.levels, oracle.levels(g.offs, g.cols, q.source)), (q.graph, q.source)
+    assert max(int(q.levels.max()) for q in qs if q.graph == "grid4096") > 127
+    for r in residents.values():
+        r.graph.close()

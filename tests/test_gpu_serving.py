@@ -241,3 +241,37 @@ def test_session_counter_past_2_31():
             break
     assert np.array_equal(sess.fetch(k), oracle.levels(g.offs, g.cols, srcs[1]))
     sess.close()
+
+
+def test_session_cancel_running_and_admitted():
+    """A running query cancelled mid-traversal stops at the next boundary and
+    its slot is freed without being reported; one cancelled before it starts
+    is dropped at once; both slots then serve new queries exactly (the
+    cancelled query's partial row was cleared)."""
+    g, G = resident("grid")  # ~100 levels per query
+    sess = gsw.Session(G, slots=2)
+    a, b, c = gg.pick_sources(g, 3, 31).tolist()
+    ka = sess.admit(a)
+    fin, run = sess.step(3)
+    assert not fin and run == 3  # a is mid-traversal
+    assert sess.cancel(ka)
+    kb = sess.admit(b)
+    assert kb is not None and kb != ka
+    assert sess.cancel(kb) and not sess.cancel(kb)
+    while True:
+        fin, run = sess.step(50)
+        assert not fin  # a cancelled query is never reported finished
+        if run == 0:
+            break
+    assert sess.info()["busy"] == 0
+    ks = {sess.admit(c): c, sess.admit(a): a}
+    assert set(ks) == {0, 1}
+    res = {}
+    while len(res) < 2:
+        fin, _ = sess.step(50)
+        for k in fin:
+            res[k] = sess.fetch(k)
+    for k, s in ks.items():
+        assert np.array_equal(res[k], oracle.levels(g.offs, g.cols, s)), s
+    assert not sess.cancel(0)  # nothing admitted any more
+    sess.close()

@@ -2,8 +2,10 @@
 simulated level per step) exercises admission, slot reuse, the memory budget
 and eviction without a GPU."""
 import threading
+import time
 
 import numpy as np
+import pytest
 
 import oracle
 from paper_1708_01159_amd import graphgen as gg
@@ -69,6 +71,16 @@ class StubSession:
                 return fin, run + 1
         return fin, max_levels
 
+    def cancel(self, slot):
+        with self.mu:
+            if slot in self.pending:
+                del self.pending[slot]
+                return True
+            if slot in self.state:
+                del self.state[slot]
+                return True
+            return False
+
     def fetch(self, slot, out=None):
         with self.mu:
             lv = self.finished.pop(slot)
@@ -97,9 +109,18 @@ class StubSolo:
         return lv if keep else None
 
 
+class SlowStubSession(StubSession):
+    """A stub whose levels take 0.5 ms each, so deep queries stay running."""
+
+    def step(self, max_levels):
+        time.sleep(0.0005)
+        return super().step(1)
+
+
 def make(names):
     res, cands = {}, {}
-    graphs = {"a": gg.rmat(9, 8, seed=1), "b": gg.grid(12, 9, 0.0, seed=1), "c": gg.erdos_renyi(700, 900, seed=2)}
+    graphs = {"a": gg.rmat(9, 8, seed=1), "b": gg.grid(12, 9, 0.0, seed=1), "c": gg.erdos_renyi(700, 900, seed=2),
+              "p": gg.from_edges(600, list(range(599)), list(range(1, 600)), name="path600")}
     for nm in names:
         g = graphs[nm]
         res[nm] = serve.Resident(nm, StubGraph(g), serve.component_edges(g.offs, g.cols))
@@ -197,3 +218,87 @@ def test_lanes_never_lock_out_a_session():
     qs = srv.run(trace, timeout_s=60)
     assert len(qs) == len(trace) and srv.used <= big + lane_b
     assert {q.graph for q in qs if q.path == "session"} and srv.solo_served > 0
+
+
+def test_deadline_expires_waiting_and_cancels_running():
+    """Deep queries (a 600-vertex path, 0.5 ms per level) on one slot with a
+    60 ms deadline: the running one is cancelled, those still waiting expire;
+    quick queries on another graph complete with exact levels; percentiles
+    count completed queries only."""
+    res, cands = make(["a", "p"])
+    trace = [(0.001 * i, "p", 0) for i in range(4)] + [(0.002 + 0.001 * i, "a", int(cands["a"][i])) for i in range(6)]
+    srv = serve.Server(res, slots=1, levels_per_step=1, keep_levels=True, session_factory=SlowStubSession,
+                       deadline_s=0.06)
+    qs = srv.run(trace, timeout_s=60)
+    by = {}
+    for q in qs:
+        by.setdefault((q.graph, q.status), []).append(q)
+    assert srv.cancelled >= 1
+    assert not by.get(("p", "done"))
+    assert srv.cancelled + srv.expired == len(qs) - len(by.get(("a", "done"), []))
+    for q in by.get(("a", "done"), []):
+        g = res["a"].graph.csr
+        assert np.array_equal(q.levels, oracle.levels(g.offs, g.cols, q.source))
+    for q in qs:
+        if q.status != "done":
+            assert q.levels is None and q.t_done - q.t_arrival >= 0.06
+    st = serve.summarize(qs, res, "deadline")
+    assert st["expired"] == srv.expired and st["cancelled"] == srv.cancelled
+    assert st["completed"] == len(qs) - srv.expired - srv.cancelled
+
+
+def test_deadline_expires_queries_that_never_get_a_slot():
+    # a budget below any session's size: nothing is ever admitted, every
+    # query expires at its deadline instead of the run hanging
+    res, cands = make(["a", "b"])
+    trace = serve.poisson_trace(1000.0, 0.02, ["a", "b"], cands, seed=14)
+    srv = serve.Server(res, slots=4, hbm_budget=1, keep_levels=True, session_factory=StubSession,
+                       deadline_s=0.03)
+    qs = srv.run(trace, timeout_s=60)
+    assert srv.expired == len(qs) and srv.cancelled == 0
+    assert all(q.status == "expired" and q.t_done - q.t_arrival >= 0.03 for q in qs)
+    st = serve.summarize(qs, res, "none")
+    assert st["completed"] == 0 and "p50_ms" not in st
+
+
+def test_allocation_failures_are_absorbed():
+    """Sessions whose device allocation fails (ENOMEM) are retried later;
+    every query is still answered exactly, and the failures are counted."""
+    from paper_1708_01159_amd import gsw
+
+    fails = {"left": 3}
+
+    def flaky(graph, slots):
+        if fails["left"] > 0:
+            fails["left"] -= 1
+            raise gsw.GswError(gsw.ENOMEM, "injected: hipMalloc failed")
+        return StubSession(graph, slots)
+
+    res, cands = make(["a", "b"])
+    trace = serve.poisson_trace(2000.0, 0.02, ["a", "b"], cands, seed=12)
+    srv = serve.Server(res, slots=4, keep_levels=True, session_factory=flaky)
+    qs = srv.run(trace, timeout_s=60)
+    assert srv.alloc_failures == 3 and all(q.status == "done" for q in qs)
+    for q in qs:
+        g = res[q.graph].graph.csr
+        assert np.array_equal(q.levels, oracle.levels(g.offs, g.cols, q.source))
+
+    def broken(graph, slots):
+        raise gsw.GswError(gsw.EINVAL, "not an allocation failure")
+
+    srv = serve.Server(res, slots=4, keep_levels=True, session_factory=broken)
+    with pytest.raises(gsw.GswError):
+        srv.run(trace[:3], timeout_s=60)
+
+
+def test_lane_allocation_failure_falls_back_to_sessions():
+    res, cands = make(["a"])
+
+    def no_lane(graph):
+        raise MemoryError("injected")
+
+    trace = serve.poisson_trace(300.0, 0.03, ["a"], cands, seed=13)
+    srv = serve.Server(res, slots=4, keep_levels=True, session_factory=StubSession, solo=True, solo_factory=no_lane)
+    qs = srv.run(trace, timeout_s=60)
+    assert srv.alloc_failures == 1 and srv.solo_served == 0
+    assert all(q.status == "done" and q.path == "session" for q in qs)
