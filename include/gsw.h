@@ -309,6 +309,7 @@ gsw_status gsw_bfs_profile(const gsw_graph *g, int32_t source, const int32_t *ke
                            int32_t n_kernels, int32_t reps, int32_t advance_kernel, float *times,
                            int64_t *frontier, int32_t max_levels, int32_t *n_levels, void *stream);
 
+
 /* ----------------------------------------------------------- batched BFS */
 
 #define GSW_MSBFS_MAX_SOURCES 1024
@@ -421,9 +422,10 @@ gsw_status gsw_session_info(const gsw_session *ss, int32_t *slots, int32_t *busy
 
 /* Sets the session's level counter (the iteration that gsw_session_info
  * reports and new queries record as their start) to `iteration`, in
- * [0, 2^62].  Only while no query is running and no level is queued
- * (GSW_EBUSY otherwise); admitted queries that have not started yet and
- * finished ones that have not been fetched keep their results.  The counter
+ * [0, 2^62].  Only while no query is running (GSW_EBUSY otherwise); a level
+ * still queued then has nothing to advance and is waited for and dropped.
+ * Admitted queries that have not started yet and finished ones that have not
+ * been fetched keep their results.  The counter
  * is 64-bit and never wraps in practice; this call lets a long-lived server
  * restart the numbering and lets tests start a session at any count. */
 gsw_status gsw_session_rebase(gsw_session *ss, int64_t iteration);

@@ -1528,7 +1528,8 @@ gsw_status gsw_session_rebase(gsw_session* ss, int64_t iteration) {
   std::lock_guard<std::mutex> lock(ss->mu);
   for (int k = 0; k < ss->slots; ++k)
     if (ss->state[(size_t)k] == 2 || ss->state[(size_t)k] == 4) return fail(GSW_EBUSY, "slot %d is running", k);
-  if (ss->queued != ss->done) return fail(GSW_EBUSY, "levels are still queued");
+  // levels still queued have no running query to advance: waiting for them
+  // here and dropping their records changes no slot's state
   GSW_HIP(hipSetDevice(ss->g->device));
   GSW_HIP(hipStreamSynchronize(ss->stream));
   // records of earlier levels must not be mistaken for those of the new numbering

@@ -192,7 +192,10 @@ def test_msbfs_fallback_reruns_deep_sources_in_int32(device):
             torch.cuda.synchronize()
             lv = lv.cpu().numpy()
             wide = {k: v.cpu().numpy() for k, v in wide.items()}
-        assert sorted(wide) == [0, 2, 4]  # eccentricities 199, 199, 196
+        # on a path the eccentricity of s is max(s, n - 1 - s): 199, 100, 199, 109, 196, 150
+        deep = [i for i, s in enumerate(srcs) if max(int(s), n - 1 - int(s)) > 127]
+        assert deep == [0, 2, 4, 5]
+        assert sorted(wide) == deep
         for i, s in enumerate(srcs):
             ref = np.abs(np.arange(n) - int(s))
             assert np.array_equal(ref, oracle.levels(p.offs, p.cols, int(s)))
@@ -205,9 +208,14 @@ def test_msbfs_fallback_reruns_deep_sources_in_int32(device):
     with pytest.raises(gsw.GswError) as ei:
         gsw.msbfs(G, srcs, fallback=True, wide_cap=2)
     assert ei.value.status == gsw.ERANGE
-    # nothing past the cap: no rerun
-    lv, nl, wide = gsw.msbfs(G, [100, 60], fallback=True)
-    assert wide == {} and np.array_equal(lv[0].astype(np.int32), np.abs(np.arange(n) - 100))
+    # nothing past the cap: no rerun (source 72 reaches depth 127 exactly)
+    lv, nl, wide = gsw.msbfs(G, [100, 72], fallback=True)
+    assert wide == {}
+    for i, s in enumerate((100, 72)):
+        assert np.array_equal(lv[i].astype(np.int32), np.abs(np.arange(n) - s))
+    # one level deeper (source 71 reaches 128) is rerun
+    lv, nl, wide = gsw.msbfs(G, [100, 71], fallback=True)
+    assert sorted(wide) == [1] and np.array_equal(wide[1], np.abs(np.arange(n) - 71))
     G.close()
 
 
