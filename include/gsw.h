@@ -309,6 +309,40 @@ gsw_status gsw_bfs_profile(const gsw_graph *g, int32_t source, const int32_t *ke
                            int32_t n_kernels, int32_t reps, int32_t advance_kernel, float *times,
                            int64_t *frontier, int32_t max_levels, int32_t *n_levels, void *stream);
 
+/*
+ * gsw_bfs for callers that cannot allocate memory: code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Same arguments,
+ * kernels and results as gsw_bfs; it calls no hipMalloc, hipFree,
+ * hipHostMalloc or other allocating routine and creates no events.  Its
+ * kernels' working memory (bitmaps, frontier queues, counters, level
+ * control, push_edge scan arrays, the head copy of the in-arcs, the level
+ * records, the device copy of the tree or schedule) is one fixed device
+ * array of GSW_NOALLOC_SCRATCH_BYTES per GPU, held from the library's first
+ * use of that GPU until the process ends.  Limits (GSW_EINVAL beyond them,
+ * checked before any GPU work): n <= GSW_NOALLOC_MAX_VERTICES, a tree of at
+ * most GSW_NOALLOC_MAX_TREE_NODES nodes, a schedule of at most
+ * GSW_NOALLOC_MAX_SCHEDULE entries; opts is required and must have
+ * device_ptrs = 1 (levels and parents in device memory; sources stay a host
+ * array) and time_levels 0 or 1; a fixed kernel or a schedule naming
+ * edge_scan or rev_edge_scan needs the graph's origin arrays to exist
+ * already (GSW_WITH_ORIGIN at creation), and a tree leaf naming one runs the
+ * default kernel instead when they do not.  Every call shares its GPU's
+ * array, which keeps the last call's contents; the call rebuilds or clears
+ * what it reads before reading it.  Calls from threads of one process are
+ * serialised by a lock and each returns after its work on the stream has
+ * finished; work that overlaps a call on the same GPU through any other
+ * route into this array (another thread bypassing the library, a captured
+ * replay still running) races with it.  The level records are read by
+ * copying them from device memory after every eight launches, so a
+ * search costs one host wait per eight launches.
+ */
+#define GSW_NOALLOC_MAX_VERTICES (1 << 19)
+#define GSW_NOALLOC_MAX_TREE_NODES 4095
+#define GSW_NOALLOC_MAX_SCHEDULE 4096
+#define GSW_NOALLOC_SCRATCH_BYTES 50742784 /* 48.4 MiB */
+gsw_status gsw_bfs_noalloc(const gsw_graph *g, const int32_t *sources, int32_t n_sources,
+                           int32_t *levels, int32_t *parents, gsw_level_trace *trace,
+                           int32_t trace_cap, int32_t *trace_len, const gsw_bfs_opts *opts);
 
 /* ----------------------------------------------------------- batched BFS */
 

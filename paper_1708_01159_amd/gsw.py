@@ -139,6 +139,7 @@ def lib():
         "gsw_tree_destroy": (None, [vp]),
         "gsw_tree_predict": (i32, [vp, vp, i32, i32, P(i32), P(i32)]),
         "gsw_bfs": (i32, [vp, vp, i32, vp, vp, vp, i32, P(i32), P(BfsOpts)]),
+        "gsw_bfs_noalloc": (i32, [vp, vp, i32, vp, vp, vp, i32, P(i32), P(BfsOpts)]),
         "gsw_bfs_profile": (i32, [vp, i32, vp, i32, i32, i32, vp, vp, i32, P(i32), vp]),
         "gsw_msbfs_opts_default": (None, [P(MsbfsOpts)]),
         "gsw_msbfs": (i32, [vp, vp, i32, vp, P(i32), P(MsbfsOpts)]),
@@ -460,6 +461,34 @@ def bfs(graph: Graph, sources, policy: str = "tree", kernel: int = PUSH_VERTEX, 
     rows = [_row(t) for t in tr[:min(tlen.value, cap)]]
     del keep
     return lv, pa, rows
+
+
+def bfs_noalloc(graph: Graph, sources, levels, parents=None, policy: str = "tree", kernel: int = PUSH_VERTEX,
+                schedule=None, tree: Tree = None, time_levels: bool = False, canonical_parents: bool = False,
+                stream=None, trace_cap: int = None, max_workgroups: int = 0, count_arcs: bool = False):
+    """gsw_bfs_noalloc: the search of ``bfs`` into caller-allocated device
+    tensors (``levels``, optional ``parents``: int32, ``[len(sources), n]``)
+    without any allocation in the library.  Returns the trace rows."""
+    src = np.ascontiguousarray(np.atleast_1d(np.asarray(sources)), dtype=np.int32)
+    S, n = src.shape[0], graph.n
+    check_out(levels, "int32", S * n, True, "bfs_noalloc levels")
+    if parents is not None:
+        check_out(parents, "int32", S * n, True, "bfs_noalloc parents")
+    if stream is None:
+        import torch
+
+        stream = torch.cuda.current_stream().cuda_stream
+    o, keep = _opts(policy, kernel, schedule, tree, time_levels, canonical_parents, True, stream)
+    o.max_workgroups = int(max_workgroups)
+    o.count_arcs = int(bool(count_arcs))
+    cap = trace_cap if trace_cap is not None else 64 * max(S, 1)
+    tr = (LevelTrace * max(cap, 1))()
+    tlen = ctypes.c_int32(0)
+    _check(lib().gsw_bfs_noalloc(graph.handle, src.ctypes.data, S, _ptr(levels),
+                                 _ptr(parents) if parents is not None else None, tr, cap, ctypes.byref(tlen),
+                                 ctypes.byref(o)))
+    del keep
+    return [_row(t) for t in tr[:min(tlen.value, cap)]]
 
 
 class Runner:

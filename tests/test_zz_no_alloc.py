@@ -1,0 +1,98 @@
+"""gsw_bfs_noalloc (the entry point for callers that cannot allocate) against
+gsw_bfs on the same graphs and sources: levels bit-exact (and equal to the
+oracle), parents equal under the canonical rule and valid by the invariants
+otherwise, trace rows equal; two calls in a row, the second on a smaller
+graph (n not a multiple of 64), so that state the first call left in the
+shared scratch memory would show; the graph's own workspace is never
+allocated by the no-alloc calls."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import checks
+from paper_1708_01159_amd import graphgen as gg
+from paper_1708_01159_amd import gsw, trees
+
+pytestmark = pytest.mark.gpu
+
+MAX_N = 1 << 19
+
+
+def _graphs():
+    big = gg.rmat(16, 16, seed=41)                 # 65,536 vertices
+    small = gg.grid(37, 29, 0.05, seed=42)         # 1,073 vertices (ragged last bitmap word)
+    return [(big, gg.pick_sources(big, 3, 141)), (small, gg.pick_sources(small, 2, 142))]
+
+
+def _rows_key(rows):
+    return [(t.source_idx, t.level, t.kernel, t.n_frontier, t.discovered, t.n_next, t.e_frontier) for t in rows]
+
+
+def _run_pair(g, srcs, **kw):
+    import torch
+
+    G = gsw.Graph.from_csr(g.offs, g.cols)
+    try:
+        dev0 = G.info()["dev_bytes"]
+        S = len(srcs)
+        lv = torch.full((S, g.n), 7, dtype=torch.int32, device="cuda")
+        pa = torch.full((S, g.n), 7, dtype=torch.int32, device="cuda")
+        rows = gsw.bfs_noalloc(G, srcs, lv, pa, count_arcs=True, **kw)
+        torch.cuda.synchronize()
+        # no-alloc calls leave the graph's workspace unallocated
+        assert G.info()["dev_bytes"] == dev0
+        ref_lv, ref_pa, ref_rows = gsw.bfs(G, srcs, count_arcs=True, **kw)
+        got_lv, got_pa = lv.cpu().numpy(), pa.cpu().numpy()
+        assert np.array_equal(got_lv, ref_lv)
+        assert _rows_key(rows) == _rows_key(ref_rows)
+        for i, s in enumerate(srcs):
+            assert np.array_equal(got_lv[i], oracle.levels(g.offs, g.cols, int(s))), "source %d" % s
+            checks.check_bfs(g.offs, g.cols, int(s), got_lv[i], got_pa[i])
+        if kw.get("canonical_parents"):
+            assert np.array_equal(got_pa, ref_pa)
+    finally:
+        G.close()
+
+
+@pytest.mark.parametrize("canonical", [False, True])
+def test_noalloc_tree_two_calls_big_then_small(canonical):
+    tree = trees.load_default()
+    for g, srcs in _graphs():
+        _run_pair(g, srcs, policy="tree", tree=tree, canonical_parents=canonical)
+
+
+@pytest.mark.parametrize("base", [gsw.PUSH_VERTEX, gsw.PUSH_WAVE16, gsw.PUSH_EDGE, gsw.PULL_BITMAP,
+                                  gsw.VERTEX_SCAN])
+def test_noalloc_fixed_kernels_two_calls(base):
+    for variant in (gsw.COUNT_WORKGROUP, gsw.COUNT_THREAD):
+        for g, srcs in _graphs():
+            _run_pair(g, srcs, policy="fixed", kernel=gsw.kernel_id(base, variant), canonical_parents=True)
+
+
+def test_noalloc_schedule_and_small_launches():
+    sched = [gsw.PUSH_EDGE, gsw.PULL_BITMAP, gsw.PUSH_WAVE8, gsw.PULL_BITMAP, gsw.PUSH_VERTEX]
+    for g, srcs in _graphs():
+        _run_pair(g, srcs, policy="schedule", schedule=sched, max_workgroups=3, canonical_parents=True)
+
+
+def test_noalloc_rejects_what_it_cannot_hold():
+    import torch
+
+    n = MAX_N + 7
+    offs = np.zeros(n + 1, dtype=np.int64)
+    cols = np.zeros(0, dtype=np.int32)
+    G = gsw.Graph.from_csr(offs, cols)
+    try:
+        lv = torch.empty((1, n), dtype=torch.int32, device="cuda")
+        with pytest.raises(gsw.GswError, match="at most"):
+            gsw.bfs_noalloc(G, [0], lv, policy="fixed", kernel=gsw.PUSH_VERTEX)
+    finally:
+        G.close()
+    g = gg.rmat(10, 16, seed=1)
+    G = gsw.Graph.from_csr(g.offs, g.cols)
+    try:
+        lv = torch.empty((1, g.n), dtype=torch.int32, device="cuda")
+        with pytest.raises(gsw.GswError, match="origin"):
+            gsw.bfs_noalloc(G, [int(gg.pick_sources(g, 1, 101)[0])], lv, policy="fixed", kernel=gsw.EDGE_SCAN)
+    finally:
+        G.close()
