@@ -473,6 +473,10 @@ const char *gsw_last_error(void);
 const char *gsw_kernel_name(int32_t kernel_id); /* base name, then ".wave" or ".thread" for
                                                    those count variants; "?" for an unknown id */
 int32_t gsw_abi_version(void);
+/* Build stamp: a digest of the sources the library was compiled from (the
+ * Python binding refuses a library whose stamp differs from the sources
+ * beside it), or "unstamped". */
+const char *gsw_source_digest(void);
 
 #ifdef __cplusplus
 }

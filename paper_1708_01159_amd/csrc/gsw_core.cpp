@@ -420,6 +420,11 @@ const char* gsw_feature_name(int32_t i) { return (i >= 0 && i < GSW_N_FEATURES) 
 
 int32_t gsw_abi_version(void) { return GSW_ABI_VERSION; }
 
+#ifndef GSW_SOURCE_DIGEST
+#define GSW_SOURCE_DIGEST "unstamped"
+#endif
+const char* gsw_source_digest(void) { return GSW_SOURCE_DIGEST; }
+
 void gsw_bfs_opts_default(gsw_bfs_opts* o) {
   if (!o) return;
   std::memset(o, 0, sizeof *o);

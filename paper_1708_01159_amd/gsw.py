@@ -120,6 +120,7 @@ def lib():
         "gsw_last_error": (ctypes.c_char_p, []),
         "gsw_kernel_name": (ctypes.c_char_p, [i32]),
         "gsw_abi_version": (i32, []),
+        "gsw_source_digest": (ctypes.c_char_p, []),
         "gsw_bfs_opts_default": (None, [P(BfsOpts)]),
         "gsw_graph_validate": (i32, [i64, i64, vp, vp, P(i32)]),
         "gsw_graph_create_host": (i32, [i64, i64, vp, vp, u32, P(vp)]),
@@ -156,6 +157,12 @@ def lib():
         f = getattr(L, name)
         f.restype = res
         f.argtypes = args
+    from .build import source_digest
+
+    built, here = L.gsw_source_digest().decode(), source_digest()
+    if built != here:
+        raise RuntimeError("libgsw.so was built from other sources (stamp %s, sources %s); rebuild with "
+                           "python -m paper_1708_01159_amd.build" % (built, here))
     _lib = L
     return L
 

@@ -110,8 +110,9 @@ def collect(graphs=None, reps: int = 3, kernels=None, log=print, source_seed: in
         flags = gsw.TRUSTED | (0 if "_dir" in name else gsw.ASSUME_SYMMETRIC)
         G = gsw.Graph.from_csr(g.offs, g.cols, flags=flags)
         r = reps if g.n < (1 << 19) or "grid" not in name else max(1, reps - 1)
-        for s in gg.pick_sources(g, nsrc, source_seed):
+        for i, s in enumerate(gg.pick_sources(g, nsrc, source_seed)):
             times, fr, _ = gsw.bfs_profile(G, int(s), kernels=ks, reps=r, advance_kernel=-1)
+            log("  %s source %d/%d: %d levels (%.1f s)" % (name, i + 1, nsrc, len(fr), time.time() - t0))
             disc = np.cumsum(fr)
             for d in range(len(fr)):
                 X.append(G.level_features(int(fr[d]), int(disc[d])))

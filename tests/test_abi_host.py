@@ -35,6 +35,19 @@ def test_every_declared_symbol_is_exported():
     assert not missing, missing
 
 
+def test_library_stamp_matches_sources(monkeypatch):
+    """The library carries the digest of the sources it was built from; the
+    binding refuses one built from other sources (a stale binary)."""
+    from paper_1708_01159_amd import build
+
+    lib = gsw.lib()
+    assert lib.gsw_source_digest().decode() == build.source_digest()
+    monkeypatch.setattr(gsw, "_lib", None)
+    monkeypatch.setattr(build, "source_digest", lambda: "0000000000000000")
+    with pytest.raises(RuntimeError, match="other sources"):
+        gsw.lib()
+
+
 def test_header_and_binding_agree_on_constants():
     text = open(os.path.join(ROOT, "include", "gsw.h")).read()
     consts = dict((m.group(1), int(m.group(2)))
