@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define GSW_ABI_VERSION 2
+#define GSW_ABI_VERSION 3
 
 typedef enum {
   GSW_OK = 0,
@@ -135,7 +135,8 @@ typedef struct {
   int32_t source_idx;   /* index into the sources array */
   int32_t level;        /* d: this row expanded the depth-d vertices */
   int32_t kernel;       /* kernel id (GSW_KERNEL_ID) that ran */
-  int32_t flags;        /* bit0: tree leaf undecided, fallback rule applied */
+  int32_t flags;        /* bit0: tree leaf undecided, fallback rule applied;
+                           bit2: run by a single-workgroup multi-level launch */
   int64_t n_frontier;   /* n_f(d): vertices at depth d */
   int64_t discovered;   /* vertices at depths 0..d */
   int64_t n_next;       /* vertices found at depth d+1 (0 on the last row) */
@@ -173,6 +174,14 @@ typedef struct {
   int32_t count_arcs;        /* 1: fill gsw_level_trace.e_frontier: the lanes that discover
                                 a vertex add its out-degree to per-level counters (16
                                 more bytes read per discovered vertex) */
+  int32_t no_solo;           /* 1: never run levels in single-workgroup launches.  0 (the
+                                default): while the frontier is small (at most 512
+                                vertices, with bounded arcs) and the policy names a
+                                queue-driven top-down kernel (push_vertex, push_wave,
+                                push_edge), one workgroup of 1024 threads runs such levels
+                                one after another in a single launch, deciding each next
+                                kernel itself, instead of one launch of the whole grid per
+                                level; results are the same.  Off with time_levels = 2. */
   void *stream;              /* hipStream_t for the work; NULL = library stream */
 } gsw_bfs_opts;
 
@@ -339,7 +348,7 @@ gsw_status gsw_bfs_profile(const gsw_graph *g, int32_t source, const int32_t *ke
 #define GSW_NOALLOC_MAX_VERTICES (1 << 19)
 #define GSW_NOALLOC_MAX_TREE_NODES 4095
 #define GSW_NOALLOC_MAX_SCHEDULE 4096
-#define GSW_NOALLOC_SCRATCH_BYTES 50742784 /* 48.4 MiB */
+#define GSW_NOALLOC_SCRATCH_BYTES 50774528 /* 48.4 MiB */
 gsw_status gsw_bfs_noalloc(const gsw_graph *g, const int32_t *sources, int32_t n_sources,
                            int32_t *levels, int32_t *parents, gsw_level_trace *trace,
                            int32_t trace_cap, int32_t *trace_len, const gsw_bfs_opts *opts);

@@ -22,6 +22,9 @@ namespace {
 // far have used, plus one more when the next level is push_edge (two
 // launches).  Launches queued past the end of the search do nothing.
 constexpr int kAhead = 3;
+// Single-workgroup launches queued beyond the latest record's: one runs
+// many levels, so one more is enough to follow it without a gap.
+constexpr int kSoloAhead = 2;
 
 // Launch size for queued levels: the full grid, or kSmallLaunch workgroups
 // while the search is in a quiet phase -- the latest frontier the host knows
@@ -34,7 +37,7 @@ constexpr int kAhead = 3;
 // per level).  A scale-free frontier can grow a thousandfold in one level
 // early on, which the conditions exclude.  Any size is correct: a level that
 // asks for more workgroups than its launch has strides over its work.
-constexpr int32_t kSmallLaunch = 64;
+constexpr int32_t kSmallLaunch = 16;
 constexpr int64_t kSmallFrontier = 4096;
 
 struct Policy {
@@ -242,6 +245,9 @@ BfsBase make_base(const gsw_graph* g, const Workspace& w, int32_t* lv, int32_t* 
   b.timed = timed ? 1 : 0;
   b.grid_max = level_kernel_grid(g->n, w.nw);
   b.count_arcs = count_arcs ? 1 : 0;
+  const double dm = g->deg_stats[4];
+  b.deg_max = dm >= 2147483647.0 ? 2147483647 : (int32_t)dm;
+  b.solo = 0;
   return b;
 }
 
@@ -262,6 +268,7 @@ bool take_record(const volatile unsigned long long* ring, int64_t d, Record* rec
   rec->ticks = v[kRecTicks];
   rec->next_kernel = (int)v[kRecNextKernel] - 1;
   rec->ef = (int64_t)v[kRecEf] - 1;
+  rec->launch = (int64_t)v[kRecLaunch];
   return true;
 }
 
@@ -315,7 +322,11 @@ gsw_status run_levels(gsw_graph* g, const Policy& pol, const BfsPolicy& dp, int3
   const gsw_bfs_opts* o = pol.o;
   const bool events = o->time_levels == 2;  // per-launch HIP events
   const bool timed = o->time_levels == 1;   // device wall-clock stamps
-  std::memset(w.ring, 0, (size_t)kBfsRing * kBfsRec * sizeof(unsigned long long));
+  // clear the ring slots the last search wrote (its records carry the tags
+  // this search's first levels will use)
+  const int64_t used = w.ring_used < 0 || w.ring_used > kBfsRing ? kBfsRing : w.ring_used;
+  std::memset(w.ring, 0, (size_t)used * kBfsRec * sizeof(unsigned long long));
+  w.ring_used = kBfsRing;  // until this search ends normally
   constexpr int kEv = Workspace::kLaunchEvents;
   if (events)
     for (hipEvent_t& e : w.lev)
@@ -324,45 +335,57 @@ gsw_status run_levels(gsw_graph* g, const Policy& pol, const BfsPolicy& dp, int3
   auto ev_after = [&](int64_t jj) -> hipEvent_t& { return w.lev[(size_t)((jj + 1) % kEv)]; };
   int32_t flags0 = 0;
   const int k0 = first_kernel(g, o, pol.has_origin, pol.has_rorigin, &flags0);
-  const BfsBase b = make_base(g, w, lv, pa, timed, o->count_arcs != 0);
+  BfsBase b = make_base(g, w, lv, pa, timed, o->count_arcs != 0);
+  // single-workgroup multi-level launches: not with per-launch events (their
+  // levels would share one launch's time), and with a tree its workgroup holds
+  b.solo = !o->no_solo && !events && (o->policy != GSW_POLICY_TREE || w.tree_nodes <= kSoloTree) ? 1 : 0;
   GSW_TRY(launch_init(g, b, g->iso, src, k0, flags0, s));
   if (events) GSW_HIP(hipEventRecord(ev_after(-1), s));
-  int64_t first_j = 0;  // first launch of the level whose record is read next
-  int32_t j = 0;     // launches of the level kernel so far
-  int ahead = 0;     // of those, not yet used by a level whose record was read
-  int want = kAhead + level_launches(k0, 1) - 1;
+  int64_t launched = 0;  // launches of the level kernels so far
+  int64_t consumed = 0;  // of those, launches that completed a level whose record was read
+  // A single-workgroup launch may hand its first level back untouched (too
+  // many arcs for one workgroup); the launch queued after one is therefore
+  // always a full-grid one, which runs whatever level it finds.
+  bool solo = b.solo && solo_eligible(k0, 1, 1, 1, g->n, b.deg_max);
+  bool last_solo = false;
+  int want = solo ? kSoloAhead : kAhead + level_launches(k0, 1) - 1;
   const int32_t cap = o->max_workgroups > 0 && o->max_workgroups < b.grid_max ? o->max_workgroups : b.grid_max;
   int32_t size = cap;
   int64_t nf_prev = 0;  // frontier of the level before the latest record's
-  for (int64_t d = 0;; ++d) {
-    while (ahead < want) {
-      GSW_TRY(launch_level_auto(g, b, dp, j++, size, s));
-      if (events) GSW_HIP(hipEventRecord(ev_after(j - 1), s));
-      ++ahead;
+  int64_t d = 0;
+  for (;; ++d) {
+    while (launched - consumed < want) {
+      last_solo = solo && !last_solo;
+      if (last_solo)
+        GSW_TRY(launch_level_solo(g, b, dp, (int32_t)launched, s));
+      else
+        GSW_TRY(launch_level_auto(g, b, dp, (int32_t)launched, size, s));
+      if (events) GSW_HIP(hipEventRecord(ev_after(launched), s));
+      ++launched;
     }
     Record r;
     GSW_TRY(wait_record(g, d, s, &r));
-    const int k = r.kernel;
     const int64_t nn = r.next;
     const int nk = r.next_kernel;
-    const int64_t last_j = first_j + level_launches(k, r.nf) - 1;
+    const int64_t first_j = consumed;  // launches of this level: first_j .. r.launch
     if (trace && *rows < trace_cap) {
       trace_row(&trace[*rows], src_idx, d, r, timed, w.tick_ms);
       if (events) {
         float ms = 0.0f;
-        GSW_HIP(hipEventSynchronize(ev_after(last_j)));
-        GSW_HIP(hipEventElapsedTime(&ms, ev_after(first_j - 1), ev_after(last_j)));
+        GSW_HIP(hipEventSynchronize(ev_after(r.launch)));
+        GSW_HIP(hipEventElapsedTime(&ms, ev_after(first_j - 1), ev_after(r.launch)));
         trace[*rows].ms = ms;
       }
     }
-    first_j = last_j + 1;
+    if (r.launch + 1 > consumed) consumed = r.launch + 1;
     ++*rows;
-    ahead -= level_launches(k, r.nf);
     if (nn == 0) break;
-    want = kAhead + level_launches(nk, nn) - 1;
+    solo = b.solo && solo_eligible(nk, nn, r.nf, r.disc + nn, g->n, b.deg_max);
+    want = solo ? kSoloAhead : kAhead + level_launches(nk, nn) - 1;
     size = launch_size(nk, nn, r.nf, nf_prev, r.disc, d, g->n, cap);
     nf_prev = r.nf;
   }
+  w.ring_used = d + 1;
   if (o->canonical_parents && pa) GSW_TRY(launch_canonical_parents(g, lv, pa, s));
   return GSW_OK;
 }
@@ -543,6 +566,7 @@ gsw_status gsw_bfs_profile(const gsw_graph* cg, int32_t source, const int32_t* k
   const BfsPolicy dp = device_policy(g, w, &fo, has_origin, has_rorigin);
   const BfsBase b = make_base(g, w, lv, pa, false, false);
   std::memset(w.ring, 0, (size_t)kBfsRing * kBfsRec * sizeof(unsigned long long));
+  w.ring_used = -1;  // every level reposts its record here: the next search clears the whole ring
   GSW_TRY(launch_init(g, b, g->iso, source, GSW_DEFAULT_KERNEL, 0, s));
   GSW_HIP(hipStreamSynchronize(s));
   int64_t nf = 1;

@@ -94,6 +94,7 @@ struct Workspace {
   size_t bytes = 0;
   bool head_built = false;               // head holds the graph's rows
   bool ready = false;                    // every buffer allocated and built
+  int64_t ring_used = -1;                // ring slots the last search may have written (-1: all)
 };
 
 struct MsWorkspace;  // batched BFS state (gsw_msbfs.hip)
@@ -152,6 +153,8 @@ struct BfsCtl {
   unsigned long long t_begin;  // wall clock at the start of the running level (timed levels)
   long long etot;              // push_edge: arcs of the frontier (set by the prefix launch)
   long long ef;                // arcs of the depth-d frontier (count_arcs), else -1
+  int32_t clean;               // 1: the bitmap of depth d-1 (bm[(d + 2) % 3]) is already all zero
+  int32_t pad;
 };
 // Workgroups count themselves finished, together with the queue entries they
 // appended, in kDoneGroups 64-bit counters (by index modulo kDoneGroups,
@@ -211,8 +214,41 @@ struct BfsBase {
   int32_t timed;                   // record each level's duration
   int32_t grid_max;                // workgroups of a level-kernel launch
   int32_t count_arcs;              // accumulate the next frontier's out-degrees
+  int32_t solo;                    // small-frontier levels may run in single-workgroup launches
+  int32_t deg_max;                 // largest out-degree (clamped to 2^31 - 1)
   int32_t pad;
 };
+
+// Single-workgroup multi-level launches (k_level_solo): while the frontier
+// is small, one workgroup of kSoloBlock threads runs consecutive top-down
+// levels from the queue, applies the policy between them and posts every
+// level's record, instead of one launch of the whole grid per level.  A
+// level qualifies when its kernel is a queue-driven top-down one
+// (push_vertex, push_wave, push_edge), its frontier has at most kSoloMax
+// vertices and its arcs are bounded: by the graph's largest degree, or, in
+// the shrinking tail of a search that has reached 1% of the graph, by a
+// check of the actual arc count (at most kSoloMaxArcs) before the level
+// starts.  A launch runs at most kSoloMaxLevels levels.
+// One compute unit's memory pipeline bounds such a workgroup: measured on
+// MI355X (2048 x 2048 grid), a level costs it about 3.5 us up to 64
+// frontier vertices, 4.3 us up to 256 and 6.4 us up to 512, then grows with
+// the frontier (12 us up to 1024, 22 us up to 2048), while a level kernel
+// launch costs about 6 us on the device plus about 3 us between launches at
+// any of these sizes; hence kSoloMax = 512.
+constexpr int kSoloBlock = 1024;
+constexpr int kSoloSlots = 2;  // frontier entries per thread at most
+constexpr int64_t kSoloMax = 512;
+static_assert(kSoloMax <= (int64_t)kSoloBlock * kSoloSlots, "every frontier entry has a thread slot");
+constexpr int64_t kSoloMaxArcs = 65536;
+constexpr int kSoloMaxLevels = 32;
+constexpr int32_t kSoloTree = 1024;  // tree nodes the workgroup holds in LDS
+__host__ __device__ inline bool solo_eligible(int k, long long nn, long long nf, long long disc_next, long long n,
+                                              int32_t deg_max) {
+  if (k < 0 || kernel_base(k) > GSW_K_PUSH_EDGE) return false;
+  if (nn < 1 || nn > kSoloMax) return false;
+  if ((long long)deg_max * nn <= kSoloMaxArcs) return true;
+  return nn <= nf && disc_next * 100 >= n;
+}
 
 // A tree node in 8 bytes for the device walk: left and right child (int16,
 // -1 at a leaf), the count the split tests (0: next frontier size,
@@ -230,7 +266,7 @@ constexpr int32_t kMaxTreeNodes = 32767;
 // value below 2^48 in the rest, so the host takes a record once all its
 // words bear the tag, whatever order their stores arrive in, and the device
 // never waits for them.
-constexpr int kBfsRing = 8;
+constexpr int kBfsRing = 256;
 constexpr int kBfsRec = 16;
 enum : int {
   kRecKernel = 0,   // kernel that ran level d
@@ -241,8 +277,11 @@ enum : int {
   kRecTicks = 5,    // wall-clock ticks of the level (timed levels)
   kRecNextKernel = 6,  // kernel chosen for level d+1, plus one (0: none)
   kRecEf = 7,          // arcs of the depth-d frontier plus one (0: not counted)
-  kBfsRecWords = 8
+  kRecLaunch = 8,      // index of the level-kernel launch that completed level d
+  kBfsRecWords = 9
 };
+// Trace flag of a level run by a single-workgroup multi-level launch.
+constexpr int32_t kFlagSolo = 4;
 constexpr unsigned long long kRecValueMask = (1ull << 48) - 1ull;
 // Never zero (the cleared ring) and different for the 8 levels sharing a slot.
 __host__ __device__ inline unsigned long long rec_tag(long long d) {
@@ -260,6 +299,10 @@ gsw_status launch_init(const gsw_graph* g, const BfsBase& b, const unsigned long
 // more workgroups than the launch has runs on the launch's, striding.
 gsw_status launch_level_auto(const gsw_graph* g, const BfsBase& b, const BfsPolicy& p, int32_t j,
                              int32_t workgroups, hipStream_t s);
+// Launch j as a single-workgroup multi-level launch: runs the levels that
+// qualify from the one control slot j % 2 names (none when it does not
+// qualify; the slot then passes to launch j + 1 unchanged).
+gsw_status launch_level_solo(const gsw_graph* g, const BfsBase& b, const BfsPolicy& p, int32_t j, hipStream_t s);
 // Workgroups of a level-kernel launch on a graph of n vertices (nw bitmap words).
 int32_t level_kernel_grid(int64_t n, int64_t nw);
 // Workgroups of that launch that run a level of `kernel` with n_in frontier entries.
@@ -279,6 +322,7 @@ struct Record {
   unsigned long long ticks;
   int next_kernel;  // kCtlDone when the search ended
   int64_t ef;       // arcs of the level's frontier, -1 when not counted
+  int64_t launch;   // launch that completed the level
 };
 // Level d's record from a ring (host memory), if all its words bear d's tag.
 bool take_record(const volatile unsigned long long* ring, int64_t d, Record* rec);

@@ -92,6 +92,8 @@ struct Args {
   int32_t grid;    // workgroups taking part in the level (grid-stride loops use it)
   int32_t cv;      // count variant (GSW_COUNT_*)
   int32_t count_arcs;
+  int32_t j;       // index of this launch (posted in the level's record)
+  uint32_t per;    // push_vertex, push_wave: frontier entries per workgroup
 };
 
 __host__ __device__ inline Args make_args(const BfsBase& b, int32_t j, int32_t d, uint32_t n_in, int32_t set_nx,
@@ -130,10 +132,24 @@ __host__ __device__ inline Args make_args(const BfsBase& b, int32_t j, int32_t d
   a.grid = grid;
   a.cv = 0;
   a.count_arcs = b.count_arcs;
+  a.j = j;
+  a.per = kBlock;
   return a;
 }
 
 __host__ __device__ inline int64_t div_up(int64_t x, int64_t y) { return (x + y - 1) / y; }
+
+// Frontier entries per workgroup of the lane-per-vertex push kernels
+// (push_vertex, push_wave): the entries spread over the launch's
+// participating workgroups, at least kPushMinPer and at most kBlock per
+// workgroup, so a small frontier holding hubs has them walked by many
+// workgroups at once instead of by the few that a full 256 entries each
+// would give it.
+constexpr int64_t kPushMinPer = 16;
+__host__ __device__ inline uint32_t push_per(int64_t n_in, int32_t grid_max) {
+  const int64_t per = div_up(n_in, grid_max);
+  return (uint32_t)(per < kPushMinPer ? kPushMinPer : (per > kBlock ? kBlock : per));
+}
 
 // Workgroups that run a level of kernel k with n_in frontier entries: a lane
 // per entry for the queue-driven top-down kernels, a lane per vertex or arc
@@ -148,7 +164,7 @@ __host__ __device__ inline int32_t level_grid(int k, int64_t n_in, const BfsBase
     case GSW_K_PUSH_EDGE:  // its prefix launch, or every workgroup when fused
       need = level_first_phase(k, n_in) == 2 ? (int64_t)b.grid_max : div_up(n_in, kScanTile);
       break;
-    default: need = div_up(n_in, kBlock); break;
+    default: need = div_up(n_in, push_per(n_in, b.grid_max)); break;
   }
   if (need < 1) need = 1;
   return (int32_t)(need < b.grid_max ? need : b.grid_max);
@@ -610,7 +626,7 @@ __device__ __forceinline__ void level_end(const Args& a, const BfsBase* base, co
   u64* r = ring + (size_t)(d % kBfsRing) * kBfsRec;
   const u64 tag = rec_tag(d);
   const u64 rec[kBfsRecWords] = {(u64)k_run, (u64)c->flags, (u64)nf, (u64)disc, (u64)nn, ticks & kRecValueMask,
-                              (u64)(next + 1), (u64)(c->ef + 1) & kRecValueMask};
+                              (u64)(next + 1), (u64)(c->ef + 1) & kRecValueMask, (u64)a.j};
 #pragma unroll
   for (int i = 0; i < kBfsRecWords; ++i)
     __hip_atomic_store(r + i, tag | rec[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -627,6 +643,7 @@ __device__ __forceinline__ void level_end(const Args& a, const BfsBase* base, co
   cn->grid = next >= 0 ? level_grid(next, (int64_t)nn, *base) : 1;
   cn->etot = 0;
   cn->ef = ef_next;
+  cn->clean = 0;
 }
 
 // ---------------------------------------------------------------- init
@@ -685,6 +702,7 @@ __global__ void __launch_bounds__(kBlock) k_init(BfsBase b, const u64* __restric
     c->grid = level_grid(k0, 1, b);
     c->etot = 0;
     c->ef = b.count_arcs ? (long long)(b.offs[s + 1] - b.offs[s]) : -1;
+    c->clean = 1;
   }
   if (gid < 4 * kCtrSlot) b.ctr[gid] = gid == 0 ? 1u : 0u;
   if (gid < 4 * kArcSlot) b.actr[gid] = 0ull;
@@ -785,15 +803,15 @@ __device__ __forceinline__ void long_walk(LongRows& L, uint32_t r, Stage& st, co
 
 // ------------------------------------------------- push_vertex (lane / vertex)
 __device__ __forceinline__ void body_push_vertex(const Args& a, Stage& st, const QueueIn& qi, LongRows& L) {
-  const uint32_t stride = (uint32_t)a.grid * kBlock;
+  const uint32_t stride = (uint32_t)a.grid * a.per;
   long_init(L);
   uint32_t r = 0;
-  for (uint32_t base = blockIdx.x * kBlock; base < a.n_in; base += stride, ++r) {
+  for (uint32_t base = blockIdx.x * a.per; base < a.n_in; base += stride, ++r) {
     long_round_begin(L, r);
     const uint32_t i = base + threadIdx.x;
     int32_t u = 0;
     int64_t beg = 0, end = 0;
-    if (i < a.n_in) {
+    if (threadIdx.x < a.per && i < a.n_in) {
       u = queue_at(a, qi, i);
       beg = a.offs[u];
       end = a.offs[u + 1];
@@ -813,15 +831,15 @@ __device__ __forceinline__ void body_push_wave(const Args& a, Stage& st, const Q
   const int lane = lane_id();
   const int sub = lane & (W - 1);
   const int first = lane & ~(W - 1);
-  const uint32_t stride = (uint32_t)a.grid * kBlock;
+  const uint32_t stride = (uint32_t)a.grid * a.per;
   long_init(L);
   uint32_t r = 0;
-  for (uint32_t base = blockIdx.x * kBlock; base < a.n_in; base += stride, ++r) {
+  for (uint32_t base = blockIdx.x * a.per; base < a.n_in; base += stride, ++r) {
     long_round_begin(L, r);
     const uint32_t i = base + threadIdx.x;  // this lane's own entry
     int32_t u = 0;
     int64_t beg = 0, end = 0;
-    if (i < a.n_in) {
+    if (threadIdx.x < a.per && i < a.n_in) {
       u = queue_at(a, qi, i);
       beg = a.offs[u];
       end = a.offs[u + 1];
@@ -996,6 +1014,7 @@ __device__ __forceinline__ void edge_prefix_end(const Args& a, const BfsBase& b,
     cn->grid = (int32_t)(chunks < 1 ? 1 : (chunks < b.grid_max ? chunks : b.grid_max));
     cn->etot = run;
     cn->ef = c->ef;
+    cn->clean = c->clean;
   }
 }
 
@@ -1393,6 +1412,7 @@ __global__ void __launch_bounds__(kBlock) k_level_auto(BfsBase b, BfsPolicy p, i
   if (k != GSW_K_PULL_BITMAP && k != GSW_K_VERTEX_SCAN && k != GSW_K_EDGE_SCAN && k != GSW_K_REV_EDGE_SCAN) {
     queue_in_load(cpre, d & 3, qi);
     a.n_in = qi.pre[kQueueBins];
+    a.per = push_per(a.n_in, a.grid);  // spread over the workgroups that take part
   }
   if (k == GSW_K_PUSH_EDGE && phase == 0) {
     body_edge_prefix(a, qi, b, lds.wsum);
@@ -1428,6 +1448,368 @@ __global__ void __launch_bounds__(kBlock) k_level_auto(BfsBase b, BfsPolicy p, i
   u64 total = 0ull;
   const bool last = stage_flush_finish(st, a, &total);
   level_end(a, &b, p, b.ring, k_id, st.buf, (int)sizeof(st.buf), tl, last, total);
+}
+
+// ------------------------------------ single-workgroup multi-level launches
+// While the frontier is small (kSoloMax vertices, arcs bounded), one
+// workgroup of kSoloBlock threads runs level after level of the queue-driven
+// top-down expansion, applying the policy between levels and posting every
+// level's record, so a long run of small levels (a high-diameter graph, the
+// tail of a scale-free search) costs one launch instead of one launch of the
+// whole grid per level.  Each level: every thread takes up to kSoloSlots
+// frontier vertices (entry i = thread + kSoloBlock * slot) and walks rows of
+// up to kSoloShort arcs itself, all its arcs in flight together; longer rows
+// are set aside and their arcs spread over the whole workgroup through a
+// prefix of their lengths (so one row never holds one thread).  Discoveries
+// go to the queue segment 0 of the next depth with one LDS reservation per
+// wavefront; the frontier bitmaps are not kept while the workgroup runs
+// (all three are zero then) and the one of the depth the workgroup hands
+// back is rebuilt from the queue when it stops.
+constexpr int kSoloShort = 8;
+constexpr int kSoloLong = kSoloBlock;  // long rows set aside per level at most
+constexpr int kSoloWaves = kSoloBlock / 64;
+
+struct SoloLds {
+  u64 t_node[kSoloTree];
+  int32_t t_thr[kSoloTree];
+  int32_t t_next[kSoloTree];
+  int64_t lbeg[kSoloLong];      // long rows: first arc
+  int32_t lu[kSoloLong];        // long rows: vertex
+  int32_t lpre[kSoloLong + 1];  // long rows: arc counts, then their exclusive prefix
+  int32_t wsum[kSoloWaves];
+  u64 esum;                     // arcs of the level's frontier
+  uint32_t cnt;                 // next-frontier entries reserved
+  uint32_t nlong;               // long rows set aside
+  uint32_t nn;                  // the next frontier's size, for every thread
+  int32_t go, next, nflags, pad;
+};
+
+// Claims the targets v[q] >= 0 (visited-word load, then the atomic where the
+// bit is clear) for sources u[q / PER]; winners get depth d + 1, their
+// parent, and a place in qout reserved by one LDS atomic per wavefront.
+// Every lane of the wavefront calls it.
+template <int N, int PER>
+__device__ __forceinline__ void solo_visit(const BfsBase& b, int32_t d, int32_t* qout, uint32_t* cnt,
+                                           const int32_t (&v)[N], const int32_t (&u)[N / PER]) {
+  u64 w[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) w[q] = v[q] >= 0 ? b.vis[v[q] >> 6] : ~0ull;
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    const u64 bit = 1ull << (v[q] & 63);
+    if (!(w[q] & bit)) w[q] = atomicOr(b.vis + (v[q] >> 6), bit);  // the word before this lane's bit
+  }
+  uint32_t mine = 0;
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    const bool win = v[q] >= 0 && !(w[q] & (1ull << (v[q] & 63)));
+    if (win) {
+      b.level[v[q]] = d + 1;
+      if (b.parent) b.parent[v[q]] = u[q / PER];
+      ++mine;
+    }
+  }
+  const int lane = lane_id();
+  uint32_t inc = mine;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)inc, off);
+    if (lane >= off) inc += y;
+  }
+  const uint32_t total = (uint32_t)__shfl((int)inc, 63);
+  if (total == 0u) return;
+  uint32_t base = 0u;
+  if (lane == 63) base = atomicAdd(cnt, total);
+  base = (uint32_t)__shfl((int)base, 63) + inc - mine;
+#pragma unroll
+  for (int q = 0; q < N; ++q)
+    if (v[q] >= 0 && !(w[q] & (1ull << (v[q] & 63)))) qout[base++] = v[q];
+}
+
+// Entry i of the depth-d queue as a level kernel wrote it (kQueueBins segments).
+__device__ __forceinline__ int32_t solo_queue_binned(const BfsBase& b, int32_t d, const QueueIn& qi, uint32_t i) {
+  int bin = 0;
+#pragma unroll
+  for (int k = 1; k < kQueueBins; ++k) bin += i >= qi.pre[k] ? 1 : 0;
+  return b.q[d & 1][(int64_t)bin * b.n + (i - qi.pre[bin])];
+}
+
+// Hands depth L back to the level kernel: its frontier (f entries, segment 0
+// of the depth-L queue) becomes the queue's only segment and the depth-L
+// bitmap, the counters the level will append to are zeroed, and control
+// slot cn describes level L.  Every thread calls it.
+__device__ __forceinline__ void solo_publish(const BfsBase& b, BfsCtl* cn, int32_t L, int32_t kernel, int32_t prev,
+                                             int32_t flags, long long f, long long disc, long long ef) {
+  const int tid = threadIdx.x;
+  const int32_t* q = b.q[L & 1];
+  u64* bm = b.bm[L % 3];
+  for (long long i = tid; i < f; i += kSoloBlock) {
+    const int32_t v = q[i];
+    atomicOr(bm + (v >> 6), 1ull << (v & 63));
+  }
+  if (tid < kQueueBins) {
+    b.ctr[(size_t)(L & 3) * kCtrSlot + tid * kCtrStride] = tid == 0 ? (uint32_t)f : 0u;
+    b.ctr[(size_t)((L + 1) & 3) * kCtrSlot + tid * kCtrStride] = 0u;
+    b.actr[(size_t)((L + 1) & 3) * kArcSlot + tid * kArcStride] = 0ull;
+  }
+  if (tid == 0) {
+    cn->d = L;
+    cn->kernel = kernel;
+    cn->prev = prev;
+    cn->flags = flags;
+    cn->nf = f;
+    cn->disc = disc;
+    cn->done = 0ull;
+    cn->phase = level_first_phase(kernel, f);
+    cn->t_begin = 0ull;
+    cn->grid = level_grid(kernel, f, b);
+    cn->etot = 0;
+    cn->ef = ef;
+    cn->clean = 1;
+  }
+}
+
+__global__ void __launch_bounds__(kSoloBlock) k_level_solo(BfsBase b, BfsPolicy p, int32_t j) {
+  __shared__ SoloLds L;
+  __shared__ QueueIn qi;
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wid = tid >> 6;
+  const uint32_t cpre = counters_prefetch(b.ctr);
+  const BfsCtl* c = b.ctl + (j & 1);
+  BfsCtl* cn = b.ctl + ((j + 1) & 1);
+  int32_t k_id = c->kernel;
+  int32_t d = c->d;
+  long long nf = c->nf, disc = c->disc;
+  int32_t prev = c->prev, flags = c->flags;
+  const bool tree = p.policy == GSW_POLICY_TREE;
+  const bool ok = b.solo && k_id >= 0 && k_id < GSW_N_KERNELS && kernel_base(k_id) <= GSW_K_PUSH_EDGE &&
+                  nf >= 1 && nf <= kSoloMax && (!tree || p.t_nodes <= kSoloTree);
+  if (!ok) {  // not a level for this launch: the slot passes on unchanged
+    if (tid == 0) *cn = *c;
+    return;
+  }
+  if (tid == 0) {
+    L.esum = 0ull;
+    L.cnt = 0u;
+    L.nlong = 0u;
+  }
+  if (tree)
+    for (int i = tid; i < p.t_nodes; i += kSoloBlock) {
+      L.t_node[i] = p.t_node[i];
+      L.t_thr[i] = p.t_thr[i];
+    }
+  queue_in_load(cpre, d & 3, qi);  // ends with a barrier
+  if ((long long)qi.pre[kQueueBins] < nf) nf = (long long)qi.pre[kQueueBins];  // never past the queue's entries
+  const bool check_arcs = (long long)b.deg_max * kSoloMax > kSoloMaxArcs;
+  for (int lv = 0;; ++lv) {
+    u64 t0 = 0ull;
+    if (b.timed && tid == 0) t0 = (u64)wall_clock64();
+    // the level's frontier: binned as the level kernel left it on the first
+    // level, segment 0 afterwards
+    int32_t u[kSoloSlots];
+    int64_t beg[kSoloSlots], end[kSoloSlots];
+    bool lng[kSoloSlots];
+#pragma unroll
+    for (int q = 0; q < kSoloSlots; ++q) {
+      const long long i = tid + (long long)q * kSoloBlock;
+      u[q] = -1;
+      if (i < nf) u[q] = lv == 0 ? solo_queue_binned(b, d, qi, (uint32_t)i) : b.q[d & 1][i];
+    }
+    u64 arcs = 0ull;
+#pragma unroll
+    for (int q = 0; q < kSoloSlots; ++q) {
+      beg[q] = end[q] = 0;
+      if (u[q] >= 0) {
+        beg[q] = b.offs[u[q]];
+        end[q] = b.offs[u[q] + 1];
+      }
+      const int64_t deg = end[q] - beg[q];
+      arcs += (u64)deg;
+      lng[q] = false;
+      if (deg > kSoloShort) {  // set aside while there is room, else walked by this thread
+        const uint32_t at = atomicAdd(&L.nlong, 1u);
+        if (at < (uint32_t)kSoloLong) {
+          L.lu[at] = u[q];
+          L.lbeg[at] = beg[q];
+          L.lpre[at] = (int32_t)(deg < kSoloMaxArcs ? deg : kSoloMaxArcs + 1);
+          lng[q] = true;
+        }
+      }
+    }
+    if (check_arcs || b.count_arcs) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) arcs += __shfl_xor(arcs, off);
+      if (lane == 0 && arcs) atomicAdd(&L.esum, arcs);
+    }
+    __syncthreads();
+    const u64 esum = L.esum;
+    const uint32_t nlong = L.nlong < (uint32_t)kSoloLong ? L.nlong : (uint32_t)kSoloLong;
+    if (esum > (u64)kSoloMaxArcs) {
+      // too many arcs for one workgroup: the level goes back to the level
+      // kernel untouched (on the first level nothing has changed at all)
+      if (lv == 0) {
+        if (tid == 0) *cn = *c;
+      } else {
+        solo_publish(b, cn, d, k_id, prev, flags, nf, disc, b.count_arcs ? (long long)esum : -1);
+      }
+      return;
+    }
+    if (lv == 0) {
+      // the bitmaps are not kept here: clear the depth-d frontier's words and,
+      // unless known clean, the depth-(d-1) bitmap
+#pragma unroll
+      for (int q = 0; q < kSoloSlots; ++q)
+        if (u[q] >= 0) b.bm[d % 3][u[q] >> 6] = 0ull;
+      if (!c->clean)
+        for (int64_t i = tid; i < b.nw; i += kSoloBlock) b.bm[(d + 2) % 3][i] = 0ull;
+    }
+    int32_t* qout = b.q[(d + 1) & 1];
+    // rows not set aside: a pair of slots' next four arcs each in flight together
+    for (int r0 = 0;; r0 += 4) {
+      bool any_more = false;
+#pragma unroll
+      for (int h = 0; h < kSoloSlots; h += 2) {
+        const bool more = (!lng[h] && beg[h] + r0 < end[h]) || (!lng[h + 1] && beg[h + 1] + r0 < end[h + 1]);
+        if (!__any(more)) continue;
+        any_more = true;
+        int32_t v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int q = h + (k >> 2);
+          const int64_t e = beg[q] + r0 + (k & 3);
+          v[k] = !lng[q] && e < end[q] ? b.cols[e] : -1;
+        }
+        const int32_t us[2] = {u[h], u[h + 1]};
+        solo_visit<8, 4>(b, d, qout, &L.cnt, v, us);
+      }
+      if (!any_more) break;
+    }
+    // long rows: their arcs over the whole workgroup
+    if (nlong > 0u) {
+      const int32_t x = tid < (int)nlong ? L.lpre[tid] : 0;
+      int32_t inc = x;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int32_t y = __shfl_up(inc, off);
+        if (lane >= off) inc += y;
+      }
+      if (lane == 63) L.wsum[wid] = inc;
+      __syncthreads();
+      int32_t before = 0;
+      for (int w = 0; w < wid; ++w) before += L.wsum[w];
+      if (tid < (int)nlong) L.lpre[tid] = before + inc - x;
+      if (tid == (int)nlong - 1) L.lpre[nlong] = before + inc;
+      __syncthreads();
+      const int32_t total = L.lpre[nlong];
+      const int32_t rounds = (total + 4 * kSoloBlock - 1) / (4 * kSoloBlock);  // the same in every thread
+      for (int32_t r = 0; r < rounds; ++r) {
+        int32_t v[4], us[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int32_t a = tid + (4 * r + k) * kSoloBlock;
+          v[k] = -1;
+          us[k] = 0;
+          if (a < total) {
+            int lo = 0, hi = (int)nlong - 1;
+            while (lo < hi) {
+              const int mid = (lo + hi + 1) >> 1;
+              if (L.lpre[mid] <= a) lo = mid; else hi = mid - 1;
+            }
+            v[k] = b.cols[L.lbeg[lo] + (a - L.lpre[lo])];
+            us[k] = L.lu[lo];
+          }
+        }
+        solo_visit<4, 1>(b, d, qout, &L.cnt, v, us);
+      }
+    }
+    __syncthreads();
+    // level end: the policy picks the next kernel; the level's record
+    const uint32_t nn = L.cnt;
+    const long long ndisc = disc + (long long)nn;
+    if (tree && nn > 0u) {
+      if (tid < p.t_nodes) L.t_next[tid] = tree_step(L.t_node[tid], L.t_thr[tid], (int32_t)nn, (int32_t)ndisc);
+      __syncthreads();
+    }
+    if (tid == 0) {
+      int32_t next = kCtlDone, nflags = 0;
+      if (nn > 0u) {
+        if (tree) {
+          int32_t x = L.t_next[0];
+          while (x >= 0) x = L.t_next[x];
+          next = choose_leaf(p, x == -1 ? -1 : -x - 2, k_id, &nflags);
+        } else {
+          next = choose_next(p, d + 1, (long long)nn, ndisc, k_id, &nflags);
+        }
+      }
+      u64 ticks = 0ull;
+      if (b.timed) {
+        const u64 t1 = (u64)wall_clock64();
+        ticks = t1 > t0 ? t1 - t0 : 0ull;
+      }
+      u64* r = b.ring + (size_t)(d % kBfsRing) * kBfsRec;
+      const u64 tag = rec_tag(d);
+      const long long ef = b.count_arcs ? (long long)esum : -1;
+      const u64 rec[kBfsRecWords] = {(u64)k_id, (u64)(flags | kFlagSolo), (u64)nf, (u64)disc, (u64)nn,
+                                  ticks & kRecValueMask, (u64)(next + 1), (u64)(ef + 1) & kRecValueMask,
+                                  (u64)j};
+#pragma unroll
+      for (int i = 0; i < kBfsRecWords; ++i)
+        __hip_atomic_store(r + i, tag | rec[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      L.go = lv + 1 < kSoloMaxLevels && solo_eligible(next, (long long)nn, nf, ndisc, b.n, b.deg_max) ? 1 : 0;
+      L.next = next;
+      L.nflags = nflags;
+      L.nn = nn;
+      L.cnt = 0u;
+      L.nlong = 0u;
+      L.esum = 0ull;
+    }
+    __syncthreads();
+    const int32_t next = L.next, nflags = L.nflags;
+    const long long nnx = (long long)L.nn;
+    if (!L.go) {
+      if (nnx == 0) {
+        if (tid == 0) {
+          cn->d = d + 1;
+          cn->kernel = kCtlDone;
+          cn->prev = k_id;
+          cn->flags = 0;
+          cn->nf = 0;
+          cn->disc = ndisc;
+          cn->done = 0ull;
+          cn->phase = 0;
+          cn->t_begin = 0ull;
+          cn->grid = 1;
+          cn->etot = 0;
+          cn->ef = -1;
+          cn->clean = 1;
+        }
+        return;
+      }
+      long long ef_next = -1;
+      if (b.count_arcs) {  // the next frontier's arcs, for its record
+        u64 a = 0ull;
+        const int32_t* q = b.q[(d + 1) & 1];
+        for (long long i = tid; i < nnx; i += kSoloBlock) {
+          const int32_t v = q[i];
+          a += (u64)(b.offs[v + 1] - b.offs[v]);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+        if (lane == 0 && a) atomicAdd(&L.esum, a);
+        __syncthreads();
+        ef_next = (long long)L.esum;
+      }
+      solo_publish(b, cn, d + 1, next, k_id, nflags, nnx, ndisc, ef_next);
+      return;
+    }
+    prev = k_id;
+    k_id = next;
+    flags = nflags;
+    nf = nnx;
+    disc = ndisc;
+    ++d;
+  }
 }
 
 // ------------------------------------------------------------ helpers
@@ -1516,6 +1898,13 @@ gsw_status launch_init(const gsw_graph* g, const BfsBase& b, const unsigned long
   if (blocks < cdiv(4 * kCtrSlot, kBlock)) blocks = cdiv(4 * kCtrSlot, kBlock);
   const unsigned grid = (unsigned)(blocks > kMaxGrid ? kMaxGrid : blocks);
   hipLaunchKernelGGL(k_init, dim3(grid), dim3(kBlock), 0, s, b, (const u64*)iso, source, k0, flags0);
+  GSW_HIP(hipGetLastError());
+  return GSW_OK;
+}
+
+gsw_status launch_level_solo(const gsw_graph* g, const BfsBase& b, const BfsPolicy& p, int32_t j, hipStream_t s) {
+  (void)g;
+  hipLaunchKernelGGL(k_level_solo, dim3(1), dim3(kSoloBlock), 0, s, b, p, j);
   GSW_HIP(hipGetLastError());
   return GSW_OK;
 }

@@ -6,9 +6,10 @@
 // lives in one file-scope device array of fixed size, laid out for graphs of
 // up to GSW_NOALLOC_MAX_VERTICES vertices.  The level kernels are the same as
 // gsw_bfs's; only the buffers and the host's reading of the level records
-// differ: the records go to device memory, and the host queues kBfsRing
-// launches at a time, then copies the records back and waits, so at most
-// kBfsRing records are unread when it reads them.
+// differ: the records go to device memory, and the host queues kBatch
+// launches at a time (single-workgroup multi-level launches are not used
+// here, so each launch completes at most one level), then copies those
+// levels' records back and waits.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -83,9 +84,13 @@ DeviceScratch g_dev[kMaxDevices];
 // host-side tree buffers below are one per process.
 std::mutex g_mu;
 
-// Host buffers for specialising a tree (sized for the largest tree accepted).
+// Host buffers for specialising a tree (sized for the largest tree accepted)
+// and for the record ring's copy.
 int32_t h_order[kMaxTree], h_newid[kMaxTree], h_stack[kMaxTree + 1], h_thr[kMaxTree];
 unsigned long long h_nodes[kMaxTree];
+unsigned long long h_ring[(size_t)kBfsRing * kBfsRec];
+
+constexpr int kBatch = 8;  // launches queued before each read of the records
 
 gsw_status device_scratch(int device, DeviceScratch** out) {
   if (device < 0 || device >= kMaxDevices) return fail(GSW_EINVAL, "device %d out of range", device);
@@ -170,39 +175,47 @@ gsw_status check_options(const gsw_graph* g, const gsw_bfs_opts* o) {
   return GSW_OK;
 }
 
+// Copies the ring slots of levels d .. d + count - 1 into h_ring.
+gsw_status copy_records(const Workspace& w, int64_t d, int count, hipStream_t s) {
+  const size_t rec = (size_t)kBfsRec * sizeof(unsigned long long);
+  const int first = (int)(d % kBfsRing);
+  const int a = count < kBfsRing - first ? count : kBfsRing - first;
+  GSW_HIP(hipMemcpyAsync(h_ring + (size_t)first * kBfsRec, w.d_ring + (size_t)first * kBfsRec, (size_t)a * rec,
+                         hipMemcpyDeviceToHost, s));
+  if (count > a) GSW_HIP(hipMemcpyAsync(h_ring, w.d_ring, (size_t)(count - a) * rec, hipMemcpyDeviceToHost, s));
+  return GSW_OK;
+}
+
 // One source.  The records of the levels run by the launches queued so far
 // are all in the ring once the copy that follows them completes: each level
-// takes at least one launch, so kBfsRing launches post at most kBfsRing
-// records and none is overwritten before it is read.
+// takes at least one launch, so kBatch launches post at most kBatch records.
 gsw_status run_source(gsw_graph* g, const Workspace& w, const gsw_bfs_opts* o, const BfsPolicy& dp,
                       bool has_origin, bool has_rorigin, double tick_ms, int32_t src_idx, int32_t src,
                       int32_t* lv, int32_t* pa, const unsigned long long* iso, gsw_level_trace* trace,
                       int32_t trace_cap, int32_t* rows, hipStream_t s) {
   const bool timed = o->time_levels == 1;
-  const size_t ring_bytes = (size_t)kBfsRing * kBfsRec * sizeof(unsigned long long);
-  GSW_HIP(hipMemsetAsync(w.d_ring, 0, ring_bytes, s));
+  GSW_HIP(hipMemsetAsync(w.d_ring, 0, (size_t)kBfsRing * kBfsRec * sizeof(unsigned long long), s));
   int32_t flags0 = 0;
   const int k0 = first_kernel(g, o, has_origin, has_rorigin, &flags0);
-  const BfsBase b = make_base(g, w, lv, pa, timed, o->count_arcs != 0);
+  const BfsBase b = make_base(g, w, lv, pa, timed, o->count_arcs != 0);  // solo launches off
   GSW_TRY(launch_init(g, b, iso, src, k0, flags0, s));
   const int32_t cap = o->max_workgroups > 0 && o->max_workgroups < b.grid_max ? o->max_workgroups : b.grid_max;
-  unsigned long long h_ring[kBfsRing * kBfsRec];
   int32_t j = 0;
   for (int64_t d = 0;;) {
-    for (int i = 0; i < kBfsRing; ++i) GSW_TRY(launch_level_auto(g, b, dp, j++, cap, s));
-    GSW_HIP(hipMemcpyAsync(h_ring, w.d_ring, ring_bytes, hipMemcpyDeviceToHost, s));
+    for (int i = 0; i < kBatch; ++i) GSW_TRY(launch_level_auto(g, b, dp, j++, cap, s));
+    GSW_TRY(copy_records(w, d, kBatch, s));
     GSW_HIP(hipStreamSynchronize(s));
     const int64_t d0 = d;
     Record r;
     bool ended = false;
-    while (!ended && take_record(h_ring, d, &r)) {
+    while (!ended && d - d0 < kBatch && take_record(h_ring, d, &r)) {
       if (trace && *rows < trace_cap) trace_row(&trace[*rows], src_idx, d, r, timed, tick_ms);
       ++*rows;
       ++d;
       ended = r.next == 0;
     }
     if (ended) break;
-    if (d == d0) return fail(GSW_EHIP, "level %lld posted no record in %d launches", (long long)d, kBfsRing);
+    if (d == d0) return fail(GSW_EHIP, "level %lld posted no record in %d launches", (long long)d, kBatch);
   }
   if (o->canonical_parents && pa) GSW_TRY(launch_canonical_parents(g, lv, pa, s));
   return GSW_OK;

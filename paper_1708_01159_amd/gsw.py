@@ -80,7 +80,7 @@ class BfsOpts(ctypes.Structure):
                 ("tree", ctypes.c_void_p), ("time_levels", ctypes.c_int32),
                 ("canonical_parents", ctypes.c_int32), ("device_ptrs", ctypes.c_int32),
                 ("max_workgroups", ctypes.c_int32), ("count_arcs", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("no_solo", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class MsbfsOpts(ctypes.Structure):
@@ -414,7 +414,7 @@ def _opts(policy, kernel, schedule, tree, time_levels, canonical_parents, device
         o.schedule_len = keep.shape[0]
     else:
         raise ValueError("policy must be tree, fixed or schedule")
-    o.time_levels = int(bool(time_levels))
+    o.time_levels = int(time_levels)  # 0, 1 (device clock) or 2 (HIP events)
     o.canonical_parents = int(bool(canonical_parents))
     o.device_ptrs = int(bool(device_ptrs))
     o.stream = stream
@@ -424,7 +424,7 @@ def _opts(policy, kernel, schedule, tree, time_levels, canonical_parents, device
 def bfs(graph: Graph, sources, policy: str = "tree", kernel: int = PUSH_VERTEX, schedule=None,
         tree: Tree = None, parents: bool = True, time_levels: bool = False,
         canonical_parents: bool = False, device: bool = False, stream=None, out=None,
-        trace_cap: int = None, max_workgroups: int = 0, count_arcs: bool = False):
+        trace_cap: int = None, max_workgroups: int = 0, count_arcs: bool = False, solo: bool = True):
     """Level-switched BFS from each source.
 
     Returns ``(levels, parents, trace)``: ``levels`` is ``[len(sources), n]``
@@ -433,7 +433,8 @@ def bfs(graph: Graph, sources, policy: str = "tree", kernel: int = PUSH_VERTEX, 
     ``out`` may supply preallocated ``(levels, parents)`` device tensors.
     ``max_workgroups`` > 0 caps every level launch (for tests of the
     striding paths; 0 lets the library size launches).  ``count_arcs``
-    fills each trace row's ``e_frontier``.
+    fills each trace row's ``e_frontier``.  ``solo`` allows the
+    single-workgroup multi-level launches for small frontiers.
     """
     src = np.ascontiguousarray(np.atleast_1d(np.asarray(sources)), dtype=np.int32)
     S, n = src.shape[0], graph.n
@@ -456,6 +457,7 @@ def bfs(graph: Graph, sources, policy: str = "tree", kernel: int = PUSH_VERTEX, 
     o, keep = _opts(policy, kernel, schedule, tree, time_levels, canonical_parents, device, stream)
     o.max_workgroups = int(max_workgroups)
     o.count_arcs = int(bool(count_arcs))
+    o.no_solo = int(not solo)
     cap = trace_cap if trace_cap is not None else 64 * max(S, 1)
     while True:
         tr = (LevelTrace * max(cap, 1))()
@@ -508,7 +510,7 @@ class Runner:
 
     def __init__(self, graph: Graph, levels, parents=None, policy: str = "tree", kernel=PUSH_VERTEX,
                  schedule=None, tree: Tree = None, time_levels: bool = False, stream=None,
-                 trace_cap: int = 4096):
+                 trace_cap: int = 4096, solo: bool = True):
         import torch
 
         if stream is None:
@@ -518,6 +520,7 @@ class Runner:
             check_out(parents, "int32", graph.n, True, "Runner parents")
         self.graph, self.levels, self.parents, self.tree = graph, levels, parents, tree
         self.opts, self._keep = _opts(policy, kernel, schedule, tree, time_levels, False, True, stream)
+        self.opts.no_solo = int(not solo)
         self.trace = (LevelTrace * trace_cap)()
         self.cap = trace_cap
         self.tlen = ctypes.c_int32(0)
