@@ -153,7 +153,7 @@ def _logged(runner, tag, calls, counts=None, src_index=None):
         for r in runner.rows():
             b = traffic.level_bytes(r.kernel, c, r.level) if c is not None else None
             lit = traffic.pull_bytes_literal(c, r.level) if c is not None and r.kernel % 11 == 7 else None
-            lv.append([r.kernel, r.n_frontier, b, lit])
+            lv.append([r.kernel, r.n_frontier, b, lit, r.launch, r.flags])
         calls.append({"tag": tag, "source": int(source), "levels": lv})
         return nrows
 

@@ -146,7 +146,10 @@ typedef struct {
                            workgroup's start to its last one's end, both
                            launches of a two-launch push_edge level; see
                            time_levels), or -1 when not timed */
-  int32_t reserved;
+  int32_t launch;       /* index (from 0, per source) of the level-kernel launch that
+                           completed this level (a push_edge level on more than 512
+                           entries takes two launches; a single-workgroup launch
+                           runs several levels; some launches complete none) */
 } gsw_level_trace;
 
 enum { GSW_POLICY_TREE = 0, GSW_POLICY_FIXED = 1, GSW_POLICY_SCHEDULE = 2 };

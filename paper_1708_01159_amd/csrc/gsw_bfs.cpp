@@ -282,7 +282,7 @@ void trace_row(gsw_level_trace* t, int32_t src_idx, int64_t d, const Record& r, 
   t->n_next = r.next;
   t->e_frontier = r.ef;
   t->ms = timed ? (float)((double)r.ticks * tick_ms) : -1.0f;
-  t->reserved = 0;
+  t->launch = (int32_t)r.launch;
 }
 
 int32_t launch_size(int next_kernel, int64_t nn, int64_t nf, int64_t nf_prev, int64_t disc, int64_t d, int64_t n,
@@ -346,7 +346,9 @@ gsw_status run_levels(gsw_graph* g, const Policy& pol, const BfsPolicy& dp, int3
   // A single-workgroup launch may hand its first level back untouched (too
   // many arcs for one workgroup); the launch queued after one is therefore
   // always a full-grid one, which runs whatever level it finds.
-  bool solo = b.solo && solo_eligible(k0, 1, 1, 1, g->n, b.deg_max);
+  // level 0 (the source alone) goes to one workgroup whenever the policy
+  // pushes: its arcs are checked there, and a hub source is handed back
+  bool solo = b.solo && k0 >= 0 && kernel_base(k0) <= GSW_K_PUSH_EDGE;
   bool last_solo = false;
   int want = solo ? kSoloAhead : kAhead + level_launches(k0, 1) - 1;
   const int32_t cap = o->max_workgroups > 0 && o->max_workgroups < b.grid_max ? o->max_workgroups : b.grid_max;

@@ -1173,6 +1173,112 @@ __device__ __forceinline__ u64 readlane64(u64 x, int i) {
 }
 
 
+// The chunk's k-th unvisited vertex (k in compacted order) and its word and
+// bit within the chunk.
+struct PullV {
+  int32_t v;
+  int kw, bit;
+  bool mine;
+};
+
+__device__ __forceinline__ PullV pull_vertex(int k, int total, int64_t w0, const u64 (&todo)[kPullChunk],
+                                             const int (&first)[kPullChunk]) {
+  PullV p;
+  p.mine = k < total;
+  int kw = 0;
+#pragma unroll
+  for (int i = 1; i < kPullChunk; ++i) kw += k >= first[i] ? 1 : 0;
+  u64 t = 0ull;
+  int f0 = 0;
+#pragma unroll
+  for (int i = 0; i < kPullChunk; ++i)
+    if (i == kw) {
+      t = todo[i];
+      f0 = first[i];
+    }
+  p.kw = kw;
+  p.bit = p.mine ? nth_set_bit(t, k - f0) : 0;
+  p.v = (int32_t)((w0 + kw) * 64 + p.bit);
+  return p;
+}
+
+// First in-neighbour of p.v among its head arcs that is in the frontier
+// (-1: none); *more: the row goes on past them.
+__device__ __forceinline__ int32_t pull_head_hit(const Args& a, const PullV& p, const int4 (&h)[kHeadArcs / 4],
+                                                 bool* more) {
+  int32_t hu[kHeadArcs];
+#pragma unroll
+  for (int r = 0; r < kHeadArcs / 4; ++r) {
+    hu[4 * r] = h[r].x;
+    hu[4 * r + 1] = h[r].y;
+    hu[4 * r + 2] = h[r].z;
+    hu[4 * r + 3] = h[r].w;
+  }
+  u64 hw[kHeadArcs];
+#pragma unroll
+  for (int q = 0; q < kHeadArcs; ++q) hw[q] = hu[q] >= 0 ? a.fr[hu[q] >> 6] : 0ull;
+  int32_t par = -1;
+#pragma unroll
+  for (int q = kHeadArcs - 1; q >= 0; --q)
+    if (hu[q] >= 0 && ((hw[q] >> (hu[q] & 63)) & 1ull)) par = hu[q];
+  *more = p.mine && hu[kHeadArcs - 1] >= 0;
+  return par;
+}
+
+// The rest of an unresolved row [beg, end) past its head arcs: the next
+// kPullEager arcs with independent loads, then, for rows longer still, the
+// whole wavefront 64 arcs at a time.  Every lane calls it (uniform control
+// flow); returns the lane's parent.
+__device__ __forceinline__ int32_t pull_row_rest(const Args& a, bool mine, int32_t par, int64_t beg, int64_t end) {
+  const int lane = lane_id();
+  constexpr int kProbed = kHeadArcs + kPullEager;
+  if (mine && par < 0 && end - beg > kHeadArcs) {
+    int32_t u[kPullEager];
+    u64 fw[kPullEager];
+#pragma unroll
+    for (int q = 0; q < kPullEager; ++q) u[q] = beg + kHeadArcs + q < end ? a.rcols[beg + kHeadArcs + q] : -1;
+#pragma unroll
+    for (int q = 0; q < kPullEager; ++q) fw[q] = u[q] >= 0 ? a.fr[u[q] >> 6] : 0ull;
+#pragma unroll
+    for (int q = kPullEager - 1; q >= 0; --q)
+      if (u[q] >= 0 && ((fw[q] >> (u[q] & 63)) & 1ull)) par = u[q];
+  }
+  u64 rest = __ballot(mine && par < 0 && end - beg > kProbed);
+  while (rest != 0ull) {
+    const int owner = __ffsll((long long)rest) - 1;
+    rest &= rest - 1ull;
+    const int64_t lo = __shfl(beg, owner) + kProbed;
+    const int64_t hi = __shfl(end, owner);
+    int32_t hit = -1;
+    for (int64_t cc = lo; cc < hi; cc += 64) {
+      const int64_t e = cc + lane;
+      int32_t x = -1;
+      bool h = false;
+      if (e < hi) {
+        x = a.rcols[e];
+        h = (a.fr[x >> 6] >> (x & 63)) & 1ull;
+      }
+      const u64 hm = __ballot(h);
+      if (hm != 0ull) {
+        hit = __shfl(x, __ffsll((long long)hm) - 1);
+        break;
+      }
+    }
+    if (lane == owner) par = hit;
+  }
+  return par;
+}
+
+__device__ __forceinline__ void pull_settle(const Args& a, Stage& st, u64* found_w, const PullV& p, int32_t par) {
+  const bool found = p.mine && par >= 0;
+  if (found) {
+    a.level[p.v] = a.d + 1;
+    if (a.parent) a.parent[p.v] = par;
+    atomicOr(&found_w[p.kw], 1ull << p.bit);
+  }
+  stage_push(st, a, found, p.v);
+}
+
 __device__ __forceinline__ void body_pull(const Args& a, Stage& st, u64 (*s_found)[kPullChunk]) {
   const int lane = lane_id();
   u64* found_w = s_found[threadIdx.x >> 6];
@@ -1202,96 +1308,40 @@ __device__ __forceinline__ void body_pull(const Args& a, Stage& st, u64 (*s_foun
       todo[i] = ~readlane64(seen, i);
       first[i] = __builtin_amdgcn_readlane(inc, i) - __popcll(todo[i]);
     }
-    for (int r0 = 0; r0 < total; r0 += 64) {
-      const int k = r0 + lane;
-      const bool mine = k < total;
-      int kw = 0;
-#pragma unroll
-      for (int i = 1; i < kPullChunk; ++i) kw += k >= first[i] ? 1 : 0;
-      u64 t = 0ull;
-      int f0 = 0;
-#pragma unroll
-      for (int i = 0; i < kPullChunk; ++i)
-        if (i == kw) {
-          t = todo[i];
-          f0 = first[i];
-        }
-      const int bit = mine ? nth_set_bit(t, k - f0) : 0;
-      const int32_t v = (int32_t)((w0 + kw) * 64 + bit);
-      // the row's first kHeadArcs arcs from the dense copy; the row's bounds
-      // only when it may go on past them and they found nothing
-      int64_t beg = 0, end = 0;
-      int4 h[kHeadArcs / 4];
-#pragma unroll
-      for (int r = 0; r < kHeadArcs / 4; ++r) h[r] = make_int4(-1, -1, -1, -1);
-      if (mine) {
-#pragma unroll
-        for (int r = 0; r < kHeadArcs / 4; ++r)
-          h[r] = reinterpret_cast<const int4*>(a.head)[(int64_t)v * (kHeadArcs / 4) + r];
-      }
-      int32_t hu[kHeadArcs];
+    // two of the chunk's unvisited vertices per lane and step (compacted
+    // positions r0 + lane and r0 + 64 + lane): their head records and
+    // frontier-word probes are in flight together
+    for (int r0 = 0; r0 < total; r0 += 128) {
+      const PullV A = pull_vertex(r0 + lane, total, w0, todo, first);
+      const PullV B = pull_vertex(r0 + 64 + lane, total, w0, todo, first);
+      int4 hA[kHeadArcs / 4], hB[kHeadArcs / 4];
 #pragma unroll
       for (int r = 0; r < kHeadArcs / 4; ++r) {
-        hu[4 * r] = h[r].x;
-        hu[4 * r + 1] = h[r].y;
-        hu[4 * r + 2] = h[r].z;
-        hu[4 * r + 3] = h[r].w;
+        hA[r] = make_int4(-1, -1, -1, -1);
+        hB[r] = hA[r];
       }
-      u64 hw[kHeadArcs];
 #pragma unroll
-      for (int q = 0; q < kHeadArcs; ++q) hw[q] = hu[q] >= 0 ? a.fr[hu[q] >> 6] : 0ull;
-      int32_t par = -1;
-#pragma unroll
-      for (int q = kHeadArcs - 1; q >= 0; --q)
-        if (hu[q] >= 0 && ((hw[q] >> (hu[q] & 63)) & 1ull)) par = hu[q];
-      // unresolved longer rows: the next kPullEager arcs with independent loads
-      constexpr int kProbed = kHeadArcs + kPullEager;
-      if (mine && par < 0 && hu[kHeadArcs - 1] >= 0) {
-        beg = a.roffs[v];
-        end = a.roffs[v + 1];
+      for (int r = 0; r < kHeadArcs / 4; ++r) {
+        if (A.mine) hA[r] = reinterpret_cast<const int4*>(a.head)[(int64_t)A.v * (kHeadArcs / 4) + r];
+        if (B.mine) hB[r] = reinterpret_cast<const int4*>(a.head)[(int64_t)B.v * (kHeadArcs / 4) + r];
       }
-      if (mine && par < 0 && end - beg > kHeadArcs) {
-        int32_t u[kPullEager];
-        u64 fw[kPullEager];
-#pragma unroll
-        for (int q = 0; q < kPullEager; ++q)
-          u[q] = beg + kHeadArcs + q < end ? a.rcols[beg + kHeadArcs + q] : -1;
-#pragma unroll
-        for (int q = 0; q < kPullEager; ++q) fw[q] = u[q] >= 0 ? a.fr[u[q] >> 6] : 0ull;
-#pragma unroll
-        for (int q = kPullEager - 1; q >= 0; --q)
-          if (u[q] >= 0 && ((fw[q] >> (u[q] & 63)) & 1ull)) par = u[q];
+      bool moreA = false, moreB = false;
+      int32_t parA = pull_head_hit(a, A, hA, &moreA);
+      int32_t parB = pull_head_hit(a, B, hB, &moreB);
+      // the row's bounds only when it may go on past the head and that found nothing
+      int64_t begA = 0, endA = 0, begB = 0, endB = 0;
+      if (moreA && parA < 0) {
+        begA = a.roffs[A.v];
+        endA = a.roffs[A.v + 1];
       }
-      u64 rest = __ballot(mine && par < 0 && end - beg > kProbed);
-      while (rest != 0ull) {
-        const int owner = __ffsll((long long)rest) - 1;
-        rest &= rest - 1ull;
-        const int64_t lo = __shfl(beg, owner) + kProbed;
-        const int64_t hi = __shfl(end, owner);
-        int32_t hit = -1;
-        for (int64_t cc = lo; cc < hi; cc += 64) {
-          const int64_t e = cc + lane;
-          int32_t x = -1;
-          bool h = false;
-          if (e < hi) {
-            x = a.rcols[e];
-            h = (a.fr[x >> 6] >> (x & 63)) & 1ull;
-          }
-          const u64 hm = __ballot(h);
-          if (hm != 0ull) {
-            hit = __shfl(x, __ffsll((long long)hm) - 1);
-            break;
-          }
-        }
-        if (lane == owner) par = hit;
+      if (moreB && parB < 0) {
+        begB = a.roffs[B.v];
+        endB = a.roffs[B.v + 1];
       }
-      const bool found = par >= 0;
-      if (found) {
-        a.level[v] = a.d + 1;
-        if (a.parent) a.parent[v] = par;
-        atomicOr(&found_w[kw], 1ull << bit);
-      }
-      stage_push(st, a, found, v);
+      parA = pull_row_rest(a, A.mine, parA, begA, endA);
+      parB = pull_row_rest(a, B.mine, parB, begB, endB);
+      pull_settle(a, st, found_w, A, parA);
+      pull_settle(a, st, found_w, B, parB);
     }
     // the LDS words are this wave's alone and its LDS operations complete in
     // order; the barrier only keeps the compiler from moving the reads up

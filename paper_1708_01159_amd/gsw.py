@@ -71,7 +71,7 @@ class LevelTrace(ctypes.Structure):
                 ("kernel", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("n_frontier", ctypes.c_int64), ("discovered", ctypes.c_int64),
                 ("n_next", ctypes.c_int64), ("e_frontier", ctypes.c_int64),
-                ("ms", ctypes.c_float), ("reserved", ctypes.c_int32)]
+                ("ms", ctypes.c_float), ("launch", ctypes.c_int32)]
 
 
 class BfsOpts(ctypes.Structure):
@@ -384,6 +384,7 @@ class TraceRow:
     n_next: int
     ms: float
     e_frontier: int = -1
+    launch: int = -1
 
     @property
     def kernel_name(self):
@@ -392,7 +393,7 @@ class TraceRow:
 
 def _row(t):
     return TraceRow(t.source_idx, t.level, t.kernel, t.flags, t.n_frontier, t.discovered, t.n_next, t.ms,
-                    t.e_frontier)
+                    t.e_frontier, t.launch)
 
 
 def _opts(policy, kernel, schedule, tree, time_levels, canonical_parents, device_ptrs, stream):

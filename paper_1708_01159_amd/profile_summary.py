@@ -1,14 +1,14 @@
 """Per-variant summary of a rocprofv3-profiled benchmark run (no GPU needed).
 
-Every expansion variant runs inside one kernel, k_level_auto, so the
-profiler's per-kernel rows cannot tell them apart.  The benchmark's
-``--dispatch-log`` records, for every BFS call, each level's kernel id,
-frontier size and algorithmic bytes (both byte models).  Each call starts
-with one k_init dispatch; each level then takes one k_level_auto launch (two
-for push_edge on more than 512 entries); the call's remaining launches find
-the search ended.  Aligning the dispatches in start order with that log
-labels every level-kernel dispatch with the variant it ran, for the kernel
-trace and for the FETCH_SIZE / WRITE_SIZE counter runs alike.
+Every expansion variant runs inside one kernel, k_level_auto (or, for runs
+of small levels, k_level_solo), so the profiler's per-kernel rows cannot
+tell them apart.  The benchmark's ``--dispatch-log`` records, for every BFS
+call, each level's kernel id, frontier size, algorithmic bytes (both byte
+models), trace flags and the index of the launch that completed it.  Each
+call starts with one k_init dispatch followed by its level-kernel launches
+in order, so the launch index labels every level-kernel dispatch with the
+variant it ran, for the kernel trace and for the FETCH_SIZE / WRITE_SIZE
+counter runs alike.
 
 The summary gives, for the dominant variant, the mean algorithmic bytes and
 the mean rocprofv3 duration over the same set of dispatches (every call of
@@ -29,8 +29,8 @@ import numpy as np
 EDGE_FUSE = 512  # the library's one-launch limit for push_edge frontiers
 N_BASE = 11
 PUSH_EDGE = 6
-PROFILE_CMD = ("python3 -u bench.py --steps 2 --warmup 1 --no-compare --copy-calib --cpu-budget 1 "
-               "--dispatch-log {d}/dispatch_log.json")
+PROFILE_CMD = ("python3 -u bench.py --steps 2 --warmup 1 --no-compare --no-batched --no-sweep --no-serving "
+               "--copy-calib --cpu-budget 1 --dispatch-log {d}/dispatch_log.json")
 HBM_PEAK_GBS = 8000.0
 
 
@@ -44,25 +44,48 @@ def _short(name):
     return name.split("(")[0][:48]
 
 
+SOLO_FLAG = 4  # trace flag of a level run by a single-workgroup launch
+LEVEL_KERNELS = ("k_level_auto", "k_level_solo")
+
+
 def _align(dispatches, calls, names):
-    """Label each dispatch (in start order) with (variant, bytes, literal bytes)."""
+    """Label each dispatch (in start order) with (variant, bytes, literal bytes).
+
+    Each call starts with one k_init dispatch, followed by its level-kernel
+    dispatches (k_level_auto, k_level_solo) in launch order; every level's
+    trace row names the launch that completed it.  A launch that completed
+    one full-grid level is labelled with that level's kernel (a push_edge
+    level on more than 512 entries also took the launch before it, its
+    prefix sum); a single-workgroup launch with the levels it ran; a launch
+    that completed none (the search had ended, or a single-workgroup launch
+    handed its level on) as such."""
     labels = [None for _ in dispatches]
     starts = [i for i, d in enumerate(dispatches) if _short(d[0]) == "k_init"]
     if len(starts) != len(calls):
         raise SystemExit("profile has %d k_init dispatches, the dispatch log %d calls" % (len(starts), len(calls)))
     for c, (i0, call) in enumerate(zip(starts, calls)):
         i1 = starts[c + 1] if c + 1 < len(starts) else len(dispatches)
-        mine = [i for i in range(i0 + 1, i1) if _short(dispatches[i][0]) == "k_level_auto"]
-        want = []
-        for k, nf, b, lit in call["levels"]:
-            if k % N_BASE == PUSH_EDGE and nf > EDGE_FUSE:
-                want += [(names[k] + " (prefix)", None, None), (names[k] + " (expand)", b, None)]
-            else:
-                want.append((names[k], b, lit))
-        if len(want) > len(mine):
-            raise SystemExit("call %d: %d level launches logged, %d dispatched" % (c, len(want), len(mine)))
+        mine = [i for i in range(i0 + 1, i1) if _short(dispatches[i][0]) in LEVEL_KERNELS]
+        by_launch = {}
+        for k, nf, b, lit, launch, flags in call["levels"]:
+            by_launch.setdefault(launch, []).append((k, nf, b, lit, flags))
+        if by_launch and max(by_launch) >= len(mine):
+            raise SystemExit("call %d: launch %d logged, %d dispatched" % (c, max(by_launch), len(mine)))
         for j, i in enumerate(mine):
-            labels[i] = want[j] if j < len(want) else ("(search ended)", None, None)
+            lv = by_launch.get(j)
+            if not lv:
+                if labels[i] is None:
+                    labels[i] = ("(no level completed)", None, None)
+            elif any(f & SOLO_FLAG for *_, f in lv):
+                labels[i] = ("single-workgroup launch", None, None)
+            else:
+                k, nf, b, lit, _ = lv[0]
+                if k % N_BASE == PUSH_EDGE and nf > EDGE_FUSE:
+                    labels[i] = (names[k] + " (expand)", b, None)
+                    if j > 0:
+                        labels[mine[j - 1]] = (names[k] + " (prefix)", None, None)
+                else:
+                    labels[i] = (names[k], b, lit)
     return labels
 
 

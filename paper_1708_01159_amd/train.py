@@ -292,12 +292,18 @@ def fit(rows, valid, seed=0, log=print, grid=GRID):
     tr, te = perm[:cut], perm[cut:]
     c1 = make(depth, leaf).fit(X[tr], y[tr], sample_weight=None if w is None else w[tr])
     report["row_split"] = _named(evaluate(c1, X[te], T[te]))
-    # held-out training graphs
+    # held-out training graphs: every graph predicted by a tree fitted on the
+    # other folds (3 folds grouped by graph), and one 70/30 split by graph
+    cols = np.zeros(len(y), dtype=np.int64)
+    for f in folds:
+        c = make(depth, leaf).fit(X[~f], y[~f], sample_weight=None if w is None else w[~f])
+        cols[f] = tree_columns(c, X[f])
+    report["graph_split"] = dict(_named(scores(cols, T)), folds=[sorted(np.unique(graph[f]).tolist()) for f in folds])
     names = np.unique(graph)
     hold = rng.choice(names, size=max(1, len(names) * 3 // 10), replace=False)
     m = np.isin(graph, hold)
     c2 = make(depth, leaf).fit(X[~m], y[~m], sample_weight=None if w is None else w[~m])
-    report["graph_split"] = dict(_named(evaluate(c2, X[m], T[m])), held_out=sorted(hold.tolist()))
+    report["graph_split_one_30pct"] = dict(_named(evaluate(c2, X[m], T[m])), held_out=sorted(hold.tolist()))
     report["validation"] = dict(_named(evaluate(final, Xv, Tv)), graphs=sorted(np.unique(gv).tolist()))
     report["train_all"] = _named(evaluate(final, X, T))
     reg_cols, rf_cols = _model_variants(X, T, Xv, Tv, seed)

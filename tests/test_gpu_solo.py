@@ -98,8 +98,8 @@ def _run_both(name, **kw):
 @pytest.mark.parametrize("name", list(CASES))
 def test_solo_tree_policy(name):
     tr = _run_both(name, policy="tree", tree=trees.load_default())
-    if name in ("grid_ragged", "grid_full", "path3000"):  # the tree pushes on these
-        assert sum(1 for t in tr if t.flags & SOLO) > len(tr) // 2
+    if name in ("grid_ragged", "grid_full", "path3000"):  # the tree pushes on some of their small levels
+        assert any(t.flags & SOLO for t in tr)
 
 
 @pytest.mark.parametrize("name", list(CASES))

@@ -31,7 +31,9 @@ def _rows_key(rows):
 def _run_pair(g, srcs, **kw):
     import torch
 
-    G = gsw.Graph.from_csr(g.offs, g.cols)
+    # with the origin arrays built at creation both entry points may run the
+    # edge lists, so their per-level choices are the same
+    G = gsw.Graph.from_csr(g.offs, g.cols, flags=gsw.WITH_ORIGIN)
     try:
         dev0 = G.info()["dev_bytes"]
         S = len(srcs)
