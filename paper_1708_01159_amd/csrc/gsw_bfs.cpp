@@ -338,7 +338,7 @@ gsw_status run_levels(gsw_graph* g, const Policy& pol, const BfsPolicy& dp, int3
   BfsBase b = make_base(g, w, lv, pa, timed, o->count_arcs != 0);
   // single-workgroup multi-level launches: not with per-launch events (their
   // levels would share one launch's time), and with a tree its workgroup holds
-  b.solo = !o->no_solo && !events && (o->policy != GSW_POLICY_TREE || w.tree_nodes <= kSoloTree) ? 1 : 0;
+  b.solo = !o->no_solo && !events && (o->policy != GSW_POLICY_TREE || w.tree_nodes <= kSoloTree) ? kSoloMaxLevels : 0;
   GSW_TRY(launch_init(g, b, g->iso, src, k0, flags0, s));
   if (events) GSW_HIP(hipEventRecord(ev_after(-1), s));
   int64_t launched = 0;  // launches of the level kernels so far
@@ -346,9 +346,7 @@ gsw_status run_levels(gsw_graph* g, const Policy& pol, const BfsPolicy& dp, int3
   // A single-workgroup launch may hand its first level back untouched (too
   // many arcs for one workgroup); the launch queued after one is therefore
   // always a full-grid one, which runs whatever level it finds.
-  // level 0 (the source alone) goes to one workgroup whenever the policy
-  // pushes: its arcs are checked there, and a hub source is handed back
-  bool solo = b.solo && k0 >= 0 && kernel_base(k0) <= GSW_K_PUSH_EDGE;
+  bool solo = b.solo && solo_eligible(k0, 1, 1, 1, g->n, b.deg_max);
   bool last_solo = false;
   int want = solo ? kSoloAhead : kAhead + level_launches(k0, 1) - 1;
   const int32_t cap = o->max_workgroups > 0 && o->max_workgroups < b.grid_max ? o->max_workgroups : b.grid_max;
@@ -567,11 +565,14 @@ gsw_status gsw_bfs_profile(const gsw_graph* cg, int32_t source, const int32_t* k
   const bool has_rorigin = g->rorigin != nullptr || g->nnz == 0;
   const BfsPolicy dp = device_policy(g, w, &fo, has_origin, has_rorigin);
   const BfsBase b = make_base(g, w, lv, pa, false, false);
+  BfsBase b_solo = b;  // one level per single-workgroup launch
+  b_solo.solo = 1;
   std::memset(w.ring, 0, (size_t)kBfsRing * kBfsRec * sizeof(unsigned long long));
   w.ring_used = -1;  // every level reposts its record here: the next search clears the whole ring
   GSW_TRY(launch_init(g, b, g->iso, source, GSW_DEFAULT_KERNEL, 0, s));
   GSW_HIP(hipStreamSynchronize(s));
   int64_t nf = 1;
+  int64_t nf1 = 0, nf2 = 0, disc1 = 0;  // frontiers of the two levels before, discovered before this one
   uint32_t bins[kQueueBins] = {1};  // segment sizes of the current queue
   std::vector<float> samples((size_t)reps);
   BfsCtl saved_ctl;
@@ -619,12 +620,21 @@ gsw_status gsw_bfs_profile(const gsw_graph* cg, int32_t source, const int32_t* k
       GSW_HIP(hipStreamSynchronize(s));  // the staging copy is reused by the next restore
       return GSW_OK;
     };
-    // one level with kernel k as the level loop runs it: one launch of the
-    // level kernel, two for push_edge on more than kEdgeFuse entries
+    // one level with kernel k as the level loop runs it: a single-workgroup
+    // launch when the level qualifies for one by the graph's degree bound
+    // (never handed back), else the level kernel with the loop's launch size,
+    // twice for push_edge on more than kEdgeFuse entries
     auto run = [&](int k, bool timed_bracket) -> gsw_status {
+      const bool solo = kernel_base(k) <= GSW_K_PUSH_EDGE && nf <= kSoloMax &&
+                        (long long)b.deg_max * nf <= kSoloMaxArcs;
+      const int32_t size = launch_size(k, nf, nf1, nf2, disc1, d - 1, n, b.grid_max);
       if (timed_bracket) GSW_HIP(hipEventRecord(w.ev[0], s));
-      GSW_TRY(launch_level_auto(g, b, dp, 0, b.grid_max, s));
-      if (level_launches(k, nf) == 2) GSW_TRY(launch_level_auto(g, b, dp, 1, b.grid_max, s));
+      if (solo) {
+        GSW_TRY(launch_level_solo(g, b_solo, dp, 0, s));
+      } else {
+        GSW_TRY(launch_level_auto(g, b, dp, 0, size, s));
+        if (level_launches(k, nf) == 2) GSW_TRY(launch_level_auto(g, b, dp, 1, size, s));
+      }
       if (timed_bracket) GSW_HIP(hipEventRecord(w.ev[1], s));
       return GSW_OK;
     };
@@ -653,8 +663,10 @@ gsw_status gsw_bfs_profile(const gsw_graph* cg, int32_t source, const int32_t* k
       }
     }
     GSW_TRY(restore(adv));
+    const bool adv_solo = kernel_base(adv) <= GSW_K_PUSH_EDGE && nf <= kSoloMax &&
+                          (long long)b.deg_max * nf <= kSoloMaxArcs;
     GSW_TRY(run(adv, false));
-    cur = level_launches(adv, nf) & 1;  // slot written by the last launch
+    cur = adv_solo ? 1 : level_launches(adv, nf) & 1;  // slot written by the last launch
     GSW_HIP(hipStreamSynchronize(s));
     Record r;
     GSW_TRY(wait_record(g, d, s, &r));
@@ -665,6 +677,9 @@ gsw_status gsw_bfs_profile(const gsw_graph* cg, int32_t source, const int32_t* k
     if (frontier) frontier[d] = nf;
     if (n_levels) *n_levels = d + 1;
     if (nn == 0) break;
+    nf2 = nf1;
+    nf1 = nf;
+    disc1 += nf;
     nf = nn;
   }
   GSW_HIP(hipStreamSynchronize(s));

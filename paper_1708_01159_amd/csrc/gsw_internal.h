@@ -214,7 +214,7 @@ struct BfsBase {
   int32_t timed;                   // record each level's duration
   int32_t grid_max;                // workgroups of a level-kernel launch
   int32_t count_arcs;              // accumulate the next frontier's out-degrees
-  int32_t solo;                    // small-frontier levels may run in single-workgroup launches
+  int32_t solo;                    // levels one single-workgroup launch may run (0: such launches off)
   int32_t deg_max;                 // largest out-degree (clamped to 2^31 - 1)
   int32_t pad;
 };

@@ -1225,24 +1225,31 @@ __device__ __forceinline__ int32_t pull_head_hit(const Args& a, const PullV& p, 
   return par;
 }
 
-// The rest of an unresolved row [beg, end) past its head arcs: the next
-// kPullEager arcs with independent loads, then, for rows longer still, the
-// whole wavefront 64 arcs at a time.  Every lane calls it (uniform control
-// flow); returns the lane's parent.
+// The rest of an unresolved row [beg, end) past its head arcs: its own lane
+// goes on kPullEager arcs at a time with independent loads up to kPullLane
+// arcs into the row (the lanes of a wavefront in step, each on its own
+// row), then rows longer still are scanned by the whole wavefront 64 arcs
+// at a time, one row after another.  Every lane calls it (uniform control
+// flow); returns the lane's parent, the first in-neighbour in row order in
+// the frontier.
+constexpr int64_t kPullLane = 64;
 __device__ __forceinline__ int32_t pull_row_rest(const Args& a, bool mine, int32_t par, int64_t beg, int64_t end) {
   const int lane = lane_id();
-  constexpr int kProbed = kHeadArcs + kPullEager;
-  if (mine && par < 0 && end - beg > kHeadArcs) {
-    int32_t u[kPullEager];
-    u64 fw[kPullEager];
+  const int64_t lim = end - beg < kPullLane ? end - beg : kPullLane;
+  for (int64_t off = kHeadArcs; __any(mine && par < 0 && off < lim); off += kPullEager) {
+    if (mine && par < 0 && off < lim) {
+      int32_t u[kPullEager];
+      u64 fw[kPullEager];
 #pragma unroll
-    for (int q = 0; q < kPullEager; ++q) u[q] = beg + kHeadArcs + q < end ? a.rcols[beg + kHeadArcs + q] : -1;
+      for (int q = 0; q < kPullEager; ++q) u[q] = off + q < lim ? a.rcols[beg + off + q] : -1;
 #pragma unroll
-    for (int q = 0; q < kPullEager; ++q) fw[q] = u[q] >= 0 ? a.fr[u[q] >> 6] : 0ull;
+      for (int q = 0; q < kPullEager; ++q) fw[q] = u[q] >= 0 ? a.fr[u[q] >> 6] : 0ull;
 #pragma unroll
-    for (int q = kPullEager - 1; q >= 0; --q)
-      if (u[q] >= 0 && ((fw[q] >> (u[q] & 63)) & 1ull)) par = u[q];
+      for (int q = kPullEager - 1; q >= 0; --q)
+        if (u[q] >= 0 && ((fw[q] >> (u[q] & 63)) & 1ull)) par = u[q];
+    }
   }
+  constexpr int64_t kProbed = kPullLane;
   u64 rest = __ballot(mine && par < 0 && end - beg > kProbed);
   while (rest != 0ull) {
     const int owner = __ffsll((long long)rest) - 1;
@@ -1633,7 +1640,7 @@ __global__ void __launch_bounds__(kSoloBlock) k_level_solo(BfsBase b, BfsPolicy 
   long long nf = c->nf, disc = c->disc;
   int32_t prev = c->prev, flags = c->flags;
   const bool tree = p.policy == GSW_POLICY_TREE;
-  const bool ok = b.solo && k_id >= 0 && k_id < GSW_N_KERNELS && kernel_base(k_id) <= GSW_K_PUSH_EDGE &&
+  const bool ok = b.solo > 0 && k_id >= 0 && k_id < GSW_N_KERNELS && kernel_base(k_id) <= GSW_K_PUSH_EDGE &&
                   nf >= 1 && nf <= kSoloMax && (!tree || p.t_nodes <= kSoloTree);
   if (!ok) {  // not a level for this launch: the slot passes on unchanged
     if (tid == 0) *cn = *c;
@@ -1806,7 +1813,7 @@ __global__ void __launch_bounds__(kSoloBlock) k_level_solo(BfsBase b, BfsPolicy 
 #pragma unroll
       for (int i = 0; i < kBfsRecWords; ++i)
         __hip_atomic_store(r + i, tag | rec[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      L.go = lv + 1 < kSoloMaxLevels && solo_eligible(next, (long long)nn, nf, ndisc, b.n, b.deg_max) ? 1 : 0;
+      L.go = lv + 1 < b.solo && solo_eligible(next, (long long)nn, nf, ndisc, b.n, b.deg_max) ? 1 : 0;
       L.next = next;
       L.nflags = nflags;
       L.nn = nn;

@@ -11,6 +11,10 @@ from paper_1708_01159_amd import gsw, train
 def test_labels_take_the_fastest_lowest_on_ties_and_skip_unmeasured():
     T = np.array([[3.0, 1.0, 2.0], [1.0, 1.0, 5.0], [-1.0, 4.0, 4.0], [2.0, -1.0, 1.5]])
     assert train.labels(T).tolist() == [1, 0, 1, 2]
+    # within the tolerance of the fastest is a tie, beyond it is not
+    T = np.array([[1.015, 1.0, 3.0], [1.03, 1.0, 3.0], [5.0, 2.0, 2.03]])
+    assert train.labels(T).tolist() == [0, 1, 1]
+    assert train.labels(T, tol=0.0).tolist() == [1, 1, 1]
 
 
 def test_weights():
