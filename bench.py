@@ -25,7 +25,9 @@ Prints ONE JSON line.  Besides the contract fields:
                    model and the scope table's literal pull formula);
                    traffic = HBM bytes per launch from the committed
                    rocprofv3 counter summary while the kernel source it was
-                   taken on is unchanged
+                   taken on is unchanged, with that summary's mean kernel
+                   duration and the fraction it gives (the event brackets
+                   also hold the gap before each launch starts)
   cpu_baseline     the CPU oracle on a bounded sample of the same sources
   batched          R-MAT scale 20, B = 64/256/1024 vs the same sources one at a
                    time; thresholds and block size tuned on a disjoint sample
@@ -110,10 +112,11 @@ def cpu_baseline(g, srcs, m_c, budget_s):
             "cpu": cpu_model(), "host_nproc": os.cpu_count(), "host_cpus_available": affinity}
 
 
-def counter_traffic(kernel_name):
-    """HBM bytes per launch of ``kernel_name`` from the committed rocprofv3
-    counter summary, or None when that summary is missing, is for another
-    kernel, or was taken on a different kernel source."""
+def committed_profile(kernel_name):
+    """Fields of the committed rocprofv3 summary of ``kernel_name`` (HBM
+    traffic per launch, mean duration, dispatches), or None when that summary
+    is missing, is for another kernel, or was taken on a different kernel
+    source."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "%s_rmat22.md" % kernel_name)
@@ -123,11 +126,32 @@ def counter_traffic(kernel_name):
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except OSError:
         return None
-    fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and
-                  line.split(": ", 1)[0] in ("traffic_bytes_per_launch", "kernel", "kernel_source_sha256"))
+    keys = ("traffic_bytes_per_launch", "kernel", "kernel_source_sha256", "mean_duration_us", "dispatches",
+            "algorithmic_bytes_per_launch")
+    fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and line.split(": ", 1)[0] in keys)
     if fields.get("kernel") != kernel_name or fields.get("kernel_source_sha256") != sha:
         return None
-    return int(fields["traffic_bytes_per_launch"])
+    return fields
+
+
+def copy_calibration():
+    """A plain 1 GiB device copy (torch), twice: the profiler's counters for
+    it scale the counter runs of the same command."""
+    import torch
+
+    a = torch.empty(1 << 28, dtype=torch.int32, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b.copy_(a)
+    ev0.record()
+    b.copy_(a)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    out = {"bytes_read": a.numel() * 4, "bytes_written": a.numel() * 4, "ms": round(ms, 4),
+           "gbs": round(2 * a.numel() * 4 / ms / 1e6, 1)}
+    del a, b
+    return out
 
 
 def timed(runner, src, sync):
@@ -228,12 +252,21 @@ def run_headline(args, g, G, tree, srcs, calls):
     achieved = mean_b / mean_t / 1e9 if mean_t > 0 else 0.0
     roofline = {"bound": "hbm", "kernel": gsw.KERNEL_NAMES[dom], "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": counter_traffic(gsw.KERNEL_NAMES[dom]),
+                "traffic": None,
                 "bytes_per_launch": int(round(mean_b)),
                 "mean_launch_ms": round(mean_t * 1e3, 5),
                 "launches": launches, "sources": len(srcs),
                 "timing": "HIP events recorded on the search's stream after every launch",
                 "share_of_kernel_time": round(float(ktime[dom] / ktime.sum()), 3)}
+    prof = committed_profile(gsw.KERNEL_NAMES[dom])
+    if prof:
+        # the rocprofv3 kernel trace of the profiling command: its mean
+        # duration excludes the dispatch gap that the event brackets include
+        roofline["traffic"] = int(prof["traffic_bytes_per_launch"])
+        d_us = float(prof["mean_duration_us"])
+        roofline["rocprof_mean_launch_us"] = d_us
+        roofline["rocprof_dispatches"] = int(prof["dispatches"])
+        roofline["frac_rocprof_duration"] = round(mean_b / (d_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
     if b_lit:
         lit = b_lit / launches
         roofline["bytes_per_launch_literal"] = int(round(lit))
@@ -477,6 +510,8 @@ def main():
                     help="write every BFS call's (kernel, frontier, bytes) per level to this JSON file")
     ap.add_argument("--batched-only", default=None, metavar="B[,B...]",
                     help="only the batched section at these batch sizes (one JSON line; for profiling)")
+    ap.add_argument("--summarize-batched", default=None, metavar="DIR",
+                    help="print the batched-path rocprofv3 summary of DIR (no GPU)")
     ap.add_argument("--summarize-profile", default=None, metavar="DIR",
                     help="no GPU: per-variant summary of the rocprofv3 runs in DIR, then exit")
     args = ap.parse_args()
@@ -485,6 +520,11 @@ def main():
         from paper_1708_01159_amd import profile_summary
 
         print(profile_summary.summarize(args.summarize_profile, ROOT))
+        return
+    if args.summarize_batched:
+        from paper_1708_01159_amd import profile_summary
+
+        print(profile_summary.summarize_batched(args.summarize_batched))
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -507,7 +547,10 @@ def main():
 
     if args.batched_only:
         sizes = tuple(int(x) for x in args.batched_only.split(","))
-        print(json.dumps({"batched": bench_batched(sizes)}), flush=True)
+        line = {"batched": bench_batched(sizes)}
+        if args.copy_calib:
+            line["copy_calibration"] = copy_calibration()
+        print(json.dumps(line), flush=True)
         return
 
     late = lambda: time.perf_counter() - T0 > args.budget
@@ -545,18 +588,7 @@ def main():
         }
 
     if args.copy_calib:
-        a = torch.empty(1 << 28, dtype=torch.int32, device="cuda").fill_(1)
-        b = torch.empty_like(a)
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        b.copy_(a)
-        ev0.record()
-        b.copy_(a)
-        ev1.record()
-        torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1)
-        extra["copy_calibration"] = {"bytes_read": a.numel() * 4, "bytes_written": a.numel() * 4,
-                                     "ms": round(ms, 4), "gbs": round(2 * a.numel() * 4 / ms / 1e6, 1)}
-        del a, b
+        extra["copy_calibration"] = copy_calibration()
 
     sweep_graphs = {}
     if not args.no_compare:

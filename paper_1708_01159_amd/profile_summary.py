@@ -177,3 +177,80 @@ def summarize(d, root):
           "frac_of_8tbs: %.4f" % (achieved / HBM_PEAK_GBS),
           "traffic_bytes_per_launch: %d" % traffic, "kernel_source_sha256: %s" % sha, "```"]
     return "\n".join(L)
+
+
+BATCHED_CMD = "python3 -u bench.py --batched-only 1024 --copy-calib"
+MS_KERNELS = ("k_ms_init", "k_ms_sources", "k_ms_push", "k_ms_level", "k_ms_finalize", "k_ms_transpose")
+
+
+def summarize_batched(d, tuned_batches: int = 6):
+    """Per-kernel summary of the batched path (R-MAT scale 20, 1024 sources)
+    over the last ``tuned_batches`` batches of the profiled command (the
+    tuned batch, run once untimed and five times timed; the autotuning
+    batches before them are left out): rocprofv3 durations, FETCH_SIZE and
+    WRITE_SIZE scaled by the 1 GiB copy of the same run, the traffic rate
+    against 8 TB/s, and for the transpose -- a pure stream of B*n bytes in
+    and B*n bytes out -- its algorithmic bytes and roofline fraction.  The
+    level kernels' algorithmic bytes depend on each source's direction and
+    on early exits that only the device sees, so their line gives the
+    measured traffic."""
+    line = json.loads(open(os.path.join(d, "trace_bench.json")).read().strip().splitlines()[-1])
+    tr = sorted(_csv_rows(os.path.join(d, "trace", "run_kernel_trace.csv")), key=lambda r: int(r["Start_Timestamp"]))
+    disp = [(_short(r["Kernel_Name"]), (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3) for r in tr]
+
+    def counters(sub, name):
+        rows = [r for r in _csv_rows(os.path.join(d, sub, "run_counter_collection.csv")) if r["Counter_Name"] == name]
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        return [(_short(r["Kernel_Name"]), float(r["Counter_Value"])) for r in rows]
+
+    fe, wr = counters("fetch", "FETCH_SIZE"), counters("write", "WRITE_SIZE")
+    GiB = 1 << 30
+    f_scale = GiB / (np.mean(sorted(v for n, v in fe if "copyBuffer" in n)[-2:]) * 1024)
+    w_scale = GiB / (np.mean(sorted(v for n, v in wr if "copyBuffer" in n)[-2:]) * 1024)
+
+    def last_batches(rows):
+        starts = [i for i, r in enumerate(rows) if r[0] == "k_ms_init"]
+        if len(starts) < tuned_batches:
+            raise SystemExit("profile has %d batches, fewer than %d" % (len(starts), tuned_batches))
+        i0 = starts[-tuned_batches]
+        return [r for r in rows[i0:] if r[0] in MS_KERNELS]
+
+    t_rows, f_rows, w_rows = last_batches(disp), last_batches(fe), last_batches(wr)
+    B, n = 1024, 1 << 20
+    info = line["batched"]["batches"][str(B)]
+    L = ["# Batched multi-source BFS on R-MAT scale 20, %d sources" % B, "",
+         "Commands (from the repository root, `TMPDIR=/tmp`; the trace run's stdout is `trace_bench.json`):", "",
+         "```",
+         "rocprofv3 --kernel-trace --stats --output-format csv -d {d}/trace -o run -- ".format(d=d) + BATCHED_CMD,
+         "rocprofv3 --pmc FETCH_SIZE --output-format csv -d {d}/fetch -o run -- ".format(d=d) + BATCHED_CMD,
+         "rocprofv3 --pmc WRITE_SIZE --output-format csv -d {d}/write -o run -- ".format(d=d) + BATCHED_CMD,
+         "python3 bench.py --summarize-batched " + d, "```", "",
+         "The tuned batch (thresholds %g / %g, block %d) runs once untimed and five times timed after the "
+         "autotuning batches; the table covers those last %d batches, per batch.  The bench line of the trace "
+         "run: %.3f ms per batch, %.1f GTEPS.  Counter scale from the plain 1 GiB device copy of the same run: "
+         "FETCH_SIZE x %.3f, WRITE_SIZE x %.3f." % (info["push_to_pull"], info["pull_to_push"], info["block_size"],
+                                                    tuned_batches, info["ms"], info["gteps"], f_scale, w_scale), "",
+         "| kernel | launches per batch | us per batch | fetched MB | written MB | traffic GB/s | of 8 TB/s |",
+         "|---|---:|---:|---:|---:|---:|---:|"]
+    per = {}
+    for k in MS_KERNELS:
+        t = [x for nm, x in t_rows if nm == k]
+        f = [x for nm, x in f_rows if nm == k]
+        w = [x for nm, x in w_rows if nm == k]
+        if not t:
+            continue
+        us = sum(t) / tuned_batches
+        fb = sum(f) * 1024 * f_scale / tuned_batches
+        wb = sum(w) * 1024 * w_scale / tuned_batches
+        rate = (fb + wb) / (us * 1e-6) / 1e9
+        per[k] = (us, fb, wb)
+        L.append("| %s | %.1f | %.1f | %.1f | %.1f | %.0f | %.3f |" % (
+            k, len(t) / tuned_batches, us, fb / 1e6, wb / 1e6, rate, rate / HBM_PEAK_GBS))
+    if "k_ms_transpose" in per:
+        us, fb, wb = per["k_ms_transpose"]
+        alg = 2.0 * B * n
+        L += ["", "k_ms_transpose: algorithmic bytes %.1f MB per batch (the int8 levels, %d x %d bytes, read "
+              "vertex-major and written source-major); %.1f us -> %.0f GB/s = **%.3f** of 8 TB/s; counter "
+              "traffic / algorithmic = %.2f." % (alg / 1e6, B, n, us, alg / (us * 1e-6) / 1e9,
+                                                 alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, (fb + wb) / alg)]
+    return "\n".join(L)

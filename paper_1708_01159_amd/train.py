@@ -177,6 +177,28 @@ def scores(chosen_col, T):
             float(chosen.sum() / best.sum()))
 
 
+def relabel_leaves(clf, X, T):
+    """Cost-sensitive leaves: each leaf of the fitted tree predicts the
+    kernel, among the tree's classes, with the least total measured time over
+    the training rows the leaf holds, instead of the most frequent label.
+    The splits stay the Gini tree's.  A frontier's size and the discovered
+    count cannot tell a hub from a leaf vertex, so rows that look alike can
+    have very different costs per kernel: the majority label (the kernel
+    that is a hair faster on most of them) may be very slow on the rest,
+    while the least total time weighs every row by what the choice costs."""
+    t = np.where(T < 0, np.inf, T)
+    leaf = clf.apply(X.astype(np.float32))
+    cls = clf.classes_.astype(np.int64)
+    v = clf.tree_.value
+    for nd in np.unique(leaf):
+        tot = t[leaf == nd][:, cls].sum(axis=0)
+        best = int(np.argmin(tot))
+        w = float(v[nd].sum())
+        v[nd] = 0.0
+        v[nd, 0, best] = w if w > 0 else 1.0
+    return clf
+
+
 def tree_columns(clf, X):
     """Column (kernel index into the rows' kernel list) the classifier picks.
     Features are compared in float32, as the library does."""
@@ -266,7 +288,8 @@ def _graph_folds(graph, k: int, seed: int):
     return [np.isin(graph, names[order[i::k]]) for i in range(k)]
 
 
-GRID = [(d, leaf, w) for d in (6, 8, 10, 12) for leaf in (1, 5, 20) for w in ("none", "regret", "graph")]
+GRID = [(d, leaf, w, lv) for d in (6, 8, 10, 12) for leaf in (1, 5, 20) for w in ("none", "regret")
+        for lv in ("majority", "time")]
 
 
 def fit(rows, valid, seed=0, log=print, grid=GRID):
@@ -281,53 +304,57 @@ def fit(rows, valid, seed=0, log=print, grid=GRID):
     def make(depth, leaf):
         return DecisionTreeClassifier(criterion="gini", max_depth=depth, min_samples_leaf=leaf, random_state=seed)
 
+    def fit_one(depth, leaf, leaves, Xf, yf, Tf, wf):
+        c = make(depth, leaf).fit(Xf, yf, sample_weight=wf)
+        return relabel_leaves(c, Xf, Tf) if leaves == "time" else c
+
     # hyper-parameters by the validation graphs' total-time ratio: the
     # smallest tree within SELECT_TOL of the best; the 3-fold cross-validation
     # over the training graphs grouped by graph (each fold's graphs predicted
     # by a tree fitted on the others) is reported beside it
     folds = _graph_folds(graph, 3, seed)
     sel = []
-    for depth, leaf, wscheme in grid:
+    for depth, leaf, wscheme, leaves in grid:
         w = _weights(T, graph, wscheme)
-        clf = make(depth, leaf).fit(X, y, sample_weight=w)
+        clf = fit_one(depth, leaf, leaves, X, y, T, w)
         acc, slow, ratio = evaluate(clf, Xv, Tv)
         cols = np.zeros(len(y), dtype=np.int64)
         for f in folds:
-            c = make(depth, leaf).fit(X[~f], y[~f], sample_weight=None if w is None else w[~f])
+            c = fit_one(depth, leaf, leaves, X[~f], y[~f], T[~f], None if w is None else w[~f])
             cols[f] = tree_columns(c, X[f])
         cv = scores(cols, T)[2]
-        sel.append(dict(max_depth=depth, min_samples_leaf=leaf, weights=wscheme, valid_time_ratio=round(ratio, 4),
-                        valid_accuracy=round(acc, 4), graph_cv_time_ratio=round(cv, 4),
-                        nodes=int(clf.tree_.node_count)))
-        log("depth %2d leaf %2d %-6s: validation time ratio %.4f, accuracy %.3f; grouped CV %.4f; %d nodes"
-            % (depth, leaf, wscheme, ratio, acc, cv, clf.tree_.node_count))
+        sel.append(dict(max_depth=depth, min_samples_leaf=leaf, weights=wscheme, leaves=leaves,
+                        valid_time_ratio=round(ratio, 4), valid_accuracy=round(acc, 4),
+                        graph_cv_time_ratio=round(cv, 4), nodes=int(clf.tree_.node_count)))
+        log("depth %2d leaf %2d %-6s %-8s: validation time ratio %.4f, accuracy %.3f; grouped CV %.4f; %d nodes"
+            % (depth, leaf, wscheme, leaves, ratio, acc, cv, clf.tree_.node_count))
     top = min(r["valid_time_ratio"] for r in sel)
     best = min((r for r in sel if r["valid_time_ratio"] <= top * (1.0 + SELECT_TOL)),
-               key=lambda r: (r["nodes"], r["valid_time_ratio"]))
-    depth, leaf, wscheme = best["max_depth"], best["min_samples_leaf"], best["weights"]
+               key=lambda r: (r["nodes"], r["graph_cv_time_ratio"], r["valid_time_ratio"]))
+    depth, leaf, wscheme, leaves = best["max_depth"], best["min_samples_leaf"], best["weights"], best["leaves"]
     w = _weights(T, graph, wscheme)
-    final = make(depth, leaf).fit(X, y, sample_weight=w)
+    final = fit_one(depth, leaf, leaves, X, y, T, w)
     report = {"selection": {"chosen": best, "grid": sel,
-                            "by": "validation graphs' total-time ratio: the smallest tree within %.1f%% of the best"
-                                  % (100 * SELECT_TOL)}}
+                            "by": "validation graphs' total-time ratio: the smallest tree within %.1f%% of the best "
+                                  "(equal sizes: the better graph-grouped cross-validation)" % (100 * SELECT_TOL)}}
     rng = np.random.default_rng(seed)
     # the paper's split: 70% of the training rows at random
     perm = rng.permutation(len(y))
     cut = int(0.7 * len(y))
     tr, te = perm[:cut], perm[cut:]
-    c1 = make(depth, leaf).fit(X[tr], y[tr], sample_weight=None if w is None else w[tr])
+    c1 = fit_one(depth, leaf, leaves, X[tr], y[tr], T[tr], None if w is None else w[tr])
     report["row_split"] = _named(evaluate(c1, X[te], T[te]))
     # held-out training graphs: every graph predicted by a tree fitted on the
     # other folds (3 folds grouped by graph), and one 70/30 split by graph
     cols = np.zeros(len(y), dtype=np.int64)
     for f in folds:
-        c = make(depth, leaf).fit(X[~f], y[~f], sample_weight=None if w is None else w[~f])
+        c = fit_one(depth, leaf, leaves, X[~f], y[~f], T[~f], None if w is None else w[~f])
         cols[f] = tree_columns(c, X[f])
     report["graph_split"] = dict(_named(scores(cols, T)), folds=[sorted(np.unique(graph[f]).tolist()) for f in folds])
     names = np.unique(graph)
     hold = rng.choice(names, size=max(1, len(names) * 3 // 10), replace=False)
     m = np.isin(graph, hold)
-    c2 = make(depth, leaf).fit(X[~m], y[~m], sample_weight=None if w is None else w[~m])
+    c2 = fit_one(depth, leaf, leaves, X[~m], y[~m], T[~m], None if w is None else w[~m])
     report["graph_split_one_30pct"] = dict(_named(evaluate(c2, X[m], T[m])), held_out=sorted(hold.tolist()))
     report["validation"] = dict(_named(evaluate(final, Xv, Tv)), graphs=sorted(np.unique(gv).tolist()))
     report["train_all"] = _named(evaluate(final, X, T))
@@ -343,7 +370,7 @@ def fit(rows, valid, seed=0, log=print, grid=GRID):
     report["gini_importance"] = {FEATURES[i]: round(float(v), 4)
                                  for i, v in enumerate(final.feature_importances_) if v > 0}
     report["nodes"] = int(final.tree_.node_count)
-    report["params"] = dict(max_depth=depth, min_samples_leaf=leaf, weights=wscheme, seed=seed,
+    report["params"] = dict(max_depth=depth, min_samples_leaf=leaf, weights=wscheme, leaves=leaves, seed=seed,
                             rows=int(len(y)), valid_rows=int(len(Tv)))
     return final, ks, report
 

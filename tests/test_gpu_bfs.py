@@ -194,7 +194,7 @@ def test_device_tree_walk_matches_oracle(name, which):
     else:
         T = _big_tree(depth={"mid": 7, "big": 9, "huge": 11}[which])
         tree = gsw.Tree(T)
-    assert len(T["left"]) > {"shipped": 100, "mid": 192, "big": 512, "huge": 2048}[which]
+    assert len(T["left"]) > {"shipped": 50, "mid": 192, "big": 512, "huge": 2048}[which]
     lv, pa, trace = gsw.bfs(G, srcs, policy="tree", tree=tree)
     _check_result(g, srcs, refs, comp, lv, pa, trace)
     gf = ofeat.graph_features(g.offs)

@@ -51,6 +51,22 @@ def test_table2_by_hand():
     assert out["best fixed kernel per graph"]["average"] == pytest.approx((1.5 + 1.0 + 1.0) / 3, abs=1e-3)
 
 
+def test_cost_sensitive_leaves():
+    """A leaf whose rows mostly favour kernel 0 by a hair, while one row is
+    far slower with it, predicts kernel 1 once relabelled by total time."""
+    from sklearn.tree import DecisionTreeClassifier
+
+    X = np.zeros((5, 2))
+    X[:, 0] = [0, 0, 0, 0, 1]
+    T = np.array([[1.0, 1.1], [1.0, 1.1], [1.0, 1.1], [50.0, 1.2], [3.0, 1.0]])
+    y = train.labels(T)
+    c = DecisionTreeClassifier(max_depth=1).fit(X, y)
+    assert c.predict(np.array([[0.0, 0.0]], dtype=np.float32))[0] == 0  # the majority
+    train.relabel_leaves(c, X, T)
+    assert c.predict(np.array([[0.0, 0.0]], dtype=np.float32))[0] == 1  # 53 ms against 4.5 ms
+    assert c.predict(np.array([[1.0, 0.0]], dtype=np.float32))[0] == 1
+
+
 def test_fit_export_load_round_trip(tmp_path):
     """A tree fitted on synthetic rows, exported, read back by the library's
     JSON reader, chooses what scikit-learn and the oracle walk choose."""
@@ -62,7 +78,7 @@ def test_fit_export_load_round_trip(tmp_path):
     rows = dict(X=X, T=T, graph=np.array(["g%d" % (i % 7) for i in range(n)]),
                 source=np.arange(n) % 5, level=np.zeros(n, dtype=int), kernels=np.array([0, 6, 7, 11 + 10]))
     valid = dict(rows)
-    grid = [(4, 5, "regret"), (6, 1, "none")]
+    grid = [(4, 5, "regret", "majority"), (6, 1, "none", "time")]
     clf, ks, report = train.fit(rows, valid, grid=grid, log=lambda *a: None)
     assert report["params"]["max_depth"] in (4, 6) and report["validation"]["time_ratio"] >= 1.0
     assert set(report["model_variants_on_validation"]) >= {"random forest (64 trees)"}
