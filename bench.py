@@ -468,7 +468,13 @@ def bench_serving(tree, preloaded):
             row["batched"]["per_graph_p99_ms"] = serve.per_graph_p99(qb)
         except TimeoutError as e:
             row["batched"] = {"timed_out": str(e)}
-        log("serving %d QPS batched: %s" % (rate, fmt(row["batched"]) if "p50_ms" in row["batched"] else "timed out"))
+        except gsw.GswError as e:  # recorded; the server has closed its sessions
+            import traceback
+
+            traceback.print_exc(file=sys.stderr)
+            row["batched"] = {"error": str(e)}
+        log("serving %d QPS batched: %s" % (rate, fmt(row["batched"]) if "p50_ms" in row["batched"] else
+                                            "failed: %s" % next(iter(row["batched"].values()))))
         if rate <= 500:
             try:
                 qo = serve.serve_one_at_a_time(residents, trace, tree, timeout_s=150)
@@ -486,6 +492,22 @@ def bench_serving(tree, preloaded):
             "note": "rmat22 is the headline graph (seed 2) and chunglu23 the sweep's (seed 4); the others use "
                     "seeds 7-14; one at a time is run up to 500 QPS (it saturates beyond)",
             "runs": runs}
+
+
+def optional_section(name, fn, *a):
+    """Runs one of the comparison sections after the headline; a library error
+    there is recorded in the JSON line (with its traceback on stderr) instead
+    of ending the run before the headline is printed."""
+    from paper_1708_01159_amd import gsw
+
+    try:
+        return fn(*a)
+    except (gsw.GswError, TimeoutError) as e:
+        import traceback
+
+        traceback.print_exc(file=sys.stderr)
+        log("%s section failed: %s" % (name, e))
+        return {"error": "%s: %s" % (type(e).__name__, e)}
 
 
 def main():
@@ -596,12 +618,16 @@ def main():
             if late():
                 skipped.append("batched")
             else:
-                extra["batched"] = bench_batched()
+                extra["batched"] = optional_section("batched", bench_batched)
         if not args.no_sweep:
             if late():
                 skipped.append("sweep")
             else:
-                extra["sweep"], sweep_graphs = bench_sweep(tree)
+                r = optional_section("sweep", bench_sweep, tree)
+                if "error" in r:
+                    extra["sweep"] = r
+                else:
+                    extra["sweep"], sweep_graphs = r
         if not args.no_serving:
             if late():
                 skipped.append("serving")
@@ -609,7 +635,7 @@ def main():
                 pre = {"rmat22": (g, G)}
                 cl = sweep_graphs.get("chunglu23") or gg.workload("chunglu23")
                 pre["chunglu23"] = (cl, gsw.Graph.from_csr(cl.offs, cl.cols, flags=gsw.ASSUME_SYMMETRIC | gsw.TRUSTED))
-                extra["serving"] = bench_serving(tree, pre)
+                extra["serving"] = optional_section("serving", bench_serving, tree, pre)
                 pre["chunglu23"][1].close()
     if skipped:
         extra["skipped_for_time"] = skipped

@@ -297,22 +297,13 @@ int32_t launch_size(int next_kernel, int64_t nn, int64_t nf, int64_t nf_prev, in
 
 namespace {
 
-// Waits until level d's record is in the ring.  Polls the stream for errors
-// now and then so a failed launch cannot leave the host spinning.
+// Waits until level d's record is in the ring.
 gsw_status wait_record(const gsw_graph* g, int64_t d, hipStream_t s, Record* rec) {
-  auto take = [&]() -> bool { return take_record(g->ws.ring, d, rec); };
-  for (uint64_t it = 0;; ++it) {
-    if (take()) return GSW_OK;
-    if ((it & 4095u) == 4095u) {
-      const hipError_t e = hipStreamQuery(s);
-      if (e == hipSuccess) {
-        if (take()) return GSW_OK;
-        return fail(GSW_EHIP, "level %lld finished without posting its record", (long long)d);
-      }
-      if (e != hipErrorNotReady) return fail(GSW_EHIP, "level %lld: %s", (long long)d, hipGetErrorString(e));
-    }
-    __builtin_ia32_pause();
-  }
+  bool missing = false;
+  const hipError_t e = await_record([&]() -> bool { return take_record(g->ws.ring, d, rec); }, s, &missing);
+  if (e != hipSuccess) return fail(GSW_EHIP, "level %lld: %s", (long long)d, hipGetErrorString(e));
+  if (missing) return fail(GSW_EHIP, "level %lld finished without posting its record", (long long)d);
+  return GSW_OK;
 }
 
 gsw_status run_levels(gsw_graph* g, const Policy& pol, const BfsPolicy& dp, int32_t src_idx, int32_t src,

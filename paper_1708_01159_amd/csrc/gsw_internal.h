@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cstdarg>
 #include <cstdint>
 #include <mutex>
@@ -29,6 +30,43 @@ void clear_error();
     gsw_status s_ = (expr);           \
     if (s_ != GSW_OK) return s_;      \
   } while (0)
+
+// Host wait for a record that a kernel posts to mapped host memory: spins on
+// posted(), asking the stream for errors now and then so a failed launch
+// cannot leave the host spinning.  A stream that reports idle before the
+// record is seen is not taken at its word: it is synchronized once, and the
+// record then has kRecordGraceMs to appear before *missing is set.  The
+// record of a level that really ran is therefore never reported missing
+// because the idle report came early; a record that never comes costs the
+// grace period.  Returns the stream's error, if any.
+constexpr int kRecordGraceMs = 5000;
+
+template <class Posted>
+hipError_t await_record(Posted posted, hipStream_t s, bool* missing) {
+  *missing = false;
+  bool idle = false;
+  std::chrono::steady_clock::time_point since{};
+  for (uint64_t it = 0;; ++it) {
+    if (posted()) return hipSuccess;
+    if ((it & 4095u) == 4095u) {
+      if (!idle) {
+        const hipError_t e = hipStreamQuery(s);
+        if (e == hipSuccess) {
+          idle = true;
+          const hipError_t e2 = hipStreamSynchronize(s);
+          if (e2 != hipSuccess) return e2;
+          since = std::chrono::steady_clock::now();
+        } else if (e != hipErrorNotReady) {
+          return e;
+        }
+      } else if (std::chrono::steady_clock::now() - since > std::chrono::milliseconds(kRecordGraceMs)) {
+        *missing = !posted();
+        return hipSuccess;
+      }
+    }
+    __builtin_ia32_pause();
+  }
+}
 
 // Frontier queues are split into kQueueBins segments, one per residue of the
 // producing workgroup id, each with room for every vertex; a workgroup stages

@@ -728,26 +728,23 @@ void stats_free(LevelStats* st) {
   *st = LevelStats();
 }
 
-// Spins until level d's record is in the ring, polling the stream for
-// errors now and then; returns its words through *rec.
+// Waits until level d's record is in the ring; returns its words through
+// *rec.  A record that never comes is reported with what the ring slot and
+// the device's level counter hold.
 gsw_status wait_record(const LevelStats& st, int64_t d, hipStream_t s, const char* who,
                        const volatile u64** rec) {
   const volatile u64* r = st.ring + (size_t)(d % kRing) * kRecWords;
-  for (uint64_t it = 0;; ++it) {
-    if (r[0] == (u64)d + 1ull) {
-      *rec = r;
-      return GSW_OK;
-    }
-    if ((it & 4095u) == 4095u) {
-      const hipError_t e = hipStreamQuery(s);
-      if (e == hipSuccess) {
-        if (r[0] == (u64)d + 1ull) continue;
-        return fail(GSW_EHIP, "%s: level %lld finished without reporting", who, (long long)d);
-      }
-      if (e != hipErrorNotReady) return fail(GSW_EHIP, "%s: %s", who, hipGetErrorString(e));
-    }
-    __builtin_ia32_pause();
+  bool missing = false;
+  const hipError_t e = await_record([&]() -> bool { return r[0] == (u64)d + 1ull; }, s, &missing);
+  if (e != hipSuccess) return fail(GSW_EHIP, "%s: %s", who, hipGetErrorString(e));
+  if (missing) {
+    long long dev = -1;
+    (void)hipMemcpy(&dev, &st.ctl->d, sizeof dev, hipMemcpyDeviceToHost);
+    return fail(GSW_EHIP, "%s: level %lld finished without reporting (its ring slot holds %llu, the device "
+                "level counter %lld)", who, (long long)d, (unsigned long long)r[0], dev);
   }
+  *rec = r;
+  return GSW_OK;
 }
 
 // Fills the staging control block for a traversal whose first level expands

@@ -309,13 +309,49 @@ class Server:
 
     def run(self, trace, timeout_s: float = 600.0):
         """Serves ``trace`` = [(t_arrival, graph, source)] in real time; returns
-        the list of completed Query objects."""
+        the list of completed Query objects.  On an error (a worker's, or the
+        time limit) every query still in a slot is cancelled, the workers are
+        waited for and the sessions closed before the error is raised."""
+        self._slot_q = collections.defaultdict(dict)  # graph -> slot -> Query (admitted, not yet fetched)
+        self._live = {}                               # graph -> worker future
+        self._solo_busy = {}                          # graph -> future of its single-source lane
+        try:
+            queries = self._serve(trace, timeout_s)
+        except BaseException:
+            self._abandon()
+            raise
+        self._shut()
+        return queries
+
+    def _abandon(self):
+        with self._slot_mu:
+            for name, slots in self._slot_q.items():
+                sess = self.sessions.get(name)
+                for k in list(slots):
+                    if sess is not None and sess.cancel(k):
+                        del slots[k]
+        for fut in list(self._live.values()) + list(self._solo_busy.values()):
+            try:
+                fut.result()
+            except Exception:  # noqa: BLE001 (the first error is the one raised)
+                pass
+        self._shut()
+
+    def _shut(self):
+        for name in list(self.sessions):
+            self._close(name)
+        for name, (lane, ex) in self._solo_lanes.items():
+            ex.shutdown(wait=True)
+            self.used -= lane_bytes(self.res[name].graph)
+            self._held -= lane_bytes(self.res[name].graph)
+        self._solo_lanes = {}
+
+    def _serve(self, trace, timeout_s):
         queries = [Query(i, g, s, t) for i, (t, g, s) in enumerate(sorted(trace))]
         pending = collections.defaultdict(collections.deque)
-        slot_q = collections.defaultdict(dict)  # graph -> slot -> Query (admitted, not yet fetched)
+        slot_q = self._slot_q
         done_q = collections.deque()            # completed queries, appended by workers
-        self._live = {}                         # graph -> worker future
-        solo_busy = {}                          # graph -> future of its single-source lane
+        solo_busy = self._solo_busy
         est = collections.defaultdict(lambda: {"solo": 0.5e-3, "session": 1.0e-3})  # s, moving averages
         nxt = 0
         done = 0
@@ -384,13 +420,6 @@ class Server:
                     time.sleep(max(0.0, min(until_next, 0.001)))
         for fut in list(self._live.values()) + list(solo_busy.values()):
             fut.result()
-        for name in list(self.sessions):
-            self._close(name)
-        for name, (lane, ex) in self._solo_lanes.items():
-            ex.shutdown(wait=True)
-            self.used -= lane_bytes(self.res[name].graph)
-            self._held -= lane_bytes(self.res[name].graph)
-        self._solo_lanes = {}
         return queries
 
 

@@ -302,3 +302,36 @@ def test_lane_allocation_failure_falls_back_to_sessions():
     qs = srv.run(trace, timeout_s=60)
     assert srv.alloc_failures == 1 and srv.solo_served == 0
     assert all(q.status == "done" and q.path == "session" for q in qs)
+
+
+def test_worker_error_cancels_closes_and_raises():
+    """A session step that fails on one graph ends the run with that error
+    only after the other graphs' in-flight queries are cancelled, every worker
+    has returned and every session is closed (none is left stepping)."""
+    from paper_1708_01159_amd import gsw
+
+    opened, closed = [], []
+
+    class Tracked(SlowStubSession):
+        def __init__(self, graph, slots):
+            super().__init__(graph, slots)
+            opened.append(self)
+
+        def step(self, max_levels):
+            if self.g.n == 600 and self.it >= 3:
+                raise gsw.GswError(gsw.EHIP, "injected: level 3 finished without reporting")
+            return super().step(max_levels)
+
+        def close(self):
+            closed.append(self)
+
+    res, cands = make(["p", "a", "b"])
+    trace = serve.poisson_trace(3000.0, 0.05, ["p", "a", "b"], cands, seed=14)
+    srv = serve.Server(res, slots=4, keep_levels=True, session_factory=Tracked)
+    with pytest.raises(gsw.GswError, match="level 3"):
+        srv.run(trace, timeout_s=60)
+    assert opened and sorted(map(id, closed)) == sorted(map(id, opened))
+    assert not srv.sessions and not srv.workers
+    assert all(f.done() for f in srv._live.values())
+    for s in opened:
+        assert not s.state, "a query was left running in a closed session"
