@@ -9,6 +9,8 @@ Contents
   * ``bfs``           -- plain single-threaded FIFO BFS in C (``bfs_oracle.c``):
                          hop-distance levels, one valid parent per vertex, the
                          per-depth vertex and degree histograms.
+  * ``components``    -- weakly connected components in C (disjoint-set
+                         forest), labelled by each component's smallest id.
   * ``msbfs_levels``  -- the multi-source result: one ``bfs`` per source,
                          stored as int8 with the 127 cap as a range error.
   * ``checks``        -- Graph500-style invariants and connected components.
@@ -53,6 +55,8 @@ def load(path: str = _LIB):
     lib.oracle_bfs.restype = ctypes.c_int64
     lib.oracle_bfs.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    lib.oracle_components.restype = ctypes.c_int64
+    lib.oracle_components.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     return lib
 
 
@@ -111,6 +115,21 @@ def msbfs_levels(offs, cols, sources, cap: int = INT8_CAP):
             ok = False
         out[i] = np.where(lv > cap, cap, lv).astype(np.int8)
     return out, ok
+
+
+def components(offs, cols, lib=None):
+    """Weakly connected components (``bfs_oracle.c``, disjoint-set forest):
+    ``(label int32[n], count)``, ``label[v]`` the smallest vertex id of the
+    component of v, every arc joining its ends whatever its direction."""
+    lib = lib or _get()
+    offs = np.ascontiguousarray(offs, dtype=np.int64)
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    n = offs.shape[0] - 1
+    label = np.empty(n, dtype=np.int32)
+    c = lib.oracle_components(n, offs.ctypes.data, cols.ctypes.data, label.ctypes.data)
+    if c < 0:
+        raise ValueError("oracle_components rejected its arguments (n=%d)" % n)
+    return label, int(c)
 
 
 def component_edges(offs, level) -> int:

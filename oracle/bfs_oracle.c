@@ -64,3 +64,45 @@ int64_t oracle_bfs(int64_t n, const int64_t *offs, const int32_t *cols, int64_t 
   }
   return (int64_t)maxd + 1;
 }
+
+/*
+ * Weakly connected components (the second traversal on the switching
+ * framework: the paper expects its per-iteration kernel choice to carry over
+ * to other traversal algorithms, Section VI).  label[v] is the smallest
+ * vertex id of the component that contains v, every arc u -> v joining u and
+ * v whatever its direction.  That result has a plain definition, so this is
+ * the textbook disjoint-set forest: one union per arc, with path halving,
+ * the larger root linked under the smaller, so that every root is the
+ * smallest id of its set.  Returns the number of components, or a negative
+ * value on bad arguments / allocation failure.
+ */
+static int32_t cc_find(int32_t *up, int32_t x) {
+  while (up[x] != x) {
+    up[x] = up[up[x]];
+    x = up[x];
+  }
+  return x;
+}
+
+int64_t oracle_components(int64_t n, const int64_t *offs, const int32_t *cols, int32_t *label) {
+  if (n < 1 || !offs || !label) return -1;
+  int32_t *up = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+  if (!up) return -2;
+  for (int64_t v = 0; v < n; ++v) up[v] = (int32_t)v;
+  for (int64_t u = 0; u < n; ++u) {
+    for (int64_t e = offs[u]; e < offs[u + 1]; ++e) {
+      int32_t a = cc_find(up, (int32_t)u), b = cc_find(up, cols[e]);
+      if (a < b)
+        up[b] = a;
+      else if (b < a)
+        up[a] = b;
+    }
+  }
+  int64_t count = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    label[v] = cc_find(up, (int32_t)v);
+    if (label[v] == v) ++count;
+  }
+  free(up);
+  return count;
+}
