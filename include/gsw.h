@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define GSW_ABI_VERSION 3
+#define GSW_ABI_VERSION 4
 
 typedef enum {
   GSW_OK = 0,
@@ -410,6 +410,69 @@ void gsw_msbfs_opts_default(gsw_msbfs_opts *opts);
  */
 gsw_status gsw_msbfs(const gsw_graph *g, const int32_t *sources, int32_t n_sources, int8_t *levels,
                      int32_t *n_levels, const gsw_msbfs_opts *opts);
+
+/* -------------------------------------------------- connected components */
+
+/*
+ * Weakly connected components: a second traversal on the same switching
+ * framework (the paper expects its per-iteration choice of interchangeable
+ * kernels to carry over to other traversal algorithms, Section VI).  Every
+ * arc joins its two ends whatever its direction.
+ *   Phase 1 (symmetric graphs with arcs, opts->bfs_first): the component of
+ *   a vertex of largest out-degree (the smallest id among ties) is found by
+ *   the level-switched BFS of gsw_bfs, with opts->tree choosing each level's
+ *   kernel.
+ *   Phase 2: minimum-label propagation over the other vertices with arcs,
+ *   each starting from its own id, until an iteration changes no label.
+ *   Each iteration runs one of two kernels: PUSH (one lane per vertex whose
+ *   label fell in the previous iteration lowers its neighbours' labels with
+ *   atomicMin) or PULL (one lane per vertex left to phase 2 takes the
+ *   smallest label among its neighbours), chosen per iteration by
+ *   opts->policy.
+ * On a directed graph a vertex's neighbours are its out- and in-neighbours
+ * (over the transpose the library keeps) and phase 1 is skipped.
+ *   labels        [n] int32: the smallest vertex id of v's component
+ *                 (device memory when opts->device_ptrs, else host).
+ *   n_components  receives the number of components (isolated vertices
+ *                 count one each); may be NULL.
+ *   trace         host array of trace_cap rows or NULL; *trace_len (may be
+ *                 NULL) receives the rows produced (phase 1 as row 0 when it
+ *                 runs), which can exceed trace_cap.
+ * The graph's working memory for this call (4 int32 arrays of n and a bitmap)
+ * is allocated on first use and held until gsw_graph_destroy.
+ */
+enum { GSW_CC_SWITCH = 0, GSW_CC_PUSH = 1, GSW_CC_PULL = 2 };   /* gsw_cc_opts.policy */
+enum { GSW_CC_K_BFS = 0, GSW_CC_K_PUSH = 1, GSW_CC_K_PULL = 2 }; /* gsw_cc_trace.kernel */
+
+typedef struct {
+  int32_t iteration; /* from 0; phase 1, when it runs, is iteration 0 */
+  int32_t kernel;    /* GSW_CC_K_* */
+  int64_t n_active;  /* vertices whose label fell in the previous iteration (all the
+                        vertices left to phase 2 at its first iteration; phase 1: 1, its seed) */
+  int64_t e_active;  /* their arcs (out + in on a directed graph); -1 on the phase-1 row */
+  int64_t changed;   /* vertices whose label this iteration lowered (phase 1: vertices reached) */
+  float ms;          /* HIP events around the iteration's launches (phase 1: the BFS and
+                        the labelling of its component) */
+  int32_t pad;
+} gsw_cc_trace;
+
+typedef struct {
+  int32_t policy;        /* GSW_CC_SWITCH: pull when the active vertices' arcs exceed
+                            pull_above x the arcs of all vertices left to phase 2, else push;
+                            GSW_CC_PUSH / GSW_CC_PULL: that kernel at every iteration */
+  int32_t bfs_first;     /* 1: phase 1 on symmetric graphs; 0: propagation only */
+  const gsw_tree *tree;  /* policy of the phase-1 BFS (NULL: the default kernel at every level) */
+  float pull_above;      /* GSW_CC_SWITCH threshold, >= 0 */
+  int32_t device_ptrs;   /* 1: labels is device memory; 0: host */
+  void *stream;          /* hipStream_t; NULL = library stream */
+} gsw_cc_opts;
+
+/* Fills opts: switch policy, pull_above 0.05, phase 1 on, no tree, host labels,
+ * library stream. */
+void gsw_cc_opts_default(gsw_cc_opts *opts);
+
+gsw_status gsw_cc(const gsw_graph *g, int32_t *labels, int64_t *n_components, gsw_cc_trace *trace,
+                  int32_t trace_cap, int32_t *trace_len, const gsw_cc_opts *opts);
 
 /* -------------------------------------------------------- serving sessions */
 

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgsw.so")
 OBJ = os.path.join(HERE, "_build")
 ARCH = os.environ.get("GSW_OFFLOAD_ARCH", "gfx950")
-SOURCES = ["gsw_kernels.hip", "gsw_core.cpp", "gsw_bfs.cpp", "gsw_msbfs.hip", "gsw_noalloc.hip"]
+SOURCES = ["gsw_kernels.hip", "gsw_core.cpp", "gsw_bfs.cpp", "gsw_msbfs.hip", "gsw_noalloc.hip", "gsw_cc.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 COMMON = [

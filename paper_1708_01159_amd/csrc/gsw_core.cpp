@@ -387,6 +387,7 @@ void free_graph(gsw_graph* g) {
     if (g->cols) (void)hipFree((void*)g->cols);
   }
   ms_release(g);
+  cc_release(g);
   if (g->stream) (void)hipStreamDestroy(g->stream);
   delete g;
 }
@@ -535,7 +536,7 @@ gsw_status gsw_graph_info(const gsw_graph* g, int64_t* n, int64_t* nnz, double d
   if (n) *n = g->n;
   if (nnz) *nnz = g->nnz;
   if (deg_stats) std::memcpy(deg_stats, g->deg_stats, sizeof g->deg_stats);
-  if (dev_bytes) *dev_bytes = g->csr_bytes + g->rcsr_bytes + g->origin_bytes + g->ws.bytes;
+  if (dev_bytes) *dev_bytes = g->csr_bytes + g->rcsr_bytes + g->origin_bytes + g->ws.bytes + cc_workspace_bytes(g);
   return GSW_OK;
 }
 

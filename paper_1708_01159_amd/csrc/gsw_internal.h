@@ -136,6 +136,7 @@ struct Workspace {
 };
 
 struct MsWorkspace;  // batched BFS state (gsw_msbfs.hip)
+struct CcWorkspace;  // connected-components state (gsw_cc.hip)
 
 }  // namespace gsw
 
@@ -162,6 +163,7 @@ struct gsw_graph {
   // chunk index) entries, built on first use; -1 = not built yet
   unsigned long long* heavy = nullptr;
   int64_t n_heavy = -1;
+  gsw::CcWorkspace* cc = nullptr; // connected components, allocated on first use
   hipStream_t stream = nullptr;   // library stream for this graph
   std::mutex mu;
 };
@@ -399,6 +401,8 @@ bool kernel_is_pull(int k);
 // The kernel of base `base` and the count variant of k.
 inline int kernel_with_base(int k, int base) { return base + GSW_N_BASE_KERNELS * kernel_count(k); }
 void ms_release(gsw_graph* g);
+void cc_release(gsw_graph* g);
+size_t cc_workspace_bytes(const gsw_graph* g);
 
 
 }  // namespace gsw

@@ -92,6 +92,21 @@ class MsbfsOpts(ctypes.Structure):
                 ("tree", ctypes.c_void_p), ("stream", ctypes.c_void_p)]
 
 
+class CcTrace(ctypes.Structure):
+    _fields_ = [("iteration", ctypes.c_int32), ("kernel", ctypes.c_int32), ("n_active", ctypes.c_int64),
+                ("e_active", ctypes.c_int64), ("changed", ctypes.c_int64), ("ms", ctypes.c_float),
+                ("pad", ctypes.c_int32)]
+
+
+class CcOpts(ctypes.Structure):
+    _fields_ = [("policy", ctypes.c_int32), ("bfs_first", ctypes.c_int32), ("tree", ctypes.c_void_p),
+                ("pull_above", ctypes.c_float), ("device_ptrs", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+CC_SWITCH, CC_PUSH, CC_PULL = 0, 1, 2          # gsw_cc_opts.policy
+CC_K_BFS, CC_K_PUSH, CC_K_PULL = 0, 1, 2       # gsw_cc_trace.kernel
+CC_KERNEL_NAMES = ("bfs", "push", "pull")
+
 MSBFS_MAX_SOURCES = 1024
 MSBFS_LEVEL_CAP = 127
 
@@ -152,6 +167,8 @@ def lib():
         "gsw_session_cancel": (i32, [vp, i32]),
         "gsw_session_info": (i32, [vp, P(i32), P(i32), P(i64), P(ctypes.c_size_t)]),
         "gsw_session_set_thresholds": (i32, [vp, ctypes.c_float, ctypes.c_float]),
+        "gsw_cc_opts_default": (None, [P(CcOpts)]),
+        "gsw_cc": (i32, [vp, vp, P(i64), vp, i32, P(i32), P(CcOpts)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -499,6 +516,47 @@ def bfs_noalloc(graph: Graph, sources, levels, parents=None, policy: str = "tree
                                  ctypes.byref(o)))
     del keep
     return [_row(t) for t in tr[:min(tlen.value, cap)]]
+
+
+def components(graph: Graph, policy: str = "switch", bfs_first: bool = True, tree: Tree = None,
+               pull_above: float = None, device: bool = False, stream=None, out=None, trace_cap: int = 4096):
+    """Weakly connected components (gsw_cc).  Returns ``(labels, n_components,
+    trace)``: ``labels`` int32 ``[n]``, the smallest vertex id of each
+    vertex's component (numpy, or a torch CUDA tensor when ``device``;
+    ``out`` may supply it), ``trace`` a list of dicts, one per iteration.
+    ``policy``: "switch" (push or pull per iteration), "push" or "pull";
+    ``tree`` picks the kernels of the phase-1 BFS (None: the default kernel)."""
+    pol = {"switch": CC_SWITCH, "push": CC_PUSH, "pull": CC_PULL}[policy]
+    n = graph.n
+    o = CcOpts()
+    lib().gsw_cc_opts_default(ctypes.byref(o))
+    o.policy = pol
+    o.bfs_first = int(bool(bfs_first))
+    o.tree = tree.handle if tree is not None else None
+    if pull_above is not None:
+        o.pull_above = float(pull_above)
+    if device:
+        import torch
+
+        if out is not None:
+            check_out(out, "int32", n, True, "components labels")
+            lab = out
+        else:
+            lab = torch.empty(n, dtype=torch.int32, device="cuda")
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+    else:
+        lab = np.empty(n, dtype=np.int32)
+    o.device_ptrs = int(bool(device))
+    o.stream = stream
+    tr = (CcTrace * max(trace_cap, 1))()
+    tlen = ctypes.c_int32(0)
+    nc = ctypes.c_int64(0)
+    _check(lib().gsw_cc(graph.handle, _ptr(lab), ctypes.byref(nc), tr, trace_cap, ctypes.byref(tlen),
+                        ctypes.byref(o)))
+    rows = [dict(iteration=t.iteration, kernel=CC_KERNEL_NAMES[t.kernel], n_active=t.n_active,
+                 e_active=t.e_active, changed=t.changed, ms=t.ms) for t in tr[:min(tlen.value, trace_cap)]]
+    return lab, int(nc.value), rows
 
 
 class Runner:
