@@ -427,6 +427,60 @@ def bench_sweep(tree):
     return res, graphs
 
 
+# ----------------------------------------------------- connected components
+def bench_components(tree, preloaded):
+    """Weakly connected components (gsw_cc) on the headline graph and the
+    sweep's scale-free graph: the default path (the tree-switched BFS for the
+    largest-degree component, then propagation with push or pull chosen per
+    iteration) and propagation alone under each policy, against the oracle's
+    result and time; the pull kernel's algorithmic bytes per iteration."""
+    import torch
+
+    import oracle
+    from paper_1708_01159_amd import gsw
+
+    sync = torch.cuda.synchronize
+    res = {}
+    for name, (g, G) in preloaded.items():
+        t = time.perf_counter()
+        want, count = oracle.components(g.offs, g.cols)
+        t_cpu = time.perf_counter() - t
+        out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        row = {"n": g.n, "nnz": g.nnz, "components": count, "oracle_s": round(t_cpu, 3)}
+        for label, kw in (("bfs_then_switch", dict(policy="switch")),
+                          ("propagation_switch", dict(policy="switch", bfs_first=False)),
+                          ("propagation_push", dict(policy="push", bfs_first=False)),
+                          ("propagation_pull", dict(policy="pull", bfs_first=False))):
+            best, tr = 1e9, None
+            for _ in range(3):
+                sync()
+                t0 = time.perf_counter()
+                _, nc, tr = gsw.components(G, tree=tree, device=True, out=out, **kw)
+                sync()
+                best = min(best, time.perf_counter() - t0)
+            ok = nc == count and np.array_equal(out.cpu().numpy(), want)
+            row[label] = {"ms": round(best * 1e3, 3), "iterations": len(tr), "equal_to_oracle": bool(ok),
+                          "kernels": [r["kernel"] for r in tr][:16]}
+            if label == "propagation_pull":
+                # per pull iteration: every remaining vertex's row bounds (2 x 8 B), its label
+                # and list entry (4 + 4 B), and per arc a column and a label (4 + 4 B)
+                its = [r for r in tr if r["kernel"] == "pull"]
+                n_rest, e_rest = tr[0]["n_active"], tr[0]["e_active"]
+                b = 24 * n_rest + 8 * e_rest
+                ms = float(np.mean([r["ms"] for r in its]))
+                row["pull_roofline"] = {"bound": "hbm", "bytes_per_iteration": int(b), "mean_iteration_ms": round(ms, 4),
+                                        "achieved_gbs": round(b / ms / 1e6, 1),
+                                        "frac": round(b / ms / 1e6 / 8000.0, 4),
+                                        "timing": "HIP events around each iteration"}
+        row["speedup_over_oracle"] = round(t_cpu / (row["bfs_then_switch"]["ms"] * 1e-3), 1)
+        log("components %s: %d components, %.3f ms (bfs then switch) vs oracle %.2f s; propagation alone "
+            "switch/push/pull %.2f / %.2f / %.2f ms" % (
+                name, count, row["bfs_then_switch"]["ms"], t_cpu, row["propagation_switch"]["ms"],
+                row["propagation_push"]["ms"], row["propagation_pull"]["ms"]))
+        res[name] = row
+    return res
+
+
 # ---------------------------------------------------------------- serving
 SERVING_RATES = (100, 500, 1000, 2000, 5000)
 SERVING_SECONDS = 4.0
@@ -526,6 +580,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-components", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (scale for HBM byte counters)")
     ap.add_argument("--dispatch-log", default=None,
@@ -628,15 +683,27 @@ def main():
                     extra["sweep"] = r
                 else:
                     extra["sweep"], sweep_graphs = r
+        cl_graph = None
+        if not args.no_components:
+            if late():
+                skipped.append("components")
+            else:
+                cl = sweep_graphs.get("chunglu23") or gg.workload("chunglu23")
+                cl_graph = (cl, gsw.Graph.from_csr(cl.offs, cl.cols, flags=gsw.ASSUME_SYMMETRIC | gsw.TRUSTED))
+                extra["components"] = optional_section("components", bench_components, tree,
+                                                       {"rmat22": (g, G), "chunglu23": cl_graph})
         if not args.no_serving:
             if late():
                 skipped.append("serving")
             else:
                 pre = {"rmat22": (g, G)}
-                cl = sweep_graphs.get("chunglu23") or gg.workload("chunglu23")
-                pre["chunglu23"] = (cl, gsw.Graph.from_csr(cl.offs, cl.cols, flags=gsw.ASSUME_SYMMETRIC | gsw.TRUSTED))
+                if cl_graph is None:
+                    cl = sweep_graphs.get("chunglu23") or gg.workload("chunglu23")
+                    cl_graph = (cl, gsw.Graph.from_csr(cl.offs, cl.cols, flags=gsw.ASSUME_SYMMETRIC | gsw.TRUSTED))
+                pre["chunglu23"] = cl_graph
                 extra["serving"] = optional_section("serving", bench_serving, tree, pre)
-                pre["chunglu23"][1].close()
+        if cl_graph is not None:
+            cl_graph[1].close()
     if skipped:
         extra["skipped_for_time"] = skipped
 

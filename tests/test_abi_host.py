@@ -327,3 +327,26 @@ def test_check_out_rules():
                 out=(torch.zeros((1, 10), dtype=torch.int32), None))
     with pytest.raises(ValueError):
         gsw.msbfs(_FakeGraph(), [0], out=torch.zeros((1, 10), dtype=torch.int8))
+
+
+def test_components_abi_constants_layout_and_null_arguments():
+    """gsw_cc's enums and structs as the binding lays them out, its defaults,
+    and its argument checks that need no GPU."""
+    import ctypes
+
+    text = open(os.path.join(ROOT, "include", "gsw.h")).read()
+    pol = dict((m.group(1), int(m.group(2))) for m in re.finditer(r"GSW_CC_(SWITCH|PUSH|PULL) = (\d+)", text))
+    assert (pol["SWITCH"], pol["PUSH"], pol["PULL"]) == (gsw.CC_SWITCH, gsw.CC_PUSH, gsw.CC_PULL)
+    ks = dict((m.group(1), int(m.group(2))) for m in re.finditer(r"GSW_CC_K_(BFS|PUSH|PULL) = (\d+)", text))
+    assert [ks["BFS"], ks["PUSH"], ks["PULL"]] == [gsw.CC_K_BFS, gsw.CC_K_PUSH, gsw.CC_K_PULL]
+    assert gsw.CC_KERNEL_NAMES[gsw.CC_K_PULL] == "pull"
+    assert ctypes.sizeof(gsw.CcTrace) == 40 and gsw.CcTrace.ms.offset == 32
+    assert ctypes.sizeof(gsw.CcOpts) == 32 and gsw.CcOpts.stream.offset == 24
+    o = gsw.CcOpts()
+    gsw.lib().gsw_cc_opts_default(ctypes.byref(o))
+    assert (o.policy, o.bfs_first, o.device_ptrs) == (gsw.CC_SWITCH, 1, 0)
+    assert abs(o.pull_above - 0.05) < 1e-7 and o.tree is None and o.stream is None
+    lab = np.zeros(4, dtype=np.int32)
+    nc = ctypes.c_int64(-1)
+    st = gsw.lib().gsw_cc(None, lab.ctypes.data, ctypes.byref(nc), None, 0, None, ctypes.byref(o))
+    assert st == gsw.EINVAL and nc.value == 0 and "null graph" in gsw.last_error()
