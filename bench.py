@@ -294,9 +294,28 @@ def run_fixed(G, srcs, m_c, out_lv, out_pa, kernels=None):
     return fixed
 
 
+def level_times(G, s, reps):
+    """Per-level time (ms) of every kernel from the same saved state
+    (gsw_bfs_profile), with the push kernels' times on the levels the search
+    runs in single-workgroup multi-level launches replaced by what such a
+    launch costs per level -- the correction the tree's training rows get
+    (paper_1708_01159_amd.train.apply_solo): the profile times each level as
+    a launch of its own."""
+    from paper_1708_01159_amd import gsw, train
+
+    times, fr, ks = gsw.bfs_profile(G, int(s), reps=reps, advance_kernel=-1)
+    _, _, tr = gsw.bfs(G, [int(s)], policy="fixed", kernel=gsw.PUSH_VERTEX, parents=False, time_levels=True,
+                       trace_cap=len(fr) + 64)
+    solo = np.full(len(fr), np.nan)
+    for t in tr:
+        if t.level < len(fr) and t.flags & 4:
+            solo[t.level] = t.ms
+    return train.apply_solo(times, solo, ks)
+
+
 def run_best_per_level(G, srcs, m_c, med_switched, traces, out_lv, out_pa, reps, steps):
     """Per source: each level's fastest kernel measured from the same saved
-    state (all 33 kernels), replayed end to end."""
+    state (all 33 kernels; level_times), replayed end to end."""
     import torch
 
     from paper_1708_01159_amd import gsw
@@ -306,7 +325,7 @@ def run_best_per_level(G, srcs, m_c, med_switched, traces, out_lv, out_pa, reps,
     sched_runner = gsw.Runner(G, out_lv, out_pa, policy="schedule", schedule=[0], trace_cap=1 << 16)
     picks_of = {i: [r.kernel for r in tr] for i, _, tr in traces}
     for i, s in enumerate(srcs):
-        times, _, _ = gsw.bfs_profile(G, int(s), reps=reps, advance_kernel=-1)
+        times = level_times(G, s, reps)
         sched = np.argmin(times, axis=1).astype(np.int32)
         sched_runner.set_schedule(sched)
         sched_runner.run(int(s))
@@ -411,7 +430,7 @@ def bench_sweep(tree):
         sched = gsw.Runner(G, lv, None, policy="schedule", schedule=[0], trace_cap=1 << 16)
         r_sw, r_bpl = [], []
         for i, s in enumerate(srcs[:bpl_src]):
-            times, _, _ = gsw.bfs_profile(G, int(s), reps=reps, advance_kernel=-1)
+            times = level_times(G, s, reps)
             sched.set_schedule(np.argmin(times, axis=1).astype(np.int32))
             sched.run(int(s))
             r_bpl.append(min(timed(sched, s, sync), timed(sched, s, sync)))

@@ -25,6 +25,10 @@ lookup.  Here:
            future work are fitted on the same rows and reported beside it: a
            regression tree per kernel (predict each kernel's level time, take
            the smallest) and a random forest classifier.
+  solo     per row, the level's time when the search runs it in a
+           single-workgroup multi-level launch (small top-down levels): the
+           push kernels' times on such rows are replaced by it before fitting,
+           since the profile times every level as a launch of its own.
   export   JSON with the flat node arrays gsw_tree_load() reads.
 
 Every graph here is a synthetic family member at its own seed; the graphs and
@@ -37,6 +41,8 @@ graph it was trained on.
 
     python -m paper_1708_01159_amd.train collect --out rows.npz
     python -m paper_1708_01159_amd.train collect --set valid --out valid.npz
+    python -m paper_1708_01159_amd.train solo --rows rows.npz --out rows.npz
+    python -m paper_1708_01159_amd.train solo --set valid --rows valid.npz --out valid.npz
     python -m paper_1708_01159_amd.train fit --rows rows.npz --valid valid.npz --out trees/mi355x.json
 """
 from __future__ import annotations
@@ -135,6 +141,62 @@ def collect(graphs=None, reps: int = 3, kernels=None, log=print, source_seed: in
         log("collected %-22s n=%-9d nnz=%-10d rows=%d (%.1f s)" % (name, g.n, g.nnz, len(X), time.time() - t0))
     return dict(X=np.array(X), T=np.array(T, dtype=np.float64), graph=np.array(gname),
                 source=np.array(src), level=np.array(lvl), kernels=np.array(ks))
+
+
+# A single-workgroup launch runs up to 32 small top-down levels back to back
+# (gsw_bfs_opts.no_solo); the profile above times each level as one launch
+# of its own, so on such levels it charges a push kernel a whole launch
+# (about 6-12 us on MI355X) where the search pays a few microseconds.  The
+# share of one launch's cost that each of its levels carries:
+SOLO_LAUNCH_SHARE_MS = 0.0005
+
+
+def solo_times(graphs, rows, log=print):
+    """Per row: the device time (ms) of the row's level when the search runs
+    it in a single-workgroup launch, NaN when it does not.  One search per
+    (graph, source) with push_vertex at every level and device-stamped level
+    times; BFS level sets do not depend on the kernel, so its level d is the
+    row's level d, and every queue-driven top-down kernel runs such a level
+    the same way."""
+    import torch  # noqa: F401  (one HIP runtime: torch's)
+
+    out = np.full(len(rows["level"]), np.nan)
+    want = {}
+    for i, (gname, s, d) in enumerate(zip(rows["graph"], rows["source"], rows["level"])):
+        want.setdefault(str(gname), {}).setdefault(int(s), []).append((int(d), i))
+    for name, maker, _ in graphs:
+        if name not in want:
+            continue
+        t0 = time.time()
+        g = maker()
+        flags = gsw.TRUSTED | (0 if "_dir" in name else gsw.ASSUME_SYMMETRIC)
+        G = gsw.Graph.from_csr(g.offs, g.cols, flags=flags)
+        n_solo = 0
+        for s, items in want[name].items():
+            _, _, tr = gsw.bfs(G, [s], policy="fixed", kernel=gsw.PUSH_VERTEX, parents=False, time_levels=True,
+                               trace_cap=max(d for d, _ in items) + 64)
+            by_level = {t.level: t for t in tr}
+            for d, i in items:
+                t = by_level.get(d)
+                if t is not None and t.flags & 4:
+                    out[i] = t.ms
+                    n_solo += 1
+        G.close()
+        log("solo times %-22s %d of %d rows (%.1f s)" % (name, n_solo, sum(len(v) for v in want[name].values()),
+                                                        time.time() - t0))
+    return out
+
+
+def apply_solo(T, solo_ms, kernels):
+    """T with the push kernels' times replaced, on rows whose level runs in a
+    single-workgroup launch, by that launch's cost per level (the level's
+    device time plus SOLO_LAUNCH_SHARE_MS)."""
+    T = np.array(T, dtype=np.float64, copy=True)
+    m = ~np.isnan(np.asarray(solo_ms, dtype=np.float64))
+    cols = [j for j, k in enumerate(kernels) if gsw.kernel_base(int(k)) <= gsw.PUSH_EDGE]
+    for j in cols:
+        T[m, j] = np.asarray(solo_ms)[m] + SOLO_LAUNCH_SHARE_MS
+    return T
 
 
 TIE_TOL = 0.02  # level times within 2% of the fastest count as ties (measurement noise)
@@ -397,9 +459,14 @@ def export(clf, ks, path: str, report=None, name="mi355x"):
 
 
 def _load_rows(paths):
+    """Rows of one or more collect files; where every file carries the solo
+    pass (solo_ms), T is corrected with it (apply_solo)."""
     parts = [dict(np.load(p, allow_pickle=False)) for p in paths]
     rows = {k: np.concatenate([p[k] for p in parts]) for k in ("X", "T", "graph", "source", "level")}
     rows["kernels"] = parts[0]["kernels"]
+    if all("solo_ms" in p for p in parts):
+        rows["solo_ms"] = np.concatenate([p["solo_ms"] for p in parts])
+        rows["T"] = apply_solo(rows["T"], rows["solo_ms"], rows["kernels"])
     return rows
 
 
@@ -411,12 +478,23 @@ def main(argv=None):
     c.add_argument("--set", default="train", choices=["train", "valid"])
     c.add_argument("--reps", type=int, default=3)
     c.add_argument("--only", default=None, help="comma-separated graph names")
+    so = sub.add_parser("solo", help="add the single-workgroup level times to a collect file")
+    so.add_argument("--rows", required=True)
+    so.add_argument("--set", default="train", choices=["train", "valid"])
+    so.add_argument("--out", required=True)
     f = sub.add_parser("fit")
     f.add_argument("--rows", required=True, nargs="+")
     f.add_argument("--valid", required=True, nargs="+")
     f.add_argument("--out", required=True)
     f.add_argument("--seed", type=int, default=0)
     a = ap.parse_args(argv)
+    if a.cmd == "solo":
+        rows = dict(np.load(a.rows, allow_pickle=False))
+        rows["solo_ms"] = solo_times(TRAIN_GRAPHS if a.set == "train" else VALID_GRAPHS, rows,
+                                     log=lambda *x: print(*x, flush=True))
+        np.savez_compressed(a.out, **rows)
+        print("wrote", a.out, int(np.sum(~np.isnan(rows["solo_ms"]))), "solo rows of", len(rows["level"]), flush=True)
+        return
     if a.cmd == "collect":
         graphs = TRAIN_GRAPHS if a.set == "train" else VALID_GRAPHS
         if a.only:

@@ -91,3 +91,25 @@ def test_fit_export_load_round_trip(tmp_path):
         assert (k, unknown) == (k2, u2)
         if not unknown:
             assert k == ks[int(clf.predict(x.astype(np.float32).reshape(1, -1))[0])]
+
+
+def test_apply_solo_replaces_push_times_on_single_workgroup_rows(tmp_path):
+    from paper_1708_01159_amd import gsw, train
+
+    ks = np.arange(gsw.N_KERNELS)
+    T = np.full((3, len(ks)), 0.010)
+    T[:, gsw.PULL_BITMAP] = 0.008
+    solo = np.array([np.nan, 0.003, np.nan])
+    T2 = train.apply_solo(T, solo, ks)
+    push = [k for k in ks if gsw.kernel_base(int(k)) <= gsw.PUSH_EDGE]
+    other = [k for k in ks if gsw.kernel_base(int(k)) > gsw.PUSH_EDGE]
+    assert np.allclose(T2[1, push], 0.003 + train.SOLO_LAUNCH_SHARE_MS)
+    assert np.array_equal(T2[1, other], T[1, other]) and np.array_equal(T2[[0, 2]], T[[0, 2]])
+    assert train.labels(T2)[1] == 0 and train.labels(T)[1] == gsw.PULL_BITMAP  # push now wins that level
+    # collect files with the solo pass are corrected on load; without it they are not
+    rows = dict(X=np.zeros((3, gsw.N_FEATURES)), T=T, graph=np.array(["a"] * 3), source=np.zeros(3, dtype=np.int64),
+                level=np.arange(3), kernels=ks)
+    np.savez(tmp_path / "plain.npz", **rows)
+    np.savez(tmp_path / "solo.npz", solo_ms=solo, **rows)
+    assert np.array_equal(train._load_rows([str(tmp_path / "plain.npz")])["T"], T)
+    assert np.array_equal(train._load_rows([str(tmp_path / "solo.npz")])["T"], T2)
