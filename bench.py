@@ -500,6 +500,33 @@ def bench_components(tree, preloaded):
     return res
 
 
+def components_pull_only(calls: int = 4):
+    """Connected components of R-MAT 22 by propagation alone with the pull
+    kernel at every iteration (each iteration reads every arc: the kernel's
+    byte model is exact per launch), for the profiler: one untimed call, then
+    `calls` calls; labels checked against the oracle."""
+    import torch
+
+    import oracle
+    from paper_1708_01159_amd import gsw
+    from paper_1708_01159_amd import graphgen as gg
+
+    g = gg.workload("rmat22")
+    G = gsw.Graph.from_csr(g.offs, g.cols, flags=gsw.ASSUME_SYMMETRIC | gsw.TRUSTED)
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    want, count = oracle.components(g.offs, g.cols)
+    tr = None
+    for _ in range(calls + 1):
+        _, nc, tr = gsw.components(G, policy="pull", bfs_first=False, device=True, out=out)
+    torch.cuda.synchronize()
+    ok = nc == count and np.array_equal(out.cpu().numpy(), want)
+    n_rest, e_rest = tr[0]["n_active"], tr[0]["e_active"]
+    G.close()
+    return {"workload": "R-MAT scale 22, seed 2", "calls": calls + 1, "iterations_per_call": len(tr),
+            "n_rest": int(n_rest), "e_rest": int(e_rest), "bytes_per_iteration": int(24 * n_rest + 8 * e_rest),
+            "mean_iteration_ms_events": round(float(np.mean([r["ms"] for r in tr])), 4), "equal_to_oracle": bool(ok)}
+
+
 # ---------------------------------------------------------------- serving
 SERVING_RATES = (100, 500, 1000, 2000, 5000)
 SERVING_SECONDS = 4.0
@@ -606,6 +633,10 @@ def main():
                     help="write every BFS call's (kernel, frontier, bytes) per level to this JSON file")
     ap.add_argument("--batched-only", default=None, metavar="B[,B...]",
                     help="only the batched section at these batch sizes (one JSON line; for profiling)")
+    ap.add_argument("--components-only", action="store_true",
+                    help="only connected components on R-MAT 22 by pull propagation (one JSON line; for profiling)")
+    ap.add_argument("--summarize-components", default=None, metavar="DIR",
+                    help="print the components rocprofv3 summary of DIR (no GPU)")
     ap.add_argument("--summarize-batched", default=None, metavar="DIR",
                     help="print the batched-path rocprofv3 summary of DIR (no GPU)")
     ap.add_argument("--summarize-profile", default=None, metavar="DIR",
@@ -621,6 +652,11 @@ def main():
         from paper_1708_01159_amd import profile_summary
 
         print(profile_summary.summarize_batched(args.summarize_batched))
+        return
+    if args.summarize_components:
+        from paper_1708_01159_amd import profile_summary
+
+        print(profile_summary.summarize_components(args.summarize_components))
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -640,6 +676,13 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     torch.cuda.set_device(0)
+
+    if args.components_only:
+        line = {"components_pull": components_pull_only()}
+        if args.copy_calib:
+            line["copy_calibration"] = copy_calibration()
+        print(json.dumps(line), flush=True)
+        return
 
     if args.batched_only:
         sizes = tuple(int(x) for x in args.batched_only.split(","))

@@ -254,3 +254,61 @@ def summarize_batched(d, tuned_batches: int = 6):
               "traffic / algorithmic = %.2f." % (alg / 1e6, B, n, us, alg / (us * 1e-6) / 1e9,
                                                  alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, (fb + wb) / alg)]
     return "\n".join(L)
+
+
+COMPONENTS_CMD = "python3 -u bench.py --components-only --copy-calib"
+
+
+def summarize_components(d):
+    """The pull kernel of connected components (k_cc_pull) over the profiled
+    command's calls: rocprofv3 mean duration, FETCH_SIZE and WRITE_SIZE per
+    launch scaled by the 1 GiB copy of the same run, and the algorithmic
+    bytes per launch from the command's own line (every launch reads every
+    arc: 24 bytes per vertex with arcs plus 8 per arc)."""
+    line = json.loads(open(os.path.join(d, "trace_bench.json")).read().strip().splitlines()[-1])
+    info = line["components_pull"]
+    tr = [r for r in _csv_rows(os.path.join(d, "trace", "run_kernel_trace.csv"))]
+    durs = {}
+    for r in tr:
+        durs.setdefault(_short(r["Kernel_Name"]), []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+
+    def counters(sub, name):
+        out = {}
+        for r in _csv_rows(os.path.join(d, sub, "run_counter_collection.csv")):
+            if r["Counter_Name"] == name:
+                out.setdefault(_short(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+        return out
+
+    fe, wr = counters("fetch", "FETCH_SIZE"), counters("write", "WRITE_SIZE")
+    GiB = 1 << 30
+    cb = [k for k in fe if "copyBuffer" in k][0]
+    f_scale = GiB / (np.mean(sorted(fe[cb])[-2:]) * 1024)
+    w_scale = GiB / (np.mean(sorted(wr[cb])[-2:]) * 1024)
+    L = ["# Connected components on R-MAT scale 22: the pull propagation kernel", "",
+         "Commands (from the repository root, `TMPDIR=/tmp`; the trace run's stdout is `trace_bench.json`):", "",
+         "```",
+         "rocprofv3 --kernel-trace --stats --output-format csv -d {d}/trace -o run -- ".format(d=d) + COMPONENTS_CMD,
+         "rocprofv3 --pmc FETCH_SIZE --output-format csv -d {d}/fetch -o run -- ".format(d=d) + COMPONENTS_CMD,
+         "rocprofv3 --pmc WRITE_SIZE --output-format csv -d {d}/write -o run -- ".format(d=d) + COMPONENTS_CMD,
+         "python3 bench.py --summarize-components " + d, "```", "",
+         "%d calls of gsw_cc with propagation alone and the pull kernel at every iteration (%d iterations per "
+         "call; labels equal to the oracle: %s).  Every launch of k_cc_pull reads the rows of all %d vertices "
+         "with arcs and all %d arcs.  Counter scale from the plain 1 GiB device copy of the same run: "
+         "FETCH_SIZE x %.3f, WRITE_SIZE x %.3f." % (info["calls"], info["iterations_per_call"],
+                                                    info["equal_to_oracle"], info["n_rest"], info["e_rest"],
+                                                    f_scale, w_scale), "",
+         "| kernel | dispatches | avg us | FETCH_SIZE avg KB | WRITE_SIZE avg KB |", "|---|---:|---:|---:|---:|"]
+    for k in sorted(durs, key=lambda k: -sum(durs[k])):
+        if not k.startswith("k_cc"):
+            continue
+        L.append("| %s | %d | %.2f | %.1f | %.1f |" % (k, len(durs[k]), np.mean(durs[k]),
+                                                      np.mean(fe.get(k, [0.0])), np.mean(wr.get(k, [0.0]))))
+    us = float(np.mean(durs["k_cc_pull"]))
+    alg = info["bytes_per_iteration"]
+    traffic = (np.mean(fe["k_cc_pull"]) * f_scale + np.mean(wr["k_cc_pull"]) * w_scale) * 1024
+    L += ["", "k_cc_pull per launch: algorithmic %.1f MB; rocprofv3 mean %.1f us -> %.0f GB/s = **%.3f** of "
+          "8 TB/s; HBM traffic (scaled counters) %.1f MB, traffic / algorithmic = %.2f; the events of the bench "
+          "line: %.1f us per iteration." % (alg / 1e6, us, alg / (us * 1e-6) / 1e9,
+                                             alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, traffic / 1e6, traffic / alg,
+                                             info["mean_iteration_ms_events"] * 1e3)]
+    return "\n".join(L)
