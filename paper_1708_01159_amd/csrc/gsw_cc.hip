@@ -61,6 +61,7 @@ namespace {
 
 constexpr int kCcBlock = 256;
 constexpr int64_t kCcLane = 32;  // rows of at most this many arcs are walked by their own lane
+constexpr int kCcBatch = 8;      // arcs a lane keeps in flight (column loads, then label loads)
 constexpr int kCcGridMax = 2048;
 // counters, 16 words apart
 enum : int { kCtrCount = 0, kCtrArcs = 16, kCtrKey = 32, kCtrReached = 48, kCtrRoots = 64, kCcCtr = 80 };
@@ -85,6 +86,31 @@ __device__ __forceinline__ int32_t wave_min(int32_t x) {
   return x;
 }
 
+// Combines one value per thread over the workgroup (op: max, min or sum);
+// the result is valid in thread 0.  Reductions over all n vertices end with
+// one global atomic per workgroup: one per wave (8192 on one counter for a
+// launch of 2048 workgroups) serialise into tens of microseconds.
+template <class Op>
+__device__ __forceinline__ u64 cc_block_reduce(u64 x, Op op) {
+  __shared__ u64 part[kCcBlock / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x = op(x, __shfl_xor(x, off));
+  if (cc_lane() == 0) part[threadIdx.x >> 6] = x;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int w = 1; w < kCcBlock / 64; ++w) x = op(x, part[w]);
+  return x;
+}
+struct CcMax {
+  __device__ u64 operator()(u64 a, u64 b) const { return a > b ? a : b; }
+};
+struct CcMin {
+  __device__ u64 operator()(u64 a, u64 b) const { return a < b ? a : b; }
+};
+struct CcSum {
+  __device__ u64 operator()(u64 a, u64 b) const { return a + b; }
+};
+
 // Appends the lanes with `take` set to list (one atomic per wave); every
 // active lane of the wave calls it with the same control flow.
 __device__ __forceinline__ void cc_append(bool take, int32_t v, int32_t* list, u64* count) {
@@ -96,6 +122,52 @@ __device__ __forceinline__ void cc_append(bool take, int32_t v, int32_t* list, u
   if (lane == leader) pos = atomicAdd(count, (u64)__popcll(m));
   pos = __shfl(pos, leader);
   if (take) list[pos + (u64)__popcll(m & ((1ull << lane) - 1ull))] = v;
+}
+
+// Workgroup staging of list appends for loops whose trip count is uniform
+// over the workgroup: entries gather in LDS and go out with one global
+// atomic per kCcStage of them (appends to one counter serialise, about 11 ns
+// each, so one atomic per wave would cost more than the kernel's reads when
+// millions of vertices change).  Every thread calls cc_stage_add and
+// cc_stage_flush at the same points.
+constexpr int kCcStage = 2048;
+struct CcStage {
+  int32_t buf[kCcStage];
+  uint32_t n;
+  unsigned long long base;
+};
+
+__device__ __forceinline__ void cc_stage_init(CcStage& S) {
+  if (threadIdx.x == 0) S.n = 0u;
+  __syncthreads();
+}
+
+__device__ __forceinline__ void cc_stage_flush(CcStage& S, int32_t* list, u64* count) {
+  __syncthreads();
+  const uint32_t m = S.n;
+  if (m == 0u) return;  // uniform: every thread read the same S.n after the barrier
+  if (threadIdx.x == 0) S.base = atomicAdd(count, (u64)m);
+  __syncthreads();
+  const u64 b = S.base;
+  for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) list[b + i] = S.buf[i];
+  __syncthreads();
+  if (threadIdx.x == 0) S.n = 0u;
+  __syncthreads();
+}
+
+// Adds the threads with `take` set (at most one entry per thread per call);
+// flushes first when the buffer could overflow.
+__device__ __forceinline__ void cc_stage_add(CcStage& S, bool take, int32_t v, int32_t* list, u64* count) {
+  __syncthreads();
+  if (S.n + blockDim.x > (uint32_t)kCcStage) cc_stage_flush(S, list, count);
+  const u64 m = __ballot(take);
+  if (m == 0ull) return;
+  const int lane = cc_lane();
+  const int leader = __ffsll((long long)m) - 1;
+  uint32_t pos = 0;
+  if (lane == leader) pos = atomicAdd(&S.n, (uint32_t)__popcll(m));
+  pos = (uint32_t)__shfl((int)pos, leader);
+  if (take) S.buf[pos + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = v;
 }
 
 __device__ __forceinline__ int64_t cc_degree(const int64_t* offs, const int64_t* roffs, int32_t v) {
@@ -114,12 +186,8 @@ __global__ void __launch_bounds__(kCcBlock) k_cc_argmax(const int64_t* __restric
     const u64 k = ((u64)d << 32) | (u64)(0x7fffffffu - (uint32_t)v);
     best = k > best ? k : best;
   }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const u64 o = __shfl_xor(best, off);
-    best = o > best ? o : best;
-  }
-  if (cc_lane() == 0) atomicMax(key, best);
+  best = cc_block_reduce(best, CcMax());
+  if (threadIdx.x == 0) atomicMax(key, best);
 }
 
 // Phase 1 result: the smallest reached id and the number of reached vertices.
@@ -131,13 +199,10 @@ __global__ void __launch_bounds__(kCcBlock) k_cc_reached(const int32_t* __restri
       lo = (u64)v < lo ? (u64)v : lo;
       ++cnt;
     }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const u64 o = __shfl_xor(lo, off);
-    lo = o < lo ? o : lo;
-  }
-  cnt = wave_sum(cnt);
-  if (cc_lane() == 0) {
+  lo = cc_block_reduce(lo, CcMin());
+  __syncthreads();  // the partials are reused by the second reduction
+  cnt = cc_block_reduce(cnt, CcSum());
+  if (threadIdx.x == 0) {
     if (lo < (u64)n) atomicMin(first, lo);
     if (cnt) atomicAdd(reached, cnt);
   }
@@ -151,6 +216,8 @@ __global__ void __launch_bounds__(kCcBlock) k_cc_seed(const int32_t* level, cons
                                                       const int64_t* __restrict__ offs,
                                                       const int64_t* __restrict__ roffs, int64_t n, int32_t* label,
                                                       int32_t* rest, u64* ctr) {
+  __shared__ CcStage S;
+  cc_stage_init(S);
   const int32_t gmin = level ? (int32_t)*first : 0;
   u64 arcs = 0ull;
   for (int64_t base = (int64_t)blockIdx.x * kCcBlock; base < n; base += (int64_t)gridDim.x * kCcBlock) {
@@ -165,10 +232,11 @@ __global__ void __launch_bounds__(kCcBlock) k_cc_seed(const int32_t* level, cons
         arcs += (u64)d;
       }
     }
-    cc_append(take, (int32_t)v, rest, ctr + kCtrCount);
+    cc_stage_add(S, take, (int32_t)v, rest, ctr + kCtrCount);
   }
-  arcs = wave_sum(arcs);
-  if (cc_lane() == 0 && arcs) atomicAdd(ctr + kCtrArcs, arcs);
+  cc_stage_flush(S, rest, ctr + kCtrCount);
+  arcs = cc_block_reduce(arcs, CcSum());
+  if (threadIdx.x == 0 && arcs) atomicAdd(ctr + kCtrArcs, arcs);
 }
 
 // Lowers v's label to lu; true when it fell and v was not yet on the next
@@ -209,15 +277,19 @@ __global__ void __launch_bounds__(kCcBlock) k_cc_push(const int32_t* __restrict_
         end = ro[u + 1];
       }
       const bool own = end - beg <= kCcLane;
-      for (int64_t k = 0; __any(own && beg + k < end); ++k) {
-        bool take = false;
-        int32_t v = 0;
-        if (own && beg + k < end) {
-          v = co[beg + k];
-          take = cc_lower(label, mark, v, lu);
-          if (take) arcs += (u64)cc_degree(offs, roffs, v);
+      for (int64_t k = 0; __any(own && beg + k < end); k += kCcBatch) {
+        int32_t v[kCcBatch], lw[kCcBatch];
+#pragma unroll
+        for (int q = 0; q < kCcBatch; ++q) v[q] = own && beg + k + q < end ? co[beg + k + q] : -1;
+#pragma unroll
+        for (int q = 0; q < kCcBatch; ++q) lw[q] = v[q] >= 0 ? label[v[q]] : 0x7fffffff;
+#pragma unroll
+        for (int q = 0; q < kCcBatch; ++q) {
+          // the plain read filters: only arcs that would lower a label reach the atomics
+          const bool take = v[q] >= 0 && lu < lw[q] && cc_lower(label, mark, v[q], lu);
+          if (take) arcs += (u64)cc_degree(offs, roffs, v[q]);
+          cc_append(take, v[q], qout, ctr + kCtrCount);
         }
-        cc_append(take, v, qout, ctr + kCtrCount);
       }
       u64 longs = __ballot(!own);
       while (longs != 0ull) {
@@ -239,8 +311,8 @@ __global__ void __launch_bounds__(kCcBlock) k_cc_push(const int32_t* __restrict_
       }
     }
   }
-  arcs = wave_sum(arcs);
-  if (lane == 0 && arcs) atomicAdd(ctr + kCtrArcs, arcs);
+  arcs = cc_block_reduce(arcs, CcSum());
+  if (threadIdx.x == 0 && arcs) atomicAdd(ctr + kCtrArcs, arcs);
 }
 
 // Pull: every remaining vertex takes the smallest label among itself and its
@@ -251,6 +323,8 @@ __global__ void __launch_bounds__(kCcBlock) k_cc_pull(const int32_t* __restrict_
                                                       const int32_t* __restrict__ cols,
                                                       const int64_t* __restrict__ roffs,
                                                       const int32_t* __restrict__ rcols, int32_t* qout, u64* ctr) {
+  __shared__ CcStage S;
+  cc_stage_init(S);
   const int lane = cc_lane();
   u64 arcs = 0ull;
   const int nrows = roffs ? 2 : 1;
@@ -269,15 +343,30 @@ __global__ void __launch_bounds__(kCcBlock) k_cc_pull(const int32_t* __restrict_
         end = ro[v + 1];
       }
       const bool own = end - beg <= kCcLane;
-      for (int64_t k = 0; __any(own && beg + k < end); ++k)
-        if (own && beg + k < end) m = min(m, label[co[beg + k]]);
+      for (int64_t k = 0; __any(own && beg + k < end); k += kCcBatch) {
+        if (own && beg + k < end) {
+          int32_t u[kCcBatch];
+#pragma unroll
+          for (int q = 0; q < kCcBatch; ++q) u[q] = beg + k + q < end ? co[beg + k + q] : -1;
+#pragma unroll
+          for (int q = 0; q < kCcBatch; ++q)
+            if (u[q] >= 0) m = min(m, label[u[q]]);
+        }
+      }
       u64 longs = __ballot(!own);
       while (longs != 0ull) {
         const int owner = __ffsll((long long)longs) - 1;
         longs &= longs - 1ull;
         const int64_t lo = __shfl(beg, owner), hi = __shfl(end, owner);
         int32_t w = 0x7fffffff;
-        for (int64_t c = lo + lane; c < hi; c += 64) w = min(w, label[co[c]]);
+        for (int64_t c = lo + lane; c < hi; c += 64 * 4) {
+          int32_t u[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) u[q] = c + 64 * q < hi ? co[c + 64 * q] : -1;
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (u[q] >= 0) w = min(w, label[u[q]]);
+        }
         w = wave_min(w);
         if (lane == owner) m = min(m, w);
       }
@@ -287,10 +376,11 @@ __global__ void __launch_bounds__(kCcBlock) k_cc_pull(const int32_t* __restrict_
       label[v] = m;
       arcs += (u64)cc_degree(offs, roffs, v);
     }
-    cc_append(take, v, qout, ctr + kCtrCount);
+    cc_stage_add(S, take, v, qout, ctr + kCtrCount);
   }
-  arcs = wave_sum(arcs);
-  if (lane == 0 && arcs) atomicAdd(ctr + kCtrArcs, arcs);
+  cc_stage_flush(S, qout, ctr + kCtrCount);
+  arcs = cc_block_reduce(arcs, CcSum());
+  if (threadIdx.x == 0 && arcs) atomicAdd(ctr + kCtrArcs, arcs);
 }
 
 // Clears the list's bits of the mark bitmap (the only bits set after a push).
@@ -306,8 +396,8 @@ __global__ void __launch_bounds__(kCcBlock) k_cc_roots(const int32_t* __restrict
   u64 c = 0ull;
   for (int64_t v = (int64_t)blockIdx.x * kCcBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kCcBlock)
     c += label[v] == (int32_t)v ? 1ull : 0ull;
-  c = wave_sum(c);
-  if (cc_lane() == 0 && c) atomicAdd(roots, c);
+  c = cc_block_reduce(c, CcSum());
+  if (threadIdx.x == 0 && c) atomicAdd(roots, c);
 }
 
 __global__ void k_cc_zero(u64* ctr, int words) {
