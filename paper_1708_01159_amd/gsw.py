@@ -523,7 +523,8 @@ def components(graph: Graph, policy: str = "switch", bfs_first: bool = True, tre
     """Weakly connected components (gsw_cc).  Returns ``(labels, n_components,
     trace)``: ``labels`` int32 ``[n]``, the smallest vertex id of each
     vertex's component (numpy, or a torch CUDA tensor when ``device``;
-    ``out`` may supply it), ``trace`` a list of dicts, one per iteration.
+    ``out`` may supply it, a CUDA tensor when ``device``, else a numpy
+    array), ``trace`` a list of dicts, one per iteration.
     ``policy``: "switch" (push or pull per iteration), "push" or "pull";
     ``tree`` picks the kernels of the phase-1 BFS (None: the default kernel)."""
     pol = {"switch": CC_SWITCH, "push": CC_PUSH, "pull": CC_PULL}[policy]
@@ -545,6 +546,9 @@ def components(graph: Graph, policy: str = "switch", bfs_first: bool = True, tre
             lab = torch.empty(n, dtype=torch.int32, device="cuda")
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
+    elif out is not None:
+        check_out(out, "int32", n, False, "components labels")
+        lab = out
     else:
         lab = np.empty(n, dtype=np.int32)
     o.device_ptrs = int(bool(device))

@@ -350,3 +350,16 @@ def test_components_abi_constants_layout_and_null_arguments():
     nc = ctypes.c_int64(-1)
     st = gsw.lib().gsw_cc(None, lab.ctypes.data, ctypes.byref(nc), None, 0, None, ctypes.byref(o))
     assert st == gsw.EINVAL and nc.value == 0 and "null graph" in gsw.last_error()
+
+
+def test_components_binding_checks_outputs_before_the_call():
+    import torch
+
+    with pytest.raises(ValueError, match="CUDA tensor"):
+        gsw.components(_FakeGraph(), device=True, out=torch.zeros(10, dtype=torch.int32))
+    with pytest.raises(ValueError, match="need"):
+        gsw.components(_FakeGraph(), out=np.zeros(9, dtype=np.int32))
+    with pytest.raises(ValueError, match="host output"):
+        gsw.components(_FakeGraph(), out=torch.zeros(10, dtype=torch.int32))
+    with pytest.raises(KeyError):
+        gsw.components(_FakeGraph(), policy="sideways")
