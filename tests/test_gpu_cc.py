@@ -130,6 +130,9 @@ def test_device_output_and_repeat_calls():
         assert nc == count and np.array_equal(out.cpu().numpy(), want)
     with pytest.raises(ValueError):
         gsw.components(G, device=True, out=torch.empty(g.n - 1, dtype=torch.int32, device="cuda"))
+    host = np.full(g.n, 7, dtype=np.int32)
+    lab, nc, _ = gsw.components(G, out=host, tree=trees.load_default())
+    assert lab is host and nc == count and np.array_equal(host, want)
 
 
 def test_full_size_rmat22():
