@@ -146,7 +146,7 @@ int32_t specialise_tree(const gsw_graph* g, const gsw_tree* t, const TreeBuf& bu
 namespace {
 
 // Device copy of the specialised tree, uploaded once per (workspace, tree).
-gsw_status ensure_tree(gsw_graph* g, const gsw_tree* t) {
+gsw_status ensure_tree(gsw_graph* g, const gsw_tree* t, hipStream_t s) {
   Workspace& w = g->ws;
   if (w.tree_id == t->id) return GSW_OK;
   if (t->n_nodes > kMaxTreeNodes) return fail(GSW_EINVAL, "tree of %d nodes: at most %d", t->n_nodes, kMaxTreeNodes);
@@ -168,15 +168,18 @@ gsw_status ensure_tree(gsw_graph* g, const gsw_tree* t) {
     }
     w.tree_cap = m;
   }
-  GSW_HIP(hipMemcpy(w.d_tree, nodes.data(), (size_t)m * sizeof(unsigned long long), hipMemcpyHostToDevice));
-  GSW_HIP(hipMemcpy(w.d_thr, thr.data(), (size_t)m * sizeof(int32_t), hipMemcpyHostToDevice));
+  // on the search's stream (ordered before its launches), waited for before
+  // the host buffers go
+  GSW_HIP(hipMemcpyAsync(w.d_tree, nodes.data(), (size_t)m * sizeof(unsigned long long), hipMemcpyHostToDevice, s));
+  GSW_HIP(hipMemcpyAsync(w.d_thr, thr.data(), (size_t)m * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  GSW_HIP(hipStreamSynchronize(s));
   w.tree_nodes = m;
   w.tree_id = t->id;
   return GSW_OK;
 }
 
 // Device copy of a schedule; re-uploaded only when its contents change.
-gsw_status ensure_schedule(gsw_graph* g, const int32_t* sched, int32_t len) {
+gsw_status ensure_schedule(gsw_graph* g, const int32_t* sched, int32_t len, hipStream_t s) {
   Workspace& w = g->ws;
   std::vector<int32_t>* cached = &w.sched_host;
   if (w.d_sched && (int32_t)cached->size() == len && std::equal(cached->begin(), cached->end(), sched))
@@ -191,7 +194,8 @@ gsw_status ensure_schedule(gsw_graph* g, const int32_t* sched, int32_t len) {
     }
     w.sched_cap = len;
   }
-  GSW_HIP(hipMemcpy(w.d_sched, sched, (size_t)len * sizeof(int32_t), hipMemcpyHostToDevice));
+  GSW_HIP(hipMemcpyAsync(w.d_sched, sched, (size_t)len * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  GSW_HIP(hipStreamSynchronize(s));
   cached->assign(sched, sched + len);
   return GSW_OK;
 }
@@ -247,6 +251,7 @@ BfsBase make_base(const gsw_graph* g, const Workspace& w, int32_t* lv, int32_t* 
   b.count_arcs = count_arcs ? 1 : 0;
   const double dm = g->deg_stats[4];
   b.deg_max = dm >= 2147483647.0 ? 2147483647 : (int32_t)dm;
+  b.head_ranked = w.head_ranked ? 1 : 0;
   b.solo = 0;
   return b;
 }
@@ -423,9 +428,9 @@ gsw_status bfs_sources(gsw_graph* g, const gsw_bfs_opts* o, const int32_t* sourc
   GSW_TRY(ensure_workspace(g));
   if (may_pick(o, GSW_K_EDGE_SCAN)) GSW_TRY(ensure_origin(g));
   if (may_pick(o, GSW_K_REV_EDGE_SCAN)) GSW_TRY(ensure_rorigin(g));
-  if (o->policy == GSW_POLICY_TREE) GSW_TRY(ensure_tree(g, o->tree));
-  if (o->policy == GSW_POLICY_SCHEDULE) GSW_TRY(ensure_schedule(g, o->schedule, o->schedule_len));
   const hipStream_t s = pick_stream(g, o->stream);
+  if (o->policy == GSW_POLICY_TREE) GSW_TRY(ensure_tree(g, o->tree, s));
+  if (o->policy == GSW_POLICY_SCHEDULE) GSW_TRY(ensure_schedule(g, o->schedule, o->schedule_len, s));
   const bool has_origin = g->origin != nullptr || g->nnz == 0;
   const bool has_rorigin = g->rorigin != nullptr || g->nnz == 0;
   const Policy pol{o, has_origin, has_rorigin};

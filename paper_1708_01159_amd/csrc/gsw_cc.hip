@@ -443,9 +443,9 @@ gsw_status ensure_cc(gsw_graph* g) {
     }
     w->bytes += it.bytes;
   }
+  // (the mark bitmap is cleared by every call, on its stream)
   if (hipHostMalloc((void**)&w->h_ctr, kCcCtr * sizeof(u64), hipHostMallocDefault) != hipSuccess ||
-      hipEventCreate(&w->ev[0]) != hipSuccess || hipEventCreate(&w->ev[1]) != hipSuccess ||
-      hipMemset(w->mark, 0, (size_t)cdiv(g->n, 64) * sizeof(u64)) != hipSuccess) {
+      hipEventCreate(&w->ev[0]) != hipSuccess || hipEventCreate(&w->ev[1]) != hipSuccess) {
     (void)hipGetLastError();
     cc_free(w);
     return fail(GSW_EHIP, "connected-components staging memory or events");
@@ -529,7 +529,7 @@ gsw_status gsw_cc(const gsw_graph* cg, int32_t* labels, int64_t* n_components, g
     return ms;
   };
 
-  // a call that failed half-way may have left marks behind
+  // fresh memory, or a call that failed half-way, may hold marks
   GSW_HIP(hipMemsetAsync(w.mark, 0, (size_t)cdiv(n, 64) * sizeof(u64), s));
   zero();
   const bool bfs = o->bfs_first && g->symmetric && g->nnz > 0;

@@ -285,10 +285,11 @@ gsw_status ensure_workspace(gsw_graph* g) {
   if (!w.d_ring) GSW_HIP(hipHostGetDevicePointer((void**)&w.d_ring, w.ring, 0));
   if (!w.head_built) {
     if (n > 0) {
-      GSW_TRY(launch_build_head(g, w.head, g->stream));
+      GSW_TRY(launch_build_head(g, w.head, true, g->stream));
       GSW_HIP(hipStreamSynchronize(g->stream));
     }
     w.head_built = true;
+    w.head_ranked = true;
   }
   if (!g->iso) {
     const size_t ib = (size_t)w.nw * sizeof(unsigned long long);
@@ -471,6 +472,9 @@ gsw_status gsw_graph_create_host(int64_t n, int64_t nnz, const int64_t* offs, co
       (nnz > 0 && hipMemcpy((void*)g->cols, cols, (size_t)nnz * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess))
     st = fail(GSW_EHIP, "copying the CSR to the device failed");
   if (st == GSW_OK) st = set_in_arcs(g, t_offs, t_cols);
+  // the uploads ran on the null stream, which the library's non-blocking
+  // streams do not wait for: they must have landed before any search reads them
+  if (st == GSW_OK && hipStreamSynchronize(nullptr) != hipSuccess) st = fail(GSW_EHIP, "CSR upload");
   if (st == GSW_OK && (flags & GSW_WITH_ORIGIN)) st = ensure_origin(g);
   if (st == GSW_OK && (flags & GSW_WITH_ORIGIN)) st = ensure_rorigin(g);
   if (st != GSW_OK) {
@@ -514,6 +518,7 @@ gsw_status gsw_graph_create_device(int64_t n, int64_t nnz, const int64_t* d_offs
   g->cols = d_cols;
   g->owns_csr = false;
   st = set_in_arcs(g, t_offs, t_cols);
+  if (st == GSW_OK && hipStreamSynchronize(nullptr) != hipSuccess) st = fail(GSW_EHIP, "transpose upload");
   if (st == GSW_OK && (flags & GSW_WITH_ORIGIN)) st = ensure_origin(g);
   if (st == GSW_OK && (flags & GSW_WITH_ORIGIN)) st = ensure_rorigin(g);
   if (st != GSW_OK) {

@@ -83,12 +83,18 @@ constexpr int kCtrSlot = kQueueBins * kCtrStride;  // words per level in the cou
 // never treated as unvisited.
 struct BfsCtl;
 
-// Bottom-up probes start from a dense copy of the first kHeadArcs in-arcs of
-// every vertex ([n][kHeadArcs], -1 past the row's end): a wave's unvisited
+// Bottom-up probes start from a dense copy of kHeadArcs in-arcs of every
+// vertex ([n][kHeadArcs], -1 past the row's end): a wave's unvisited
 // vertices read theirs as consecutive 16-byte records instead of one
 // scattered cache line per row, and only rows still unresolved after them
-// are read in the CSR.
+// are read in the CSR.  The single-source workspace ranks them: the
+// kHeadArcs in-neighbours of largest out-degree among the row's first
+// kHeadScan arcs (a vertex of larger degree is in a large frontier sooner),
+// so most vertices of a large bottom-up level resolve in the head; rows that
+// do not are then probed from their start.  The no-allocation path, which
+// rebuilds the head on every call, copies the row's first kHeadArcs arcs.
 constexpr int kHeadArcs = 4;
+constexpr int kHeadScan = 256;
 
 // Per-level arc counters (gsw_bfs_opts.count_arcs): a ring of 4 levels of
 // kQueueBins 64-bit counters, kArcStride words apart.
@@ -131,6 +137,7 @@ struct Workspace {
   double tick_ms = 0.0;                  // milliseconds per wall-clock tick
   size_t bytes = 0;
   bool head_built = false;               // head holds the graph's rows
+  bool head_ranked = false;              // head holds ranked in-arcs, not the first ones
   bool ready = false;                    // every buffer allocated and built
   int64_t ring_used = -1;                // ring slots the last search may have written (-1: all)
 };
@@ -256,7 +263,7 @@ struct BfsBase {
   int32_t count_arcs;              // accumulate the next frontier's out-degrees
   int32_t solo;                    // levels one single-workgroup launch may run (0: such launches off)
   int32_t deg_max;                 // largest out-degree (clamped to 2^31 - 1)
-  int32_t pad;
+  int32_t head_ranked;             // head holds ranked in-arcs (bottom-up rows are then probed from their start)
 };
 
 // Single-workgroup multi-level launches (k_level_solo): while the frontier
@@ -351,7 +358,8 @@ gsw_status launch_isolated(const gsw_graph* g, unsigned long long* iso, hipStrea
 gsw_status launch_canonical_parents(const gsw_graph* g, const int32_t* level, int32_t* parent,
                                     hipStream_t s);
 gsw_status launch_build_origin(const int64_t* offs, int64_t n, int32_t* origin, hipStream_t s);
-gsw_status launch_build_head(const gsw_graph* g, int32_t* head, hipStream_t s);
+// ranked: the kHeadArcs in-neighbours of largest out-degree (see kHeadArcs), else the first ones.
+gsw_status launch_build_head(const gsw_graph* g, int32_t* head, bool ranked, hipStream_t s);
 
 // ----- pieces of the single-source level loop (gsw_bfs.cpp)
 // A level's record, decoded.

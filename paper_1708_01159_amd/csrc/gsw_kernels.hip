@@ -67,7 +67,8 @@ struct Args {
   const int64_t* __restrict__ roffs;   // in-arcs (the same arrays as offs/cols when symmetric)
   const int32_t* __restrict__ rcols;
   const int32_t* __restrict__ rorigin;
-  const int32_t* __restrict__ head;  // first kHeadArcs in-arcs of every vertex, -1 padded
+  const int32_t* __restrict__ head;  // kHeadArcs in-arcs of every vertex, -1 padded
+  int32_t head_ranked;               // 1: ranked, not the row's first arcs
   int32_t* __restrict__ level;
   int32_t* __restrict__ parent;
   u64* vis;
@@ -106,6 +107,7 @@ __host__ __device__ inline Args make_args(const BfsBase& b, int32_t j, int32_t d
   a.rcols = b.rcols;
   a.rorigin = b.rorigin;
   a.head = b.head;
+  a.head_ranked = b.head_ranked;
   a.level = b.level;
   a.parent = b.parent;
   a.vis = b.vis;
@@ -1236,7 +1238,7 @@ constexpr int64_t kPullLane = 64;
 __device__ __forceinline__ int32_t pull_row_rest(const Args& a, bool mine, int32_t par, int64_t beg, int64_t end) {
   const int lane = lane_id();
   const int64_t lim = end - beg < kPullLane ? end - beg : kPullLane;
-  for (int64_t off = kHeadArcs; __any(mine && par < 0 && off < lim); off += kPullEager) {
+  for (int64_t off = a.head_ranked ? 0 : kHeadArcs; __any(mine && par < 0 && off < lim); off += kPullEager) {
     if (mine && par < 0 && off < lim) {
       int32_t u[kPullEager];
       u64 fw[kPullEager];
@@ -1900,6 +1902,37 @@ __global__ void __launch_bounds__(kBlock) k_build_head(const int64_t* __restrict
   }
 }
 
+// The ranked head: per vertex (rows of in-arcs), the four in-neighbours of
+// largest out-degree among the row's first kHeadScan arcs, in decreasing
+// degree (an earlier arc first among equal degrees), -1 padded.
+__global__ void __launch_bounds__(kBlock) k_build_head_ranked(const int64_t* __restrict__ roffs,
+                                                              const int32_t* __restrict__ rcols,
+                                                              const int64_t* __restrict__ offs,
+                                                              int4* __restrict__ head, int64_t n) {
+  static_assert(kHeadArcs == 4, "one int4 record per row");
+  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
+    const int64_t beg = roffs[v], deg = roffs[v + 1] - beg;
+    const int64_t lim = deg < kHeadScan ? deg : kHeadScan;
+    int32_t id[4] = {-1, -1, -1, -1};
+    int64_t dg[4] = {-1, -1, -1, -1};
+    for (int64_t e = 0; e < lim; ++e) {
+      const int32_t u = rcols[beg + e];
+      const int64_t du = offs[u + 1] - offs[u];
+      if (du > dg[3]) {  // insertion into the four largest so far
+        int k = 3;
+        while (k > 0 && du > dg[k - 1]) {
+          dg[k] = dg[k - 1];
+          id[k] = id[k - 1];
+          --k;
+        }
+        dg[k] = du;
+        id[k] = u;
+      }
+    }
+    head[v] = make_int4(id[0], id[1], id[2], id[3]);
+  }
+}
+
 // parent[v] = the smallest u with an arc u -> v one level up (rows of the
 // in-arcs, any order).
 __global__ void __launch_bounds__(kBlock) k_canonical_parents(const int64_t* __restrict__ offs,
@@ -1975,9 +2008,13 @@ gsw_status launch_level_auto(const gsw_graph* g, const BfsBase& b, const BfsPoli
   return GSW_OK;
 }
 
-gsw_status launch_build_head(const gsw_graph* g, int32_t* head, hipStream_t s) {
-  hipLaunchKernelGGL(k_build_head, dim3(persistent_grid(cdiv(g->n, kBlock))), dim3(kBlock), 0, s, g->roffs,
-                     g->rcols, reinterpret_cast<int4*>(head), g->n);
+gsw_status launch_build_head(const gsw_graph* g, int32_t* head, bool ranked, hipStream_t s) {
+  if (ranked)
+    hipLaunchKernelGGL(k_build_head_ranked, dim3(persistent_grid(cdiv(g->n, kBlock))), dim3(kBlock), 0, s,
+                       g->roffs, g->rcols, g->offs, reinterpret_cast<int4*>(head), g->n);
+  else
+    hipLaunchKernelGGL(k_build_head, dim3(persistent_grid(cdiv(g->n, kBlock))), dim3(kBlock), 0, s, g->roffs,
+                       g->rcols, reinterpret_cast<int4*>(head), g->n);
   GSW_HIP(hipGetLastError());
   return GSW_OK;
 }

@@ -695,7 +695,11 @@ size_t stats_bytes() {
          (size_t)kMsStats * kMaxSlots * sizeof(u64) + sizeof(MsCtl);
 }
 
-gsw_status stats_alloc(LevelStats* st) {
+// The counters are cleared on `s`, the stream that will use them, and the
+// call waits for it: a clear on the null stream is asynchronous to the host
+// and unordered with a non-blocking stream, so under load it could land
+// after the traversal has started and zero its control block.
+gsw_status stats_alloc(LevelStats* st, hipStream_t s) {
   const size_t sb = (size_t)kMsStats * kMsStatStride * sizeof(u64);
   const size_t ab = (size_t)kMsStats * kMaxWords * sizeof(u64);
   const size_t eb = (size_t)kMsStats * kMaxSlots * sizeof(u64);
@@ -708,8 +712,9 @@ gsw_status stats_alloc(LevelStats* st) {
       return fail(GSW_ENOMEM, "hipMalloc(%zu) for level statistics failed", bs[k]);
     }
     st->bytes += bs[k];
-    GSW_HIP(hipMemset(*ps[k], 0, bs[k]));
+    GSW_HIP(hipMemsetAsync(*ps[k], 0, bs[k], s));
   }
+  GSW_HIP(hipStreamSynchronize(s));
   GSW_HIP(hipHostMalloc((void**)&st->h_ctl, sizeof(MsCtl), hipHostMallocDefault));
   std::memset(st->h_ctl, 0, sizeof(MsCtl));
   GSW_HIP(hipHostMalloc((void**)&st->ring, (size_t)kRing * kRecWords * sizeof(u64),
@@ -859,7 +864,7 @@ void ms_free(MsWorkspace* m) {
   delete m;
 }
 
-gsw_status ms_ensure(gsw_graph* g, int W) {
+gsw_status ms_ensure(gsw_graph* g, int W, hipStream_t s) {
   GSW_TRY(ensure_heavy(g));
   MsWorkspace*& m = g->ms;
   if (m && m->W == W) return GSW_OK;
@@ -889,7 +894,7 @@ gsw_status ms_ensure(gsw_graph* g, int W) {
     }
     m->bytes += it.bytes;
   }
-  if (st == GSW_OK) st = stats_alloc(&m->st);
+  if (st == GSW_OK) st = stats_alloc(&m->st, s);
   if (st != GSW_OK) {
     ms_free(m);
     m = nullptr;
@@ -1013,9 +1018,9 @@ gsw_status gsw_msbfs(const gsw_graph* cg, const int32_t* sources, int32_t n_sour
   std::lock_guard<std::mutex> lock(g->mu);
   GSW_HIP(hipSetDevice(g->device));
   const int W = (n_sources + 63) / 64;
-  GSW_TRY(ms_ensure(g, W));
-  MsWorkspace* m = g->ms;
   const hipStream_t s = pick_stream(g, o->stream);
+  GSW_TRY(ms_ensure(g, W, s));
+  MsWorkspace* m = g->ms;
   const int B = W * 64;  // level bytes per vertex in the workspace
   const int G = group_lanes(W);
   const int64_t nw = cdiv(g->n, 64);
@@ -1254,17 +1259,21 @@ gsw_status gsw_session_create(const gsw_graph* cg, int32_t max_slots, gsw_sessio
   }
   ss->fbm[0] = ss->bms;
   ss->fbm[1] = ss->bms + nw;
-  gsw_status st = stats_alloc(&ss->st);
+  gsw_status st = GSW_OK;
+  if (hipStreamCreateWithFlags(&ss->stream, hipStreamNonBlocking) != hipSuccess) {
+    ss->stream = nullptr;
+    st = fail(GSW_EHIP, "session stream");
+  }
+  if (st == GSW_OK) st = stats_alloc(&ss->st, ss->stream);
   if (st == GSW_OK) {
     ss->bytes += ss->st.bytes;
-    if (hipStreamCreateWithFlags(&ss->stream, hipStreamNonBlocking) != hipSuccess ||
-        hipHostMalloc((void**)&ss->h_masks, gsw_session::kStage * 2 * (size_t)kMaxWords * sizeof(u64),
+    if (hipHostMalloc((void**)&ss->h_masks, gsw_session::kStage * 2 * (size_t)kMaxWords * sizeof(u64),
                       hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&ss->h_seed, gsw_session::kStage * 2 * (size_t)max_slots * sizeof(int32_t),
                       hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&ss->h_start, gsw_session::kStage * (size_t)max_slots * sizeof(long long),
                       hipHostMallocDefault) != hipSuccess)
-      st = fail(GSW_EHIP, "session stream or pinned staging memory");
+      st = fail(GSW_EHIP, "session pinned staging memory");
   }
   if (st == GSW_OK) {
     const hipStream_t s = ss->stream;

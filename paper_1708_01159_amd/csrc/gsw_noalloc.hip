@@ -247,7 +247,7 @@ extern "C" gsw_status gsw_bfs_noalloc(const gsw_graph* cg, const int32_t* source
   scratch_workspace(ds->ptr, g->n, &w);
   unsigned long long* iso = reinterpret_cast<unsigned long long*>(ds->ptr + kLayout.iso);
   // graph-derived buffers, rebuilt every call (the array is shared by every graph)
-  GSW_TRY(launch_build_head(g, w.head, s));
+  GSW_TRY(launch_build_head(g, w.head, false, s));
   GSW_TRY(launch_isolated(g, iso, s));
   if (opts->policy == GSW_POLICY_TREE) {
     const TreeBuf buf{h_order, h_newid, h_stack, h_nodes, h_thr};

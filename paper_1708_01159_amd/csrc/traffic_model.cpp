@@ -66,3 +66,88 @@ extern "C" int64_t tm_level_counts(int64_t n, const int64_t* offs, const int32_t
   }
   return D;
 }
+
+// Counts for a bottom-up level whose probes start from a ranked head (the
+// library's single-source workspace): every unvisited vertex with arcs reads
+// its head record and probes its h(v) = min(4, deg) head neighbours -- the
+// four of largest degree among its first 256 arcs; when none of them is in
+// the frontier and the row has at least four arcs, it reads the row bounds
+// and probes the row from its start, up to the first frontier neighbour (all
+// of it when there is none).  Per depth d:
+//   fcost[d]  over the vertices at depth d: full(v) = h(v) + (deg >= 4 ? deg : 0),
+//             the probes of a vertex that finds nothing
+//   rowc[d]   vertices at depth d with deg >= 4 (a row read when nothing is found)
+//   fsave[d]  over the vertices v at depth d+1: full(v) - found(v), found(v) =
+//             h(v) on a head hit, else h(v) + (position of v's first neighbour
+//             at depth d in the row, from 1)
+//   rsave[d]  vertices at depth d+1 with deg >= 4 found by their head (no row read)
+// and in tot[0..1] the sums of full(v) and of [deg >= 4] over every vertex.
+extern "C" int64_t tm_ranked_counts(int64_t n, const int64_t* offs, const int32_t* cols, const int32_t* level,
+                                    int64_t cap, int64_t* fcost, int64_t* rowc, int64_t* fsave, int64_t* rsave,
+                                    int64_t* tot) {
+  int32_t dmax = -1;
+  for (int64_t v = 0; v < n; ++v) dmax = level[v] > dmax ? level[v] : dmax;
+  const int64_t D = (int64_t)dmax + 1;
+  if (D > cap) return -1;
+  for (int64_t d = 0; d < cap; ++d) fcost[d] = rowc[d] = fsave[d] = rsave[d] = 0;
+  int64_t tf = 0, tr = 0;
+#pragma omp parallel reduction(+ : tf, tr)
+  {
+    std::vector<int64_t> lf((std::size_t)D, 0), lr((std::size_t)D, 0), lfs((std::size_t)D, 0), lrs((std::size_t)D, 0);
+#pragma omp for schedule(dynamic, 4096)
+    for (int64_t v = 0; v < n; ++v) {
+      const int64_t deg = offs[v + 1] - offs[v];
+      const int64_t h = deg < 4 ? deg : 4;
+      const int64_t full = h + (deg >= 4 ? deg : 0);
+      tf += full;
+      tr += deg >= 4 ? 1 : 0;
+      const int32_t L = level[v];
+      if (L < 0) continue;
+      lf[(std::size_t)L] += full;
+      lr[(std::size_t)L] += deg >= 4 ? 1 : 0;
+      if (L < 1) continue;
+      // the ranked head: four largest degrees among the first 256 arcs, earlier arcs first on ties
+      int32_t id[4] = {-1, -1, -1, -1};
+      int64_t dg[4] = {-1, -1, -1, -1};
+      const int64_t lim = deg < 256 ? deg : 256;
+      for (int64_t e = 0; e < lim; ++e) {
+        const int32_t u = cols[offs[v] + e];
+        const int64_t du = offs[u + 1] - offs[u];
+        if (du > dg[3]) {
+          int k = 3;
+          while (k > 0 && du > dg[k - 1]) {
+            dg[k] = dg[k - 1];
+            id[k] = id[k - 1];
+            --k;
+          }
+          dg[k] = du;
+          id[k] = u;
+        }
+      }
+      bool hit = false;
+      for (int k = 0; k < 4; ++k) hit = hit || (id[k] >= 0 && level[id[k]] == L - 1);
+      int64_t found = h;
+      if (!hit) {
+        int64_t pos = deg;
+        for (int64_t e = offs[v]; e < offs[v + 1]; ++e)
+          if (level[cols[e]] == L - 1) {
+            pos = e - offs[v] + 1;
+            break;
+          }
+        found += deg >= 4 ? pos : 0;
+      }
+      lfs[(std::size_t)(L - 1)] += full - found;
+      lrs[(std::size_t)(L - 1)] += (hit && deg >= 4) ? 1 : 0;
+    }
+#pragma omp critical
+    for (int64_t d = 0; d < D; ++d) {
+      fcost[d] += lf[(std::size_t)d];
+      rowc[d] += lr[(std::size_t)d];
+      fsave[d] += lfs[(std::size_t)d];
+      rsave[d] += lrs[(std::size_t)d];
+    }
+  }
+  tot[0] = tf;
+  tot[1] = tr;
+  return D;
+}

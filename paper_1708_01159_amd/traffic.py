@@ -21,17 +21,23 @@ vertices, nw = ceil(n/64) bitmap words):
     rev_edge_scan:           + nnz*4 (destination of every arc) + nw*8 (its
                                visited word, read once per run of a word)
   pull_bitmap    + nw*8 (visited words) + sum over unvisited v of
-                 (16 row offsets + p_v*(4 column + 8 frontier word))
-                 + 16 per word holding a discovery (visited and next words),
-                 where p_v counts the neighbours read up to the first one in
-                 the frontier (all of them when none is).  Degree-0 vertices
-                 start visited (the search marks them at init), so they cost
-                 only their visited bit.
+                 (16 head record + q_v*(4 column + 8 frontier word)
+                  + 16 row offsets when v reads its row)
+                 + 16 per word holding a discovery (visited and next words).
+                 The probes start from the ranked head: v probes its
+                 min(4, deg) head neighbours (the four of largest degree
+                 among its first 256 arcs); when none is in the frontier and
+                 the row has at least four arcs, it reads its row bounds and
+                 probes the row from the start up to the first frontier
+                 neighbour (all of it when none is).  q_v counts those
+                 probes.  Degree-0 vertices start visited (the search marks
+                 them at init), so they cost only their visited bit.
 
 ``pull_bytes_literal`` is the pull formula exactly as the scope table writes
 it -- (n/64)*8*3 for the visited, frontier and next words, 16 + p_v*12 for
-every unvisited vertex including the degree-0 ones, and n_x*12 -- reported
-beside the model above.
+every unvisited vertex including the degree-0 ones, p_v the neighbours in row
+order up to the first one in the frontier, and n_x*12 -- reported beside the
+model above.
 """
 from __future__ import annotations
 
@@ -60,6 +66,9 @@ def _load():
         L.tm_level_counts.restype = ctypes.c_int64
         L.tm_level_counts.argtypes = [ctypes.c_int64] + [ctypes.c_void_p] * 3 + [ctypes.c_int64] + \
             [ctypes.c_void_p] * 4
+        L.tm_ranked_counts.restype = ctypes.c_int64
+        L.tm_ranked_counts.argtypes = [ctypes.c_int64] + [ctypes.c_void_p] * 3 + [ctypes.c_int64] + \
+            [ctypes.c_void_p] * 5
         _lib = L
     return _lib
 
@@ -87,9 +96,24 @@ class Counts:
         self.src_isolated = int(offs[source + 1] == offs[source])
         self.cum_nf = np.cumsum(self.nf)
         self.cum_ef = np.cumsum(self.ef)
+        self.fcost, self.rowc, self.fsave, self.rsave = (np.zeros(cap, dtype=np.int64) for _ in range(4))
+        tot = np.zeros(2, dtype=np.int64)
+        if _load().tm_ranked_counts(n, offs.ctypes.data, cols.ctypes.data, level.ctypes.data, cap,
+                                    self.fcost.ctypes.data, self.rowc.ctypes.data, self.fsave.ctypes.data,
+                                    self.rsave.ctypes.data, tot.ctypes.data) < 0:
+            raise ValueError("level array deeper than its own maximum")
+        self.full_total, self.row_total = int(tot[0]), int(tot[1])
+        self.cum_fcost = np.cumsum(self.fcost)
+        self.cum_rowc = np.cumsum(self.rowc)
 
     def at(self, a, d):
         return int(a[d]) if 0 <= d < a.shape[0] else 0
+
+    def ranked_terms(self, d: int):
+        """(probes, row reads) of a bottom-up level d with the ranked head."""
+        probes = self.full_total - self.at(self.cum_fcost, d) - self.at(self.fsave, d)
+        rows = self.row_total - self.at(self.cum_rowc, d) - self.at(self.rsave, d)
+        return probes, rows
 
     def pull_terms(self, d: int):
         """(probes, unvisited vertices with arcs, unvisited vertices) at level d."""
@@ -123,8 +147,9 @@ def level_bytes(kernel: int, c: Counts, d: int) -> int:
     n_f, e_f, n_x = c.at(c.nf, d), c.at(c.ef, d), c.at(c.nf, d + 1)
     b = c.nw * 8 + n_x * 12
     if k == PULL:
-        probes, unv_pos, _ = c.pull_terms(d)
-        return b + c.nw * 8 + unv_pos * 16 + probes * 12 + c.at(c.words, d + 1) * 16
+        _, unv_pos, _ = c.pull_terms(d)
+        probes, rows = c.ranked_terms(d)
+        return b + c.nw * 8 + unv_pos * 16 + rows * 16 + probes * 12 + c.at(c.words, d + 1) * 16
     b += e_f * 12 + n_x * 8
     if k in PUSH_FAMILY:
         return b + n_f * 20
@@ -173,3 +198,35 @@ def pull_probes_reference(offs, cols, level, d: int, skip_isolated: bool = True)
             first[1:] = hr[1:] != hr[:-1]
             probes[hr[first]] = hp[first] + 1
     return int(probes.sum()), int(unv.shape[0])
+
+
+def ranked_head(offs, cols, v: int):
+    """The head of v as the library's single-source workspace builds it: the
+    four neighbours of largest degree among the first 256 arcs, an earlier
+    arc first among equal degrees."""
+    deg = np.diff(np.asarray(offs, dtype=np.int64))
+    row = np.asarray(cols[offs[v]:offs[v] + min(256, int(deg[v]))], dtype=np.int64)
+    order = sorted(range(row.shape[0]), key=lambda e: (-int(deg[row[e]]), e))
+    return [int(row[e]) for e in order[:4]]
+
+
+def ranked_probes_reference(offs, cols, level, d: int):
+    """(probes, row reads) of a bottom-up level d with the ranked head, by
+    walking every unvisited vertex in Python (slow; the check of ``Counts``)."""
+    offs = np.asarray(offs, dtype=np.int64)
+    lv = np.asarray(level)
+    probes = rows = 0
+    for v in np.flatnonzero(((lv == -1) | (lv > d)) & (offs[1:] > offs[:-1])):
+        deg = int(offs[v + 1] - offs[v])
+        h = min(4, deg)
+        if any(lv[u] == d for u in ranked_head(offs, cols, int(v))):
+            probes += h
+            continue
+        nb = lv[cols[offs[v]:offs[v + 1]]]
+        hits = np.flatnonzero(nb == d)
+        if deg >= 4:
+            rows += 1
+            probes += h + (int(hits[0]) + 1 if hits.shape[0] else deg)
+        else:
+            probes += h
+    return probes, rows

@@ -263,10 +263,13 @@ def _probe_positions_graph():
 
 
 @pytest.mark.parametrize("name", ["probe_positions", "rmat14", "chunglu", "er_ragged", "grid", "disjoint"])
-def test_pull_parent_is_first_frontier_neighbour(name):
-    # rows are sorted, so a bottom-up level that stops at the first neighbour
-    # in the frontier (Section III-A) gives exactly the smallest neighbour one
-    # level up: with pull at every level, parents equal the canonical ones
+def test_pull_parent_is_a_frontier_neighbour(name):
+    # a bottom-up level probes a vertex's ranked head (its neighbours of
+    # largest degree) and then its row from the start, stopping at the first
+    # neighbour in the frontier (Section III-A): with pull at every level the
+    # levels are exact and every parent is a neighbour one level up, found
+    # wherever it sits in the row (the head, the lane's own probes or the
+    # wave's scan); canonical parents are the smallest such neighbour
     if name == "probe_positions":
         g = _probe_positions_graph()
         G = gsw.Graph.from_csr(g.offs, g.cols)
@@ -277,6 +280,9 @@ def test_pull_parent_is_first_frontier_neighbour(name):
     lv, pa, _ = gsw.bfs(G, srcs, policy="fixed", kernel=gsw.PULL_BITMAP)
     for i in range(len(srcs)):
         assert np.array_equal(lv[i], refs[i][0])
+        checks.check_bfs(g.offs, g.cols, int(srcs[i]), lv[i], pa[i])
+    lv, pa, _ = gsw.bfs(G, srcs, policy="fixed", kernel=gsw.PULL_BITMAP, canonical_parents=True)
+    for i in range(len(srcs)):
         assert np.array_equal(pa[i], _canonical(g, refs[i][0])), (name, int(srcs[i]))
 
 

@@ -275,3 +275,33 @@ def test_session_cancel_running_and_admitted():
         assert np.array_equal(res[k], oracle.levels(g.offs, g.cols, s)), s
     assert not sess.cancel(0)  # nothing admitted any more
     sess.close()
+
+
+def test_session_created_while_the_default_stream_is_busy():
+    """A session's device state is initialised on the session's own stream:
+    one created while the process's default stream still has work queued
+    (a bounded spin kernel) answers its queries exactly.  Initialising it on
+    the default stream, which the session's non-blocking stream does not wait
+    for, would let that work land after the session's first levels and reset
+    its level counter."""
+    import torch
+
+    g, G = resident("rmat12")
+    srcs = gg.pick_sources(g, 6, 11)
+    for rep in range(3):
+        torch.cuda._sleep(20_000_000)  # a few ms of spinning on the default stream
+        sess = gsw.Session(G, slots=8)
+        got, slot_src = {}, {}
+        for s in srcs:
+            slot_src[sess.admit(int(s))] = int(s)
+        for _ in range(100):
+            fin, run = sess.step(64)
+            for k in fin:
+                got[slot_src.pop(k)] = sess.fetch(k)
+            if not slot_src:
+                break
+        assert sorted(got) == sorted(int(s) for s in srcs)
+        for s, lv in got.items():
+            assert np.array_equal(lv, oracle.levels(g.offs, g.cols, s)), (rep, s)
+        sess.close()
+        torch.cuda.synchronize()

@@ -34,3 +34,23 @@ def test_isolated_source_and_literal_formula():
     assert traffic.pull_bytes_literal(c, 0) == 24 + 9 * 16 + 48
     # model: clear 8 + visited 8 + 3 * 16 + 4 * 12, no discoveries
     assert traffic.level_bytes(traffic.PULL, c, 0) == 8 + 8 + 48 + 48
+
+
+def test_ranked_pull_counts_match_walk():
+    """The model of the bottom-up level with the ranked head against a
+    direct walk: head probes, row reads and row probes per level."""
+    for g in (gg.rmat(10, 16, seed=3), gg.grid(30, 21, 0.05, seed=4), gg.chung_lu(3000, 2.1, 8.0, seed=5),
+              gg.from_edges(300, [0, 1, 2, 5], [1, 2, 3, 6])):
+        for s in gg.pick_sources(g, 2, 6):
+            lv = oracle.levels(g.offs, g.cols, int(s))
+            c = traffic.Counts(g.offs, g.cols, lv, int(s))
+            for d in range(int(lv.max()) + 1):
+                assert c.ranked_terms(d) == traffic.ranked_probes_reference(g.offs, g.cols, lv, d), (g.name, int(s), d)
+
+
+def test_ranked_head_order():
+    # vertex 0's neighbours 1..6 with degrees 1, 3, 2, 3, 1, 4: the head is 6, 2, 4, 3
+    src = [0] * 6 + [2, 2, 3, 4, 4, 6, 6, 6]
+    dst = [1, 2, 3, 4, 5, 6] + [7, 8, 9, 10, 11, 12, 13, 14]
+    g = gg.from_edges(15, src, dst)
+    assert traffic.ranked_head(g.offs, g.cols, 0) == [6, 2, 4, 3]
