@@ -208,6 +208,18 @@ gsw_status set_in_arcs(gsw_graph* g, const std::vector<int64_t>& t_offs, const s
 
 }  // namespace
 
+// Ranking the head pays on a skewed out-degree law (standard deviation above
+// the mean: R-MAT, Chung-Lu, power laws), where a few in-neighbours of large
+// degree enter the frontier long before the rest.  On a narrow law (a
+// Poisson or a mesh) the ranks are near ties, so the ranked head resolves
+// about as many rows as the first arcs do, and the rows it misses would
+// probe their head arcs a second time.
+bool head_ranking_pays(const gsw_graph* g) {
+  if (g->n <= 0 || g->nnz <= 0) return false;
+  const double mean = (double)g->nnz / (double)g->n;
+  return g->deg_stats[5] > mean;
+}
+
 hipStream_t pick_stream(gsw_graph* g, void* user_stream) {
   return user_stream ? (hipStream_t)user_stream : library_stream(g);
 }
@@ -284,12 +296,13 @@ gsw_status ensure_workspace(gsw_graph* g) {
   }
   if (!w.d_ring) GSW_HIP(hipHostGetDevicePointer((void**)&w.d_ring, w.ring, 0));
   if (!w.head_built) {
+    const bool ranked = head_ranking_pays(g);
     if (n > 0) {
-      GSW_TRY(launch_build_head(g, w.head, true, g->stream));
+      GSW_TRY(launch_build_head(g, w.head, ranked, g->stream));
       GSW_HIP(hipStreamSynchronize(g->stream));
     }
     w.head_built = true;
-    w.head_ranked = true;
+    w.head_ranked = ranked;
   }
   if (!g->iso) {
     const size_t ib = (size_t)w.nw * sizeof(unsigned long long);

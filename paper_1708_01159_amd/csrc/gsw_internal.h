@@ -87,12 +87,14 @@ struct BfsCtl;
 // vertex ([n][kHeadArcs], -1 past the row's end): a wave's unvisited
 // vertices read theirs as consecutive 16-byte records instead of one
 // scattered cache line per row, and only rows still unresolved after them
-// are read in the CSR.  The single-source workspace ranks them: the
+// are read in the CSR.  On a graph whose out-degrees are skewed
+// (head_ranking_pays) the single-source workspace ranks them: the
 // kHeadArcs in-neighbours of largest out-degree among the row's first
 // kHeadScan arcs (a vertex of larger degree is in a large frontier sooner),
 // so most vertices of a large bottom-up level resolve in the head; rows that
-// do not are then probed from their start.  The no-allocation path, which
-// rebuilds the head on every call, copies the row's first kHeadArcs arcs.
+// do not are then probed from their start.  Otherwise, and on the
+// no-allocation path, which rebuilds the head on every call, the head is the
+// row's first kHeadArcs arcs and the rest of the row is probed past them.
 constexpr int kHeadArcs = 4;
 constexpr int kHeadScan = 256;
 
@@ -359,6 +361,7 @@ gsw_status launch_canonical_parents(const gsw_graph* g, const int32_t* level, in
                                     hipStream_t s);
 gsw_status launch_build_origin(const int64_t* offs, int64_t n, int32_t* origin, hipStream_t s);
 // ranked: the kHeadArcs in-neighbours of largest out-degree (see kHeadArcs), else the first ones.
+bool head_ranking_pays(const gsw_graph* g);
 gsw_status launch_build_head(const gsw_graph* g, int32_t* head, bool ranked, hipStream_t s);
 
 // ----- pieces of the single-source level loop (gsw_bfs.cpp)

@@ -67,24 +67,26 @@ extern "C" int64_t tm_level_counts(int64_t n, const int64_t* offs, const int32_t
   return D;
 }
 
-// Counts for a bottom-up level whose probes start from a ranked head (the
-// library's single-source workspace): every unvisited vertex with arcs reads
-// its head record and probes its h(v) = min(4, deg) head neighbours -- the
-// four of largest degree among its first 256 arcs; when none of them is in
-// the frontier and the row has at least four arcs, it reads the row bounds
-// and probes the row from its start, up to the first frontier neighbour (all
-// of it when there is none).  Per depth d:
-//   fcost[d]  over the vertices at depth d: full(v) = h(v) + (deg >= 4 ? deg : 0),
+// Counts for a bottom-up level whose probes start from the dense head copy:
+// every unvisited vertex with arcs reads its head record and probes its
+// h(v) = min(4, deg) head neighbours -- ranked (the four of largest degree
+// among its first 256 arcs, the library's choice on a skewed degree law) or
+// else the row's first four arcs; when none of them is in the frontier and
+// the row has at least four arcs, it reads the row bounds and probes the row
+// from r0 (0 with a ranked head, 4 past the first arcs otherwise) up to the
+// first frontier neighbour (to the row's end when there is none).  Per depth d:
+//   fcost[d]  over the vertices at depth d: full(v) = h(v) + (deg >= 4 ? deg - r0 : 0),
 //             the probes of a vertex that finds nothing
 //   rowc[d]   vertices at depth d with deg >= 4 (a row read when nothing is found)
 //   fsave[d]  over the vertices v at depth d+1: full(v) - found(v), found(v) =
 //             h(v) on a head hit, else h(v) + (position of v's first neighbour
-//             at depth d in the row, from 1)
+//             at depth d in the row, from 1) - r0
 //   rsave[d]  vertices at depth d+1 with deg >= 4 found by their head (no row read)
 // and in tot[0..1] the sums of full(v) and of [deg >= 4] over every vertex.
-extern "C" int64_t tm_ranked_counts(int64_t n, const int64_t* offs, const int32_t* cols, const int32_t* level,
-                                    int64_t cap, int64_t* fcost, int64_t* rowc, int64_t* fsave, int64_t* rsave,
-                                    int64_t* tot) {
+extern "C" int64_t tm_head_counts(int64_t n, const int64_t* offs, const int32_t* cols, const int32_t* level,
+                                  int64_t cap, int64_t* fcost, int64_t* rowc, int64_t* fsave, int64_t* rsave,
+                                  int64_t* tot, int32_t ranked) {
+  const int64_t r0 = ranked ? 0 : 4;
   int32_t dmax = -1;
   for (int64_t v = 0; v < n; ++v) dmax = level[v] > dmax ? level[v] : dmax;
   const int64_t D = (int64_t)dmax + 1;
@@ -98,7 +100,7 @@ extern "C" int64_t tm_ranked_counts(int64_t n, const int64_t* offs, const int32_
     for (int64_t v = 0; v < n; ++v) {
       const int64_t deg = offs[v + 1] - offs[v];
       const int64_t h = deg < 4 ? deg : 4;
-      const int64_t full = h + (deg >= 4 ? deg : 0);
+      const int64_t full = h + (deg >= 4 ? deg - r0 : 0);
       tf += full;
       tr += deg >= 4 ? 1 : 0;
       const int32_t L = level[v];
@@ -110,7 +112,8 @@ extern "C" int64_t tm_ranked_counts(int64_t n, const int64_t* offs, const int32_
       int32_t id[4] = {-1, -1, -1, -1};
       int64_t dg[4] = {-1, -1, -1, -1};
       const int64_t lim = deg < 256 ? deg : 256;
-      for (int64_t e = 0; e < lim; ++e) {
+      for (int64_t k = 0; !ranked && k < h; ++k) id[k] = cols[offs[v] + k];
+      for (int64_t e = 0; ranked && e < lim; ++e) {
         const int32_t u = cols[offs[v] + e];
         const int64_t du = offs[u + 1] - offs[u];
         if (du > dg[3]) {
@@ -134,7 +137,7 @@ extern "C" int64_t tm_ranked_counts(int64_t n, const int64_t* offs, const int32_
             pos = e - offs[v] + 1;
             break;
           }
-        found += deg >= 4 ? pos : 0;
+        found += deg >= 4 ? pos - r0 : 0;
       }
       lfs[(std::size_t)(L - 1)] += full - found;
       lrs[(std::size_t)(L - 1)] += (hit && deg >= 4) ? 1 : 0;

@@ -24,13 +24,15 @@ vertices, nw = ceil(n/64) bitmap words):
                  (16 head record + q_v*(4 column + 8 frontier word)
                   + 16 row offsets when v reads its row)
                  + 16 per word holding a discovery (visited and next words).
-                 The probes start from the ranked head: v probes its
-                 min(4, deg) head neighbours (the four of largest degree
-                 among its first 256 arcs); when none is in the frontier and
-                 the row has at least four arcs, it reads its row bounds and
-                 probes the row from the start up to the first frontier
-                 neighbour (all of it when none is).  q_v counts those
-                 probes.  Degree-0 vertices start visited (the search marks
+                 The probes start from the head: v probes its min(4, deg)
+                 head neighbours; when none is in the frontier and the row
+                 has at least four arcs, it reads its row bounds and probes
+                 the row up to the first frontier neighbour (all of it when
+                 none is).  On a skewed degree law (standard deviation above
+                 the mean) the head is ranked -- the four neighbours of
+                 largest degree among the first 256 arcs -- and the row is
+                 probed from its start; otherwise the head is the first four
+                 arcs and the row is probed past them.  q_v counts the probes.  Degree-0 vertices start visited (the search marks
                  them at init), so they cost only their visited bit.
 
 ``pull_bytes_literal`` is the pull formula exactly as the scope table writes
@@ -66,9 +68,9 @@ def _load():
         L.tm_level_counts.restype = ctypes.c_int64
         L.tm_level_counts.argtypes = [ctypes.c_int64] + [ctypes.c_void_p] * 3 + [ctypes.c_int64] + \
             [ctypes.c_void_p] * 4
-        L.tm_ranked_counts.restype = ctypes.c_int64
-        L.tm_ranked_counts.argtypes = [ctypes.c_int64] + [ctypes.c_void_p] * 3 + [ctypes.c_int64] + \
-            [ctypes.c_void_p] * 5
+        L.tm_head_counts.restype = ctypes.c_int64
+        L.tm_head_counts.argtypes = [ctypes.c_int64] + [ctypes.c_void_p] * 3 + [ctypes.c_int64] + \
+            [ctypes.c_void_p] * 5 + [ctypes.c_int32]
         _lib = L
     return _lib
 
@@ -76,8 +78,9 @@ def _load():
 class Counts:
     """Per-depth counts of one source's BFS (see ``csrc/traffic_model.cpp``)."""
 
-    def __init__(self, offs, cols, level, source: int):
+    def __init__(self, offs, cols, level, source: int, ranked=None):
         offs = np.ascontiguousarray(offs, dtype=np.int64)
+        self.ranked = head_is_ranked(offs) if ranked is None else bool(ranked)
         cols = np.ascontiguousarray(cols, dtype=np.int32)
         level = np.ascontiguousarray(level, dtype=np.int32)
         n = level.shape[0]
@@ -98,9 +101,9 @@ class Counts:
         self.cum_ef = np.cumsum(self.ef)
         self.fcost, self.rowc, self.fsave, self.rsave = (np.zeros(cap, dtype=np.int64) for _ in range(4))
         tot = np.zeros(2, dtype=np.int64)
-        if _load().tm_ranked_counts(n, offs.ctypes.data, cols.ctypes.data, level.ctypes.data, cap,
-                                    self.fcost.ctypes.data, self.rowc.ctypes.data, self.fsave.ctypes.data,
-                                    self.rsave.ctypes.data, tot.ctypes.data) < 0:
+        if _load().tm_head_counts(n, offs.ctypes.data, cols.ctypes.data, level.ctypes.data, cap,
+                                  self.fcost.ctypes.data, self.rowc.ctypes.data, self.fsave.ctypes.data,
+                                  self.rsave.ctypes.data, tot.ctypes.data, int(self.ranked)) < 0:
             raise ValueError("level array deeper than its own maximum")
         self.full_total, self.row_total = int(tot[0]), int(tot[1])
         self.cum_fcost = np.cumsum(self.fcost)
@@ -109,8 +112,9 @@ class Counts:
     def at(self, a, d):
         return int(a[d]) if 0 <= d < a.shape[0] else 0
 
-    def ranked_terms(self, d: int):
-        """(probes, row reads) of a bottom-up level d with the ranked head."""
+    def head_terms(self, d: int):
+        """(probes, row reads) of a bottom-up level d starting from the head
+        (ranked or the first arcs, as ``self.ranked`` says)."""
         probes = self.full_total - self.at(self.cum_fcost, d) - self.at(self.fsave, d)
         rows = self.row_total - self.at(self.cum_rowc, d) - self.at(self.rsave, d)
         return probes, rows
@@ -121,6 +125,15 @@ class Counts:
         reached = self.at(self.cum_nf, d)
         unv_pos = self.n_pos - (reached - self.src_isolated)
         return probes, unv_pos, self.n - reached
+
+
+def head_is_ranked(offs) -> bool:
+    """Whether the library ranks the head of this graph: its out-degree
+    standard deviation (population) is above the mean degree."""
+    deg = np.diff(np.asarray(offs, dtype=np.int64))
+    if deg.shape[0] == 0 or int(deg.sum()) == 0:
+        return False
+    return bool(deg.std() > deg.mean())
 
 
 def component_edges(offs, level) -> int:
@@ -148,7 +161,7 @@ def level_bytes(kernel: int, c: Counts, d: int) -> int:
     b = c.nw * 8 + n_x * 12
     if k == PULL:
         _, unv_pos, _ = c.pull_terms(d)
-        probes, rows = c.ranked_terms(d)
+        probes, rows = c.head_terms(d)
         return b + c.nw * 8 + unv_pos * 16 + rows * 16 + probes * 12 + c.at(c.words, d + 1) * 16
     b += e_f * 12 + n_x * 8
     if k in PUSH_FAMILY:
@@ -210,23 +223,26 @@ def ranked_head(offs, cols, v: int):
     return [int(row[e]) for e in order[:4]]
 
 
-def ranked_probes_reference(offs, cols, level, d: int):
-    """(probes, row reads) of a bottom-up level d with the ranked head, by
-    walking every unvisited vertex in Python (slow; the check of ``Counts``)."""
+def head_probes_reference(offs, cols, level, d: int, ranked: bool):
+    """(probes, row reads) of a bottom-up level d starting from the head
+    (ranked, or the row's first four arcs), by walking every unvisited
+    vertex in Python (slow; the check of ``Counts``)."""
     offs = np.asarray(offs, dtype=np.int64)
     lv = np.asarray(level)
+    r0 = 0 if ranked else 4
     probes = rows = 0
     for v in np.flatnonzero(((lv == -1) | (lv > d)) & (offs[1:] > offs[:-1])):
         deg = int(offs[v + 1] - offs[v])
         h = min(4, deg)
-        if any(lv[u] == d for u in ranked_head(offs, cols, int(v))):
+        head = ranked_head(offs, cols, int(v)) if ranked else [int(u) for u in cols[offs[v]:offs[v] + h]]
+        if any(lv[u] == d for u in head):
             probes += h
             continue
         nb = lv[cols[offs[v]:offs[v + 1]]]
         hits = np.flatnonzero(nb == d)
         if deg >= 4:
             rows += 1
-            probes += h + (int(hits[0]) + 1 if hits.shape[0] else deg)
+            probes += h + (int(hits[0]) + 1 if hits.shape[0] else deg) - r0
         else:
             probes += h
     return probes, rows

@@ -264,9 +264,11 @@ def _probe_positions_graph():
 
 @pytest.mark.parametrize("name", ["probe_positions", "rmat14", "chunglu", "er_ragged", "grid", "disjoint"])
 def test_pull_parent_is_a_frontier_neighbour(name):
-    # a bottom-up level probes a vertex's ranked head (its neighbours of
-    # largest degree) and then its row from the start, stopping at the first
-    # neighbour in the frontier (Section III-A): with pull at every level the
+    # a bottom-up level probes a vertex's head (its neighbours of largest
+    # degree on a skewed degree law -- rmat14, chunglu, disjoint and this
+    # graph -- else its first arcs: er_ragged, grid) and then its row,
+    # stopping at the first neighbour in the frontier (Section III-A): with
+    # pull at every level the
     # levels are exact and every parent is a neighbour one level up, found
     # wherever it sits in the row (the head, the lane's own probes or the
     # wave's scan); canonical parents are the smallest such neighbour

@@ -36,16 +36,32 @@ def test_isolated_source_and_literal_formula():
     assert traffic.level_bytes(traffic.PULL, c, 0) == 8 + 8 + 48 + 48
 
 
-def test_ranked_pull_counts_match_walk():
-    """The model of the bottom-up level with the ranked head against a
-    direct walk: head probes, row reads and row probes per level."""
+def test_head_pull_counts_match_walk():
+    """The model of the bottom-up level starting from the head, ranked and
+    not, against a direct walk: head probes, row reads and row probes per
+    level; without ranking a vertex probes max(p_v, h_v) arcs (the head is
+    probed whole), so never fewer than the row-order p_v."""
     for g in (gg.rmat(10, 16, seed=3), gg.grid(30, 21, 0.05, seed=4), gg.chung_lu(3000, 2.1, 8.0, seed=5),
-              gg.from_edges(300, [0, 1, 2, 5], [1, 2, 3, 6])):
+              gg.erdos_renyi(2000, 8000, seed=7), gg.from_edges(300, [0, 1, 2, 5], [1, 2, 3, 6])):
         for s in gg.pick_sources(g, 2, 6):
             lv = oracle.levels(g.offs, g.cols, int(s))
-            c = traffic.Counts(g.offs, g.cols, lv, int(s))
-            for d in range(int(lv.max()) + 1):
-                assert c.ranked_terms(d) == traffic.ranked_probes_reference(g.offs, g.cols, lv, d), (g.name, int(s), d)
+            for ranked in (True, False):
+                c = traffic.Counts(g.offs, g.cols, lv, int(s), ranked=ranked)
+                for d in range(int(lv.max()) + 1):
+                    want = traffic.head_probes_reference(g.offs, g.cols, lv, d, ranked)
+                    assert c.head_terms(d) == want, (g.name, int(s), d, ranked)
+                    if not ranked:
+                        assert want[0] >= traffic.pull_probes_reference(g.offs, g.cols, lv, d)[0]
+
+
+def test_head_ranking_rule():
+    """Ranked on skewed degree laws, not on narrow ones, as the library
+    decides from its degree statistics."""
+    assert traffic.head_is_ranked(gg.rmat(12, 16, seed=3).offs)
+    assert traffic.head_is_ranked(gg.chung_lu(5000, 2.1, 8.0, seed=5).offs)
+    assert not traffic.head_is_ranked(gg.erdos_renyi(5000, 20000, seed=6).offs)
+    assert not traffic.head_is_ranked(gg.grid(40, 31, 0.05, seed=4).offs)
+    assert not traffic.head_is_ranked(np.zeros(5, dtype=np.int64))
 
 
 def test_ranked_head_order():
