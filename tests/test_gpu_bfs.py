@@ -288,6 +288,46 @@ def test_pull_parent_is_a_frontier_neighbour(name):
         assert np.array_equal(pa[i], _canonical(g, refs[i][0])), (name, int(srcs[i]))
 
 
+def _pull_parents_expected(g, lv, ranked):
+    """The parent a bottom-up level gives each vertex of depth >= 1: the
+    first of its head neighbours one level up, in head order, else the first
+    such neighbour in row order.  A ranked head is the four neighbours of
+    largest degree among the row's first 256 arcs (an earlier arc first
+    among equals), else the head is the row's first four arcs."""
+    deg = np.diff(g.offs)
+    want = np.full(g.n, -1, dtype=np.int64)
+    for v in np.flatnonzero(lv >= 1):
+        row = g.cols[g.offs[v]:g.offs[v + 1]]
+        up = lv[row] == lv[v] - 1
+        if ranked:
+            scan = row[:256]
+            head = sorted(range(scan.shape[0]), key=lambda e: (-int(deg[scan[e]]), e))[:4]
+            hits = [int(scan[e]) for e in head if up[e]]
+            if hits:
+                want[v] = hits[0]
+                continue
+        want[v] = int(row[np.argmax(up)])
+    return want
+
+
+@pytest.mark.parametrize("name", ["rmat14", "chunglu", "star", "er_ragged", "grid"])
+def test_pull_parents_follow_the_head_rule(name):
+    # the library ranks the head exactly where the byte model does (out-degree
+    # standard deviation above the mean): with pull at every level every
+    # parent is the one the head the rule picks gives
+    from paper_1708_01159_amd import traffic
+
+    g, G, srcs, refs, comp = case(name)
+    ranked = traffic.head_is_ranked(g.offs)
+    assert ranked == (name in ("rmat14", "chunglu", "star"))
+    lv, pa, _ = gsw.bfs(G, srcs[:2], policy="fixed", kernel=gsw.PULL_BITMAP)
+    for i in range(min(2, len(srcs))):
+        assert np.array_equal(lv[i], refs[i][0])
+        want = _pull_parents_expected(g, lv[i], ranked)
+        m = lv[i] >= 1
+        assert np.array_equal(pa[i][m], want[m]), (name, int(srcs[i]))
+
+
 def test_device_pointers_and_torch_stream():
     import torch
 
