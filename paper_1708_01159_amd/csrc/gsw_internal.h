@@ -360,8 +360,9 @@ gsw_status launch_isolated(const gsw_graph* g, unsigned long long* iso, hipStrea
 gsw_status launch_canonical_parents(const gsw_graph* g, const int32_t* level, int32_t* parent,
                                     hipStream_t s);
 gsw_status launch_build_origin(const int64_t* offs, int64_t n, int32_t* origin, hipStream_t s);
-// ranked: the kHeadArcs in-neighbours of largest out-degree (see kHeadArcs), else the first ones.
+// Whether the single-source workspace ranks the head (out-degree standard deviation above the mean).
 bool head_ranking_pays(const gsw_graph* g);
+// ranked: the kHeadArcs in-neighbours of largest out-degree (see kHeadArcs), else the first ones.
 gsw_status launch_build_head(const gsw_graph* g, int32_t* head, bool ranked, hipStream_t s);
 
 // ----- pieces of the single-source level loop (gsw_bfs.cpp)
