@@ -3,7 +3,8 @@ R-MAT scale 22 with the shipped tree (8 of the 64 timed sources: levels
 bit-exact against the oracle, per-level counts against its histogram,
 parents through the invariants on two), every one of the 33 fixed kernels
 on one R-MAT 22 source, the batched search at scale 20 with 1024 sources
-(sampled rows), two sources of each structure-sweep graph, and served
+(sampled rows), two sources of each structure-sweep graph, the bottom-up
+parents of ER 2^22 (first-arcs head) exactly, and served
 queries on the two largest serving graphs (R-MAT 24 and the full 4096 x 4096
 grid, whose 8,190-level queries need int32 slots)."""
 import numpy as np
@@ -99,6 +100,39 @@ def test_sweep_graph_one_source(name):
         ref, _, hist, _ = oracle.bfs(g.offs, g.cols, int(s))
         assert np.array_equal(lv[0].cpu().numpy(), ref), (name, int(s))
         assert [t.n_frontier for t in r.rows()] == hist.tolist()
+    G.close()
+
+
+def first_up_neighbour(offs, cols, level):
+    """Per vertex of depth >= 1, its first neighbour in row order one level
+    up (-1 elsewhere), vectorised over the arcs."""
+    n = level.shape[0]
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(offs))
+    idx = np.flatnonzero((level[rows] >= 1) & (level[cols] == level[rows] - 1))
+    r = rows[idx]
+    first = np.ones(idx.shape[0], dtype=bool)
+    first[1:] = r[1:] != r[:-1]
+    want = np.full(n, -1, dtype=np.int64)
+    want[r[first]] = cols[idx[first]]
+    return want
+
+
+def test_er22_pull_parents_first_in_row_order():
+    """ER 2^22's degree law is narrow, so its bottom-up head is the rows'
+    first arcs and the probes go on in row order: with pull at every level
+    each parent is the first neighbour one level up in row order."""
+    from paper_1708_01159_amd import traffic
+
+    g = gg.workload("er22")
+    assert not traffic.head_is_ranked(g.offs)
+    G = gsw.Graph.from_csr(g.offs, g.cols, flags=gsw.ASSUME_SYMMETRIC | gsw.TRUSTED)
+    k, seed = gg.WORKLOAD_SOURCES["er22"]
+    s = int(gg.pick_sources(g, k, seed)[0])
+    ref = oracle.levels(g.offs, g.cols, s)
+    lv, pa, _ = gsw.bfs(G, [s], policy="fixed", kernel=gsw.PULL_BITMAP)
+    assert np.array_equal(lv[0], ref)
+    m = ref >= 1
+    assert np.array_equal(pa[0][m], first_up_neighbour(g.offs, g.cols, ref)[m])
     G.close()
 
 
