@@ -50,6 +50,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -271,6 +272,24 @@ def evaluate(clf, X, T):
     return scores(tree_columns(clf, X), T)
 
 
+def family(graph_name: str) -> str:
+    """The generator family of a training graph's name (its leading letters:
+    rmat, er, grid, chunglu)."""
+    m = re.match(r"[a-z]+", str(graph_name))
+    return m.group(0) if m else str(graph_name)
+
+
+def family_ratios(chosen_col, T, graph):
+    """Total-time ratio (chosen over fastest) of choosing column chosen_col[i]
+    at row i, per graph family: a tree can look fine pooled and still lose
+    one family badly."""
+    t = np.where(T < 0, np.inf, T)
+    chosen = t[np.arange(len(t)), chosen_col]
+    best = t.min(axis=1)
+    fam = np.array([family(x) for x in graph])
+    return {f: round(float(chosen[fam == f].sum() / best[fam == f].sum()), 4) for f in sorted(set(fam.tolist()))}
+
+
 def _named(t):
     return dict(zip(("accuracy", "mean_slowdown", "time_ratio"), t))
 
@@ -412,13 +431,15 @@ def fit(rows, valid, seed=0, log=print, grid=GRID):
     for f in folds:
         c = fit_one(depth, leaf, leaves, X[~f], y[~f], T[~f], None if w is None else w[~f])
         cols[f] = tree_columns(c, X[f])
-    report["graph_split"] = dict(_named(scores(cols, T)), folds=[sorted(np.unique(graph[f]).tolist()) for f in folds])
+    report["graph_split"] = dict(_named(scores(cols, T)), folds=[sorted(np.unique(graph[f]).tolist()) for f in folds],
+                                 by_family=family_ratios(cols, T, graph))
     names = np.unique(graph)
     hold = rng.choice(names, size=max(1, len(names) * 3 // 10), replace=False)
     m = np.isin(graph, hold)
     c2 = fit_one(depth, leaf, leaves, X[~m], y[~m], T[~m], None if w is None else w[~m])
     report["graph_split_one_30pct"] = dict(_named(evaluate(c2, X[m], T[m])), held_out=sorted(hold.tolist()))
-    report["validation"] = dict(_named(evaluate(final, Xv, Tv)), graphs=sorted(np.unique(gv).tolist()))
+    report["validation"] = dict(_named(evaluate(final, Xv, Tv)), graphs=sorted(np.unique(gv).tolist()),
+                                by_family=family_ratios(tree_columns(final, Xv), Tv, gv))
     report["train_all"] = _named(evaluate(final, X, T))
     reg_cols, rf_cols = _model_variants(X, T, Xv, Tv, seed)
     report["model_variants_on_validation"] = {

@@ -82,6 +82,7 @@ def test_fit_export_load_round_trip(tmp_path):
     clf, ks, report = train.fit(rows, valid, grid=grid, log=lambda *a: None)
     assert report["params"]["max_depth"] in (4, 6) and report["validation"]["time_ratio"] >= 1.0
     assert set(report["model_variants_on_validation"]) >= {"random forest (64 trees)"}
+    assert set(report["graph_split"]["by_family"]) == {"g"} and report["validation"]["by_family"]["g"] >= 1.0
     path = str(tmp_path / "t.json")
     arrays = train.export(clf, ks, path, report)
     loaded = gsw.Tree.load(path)
@@ -91,6 +92,15 @@ def test_fit_export_load_round_trip(tmp_path):
         assert (k, unknown) == (k2, u2)
         if not unknown:
             assert k == ks[int(clf.predict(x.astype(np.float32).reshape(1, -1))[0])]
+
+
+def test_family_ratios_by_hand():
+    assert [train.family(x) for x in ("rmat22_s200", "er20_d8_s401", "grid1024_del5_s202", "chunglu23_s220")] == \
+        ["rmat", "er", "grid", "chunglu"]
+    T = np.array([[1.0, 2.0], [4.0, 1.0], [2.0, 2.0], [3.0, -1.0]])
+    graph = np.array(["rmat20_s1", "rmat22_s2", "er20_s3", "er21_s4"])
+    # rmat: chosen 2 + 1 over best 1 + 1; er: chosen 2 + 3 over best 2 + 3
+    assert train.family_ratios(np.array([1, 1, 0, 0]), T, graph) == {"er": 1.0, "rmat": 1.5}
 
 
 def test_apply_solo_replaces_push_times_on_single_workgroup_rows(tmp_path):
